@@ -1,0 +1,135 @@
+"""Galerkin coarse operator and coarse-level objects (oracle; test
+infrastructure only).
+
+* D_1 = R M T, Q_1 = R Q T = (gamma5)_1 D_1 (section "Variance reduction using
+  deflation"; appendix "Chirality on the coarse subspaces" shows the two agree
+  when the basis preserves chirality).
+* Nearest-neighbour stencil structure of the coarse operator (fig:A): per
+  coarse site one self block and one block for each of the 2d = 8 neighbours,
+  each (2 Nv) x (2 Nv).
+* Coarse gamma matrices (gamma5 gamma_k)_1 with an open time index
+  (eq:coarse:gamma, used with an unsummed x0 in eq:G_LL:exact).
+* Top level from coarse modes W (a non-recursive level, allowed by the remark
+  after eq:mglma:decomp): W = chirally split, orthonormalised coarse vectors,
+  D_2 = W^+ D_1 W, Q_2 = W^+ Q_1 W = (gamma5)_2 D_2.
+
+Stencil reading: entry D1[y][dir] collects the fine hops leaving block y
+through its +mu (dir = 1+2mu) or -mu (dir = 2+2mu) face; dir = 0 collects the
+clover/diagonal term and the hops that stay inside the block.  The apply sums
+all nine entries, so lattices with a coarse extent of 1 or 2 (where neighbours
+coincide) need no special case.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .dirac import WilsonClover, gammas, spin_mul
+from .subspace import BlockBasis, gram_schmidt, coarse_gamma5
+
+
+def _face_mask(bl, mu, which):
+    """Lattice mask of sites whose local block coordinate along mu is
+    b_mu - 1 (which='hi') or 0 (which='lo')."""
+    L = bl.L
+    x = np.arange(L[mu]) % bl.b[mu]
+    m1 = (x == (bl.b[mu] - 1)) if which == "hi" else (x == 0)
+    shape = [1, 1, 1, 1]
+    shape[mu] = L[mu]
+    return m1.reshape(shape)
+
+
+def galerkin(D: WilsonClover, B: BlockBasis, chunk=8):
+    """D1[V1][9][nc][nc] with D1 = R M T entry by entry (stencil form)."""
+    bl = B.bl
+    nc, V1 = B.nc, bl.V1
+    D1 = np.zeros((V1, 9, nc, nc), dtype=np.complex128)
+    kappa = D.kappa
+    for j0 in range(0, nc, chunk):
+        j1 = min(nc, j0 + chunk)
+        e = np.zeros((j1 - j0, V1, nc), dtype=np.complex128)
+        for j in range(j0, j1):
+            e[j - j0, :, j] = 1.0
+        Phi = B.prolong(e)                          # Phi_j = sum_y phi_{y,j}
+        self_part = D.clover_apply(Phi)
+        for mu in range(4):
+            hi = _face_mask(bl, mu, "hi")[None, ..., None, None]
+            lo = _face_mask(bl, mu, "lo")[None, ..., None, None]
+            fw = -kappa * D.hop(Phi, mu, +1)
+            bw = -kappa * D.hop(Phi, mu, -1)
+            self_part = self_part + np.where(hi, 0, fw) + np.where(lo, 0, bw)
+            D1[:, 1 + 2 * mu, :, j0:j1] = np.moveaxis(B.restrict(np.where(hi, fw, 0)), 0, -1)
+            D1[:, 2 + 2 * mu, :, j0:j1] = np.moveaxis(B.restrict(np.where(lo, bw, 0)), 0, -1)
+        D1[:, 0, :, j0:j1] = np.moveaxis(B.restrict(self_part), 0, -1)
+    return D1
+
+
+def coarse_apply(D1, nbr, v):
+    """out[n][y] = sum_dir D1[y][dir] v[n][nbr[y][dir]]  (fig:A stencil)."""
+    out = np.zeros_like(v)
+    for d in range(9):
+        out += np.einsum("yij,nyj->nyi", D1[:, d], v[:, nbr[:, d]])
+    return out
+
+
+def coarse_dense(D1, nbr):
+    """Dense (V1*nc) x (V1*nc) matrix of the coarse stencil."""
+    V1, _, nc, _ = D1.shape
+    A = np.zeros((V1 * nc, V1 * nc), dtype=np.complex128)
+    for y in range(V1):
+        for d in range(9):
+            z = nbr[y, d]
+            A[y * nc:(y + 1) * nc, z * nc:(z + 1) * nc] += D1[y, d]
+    return A
+
+
+def coarse_gammas(B: BlockBasis):
+    """Gamma1[V1][b0][3][nc][nc]: (gamma5 gamma_k)_1 restricted to the fine time
+    slice y0*b0 + t of block y (eq:coarse:gamma with an open time index)."""
+    bl = B.bl
+    g, g5 = gammas()
+    Nv, nc = B.Nv, B.nc
+    # full 4-spin form of every basis vector on its block
+    full = np.zeros((bl.V1, nc, *bl.b, 4, 3), dtype=np.complex128)
+    for a in range(2):
+        full[:, a * Nv:(a + 1) * Nv, ..., 2 * a:2 * a + 2, :] = B.phi[:, a]
+    out = np.zeros((bl.V1, bl.b[0], 3, nc, nc), dtype=np.complex128)
+    for k in range(1, 4):
+        G = g5 @ g[k]
+        gf = spin_mul(G, full)
+        # sum over the spatial block sites, spin and colour, time kept open
+        out[:, :, k - 1] = np.einsum("yitxzwsc,yjtxzwsc->ytij", full.conj(), gf)
+    return out
+
+
+class TopLevel:
+    """Exact top level spanned by chirally split coarse modes."""
+
+    def __init__(self, modes, D1, nbr, Nv):
+        """modes: [Nlm][V1][nc] coarse vectors (any full-rank set)."""
+        Nlm, V1, nc = modes.shape
+        self.Nlm, self.r = Nlm, 2 * Nlm
+        g5c = coarse_gamma5(Nv)
+        cols = []
+        for a in range(2):
+            keep = (g5c > 0) if a == 0 else (g5c < 0)
+            part = modes * keep[None, None, :]
+            q = gram_schmidt(part.reshape(Nlm, -1))
+            cols.append(q)
+        # W[V1*nc][r], column index alpha*Nlm + m
+        self.W = np.concatenate(cols, axis=0).T.copy()
+        AW = coarse_apply(D1, nbr, self.W.T.reshape(self.r, V1, nc)).reshape(self.r, -1).T
+        self.D2 = self.W.conj().T @ AW
+        self.g5 = np.concatenate([np.ones(Nlm), -np.ones(Nlm)])
+        self.Q2 = self.g5[:, None] * self.D2
+
+    def gammas(self, Gamma1, bl):
+        """Gamma2[L0][3][r][r] = W^+ (gamma5 gamma_k)_1(x0) W."""
+        V1, b0, _, nc, _ = Gamma1.shape
+        Wy = self.W.reshape(V1, nc, self.r)
+        out = np.zeros((bl.L[0], 3, self.r, self.r), dtype=np.complex128)
+        y0 = np.unravel_index(np.arange(V1), bl.L1)[0]
+        for t in range(b0):
+            m = np.einsum("yia,ykij,yjb->ykab", Wy.conj(), Gamma1[:, t], Wy)
+            for y in range(V1):
+                out[y0[y] * b0 + t] += m[y]
+        return out

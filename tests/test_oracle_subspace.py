@@ -1,0 +1,141 @@
+"""Pins of the oracle's block basis, restrictor/prolongator, Galerkin coarse
+operator and top level: partition of the lattice, QR uniqueness against
+numpy's Householder QR, RT = 1, the chirality relations of the appendix,
+the Galerkin identity against a dense R M T, (gamma5)_1 D_1 Hermitian,
+exact eigenvalue reproduction and gauge invariance of D_1."""
+import numpy as np
+import pytest
+
+from oracle import dirac, subspace, coarse
+from paper_2412_06347_amd import synth
+
+
+def _setup(L, b, Nv, seed=1, kappa=0.124, csw=1.0):
+    U = synth.gauge_field(L, 0.3, seed)
+    D = dirac.WilsonClover(U, L, kappa, csw)
+    bl = subspace.Blocking(L, b)
+    tv = dirac.fields_to_lattice(synth.gaussian_fields(Nv, L, seed + 100), L)
+    B = subspace.BlockBasis(bl, tv)
+    return U, D, bl, tv, B
+
+
+def test_block_partition():
+    L, b = (4, 6, 2, 4), (2, 3, 2, 1)
+    bl = subspace.Blocking(L, b)
+    assert bl.V1 == 2 * 2 * 1 * 4
+    f = np.arange(np.prod(L)).reshape(1, *L).astype(float)
+    blocks = bl.to_blocks(f[..., None])[..., 0]
+    assert sorted(blocks.ravel()) == list(range(np.prod(L)))    # each site once
+    assert np.array_equal(bl.from_blocks(blocks[..., None])[..., 0], f)
+    for y in range(bl.V1):
+        for s in blocks[0, y].ravel():
+            x = np.unravel_index(int(s), L)
+            assert bl.block_of(x) == y
+
+
+def test_gram_schmidt_matches_qr():
+    rng = np.random.default_rng(1)
+    W = rng.standard_normal((5, 7, 40)) + 1j * rng.standard_normal((5, 7, 40))
+    Q = subspace.gram_schmidt(W)
+    for i in range(5):
+        q, r = np.linalg.qr(W[i].T)
+        ph = np.diag(r) / np.abs(np.diag(r))
+        q = q * ph[None, :]           # positive real diagonal of R
+        assert np.abs(Q[i].T - q).max() < 1e-12
+    with pytest.raises(subspace.RankError):
+        W2 = W.copy()
+        W2[:, 3] = W2[:, 1] * (2 - 1j)
+        subspace.gram_schmidt(W2)
+
+
+def test_restrict_prolong_identities():
+    L, b, Nv = (4, 4, 2, 2), (2, 2, 2, 2), 3
+    U, D, bl, tv, B = _setup(L, b, Nv)
+    T = B.basis_canonical().reshape(bl.V1 * B.nc, -1).T          # 12V x (V1 nc)
+    assert np.abs(T.conj().T @ T - np.eye(T.shape[1])).max() < 1e-13   # RT = 1
+    P = T @ T.conj().T
+    assert np.abs(P @ P - P).max() < 1e-13
+    G5 = np.kron(np.eye(bl.L[0] * bl.L[1] * bl.L[2] * bl.L[3]), np.kron(np.diag([1, 1, -1, -1]), np.eye(3)))
+    assert np.abs(P @ G5 - G5 @ P).max() < 1e-13                 # [P, gamma5] = 0
+    g5c = np.tile(subspace.coarse_gamma5(Nv), bl.V1)
+    R = T.conj().T
+    assert np.abs(R @ G5 - g5c[:, None] * R).max() < 1e-13       # R gamma5 = (gamma5)_1 R
+    # restrict/prolong of the class agree with the dense matrices
+    psi = dirac.fields_to_lattice(synth.gaussian_fields(2, L, 7), L)
+    rc = B.restrict(psi).reshape(2, -1)
+    assert np.abs(rc - (R @ psi.reshape(2, -1).T).T).max() < 1e-12
+    c = synth.gaussian_coarse(2, bl.V1, B.nc, 8)
+    assert np.abs(B.prolong(c).reshape(2, -1) - (T @ c.reshape(2, -1).T).T).max() < 1e-12
+
+
+@pytest.mark.parametrize("L,b", [((4, 4, 6, 2), (2, 2, 2, 2)),    # coarse extents 2,2,3,1
+                                 ((6, 2, 2, 4), (2, 1, 2, 4)),     # b=1 and b=L directions
+                                 ((6, 6, 3, 3), (2, 2, 1, 1))])    # coarse extents 3
+def test_galerkin_identity(L, b):
+    Nv = 2
+    U, D, bl, tv, B = _setup(L, b, Nv)
+    D1 = coarse.galerkin(D, B)
+    nbr = bl.neighbour_table()
+    A = coarse.coarse_dense(D1, nbr)
+    T = B.basis_canonical().reshape(bl.V1 * B.nc, -1).T
+    brute = T.conj().T @ D.dense() @ T
+    assert np.abs(A - brute).max() < 1e-13 * np.abs(brute).max()
+    g5c = np.tile(subspace.coarse_gamma5(Nv), bl.V1)
+    Q1 = g5c[:, None] * A
+    assert np.abs(Q1 - Q1.conj().T).max() < 1e-13
+    # coarse apply == R M T psi
+    c = synth.gaussian_coarse(2, bl.V1, B.nc, 3)
+    lhs = coarse.coarse_apply(D1, nbr, c).reshape(2, -1)
+    rhs = B.restrict(D.M(B.prolong(c))).reshape(2, -1)
+    assert np.abs(lhs - rhs).max() < 1e-12 * np.abs(rhs).max()
+
+
+def test_exact_eigenvalue_reproduction():
+    """Test vectors = exact eigenvectors of Q => Q_1 has exactly those eigenvalues
+    (appendix on the spectra of coarse and fine operators)."""
+    L, b, Nv = (4, 2, 2, 4), (2, 2, 2, 2), 4
+    U = synth.gauge_field(L, 0.3, 5)
+    D = dirac.WilsonClover(U, L, 0.124, 1.0)
+    G5 = np.kron(np.eye(int(np.prod(L))), np.kron(np.diag([1, 1, -1, -1]), np.eye(3)))
+    Q = G5 @ D.dense()
+    w, v = np.linalg.eigh(Q)
+    idx = np.argsort(np.abs(w))[:Nv]
+    tv = v[:, idx].T.reshape(Nv, *L, 4, 3)
+    bl = subspace.Blocking(L, b)
+    B = subspace.BlockBasis(bl, tv)
+    D1 = coarse.galerkin(D, B)
+    A = coarse.coarse_dense(D1, bl.neighbour_table())
+    g5c = np.tile(subspace.coarse_gamma5(Nv), bl.V1)
+    w1 = np.linalg.eigvalsh(g5c[:, None] * A)
+    for lam in w[idx]:
+        assert np.min(np.abs(w1 - lam)) < 1e-12
+
+
+def test_galerkin_gauge_invariant():
+    L, b, Nv = (4, 2, 4, 2), (2, 2, 2, 2), 2
+    U, D, bl, tv, B = _setup(L, b, Nv, seed=4)
+    D1 = coarse.galerkin(D, B)
+    Om = synth.gauge_transform(L, seed=2).reshape(*L, 3, 3)
+    Ul = dirac.gauge_to_lattice(U, L)
+    Ut = np.stack([Om @ Ul[mu] @ np.swapaxes(dirac.shift(Om, mu, +1, 0), -1, -2).conj()
+                   for mu in range(4)])
+    Dt = dirac.WilsonClover(np.moveaxis(Ut, 0, 4).reshape(-1, 4, 3, 3), L, D.kappa, D.csw)
+    Bt = subspace.BlockBasis(bl, dirac.colour_mul(Om, tv))
+    D1t = coarse.galerkin(Dt, Bt)
+    assert np.abs(D1t - D1).max() < 1e-12
+
+
+def test_top_level():
+    L, b, Nv, Nlm = (4, 2, 4, 2), (2, 2, 2, 2), 3, 2
+    U, D, bl, tv, B = _setup(L, b, Nv)
+    D1 = coarse.galerkin(D, B)
+    nbr = bl.neighbour_table()
+    modes = synth.gaussian_coarse(Nlm, bl.V1, B.nc, 5)
+    top = coarse.TopLevel(modes, D1, nbr, Nv)
+    W = top.W
+    assert np.abs(W.conj().T @ W - np.eye(2 * Nlm)).max() < 1e-13
+    g5c = np.tile(subspace.coarse_gamma5(Nv), bl.V1)
+    assert np.abs(g5c[:, None] * W - W * top.g5[None, :]).max() < 1e-14   # definite chirality
+    A = coarse.coarse_dense(D1, nbr)
+    assert np.abs(top.D2 - W.conj().T @ A @ W).max() < 1e-12
+    assert np.abs(top.Q2 - top.Q2.conj().T).max() < 1e-12
