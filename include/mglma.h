@@ -1,0 +1,216 @@
+/*
+ * mglma.h -- C ABI of the MI355X multigrid low-mode-averaging hot path.
+ *
+ * Operations follow Gruber, Harris, Krstic Marinkovic, "Multigrid low-mode
+ * averaging" (arXiv:2412.06347):
+ *   - Wilson-clover operator M and Q = gamma5 M      (section "Variance
+ *     reduction using deflation"; fermions of tab:ensembles)
+ *   - chirally split block basis, restrictor R, prolongator T
+ *                                                    (eq:mg_basis, eq:res_mg,
+ *                                                     eq:pro_mg, eq:chirality:B)
+ *   - Galerkin coarse operator D_1 = R M T, Q_1 = (gamma5)_1 D_1 (fig:A)
+ *   - solves on the fine and the coarse level
+ *   - sources and the contractions of the isovector vector correlator
+ *     (eq:tmr, eq:C_ij, eq:C_stoch2, eq:coarse:gamma, eq:G_LL:exact)
+ *
+ * Conventions (all calls):
+ *   - Return 0 on success or a negative MGLMA_ERR_* code; nothing throws.
+ *   - A context is used by one host thread at a time.  All GPU work of a
+ *     context is enqueued on its stream (mglma_set_stream); calls return
+ *     after enqueueing unless documented as synchronising.
+ *   - Pointers named *_dev are device memory owned by the caller; the library
+ *     never frees them and keeps no reference after the call returns.
+ *   - Complex numbers are stored (re, im) interleaved.
+ *   - Site ordering.  Canonical: s = ((x0*L1 + x1)*L2 + x2)*L3 + x3 (x0 is
+ *     time).  Device ("blocked"): i = k*Vb + l with k the block index
+ *     (lexicographic over the block grid, last direction fastest) and l the
+ *     lexicographic index inside the b0 x b1 x b2 x b3 block.
+ *   - Fine fields in device layout: element (rhs, spin s, colour c, site i)
+ *     at ((rhs*12 + 3*s + c)*V + i), one complex of the field's precision:
+ *     F64 = 2 doubles, F32 = 2 floats, F16 = 2 IEEE halves.
+ *   - Coarse fields: element (rhs, coarse site y, index j) at
+ *     ((rhs*V1 + y)*nc + j), nc = 2*Nv, j = alpha*Nv + c with alpha = 0 the
+ *     gamma5 = +1 chirality (spins 0,1) and alpha = 1 the gamma5 = -1 one.
+ *   - Dirac matrices: chiral basis, gamma5 = diag(1,1,-1,-1).
+ *   - The operator is kappa-normalised: M = 2 kappa D, so propagators are
+ *     M^{-1} and correlators differ from the D^{-1} ones by (2 kappa)^2.
+ */
+#ifndef MGLMA_H
+#define MGLMA_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------- */
+#define MGLMA_OK                  0
+#define MGLMA_ERR_ARG            -1  /* invalid argument or null pointer      */
+#define MGLMA_ERR_SHAPE          -2  /* sizes inconsistent with the lattice  */
+#define MGLMA_ERR_OOM            -3  /* device allocation failed              */
+#define MGLMA_ERR_NONFINITE      -4  /* NaN/Inf in an input or a residual     */
+#define MGLMA_ERR_RANK           -5  /* block basis rank deficient            */
+#define MGLMA_ERR_NOT_CONVERGED  -6  /* solver hit its limit (stats filled)   */
+#define MGLMA_ERR_NO_SUBSPACE    -7  /* call needs mglma_build_subspace first */
+#define MGLMA_ERR_HIP            -8  /* a HIP runtime call failed             */
+#define MGLMA_ERR_NO_GAUGE       -9  /* call needs mglma_load_gauge first     */
+#define MGLMA_ERR_NO_TOP        -10  /* call needs mglma_set_top_modes first  */
+
+typedef enum { MGLMA_F64 = 0, MGLMA_F32 = 1, MGLMA_F16 = 2, MGLMA_BF16 = 3 } mglma_prec;
+
+typedef struct mglma_ctx mglma_ctx;
+
+typedef struct {
+    int    L[4];      /* lattice extents, direction 0 = time                  */
+    int    block[4];  /* block size b_mu of the aggregation (eq:block_def);
+                         must divide L[mu]                                     */
+    double kappa;     /* hopping parameter                                     */
+    double csw;       /* clover coefficient                                    */
+    double bc[4];     /* fermion boundary phase (+1 or -1) on hops that wrap  */
+} mglma_lattice;
+
+typedef struct {
+    double tol;          /* target true relative residual ||b-Mx||/||b||      */
+    int    max_outer;    /* FP64 defect-correction cycles                      */
+    int    max_inner;    /* inner FGCR iterations per cycle                    */
+    int    gcr_m;        /* inner FGCR restart length                          */
+    double inner_tol;    /* relative reduction asked of each inner solve       */
+    int    nu_post;      /* MR smoothing steps after the coarse correction     */
+    int    coarse_iters; /* GCR steps of the coarse solve in the preconditioner*/
+    int    smoother;     /* precision of the smoother Dslash (mglma_prec)      */
+    int    inner;        /* precision of the inner Krylov vectors (F32 or F64) */
+    int    coarse;       /* precision of the preconditioner's coarse operator  */
+    int    use_mg;       /* 1: MG preconditioner, 0: unpreconditioned GCR      */
+} mglma_solve_params;
+
+typedef struct {
+    int    outer;        /* defect-correction cycles done                      */
+    int    inner;        /* inner iterations summed over cycles                */
+    int    coarse;       /* coarse operator applications                      */
+    double true_rel_res; /* ||b - M x|| / ||b|| in FP64 at return              */
+    double seconds;      /* wall time of the call                              */
+    int    status;       /* 0 or MGLMA_ERR_NOT_CONVERGED for this right-hand side */
+} mglma_solve_stats;
+
+/* ---- context ----------------------------------------------------------- */
+/* Create a context for one lattice on the current HIP device.  `stream` is
+ * a hipStream_t (NULL = default stream).  Errors: ARG, SHAPE, OOM, HIP.   */
+int  mglma_create(mglma_ctx** ctx, const mglma_lattice* lat, void* stream);
+void mglma_destroy(mglma_ctx* ctx);
+int  mglma_set_stream(mglma_ctx* ctx, void* stream);
+const char* mglma_strerror(int code);
+/* Sizes: 0 V, 1 V1, 2 Vb, 3 Nv, 4 nc, 5 Nlm, 6 r = 2 Nlm, 7 spatial volume. */
+long mglma_query(const mglma_ctx* ctx, int what);
+/* Device bytes held by the context (gauge, clover, basis, coarse op, ...). */
+size_t mglma_resident_bytes(const mglma_ctx* ctx);
+/* Bytes of one fine / coarse field of `prec` (times nrhs).                  */
+size_t mglma_fine_bytes(const mglma_ctx* ctx, int prec, int nrhs);
+size_t mglma_coarse_bytes(const mglma_ctx* ctx, int prec, int nrhs);
+
+/* ---- fine level --------------------------------------------------------- */
+/* Load the links U_mu(x) (canonical order, [V][4][3][3] complex128, U_mu(x)
+ * maps x+mu to x) and build the clover term 1 + A(x) with
+ * A = i kappa c_sw sum_{mu<nu} sigma_{mu nu} F_{mu nu}, F the traceless part of
+ * (Q_{mu nu} - Q_{mu nu}^+)/8 over the four plaquette leaves.  Keeps FP64,
+ * FP32 and FP16 copies resident.  Synchronising.  Errors: ARG, NONFINITE.  */
+int mglma_load_gauge(mglma_ctx* ctx, const double* U_dev);
+/* Export 1 + A as two 6x6 chirality blocks per site, canonical order,
+ * [V][2][6][6] complex128 (block index 3*s'+c, s' = spin within the
+ * chirality).  For tests.                                                   */
+int mglma_export_clover(mglma_ctx* ctx, double* out_dev);
+/* Convert `nrhs` fine fields between canonical ([rhs][V][4][3] complex128)
+ * and device layout of precision `prec` (F64/F32/F16, round to nearest).    */
+int mglma_import_fields(mglma_ctx* ctx, int prec, const double* canon_dev, void* dev, int nrhs);
+int mglma_export_fields(mglma_ctx* ctx, int prec, const void* dev, double* canon_dev, int nrhs);
+/* out = M in (gamma5 = 0) or Q in = gamma5 M in (gamma5 = 1) for nrhs fields
+ * in device layout; F64 computes in FP64, F32 and F16 in FP32.  in != out.  */
+int mglma_apply_D(mglma_ctx* ctx, int prec, int gamma5, const void* in_dev, void* out_dev, int nrhs);
+
+/* ---- subspace ----------------------------------------------------------- */
+/* Build the basis phi^{B_y}_{alpha c}: for every block y and chirality alpha
+ * the fields P_alpha theta_{B_y} v_c, c = 0..Nv-1, orthonormalised in order c
+ * (QR with positive real diagonal, eq:mg_basis with eq:chirality:B), then the
+ * Galerkin operator D_1 = R M T as 9 blocks nc x nc per coarse site and the
+ * coarse gamma matrices (gamma5 gamma_k)_1 per block time slice.
+ * testvecs_dev: Nv fine fields, device layout, F64.  Synchronising.
+ * Errors: NO_GAUGE, ARG, RANK (a block's vectors are linearly dependent).   */
+int mglma_build_subspace(mglma_ctx* ctx, int Nv, const double* testvecs_dev);
+/* Export the basis in canonical order: [V1][nc][V][4][3] is too large, so
+ * this exports [V1][nc][Vb][4][3] complex128 with the block-local sites in
+ * lexicographic order (zeros on the spins of the other chirality).          */
+int mglma_export_basis(mglma_ctx* ctx, double* out_dev);
+/* Export D_1 as [V1][9][nc][nc] complex128; direction 0 = self, 1+2mu = +mu
+ * neighbour, 2+2mu = -mu neighbour; row index = output.                     */
+int mglma_export_coarse_op(mglma_ctx* ctx, double* out_dev);
+/* coarse = R fine (eq:res_mg), fine = T coarse (eq:pro_mg); F64 or F32.     */
+int mglma_restrict(mglma_ctx* ctx, int prec, const void* fine_dev, void* coarse_dev, int nrhs);
+int mglma_prolong(mglma_ctx* ctx, int prec, const void* coarse_dev, void* fine_dev, int nrhs);
+/* out = D_1 in (gamma5 = 0) or Q_1 in (gamma5 = 1).  prec F64, F32 (FP32
+ * operator) or BF16 (bfloat16 operator on the matrix cores, FP32 vectors). */
+int mglma_coarse_apply(mglma_ctx* ctx, int prec, int gamma5, const void* in_dev, void* out_dev, int nrhs);
+
+/* ---- top (exact) level -------------------------------------------------- */
+/* Set the exact top level from Nlm coarse vectors modes_dev ([Nlm][V1][nc]
+ * complex128): each is split by (gamma5)_1 chirality and each chirality set
+ * orthonormalised in order, giving W with r = 2 Nlm columns; then
+ * D_2 = W^+ D_1 W, Q_2 = (gamma5)_2 D_2 and (gamma5 gamma_k)_2(x0) = W^+
+ * (gamma5 gamma_k)_1(x0) W.  Synchronising.  Errors: NO_SUBSPACE, RANK.    */
+int mglma_set_top_modes(mglma_ctx* ctx, int Nlm, const double* modes_dev);
+
+/* ---- solves -------------------------------------------------------------- */
+/* x = M^{-1} b for nrhs fields (device layout, F64) to the true relative
+ * residual p->tol.  Mixed precision: inner FGCR on p->inner vectors with the
+ * multigrid preconditioner (coarse correction with p->coarse operator, then
+ * p->nu_post MR smoothing steps in p->smoother precision) inside an FP64
+ * defect-correction loop.  stats may be NULL or hold nrhs entries.
+ * Synchronising.  Errors: NO_GAUGE, NO_SUBSPACE (use_mg), NONFINITE,
+ * NOT_CONVERGED (x holds the last iterate).                                 */
+int mglma_solve(mglma_ctx* ctx, const mglma_solve_params* p, const double* b_dev,
+                double* x_dev, int nrhs, mglma_solve_stats* stats);
+/* x = D_1^{-1} b on the coarse level (coarse fields, F64) to relative
+ * residual p->tol; inner GCR uses the p->coarse operator inside FP64 defect
+ * correction.  Synchronising.                                               */
+int mglma_coarse_solve(mglma_ctx* ctx, const mglma_solve_params* p, const double* b_dev,
+                       double* x_dev, int nrhs, mglma_solve_stats* stats);
+/* Apply the level pieces to solved/sourced fields (device layout, F64):
+ *   ge1 = T D_1^{-1} R eta   (S_1 + S_2 for three levels, S_1 for two)
+ *   top = T W D_2^{-1} W^+ R eta   (needs the top level; may be NULL)
+ * Synchronising.                                                            */
+int mglma_subspace_pieces(mglma_ctx* ctx, const mglma_solve_params* p, const double* eta_dev,
+                          double* ge1_dev, double* top_dev, int nrhs);
+
+/* ---- sources ------------------------------------------------------------- */
+/* The 12 point sources e_{y,(s,c)}, column index 3*s + c, F64 device layout. */
+int mglma_point_sources(mglma_ctx* ctx, const int y[4], double* out_dev);
+/* Spin-diluted time-diluted wall sources eta_n^{(s)} = delta_{x0,t_n} e_s xi_n
+ * for n < nsrc: xi_dev [nsrc][L1*L2*L3][3] complex128 noise, t_host [nsrc]
+ * slices; out has 4*nsrc fields, index 4n + s.                              */
+int mglma_noise_sources(mglma_ctx* ctx, int nsrc, const double* xi_dev, const int* t_host,
+                        double* out_dev);
+
+/* ---- contractions (eq:tmr, eq:C_stoch2) ---------------------------------- */
+/* Point-source correlator of two propagator pieces from the same source y:
+ *   C(y0+t, y0) = -1/3 sum_k sum_x tr{ S_i(x,y) gamma_k S_j(y,x) gamma_k },
+ * t = 0..L0-1, with psi_i = the 12 columns of S_i(.,y), psi_j likewise.
+ * Result: C_host[L0] complex128 (re, im).  Synchronising.                   */
+int mglma_contract_point(mglma_ctx* ctx, const double* psi_i_dev, const double* psi_j_dev,
+                         int y0, double* C_host);
+/* The same for coarse vectors c_i = 12 coarse fields with S_i(.,y) = T c_i,
+ * evaluated on the coarse grid through (gamma5 gamma_k)_1 (eq:coarse:gamma). */
+int mglma_contract_point_coarse(mglma_ctx* ctx, const double* ci_dev, const double* cj_dev,
+                                int y0, double* C_host);
+/* One-source stochastic estimator G^n_ij(t_n + t, t_n), t = 0..L0-1
+ * (eq:C_stoch2, spin-diagonal): psi_i = S_i eta^{(s)}, psi_j = S_j eta^{(s)}
+ * for the four spins s (4 fields each).  Result C_host[L0] complex.        */
+int mglma_contract_stoch(mglma_ctx* ctx, const double* psi_i_dev, const double* psi_j_dev,
+                         int tn, double* C_host);
+int mglma_contract_stoch_coarse(mglma_ctx* ctx, const double* ci_dev, const double* cj_dev,
+                                int tn, double* C_host);
+/* Exact top-level term eq:G_LL:exact, G(t) for t = 0..L0-1 (complex).     */
+int mglma_contract_top(mglma_ctx* ctx, double* G_host);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MGLMA_H */

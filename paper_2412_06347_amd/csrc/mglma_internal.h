@@ -1,0 +1,257 @@
+// Internal declarations of the MI355X multigrid low-mode-averaging library.
+// Everything here is private to libmglma; the public ABI is include/mglma.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+#include <stddef.h>
+#include <complex>
+#include <vector>
+#include <string>
+
+#include "../../include/mglma.h"
+
+#define MG_TRY(expr)                                        \
+    do {                                                    \
+        int _rc = (expr);                                   \
+        if (_rc != MGLMA_OK) return _rc;                    \
+    } while (0)
+
+#define HIP_TRY(expr)                                       \
+    do {                                                    \
+        hipError_t _e = (expr);                             \
+        if (_e != hipSuccess) {                             \
+            mg_last_hip_error(_e, #expr, __FILE__, __LINE__); \
+            return MGLMA_ERR_HIP;                           \
+        }                                                   \
+    } while (0)
+
+void mg_last_hip_error(hipError_t e, const char* what, const char* file, int line);
+
+typedef uint16_t bf16_t;   // raw bfloat16 bits
+
+// ---------------------------------------------------------------------------
+// integer division by a runtime constant (n < 2^31): q = (umulhi(n,m) + n) >> s
+// ---------------------------------------------------------------------------
+struct FastDiv {
+    uint32_t d, m, s;
+};
+static inline FastDiv make_fastdiv(uint32_t d) {
+    FastDiv f;
+    f.d = d;
+    uint32_t s = 0;
+    while ((1ull << s) < d) s++;
+    f.s = s;
+    f.m = (uint32_t)((((uint64_t)1 << 32) * (((uint64_t)1 << s) - d)) / d + 1);
+    return f;
+}
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) {
+    return (__umulhi(n, f.m) + n) >> f.s;
+}
+
+// ---------------------------------------------------------------------------
+// lattice geometry in the blocked device order
+// ---------------------------------------------------------------------------
+struct Geo {
+    int L[4], b[4], L1[4];
+    int V, Vb, V1, V3;       // sites, sites per block, blocks, spatial volume
+    int sl[4];               // stride of local coordinate mu inside a block
+    int sk[4];               // stride of block coordinate mu in the block index
+    FastDiv fb[4], fL1[4], fVb, fL[4];
+    int bcneg[4];            // 1 if the fermion phase on wrapping hops is -1
+};
+
+Geo make_geo(const int L[4], const int b[4], const double bc[4]);
+
+// coordinates of blocked index i
+__device__ __forceinline__ void geo_coords(const Geo& g, int i, int lc[4], int yc[4]) {
+    uint32_t k = fdiv((uint32_t)i, g.fVb);
+    uint32_t l = (uint32_t)i - k * (uint32_t)g.Vb;
+#pragma unroll
+    for (int mu = 3; mu >= 0; --mu) {
+        uint32_t q = fdiv(l, g.fb[mu]);
+        lc[mu] = (int)(l - q * (uint32_t)g.b[mu]);
+        l = q;
+        uint32_t qk = fdiv(k, g.fL1[mu]);
+        yc[mu] = (int)(k - qk * (uint32_t)g.L1[mu]);
+        k = qk;
+    }
+}
+// blocked index of full coordinates x (0 <= x_mu < L_mu)
+__device__ __forceinline__ int geo_index(const Geo& g, const int x[4]) {
+    int k = 0, l = 0;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        int y = (int)fdiv((uint32_t)x[mu], g.fb[mu]);
+        int lm = x[mu] - y * g.b[mu];
+        k = k * g.L1[mu] + y;
+        l = l * g.b[mu] + lm;
+    }
+    return k * g.Vb + l;
+}
+// canonical (lexicographic) index -> full coordinates
+__device__ __forceinline__ void canon_coords(const Geo& g, int s, int x[4]) {
+    uint32_t r = (uint32_t)s;
+#pragma unroll
+    for (int mu = 3; mu >= 0; --mu) {
+        uint32_t q = fdiv(r, g.fL[mu]);
+        x[mu] = (int)(r - q * (uint32_t)g.L[mu]);
+        r = q;
+    }
+}
+// neighbour x + mu (dir = +1) or x - mu (dir = -1); *wrap = crossed the lattice edge
+__device__ __forceinline__ int geo_fwd(const Geo& g, int i, int mu, const int lc[4], const int yc[4], bool* wrap) {
+    if (lc[mu] + 1 < g.b[mu]) { *wrap = false; return i + g.sl[mu]; }
+    int d = -(g.b[mu] - 1) * g.sl[mu];
+    if (yc[mu] + 1 < g.L1[mu]) { *wrap = false; return i + d + g.sk[mu] * g.Vb; }
+    *wrap = true;
+    return i + d - (g.L1[mu] - 1) * g.sk[mu] * g.Vb;
+}
+__device__ __forceinline__ int geo_bwd(const Geo& g, int i, int mu, const int lc[4], const int yc[4], bool* wrap) {
+    if (lc[mu] > 0) { *wrap = false; return i - g.sl[mu]; }
+    int d = (g.b[mu] - 1) * g.sl[mu];
+    if (yc[mu] > 0) { *wrap = false; return i + d - g.sk[mu] * g.Vb; }
+    *wrap = true;
+    return i + d + (g.L1[mu] - 1) * g.sk[mu] * g.Vb;
+}
+
+// ---------------------------------------------------------------------------
+// complex arithmetic
+// ---------------------------------------------------------------------------
+template <typename R> struct cx {
+    R re, im;
+};
+template <typename R> __device__ __forceinline__ cx<R> cmk(R a, R b) { cx<R> z; z.re = a; z.im = b; return z; }
+template <typename R> __device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return cmk(a.re + b.re, a.im + b.im); }
+template <typename R> __device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return cmk(a.re - b.re, a.im - b.im); }
+template <typename R> __device__ __forceinline__ cx<R> operator-(cx<R> a) { return cmk(-a.re, -a.im); }
+template <typename R> __device__ __forceinline__ cx<R> operator*(cx<R> a, cx<R> b) {
+    return cmk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <typename R> __device__ __forceinline__ cx<R> operator*(R s, cx<R> a) { return cmk(s * a.re, s * a.im); }
+template <typename R> __device__ __forceinline__ cx<R> conj(cx<R> a) { return cmk(a.re, -a.im); }
+template <typename R> __device__ __forceinline__ cx<R> mul_i(cx<R> a) { return cmk(-a.im, a.re); }     // i*a
+template <typename R> __device__ __forceinline__ cx<R> mul_mi(cx<R> a) { return cmk(a.im, -a.re); }    // -i*a
+// acc += a*b
+template <typename R> __device__ __forceinline__ void cmac(cx<R>& acc, cx<R> a, cx<R> b) {
+    acc.re = fma(a.re, b.re, acc.re); acc.re = fma(-a.im, b.im, acc.re);
+    acc.im = fma(a.re, b.im, acc.im); acc.im = fma(a.im, b.re, acc.im);
+}
+// acc += conj(a)*b
+template <typename R> __device__ __forceinline__ void cjmac(cx<R>& acc, cx<R> a, cx<R> b) {
+    acc.re = fma(a.re, b.re, acc.re); acc.re = fma(a.im, b.im, acc.re);
+    acc.im = fma(a.re, b.im, acc.im); acc.im = fma(-a.im, b.re, acc.im);
+}
+
+// ---------------------------------------------------------------------------
+// storage types: double2 (F64), float2 (F32), __half2 (F16)
+// ---------------------------------------------------------------------------
+template <typename S> struct StoreT;
+template <> struct StoreT<double2> {
+    typedef double R;
+    static __device__ __forceinline__ cx<double> ld(const double2* p) { double2 v = *p; return cmk(v.x, v.y); }
+    static __device__ __forceinline__ void st(double2* p, cx<double> v) { *p = make_double2(v.re, v.im); }
+};
+template <> struct StoreT<float2> {
+    typedef float R;
+    static __device__ __forceinline__ cx<float> ld(const float2* p) { float2 v = *p; return cmk(v.x, v.y); }
+    static __device__ __forceinline__ void st(float2* p, cx<float> v) { *p = make_float2(v.re, v.im); }
+};
+template <> struct StoreT<__half2> {
+    typedef float R;
+    static __device__ __forceinline__ cx<float> ld(const __half2* p) { float2 v = __half22float2(*p); return cmk(v.x, v.y); }
+    static __device__ __forceinline__ void st(__half2* p, cx<float> v) { *p = __floats2half2_rn(v.re, v.im); }
+};
+template <typename S, typename R> __device__ __forceinline__ cx<R> ldc(const S* p) {
+    cx<typename StoreT<S>::R> v = StoreT<S>::ld(p);
+    return cmk((R)v.re, (R)v.im);
+}
+template <typename S, typename R> __device__ __forceinline__ void stc(S* p, cx<R> v) {
+    typedef typename StoreT<S>::R RS;
+    StoreT<S>::st(p, cmk((RS)v.re, (RS)v.im));
+}
+
+// ---------------------------------------------------------------------------
+// the context
+// ---------------------------------------------------------------------------
+struct Scratch {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct mglma_ctx {
+    int L[4], b[4];
+    double kappa, csw, bc[4];
+    Geo geo;
+    hipStream_t stream = nullptr;
+    int device = 0;
+
+    // gauge links [4][9][V] and clover 1+A [2][18][V] (packed Hermitian 6x6)
+    double2* U64 = nullptr; float2* U32 = nullptr; __half2* U16 = nullptr;
+    double2* C64 = nullptr; float2* C32 = nullptr; __half2* C16 = nullptr;
+    bool have_gauge = false;
+
+    // subspace: basis [V1][2][Nv][6][Vb], coarse operator [V1][9][nc][nc]
+    int Nv = 0, nc = 0;
+    double2* B64 = nullptr; float2* B32 = nullptr;
+    double2* D64 = nullptr; float2* D32 = nullptr;
+    bf16_t* Dbf = nullptr;       // [V1][9][2][nc][nc] planar re/im bfloat16
+    double2* G1 = nullptr;       // coarse gammas [V1][b0][3][Nv][Nv] (alpha=0 rows, alpha=1 cols)
+    bool have_subspace = false;
+
+    // top level
+    int Nlm = 0, r = 0;
+    double2* W = nullptr;                          // [r][V1][nc]
+    std::vector<std::complex<double>> D2, Q2inv;   // r x r
+    std::vector<std::complex<double>> Gamma2;      // [L0][3][r][r]
+    bool have_top = false;
+
+    // reusable scratch (grown on demand) and reduction buffers
+    Scratch scr[8];
+    double* red_part = nullptr; size_t red_part_n = 0;
+    unsigned* red_cnt = nullptr; size_t red_cnt_n = 0;
+    double* hbuf = nullptr; size_t hbuf_n = 0;     // pinned host staging
+
+    size_t resident = 0;
+};
+
+// scratch slot i of at least `bytes` bytes (contents undefined)
+int mg_scratch(mglma_ctx* c, int slot, size_t bytes, void** out);
+int mg_malloc(mglma_ctx* c, void** p, size_t bytes);
+void mg_free(mglma_ctx* c, void* p, size_t bytes);
+int mg_host(mglma_ctx* c, size_t ndoubles, double** out);
+
+// ---------------------------------------------------------------------------
+// kernel launchers shared between translation units
+// ---------------------------------------------------------------------------
+int mg_dslash(mglma_ctx* c, int prec, int gamma5, const void* in, void* out, int nrhs);
+
+// BLAS-1 on fine or coarse vectors of `n` complex per right-hand side
+// (prec F64 or F32 or F16 storage).  Scalars live in device memory.
+int mg_norm2(mglma_ctx* c, int prec, const void* x, size_t n, int nrhs, double* out_dev);
+int mg_dot(mglma_ctx* c, int prec, const void* x, const void* y, size_t n, int nrhs, double* out_dev);
+// out[j][r] = <x_j, y>_r for j < k, x_j = x + j*stride (stride in complex elements, per vector set)
+int mg_multidot(mglma_ctx* c, int prec, const void* x, size_t xstride, int k, const void* y, size_t n, int nrhs,
+                double* out_dev);
+// y_r += sum_j coef[j][r] * x_j,r  (coef complex, multiplied by `sign`)
+int mg_multiaxpy(mglma_ctx* c, int prec, const void* x, size_t xstride, int k, const double* coef_dev, double sign,
+                 void* y, size_t n, int nrhs);
+// y_r = a_r * x_r + b_r * y_r with complex a, b from device arrays (NULL = 0 / 1)
+int mg_axpby(mglma_ctx* c, int prec, const double* a_dev, const void* x, const double* b_dev, void* y, size_t n,
+             int nrhs);
+// convert between precisions with a per-rhs real scale (scale_dev may be NULL = 1)
+int mg_convert(mglma_ctx* c, int pin, const void* x, int pout, void* y, size_t n, int nrhs, const double* scale_dev,
+               int invert_scale);
+int mg_zero(mglma_ctx* c, void* p, size_t bytes);
+int mg_copy(mglma_ctx* c, void* dst, const void* src, size_t bytes);
+
+// subspace
+int mg_restrict(mglma_ctx* c, int prec, const void* fine, void* coarse, int nrhs);
+int mg_prolong(mglma_ctx* c, int prec, const void* coarse, void* fine, int nrhs);
+int mg_coarse_apply(mglma_ctx* c, int prec, int gamma5, const void* in, void* out, int nrhs);
+
+// sizes
+static inline size_t prec_cbytes(int prec) {
+    return prec == MGLMA_F64 ? 16 : prec == MGLMA_F32 ? 8 : 4;
+}

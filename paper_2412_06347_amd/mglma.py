@@ -1,0 +1,244 @@
+"""Thin ctypes binding of libmglma.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module only passes device
+pointers (``torch.Tensor.data_ptr()``), sizes and the current HIP stream.  It
+raises if the library is missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmglma.so")
+
+F64, F32, F16, BF16 = 0, 1, 2, 3
+
+SYMBOLS = [
+    "mglma_create", "mglma_destroy", "mglma_set_stream", "mglma_strerror", "mglma_query",
+    "mglma_resident_bytes", "mglma_fine_bytes", "mglma_coarse_bytes",
+    "mglma_load_gauge", "mglma_export_clover", "mglma_import_fields", "mglma_export_fields",
+    "mglma_apply_D", "mglma_build_subspace", "mglma_export_basis", "mglma_export_coarse_op",
+    "mglma_restrict", "mglma_prolong", "mglma_coarse_apply", "mglma_set_top_modes",
+    "mglma_solve", "mglma_coarse_solve", "mglma_subspace_pieces",
+    "mglma_point_sources", "mglma_noise_sources",
+    "mglma_contract_point", "mglma_contract_point_coarse", "mglma_contract_stoch",
+    "mglma_contract_stoch_coarse", "mglma_contract_top",
+]
+
+
+class Lattice(C.Structure):
+    _fields_ = [("L", C.c_int * 4), ("block", C.c_int * 4), ("kappa", C.c_double),
+                ("csw", C.c_double), ("bc", C.c_double * 4)]
+
+
+class SolveParams(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_outer", C.c_int), ("max_inner", C.c_int),
+                ("gcr_m", C.c_int), ("inner_tol", C.c_double), ("nu_post", C.c_int),
+                ("coarse_iters", C.c_int), ("smoother", C.c_int), ("inner", C.c_int),
+                ("coarse", C.c_int), ("use_mg", C.c_int)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("outer", C.c_int), ("inner", C.c_int), ("coarse", C.c_int),
+                ("true_rel_res", C.c_double), ("seconds", C.c_double), ("status", C.c_int)]
+
+
+class MglmaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("mglma error %d: %s" % (code, msg))
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libmglma.so not built (run __graft_entry__.build() or "
+                              "python -m paper_2412_06347_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        L.mglma_strerror.restype = C.c_char_p
+        L.mglma_query.restype = C.c_long
+        L.mglma_resident_bytes.restype = C.c_size_t
+        L.mglma_fine_bytes.restype = C.c_size_t
+        L.mglma_coarse_bytes.restype = C.c_size_t
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise MglmaError(rc, lib().mglma_strerror(rc).decode())
+    return rc
+
+
+def _ptr(t):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+def default_params(**kw):
+    p = SolveParams(tol=1e-10, max_outer=12, max_inner=200, gcr_m=16, inner_tol=1e-5,
+                    nu_post=4, coarse_iters=16, smoother=F32, inner=F32, coarse=F32, use_mg=1)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+class Context:
+    """One lattice + its resident gauge field, subspace and top level."""
+
+    def __init__(self, L, block, kappa, csw, bc=(-1.0, 1.0, 1.0, 1.0), stream=None):
+        import torch
+        self.L = tuple(int(x) for x in L)
+        self.block = tuple(int(x) for x in block)
+        lat = Lattice((C.c_int * 4)(*self.L), (C.c_int * 4)(*self.block), float(kappa),
+                      float(csw), (C.c_double * 4)(*bc))
+        self._ctx = C.c_void_p()
+        _check(lib().mglma_create(C.byref(self._ctx), C.byref(lat), C.c_void_p(0)))
+        self.set_stream(stream if stream is not None else torch.cuda.current_stream())
+
+    def set_stream(self, stream):
+        self.stream = stream
+        _check(lib().mglma_set_stream(self._ctx, C.c_void_p(stream.cuda_stream)))
+
+    def close(self):
+        if self._ctx:
+            lib().mglma_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- sizes ----------------------------------------------------------
+    def query(self, what):
+        return int(lib().mglma_query(self._ctx, what))
+
+    @property
+    def V(self):
+        return self.query(0)
+
+    @property
+    def V1(self):
+        return self.query(1)
+
+    @property
+    def nc(self):
+        return self.query(4)
+
+    @property
+    def r(self):
+        return self.query(6)
+
+    def resident_bytes(self):
+        return int(lib().mglma_resident_bytes(self._ctx))
+
+    # ---- allocation helpers (device memory from torch) ------------------
+    def fine(self, nrhs, prec=F64, device="cuda"):
+        import torch
+        per = {F64: torch.float64, F32: torch.float32, F16: torch.float16}[prec]
+        return torch.empty((nrhs, 12, self.V, 2), dtype=per, device=device)
+
+    def coarse(self, nrhs, device="cuda"):
+        import torch
+        return torch.empty((nrhs, self.V1, self.nc, 2), dtype=torch.float64, device=device)
+
+    def coarse32(self, nrhs, device="cuda"):
+        import torch
+        return torch.empty((nrhs, self.V1, self.nc, 2), dtype=torch.float32, device=device)
+
+    # ---- fine level -------------------------------------------------------
+    def load_gauge(self, U):
+        _check(lib().mglma_load_gauge(self._ctx, _ptr(U)))
+
+    def export_clover(self, out):
+        _check(lib().mglma_export_clover(self._ctx, _ptr(out)))
+
+    def import_fields(self, canon, dev, prec=F64):
+        _check(lib().mglma_import_fields(self._ctx, prec, _ptr(canon), _ptr(dev), canon.shape[0]))
+
+    def export_fields(self, dev, canon, prec=F64):
+        _check(lib().mglma_export_fields(self._ctx, prec, _ptr(dev), _ptr(canon), dev.shape[0]))
+
+    def apply_D(self, x, y, prec=F64, gamma5=0):
+        _check(lib().mglma_apply_D(self._ctx, prec, gamma5, _ptr(x), _ptr(y), x.shape[0]))
+
+    # ---- subspace ---------------------------------------------------------
+    def build_subspace(self, testvecs):
+        _check(lib().mglma_build_subspace(self._ctx, testvecs.shape[0], _ptr(testvecs)))
+
+    def export_basis(self, out):
+        _check(lib().mglma_export_basis(self._ctx, _ptr(out)))
+
+    def export_coarse_op(self, out):
+        _check(lib().mglma_export_coarse_op(self._ctx, _ptr(out)))
+
+    def restrict(self, fine, coarse, prec=F64):
+        _check(lib().mglma_restrict(self._ctx, prec, _ptr(fine), _ptr(coarse), fine.shape[0]))
+
+    def prolong(self, coarse, fine, prec=F64):
+        _check(lib().mglma_prolong(self._ctx, prec, _ptr(coarse), _ptr(fine), coarse.shape[0]))
+
+    def coarse_apply(self, x, y, prec=F64, gamma5=0):
+        _check(lib().mglma_coarse_apply(self._ctx, prec, gamma5, _ptr(x), _ptr(y), x.shape[0]))
+
+    def set_top_modes(self, modes):
+        _check(lib().mglma_set_top_modes(self._ctx, modes.shape[0], _ptr(modes)))
+
+    # ---- solves -------------------------------------------------------------
+    def solve(self, b, x, params=None, raise_on_error=True):
+        n = b.shape[0]
+        st = (SolveStats * max(n, 1))()
+        rc = lib().mglma_solve(self._ctx, C.byref(params or default_params()), _ptr(b), _ptr(x), n, st)
+        if raise_on_error:
+            _check(rc)
+        return rc, [dict(outer=s.outer, inner=s.inner, coarse=s.coarse, true_rel_res=s.true_rel_res,
+                         seconds=s.seconds, status=s.status) for s in st[:n]]
+
+    def coarse_solve(self, b, x, params=None):
+        n = b.shape[0]
+        st = (SolveStats * max(n, 1))()
+        _check(lib().mglma_coarse_solve(self._ctx, C.byref(params or default_params()), _ptr(b), _ptr(x), n, st))
+        return [dict(outer=s.outer, inner=s.inner, true_rel_res=s.true_rel_res) for s in st[:n]]
+
+    def subspace_pieces(self, eta, ge1, top=None, params=None):
+        _check(lib().mglma_subspace_pieces(self._ctx, C.byref(params or default_params()), _ptr(eta),
+                                           _ptr(ge1), _ptr(top), eta.shape[0]))
+
+    # ---- sources and contractions --------------------------------------------
+    def point_sources(self, y, out):
+        _check(lib().mglma_point_sources(self._ctx, (C.c_int * 4)(*y), _ptr(out)))
+
+    def noise_sources(self, xi, t, out):
+        t = np.ascontiguousarray(t, dtype=np.int32)
+        _check(lib().mglma_noise_sources(self._ctx, xi.shape[0], _ptr(xi),
+                                         t.ctypes.data_as(C.POINTER(C.c_int)), _ptr(out)))
+
+    def _corr(self, fn, a, b, t0):
+        out = np.zeros((self.L[0], 2), dtype=np.float64)
+        _check(fn(self._ctx, _ptr(a), _ptr(b), int(t0), out.ctypes.data_as(C.c_void_p)))
+        return out[:, 0] + 1j * out[:, 1]
+
+    def contract_point(self, psi_i, psi_j, y0):
+        return self._corr(lib().mglma_contract_point, psi_i, psi_j, y0)
+
+    def contract_point_coarse(self, ci, cj, y0):
+        return self._corr(lib().mglma_contract_point_coarse, ci, cj, y0)
+
+    def contract_stoch(self, psi_i, psi_j, tn):
+        return self._corr(lib().mglma_contract_stoch, psi_i, psi_j, tn)
+
+    def contract_stoch_coarse(self, ci, cj, tn):
+        return self._corr(lib().mglma_contract_stoch_coarse, ci, cj, tn)
+
+    def contract_top(self):
+        out = np.zeros((self.L[0], 2), dtype=np.float64)
+        _check(lib().mglma_contract_top(self._ctx, out.ctypes.data_as(C.c_void_p)))
+        return out[:, 0] + 1j * out[:, 1]
