@@ -1,0 +1,327 @@
+#!/usr/bin/env python3
+"""Benchmark of the MG low-mode-averaging hot path on one MI355X.
+
+One step = one pass of the whole hot path over one synthetic gauge field:
+clover build, block basis (Gram-Schmidt), Galerkin coarse operator, coarse
+gammas, exact top level, 12 point sources, the 12 mixed-precision MG solves
+to a true FP64 relative residual of 1e-10, the coarse-level pieces
+D_1^{-1} R eta and W D_2^{-1} W^+ R eta, and the contractions (fine point
+correlator, coarse-route correlators, exact top term, level sums).
+
+Prints ONE JSON line (rank 0).  Only N = 1 GPU is supported.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+WORKLOADS = {
+    # 24^3 x 48, eps = 0.25, kappa = 0.125, c_sw = 1, 12 point-source RHS batched,
+    # 4^4 blocks, Nv = 24 test vectors, Nlm = 16 top modes
+    "24c48": dict(L=(48, 24, 24, 24), block=(4, 4, 4, 4), eps=0.25, kappa=0.125, csw=1.0, Nv=24, Nlm=16,
+                  seed=3),
+    # 16^3 x 32, eps = 0.3, kappa = 0.124
+    "16c32": dict(L=(32, 16, 16, 16), block=(4, 4, 4, 4), eps=0.3, kappa=0.124, csw=1.0, Nv=24, Nlm=16, seed=2),
+    # 4^4, eps = 0.3, kappa = 0.120, 2^4 blocks
+    "4c4": dict(L=(4, 4, 4, 4), block=(2, 2, 2, 2), eps=0.3, kappa=0.120, csw=1.0, Nv=8, Nlm=4, seed=1),
+}
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def mixed_params(mglma, **kw):
+    p = dict(tol=1e-10, max_outer=10, max_inner=120, gcr_m=8, inner_tol=1e-5, nu_post=4, coarse_iters=16,
+             smoother=mglma.F32, inner=mglma.F32, coarse=mglma.BF16, use_mg=1)
+    p.update(kw)
+    return mglma.default_params(**p)
+
+
+def fp64_params(mglma, **kw):
+    p = dict(tol=1e-10, max_outer=3, max_inner=400, gcr_m=8, inner_tol=1e-11, nu_post=4, coarse_iters=16,
+             smoother=mglma.F64, inner=mglma.F64, coarse=mglma.F64, use_mg=1)
+    p.update(kw)
+    return mglma.default_params(**p)
+
+
+class Pipeline:
+    """Resident inputs and the step of the hot path."""
+
+    def __init__(self, wl, log_setup=True):
+        import torch
+        from paper_2412_06347_amd import mglma, synth
+        self.torch, self.mglma, self.synth = torch, mglma, synth
+        self.wl = wl
+        L = wl["L"]
+        t0 = time.time()
+        U = synth.gauge_field(L, wl["eps"], wl["seed"])
+        self.U = torch.from_numpy(U.view(np.float64)).cuda()
+        del U
+        self.ctx = mglma.Context(L, wl["block"], wl["kappa"], wl["csw"])
+        ctx = self.ctx
+        ctx.load_gauge(self.U)
+        # test vectors: Gaussian fields improved by three rounds of approximate
+        # inverse iteration (unpreconditioned FP32 GCR steps) -- an input to the
+        # hot path, prepared outside the timed region
+        tv = synth.gaussian_fields(wl["Nv"], L, wl["seed"] + 1000)
+        x = ctx.fine(wl["Nv"])
+        ctx.import_fields(torch.from_numpy(tv.view(np.float64)).cuda(), x)
+        del tv
+        y = ctx.fine(wl["Nv"])
+        p = mglma.default_params(use_mg=0, inner=mglma.F32, max_outer=1, max_inner=12, gcr_m=12, tol=1e-30,
+                                 inner_tol=1e-30)
+        for _ in range(3):
+            ctx.solve(x, y, p, raise_on_error=False)
+            nrm = torch.linalg.vector_norm(y.reshape(wl["Nv"], -1), dim=1)
+            x = (y / nrm[:, None, None, None]).contiguous()
+        self.tv = x
+        del y
+        # top modes: restricted test vectors refined by two coarse inverse iterations
+        ctx.build_subspace(self.tv)
+        nc, V1 = ctx.nc, ctx.V1
+        m = ctx.coarse(wl["Nv"])
+        ctx.restrict(self.tv, m)
+        m = m[: wl["Nlm"]].contiguous()
+        cp = mglma.default_params(tol=1e-3, coarse=mglma.BF16, coarse_iters=16)
+        for _ in range(2):
+            z = torch.empty_like(m)
+            ctx.coarse_solve(m, z, cp)
+            nrm = torch.linalg.vector_norm(z.reshape(wl["Nlm"], -1), dim=1)
+            m = (z / nrm[:, None, None, None]).contiguous()
+        self.modes = m
+        self.src = ctx.fine(12)
+        self.x = ctx.fine(12)
+        self.cg = ctx.coarse(12)
+        self.ct = ctx.coarse(12)
+        torch.cuda.synchronize()
+        if log_setup:
+            log("setup %.1f s (V=%d, V1=%d, nc=%d, resident %.2f GB)" % (time.time() - t0, ctx.V, V1, nc,
+                                                                         ctx.resident_bytes() / 1e9))
+
+    def step(self, params):
+        ctx, mglma = self.ctx, self.mglma
+        ctx.load_gauge(self.U)                         # clover term
+        ctx.build_subspace(self.tv)                    # basis, Galerkin D_1, coarse gammas
+        ctx.set_top_modes(self.modes)                  # W, D_2, (gamma5 gamma_k)_2
+        ctx.point_sources((0, 0, 0, 0), self.src)      # 12 point sources
+        rc, stats = ctx.solve(self.src, self.x, params)
+        cp = mglma.default_params(tol=1e-10, coarse=mglma.BF16, coarse_iters=16)
+        ctx.coarse_pieces(self.src, self.cg, self.ct, cp)
+        C_all = ctx.contract_point(self.x, self.x, 0)
+        C_ge1 = ctx.contract_point_coarse(self.cg, self.cg, 0)
+        C_top = ctx.contract_point_coarse(self.ct, self.ct, 0)
+        G_exact = ctx.contract_top()
+        levels = dict(L0=C_all - C_ge1, L1=C_ge1 - C_top, L2pt=C_top, L2exact=G_exact)
+        return stats, levels
+
+
+def kernel_time(torch, fn, reps, stream):
+    """Average duration of fn() in ms, timed with HIP events on `stream`."""
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def cpu_baseline(wl, budget_s=20.0):
+    """The oracle (numpy FP64, single thread) on a bounded sample of the same
+    workload: restarted GCR(16) iterations on one point-source system of the
+    same lattice; the full-solve time is extrapolated from the per-iteration
+    time and the observed residual reduction rate."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:  # pragma: no cover
+        threadpool_limits = None
+    from oracle import dirac, estimators
+    from paper_2412_06347_amd import synth
+    L = wl["L"]
+    ctx = threadpool_limits(1) if threadpool_limits else None
+    try:
+        U = synth.gauge_field(L, wl["eps"], wl["seed"])
+        D = dirac.WilsonClover(U, L, wl["kappa"], wl["csw"])
+        b = estimators.point_sources(L, (0, 0, 0, 0))[:1]
+        t0 = time.time()
+        D.M(b)
+        t_apply = time.time() - t0
+        # GCR iterations within the budget (each iteration ~ one apply + vector algebra)
+        x = np.zeros_like(b)
+        r = b.copy()
+        bn = np.linalg.norm(b)
+        P, AP = [], []
+        it = 0
+        t0 = time.time()
+        while time.time() - t0 < budget_s and it < 400:
+            if len(P) == 16:
+                P, AP = [], []
+            p = r.copy()
+            ap = D.M(p)
+            for q, aq in zip(P, AP):
+                beta = np.vdot(aq, ap)
+                ap = ap - beta * aq
+                p = p - beta * q
+            nrm = np.linalg.norm(ap)
+            ap /= nrm
+            p /= nrm
+            alpha = np.vdot(ap, r)
+            x += alpha * p
+            r -= alpha * ap
+            P.append(p)
+            AP.append(ap)
+            it += 1
+        t_it = (time.time() - t0) / it
+        res = np.linalg.norm(r) / bn
+        rate = np.log(res) / it
+        iters_needed = np.log(1e-10) / rate if rate < 0 else float("inf")
+        solves_per_s = 1.0 / (t_it * iters_needed)
+        return dict(value=float(solves_per_s), unit="solves/s", cores=1, kind="oracle",
+                    sample="numpy FP64 oracle, 1 thread: %d GCR(16) iterations (%.1f s, one apply %.2f s) on one "
+                           "point-source system of the %s lattice reduced the residual to %.2e; full solve to 1e-10 "
+                           "extrapolated at that rate to %.0f iterations" % (it, t_it * it, t_apply,
+                                                                             "x".join(map(str, L)), res,
+                                                                             iters_needed))
+    finally:
+        if ctx is not None:
+            ctx.__exit__(None, None, None)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="24c48", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison step")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--calib-copy", action="store_true", help="only run a plain 1 GiB device copy (counter scale)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one MI355X only: the hot path runs on a single GPU "
+              "(multi-GPU sharding is not built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if args.calib_copy:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes_read": a.numel() * 8, "copies": 3}))
+        return
+    from paper_2412_06347_amd import mglma
+    wl = WORKLOADS[args.workload]
+    P = Pipeline(wl)
+    stream = torch.cuda.current_stream()
+    params = mixed_params(mglma)
+    for _ in range(args.warmup):
+        P.step(params)
+    torch.cuda.synchronize()
+    lat = []
+    stats = levels = None
+    t_all0 = time.perf_counter()
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        stats, levels = P.step(params)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+    t_all = time.perf_counter() - t_all0
+    nsolve = 12 * args.steps
+    value = nsolve / t_all
+    res = max(s["true_rel_res"] for s in stats)
+    log("mixed: %.3f s/step, max true rel res %.2e, outer %s inner %s" % (
+        t_all / args.steps, res, [s["outer"] for s in stats][:1], [s["inner"] for s in stats][:1]))
+    out = {}
+    # FP64 comparison (same pipeline, every precision FP64)
+    fp64 = None
+    if not args.no_fp64:
+        t0 = time.perf_counter()
+        st64, lv64 = P.step(fp64_params(mglma))
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t0
+        fp64 = dict(solves_per_s=12 / t64, s_per_step=t64, max_true_rel_res=max(s["true_rel_res"] for s in st64),
+                    corr_L0_rel_diff_vs_mixed=float(np.linalg.norm(lv64["L0"] - levels["L0"]) /
+                                                    np.linalg.norm(lv64["L0"])))
+        log("fp64: %.3f s/step" % t64)
+    # dominant kernel: FP32 Wilson-clover apply on the 12-RHS batch, HIP events on the library's stream
+    ctx = P.ctx
+    V = ctx.V
+    x32 = ctx.fine(12, mglma.F32)
+    y32 = ctx.fine(12, mglma.F32)
+    x32.normal_()
+    ms32 = kernel_time(torch, lambda: ctx.apply_D(x32, y32, mglma.F32), 20, stream)
+    nr = 12
+    alg_bytes_32 = V * (144 + 48 * nr) * 4
+    ach = alg_bytes_32 / (ms32 * 1e-3) / 1e9
+    x64 = ctx.fine(1, mglma.F64)
+    y64 = ctx.fine(1, mglma.F64)
+    x64.normal_()
+    ms64 = kernel_time(torch, lambda: ctx.apply_D(x64, y64, mglma.F64), 20, stream)
+    x16 = ctx.fine(1, mglma.F16)
+    y16 = ctx.fine(1, mglma.F16)
+    x16.normal_()
+    ms16 = kernel_time(torch, lambda: ctx.apply_D(x16, y16, mglma.F16), 20, stream)
+    x1 = ctx.fine(1, mglma.F32)
+    y1 = ctx.fine(1, mglma.F32)
+    x1.normal_()
+    ms1 = kernel_time(torch, lambda: ctx.apply_D(x1, y1, mglma.F32), 20, stream)
+    dslash_gbs = {
+        "f64_1rhs": V * 192 * 8 / (ms64 * 1e-3) / 1e9,
+        "f32_1rhs": V * 192 * 4 / (ms1 * 1e-3) / 1e9,
+        "f16_1rhs": V * 192 * 2 / (ms16 * 1e-3) / 1e9,
+        "f32_12rhs": ach,
+    }
+    traffic = None
+    tf = os.environ.get("MGLMA_TRAFFIC_JSON")
+    if tf and os.path.exists(tf):
+        traffic = json.load(open(tf)).get("dslash_f32_12rhs_bytes")
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(wl, args.cpu_budget)
+    L = wl["L"]
+    line = {
+        "metric": "MG solves/s to rel. residual 1e-10 (mixed vs FP64); Dslash HBM GB/s; p50/p99 latency",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t_all / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+bf16 inner, f64 outer",
+        "data": "synthetic",
+        "config": {"workload": "%dx%d^3 Wilson-clover, eps=%g, kappa=%g, c_sw=%g, %d^4 blocks, Nv=%d, Nlm=%d, "
+                               "12 point-source RHS batched, mixed-precision MG-GCR to 1e-10" %
+                               (L[0], L[1], wl["eps"], wl["kappa"], wl["csw"], wl["block"][0], wl["Nv"], wl["Nlm"]),
+                   "lattice": list(L), "block": list(wl["block"]), "nrhs": 12},
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                      "unit": "s per 12-RHS step"},
+        "max_true_rel_res": res,
+        "fp64_path": fp64,
+        "speedup_mixed_vs_fp64": (value / fp64["solves_per_s"]) if fp64 else None,
+        "dslash_GBs": dslash_gbs,
+        "roofline": {"bound": "hbm", "kernel": "k_dslash<float2,float2,float> (12 RHS)", "achieved": ach,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                     "traffic": traffic, "avg_ms": ms32},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -143,6 +143,11 @@ int mglma_export_basis(mglma_ctx* ctx, double* out_dev);
 /* Export D_1 as [V1][9][nc][nc] complex128; direction 0 = self, 1+2mu = +mu
  * neighbour, 2+2mu = -mu neighbour; row index = output.                     */
 int mglma_export_coarse_op(mglma_ctx* ctx, double* out_dev);
+/* Export (gamma5 gamma_k)_1 restricted to the fine time slice y0*b0 + t of
+ * coarse site y: [V1][b0][3][Nv][Nv] complex128, rows = alpha 0 basis
+ * vectors, columns = alpha 1 basis vectors (the alpha 1 x alpha 0 block is
+ * minus its adjoint, the diagonal blocks vanish).  For tests.              */
+int mglma_export_coarse_gammas(mglma_ctx* ctx, double* out_dev);
 /* coarse = R fine (eq:res_mg), fine = T coarse (eq:pro_mg); F64 or F32.     */
 int mglma_restrict(mglma_ctx* ctx, int prec, const void* fine_dev, void* coarse_dev, int nrhs);
 int mglma_prolong(mglma_ctx* ctx, int prec, const void* coarse_dev, void* fine_dev, int nrhs);
@@ -173,12 +178,15 @@ int mglma_solve(mglma_ctx* ctx, const mglma_solve_params* p, const double* b_dev
  * correction.  Synchronising.                                               */
 int mglma_coarse_solve(mglma_ctx* ctx, const mglma_solve_params* p, const double* b_dev,
                        double* x_dev, int nrhs, mglma_solve_stats* stats);
-/* Apply the level pieces to solved/sourced fields (device layout, F64):
- *   ge1 = T D_1^{-1} R eta   (S_1 + S_2 for three levels, S_1 for two)
- *   top = T W D_2^{-1} W^+ R eta   (needs the top level; may be NULL)
- * Synchronising.                                                            */
-int mglma_subspace_pieces(mglma_ctx* ctx, const mglma_solve_params* p, const double* eta_dev,
-                          double* ge1_dev, double* top_dev, int nrhs);
+/* Coarse-level propagator pieces for fine sources eta (device layout, F64):
+ *   ge1_dev = D_1^{-1} R eta            (so T ge1 = T D_1^{-1} R eta is S_1 for
+ *                                        two levels, S_1 + S_2 for three)
+ *   top_dev = W D_2^{-1} W^+ R eta      (T top = S_2; needs the top level,
+ *                                        may be NULL)
+ * Outputs are coarse fields (F64).  The coarse solve stops at p->tol.
+ * Synchronising.  Errors: NO_SUBSPACE, NO_TOP, NOT_CONVERGED.              */
+int mglma_coarse_pieces(mglma_ctx* ctx, const mglma_solve_params* p, const double* eta_dev,
+                        double* ge1_dev, double* top_dev, int nrhs);
 
 /* ---- sources ------------------------------------------------------------- */
 /* The 12 point sources e_{y,(s,c)}, column index 3*s + c, F64 device layout. */

@@ -1,0 +1,246 @@
+// Contractions of the isovector vector correlator.
+//
+// All of them are sums over a time slice of bilinears psi_b(x)^+ G_k psi_a(x)
+// with G_k = gamma5 gamma_k (k = 1..3), weighted by a source-side spin factor:
+//  * point source (eq:tmr with one source position y):
+//      C(y0+t, y0) = -1/3 sum_k sum_{a,b} (gamma_k gamma5)_{ab} sum_x psi^j_b(x)^+ G_k psi^i_a(x),
+//    a, b = (spin, colour) source indices with equal colour, using
+//    S(y,x) = gamma5 S(x,y)^+ gamma5;
+//  * stochastic spin-diluted wall source (eq:C_stoch2):
+//      G^n(t_n+t, t_n) = -1/(3 L^3) sum_k sum_s conj((gamma5 gamma_k^+)_{s's}) sum_x
+//                        (S_j eta^{(s')})^+ G_k (S_i eta^{(s)}),  s' the row of column s;
+//  * the same on coarse vectors through (gamma5 gamma_k)_1 per block time
+//    slice (eq:coarse:gamma), so fields T c are never formed.
+// In the chiral basis G_k = [[0, m_k], [m_k, 0]] with m_k = -i sigma_k, one
+// entry per row and column.
+//
+// Each site (coarse site and block slice) writes its weighted density; a
+// second pass adds the densities of every time slice in a fixed order, so the
+// result does not depend on launch or batch composition.
+#include "mglma_internal.h"
+
+struct Term {
+    int a, b, k;      // field of set i, field of set j, gamma index
+    double cre, cim;  // weight
+};
+#define MAXTERMS 36
+struct TermList {
+    Term t[MAXTERMS];
+    int n;
+};
+
+// point-source terms: for each k and source spin s_a and colour c:
+// b = (s_b, c) with s_b the column of row s_a of gamma_k gamma5 = -G_k
+static TermList point_terms() {
+    TermList L;
+    L.n = 0;
+    for (int k = 1; k <= 3; ++k)
+        for (int sa = 0; sa < 4; ++sa) {
+            int sb;
+            double cr, ci;
+            gk_row(k, sa, &sb, &cr, &ci);
+            for (int col = 0; col < 3; ++col) {
+                Term& T = L.t[L.n++];
+                T.a = 3 * sa + col;
+                T.b = 3 * sb + col;
+                T.k = k;
+                // -1/3 * (gamma_k gamma5)_{sa sb} = -1/3 * (-G_k[sa][sb])
+                T.cre = cr / 3.0;
+                T.cim = ci / 3.0;
+            }
+        }
+    return L;
+}
+
+// stochastic terms: for each k and source spin s: s' = row of the entry in column s
+static TermList stoch_terms(double L3) {
+    TermList L;
+    L.n = 0;
+    for (int k = 1; k <= 3; ++k)
+        for (int sp = 0; sp < 4; ++sp) {
+            int s;
+            double cr, ci;
+            gk_row(k, sp, &s, &cr, &ci);   // G_k[sp][s] = (cr, ci)
+            Term& T = L.t[L.n++];
+            T.a = s;
+            T.b = sp;
+            T.k = k;
+            // -1/(3 L^3) conj(G_k[s'][s])
+            T.cre = -cr / (3.0 * L3);
+            T.cim = ci / (3.0 * L3);
+        }
+    return L;
+}
+
+// density[i] = sum_terms w * psi^j_b(x)^+ G_k psi^i_a(x)
+__global__ __launch_bounds__(256) void k_fine_density(Geo g, const double2* __restrict__ pi,
+                                                      const double2* __restrict__ pj, TermList T,
+                                                      double2* __restrict__ dens) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.V) return;
+    const size_t V = g.V;
+    cx<double> tot = cmk(0.0, 0.0);
+    for (int q = 0; q < T.n; ++q) {
+        const Term tm = T.t[q];
+        const double2* A = pi + (size_t)tm.a * 12 * V + i;
+        const double2* B = pj + (size_t)tm.b * 12 * V + i;
+        cx<double> s = cmk(0.0, 0.0);
+        for (int sp = 0; sp < 4; ++sp) {
+            int tc;
+            double cr, ci;
+            gk_row(tm.k, sp, &tc, &cr, &ci);
+            cx<double> acc = cmk(0.0, 0.0);
+            for (int col = 0; col < 3; ++col)
+                cjmac(acc, ldc<double2, double>(B + (size_t)(3 * sp + col) * V),
+                      ldc<double2, double>(A + (size_t)(3 * tc + col) * V));
+            s = s + cmk(cr, ci) * acc;
+        }
+        tot = tot + cmk(tm.cre, tm.cim) * s;
+    }
+    dens[i] = make_double2(tot.re, tot.im);
+}
+
+// out[x0] = sum over the spatial sites of slice x0 (lexicographic order)
+__global__ __launch_bounds__(256) void k_slice_sum(Geo g, const double2* __restrict__ dens, double2* __restrict__ out) {
+    const int x0 = blockIdx.x;
+    __shared__ double lre[256], lim[256];
+    double re = 0.0, im = 0.0;
+    for (int xs = threadIdx.x; xs < g.V3; xs += blockDim.x) {
+        int x[4];
+        int r = xs;
+        x[3] = r % g.L[3]; r /= g.L[3];
+        x[2] = r % g.L[2]; r /= g.L[2];
+        x[1] = r;
+        x[0] = x0;
+        double2 v = dens[geo_index(g, x)];
+        re += v.x;
+        im += v.y;
+    }
+    lre[threadIdx.x] = re;
+    lim[threadIdx.x] = im;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            lre[threadIdx.x] += lre[threadIdx.x + o];
+            lim[threadIdx.x] += lim[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[x0] = make_double2(lre[0], lim[0]);
+}
+
+// coarse density per (coarse site y, block slice t): sum_terms w * u^+ Gamma1_k(y,t) v,
+// u = c^j_b(y), v = c^i_a(y), Gamma1 = [[0, Gb], [-Gb^+, 0]]:
+//   u^+ Gamma v = u0^+ Gb v1 - conj(v0^+ Gb u1)
+__global__ __launch_bounds__(256) void k_coarse_density(Geo g, int Nv, const double2* __restrict__ G1,
+                                                        const double2* __restrict__ ci,
+                                                        const double2* __restrict__ cj, TermList T,
+                                                        double2* __restrict__ dens) {
+    const int y = blockIdx.x / g.b[0], t = blockIdx.x % g.b[0];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nc = 2 * Nv;
+    const size_t V1 = g.V1;
+    __shared__ double wre[4], wim[4];
+    cx<double> wt = cmk(0.0, 0.0);   // this wave's weighted sum (lane 0)
+    for (int q = w; q < T.n; q += 4) {
+        const Term tm = T.t[q];
+        const double2* Gb = G1 + (((size_t)y * g.b[0] + t) * 3 + (tm.k - 1)) * Nv * Nv;
+        const double2* u = cj + ((size_t)tm.b * V1 + y) * nc;
+        const double2* v = ci + ((size_t)tm.a * V1 + y) * nc;
+        cx<double> s1 = cmk(0.0, 0.0), s2 = cmk(0.0, 0.0);
+        for (int cd = lane; cd < Nv * Nv; cd += 64) {
+            int c = cd / Nv, d = cd % Nv;
+            cx<double> gcd = ldc<double2, double>(Gb + cd);
+            cx<double> t1 = gcd * ldc<double2, double>(v + Nv + d);
+            cjmac(s1, ldc<double2, double>(u + c), t1);
+            cx<double> t2 = gcd * ldc<double2, double>(u + Nv + d);
+            cjmac(s2, ldc<double2, double>(v + c), t2);
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            s1.re += __shfl_xor(s1.re, o, 64); s1.im += __shfl_xor(s1.im, o, 64);
+            s2.re += __shfl_xor(s2.re, o, 64); s2.im += __shfl_xor(s2.im, o, 64);
+        }
+        cx<double> val = s1 - conj(s2);
+        wt = wt + cmk(tm.cre, tm.cim) * val;
+    }
+    if (lane == 0) { wre[w] = wt.re; wim[w] = wt.im; }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        dens[blockIdx.x] = make_double2(wre[0] + wre[1] + wre[2] + wre[3], wim[0] + wim[1] + wim[2] + wim[3]);
+}
+
+// out[x0] = sum over the coarse sites of time row x0 / b0 of dens[y][x0 % b0]
+__global__ void k_coarse_slice_sum(Geo g, const double2* __restrict__ dens, double2* __restrict__ out) {
+    const int x0 = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x0 >= g.L[0]) return;
+    const int b0 = g.b[0], y0 = x0 / b0, t = x0 % b0, rowsz = g.V1 / g.L1[0];
+    double re = 0.0, im = 0.0;
+    for (int ys = 0; ys < rowsz; ++ys) {
+        double2 v = dens[(size_t)(y0 * rowsz + ys) * b0 + t];
+        re += v.x;
+        im += v.y;
+    }
+    out[x0] = make_double2(re, im);
+}
+
+static int finish_host(mglma_ctx* c, const double2* out_dev, int t0, double* C_host) {
+    const int L0 = c->L[0];
+    double* h;
+    MG_TRY(mg_host(c, 2 * (size_t)L0, &h));
+    HIP_TRY(hipMemcpyAsync(h, out_dev, (size_t)L0 * 16, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int t = 0; t < L0; ++t) {
+        int x0 = (t0 + t) % L0;
+        C_host[2 * t] = h[2 * x0];
+        C_host[2 * t + 1] = h[2 * x0 + 1];
+    }
+    return MGLMA_OK;
+}
+
+static int fine_contract(mglma_ctx* c, const double* pi, const double* pj, const TermList& T, int t0, double* C) {
+    const Geo& g = c->geo;
+    double2 *dens, *out;
+    MG_TRY(mg_scratch(c, 28, (size_t)g.V * 16, (void**)&dens));
+    MG_TRY(mg_scratch(c, 29, (size_t)g.L[0] * 16 + 256, (void**)&out));
+    hipLaunchKernelGGL(k_fine_density, dim3((g.V + 255) / 256), dim3(256), 0, c->stream, g, (const double2*)pi,
+                       (const double2*)pj, T, dens);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_slice_sum, dim3(g.L[0]), dim3(256), 0, c->stream, g, dens, out);
+    HIP_TRY(hipGetLastError());
+    return finish_host(c, out, t0, C);
+}
+
+static int coarse_contract(mglma_ctx* c, const double* ci, const double* cj, const TermList& T, int t0, double* C) {
+    const Geo& g = c->geo;
+    double2 *dens, *out;
+    MG_TRY(mg_scratch(c, 28, (size_t)g.V1 * g.b[0] * 16, (void**)&dens));
+    MG_TRY(mg_scratch(c, 29, (size_t)g.L[0] * 16 + 256, (void**)&out));
+    hipLaunchKernelGGL(k_coarse_density, dim3(g.V1 * g.b[0]), dim3(256), 0, c->stream, g, c->Nv, c->G1,
+                       (const double2*)ci, (const double2*)cj, T, dens);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_coarse_slice_sum, dim3((g.L[0] + 63) / 64), dim3(64), 0, c->stream, g, dens, out);
+    HIP_TRY(hipGetLastError());
+    return finish_host(c, out, t0, C);
+}
+
+extern "C" int mglma_contract_point(mglma_ctx* c, const double* pi, const double* pj, int y0, double* C) {
+    if (!c || !pi || !pj || !C || y0 < 0 || y0 >= (c ? c->L[0] : 0)) return MGLMA_ERR_ARG;
+    return fine_contract(c, pi, pj, point_terms(), y0, C);
+}
+
+extern "C" int mglma_contract_point_coarse(mglma_ctx* c, const double* ci, const double* cj, int y0, double* C) {
+    if (!c || !ci || !cj || !C || y0 < 0 || y0 >= (c ? c->L[0] : 0)) return MGLMA_ERR_ARG;
+    if (!c->have_subspace) return MGLMA_ERR_NO_SUBSPACE;
+    return coarse_contract(c, ci, cj, point_terms(), y0, C);
+}
+
+extern "C" int mglma_contract_stoch(mglma_ctx* c, const double* pi, const double* pj, int tn, double* C) {
+    if (!c || !pi || !pj || !C || tn < 0 || tn >= (c ? c->L[0] : 0)) return MGLMA_ERR_ARG;
+    return fine_contract(c, pi, pj, stoch_terms((double)c->geo.V3), tn, C);
+}
+
+extern "C" int mglma_contract_stoch_coarse(mglma_ctx* c, const double* ci, const double* cj, int tn, double* C) {
+    if (!c || !ci || !cj || !C || tn < 0 || tn >= (c ? c->L[0] : 0)) return MGLMA_ERR_ARG;
+    if (!c->have_subspace) return MGLMA_ERR_NO_SUBSPACE;
+    return coarse_contract(c, ci, cj, stoch_terms((double)c->geo.V3), tn, C);
+}

@@ -156,7 +156,6 @@ extern "C" int mglma_create(mglma_ctx** out, const mglma_lattice* lat, void* str
     return MGLMA_OK;
 }
 
-static void free_subspace(mglma_ctx* c);
 static void free_top(mglma_ctx* c) {
     const Geo& g = c->geo;
     mg_free(c, c->W, (size_t)c->r * g.V1 * c->nc * 16);
@@ -166,7 +165,7 @@ static void free_top(mglma_ctx* c) {
     c->Nlm = c->r = 0;
 }
 
-static void free_subspace(mglma_ctx* c) {
+void mg_free_subspace(mglma_ctx* c) {
     const Geo& g = c->geo;
     free_top(c);
     size_t nb = (size_t)g.V * 12 * c->Nv;
@@ -174,6 +173,7 @@ static void free_subspace(mglma_ctx* c) {
     mg_free(c, c->B32, nb * 8); c->B32 = nullptr;
     size_t nd = (size_t)g.V1 * 9 * c->nc * c->nc;
     mg_free(c, c->D64, nd * 16); c->D64 = nullptr;
+    mg_free(c, c->D64t, nd * 16); c->D64t = nullptr;
     mg_free(c, c->D32, nd * 8); c->D32 = nullptr;
     mg_free(c, c->Dbf, nd * 4); c->Dbf = nullptr;
     mg_free(c, c->G1, (size_t)g.V1 * g.b[0] * 3 * c->Nv * c->Nv * 16); c->G1 = nullptr;
@@ -195,9 +195,9 @@ static void free_gauge(mglma_ctx* c) {
 extern "C" void mglma_destroy(mglma_ctx* c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
-    free_subspace(c);
+    mg_free_subspace(c);
     free_gauge(c);
-    for (int i = 0; i < 8; ++i) mg_free(c, c->scr[i].ptr, c->scr[i].bytes);
+    for (int i = 0; i < 32; ++i) mg_free(c, c->scr[i].ptr, c->scr[i].bytes);
     mg_free(c, c->red_part, c->red_part_n * sizeof(double));
     mg_free(c, c->red_cnt, c->red_cnt_n * sizeof(unsigned));
     if (c->hbuf) (void)hipHostFree(c->hbuf);

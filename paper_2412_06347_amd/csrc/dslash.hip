@@ -184,3 +184,51 @@ extern "C" int mglma_apply_D(mglma_ctx* c, int prec, int gamma5, const void* in,
     if (!c->have_gauge) return MGLMA_ERR_NO_GAUGE;
     return mg_dslash(c, prec, gamma5 ? 1 : 0, in, out, nrhs);
 }
+
+// Pieces of M used to assemble the Galerkin coarse operator (fig:A): for
+// mode 0 the clover term plus the hops that stay inside the sender's block,
+// for mode 1+2mu (2+2mu) only the forward (backward) mu hops that leave the
+// block through its +mu (-mu) face.  FP64 only.
+__global__ __launch_bounds__(256) void k_dslash_piece(Geo g, const double2* __restrict__ in, double2* __restrict__ out,
+                                                      const double2* __restrict__ U, const double2* __restrict__ C,
+                                                      double kappa, int mode) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.V) return;
+    const size_t V = g.V;
+    const size_t roff = (size_t)blockIdx.y * 12 * V;
+    const double2* pin = in + roff;
+    int lc[4], yc[4];
+    geo_coords(g, i, lc, yc);
+    cx<double> acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = cmk(0.0, 0.0);
+#define PIECE(MU)                                                                                   \
+    {                                                                                               \
+        bool cf = lc[MU] == g.b[MU] - 1, cb = lc[MU] == 0;                                          \
+        if (mode == 0 ? !cf : (mode == 1 + 2 * MU && cf))                                           \
+            hop<MU, true, double2, double2, double>(g, i, lc, yc, pin, U, acc);                     \
+        if (mode == 0 ? !cb : (mode == 2 + 2 * MU && cb))                                           \
+            hop<MU, false, double2, double2, double>(g, i, lc, yc, pin, U, acc);                    \
+    }
+    PIECE(0) PIECE(1) PIECE(2) PIECE(3)
+#undef PIECE
+    double2* po = out + roff;
+    for (int ch = 0; ch < 2; ++ch) {
+        cx<double> p[6], res[6];
+        if (mode == 0) {
+            for (int k = 0; k < 6; ++k) p[k] = ldc<double2, double>(pin + (size_t)(6 * ch + k) * V + i);
+            clover_block<double2, double>(C + (size_t)ch * 18 * V, V, i, p, res);
+        } else {
+            for (int k = 0; k < 6; ++k) res[k] = cmk(0.0, 0.0);
+        }
+        for (int k = 0; k < 6; ++k) stc<double2, double>(po + (size_t)(6 * ch + k) * V + i, res[k] - kappa * acc[6 * ch + k]);
+    }
+}
+
+int mg_dslash_piece(mglma_ctx* c, int mode, const double2* in, double2* out, int nrhs) {
+    const Geo& g = c->geo;
+    dim3 grid((g.V + 255) / 256, nrhs);
+    hipLaunchKernelGGL(k_dslash_piece, grid, dim3(256), 0, c->stream, g, in, out, c->U64, c->C64, c->kappa, mode);
+    HIP_TRY(hipGetLastError());
+    return MGLMA_OK;
+}

@@ -195,7 +195,7 @@ struct mglma_ctx {
     // subspace: basis [V1][2][Nv][6][Vb], coarse operator [V1][9][nc][nc]
     int Nv = 0, nc = 0;
     double2* B64 = nullptr; float2* B32 = nullptr;
-    double2* D64 = nullptr; float2* D32 = nullptr;
+    double2* D64 = nullptr; double2* D64t = nullptr; float2* D32 = nullptr;   // D32 column-major
     bf16_t* Dbf = nullptr;       // [V1][9][2][nc][nc] planar re/im bfloat16
     double2* G1 = nullptr;       // coarse gammas [V1][b0][3][Nv][Nv] (alpha=0 rows, alpha=1 cols)
     bool have_subspace = false;
@@ -208,7 +208,7 @@ struct mglma_ctx {
     bool have_top = false;
 
     // reusable scratch (grown on demand) and reduction buffers
-    Scratch scr[8];
+    Scratch scr[32];
     double* red_part = nullptr; size_t red_part_n = 0;
     unsigned* red_cnt = nullptr; size_t red_cnt_n = 0;
     double* hbuf = nullptr; size_t hbuf_n = 0;     // pinned host staging
@@ -255,3 +255,20 @@ int mg_coarse_apply(mglma_ctx* c, int prec, int gamma5, const void* in, void* ou
 static inline size_t prec_cbytes(int prec) {
     return prec == MGLMA_F64 ? 16 : prec == MGLMA_F32 ? 8 : 4;
 }
+int mg_dslash_piece(mglma_ctx* c, int mode, const double2* in, double2* out, int nrhs);
+void mg_free_subspace(mglma_ctx* c);
+
+// ---------------------------------------------------------------------------
+// gamma5 gamma_k in the chiral basis: one entry per row
+// ---------------------------------------------------------------------------
+// (G_k psi)(s) = coef * psi(col) : column and coefficient of row s of gamma5 gamma_k
+__host__ __device__ inline void gk_row(int k, int s, int* t, double* cre, double* cim) {
+    // k = 1..3
+    static const int tcol[3][4] = {{3, 2, 1, 0}, {3, 2, 1, 0}, {2, 3, 0, 1}};
+    static const double re[3][4] = {{0, 0, 0, 0}, {-1, 1, -1, 1}, {0, 0, 0, 0}};
+    static const double im[3][4] = {{-1, -1, -1, -1}, {0, 0, 0, 0}, {-1, 1, -1, 1}};
+    *t = tcol[k - 1][s];
+    *cre = re[k - 1][s];
+    *cim = im[k - 1][s];
+}
+

@@ -1,0 +1,470 @@
+// Solvers: FP64 defect correction around a flexible GCR whose preconditioner
+// is the two-level method built from the block basis (coarse correction with
+// the Galerkin operator, then minimal-residual smoothing on M), and a
+// coarse-level solve.  The paper inverts with GCR-type Krylov solvers on both
+// levels (section "Comparison of the cost"); the precisions are this
+// library's design: FP32 (or FP16-stored) work inside an FP64 outer loop.
+//
+// All Krylov scalars stay on the device; the host reads one norm per
+// right-hand side per fine iteration to decide convergence.
+#include "mglma_internal.h"
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+enum {
+    WS_SCAL = 8, WS_R64, WS_T64, WS_RIN, WS_E, WS_Z, WS_W, WS_RC, WS_EC, WS_CP, WS_CQ, WS_CR, WS_SS, WS_ST, WS_X16,
+    WS_CX64, WS_CR64, WS_CT64, WS_PIECE, WS_COUNT
+};
+
+// ---------------------------------------------------------------------------
+// scalar kernels (per right-hand side)
+// ---------------------------------------------------------------------------
+__global__ void k_rsqrt_c(const double* n2, double* out, int n) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    double v = n2[r];
+    out[2 * r] = v > 0.0 ? 1.0 / sqrt(v) : 0.0;
+    out[2 * r + 1] = 0.0;
+}
+__global__ void k_sqrt_masked(const double* n2, const int* active, double* out, int n) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    out[r] = active[r] ? sqrt(n2[r]) : 0.0;
+}
+// omega = <t,s>/<t,t>  (MR step), stored complex; zero if t = 0
+__global__ void k_mr_omega(const double* ts, const double* tt, double* om, int n) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    double d = tt[r];
+    om[2 * r] = d > 0.0 ? ts[2 * r] / d : 0.0;
+    om[2 * r + 1] = d > 0.0 ? ts[2 * r + 1] / d : 0.0;
+}
+
+template <typename S, typename R>
+__global__ void k_accum(double2* __restrict__ x, const S* __restrict__ e, const double* __restrict__ s, size_t n) {
+    const int r = blockIdx.y;
+    const double sc = s[r];
+    if (sc == 0.0) return;
+    const size_t off = (size_t)r * n;
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+        cx<double> v = ldc<S, double>(e + off + k);
+        double2 a = x[off + k];
+        x[off + k] = make_double2(fma(sc, v.re, a.x), fma(sc, v.im, a.y));
+    }
+}
+// scale = sqrt(n2 / n), or 1 if zero
+__global__ void k_rms(const double* n2, double n, double* out, int nr) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nr) return;
+    double v = sqrt(n2[r] / n);
+    out[r] = v > 0.0 ? v : 1.0;
+}
+
+// s = r - t in any storage precision
+template <typename S, typename R>
+__global__ void k_sub(const S* __restrict__ a, const S* __restrict__ b, S* __restrict__ o, size_t n) {
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
+        stc<S, R>(o + k, ldc<S, R>(a + k) - ldc<S, R>(b + k));
+}
+
+static int mg_sub(mglma_ctx* c, int prec, const void* a, const void* b, void* o, size_t n, int nrhs) {
+    size_t tot = n * (size_t)nrhs;
+    size_t nb = (tot + 1023) / 1024;
+    if (nb > 8192) nb = 8192;
+    switch (prec) {
+        case MGLMA_F64: hipLaunchKernelGGL((k_sub<double2, double>), dim3(nb), dim3(256), 0, c->stream, (const double2*)a, (const double2*)b, (double2*)o, tot); break;
+        case MGLMA_F32: hipLaunchKernelGGL((k_sub<float2, float>), dim3(nb), dim3(256), 0, c->stream, (const float2*)a, (const float2*)b, (float2*)o, tot); break;
+        default: return MGLMA_ERR_ARG;
+    }
+    HIP_TRY(hipGetLastError());
+    return MGLMA_OK;
+}
+
+// r = b - t
+__global__ void k_xmy(const double2* __restrict__ b, const double2* __restrict__ t, double2* __restrict__ r, size_t n) {
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+        double2 u = b[k], v = t[k];
+        r[k] = make_double2(u.x - v.x, u.y - v.y);
+    }
+}
+
+static dim3 grid1(size_t n) {
+    size_t b = (n + 1023) / 1024;
+    if (b > 4096) b = 4096;
+    return dim3((unsigned)(b ? b : 1));
+}
+
+// ---------------------------------------------------------------------------
+// solver state
+// ---------------------------------------------------------------------------
+struct Scal {
+    double* base;
+    int nrhs, m;
+    double* bn2() { return base; }
+    double* rn2() { return base + nrhs; }
+    double* nw2() { return base + 2 * nrhs; }
+    double* tt() { return base + 3 * nrhs; }
+    double* scale() { return base + 4 * nrhs; }
+    double* invc() { return base + 5 * nrhs; }            // complex
+    double* alpha() { return base + 7 * nrhs; }           // complex
+    double* omega() { return base + 9 * nrhs; }           // complex
+    double* ts() { return base + 11 * nrhs; }             // complex
+    double* cn2() { return base + 13 * nrhs; }
+    double* cinv() { return base + 14 * nrhs; }           // complex
+    double* calpha() { return base + 16 * nrhs; }         // complex
+    double* beta() { return base + 18 * nrhs; }           // complex [m][nrhs]
+    double* cbeta() { return base + 18 * nrhs + 2 * m * nrhs; }   // complex [m][nrhs]
+    int* active() { return (int*)(base + 18 * nrhs + 4 * m * nrhs); }
+    double* hscale() { return base + 19 * nrhs + 4 * m * nrhs; }   // half-precision smoother scale
+    static size_t bytes(int nrhs, int m) { return (20 * (size_t)nrhs + 4 * (size_t)m * nrhs) * 8 + 256; }
+};
+
+struct SolveCtx {
+    mglma_ctx* c;
+    const mglma_solve_params* p;
+    int nrhs;
+    Scal s;
+    int coarse_applies = 0;
+};
+
+static inline size_t fine_n(mglma_ctx* c) { return (size_t)c->geo.V * 12; }
+static inline size_t coarse_n(mglma_ctx* c) { return (size_t)c->geo.V1 * c->nc; }
+
+// ---------------------------------------------------------------------------
+// coarse GCR with a fixed number of steps (preconditioner use, no host sync)
+//   vectors in precision vp (F32 or F64), operator precision op
+// ---------------------------------------------------------------------------
+static int coarse_gcr_fixed(SolveCtx& S, int vp, int op, const void* b, void* x, int iters) {
+    mglma_ctx* c = S.c;
+    const int nrhs = S.nrhs;
+    const size_t n = coarse_n(c);
+    const size_t vb = prec_cbytes(vp);
+    const int mc = iters < 8 ? iters : 8;
+    void *P, *Q, *r;
+    MG_TRY(mg_scratch(c, WS_CP, (size_t)mc * nrhs * n * vb, &P));
+    MG_TRY(mg_scratch(c, WS_CQ, (size_t)mc * nrhs * n * vb, &Q));
+    MG_TRY(mg_scratch(c, WS_CR, (size_t)nrhs * n * vb, &r));
+    MG_TRY(mg_zero(c, x, (size_t)nrhs * n * vb));
+    MG_TRY(mg_copy(c, r, b, (size_t)nrhs * n * vb));
+    const size_t setsz = (size_t)nrhs * n;   // elements per vector set
+    for (int k = 0; k < iters; ++k) {
+        int j = k % mc;
+        char* pj = (char*)P + (size_t)j * setsz * vb;
+        char* qj = (char*)Q + (size_t)j * setsz * vb;
+        MG_TRY(mg_copy(c, pj, r, setsz * vb));
+        int opp = op;
+        if (vp == MGLMA_F64) opp = MGLMA_F64;
+        MG_TRY(mg_coarse_apply(c, opp, 0, pj, qj, nrhs));
+        S.coarse_applies++;
+        if (j > 0) {
+            MG_TRY(mg_multidot(c, vp, Q, setsz, j, qj, n, nrhs, S.s.cbeta()));
+            MG_TRY(mg_multiaxpy(c, vp, Q, setsz, j, S.s.cbeta(), -1.0, qj, n, nrhs));
+            MG_TRY(mg_multiaxpy(c, vp, P, setsz, j, S.s.cbeta(), -1.0, pj, n, nrhs));
+        }
+        MG_TRY(mg_norm2(c, vp, qj, n, nrhs, S.s.cn2()));
+        hipLaunchKernelGGL(k_rsqrt_c, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, S.s.cn2(), S.s.cinv(), nrhs);
+        MG_TRY(mg_axpby(c, vp, nullptr, nullptr, S.s.cinv(), qj, n, nrhs));
+        MG_TRY(mg_axpby(c, vp, nullptr, nullptr, S.s.cinv(), pj, n, nrhs));
+        MG_TRY(mg_dot(c, vp, qj, r, n, nrhs, S.s.calpha()));
+        MG_TRY(mg_multiaxpy(c, vp, pj, 0, 1, S.s.calpha(), 1.0, x, n, nrhs));
+        MG_TRY(mg_multiaxpy(c, vp, qj, 0, 1, S.s.calpha(), -1.0, r, n, nrhs));
+    }
+    HIP_TRY(hipGetLastError());
+    return MGLMA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// two-level preconditioner z = B r (fine vectors in precision vp)
+// ---------------------------------------------------------------------------
+static int precondition(SolveCtx& S, int vp, const void* r, void* z) {
+    mglma_ctx* c = S.c;
+    const mglma_solve_params* p = S.p;
+    const int nrhs = S.nrhs;
+    const size_t n = fine_n(c), vb = prec_cbytes(vp);
+    if (!p->use_mg) {
+        MG_TRY(mg_copy(c, z, r, (size_t)nrhs * n * vb));
+        return MGLMA_OK;
+    }
+    const size_t nc = coarse_n(c);
+    void *rc, *ec;
+    MG_TRY(mg_scratch(c, WS_RC, (size_t)nrhs * nc * vb, &rc));
+    MG_TRY(mg_scratch(c, WS_EC, (size_t)nrhs * nc * vb, &ec));
+    // coarse correction
+    MG_TRY(mg_restrict(c, vp, r, rc, nrhs));
+    MG_TRY(coarse_gcr_fixed(S, vp, p->coarse, rc, ec, p->coarse_iters));
+    MG_TRY(mg_prolong(c, vp, ec, z, nrhs));
+    if (p->nu_post <= 0) return MGLMA_OK;
+    // MR smoothing on M z = r: s = r - M z; t = M s; omega = <t,s>/<t,t>; z += omega s; s -= omega t
+    void *s, *t;
+    MG_TRY(mg_scratch(c, WS_SS, (size_t)nrhs * n * vb, &s));
+    MG_TRY(mg_scratch(c, WS_ST, (size_t)nrhs * n * vb, &t));
+    const int sp = (vp == MGLMA_F32 && p->smoother == MGLMA_F16) ? MGLMA_F16 : vp;
+    MG_TRY(mg_dslash(c, vp, 0, z, t, nrhs));
+    MG_TRY(mg_sub(c, vp, r, t, s, n, nrhs));
+    void* s16 = nullptr;
+    if (sp == MGLMA_F16) MG_TRY(mg_scratch(c, WS_X16, (size_t)nrhs * n * 4 * 2, &s16));
+    for (int it = 0; it < p->nu_post; ++it) {
+        if (sp == MGLMA_F16) {
+            // half-precision operator application on a rescaled copy of s
+            void* t16 = (char*)s16 + (size_t)nrhs * n * 4;
+            MG_TRY(mg_norm2(c, vp, s, n, nrhs, S.s.tt()));
+            // scale[r] = rms entry of s: s/scale has entries of order one in half precision
+            hipLaunchKernelGGL(k_rms, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, S.s.tt(), (double)n,
+                               S.s.hscale(), nrhs);
+            MG_TRY(mg_convert(c, vp, s, MGLMA_F16, s16, n, nrhs, S.s.hscale(), 1));
+            MG_TRY(mg_dslash(c, MGLMA_F16, 0, s16, t16, nrhs));
+            MG_TRY(mg_convert(c, MGLMA_F16, t16, vp, t, n, nrhs, S.s.hscale(), 0));
+        } else {
+            MG_TRY(mg_dslash(c, vp, 0, s, t, nrhs));
+        }
+        MG_TRY(mg_dot(c, vp, t, s, n, nrhs, S.s.ts()));
+        MG_TRY(mg_norm2(c, vp, t, n, nrhs, S.s.tt()));
+        hipLaunchKernelGGL(k_mr_omega, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, S.s.ts(), S.s.tt(),
+                           S.s.omega(), nrhs);
+        MG_TRY(mg_multiaxpy(c, vp, s, 0, 1, S.s.omega(), 1.0, z, n, nrhs));
+        if (it + 1 < p->nu_post) MG_TRY(mg_multiaxpy(c, vp, t, 0, 1, S.s.omega(), -1.0, s, n, nrhs));
+    }
+    HIP_TRY(hipGetLastError());
+    return MGLMA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// inner flexible GCR(m) on M e = rin, vectors in precision vp; returns the
+// number of iterations.  Stops when every active right-hand side has
+// ||r|| <= inner_tol ||rin|| (checked on the host each iteration).
+// ---------------------------------------------------------------------------
+static int inner_fgcr(SolveCtx& S, int vp, const void* rin, void* e, const std::vector<int>& active, int* iters) {
+    mglma_ctx* c = S.c;
+    const mglma_solve_params* p = S.p;
+    const int nrhs = S.nrhs;
+    const size_t n = fine_n(c), vb = prec_cbytes(vp), setsz = (size_t)nrhs * n;
+    const int m = p->gcr_m;
+    void *Z, *W, *r;
+    MG_TRY(mg_scratch(c, WS_Z, (size_t)m * setsz * vb, &Z));
+    MG_TRY(mg_scratch(c, WS_W, (size_t)m * setsz * vb, &W));
+    MG_TRY(mg_scratch(c, WS_CX64, setsz * vb, &r));
+    MG_TRY(mg_zero(c, e, setsz * vb));
+    MG_TRY(mg_copy(c, r, rin, setsz * vb));
+    double* h;
+    MG_TRY(mg_host(c, 2 * (size_t)nrhs, &h));
+    MG_TRY(mg_norm2(c, vp, r, n, nrhs, S.s.rn2()));
+    HIP_TRY(hipMemcpyAsync(h, S.s.rn2(), nrhs * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    std::vector<double> r0(h, h + nrhs);
+    int k = 0;
+    for (; k < p->max_inner; ++k) {
+        const int j = k % m;
+        char* zj = (char*)Z + (size_t)j * setsz * vb;
+        char* wj = (char*)W + (size_t)j * setsz * vb;
+        MG_TRY(precondition(S, vp, r, zj));
+        MG_TRY(mg_dslash(c, vp, 0, zj, wj, nrhs));
+        if (j > 0) {
+            MG_TRY(mg_multidot(c, vp, W, setsz, j, wj, n, nrhs, S.s.beta()));
+            MG_TRY(mg_multiaxpy(c, vp, W, setsz, j, S.s.beta(), -1.0, wj, n, nrhs));
+            MG_TRY(mg_multiaxpy(c, vp, Z, setsz, j, S.s.beta(), -1.0, zj, n, nrhs));
+        }
+        MG_TRY(mg_norm2(c, vp, wj, n, nrhs, S.s.nw2()));
+        hipLaunchKernelGGL(k_rsqrt_c, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, S.s.nw2(), S.s.invc(), nrhs);
+        MG_TRY(mg_axpby(c, vp, nullptr, nullptr, S.s.invc(), wj, n, nrhs));
+        MG_TRY(mg_axpby(c, vp, nullptr, nullptr, S.s.invc(), zj, n, nrhs));
+        MG_TRY(mg_dot(c, vp, wj, r, n, nrhs, S.s.alpha()));
+        MG_TRY(mg_multiaxpy(c, vp, zj, 0, 1, S.s.alpha(), 1.0, e, n, nrhs));
+        MG_TRY(mg_multiaxpy(c, vp, wj, 0, 1, S.s.alpha(), -1.0, r, n, nrhs));
+        MG_TRY(mg_norm2(c, vp, r, n, nrhs, S.s.rn2()));
+        HIP_TRY(hipMemcpyAsync(h, S.s.rn2(), nrhs * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        bool done = true;
+        for (int q = 0; q < nrhs; ++q) {
+            if (!std::isfinite(h[q])) return MGLMA_ERR_NONFINITE;
+            if (active[q] && h[q] > p->inner_tol * p->inner_tol * r0[q]) done = false;
+        }
+        if (done) { ++k; break; }
+    }
+    *iters = k;
+    return MGLMA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// ABI: fine solve with FP64 defect correction
+// ---------------------------------------------------------------------------
+extern "C" int mglma_solve(mglma_ctx* c, const mglma_solve_params* p, const double* b, double* x, int nrhs,
+                           mglma_solve_stats* stats) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!c || !p || !b || !x || nrhs < 1 || nrhs > 4096) return MGLMA_ERR_ARG;
+    if (!c->have_gauge) return MGLMA_ERR_NO_GAUGE;
+    if (p->use_mg && !c->have_subspace) return MGLMA_ERR_NO_SUBSPACE;
+    if (p->gcr_m < 1 || p->gcr_m > 64 || p->max_inner < 1 || p->max_outer < 1) return MGLMA_ERR_ARG;
+    const int vp = p->inner == MGLMA_F64 ? MGLMA_F64 : MGLMA_F32;
+    const size_t n = fine_n(c), setsz = (size_t)nrhs * n;
+    SolveCtx S;
+    S.c = c; S.p = p; S.nrhs = nrhs;
+    S.s.nrhs = nrhs;
+    S.s.m = p->gcr_m > 8 ? p->gcr_m : 8;
+    MG_TRY(mg_scratch(c, WS_SCAL, Scal::bytes(nrhs, S.s.m), (void**)&S.s.base));
+    double2 *r64, *t64;
+    void *rin, *e;
+    MG_TRY(mg_scratch(c, WS_R64, setsz * 16, (void**)&r64));
+    MG_TRY(mg_scratch(c, WS_T64, setsz * 16, (void**)&t64));
+    MG_TRY(mg_scratch(c, WS_RIN, setsz * prec_cbytes(vp), &rin));
+    MG_TRY(mg_scratch(c, WS_E, setsz * prec_cbytes(vp), &e));
+    double* h;
+    MG_TRY(mg_host(c, 2 * (size_t)nrhs, &h));
+
+    MG_TRY(mg_norm2(c, MGLMA_F64, b, n, nrhs, S.s.bn2()));
+    HIP_TRY(hipMemcpyAsync(h, S.s.bn2(), nrhs * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    std::vector<double> bn2(h, h + nrhs), rn2(nrhs);
+    for (int q = 0; q < nrhs; ++q)
+        if (!std::isfinite(bn2[q])) return MGLMA_ERR_NONFINITE;
+    MG_TRY(mg_zero(c, x, setsz * 16));
+    MG_TRY(mg_copy(c, r64, b, setsz * 16));
+    rn2 = bn2;
+    std::vector<int> active(nrhs), outer_it(nrhs, 0), inner_it(nrhs, 0);
+    const double tol2 = p->tol * p->tol;
+    int total_inner = 0, outer = 0, rc = MGLMA_OK;
+    for (outer = 0; outer < p->max_outer; ++outer) {
+        int nact = 0;
+        for (int q = 0; q < nrhs; ++q) {
+            active[q] = (bn2[q] > 0.0 && rn2[q] > tol2 * bn2[q]) ? 1 : 0;
+            nact += active[q];
+        }
+        if (!nact) break;
+        HIP_TRY(hipMemcpyAsync(S.s.active(), active.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipMemcpyAsync(S.s.rn2(), rn2.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        // rin = r / |r| for active rhs, 0 otherwise; scale = |r| (0 when inactive)
+        hipLaunchKernelGGL(k_sqrt_masked, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, S.s.rn2(), S.s.active(),
+                           S.s.scale(), nrhs);
+        MG_TRY(mg_convert(c, MGLMA_F64, r64, vp, rin, n, nrhs, S.s.scale(), 1));
+        int it = 0;
+        rc = inner_fgcr(S, vp, rin, e, active, &it);
+        if (rc != MGLMA_OK) break;
+        total_inner += it;
+        for (int q = 0; q < nrhs; ++q)
+            if (active[q]) { outer_it[q]++; inner_it[q] += it; }
+        // x += |r| e ; r = b - M x
+        if (vp == MGLMA_F64)
+            hipLaunchKernelGGL((k_accum<double2, double>), dim3(1024, nrhs), dim3(256), 0, c->stream, (double2*)x,
+                               (const double2*)e, S.s.scale(), n);
+        else
+            hipLaunchKernelGGL((k_accum<float2, float>), dim3(1024, nrhs), dim3(256), 0, c->stream, (double2*)x,
+                               (const float2*)e, S.s.scale(), n);
+        HIP_TRY(hipGetLastError());
+        MG_TRY(mg_dslash(c, MGLMA_F64, 0, x, t64, nrhs));
+        hipLaunchKernelGGL(k_xmy, grid1(setsz), dim3(256), 0, c->stream, (const double2*)b, t64, r64, setsz);
+        MG_TRY(mg_norm2(c, MGLMA_F64, r64, n, nrhs, S.s.rn2()));
+        HIP_TRY(hipMemcpyAsync(h, S.s.rn2(), nrhs * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        for (int q = 0; q < nrhs; ++q) {
+            if (!std::isfinite(h[q])) { rc = MGLMA_ERR_NONFINITE; break; }
+            rn2[q] = h[q];
+        }
+        if (rc != MGLMA_OK) break;
+    }
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    bool all = true;
+    for (int q = 0; q < nrhs; ++q) {
+        double rel = bn2[q] > 0 ? std::sqrt(rn2[q] / bn2[q]) : 0.0;
+        bool ok = rel <= p->tol;
+        all = all && ok;
+        if (stats) {
+            stats[q].outer = outer_it[q];
+            stats[q].inner = inner_it[q];
+            stats[q].coarse = S.coarse_applies;
+            stats[q].true_rel_res = rel;
+            stats[q].seconds = secs;
+            stats[q].status = ok ? MGLMA_OK : (rc != MGLMA_OK ? rc : MGLMA_ERR_NOT_CONVERGED);
+        }
+    }
+    if (rc != MGLMA_OK) return rc;
+    return all ? MGLMA_OK : MGLMA_ERR_NOT_CONVERGED;
+}
+
+// ---------------------------------------------------------------------------
+// coarse solve to a tolerance: FP64 residual + inner coarse GCR (FP32 vectors,
+// operator p->coarse) in rounds of coarse_iters steps
+// ---------------------------------------------------------------------------
+int mg_coarse_solve(mglma_ctx* c, const mglma_solve_params* p, const double* b, double* x, int nrhs,
+                    mglma_solve_stats* stats) {
+    const size_t n = coarse_n(c), setsz = (size_t)nrhs * n;
+    SolveCtx S;
+    S.c = c; S.p = p; S.nrhs = nrhs;
+    S.s.nrhs = nrhs;
+    S.s.m = 8;
+    MG_TRY(mg_scratch(c, WS_SCAL, Scal::bytes(nrhs, S.s.m), (void**)&S.s.base));
+    const int vp = p->inner == MGLMA_F64 ? MGLMA_F64 : MGLMA_F32;
+    double2 *r64, *t64;
+    void *rin, *e;
+    MG_TRY(mg_scratch(c, WS_CR64, setsz * 16, (void**)&r64));
+    MG_TRY(mg_scratch(c, WS_CT64, setsz * 16, (void**)&t64));
+    MG_TRY(mg_scratch(c, WS_RC, setsz * prec_cbytes(vp), &rin));
+    MG_TRY(mg_scratch(c, WS_EC, setsz * prec_cbytes(vp), &e));
+    double* h;
+    MG_TRY(mg_host(c, 2 * (size_t)nrhs, &h));
+    MG_TRY(mg_norm2(c, MGLMA_F64, b, n, nrhs, S.s.bn2()));
+    HIP_TRY(hipMemcpyAsync(h, S.s.bn2(), nrhs * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    std::vector<double> bn2(h, h + nrhs), rn2 = bn2;
+    for (int q = 0; q < nrhs; ++q)
+        if (!std::isfinite(bn2[q])) return MGLMA_ERR_NONFINITE;
+    MG_TRY(mg_zero(c, x, setsz * 16));
+    MG_TRY(mg_copy(c, r64, b, setsz * 16));
+    std::vector<int> active(nrhs);
+    const double tol2 = p->tol * p->tol;
+    const int rounds = p->max_outer * p->max_inner;
+    int it = 0;
+    for (it = 0; it < rounds; ++it) {
+        int nact = 0;
+        for (int q = 0; q < nrhs; ++q) {
+            active[q] = (bn2[q] > 0.0 && rn2[q] > tol2 * bn2[q]) ? 1 : 0;
+            nact += active[q];
+        }
+        if (!nact) break;
+        HIP_TRY(hipMemcpyAsync(S.s.active(), active.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipMemcpyAsync(S.s.rn2(), rn2.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        hipLaunchKernelGGL(k_sqrt_masked, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, S.s.rn2(), S.s.active(),
+                           S.s.scale(), nrhs);
+        MG_TRY(mg_convert(c, MGLMA_F64, r64, vp, rin, n, nrhs, S.s.scale(), 1));
+        MG_TRY(coarse_gcr_fixed(S, vp, vp == MGLMA_F64 ? MGLMA_F64 : p->coarse, rin, e, p->coarse_iters));
+        if (vp == MGLMA_F64)
+            hipLaunchKernelGGL((k_accum<double2, double>), dim3(256, nrhs), dim3(256), 0, c->stream, (double2*)x,
+                               (const double2*)e, S.s.scale(), n);
+        else
+            hipLaunchKernelGGL((k_accum<float2, float>), dim3(256, nrhs), dim3(256), 0, c->stream, (double2*)x,
+                               (const float2*)e, S.s.scale(), n);
+        HIP_TRY(hipGetLastError());
+        MG_TRY(mg_coarse_apply(c, MGLMA_F64, 0, x, t64, nrhs));
+        hipLaunchKernelGGL(k_xmy, grid1(setsz), dim3(256), 0, c->stream, (const double2*)b, t64, r64, setsz);
+        MG_TRY(mg_norm2(c, MGLMA_F64, r64, n, nrhs, S.s.rn2()));
+        HIP_TRY(hipMemcpyAsync(h, S.s.rn2(), nrhs * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        for (int q = 0; q < nrhs; ++q) {
+            if (!std::isfinite(h[q])) return MGLMA_ERR_NONFINITE;
+            rn2[q] = h[q];
+        }
+    }
+    bool all = true;
+    for (int q = 0; q < nrhs; ++q) {
+        double rel = bn2[q] > 0 ? std::sqrt(rn2[q] / bn2[q]) : 0.0;
+        all = all && rel <= p->tol;
+        if (stats) {
+            stats[q].outer = it;
+            stats[q].inner = it * p->coarse_iters;
+            stats[q].coarse = S.coarse_applies;
+            stats[q].true_rel_res = rel;
+            stats[q].seconds = 0;
+            stats[q].status = rel <= p->tol ? MGLMA_OK : MGLMA_ERR_NOT_CONVERGED;
+        }
+    }
+    return all ? MGLMA_OK : MGLMA_ERR_NOT_CONVERGED;
+}
+
+extern "C" int mglma_coarse_solve(mglma_ctx* c, const mglma_solve_params* p, const double* b, double* x, int nrhs,
+                                  mglma_solve_stats* stats) {
+    if (!c || !p || !b || !x || nrhs < 1 || nrhs > 65535) return MGLMA_ERR_ARG;
+    if (!c->have_subspace) return MGLMA_ERR_NO_SUBSPACE;
+    if (p->coarse_iters < 1 || p->max_outer < 1 || p->max_inner < 1) return MGLMA_ERR_ARG;
+    return mg_coarse_solve(c, p, b, x, nrhs, stats);
+}

@@ -1,0 +1,498 @@
+// Chirally split block basis, restrictor / prolongator, Galerkin coarse
+// operator and coarse gamma matrices.
+//
+// * Basis (eq:mg_basis with eq:chirality:B): for block y and chirality alpha
+//   the fields P_alpha theta_{B_y} v_c, c < Nv, orthonormalised in order c.
+//   The result is the unique QR factor with positive real diagonal; it is
+//   computed as Cholesky QR done twice (Gram matrix, Cholesky factor R,
+//   W R^{-1}), which reaches the same factor as Gram-Schmidt to rounding.
+//   Storage: B[y][alpha][c][3 s' + col][l], s' the spin inside the chirality,
+//   l the block-local site, so one basis vector is 6*Vb contiguous complex.
+// * R and T (eq:res_mg, eq:pro_mg): per block, a (2 Nv) x (12 Vb) complex
+//   matrix times the right-hand sides.
+// * D_1 = R M T (fig:A): nine nc x nc blocks per coarse site, entry [y][dir]
+//   holding the fine hops that leave block y through face dir (dir 0: the
+//   clover term and the hops inside the block).  Built by prolonging coarse
+//   unit vectors, applying the matching piece of M and restricting.
+// * (gamma5 gamma_k)_1 per block time slice (eq:coarse:gamma with an open
+//   time index): only the alpha = 0 rows x alpha = 1 columns block is stored;
+//   the other block is minus its adjoint (gamma5 gamma_k is anti-Hermitian and
+//   flips chirality).
+#include "mglma_internal.h"
+
+int mg_dslash_piece(mglma_ctx* c, int mode, const double2* in, double2* out, int nrhs);
+
+// ---------------------------------------------------------------------------
+// basis construction
+// ---------------------------------------------------------------------------
+__global__ void k_tv_to_basis(Geo g, int Nv, const double2* __restrict__ tv, double2* __restrict__ B) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int c = blockIdx.y;
+    if (i >= g.V) return;
+    int y = i / g.Vb, l = i - y * g.Vb;
+    size_t V = g.V, Vb = g.Vb;
+    for (int sc = 0; sc < 12; ++sc) {
+        int a = sc / 6, scl = sc % 6;
+        B[((((size_t)y * 2 + a) * Nv + c) * 6 + scl) * Vb + l] = tv[((size_t)c * 12 + sc) * V + i];
+    }
+}
+
+#define GCH 32   // k-chunk of the Gram kernel
+
+// G[(y,a)][c][d] = <w_c, w_d> for c <= d
+__global__ __launch_bounds__(256) void k_gram(const double2* __restrict__ B, int Nv, int K, double2* __restrict__ G) {
+    extern __shared__ double2 sh[];   // [Nv][GCH+1]
+    const int ya = blockIdx.x;
+    const double2* W = B + (size_t)ya * Nv * K;
+    const int P = Nv * (Nv + 1) / 2;
+    const int np = (P + 255) / 256;   // pairs per thread (<= 9 for Nv <= 64)
+    cx<double> acc[9];
+    int pc[9], pd[9];
+    for (int q = 0; q < 9; ++q) {
+        acc[q] = cmk(0.0, 0.0);
+        int p = threadIdx.x + 256 * q;
+        pc[q] = pd[q] = -1;
+        if (q < np && p < P) {
+            // p -> (c, d) with c <= d, row-major over the upper triangle
+            int c = 0, rem = p;
+            while (rem >= Nv - c) { rem -= Nv - c; ++c; }
+            pc[q] = c;
+            pd[q] = c + rem;
+        }
+    }
+    for (int k0 = 0; k0 < K; k0 += GCH) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < Nv * GCH; e += 256) {
+            int c = e / GCH, kk = e % GCH;
+            sh[c * (GCH + 1) + kk] = (k0 + kk < K) ? W[(size_t)c * K + k0 + kk] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        for (int q = 0; q < 9; ++q) {
+            if (pc[q] < 0) continue;
+            const double2* a = sh + pc[q] * (GCH + 1);
+            const double2* b = sh + pd[q] * (GCH + 1);
+            for (int kk = 0; kk < GCH; ++kk)
+                cjmac(acc[q], cmk(a[kk].x, a[kk].y), cmk(b[kk].x, b[kk].y));
+        }
+    }
+    for (int q = 0; q < 9; ++q)
+        if (pc[q] >= 0) G[((size_t)ya * Nv + pc[q]) * Nv + pd[q]] = make_double2(acc[q].re, acc[q].im);
+}
+
+// In place: G (upper) -> R with G = R^+ R; then Rinv = R^{-1} (upper).
+__global__ void k_chol_inv(int Nv, double2* __restrict__ G, double2* __restrict__ Rinv, double tol, int* bad) {
+    const int ya = blockIdx.x;
+    double2* R = G + (size_t)ya * Nv * Nv;
+    double2* X = Rinv + (size_t)ya * Nv * Nv;
+    __shared__ double diag;
+    for (int j = 0; j < Nv; ++j) {
+        if (threadIdx.x == 0) {
+            double g0 = R[j * Nv + j].x;
+            double s = g0;
+            for (int i = 0; i < j; ++i) s -= R[i * Nv + j].x * R[i * Nv + j].x + R[i * Nv + j].y * R[i * Nv + j].y;
+            if (!(s > tol * tol * g0) || !(g0 > 0.0)) {
+                atomicOr(bad, 1);
+                s = 1.0;
+            }
+            diag = sqrt(s);
+            R[j * Nv + j] = make_double2(diag, 0.0);
+        }
+        __syncthreads();
+        for (int k = j + 1 + threadIdx.x; k < Nv; k += blockDim.x) {
+            cx<double> s = cmk(R[j * Nv + k].x, R[j * Nv + k].y);
+            for (int i = 0; i < j; ++i) {
+                cx<double> a = cmk(R[i * Nv + j].x, -R[i * Nv + j].y);
+                cx<double> b = cmk(R[i * Nv + k].x, R[i * Nv + k].y);
+                s = s - a * b;
+            }
+            R[j * Nv + k] = make_double2(s.re / diag, s.im / diag);
+        }
+        __syncthreads();
+    }
+    for (int d = threadIdx.x; d < Nv; d += blockDim.x) {
+        for (int cc = 0; cc < Nv; ++cc) X[cc * Nv + d] = make_double2(0.0, 0.0);
+        X[d * Nv + d] = make_double2(1.0 / R[d * Nv + d].x, 0.0);
+        for (int cc = d - 1; cc >= 0; --cc) {
+            cx<double> s = cmk(0.0, 0.0);
+            for (int e = cc + 1; e <= d; ++e)
+                cmac(s, cmk(R[cc * Nv + e].x, R[cc * Nv + e].y), cmk(X[e * Nv + d].x, X[e * Nv + d].y));
+            double rd = R[cc * Nv + cc].x;
+            X[cc * Nv + d] = make_double2(-s.re / rd, -s.im / rd);
+        }
+    }
+}
+
+// In place: w_d <- sum_{c<=d} w_c Rinv[c][d], d processed from the top down.
+__global__ __launch_bounds__(256) void k_apply_rinv(double2* __restrict__ B, int Nv, int K,
+                                                    const double2* __restrict__ Rinv) {
+    const int ya = blockIdx.x;
+    double2* W = B + (size_t)ya * Nv * K;
+    const double2* X = Rinv + (size_t)ya * Nv * Nv;
+    extern __shared__ double2 xs[];   // Nv*Nv
+    for (int e = threadIdx.x; e < Nv * Nv; e += blockDim.x) xs[e] = X[e];
+    __syncthreads();
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+        for (int d1 = Nv; d1 > 0; d1 -= 16) {
+            int d0 = d1 - 16 < 0 ? 0 : d1 - 16;
+            cx<double> acc[16];
+            for (int q = 0; q < 16; ++q) acc[q] = cmk(0.0, 0.0);
+            for (int c = 0; c < d1; ++c) {
+                double2 w = W[(size_t)c * K + k];
+                cx<double> wc = cmk(w.x, w.y);
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    int d = d0 + q;
+                    if (d < d1 && c <= d) {
+                        double2 x = xs[c * Nv + d];
+                        cmac(acc[q], wc, cmk(x.x, x.y));
+                    }
+                }
+            }
+            for (int q = 0; q < 16; ++q)
+                if (d0 + q < d1) W[(size_t)(d0 + q) * K + k] = make_double2(acc[q].re, acc[q].im);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// restrict / prolong
+// ---------------------------------------------------------------------------
+template <typename R> __device__ __forceinline__ R wsum(R v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+#define NRR 8
+
+// coarse[r][y][a*Nv + c] = sum_{l, s'col} conj(B[y][a][c][s'col][l]) fine[r][6a + s'col][y*Vb + l]
+template <typename S, typename R>
+__global__ __launch_bounds__(256) void k_restrict(Geo g, int Nv, const S* __restrict__ B, const S* __restrict__ fine,
+                                                  S* __restrict__ coarse, int nrhs) {
+    const int y = blockIdx.x;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int Vb = g.Vb, nc = 2 * Nv;
+    const size_t V = g.V, K = (size_t)6 * Vb;
+    for (int r0 = 0; r0 < nrhs; r0 += NRR) {
+        const int nr = nrhs - r0 < NRR ? nrhs - r0 : NRR;
+        for (int pair = w; pair < nc; pair += 4) {
+            const int a = pair / Nv;
+            const S* bv = B + ((size_t)y * nc + pair) * K;
+            cx<R> acc[NRR];
+#pragma unroll
+            for (int q = 0; q < NRR; ++q) acc[q] = cmk((R)0, (R)0);
+            for (int scl = 0; scl < 6; ++scl) {
+                const S* fr = fine + ((size_t)r0 * 12 + 6 * a + scl) * V + (size_t)y * Vb;
+                for (int l = lane; l < Vb; l += 64) {
+                    cx<R> b = ldc<S, R>(bv + (size_t)scl * Vb + l);
+#pragma unroll
+                    for (int q = 0; q < NRR; ++q)
+                        if (q < nr) cjmac(acc[q], b, ldc<S, R>(fr + (size_t)q * 12 * V + l));
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < NRR; ++q) {
+                R re = wsum(acc[q].re), im = wsum(acc[q].im);
+                if (lane == 0 && q < nr) stc<S, R>(coarse + ((size_t)(r0 + q) * g.V1 + y) * nc + pair, cmk(re, im));
+            }
+        }
+    }
+}
+
+// fine[r][6a + s'col][i] = sum_c B[y][a][c][s'col][l] coarse[r][y][a*Nv + c]
+template <typename S, typename R>
+__global__ __launch_bounds__(256) void k_prolong(Geo g, int Nv, const S* __restrict__ B, const S* __restrict__ coarse,
+                                                 S* __restrict__ fine, int nrhs) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.V) return;
+    const int Vb = g.Vb, nc = 2 * Nv;
+    const int y = i / Vb, l = i - y * Vb;
+    const size_t V = g.V;
+    for (int r0 = 0; r0 < nrhs; r0 += NRR) {
+        const int nr = nrhs - r0 < NRR ? nrhs - r0 : NRR;
+        for (int a = 0; a < 2; ++a) {
+            for (int scl = 0; scl < 6; ++scl) {
+                cx<R> acc[NRR];
+#pragma unroll
+                for (int q = 0; q < NRR; ++q) acc[q] = cmk((R)0, (R)0);
+                for (int c = 0; c < Nv; ++c) {
+                    cx<R> b = ldc<S, R>(B + (((size_t)y * nc + a * Nv + c) * 6 + scl) * Vb + l);
+                    const S* cr = coarse + ((size_t)r0 * g.V1 + y) * nc + a * Nv + c;
+#pragma unroll
+                    for (int q = 0; q < NRR; ++q)
+                        if (q < nr) cmac(acc[q], b, ldc<S, R>(cr + (size_t)q * g.V1 * nc));
+                }
+#pragma unroll
+                for (int q = 0; q < NRR; ++q)
+                    if (q < nr) stc<S, R>(fine + ((size_t)(r0 + q) * 12 + 6 * a + scl) * V + i, acc[q]);
+            }
+        }
+    }
+}
+
+int mg_restrict(mglma_ctx* c, int prec, const void* fine, void* coarse, int nrhs) {
+    if (nrhs <= 0) return MGLMA_OK;
+    const Geo& g = c->geo;
+    switch (prec) {
+        case MGLMA_F64:
+            hipLaunchKernelGGL((k_restrict<double2, double>), dim3(g.V1), dim3(256), 0, c->stream, g, c->Nv, c->B64,
+                               (const double2*)fine, (double2*)coarse, nrhs);
+            break;
+        case MGLMA_F32:
+            hipLaunchKernelGGL((k_restrict<float2, float>), dim3(g.V1), dim3(256), 0, c->stream, g, c->Nv, c->B32,
+                               (const float2*)fine, (float2*)coarse, nrhs);
+            break;
+        default: return MGLMA_ERR_ARG;
+    }
+    HIP_TRY(hipGetLastError());
+    return MGLMA_OK;
+}
+
+int mg_prolong(mglma_ctx* c, int prec, const void* coarse, void* fine, int nrhs) {
+    if (nrhs <= 0) return MGLMA_OK;
+    const Geo& g = c->geo;
+    dim3 grid((g.V + 255) / 256);
+    switch (prec) {
+        case MGLMA_F64:
+            hipLaunchKernelGGL((k_prolong<double2, double>), grid, dim3(256), 0, c->stream, g, c->Nv, c->B64,
+                               (const double2*)coarse, (double2*)fine, nrhs);
+            break;
+        case MGLMA_F32:
+            hipLaunchKernelGGL((k_prolong<float2, float>), grid, dim3(256), 0, c->stream, g, c->Nv, c->B32,
+                               (const float2*)coarse, (float2*)fine, nrhs);
+            break;
+        default: return MGLMA_ERR_ARG;
+    }
+    HIP_TRY(hipGetLastError());
+    return MGLMA_OK;
+}
+
+extern "C" int mglma_restrict(mglma_ctx* c, int prec, const void* fine, void* coarse, int nrhs) {
+    if (!c || !fine || !coarse || nrhs < 0) return MGLMA_ERR_ARG;
+    if (!c->have_subspace) return MGLMA_ERR_NO_SUBSPACE;
+    return mg_restrict(c, prec, fine, coarse, nrhs);
+}
+
+extern "C" int mglma_prolong(mglma_ctx* c, int prec, const void* coarse, void* fine, int nrhs) {
+    if (!c || !fine || !coarse || nrhs < 0) return MGLMA_ERR_ARG;
+    if (!c->have_subspace) return MGLMA_ERR_NO_SUBSPACE;
+    return mg_prolong(c, prec, coarse, fine, nrhs);
+}
+
+// ---------------------------------------------------------------------------
+// Galerkin operator
+// ---------------------------------------------------------------------------
+__global__ void k_unit_coarse(int V1, int nc, int j0, int nj, double2* __restrict__ out) {
+    size_t n = (size_t)nj * V1 * nc;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        int i = (int)(e % nc);
+        int jj = (int)(e / ((size_t)V1 * nc));
+        out[e] = make_double2(i == j0 + jj ? 1.0 : 0.0, 0.0);
+    }
+}
+
+// D[y][dir][i][j0+jj] = Rc[jj][y][i]
+__global__ void k_scatter_op(int V1, int nc, int dir, int j0, int nj, const double2* __restrict__ Rc,
+                             double2* __restrict__ D) {
+    size_t n = (size_t)nj * V1 * nc;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        int i = (int)(e % nc);
+        size_t t = e / nc;
+        int y = (int)(t % V1);
+        int jj = (int)(t / V1);
+        D[(((size_t)y * 9 + dir) * nc + i) * nc + j0 + jj] = Rc[e];
+    }
+}
+
+__global__ void k_op_copies(size_t nblk, int nc, const double2* __restrict__ D, double2* __restrict__ D64t,
+                            float2* __restrict__ D32t, bf16_t* __restrict__ Dbf) {
+    // D64t, D32t: column-major copies [blk][j][i]; Dbf[blk][0 = re, 1 = im][i][j]
+    size_t n = nblk * nc * nc;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        double2 v = D[e];
+        size_t blk = e / ((size_t)nc * nc), ij = e % ((size_t)nc * nc);
+        size_t i = ij / nc, j = ij % nc;
+        size_t et = blk * nc * nc + j * nc + i;
+        D64t[et] = v;
+        D32t[et] = make_float2((float)v.x, (float)v.y);
+        float fr = (float)v.x, fi = (float)v.y;
+        // round to nearest even
+        uint32_t ur = __float_as_uint(fr), ui = __float_as_uint(fi);
+        ur += 0x7fff + ((ur >> 16) & 1);
+        ui += 0x7fff + ((ui >> 16) & 1);
+        Dbf[(blk * 2 + 0) * nc * nc + ij] = (bf16_t)(ur >> 16);
+        Dbf[(blk * 2 + 1) * nc * nc + ij] = (bf16_t)(ui >> 16);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// coarse gamma matrices (gamma5 gamma_k)_1(y, t): alpha=0 rows c, alpha=1 cols d
+//   sum_{x in B_y, x0 = t} sum_col sum_{s',t'} conj(phi_{0c}(s',col)) m_k[s'][t'] phi_{1d}(t',col)
+// with m_k = -i sigma_k (the upper-right block of gamma5 gamma_k).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_coarse_gamma(Geo g, int Nv, const double2* __restrict__ B,
+                                                      double2* __restrict__ G1) {
+    const int y = blockIdx.x / g.b[0], t = blockIdx.x % g.b[0];
+    const int Vb = g.Vb, ns = Vb / g.b[0];   // spatial sites per block slice
+    const size_t K = (size_t)6 * Vb;
+    const double2* P0 = B + ((size_t)y * 2 + 0) * Nv * K;
+    const double2* P1 = B + ((size_t)y * 2 + 1) * Nv * K;
+    const int nout = 3 * Nv * Nv;
+    for (int o = threadIdx.x; o < nout; o += blockDim.x) {
+        int k = o / (Nv * Nv), cd = o % (Nv * Nv), cc = cd / Nv, d = cd % Nv;
+        cx<double> acc = cmk(0.0, 0.0);
+        for (int col = 0; col < 3; ++col) {
+            for (int ls = 0; ls < ns; ++ls) {
+                int l = t * ns + ls;
+                cx<double> a0 = ldc<double2, double>(P0 + ((size_t)cc * 6 + 0 + col) * Vb + l);
+                cx<double> a1 = ldc<double2, double>(P0 + ((size_t)cc * 6 + 3 + col) * Vb + l);
+                cx<double> b0 = ldc<double2, double>(P1 + ((size_t)d * 6 + 0 + col) * Vb + l);
+                cx<double> b1 = ldc<double2, double>(P1 + ((size_t)d * 6 + 3 + col) * Vb + l);
+                // (gamma5 gamma_k psi)(s') for the upper spins s' = 0, 1 reads spin tc in {2, 3}
+                cx<double> u0, u1;
+                {
+                    int tc;
+                    double cr, ci;
+                    gk_row(k + 1, 0, &tc, &cr, &ci);
+                    u0 = cmk(cr, ci) * (tc == 2 ? b0 : b1);
+                    gk_row(k + 1, 1, &tc, &cr, &ci);
+                    u1 = cmk(cr, ci) * (tc == 2 ? b0 : b1);
+                }
+                cjmac(acc, a0, u0);
+                cjmac(acc, a1, u1);
+            }
+        }
+        G1[(((size_t)y * g.b[0] + t) * 3 + k) * Nv * Nv + cd] = make_double2(acc.re, acc.im);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// ABI: build the subspace
+// ---------------------------------------------------------------------------
+static int cholqr_pass(mglma_ctx* c, double2* Gb, double2* Rb, int* bad) {
+    const Geo& g = c->geo;
+    const int Nv = c->Nv, K = 6 * g.Vb;
+    const int nya = g.V1 * 2;
+    size_t sh = (size_t)Nv * (GCH + 1) * sizeof(double2);
+    hipLaunchKernelGGL(k_gram, dim3(nya), dim3(256), sh, c->stream, c->B64, Nv, K, Gb);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_chol_inv, dim3(nya), dim3(64), 0, c->stream, Nv, Gb, Rb, 3e-7, bad);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_apply_rinv, dim3(nya), dim3(256), (size_t)Nv * Nv * sizeof(double2), c->stream, c->B64, Nv,
+                       K, (const double2*)Rb);
+    HIP_TRY(hipGetLastError());
+    return MGLMA_OK;
+}
+
+extern "C" int mglma_build_subspace(mglma_ctx* c, int Nv, const double* tv) {
+    if (!c || !tv) return MGLMA_ERR_ARG;
+    if (!c->have_gauge) return MGLMA_ERR_NO_GAUGE;
+    const Geo& g = c->geo;
+    if (Nv < 1 || Nv > 64 || Nv > 6 * g.Vb) return MGLMA_ERR_ARG;
+    mg_free_subspace(c);
+    c->Nv = Nv;
+    c->nc = 2 * Nv;
+    const int nc = c->nc;
+    size_t nb = (size_t)g.V * 12 * Nv;
+    size_t nd = (size_t)g.V1 * 9 * nc * nc;
+    MG_TRY(mg_malloc(c, (void**)&c->B64, nb * 16));
+    MG_TRY(mg_malloc(c, (void**)&c->B32, nb * 8));
+    MG_TRY(mg_malloc(c, (void**)&c->D64, nd * 16));
+    MG_TRY(mg_malloc(c, (void**)&c->D64t, nd * 16));
+    MG_TRY(mg_malloc(c, (void**)&c->D32, nd * 8));
+    MG_TRY(mg_malloc(c, (void**)&c->Dbf, nd * 4));
+    MG_TRY(mg_malloc(c, (void**)&c->G1, (size_t)g.V1 * g.b[0] * 3 * Nv * Nv * 16));
+
+    // 1. block-project and chirally split the test vectors
+    hipLaunchKernelGGL(k_tv_to_basis, dim3((g.V + 255) / 256, Nv), dim3(256), 0, c->stream, g, Nv,
+                       (const double2*)tv, c->B64);
+    HIP_TRY(hipGetLastError());
+    // 2. orthonormalise each (block, chirality) set: Cholesky QR twice
+    size_t gsz = (size_t)g.V1 * 2 * Nv * Nv * sizeof(double2);
+    double2 *Gb, *Rb;
+    int* bad;
+    MG_TRY(mg_scratch(c, 0, gsz, (void**)&Gb));
+    MG_TRY(mg_scratch(c, 1, gsz, (void**)&Rb));
+    MG_TRY(mg_scratch(c, 7, 64, (void**)&bad));
+    HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int), c->stream));
+    MG_TRY(cholqr_pass(c, Gb, Rb, bad));
+    int hbad = 0;
+    HIP_TRY(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (hbad) { mg_free_subspace(c); return MGLMA_ERR_RANK; }
+    MG_TRY(cholqr_pass(c, Gb, Rb, bad));
+    MG_TRY(mg_convert(c, MGLMA_F64, c->B64, MGLMA_F32, c->B32, nb, 1, nullptr, 0));
+
+    // 3. Galerkin operator, JB coarse unit vectors at a time
+    const int JB = nc < 16 ? nc : 16;
+    double2 *cu, *Phi, *Tmp, *Rc;
+    MG_TRY(mg_scratch(c, 2, (size_t)JB * g.V1 * nc * 16, (void**)&cu));
+    MG_TRY(mg_scratch(c, 3, (size_t)JB * g.V * 12 * 16, (void**)&Phi));
+    MG_TRY(mg_scratch(c, 4, (size_t)JB * g.V * 12 * 16, (void**)&Tmp));
+    MG_TRY(mg_scratch(c, 5, (size_t)JB * g.V1 * nc * 16, (void**)&Rc));
+    for (int j0 = 0; j0 < nc; j0 += JB) {
+        int nj = nc - j0 < JB ? nc - j0 : JB;
+        hipLaunchKernelGGL(k_unit_coarse, dim3(512), dim3(256), 0, c->stream, g.V1, nc, j0, nj, cu);
+        HIP_TRY(hipGetLastError());
+        MG_TRY(mg_prolong(c, MGLMA_F64, cu, Phi, nj));
+        for (int dir = 0; dir < 9; ++dir) {
+            MG_TRY(mg_dslash_piece(c, dir, Phi, Tmp, nj));
+            MG_TRY(mg_restrict(c, MGLMA_F64, Tmp, Rc, nj));
+            hipLaunchKernelGGL(k_scatter_op, dim3(1024), dim3(256), 0, c->stream, g.V1, nc, dir, j0, nj, Rc, c->D64);
+            HIP_TRY(hipGetLastError());
+        }
+    }
+    hipLaunchKernelGGL(k_op_copies, dim3(2048), dim3(256), 0, c->stream, (size_t)g.V1 * 9, nc, c->D64, c->D64t, c->D32,
+                       c->Dbf);
+    HIP_TRY(hipGetLastError());
+
+    // 4. coarse gamma matrices
+    hipLaunchKernelGGL(k_coarse_gamma, dim3(g.V1 * g.b[0]), dim3(256), 0, c->stream, g, Nv, c->B64, c->G1);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->have_subspace = true;
+    return MGLMA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// exports (tests)
+// ---------------------------------------------------------------------------
+__global__ void k_export_basis(Geo g, int Nv, const double2* __restrict__ B, double2* __restrict__ out) {
+    // out[y][j][l][s][col]
+    const int nc = 2 * Nv;
+    size_t n = (size_t)g.V1 * nc * g.Vb * 12;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        int sc = (int)(e % 12);
+        size_t t = e / 12;
+        int l = (int)(t % g.Vb);
+        t /= g.Vb;
+        int j = (int)(t % nc);
+        int y = (int)(t / nc);
+        int a = j / Nv, s = sc / 3, col = sc % 3;
+        double2 v = make_double2(0.0, 0.0);
+        if (s / 2 == a) v = B[(((size_t)y * nc + j) * 6 + (s % 2) * 3 + col) * g.Vb + l];
+        out[e] = v;
+    }
+}
+
+extern "C" int mglma_export_basis(mglma_ctx* c, double* out) {
+    if (!c || !out) return MGLMA_ERR_ARG;
+    if (!c->have_subspace) return MGLMA_ERR_NO_SUBSPACE;
+    hipLaunchKernelGGL(k_export_basis, dim3(2048), dim3(256), 0, c->stream, c->geo, c->Nv, c->B64, (double2*)out);
+    HIP_TRY(hipGetLastError());
+    return MGLMA_OK;
+}
+
+extern "C" int mglma_export_coarse_op(mglma_ctx* c, double* out) {
+    if (!c || !out) return MGLMA_ERR_ARG;
+    if (!c->have_subspace) return MGLMA_ERR_NO_SUBSPACE;
+    size_t nd = (size_t)c->geo.V1 * 9 * c->nc * c->nc;
+    return mg_copy(c, out, c->D64, nd * 16);
+}
+
+extern "C" int mglma_export_coarse_gammas(mglma_ctx* c, double* out) {
+    if (!c || !out) return MGLMA_ERR_ARG;
+    if (!c->have_subspace) return MGLMA_ERR_NO_SUBSPACE;
+    size_t n = (size_t)c->geo.V1 * c->geo.b[0] * 3 * c->Nv * c->Nv;
+    return mg_copy(c, out, c->G1, n * 16);
+}

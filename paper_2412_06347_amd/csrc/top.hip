@@ -1,0 +1,291 @@
+// Exact top level spanned by coarse modes (a level defined without the
+// recursion, as the remark after eq:mglma:decomp allows), the coarse-level
+// propagator pieces, and the exact coarsest-level correlator eq:G_LL:exact.
+//
+//   W      : r = 2 Nlm orthonormal coarse vectors of definite (gamma5)_1
+//            chirality (each mode split by chirality, each set orthonormalised
+//            in order; column index alpha*Nlm + m),
+//   D_2    = W^+ D_1 W,   Q_2 = (gamma5)_2 D_2,  (gamma5)_2 = diag(1_Nlm, -1_Nlm),
+//   G_k(x0) = (gamma5 gamma_k)_2(x0) = W^+ (gamma5 gamma_k)_1(x0) W,
+//   G_top(t) = -1/(3 L0 L^3) sum_k sum_y0 tr{ G_k(y0+t) Q_2^-1 G_k(y0) Q_2^-1 }.
+// The small r x r algebra (Cholesky, inverse, traces) runs on the host in
+// FP64; everything touching coarse vectors runs on the device.
+#include "mglma_internal.h"
+
+#include <cmath>
+
+typedef std::complex<double> zc;
+
+int mg_coarse_solve(mglma_ctx* c, const mglma_solve_params* p, const double* b, double* x, int nrhs,
+                    mglma_solve_stats* stats);
+
+// out[a*ld + r] += sum_e conj(W[a][e]) v[r][e]  via the batched multi-dot
+static int wdot(mglma_ctx* c, const double2* W, int ncols, const double2* v, int nv, double* out_dev) {
+    const size_t n = (size_t)c->geo.V1 * c->nc;
+    for (int q = 0; q < nv; ++q)
+        MG_TRY(mg_multidot(c, MGLMA_F64, W, n, ncols, v + (size_t)q * n, n, 1, out_dev + (size_t)q * ncols * 2));
+    return MGLMA_OK;
+}
+
+// Cholesky of a Hermitian positive definite n x n (row-major, upper used) -> R^{-1}
+static int chol_inv(std::vector<zc>& G, int n, std::vector<zc>& X) {
+    std::vector<zc> R(G);
+    for (int j = 0; j < n; ++j) {
+        double g0 = R[j * n + j].real();
+        double s = g0;
+        for (int i = 0; i < j; ++i) s -= std::norm(R[i * n + j]);
+        if (!(s > 1e-13 * g0) || !(g0 > 0)) return MGLMA_ERR_RANK;
+        double d = std::sqrt(s);
+        R[j * n + j] = d;
+        for (int k = j + 1; k < n; ++k) {
+            zc t = R[j * n + k];
+            for (int i = 0; i < j; ++i) t -= std::conj(R[i * n + j]) * R[i * n + k];
+            R[j * n + k] = t / d;
+        }
+    }
+    X.assign((size_t)n * n, zc(0));
+    for (int d = 0; d < n; ++d) {
+        X[d * n + d] = 1.0 / R[d * n + d].real();
+        for (int cc = d - 1; cc >= 0; --cc) {
+            zc s = 0;
+            for (int e = cc + 1; e <= d; ++e) s += R[cc * n + e] * X[e * n + d];
+            X[cc * n + d] = -s / R[cc * n + cc].real();
+        }
+    }
+    return MGLMA_OK;
+}
+
+// dense inverse by Gauss-Jordan with partial pivoting
+static int inverse(std::vector<zc> A, int n, std::vector<zc>& inv) {
+    inv.assign((size_t)n * n, zc(0));
+    for (int i = 0; i < n; ++i) inv[i * n + i] = 1.0;
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < n; ++r)
+            if (std::abs(A[r * n + col]) > std::abs(A[piv * n + col])) piv = r;
+        if (std::abs(A[piv * n + col]) == 0.0) return MGLMA_ERR_RANK;
+        if (piv != col)
+            for (int k = 0; k < n; ++k) {
+                std::swap(A[col * n + k], A[piv * n + k]);
+                std::swap(inv[col * n + k], inv[piv * n + k]);
+            }
+        zc d = 1.0 / A[col * n + col];
+        for (int k = 0; k < n; ++k) { A[col * n + k] *= d; inv[col * n + k] *= d; }
+        for (int r = 0; r < n; ++r) {
+            if (r == col) continue;
+            zc f = A[r * n + col];
+            if (f == zc(0)) continue;
+            for (int k = 0; k < n; ++k) { A[r * n + k] -= f * A[col * n + k]; inv[r * n + k] -= f * inv[col * n + k]; }
+        }
+    }
+    return MGLMA_OK;
+}
+
+// W[a][y][i] = modes[a % Nlm][y][i] if chirality(i) == a / Nlm else 0
+__global__ void k_split_modes(int Nlm, int V1, int nc, const double2* __restrict__ modes, double2* __restrict__ W) {
+    size_t n = (size_t)2 * Nlm * V1 * nc;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        int i = (int)(e % nc);
+        size_t t = e / nc;
+        int y = (int)(t % V1);
+        int a = (int)(t / V1);
+        int alpha = a / Nlm, m = a % Nlm;
+        W[e] = ((i >= nc / 2) == (alpha == 1)) ? modes[((size_t)m * V1 + y) * nc + i] : make_double2(0.0, 0.0);
+    }
+}
+
+// Gamma2 partial: A[x0][k][a][b] = sum_{y in row(x0)} W0_y^+ Gb_y(t) W1_y   (W0/W1: alpha=0/1 rows)
+// grid (L0, 3), block 256; thread per (a, b)
+__global__ __launch_bounds__(256) void k_top_gamma(Geo g, int Nv, int r, const double2* __restrict__ W,
+                                                   const double2* __restrict__ G1, double2* __restrict__ A) {
+    const int x0 = blockIdx.x, k = blockIdx.y;
+    const int b0 = g.b[0], y0 = x0 / b0, t = x0 % b0;
+    const int nc = 2 * Nv, rowsz = g.V1 / g.L1[0];
+    const size_t V1 = g.V1;
+    for (int ab = threadIdx.x; ab < r * r; ab += blockDim.x) {
+        const int a = ab / r, b = ab % r;
+        cx<double> acc = cmk(0.0, 0.0);
+        for (int ys = 0; ys < rowsz; ++ys) {
+            const int y = y0 * rowsz + ys;
+            const double2* Gb = G1 + (((size_t)y * b0 + t) * 3 + k) * Nv * Nv;
+            const double2* wa = W + ((size_t)a * V1 + y) * nc;          // alpha = 0 rows at [0, Nv)
+            const double2* wb = W + ((size_t)b * V1 + y) * nc + Nv;     // alpha = 1 rows at [Nv, 2Nv)
+            for (int cc = 0; cc < Nv; ++cc) {
+                cx<double> s = cmk(0.0, 0.0);
+                for (int d = 0; d < Nv; ++d)
+                    cmac(s, ldc<double2, double>(Gb + cc * Nv + d), ldc<double2, double>(wb + d));
+                cjmac(acc, ldc<double2, double>(wa + cc), s);
+            }
+        }
+        A[(((size_t)x0 * 3 + k) * r + a) * r + b] = make_double2(acc.re, acc.im);
+    }
+}
+
+extern "C" int mglma_set_top_modes(mglma_ctx* c, int Nlm, const double* modes) {
+    if (!c || !modes || Nlm < 1) return MGLMA_ERR_ARG;
+    if (!c->have_subspace) return MGLMA_ERR_NO_SUBSPACE;
+    const Geo& g = c->geo;
+    const int nc = c->nc, r = 2 * Nlm;
+    const size_t n = (size_t)g.V1 * nc;
+    if (r > 256 || Nlm > (long)g.V1 * c->Nv) return MGLMA_ERR_ARG;
+    // release a previous top level
+    mg_free(c, c->W, (size_t)c->r * n * 16);
+    c->W = nullptr;
+    c->have_top = false;
+    c->Nlm = Nlm;
+    c->r = r;
+    MG_TRY(mg_malloc(c, (void**)&c->W, (size_t)r * n * 16));
+    hipLaunchKernelGGL(k_split_modes, dim3(1024), dim3(256), 0, c->stream, Nlm, g.V1, nc, (const double2*)modes, c->W);
+    HIP_TRY(hipGetLastError());
+
+    // Cholesky QR, twice, for each chirality set of Nlm columns
+    double *gd, *cd, *h;
+    double2* tmp;
+    MG_TRY(mg_scratch(c, 2, (size_t)Nlm * Nlm * 16 + 4096, (void**)&gd));
+    MG_TRY(mg_scratch(c, 3, (size_t)Nlm * Nlm * 16 + 4096, (void**)&cd));
+    MG_TRY(mg_scratch(c, 4, (size_t)Nlm * n * 16, (void**)&tmp));
+    MG_TRY(mg_host(c, (size_t)2 * Nlm * Nlm + 16, &h));
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int alpha = 0; alpha < 2; ++alpha) {
+            double2* Wa = c->W + (size_t)alpha * Nlm * n;
+            // G[q][p] = <w_p, w_q> stored at gd[(q*Nlm + p)*2]
+            MG_TRY(wdot(c, Wa, Nlm, Wa, Nlm, gd));
+            HIP_TRY(hipMemcpyAsync(h, gd, (size_t)Nlm * Nlm * 16, hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(hipStreamSynchronize(c->stream));
+            std::vector<zc> G((size_t)Nlm * Nlm), X;
+            for (int q = 0; q < Nlm; ++q)
+                for (int p = 0; p < Nlm; ++p) G[p * Nlm + q] = zc(h[(q * Nlm + p) * 2], h[(q * Nlm + p) * 2 + 1]);
+            int rc = chol_inv(G, Nlm, X);
+            if (rc != MGLMA_OK) { mg_free(c, c->W, (size_t)r * n * 16); c->W = nullptr; c->Nlm = c->r = 0; return rc; }
+            // new w_d = sum_{p<=d} X[p][d] w_p ; coefficients for column d at cd[(d*Nlm + p)*2]
+            for (int d = 0; d < Nlm; ++d)
+                for (int p = 0; p < Nlm; ++p) {
+                    zc v = p <= d ? X[p * Nlm + d] : zc(0);
+                    h[(d * Nlm + p) * 2] = v.real();
+                    h[(d * Nlm + p) * 2 + 1] = v.imag();
+                }
+            HIP_TRY(hipMemcpyAsync(cd, h, (size_t)Nlm * Nlm * 16, hipMemcpyHostToDevice, c->stream));
+            MG_TRY(mg_zero(c, tmp, (size_t)Nlm * n * 16));
+            for (int d = 0; d < Nlm; ++d)
+                MG_TRY(mg_multiaxpy(c, MGLMA_F64, Wa, n, d + 1, cd + (size_t)d * Nlm * 2, 1.0, tmp + (size_t)d * n, n, 1));
+            MG_TRY(mg_copy(c, Wa, tmp, (size_t)Nlm * n * 16));
+            HIP_TRY(hipStreamSynchronize(c->stream));
+        }
+    }
+    // D2 = W^+ D1 W
+    double2* AW;
+    MG_TRY(mg_scratch(c, 5, (size_t)r * n * 16, (void**)&AW));
+    MG_TRY(mg_coarse_apply(c, MGLMA_F64, 0, c->W, AW, r));
+    double* d2d;
+    MG_TRY(mg_scratch(c, 1, (size_t)r * r * 16 + 4096, (void**)&d2d));
+    MG_TRY(wdot(c, c->W, r, AW, r, d2d));
+    MG_TRY(mg_host(c, (size_t)2 * r * r + 16, &h));
+    HIP_TRY(hipMemcpyAsync(h, d2d, (size_t)r * r * 16, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->D2.assign((size_t)r * r, zc(0));
+    for (int b = 0; b < r; ++b)
+        for (int a = 0; a < r; ++a) c->D2[a * r + b] = zc(h[(b * r + a) * 2], h[(b * r + a) * 2 + 1]);
+    std::vector<zc> Q2(c->D2);
+    for (int a = 0; a < r; ++a)
+        if (a >= Nlm)
+            for (int b = 0; b < r; ++b) Q2[a * r + b] = -Q2[a * r + b];
+    MG_TRY(inverse(Q2, r, c->Q2inv));
+    // Gamma2[x0][k] = A - A^+ with A = W0^+ Gb W1
+    double2* Ad;
+    MG_TRY(mg_scratch(c, 0, (size_t)g.L[0] * 3 * r * r * 16, (void**)&Ad));
+    hipLaunchKernelGGL(k_top_gamma, dim3(g.L[0], 3), dim3(256), 0, c->stream, g, c->Nv, r, c->W, c->G1, Ad);
+    HIP_TRY(hipGetLastError());
+    std::vector<double> hA((size_t)g.L[0] * 3 * r * r * 2);
+    HIP_TRY(hipMemcpyAsync(hA.data(), Ad, hA.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->Gamma2.assign((size_t)g.L[0] * 3 * r * r, zc(0));
+    for (int x0 = 0; x0 < g.L[0]; ++x0)
+        for (int k = 0; k < 3; ++k) {
+            size_t o = ((size_t)x0 * 3 + k) * r * r;
+            for (int a = 0; a < r; ++a)
+                for (int b = 0; b < r; ++b) {
+                    zc A_ab(hA[(o + a * r + b) * 2], hA[(o + a * r + b) * 2 + 1]);
+                    zc A_ba(hA[(o + b * r + a) * 2], hA[(o + b * r + a) * 2 + 1]);
+                    c->Gamma2[o + a * r + b] = A_ab - std::conj(A_ba);
+                }
+        }
+    c->have_top = true;
+    return MGLMA_OK;
+}
+
+extern "C" int mglma_contract_top(mglma_ctx* c, double* G_host) {
+    if (!c || !G_host) return MGLMA_ERR_ARG;
+    if (!c->have_top) return MGLMA_ERR_NO_TOP;
+    const int L0 = c->L[0], r = c->r;
+    const double L3 = (double)c->geo.V3;
+    // A[x0][k] = G_k(x0) Q2^-1
+    std::vector<zc> A((size_t)L0 * 3 * r * r, zc(0));
+    for (int x0 = 0; x0 < L0; ++x0)
+        for (int k = 0; k < 3; ++k) {
+            const zc* G = &c->Gamma2[((size_t)x0 * 3 + k) * r * r];
+            zc* o = &A[((size_t)x0 * 3 + k) * r * r];
+            for (int a = 0; a < r; ++a)
+                for (int e = 0; e < r; ++e) {
+                    zc gae = G[a * r + e];
+                    if (gae == zc(0)) continue;
+                    for (int b = 0; b < r; ++b) o[a * r + b] += gae * c->Q2inv[e * r + b];
+                }
+        }
+    for (int t = 0; t < L0; ++t) {
+        zc s = 0;
+        for (int y0 = 0; y0 < L0; ++y0) {
+            int x0 = (y0 + t) % L0;
+            for (int k = 0; k < 3; ++k) {
+                const zc* P = &A[((size_t)x0 * 3 + k) * r * r];
+                const zc* Q = &A[((size_t)y0 * 3 + k) * r * r];
+                for (int a = 0; a < r; ++a)
+                    for (int b = 0; b < r; ++b) s += P[a * r + b] * Q[b * r + a];
+            }
+        }
+        s *= -1.0 / (3.0 * L0 * L3);
+        G_host[2 * t] = s.real();
+        G_host[2 * t + 1] = s.imag();
+    }
+    return MGLMA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// coarse-level pieces: ge1 = D1^{-1} R eta,  top = W D2^{-1} W^+ R eta
+// ---------------------------------------------------------------------------
+extern "C" int mglma_coarse_pieces(mglma_ctx* c, const mglma_solve_params* p, const double* eta, double* ge1,
+                                   double* top, int nrhs) {
+    if (!c || !p || !eta || !ge1 || nrhs < 1) return MGLMA_ERR_ARG;
+    if (!c->have_subspace) return MGLMA_ERR_NO_SUBSPACE;
+    if (top && !c->have_top) return MGLMA_ERR_NO_TOP;
+    const size_t n = (size_t)c->geo.V1 * c->nc;
+    double2* Re;
+    MG_TRY(mg_scratch(c, 26, (size_t)nrhs * n * 16, (void**)&Re));
+    MG_TRY(mg_restrict(c, MGLMA_F64, eta, Re, nrhs));
+    int rc = mg_coarse_solve(c, p, (const double*)Re, ge1, nrhs, nullptr);
+    if (rc != MGLMA_OK) return rc;
+    if (top) {
+        const int r = c->r;
+        double *cf, *h;
+        MG_TRY(mg_scratch(c, 27, (size_t)nrhs * r * 16 + 4096, (void**)&cf));
+        MG_TRY(wdot(c, c->W, r, Re, nrhs, cf));   // cf[q][a] = <W_a, R eta_q>
+        MG_TRY(mg_host(c, (size_t)2 * nrhs * r + 16, &h));
+        HIP_TRY(hipMemcpyAsync(h, cf, (size_t)nrhs * r * 16, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        std::vector<zc> D2inv;
+        MG_TRY(inverse(c->D2, r, D2inv));
+        std::vector<double> co((size_t)nrhs * r * 2);
+        for (int q = 0; q < nrhs; ++q)
+            for (int a = 0; a < r; ++a) {
+                zc s = 0;
+                for (int b = 0; b < r; ++b) s += D2inv[a * r + b] * zc(h[(q * r + b) * 2], h[(q * r + b) * 2 + 1]);
+                co[(q * r + a) * 2] = s.real();
+                co[(q * r + a) * 2 + 1] = s.imag();
+            }
+        HIP_TRY(hipMemcpyAsync(cf, co.data(), co.size() * 8, hipMemcpyHostToDevice, c->stream));
+        MG_TRY(mg_zero(c, top, (size_t)nrhs * n * 16));
+        for (int q = 0; q < nrhs; ++q)
+            MG_TRY(mg_multiaxpy(c, MGLMA_F64, c->W, n, r, cf + (size_t)q * r * 2, 1.0, top + (size_t)q * n * 2, n, 1));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+    }
+    return MGLMA_OK;
+}

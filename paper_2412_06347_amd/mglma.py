@@ -21,8 +21,9 @@ SYMBOLS = [
     "mglma_resident_bytes", "mglma_fine_bytes", "mglma_coarse_bytes",
     "mglma_load_gauge", "mglma_export_clover", "mglma_import_fields", "mglma_export_fields",
     "mglma_apply_D", "mglma_build_subspace", "mglma_export_basis", "mglma_export_coarse_op",
+    "mglma_export_coarse_gammas",
     "mglma_restrict", "mglma_prolong", "mglma_coarse_apply", "mglma_set_top_modes",
-    "mglma_solve", "mglma_coarse_solve", "mglma_subspace_pieces",
+    "mglma_solve", "mglma_coarse_solve", "mglma_coarse_pieces",
     "mglma_point_sources", "mglma_noise_sources",
     "mglma_contract_point", "mglma_contract_point_coarse", "mglma_contract_stoch",
     "mglma_contract_stoch_coarse", "mglma_contract_top",
@@ -180,6 +181,9 @@ class Context:
     def export_coarse_op(self, out):
         _check(lib().mglma_export_coarse_op(self._ctx, _ptr(out)))
 
+    def export_coarse_gammas(self, out):
+        _check(lib().mglma_export_coarse_gammas(self._ctx, _ptr(out)))
+
     def restrict(self, fine, coarse, prec=F64):
         _check(lib().mglma_restrict(self._ctx, prec, _ptr(fine), _ptr(coarse), fine.shape[0]))
 
@@ -208,9 +212,9 @@ class Context:
         _check(lib().mglma_coarse_solve(self._ctx, C.byref(params or default_params()), _ptr(b), _ptr(x), n, st))
         return [dict(outer=s.outer, inner=s.inner, true_rel_res=s.true_rel_res) for s in st[:n]]
 
-    def subspace_pieces(self, eta, ge1, top=None, params=None):
-        _check(lib().mglma_subspace_pieces(self._ctx, C.byref(params or default_params()), _ptr(eta),
-                                           _ptr(ge1), _ptr(top), eta.shape[0]))
+    def coarse_pieces(self, eta, ge1, top=None, params=None):
+        _check(lib().mglma_coarse_pieces(self._ctx, C.byref(params or default_params()), _ptr(eta),
+                                         _ptr(ge1), _ptr(top), eta.shape[0]))
 
     # ---- sources and contractions --------------------------------------------
     def point_sources(self, y, out):
