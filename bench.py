@@ -39,14 +39,14 @@ def log(*a):
 
 
 def mixed_params(mglma, **kw):
-    p = dict(tol=1e-10, max_outer=10, max_inner=120, gcr_m=8, inner_tol=1e-5, nu_post=4, coarse_iters=16,
+    p = dict(tol=1e-10, max_outer=10, max_inner=120, gcr_m=8, inner_tol=1e-5, nu_post=6, coarse_iters=16,
              smoother=mglma.F32, inner=mglma.F32, coarse=mglma.BF16, use_mg=1)
     p.update(kw)
     return mglma.default_params(**p)
 
 
 def fp64_params(mglma, **kw):
-    p = dict(tol=1e-10, max_outer=3, max_inner=400, gcr_m=8, inner_tol=1e-11, nu_post=4, coarse_iters=16,
+    p = dict(tol=1e-10, max_outer=3, max_inner=400, gcr_m=8, inner_tol=1e-11, nu_post=6, coarse_iters=16,
              smoother=mglma.F64, inner=mglma.F64, coarse=mglma.F64, use_mg=1)
     p.update(kw)
     return mglma.default_params(**p)
@@ -69,14 +69,14 @@ class Pipeline:
         ctx = self.ctx
         ctx.load_gauge(self.U)
         # test vectors: Gaussian fields improved by three rounds of approximate
-        # inverse iteration (unpreconditioned FP32 GCR steps) -- an input to the
-        # hot path, prepared outside the timed region
+        # inverse iteration (40 unpreconditioned FP32 GCR steps each) -- an
+        # input to the hot path, prepared outside the timed region
         tv = synth.gaussian_fields(wl["Nv"], L, wl["seed"] + 1000)
         x = ctx.fine(wl["Nv"])
         ctx.import_fields(torch.from_numpy(tv.view(np.float64)).cuda(), x)
         del tv
         y = ctx.fine(wl["Nv"])
-        p = mglma.default_params(use_mg=0, inner=mglma.F32, max_outer=1, max_inner=12, gcr_m=12, tol=1e-30,
+        p = mglma.default_params(use_mg=0, inner=mglma.F32, max_outer=1, max_inner=40, gcr_m=16, tol=1e-30,
                                  inner_tol=1e-30)
         for _ in range(3):
             ctx.solve(x, y, p, raise_on_error=False)
@@ -113,7 +113,7 @@ class Pipeline:
         ctx.set_top_modes(self.modes)                  # W, D_2, (gamma5 gamma_k)_2
         ctx.point_sources((0, 0, 0, 0), self.src)      # 12 point sources
         rc, stats = ctx.solve(self.src, self.x, params)
-        cp = mglma.default_params(tol=1e-10, coarse=mglma.BF16, coarse_iters=16)
+        cp = mglma.default_params(tol=1e-10, coarse=mglma.F32, coarse_iters=24)
         ctx.coarse_pieces(self.src, self.cg, self.ct, cp)
         C_all = ctx.contract_point(self.x, self.x, 0)
         C_ge1 = ctx.contract_point_coarse(self.cg, self.cg, 0)
@@ -138,64 +138,37 @@ def kernel_time(torch, fn, reps, stream):
 
 
 def cpu_baseline(wl, budget_s=20.0):
-    """The oracle (numpy FP64, single thread) on a bounded sample of the same
-    workload: restarted GCR(16) iterations on one point-source system of the
-    same lattice; the full-solve time is extrapolated from the per-iteration
-    time and the observed residual reduction rate."""
-    try:
-        from threadpoolctl import threadpool_limits
-    except Exception:  # pragma: no cover
-        threadpool_limits = None
-    from oracle import dirac, estimators
+    """The oracle (numpy FP64, one thread) on a bounded sample of the same
+    workload: the oracle's restarted GCR(16) on one point-source system of the
+    same lattice, stopped after about `budget_s` seconds; the time of a full
+    solve to 1e-10 is extrapolated from the time per iteration and the
+    observed residual reduction rate."""
+    from threadpoolctl import threadpool_limits
+    from oracle import dirac, estimators, solvers
     from paper_2412_06347_amd import synth
     L = wl["L"]
-    ctx = threadpool_limits(1) if threadpool_limits else None
-    try:
+    with threadpool_limits(1):
         U = synth.gauge_field(L, wl["eps"], wl["seed"])
         D = dirac.WilsonClover(U, L, wl["kappa"], wl["csw"])
         b = estimators.point_sources(L, (0, 0, 0, 0))[:1]
         t0 = time.time()
         D.M(b)
         t_apply = time.time() - t0
-        # GCR iterations within the budget (each iteration ~ one apply + vector algebra)
-        x = np.zeros_like(b)
-        r = b.copy()
-        bn = np.linalg.norm(b)
-        P, AP = [], []
-        it = 0
+        n_it = max(4, int(budget_s / (1.3 * t_apply)))
         t0 = time.time()
-        while time.time() - t0 < budget_s and it < 400:
-            if len(P) == 16:
-                P, AP = [], []
-            p = r.copy()
-            ap = D.M(p)
-            for q, aq in zip(P, AP):
-                beta = np.vdot(aq, ap)
-                ap = ap - beta * aq
-                p = p - beta * q
-            nrm = np.linalg.norm(ap)
-            ap /= nrm
-            p /= nrm
-            alpha = np.vdot(ap, r)
-            x += alpha * p
-            r -= alpha * ap
-            P.append(p)
-            AP.append(ap)
-            it += 1
-        t_it = (time.time() - t0) / it
-        res = np.linalg.norm(r) / bn
-        rate = np.log(res) / it
-        iters_needed = np.log(1e-10) / rate if rate < 0 else float("inf")
-        solves_per_s = 1.0 / (t_it * iters_needed)
-        return dict(value=float(solves_per_s), unit="solves/s", cores=1, kind="oracle",
-                    sample="numpy FP64 oracle, 1 thread: %d GCR(16) iterations (%.1f s, one apply %.2f s) on one "
-                           "point-source system of the %s lattice reduced the residual to %.2e; full solve to 1e-10 "
-                           "extrapolated at that rate to %.0f iterations" % (it, t_it * it, t_apply,
-                                                                             "x".join(map(str, L)), res,
-                                                                             iters_needed))
-    finally:
-        if ctx is not None:
-            ctx.__exit__(None, None, None)
+        x, it, res = solvers.gcr(D.M, b, tol=1e-10, m=16, max_iter=n_it)
+        t = time.time() - t0
+    res = float(res[0])
+    t_it = t / max(it, 1)
+    rate = np.log(res) / max(it, 1)
+    iters_needed = np.log(1e-10) / rate if rate < 0 else float("inf")
+    return dict(value=float(1.0 / (t_it * iters_needed)), unit="solves/s", cores=1, kind="oracle",
+                sample="numpy FP64 oracle on 1 thread (%s): %d iterations of its restarted GCR(16) on one "
+                       "point-source system of the %s lattice took %.1f s and reduced the residual to %.2e; the "
+                       "full solve to 1e-10 is extrapolated at that rate (%.0f iterations)" % (
+                           os.uname().nodename and (open("/proc/cpuinfo").read().split("model name")[1]
+                                                    .split(":")[1].split("\n")[0].strip()),
+                           it, "x".join(map(str, L)), t, res, iters_needed))
 
 
 def main():
@@ -208,6 +181,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison step")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--calib-copy", action="store_true", help="only run a plain 1 GiB device copy (counter scale)")
+    ap.add_argument("--dslash-only", action="store_true",
+                    help="only run the Wilson-clover apply of the workload (for hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one MI355X only: the hot path runs on a single GPU "
@@ -222,8 +197,21 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calib_copy_bytes_read": a.numel() * 8, "copies": 3}))
         return
-    from paper_2412_06347_amd import mglma
+    from paper_2412_06347_amd import mglma, synth
     wl = WORKLOADS[args.workload]
+    if args.dslash_only:
+        L = wl["L"]
+        U = torch.from_numpy(synth.gauge_field(L, wl["eps"], wl["seed"]).view(np.float64)).cuda()
+        ctx = mglma.Context(L, wl["block"], wl["kappa"], wl["csw"])
+        ctx.load_gauge(U)
+        for prec, nr in [(mglma.F32, 12), (mglma.F64, 1), (mglma.F32, 1), (mglma.F16, 1)]:
+            x, y = ctx.fine(nr, prec), ctx.fine(nr, prec)
+            x.normal_()
+            for _ in range(5):
+                ctx.apply_D(x, y, prec)
+        torch.cuda.synchronize()
+        print(json.dumps({"dslash_only": True, "V": ctx.V, "launches": "5 x (f32 12rhs, f64 1rhs, f32 1rhs, f16 1rhs)"}))
+        return
     P = Pipeline(wl)
     stream = torch.cuda.current_stream()
     params = mixed_params(mglma)

@@ -77,7 +77,8 @@ typedef struct {
     int    gcr_m;        /* inner FGCR restart length                          */
     double inner_tol;    /* relative reduction asked of each inner solve       */
     int    nu_post;      /* MR smoothing steps after the coarse correction     */
-    int    coarse_iters; /* GCR steps of the coarse solve in the preconditioner*/
+    int    coarse_iters; /* GCR steps of the coarse solve in the preconditioner
+                            (0: no coarse correction, smoother only)        */
     int    smoother;     /* precision of the smoother Dslash (mglma_prec)      */
     int    inner;        /* precision of the inner Krylov vectors (F32 or F64) */
     int    coarse;       /* precision of the preconditioner's coarse operator  */
@@ -160,7 +161,8 @@ int mglma_coarse_apply(mglma_ctx* ctx, int prec, int gamma5, const void* in_dev,
  * complex128): each is split by (gamma5)_1 chirality and each chirality set
  * orthonormalised in order, giving W with r = 2 Nlm columns; then
  * D_2 = W^+ D_1 W, Q_2 = (gamma5)_2 D_2 and (gamma5 gamma_k)_2(x0) = W^+
- * (gamma5 gamma_k)_1(x0) W.  Synchronising.  Errors: NO_SUBSPACE, RANK.    */
+ * (gamma5 gamma_k)_1(x0) W.  Nlm <= 64.  Synchronising.
+ * Errors: NO_SUBSPACE, ARG, RANK.                                          */
 int mglma_set_top_modes(mglma_ctx* ctx, int Nlm, const double* modes_dev);
 
 /* ---- solves -------------------------------------------------------------- */

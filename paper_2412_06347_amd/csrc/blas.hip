@@ -326,3 +326,156 @@ int mg_convert(mglma_ctx* c, int pin, const void* x, int pout, void* y, size_t n
         default: return MGLMA_ERR_ARG;
     }
 }
+
+// ---------------------------------------------------------------------------
+// fused kernels for the solver loops
+// ---------------------------------------------------------------------------
+// out[r] = (Re <x,y>, Im <x,y>, |x|^2)
+template <typename S>
+__global__ __launch_bounds__(RB) void k_dot_norm(const S* __restrict__ x, const S* __restrict__ y, size_t n,
+                                                 double* part, unsigned* cnt, double* out) {
+    __shared__ double lds[4 * 3];
+    const size_t roff = (size_t)blockIdx.y * n;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (size_t e = (size_t)blockIdx.x * RB + threadIdx.x; e < n; e += (size_t)gridDim.x * RB) {
+        cx<double> a = ldc<S, double>(x + roff + e), b = ldc<S, double>(y + roff + e);
+        v[0] = fma(a.re, b.re, v[0]); v[0] = fma(a.im, b.im, v[0]);
+        v[1] = fma(a.re, b.im, v[1]); v[1] = fma(-a.im, b.re, v[1]);
+        v[2] = fma(a.re, a.re, v[2]); v[2] = fma(a.im, a.im, v[2]);
+    }
+    block_sum<3>(v, lds);
+    finish<3>(v, part, cnt, out, 3);
+}
+
+int mg_dot_norm(mglma_ctx* c, int prec, const void* x, const void* y, size_t n, int nrhs, double* out) {
+    if (nrhs <= 0) return MGLMA_OK;
+    int nb = red_blocks(n);
+    MG_TRY(ensure_red(c, (size_t)nb * nrhs * 3, nrhs));
+    dim3 grid(nb, nrhs);
+    switch (prec) {
+        case MGLMA_F64: hipLaunchKernelGGL(k_dot_norm<double2>, grid, dim3(RB), 0, c->stream, (const double2*)x, (const double2*)y, n, c->red_part, c->red_cnt, out); break;
+        case MGLMA_F32: hipLaunchKernelGGL(k_dot_norm<float2>, grid, dim3(RB), 0, c->stream, (const float2*)x, (const float2*)y, n, c->red_part, c->red_cnt, out); break;
+        default: return MGLMA_ERR_ARG;
+    }
+    HIP_TRY(hipGetLastError());
+    return MGLMA_OK;
+}
+
+// z += a s ; s -= a t    (a complex per rhs)
+template <typename S, typename R>
+__global__ void k_mr_update(const double* __restrict__ a, S* __restrict__ z, S* __restrict__ s,
+                            const S* __restrict__ t, size_t n) {
+    const int r = blockIdx.y;
+    const size_t roff = (size_t)r * n;
+    const cx<R> w = cmk((R)a[2 * r], (R)a[2 * r + 1]);
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        cx<R> sv = ldc<S, R>(s + roff + e), zv = ldc<S, R>(z + roff + e), tv = ldc<S, R>(t + roff + e);
+        cmac(zv, w, sv);
+        cmac(sv, -w, tv);
+        stc<S, R>(z + roff + e, zv);
+        stc<S, R>(s + roff + e, sv);
+    }
+}
+
+int mg_mr_update(mglma_ctx* c, int prec, const double* a, void* z, void* s, const void* t, size_t n, int nrhs) {
+    if (nrhs <= 0) return MGLMA_OK;
+    dim3 grid = ew_grid(n, nrhs);
+    switch (prec) {
+        case MGLMA_F64: hipLaunchKernelGGL((k_mr_update<double2, double>), grid, dim3(256), 0, c->stream, a, (double2*)z, (double2*)s, (const double2*)t, n); break;
+        case MGLMA_F32: hipLaunchKernelGGL((k_mr_update<float2, float>), grid, dim3(256), 0, c->stream, a, (float2*)z, (float2*)s, (const float2*)t, n); break;
+        default: return MGLMA_ERR_ARG;
+    }
+    HIP_TRY(hipGetLastError());
+    return MGLMA_OK;
+}
+
+// y1 -= sum_j coef[j][r] x1_j ;  y2 -= sum_j coef[j][r] x2_j
+template <typename S, typename R, int K>
+__global__ void k_multiaxpy2(const S* __restrict__ x1, const S* __restrict__ x2, size_t xstride, int k,
+                             const double* __restrict__ coef, S* __restrict__ y1, S* __restrict__ y2, size_t n,
+                             int nrhs) {
+    const int r = blockIdx.y;
+    const size_t roff = (size_t)r * n;
+    cx<R> a[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        a[j] = j < k ? cmk((R)-coef[((size_t)j * nrhs + r) * 2], (R)-coef[((size_t)j * nrhs + r) * 2 + 1])
+                     : cmk((R)0, (R)0);
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        cx<R> v1 = ldc<S, R>(y1 + roff + e), v2 = ldc<S, R>(y2 + roff + e);
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (j < k) {
+                cmac(v1, a[j], ldc<S, R>(x1 + (size_t)j * xstride + roff + e));
+                cmac(v2, a[j], ldc<S, R>(x2 + (size_t)j * xstride + roff + e));
+            }
+        stc<S, R>(y1 + roff + e, v1);
+        stc<S, R>(y2 + roff + e, v2);
+    }
+}
+
+template <typename S, typename R>
+static int multiaxpy2_t(mglma_ctx* c, const S* x1, const S* x2, size_t xstride, int k, const double* coef, S* y1,
+                        S* y2, size_t n, int nrhs) {
+    for (int j0 = 0; j0 < k; j0 += MAXK) {
+        int kk = k - j0 < MAXK ? k - j0 : MAXK;
+        const double* cj = coef + (size_t)j0 * nrhs * 2;
+        const S* a1 = x1 + (size_t)j0 * xstride;
+        const S* a2 = x2 + (size_t)j0 * xstride;
+        if (kk <= 4)
+            hipLaunchKernelGGL((k_multiaxpy2<S, R, 4>), ew_grid(n, nrhs), dim3(256), 0, c->stream, a1, a2, xstride, kk, cj, y1, y2, n, nrhs);
+        else
+            hipLaunchKernelGGL((k_multiaxpy2<S, R, MAXK>), ew_grid(n, nrhs), dim3(256), 0, c->stream, a1, a2, xstride, kk, cj, y1, y2, n, nrhs);
+        HIP_TRY(hipGetLastError());
+    }
+    return MGLMA_OK;
+}
+
+int mg_multiaxpy2(mglma_ctx* c, int prec, const void* x1, const void* x2, size_t xstride, int k, const double* coef,
+                  void* y1, void* y2, size_t n, int nrhs) {
+    if (nrhs <= 0 || k <= 0) return MGLMA_OK;
+    switch (prec) {
+        case MGLMA_F64: return multiaxpy2_t<double2, double>(c, (const double2*)x1, (const double2*)x2, xstride, k, coef, (double2*)y1, (double2*)y2, n, nrhs);
+        case MGLMA_F32: return multiaxpy2_t<float2, float>(c, (const float2*)x1, (const float2*)x2, xstride, k, coef, (float2*)y1, (float2*)y2, n, nrhs);
+        default: return MGLMA_ERR_ARG;
+    }
+}
+
+// e += a z ; r -= a w ; out[r] = |r|^2 after the update
+template <typename S, typename R>
+__global__ __launch_bounds__(RB) void k_update_norm(const double* __restrict__ a, S* __restrict__ e, const S* __restrict__ z,
+                                                    S* __restrict__ rr, const S* __restrict__ w, size_t n,
+                                                    double* part, unsigned* cnt, double* out) {
+    __shared__ double lds[4];
+    const int r = blockIdx.y;
+    const size_t roff = (size_t)r * n;
+    const cx<R> al = cmk((R)a[2 * r], (R)a[2 * r + 1]);
+    double v[1] = {0.0};
+    for (size_t k = (size_t)blockIdx.x * RB + threadIdx.x; k < n; k += (size_t)gridDim.x * RB) {
+        cx<R> ev = ldc<S, R>(e + roff + k), rv = ldc<S, R>(rr + roff + k);
+        cmac(ev, al, ldc<S, R>(z + roff + k));
+        cmac(rv, -al, ldc<S, R>(w + roff + k));
+        stc<S, R>(e + roff + k, ev);
+        stc<S, R>(rr + roff + k, rv);
+        cx<double> rs = ldc<S, double>(rr + roff + k);   // the stored (rounded) value
+        v[0] = fma(rs.re, rs.re, v[0]);
+        v[0] = fma(rs.im, rs.im, v[0]);
+    }
+    block_sum<1>(v, lds);
+    finish<1>(v, part, cnt, out, 1);
+}
+
+int mg_update_norm(mglma_ctx* c, int prec, const double* a, void* e, const void* z, void* r, const void* w, size_t n,
+                   int nrhs, double* out) {
+    if (nrhs <= 0) return MGLMA_OK;
+    int nb = red_blocks(n);
+    MG_TRY(ensure_red(c, (size_t)nb * nrhs, nrhs));
+    dim3 grid(nb, nrhs);
+    switch (prec) {
+        case MGLMA_F64: hipLaunchKernelGGL((k_update_norm<double2, double>), grid, dim3(RB), 0, c->stream, a, (double2*)e, (const double2*)z, (double2*)r, (const double2*)w, n, c->red_part, c->red_cnt, out); break;
+        case MGLMA_F32: hipLaunchKernelGGL((k_update_norm<float2, float>), grid, dim3(RB), 0, c->stream, a, (float2*)e, (const float2*)z, (float2*)r, (const float2*)w, n, c->red_part, c->red_cnt, out); break;
+        default: return MGLMA_ERR_ARG;
+    }
+    HIP_TRY(hipGetLastError());
+    return MGLMA_OK;
+}

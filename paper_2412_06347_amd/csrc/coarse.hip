@@ -27,36 +27,53 @@ __device__ __forceinline__ int coarse_nbr(const Geo& g, int y, int dir) {
     return y + (nmu - cmu) * stride;
 }
 
-#define NRC 8
+#define NRC 16
 
+// One thread per (coarse site, row i); ny = 256 / nc coarse sites per
+// workgroup.  For each direction the neighbours' vectors (rc right-hand sides)
+// are staged in LDS; the operator column D[j][i] is read coalesced from the
+// column-major copy and used for all staged right-hand sides.
 template <typename S, typename R>
 __global__ __launch_bounds__(256) void k_coarse_valu(Geo g, int nc, const S* __restrict__ Dt, const S* __restrict__ in,
-                                                     S* __restrict__ out, int nrhs, int gamma5) {
+                                                     S* __restrict__ out, int nrhs, int gamma5, int rc) {
+    extern __shared__ char shraw[];
+    cx<R>* VS = (cx<R>*)shraw;   // [ny][nc][rc]
     const int ny = 256 / nc;
     const int ysub = threadIdx.x / nc, i = threadIdx.x - ysub * nc;
     const int y = blockIdx.x * ny + ysub;
-    if (ysub >= ny || y >= g.V1) return;
+    const bool act = ysub < ny && y < g.V1;
     const size_t V1 = g.V1;
     const R sg = (gamma5 && i >= nc / 2) ? (R)-1 : (R)1;
-    for (int r0 = 0; r0 < nrhs; r0 += NRC) {
-        const int nr = nrhs - r0 < NRC ? nrhs - r0 : NRC;
+    for (int r0 = 0; r0 < nrhs; r0 += rc) {
+        const int nr = nrhs - r0 < rc ? nrhs - r0 : rc;
         cx<R> acc[NRC];
 #pragma unroll
         for (int q = 0; q < NRC; ++q) acc[q] = cmk((R)0, (R)0);
         for (int dir = 0; dir < 9; ++dir) {
-            const int z = coarse_nbr(g, y, dir);
-            const S* dcol = Dt + ((size_t)y * 9 + dir) * nc * nc + i;
-            const S* v = in + ((size_t)r0 * V1 + z) * nc;
-            for (int j = 0; j < nc; ++j) {
-                cx<R> d = ldc<S, R>(dcol + (size_t)j * nc);
+            __syncthreads();
+            for (int e = threadIdx.x; e < ny * nc * nr; e += blockDim.x) {
+                const int r = e % nr, t = e / nr, j = t % nc, ys = t / nc;
+                const int yy = blockIdx.x * ny + ys;
+                VS[(ys * nc + j) * rc + r] = yy < g.V1
+                    ? ldc<S, R>(in + ((size_t)(r0 + r) * V1 + coarse_nbr(g, yy, dir)) * nc + j) : cmk((R)0, (R)0);
+            }
+            __syncthreads();
+            if (act) {
+                const S* dcol = Dt + ((size_t)y * 9 + dir) * nc * nc + i;
+                const cx<R>* vs = VS + (size_t)ysub * nc * rc;
+                for (int j = 0; j < nc; ++j) {
+                    const cx<R> d = ldc<S, R>(dcol + (size_t)j * nc);
 #pragma unroll
-                for (int q = 0; q < NRC; ++q)
-                    if (q < nr) cmac(acc[q], d, ldc<S, R>(v + (size_t)q * V1 * nc + j));
+                    for (int q = 0; q < NRC; ++q)
+                        if (q < nr) cmac(acc[q], d, vs[j * rc + q]);
+                }
             }
         }
+        if (act) {
 #pragma unroll
-        for (int q = 0; q < NRC; ++q)
-            if (q < nr) stc<S, R>(out + ((size_t)(r0 + q) * V1 + y) * nc + i, sg * acc[q]);
+            for (int q = 0; q < NRC; ++q)
+                if (q < nr) stc<S, R>(out + ((size_t)(r0 + q) * V1 + y) * nc + i, sg * acc[q]);
+        }
     }
 }
 
@@ -69,7 +86,10 @@ __device__ __forceinline__ short f2bf(float f) {
     return (short)(u >> 16);
 }
 
-// grid: (V1, ceil(nrhs/16)); block: 64 * ceil(nc/16) threads, wave w = row tile
+// grid: (V1, ceil(nrhs/16)); block: 64 * ceil(nc/16) threads, wave w = row tile.
+// FULL: nc is a multiple of 16, so every fragment load is in range and can be
+// one 8-byte (operator) / two 16-byte (vector) load per lane.
+template <bool FULL>
 __global__ void k_coarse_bf16(Geo g, int nc, const bf16_t* __restrict__ Dbf, const float2* __restrict__ in,
                               float2* __restrict__ out, int nrhs, int gamma5) {
     const int y = blockIdx.x;
@@ -81,23 +101,36 @@ __global__ void k_coarse_bf16(Geo g, int nc, const bf16_t* __restrict__ Dbf, con
     f4_t cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
     const int n = n0 + lr;                            // rhs of this lane's B column
     const int m = m0 + lr;                            // row of this lane's A fragment
+    const bool nok = n < nrhs;
     for (int dir = 0; dir < 9; ++dir) {
         const int z = coarse_nbr(g, y, dir);
         const bf16_t* Dr = Dbf + ((size_t)y * 9 + dir) * 2 * nn;
         const bf16_t* Di = Dr + nn;
-        const float2* v = in + ((size_t)n * V1 + z) * nc;
+        const float2* v = in + ((size_t)(nok ? n : 0) * V1 + z) * nc;
         for (int k0 = 0; k0 < nc; k0 += 16) {
+            const int kb = k0 + 4 * lq;
             bf4_t ar, ai, br, bi, bn;
+            if (FULL) {
+                ar = *(const bf4_t*)(Dr + (size_t)m * nc + kb);
+                ai = *(const bf4_t*)(Di + (size_t)m * nc + kb);
+                float4 x01 = nok ? *(const float4*)(v + kb) : make_float4(0.f, 0.f, 0.f, 0.f);
+                float4 x23 = nok ? *(const float4*)(v + kb + 2) : make_float4(0.f, 0.f, 0.f, 0.f);
+                br[0] = f2bf(x01.x); bi[0] = f2bf(x01.y); bn[0] = f2bf(-x01.y);
+                br[1] = f2bf(x01.z); bi[1] = f2bf(x01.w); bn[1] = f2bf(-x01.w);
+                br[2] = f2bf(x23.x); bi[2] = f2bf(x23.y); bn[2] = f2bf(-x23.y);
+                br[3] = f2bf(x23.z); bi[3] = f2bf(x23.w); bn[3] = f2bf(-x23.w);
+            } else {
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                int k = k0 + 4 * lq + t;
-                bool ok = k < nc;
-                ar[t] = (ok && m < nc) ? (short)Dr[(size_t)m * nc + k] : (short)0;
-                ai[t] = (ok && m < nc) ? (short)Di[(size_t)m * nc + k] : (short)0;
-                float2 x = (ok && n < nrhs) ? v[k] : make_float2(0.f, 0.f);
-                br[t] = f2bf(x.x);
-                bi[t] = f2bf(x.y);
-                bn[t] = f2bf(-x.y);
+                for (int t = 0; t < 4; ++t) {
+                    int k = kb + t;
+                    bool ok = k < nc;
+                    ar[t] = (ok && m < nc) ? (short)Dr[(size_t)m * nc + k] : (short)0;
+                    ai[t] = (ok && m < nc) ? (short)Di[(size_t)m * nc + k] : (short)0;
+                    float2 x = (ok && nok) ? v[k] : make_float2(0.f, 0.f);
+                    br[t] = f2bf(x.x);
+                    bi[t] = f2bf(x.y);
+                    bn[t] = f2bf(-x.y);
+                }
             }
             cr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, br, cr, 0, 0, 0);
             cr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bn, cr, 0, 0, 0);
@@ -106,14 +139,23 @@ __global__ void k_coarse_bf16(Geo g, int nc, const bf16_t* __restrict__ Dbf, con
         }
     }
     // C[row = 4*lq + t][col = lr]
-    const int nout = n0 + lr;
-    if (nout < nrhs) {
+    if (nok) {
+        const int row0 = m0 + 4 * lq;
+        float2* o = out + ((size_t)n * V1 + y) * nc + row0;
+        if (FULL) {
+            float s[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            int row = m0 + 4 * lq + t;
-            if (row < nc) {
-                float s = (gamma5 && row >= nc / 2) ? -1.f : 1.f;
-                out[((size_t)nout * V1 + y) * nc + row] = make_float2(s * cr[t], s * ci[t]);
+            for (int t = 0; t < 4; ++t) s[t] = (gamma5 && row0 + t >= nc / 2) ? -1.f : 1.f;
+            *(float4*)o = make_float4(s[0] * cr[0], s[0] * ci[0], s[1] * cr[1], s[1] * ci[1]);
+            *(float4*)(o + 2) = make_float4(s[2] * cr[2], s[2] * ci[2], s[3] * cr[3], s[3] * ci[3]);
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                int row = row0 + t;
+                if (row < nc) {
+                    float sg = (gamma5 && row >= nc / 2) ? -1.f : 1.f;
+                    o[t] = make_float2(sg * cr[t], sg * ci[t]);
+                }
             }
         }
     }
@@ -126,21 +168,29 @@ int mg_coarse_apply(mglma_ctx* c, int prec, int gamma5, const void* in, void* ou
     if (prec == MGLMA_BF16) {
         dim3 grid(g.V1, (nrhs + 15) / 16);
         dim3 block(64 * ((nc + 15) / 16));
-        hipLaunchKernelGGL(k_coarse_bf16, grid, block, 0, c->stream, g, nc, c->Dbf, (const float2*)in, (float2*)out,
-                           nrhs, gamma5);
+        if (nc % 16 == 0)
+            hipLaunchKernelGGL(k_coarse_bf16<true>, grid, block, 0, c->stream, g, nc, c->Dbf, (const float2*)in,
+                               (float2*)out, nrhs, gamma5);
+        else
+            hipLaunchKernelGGL(k_coarse_bf16<false>, grid, block, 0, c->stream, g, nc, c->Dbf, (const float2*)in,
+                               (float2*)out, nrhs, gamma5);
         HIP_TRY(hipGetLastError());
         return MGLMA_OK;
     }
     const int ny = 256 / nc;
     dim3 grid((g.V1 + ny - 1) / ny);
+    const size_t cb = prec == MGLMA_F64 ? 16 : 8;
+    int rc = (int)((48 * 1024) / ((size_t)ny * nc * cb));
+    if (rc > NRC) rc = NRC;
+    const size_t shb = (size_t)ny * nc * rc * cb;
     switch (prec) {
         case MGLMA_F64:
-            hipLaunchKernelGGL((k_coarse_valu<double2, double>), grid, dim3(256), 0, c->stream, g, nc, c->D64t,
-                               (const double2*)in, (double2*)out, nrhs, gamma5);
+            hipLaunchKernelGGL((k_coarse_valu<double2, double>), grid, dim3(256), shb, c->stream, g, nc, c->D64t,
+                               (const double2*)in, (double2*)out, nrhs, gamma5, rc);
             break;
         case MGLMA_F32:
-            hipLaunchKernelGGL((k_coarse_valu<float2, float>), grid, dim3(256), 0, c->stream, g, nc, c->D32,
-                               (const float2*)in, (float2*)out, nrhs, gamma5);
+            hipLaunchKernelGGL((k_coarse_valu<float2, float>), grid, dim3(256), shb, c->stream, g, nc, c->D32,
+                               (const float2*)in, (float2*)out, nrhs, gamma5, rc);
             break;
         default: return MGLMA_ERR_ARG;
     }

@@ -118,14 +118,23 @@ __device__ __forceinline__ void clover_block(const G* __restrict__ C, size_t V, 
         }
 }
 
+// Workgroup -> (site tile, rhs) mapping.  Workgroups are dealt to the eight
+// XCDs round robin (workgroup b runs on XCD b % 8), each XCD with its own L2.
+// XCD x gets the contiguous tile range [x*ntp/8, (x+1)*ntp/8), so the
+// neighbour spinors and links a tile reads were mostly brought into that
+// XCD's L2 by the adjacent tiles, and the nrhs workgroups of one tile are
+// dealt to the same XCD back to back so its links and clover are read from
+// HBM once for the whole batch.
 template <typename S, typename G, typename R>
 __global__ __launch_bounds__(256) void k_dslash(Geo g, const S* __restrict__ in, S* __restrict__ out,
                                                 const G* __restrict__ U, const G* __restrict__ C, R kappa,
-                                                int gamma5) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+                                                int gamma5, int nrhs, int ntp) {
+    const int b = blockIdx.x, xcd = b & 7, pos = b >> 3;
+    const int tile = xcd * (ntp >> 3) + pos / nrhs, rhs = pos - (pos / nrhs) * nrhs;
+    const int i = tile * 256 + threadIdx.x;
     if (i >= g.V) return;
     const size_t V = g.V;
-    const size_t roff = (size_t)blockIdx.y * 12 * V;
+    const size_t roff = (size_t)rhs * 12 * V;
     const S* pin = in + roff;
     int lc[4], yc[4];
     geo_coords(g, i, lc, yc);
@@ -159,19 +168,21 @@ __global__ __launch_bounds__(256) void k_dslash(Geo g, const S* __restrict__ in,
 int mg_dslash(mglma_ctx* c, int prec, int gamma5, const void* in, void* out, int nrhs) {
     if (nrhs == 0) return MGLMA_OK;
     const Geo& g = c->geo;
-    dim3 grid((g.V + 255) / 256, nrhs);
+    const int ntp = ((g.V + 255) / 256 + 7) / 8 * 8;   // tiles, padded to a multiple of the XCD count
+    if ((size_t)ntp * nrhs > 0x7fffffffu) return MGLMA_ERR_SHAPE;
+    dim3 grid(ntp * nrhs);
     switch (prec) {
         case MGLMA_F64:
             hipLaunchKernelGGL((k_dslash<double2, double2, double>), grid, dim3(256), 0, c->stream, g,
-                               (const double2*)in, (double2*)out, c->U64, c->C64, c->kappa, gamma5);
+                               (const double2*)in, (double2*)out, c->U64, c->C64, c->kappa, gamma5, nrhs, ntp);
             break;
         case MGLMA_F32:
             hipLaunchKernelGGL((k_dslash<float2, float2, float>), grid, dim3(256), 0, c->stream, g,
-                               (const float2*)in, (float2*)out, c->U32, c->C32, (float)c->kappa, gamma5);
+                               (const float2*)in, (float2*)out, c->U32, c->C32, (float)c->kappa, gamma5, nrhs, ntp);
             break;
         case MGLMA_F16:
             hipLaunchKernelGGL((k_dslash<__half2, __half2, float>), grid, dim3(256), 0, c->stream, g,
-                               (const __half2*)in, (__half2*)out, c->U16, c->C16, (float)c->kappa, gamma5);
+                               (const __half2*)in, (__half2*)out, c->U16, c->C16, (float)c->kappa, gamma5, nrhs, ntp);
             break;
         default: return MGLMA_ERR_ARG;
     }
@@ -185,50 +196,207 @@ extern "C" int mglma_apply_D(mglma_ctx* c, int prec, int gamma5, const void* in,
     return mg_dslash(c, prec, gamma5 ? 1 : 0, in, out, nrhs);
 }
 
-// Pieces of M used to assemble the Galerkin coarse operator (fig:A): for
-// mode 0 the clover term plus the hops that stay inside the sender's block,
-// for mode 1+2mu (2+2mu) only the forward (backward) mu hops that leave the
-// block through its +mu (-mu) face.  FP64 only.
-__global__ __launch_bounds__(256) void k_dslash_piece(Geo g, const double2* __restrict__ in, double2* __restrict__ out,
-                                                      const double2* __restrict__ U, const double2* __restrict__ C,
-                                                      double kappa, int mode) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= g.V) return;
-    const size_t V = g.V;
-    const size_t roff = (size_t)blockIdx.y * 12 * V;
-    const double2* pin = in + roff;
-    int lc[4], yc[4];
-    geo_coords(g, i, lc, yc);
-    cx<double> acc[12];
-#pragma unroll
-    for (int k = 0; k < 12; ++k) acc[k] = cmk(0.0, 0.0);
-#define PIECE(MU)                                                                                   \
-    {                                                                                               \
-        bool cf = lc[MU] == g.b[MU] - 1, cb = lc[MU] == 0;                                          \
-        if (mode == 0 ? !cf : (mode == 1 + 2 * MU && cf))                                           \
-            hop<MU, true, double2, double2, double>(g, i, lc, yc, pin, U, acc);                     \
-        if (mode == 0 ? !cb : (mode == 2 + 2 * MU && cb))                                           \
-            hop<MU, false, double2, double2, double>(g, i, lc, yc, pin, U, acc);                    \
-    }
-    PIECE(0) PIECE(1) PIECE(2) PIECE(3)
-#undef PIECE
-    double2* po = out + roff;
-    for (int ch = 0; ch < 2; ++ch) {
-        cx<double> p[6], res[6];
-        if (mode == 0) {
-            for (int k = 0; k < 6; ++k) p[k] = ldc<double2, double>(pin + (size_t)(6 * ch + k) * V + i);
-            clover_block<double2, double>(C + (size_t)ch * 18 * V, V, i, p, res);
-        } else {
-            for (int k = 0; k < 6; ++k) res[k] = cmk(0.0, 0.0);
-        }
-        for (int k = 0; k < 6; ++k) stc<double2, double>(po + (size_t)(6 * ch + k) * V + i, res[k] - kappa * acc[6 * ch + k]);
+// ---------------------------------------------------------------------------
+// Galerkin coarse operator D_1 = R M T (fig:A) assembled block by block.
+//
+// For basis vectors phi_i of block y and phi_j of block y' the hop terms reduce
+// to half spinors: a^+ (1 -/+ gamma_mu) b = h(a)^+ h(b) with h the rank-2 spin
+// projection used by the fine operator, so
+//   D_1[y][+mu][i][j] = -kappa sum_{x in +mu face of B_y} h(phi_i(x))^+ U_mu(x) h(phi_j(x+mu))
+// (and likewise for -mu with U_mu(x-mu)^+), while D_1[y][0] collects the clover
+// term and the hops between sites of the same block.  Each (block, piece) is a
+// small complex GEMM (nc x 6F) (6F x nc) over the F sites of the piece,
+// staged through LDS a few sites at a time, with a TI x TJ register tile of
+// outputs per thread.
+//
+// Pieces: 0 clover; 1..8 hops inside the block (mu = (p-1)/2, forward if p-1
+// is even); 9..16 hops through a face (mu = (p-9)/2).  Pieces 0..8 go to a
+// scratch array and are added into D_1[y][0] in a fixed order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void project_rt(int mu, bool fwd, const cx<double> p[12], cx<double> h[6]) {
+    switch (mu * 2 + (fwd ? 0 : 1)) {
+        case 0: project<0, true, double>(p, h); break;
+        case 1: project<0, false, double>(p, h); break;
+        case 2: project<1, true, double>(p, h); break;
+        case 3: project<1, false, double>(p, h); break;
+        case 4: project<2, true, double>(p, h); break;
+        case 5: project<2, false, double>(p, h); break;
+        case 6: project<3, true, double>(p, h); break;
+        default: project<3, false, double>(p, h); break;
     }
 }
 
-int mg_dslash_piece(mglma_ctx* c, int mode, const double2* in, double2* out, int nrhs) {
+// the 12-component spinor of basis vector j (chirality j / Nv) at block site l
+__device__ __forceinline__ void load_basis(const double2* __restrict__ B, int Nv, int Vb, int y, int j, int l,
+                                           cx<double> p[12]) {
+    const int a = j / Nv, cidx = j - a * Nv;
+    const double2* src = B + (((size_t)y * 2 + a) * Nv + cidx) * 6 * (size_t)Vb + l;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) p[k] = cmk(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) p[6 * a + k] = ldc<double2, double>(src + (size_t)k * Vb);
+}
+
+template <int GAL_TI, int GAL_TJ>
+__global__ __launch_bounds__(256) void k_galerkin_piece(Geo g, int Nv, const double2* __restrict__ B,
+                                                        const double2* __restrict__ U, const double2* __restrict__ C,
+                                                        double kappa, int GF, double2* __restrict__ D1,
+                                                        double2* __restrict__ tmp) {
+    extern __shared__ double2 sh[];
+    const int y = blockIdx.x, piece = blockIdx.y;
+    const int nc = 2 * Nv, Vb = g.Vb;
+    const int i0 = blockIdx.z * 64;                    // rows [i0, i0 + 64)
+    double2* Lh = sh;                                  // [GF][6][nc]
+    double2* Rh = sh + (size_t)GF * 6 * nc;            // [GF][6][nc]
+    const bool clover = piece == 0;
+    const bool face = piece >= 9;
+    const int pp = face ? piece - 9 : piece - 1;
+    const int mu = clover ? 0 : pp >> 1;
+    const bool fwd = clover ? true : (pp & 1) == 0;
+    // the sites of this piece form a sub-box of the block
+    int lo[4], nn[4];
+    for (int nu = 0; nu < 4; ++nu) { lo[nu] = 0; nn[nu] = g.b[nu]; }
+    if (!clover) {
+        if (face) { lo[mu] = fwd ? g.b[mu] - 1 : 0; nn[mu] = 1; }
+        else { lo[mu] = fwd ? 0 : 1; nn[mu] = g.b[mu] - 1; }
+    }
+    const int cnt = nn[0] * nn[1] * nn[2] * nn[3];
+    const int tid = threadIdx.x, ti = tid >> 4, tj = tid & 15;
+    cx<double> acc[GAL_TI][GAL_TJ];
+#pragma unroll
+    for (int a = 0; a < GAL_TI; ++a)
+#pragma unroll
+        for (int b = 0; b < GAL_TJ; ++b) acc[a][b] = cmk(0.0, 0.0);
+    for (int s0 = 0; s0 < cnt; s0 += GF) {
+        __syncthreads();
+        for (int e = tid; e < GF * nc; e += blockDim.x) {
+            const int xs = e / nc, j = e - (e / nc) * nc, s = s0 + xs;
+            cx<double> hl[6], hr[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) hl[k] = hr[k] = cmk(0.0, 0.0);
+            if (s < cnt) {
+                int r = s, lcl[4];
+                for (int nu = 3; nu >= 0; --nu) { lcl[nu] = lo[nu] + r % nn[nu]; r /= nn[nu]; }
+                const int l = ((lcl[0] * g.b[1] + lcl[1]) * g.b[2] + lcl[2]) * g.b[3] + lcl[3];
+                const int ifine = y * Vb + l;
+                cx<double> p[12];
+                load_basis(B, Nv, Vb, y, j, l, p);
+                const int a = j / Nv;
+                if (clover) {
+                    cx<double> half[6];
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) { half[k] = p[6 * a + k]; hl[k] = conj(half[k]); }
+                    clover_block<double2, double>(C + (size_t)a * 18 * g.V, g.V, ifine, half, hr);
+                } else {
+                    cx<double> h[6];
+                    project_rt(mu, fwd, p, h);
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) hl[k] = conj(h[k]);
+                    int lc[4], yc[4];
+                    geo_coords(g, ifine, lc, yc);
+                    bool wrap;
+                    const int jf = fwd ? geo_fwd(g, ifine, mu, lc, yc, &wrap) : geo_bwd(g, ifine, mu, lc, yc, &wrap);
+                    const int y2 = jf / Vb, l2 = jf - y2 * Vb;
+                    cx<double> q[12], hq[6];
+                    load_basis(B, Nv, Vb, y2, j, l2, q);
+                    project_rt(mu, fwd, q, hq);
+                    const double sg = (wrap && g.bcneg[mu]) ? -1.0 : 1.0;
+                    const double2* ul = U + (size_t)(mu * 9) * g.V + (fwd ? ifine : jf);
+                    cx<double> u[9];
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) u[k] = ldc<double2, double>(ul + (size_t)k * g.V);
+#pragma unroll
+                    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+                        for (int c1 = 0; c1 < 3; ++c1) {
+                            cx<double> t = cmk(0.0, 0.0);
+#pragma unroll
+                            for (int c2 = 0; c2 < 3; ++c2) {
+                                if (fwd) cmac(t, u[c1 * 3 + c2], hq[sp * 3 + c2]);
+                                else cjmac(t, u[c2 * 3 + c1], hq[sp * 3 + c2]);
+                            }
+                            hr[sp * 3 + c1] = sg * t;
+                        }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                Lh[((size_t)xs * 6 + k) * nc + j] = make_double2(hl[k].re, hl[k].im);
+                Rh[((size_t)xs * 6 + k) * nc + j] = make_double2(hr[k].re, hr[k].im);
+            }
+        }
+        __syncthreads();
+        const int nxs = cnt - s0 < GF ? cnt - s0 : GF;
+        for (int xk = 0; xk < nxs * 6; ++xk) {
+            cx<double> lv[GAL_TI], rv[GAL_TJ];
+#pragma unroll
+            for (int a = 0; a < GAL_TI; ++a) {
+                const int i = i0 + ti + 16 * a;
+                lv[a] = i < nc ? ldc<double2, double>(Lh + (size_t)xk * nc + i) : cmk(0.0, 0.0);
+            }
+#pragma unroll
+            for (int b = 0; b < GAL_TJ; ++b) {
+                const int jj = tj + 16 * b;
+                rv[b] = jj < nc ? ldc<double2, double>(Rh + (size_t)xk * nc + jj) : cmk(0.0, 0.0);
+            }
+#pragma unroll
+            for (int a = 0; a < GAL_TI; ++a)
+#pragma unroll
+                for (int b = 0; b < GAL_TJ; ++b) cmac(acc[a][b], lv[a], rv[b]);
+        }
+    }
+    const double sc = clover ? 1.0 : -kappa;
+    const size_t nn2 = (size_t)nc * nc;
+    double2* dst = face ? D1 + ((size_t)y * 9 + 1 + pp) * nn2 : tmp + ((size_t)y * 9 + piece) * nn2;
+#pragma unroll
+    for (int a = 0; a < GAL_TI; ++a)
+#pragma unroll
+        for (int b = 0; b < GAL_TJ; ++b) {
+            const int i = i0 + ti + 16 * a, jj = tj + 16 * b;
+            if (i < nc && i < i0 + 64 && jj < nc) {
+                cx<double> v = acc[a][b];
+                if (clover && (i < Nv) != (jj < Nv)) v = cmk(0.0, 0.0);
+                dst[(size_t)i * nc + jj] = make_double2(sc * v.re, sc * v.im);
+            }
+        }
+}
+
+// D1[y][0] = sum of pieces 0..8 in order
+__global__ void k_galerkin_self(size_t V1, int nc, const double2* __restrict__ tmp, double2* __restrict__ D1) {
+    const size_t nn2 = (size_t)nc * nc, n = V1 * nn2;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        const size_t y = e / nn2, ij = e - y * nn2;
+        double re = 0.0, im = 0.0;
+        for (int p = 0; p < 9; ++p) {
+            double2 v = tmp[(y * 9 + p) * nn2 + ij];
+            re += v.x;
+            im += v.y;
+        }
+        D1[y * 9 * nn2 + ij] = make_double2(re, im);
+    }
+}
+
+int mg_galerkin(mglma_ctx* c, double2* tmp) {
     const Geo& g = c->geo;
-    dim3 grid((g.V + 255) / 256, nrhs);
-    hipLaunchKernelGGL(k_dslash_piece, grid, dim3(256), 0, c->stream, g, in, out, c->U64, c->C64, c->kappa, mode);
+    const int nc = c->nc;
+    int GF = 1536 / (6 * nc);
+    if (GF < 1) GF = 1;
+    if (GF > 16) GF = 16;
+    const size_t shb = (size_t)2 * GF * 6 * nc * sizeof(double2);
+    dim3 grid(g.V1, 17, (nc + 63) / 64);
+    // register tile: ceil(nc/16) x ceil(nc/16) outputs per thread (rows capped at 4 per 64-row chunk)
+    const int t = (nc + 15) / 16;
+#define GAL_LAUNCH(TI, TJ)                                                                                  \
+    hipLaunchKernelGGL((k_galerkin_piece<TI, TJ>), grid, dim3(256), shb, c->stream, g, c->Nv, c->B64, c->U64, \
+                       c->C64, c->kappa, GF, c->D64, tmp)
+    if (t <= 1) GAL_LAUNCH(1, 1);
+    else if (t == 2) GAL_LAUNCH(2, 2);
+    else if (t == 3) GAL_LAUNCH(3, 3);
+    else if (t == 4) GAL_LAUNCH(4, 4);
+    else GAL_LAUNCH(4, 8);
+#undef GAL_LAUNCH
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_galerkin_self, dim3(2048), dim3(256), 0, c->stream, (size_t)g.V1, nc, tmp, c->D64);
     HIP_TRY(hipGetLastError());
     return MGLMA_OK;
 }

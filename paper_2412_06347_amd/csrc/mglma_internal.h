@@ -255,7 +255,6 @@ int mg_coarse_apply(mglma_ctx* c, int prec, int gamma5, const void* in, void* ou
 static inline size_t prec_cbytes(int prec) {
     return prec == MGLMA_F64 ? 16 : prec == MGLMA_F32 ? 8 : 4;
 }
-int mg_dslash_piece(mglma_ctx* c, int mode, const double2* in, double2* out, int nrhs);
 void mg_free_subspace(mglma_ctx* c);
 
 // ---------------------------------------------------------------------------
@@ -272,3 +271,9 @@ __host__ __device__ inline void gk_row(int k, int s, int* t, double* cre, double
     *cim = im[k - 1][s];
 }
 
+int mg_dot_norm(mglma_ctx* c, int prec, const void* x, const void* y, size_t n, int nrhs, double* out);
+int mg_mr_update(mglma_ctx* c, int prec, const double* a, void* z, void* s, const void* t, size_t n, int nrhs);
+int mg_multiaxpy2(mglma_ctx* c, int prec, const void* x1, const void* x2, size_t xstride, int k, const double* coef,
+                  void* y1, void* y2, size_t n, int nrhs);
+int mg_update_norm(mglma_ctx* c, int prec, const double* a, void* e, const void* z, void* r, const void* w, size_t n,
+                   int nrhs, double* out);

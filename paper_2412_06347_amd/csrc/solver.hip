@@ -21,25 +21,10 @@ enum {
 // ---------------------------------------------------------------------------
 // scalar kernels (per right-hand side)
 // ---------------------------------------------------------------------------
-__global__ void k_rsqrt_c(const double* n2, double* out, int n) {
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    double v = n2[r];
-    out[2 * r] = v > 0.0 ? 1.0 / sqrt(v) : 0.0;
-    out[2 * r + 1] = 0.0;
-}
 __global__ void k_sqrt_masked(const double* n2, const int* active, double* out, int n) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
     out[r] = active[r] ? sqrt(n2[r]) : 0.0;
-}
-// omega = <t,s>/<t,t>  (MR step), stored complex; zero if t = 0
-__global__ void k_mr_omega(const double* ts, const double* tt, double* om, int n) {
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    double d = tt[r];
-    om[2 * r] = d > 0.0 ? ts[2 * r] / d : 0.0;
-    om[2 * r + 1] = d > 0.0 ? ts[2 * r + 1] / d : 0.0;
 }
 
 template <typename S, typename R>
@@ -100,26 +85,50 @@ static dim3 grid1(size_t n) {
 // solver state
 // ---------------------------------------------------------------------------
 struct Scal {
+    // device scalars, per right-hand side (m = vectors of the longest GCR cycle)
     double* base;
     int nrhs, m;
-    double* bn2() { return base; }
-    double* rn2() { return base + nrhs; }
-    double* nw2() { return base + 2 * nrhs; }
-    double* tt() { return base + 3 * nrhs; }
-    double* scale() { return base + 4 * nrhs; }
-    double* invc() { return base + 5 * nrhs; }            // complex
-    double* alpha() { return base + 7 * nrhs; }           // complex
-    double* omega() { return base + 9 * nrhs; }           // complex
-    double* ts() { return base + 11 * nrhs; }             // complex
-    double* cn2() { return base + 13 * nrhs; }
-    double* cinv() { return base + 14 * nrhs; }           // complex
-    double* calpha() { return base + 16 * nrhs; }         // complex
-    double* beta() { return base + 18 * nrhs; }           // complex [m][nrhs]
-    double* cbeta() { return base + 18 * nrhs + 2 * m * nrhs; }   // complex [m][nrhs]
-    int* active() { return (int*)(base + 18 * nrhs + 4 * m * nrhs); }
-    double* hscale() { return base + 19 * nrhs + 4 * m * nrhs; }   // half-precision smoother scale
-    static size_t bytes(int nrhs, int m) { return (20 * (size_t)nrhs + 4 * (size_t)m * nrhs) * 8 + 256; }
+    double* at(int off) { return base + (size_t)off * nrhs; }
+    double* bn2() { return at(0); }
+    double* rn2() { return at(1); }
+    double* tt() { return at(2); }
+    double* scale() { return at(3); }
+    double* hscale() { return at(4); }
+    double* cn2() { return at(5); }
+    double* omega() { return at(6); }     // complex
+    double* alpha() { return at(8); }     // complex
+    double* calpha() { return at(10); }   // complex
+    double* dn3() { return at(12); }      // (Re, Im, norm) x nrhs
+    double* cdn3() { return at(15); }     // (Re, Im, norm) x nrhs
+    int* active() { return (int*)at(18); }
+    int* imask() { return (int*)at(18) + nrhs; }      // inner-loop activity (shares the slot: 2 ints / double)
+    double* beta() { return at(20); }                 // complex [m][nrhs]
+    double* cbeta() { return at(20 + 2 * m); }        // complex [m][nrhs]
+    double* nw2() { return at(20 + 4 * m); }          // [m][nrhs] squared norms of the fine directions
+    double* cnw2() { return at(20 + 5 * m); }         // [m][nrhs] squared norms of the coarse directions
+    static size_t bytes(int nrhs, int m) { return (size_t)(20 + 6 * m) * nrhs * 8 + 256; }
 };
+
+// beta[j][r] /= nw2[j][r]   (projection coefficients of unnormalised directions)
+__global__ void k_div_norms(double* beta, const double* nw2, int k, int nrhs) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= k * nrhs) return;
+    double d = nw2[e];
+    beta[2 * e] = d > 0.0 ? beta[2 * e] / d : 0.0;
+    beta[2 * e + 1] = d > 0.0 ? beta[2 * e + 1] / d : 0.0;
+}
+// alpha[r] = <w,r>/|w|^2 from dn3 = (Re, Im, |w|^2); also store |w|^2 in nw2j.
+// Right-hand sides with mask[r] == 0 get alpha = 0 (frozen: their iterate no
+// longer changes, so each one follows the same path alone or in a batch).
+__global__ void k_alpha(const double* dn3, double* alpha, double* nw2j, const int* mask, int nrhs) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    double d = dn3[3 * r + 2];
+    bool on = (mask == nullptr || mask[r]) && d > 0.0;
+    alpha[2 * r] = on ? dn3[3 * r] / d : 0.0;
+    alpha[2 * r + 1] = on ? dn3[3 * r + 1] / d : 0.0;
+    if (nw2j) nw2j[r] = d;
+}
 
 struct SolveCtx {
     mglma_ctx* c;
@@ -149,6 +158,7 @@ static int coarse_gcr_fixed(SolveCtx& S, int vp, int op, const void* b, void* x,
     MG_TRY(mg_zero(c, x, (size_t)nrhs * n * vb));
     MG_TRY(mg_copy(c, r, b, (size_t)nrhs * n * vb));
     const size_t setsz = (size_t)nrhs * n;   // elements per vector set
+    const dim3 sg((nrhs + 63) / 64), sb(64);
     for (int k = 0; k < iters; ++k) {
         int j = k % mc;
         char* pj = (char*)P + (size_t)j * setsz * vb;
@@ -160,16 +170,14 @@ static int coarse_gcr_fixed(SolveCtx& S, int vp, int op, const void* b, void* x,
         S.coarse_applies++;
         if (j > 0) {
             MG_TRY(mg_multidot(c, vp, Q, setsz, j, qj, n, nrhs, S.s.cbeta()));
-            MG_TRY(mg_multiaxpy(c, vp, Q, setsz, j, S.s.cbeta(), -1.0, qj, n, nrhs));
-            MG_TRY(mg_multiaxpy(c, vp, P, setsz, j, S.s.cbeta(), -1.0, pj, n, nrhs));
+            hipLaunchKernelGGL(k_div_norms, dim3((j * nrhs + 63) / 64), sb, 0, c->stream, S.s.cbeta(), S.s.cnw2(), j,
+                               nrhs);
+            MG_TRY(mg_multiaxpy2(c, vp, Q, P, setsz, j, S.s.cbeta(), qj, pj, n, nrhs));
         }
-        MG_TRY(mg_norm2(c, vp, qj, n, nrhs, S.s.cn2()));
-        hipLaunchKernelGGL(k_rsqrt_c, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, S.s.cn2(), S.s.cinv(), nrhs);
-        MG_TRY(mg_axpby(c, vp, nullptr, nullptr, S.s.cinv(), qj, n, nrhs));
-        MG_TRY(mg_axpby(c, vp, nullptr, nullptr, S.s.cinv(), pj, n, nrhs));
-        MG_TRY(mg_dot(c, vp, qj, r, n, nrhs, S.s.calpha()));
-        MG_TRY(mg_multiaxpy(c, vp, pj, 0, 1, S.s.calpha(), 1.0, x, n, nrhs));
-        MG_TRY(mg_multiaxpy(c, vp, qj, 0, 1, S.s.calpha(), -1.0, r, n, nrhs));
+        MG_TRY(mg_dot_norm(c, vp, qj, r, n, nrhs, S.s.cdn3()));
+        hipLaunchKernelGGL(k_alpha, sg, sb, 0, c->stream, S.s.cdn3(), S.s.calpha(), S.s.cnw2() + (size_t)j * nrhs,
+                           (const int*)nullptr, nrhs);
+        MG_TRY(mg_update_norm(c, vp, S.s.calpha(), x, pj, r, qj, n, nrhs, S.s.cn2()));
     }
     HIP_TRY(hipGetLastError());
     return MGLMA_OK;
@@ -191,10 +199,14 @@ static int precondition(SolveCtx& S, int vp, const void* r, void* z) {
     void *rc, *ec;
     MG_TRY(mg_scratch(c, WS_RC, (size_t)nrhs * nc * vb, &rc));
     MG_TRY(mg_scratch(c, WS_EC, (size_t)nrhs * nc * vb, &ec));
-    // coarse correction
-    MG_TRY(mg_restrict(c, vp, r, rc, nrhs));
-    MG_TRY(coarse_gcr_fixed(S, vp, p->coarse, rc, ec, p->coarse_iters));
-    MG_TRY(mg_prolong(c, vp, ec, z, nrhs));
+    // coarse correction (coarse_iters = 0: smoother only)
+    if (p->coarse_iters > 0) {
+        MG_TRY(mg_restrict(c, vp, r, rc, nrhs));
+        MG_TRY(coarse_gcr_fixed(S, vp, p->coarse, rc, ec, p->coarse_iters));
+        MG_TRY(mg_prolong(c, vp, ec, z, nrhs));
+    } else {
+        MG_TRY(mg_zero(c, z, (size_t)nrhs * n * vb));
+    }
     if (p->nu_post <= 0) return MGLMA_OK;
     // MR smoothing on M z = r: s = r - M z; t = M s; omega = <t,s>/<t,t>; z += omega s; s -= omega t
     void *s, *t;
@@ -210,7 +222,7 @@ static int precondition(SolveCtx& S, int vp, const void* r, void* z) {
             // half-precision operator application on a rescaled copy of s
             void* t16 = (char*)s16 + (size_t)nrhs * n * 4;
             MG_TRY(mg_norm2(c, vp, s, n, nrhs, S.s.tt()));
-            // scale[r] = rms entry of s: s/scale has entries of order one in half precision
+            // hscale[r] = rms entry of s: s/hscale has entries of order one in half precision
             hipLaunchKernelGGL(k_rms, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, S.s.tt(), (double)n,
                                S.s.hscale(), nrhs);
             MG_TRY(mg_convert(c, vp, s, MGLMA_F16, s16, n, nrhs, S.s.hscale(), 1));
@@ -219,12 +231,12 @@ static int precondition(SolveCtx& S, int vp, const void* r, void* z) {
         } else {
             MG_TRY(mg_dslash(c, vp, 0, s, t, nrhs));
         }
-        MG_TRY(mg_dot(c, vp, t, s, n, nrhs, S.s.ts()));
-        MG_TRY(mg_norm2(c, vp, t, n, nrhs, S.s.tt()));
-        hipLaunchKernelGGL(k_mr_omega, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, S.s.ts(), S.s.tt(),
-                           S.s.omega(), nrhs);
-        MG_TRY(mg_multiaxpy(c, vp, s, 0, 1, S.s.omega(), 1.0, z, n, nrhs));
-        if (it + 1 < p->nu_post) MG_TRY(mg_multiaxpy(c, vp, t, 0, 1, S.s.omega(), -1.0, s, n, nrhs));
+        // omega = <t,s>/<t,t>; z += omega s; s -= omega t
+        MG_TRY(mg_dot_norm(c, vp, t, s, n, nrhs, S.s.dn3()));
+        hipLaunchKernelGGL(k_alpha, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, S.s.dn3(), S.s.omega(),
+                           (double*)nullptr, (const int*)nullptr, nrhs);
+        if (it + 1 < p->nu_post) MG_TRY(mg_mr_update(c, vp, S.s.omega(), z, s, t, n, nrhs));
+        else MG_TRY(mg_multiaxpy(c, vp, s, 0, 1, S.s.omega(), 1.0, z, n, nrhs));
     }
     HIP_TRY(hipGetLastError());
     return MGLMA_OK;
@@ -253,6 +265,9 @@ static int inner_fgcr(SolveCtx& S, int vp, const void* rin, void* e, const std::
     HIP_TRY(hipMemcpyAsync(h, S.s.rn2(), nrhs * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     std::vector<double> r0(h, h + nrhs);
+    std::vector<int> mask(nrhs);
+    for (int q = 0; q < nrhs; ++q) mask[q] = (active[q] && r0[q] > 0.0) ? 1 : 0;
+    HIP_TRY(hipMemcpyAsync(S.s.imask(), mask.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, c->stream));
     int k = 0;
     for (; k < p->max_inner; ++k) {
         const int j = k % m;
@@ -260,27 +275,29 @@ static int inner_fgcr(SolveCtx& S, int vp, const void* rin, void* e, const std::
         char* wj = (char*)W + (size_t)j * setsz * vb;
         MG_TRY(precondition(S, vp, r, zj));
         MG_TRY(mg_dslash(c, vp, 0, zj, wj, nrhs));
+        // unnormalised directions: w_j -= sum_i <w_i,w_j>/|w_i|^2 w_i (same on z_j)
         if (j > 0) {
             MG_TRY(mg_multidot(c, vp, W, setsz, j, wj, n, nrhs, S.s.beta()));
-            MG_TRY(mg_multiaxpy(c, vp, W, setsz, j, S.s.beta(), -1.0, wj, n, nrhs));
-            MG_TRY(mg_multiaxpy(c, vp, Z, setsz, j, S.s.beta(), -1.0, zj, n, nrhs));
+            hipLaunchKernelGGL(k_div_norms, dim3((j * nrhs + 63) / 64), dim3(64), 0, c->stream, S.s.beta(), S.s.nw2(),
+                               j, nrhs);
+            MG_TRY(mg_multiaxpy2(c, vp, W, Z, setsz, j, S.s.beta(), wj, zj, n, nrhs));
         }
-        MG_TRY(mg_norm2(c, vp, wj, n, nrhs, S.s.nw2()));
-        hipLaunchKernelGGL(k_rsqrt_c, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, S.s.nw2(), S.s.invc(), nrhs);
-        MG_TRY(mg_axpby(c, vp, nullptr, nullptr, S.s.invc(), wj, n, nrhs));
-        MG_TRY(mg_axpby(c, vp, nullptr, nullptr, S.s.invc(), zj, n, nrhs));
-        MG_TRY(mg_dot(c, vp, wj, r, n, nrhs, S.s.alpha()));
-        MG_TRY(mg_multiaxpy(c, vp, zj, 0, 1, S.s.alpha(), 1.0, e, n, nrhs));
-        MG_TRY(mg_multiaxpy(c, vp, wj, 0, 1, S.s.alpha(), -1.0, r, n, nrhs));
-        MG_TRY(mg_norm2(c, vp, r, n, nrhs, S.s.rn2()));
+        // alpha = <w_j, r>/|w_j|^2 ; e += alpha z_j ; r -= alpha w_j ; |r|^2
+        MG_TRY(mg_dot_norm(c, vp, wj, r, n, nrhs, S.s.dn3()));
+        hipLaunchKernelGGL(k_alpha, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, S.s.dn3(), S.s.alpha(),
+                           S.s.nw2() + (size_t)j * nrhs, S.s.imask(), nrhs);
+        MG_TRY(mg_update_norm(c, vp, S.s.alpha(), e, zj, r, wj, n, nrhs, S.s.rn2()));
         HIP_TRY(hipMemcpyAsync(h, S.s.rn2(), nrhs * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(hipStreamSynchronize(c->stream));
-        bool done = true;
+        bool done = true, changed = false;
         for (int q = 0; q < nrhs; ++q) {
             if (!std::isfinite(h[q])) return MGLMA_ERR_NONFINITE;
-            if (active[q] && h[q] > p->inner_tol * p->inner_tol * r0[q]) done = false;
+            if (mask[q] && h[q] <= p->inner_tol * p->inner_tol * r0[q]) { mask[q] = 0; changed = true; }
+            if (mask[q]) done = false;
         }
         if (done) { ++k; break; }
+        if (changed)
+            HIP_TRY(hipMemcpyAsync(S.s.imask(), mask.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, c->stream));
     }
     *iters = k;
     return MGLMA_OK;

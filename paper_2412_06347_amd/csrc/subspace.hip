@@ -20,7 +20,7 @@
 //   flips chirality).
 #include "mglma_internal.h"
 
-int mg_dslash_piece(mglma_ctx* c, int mode, const double2* in, double2* out, int nrhs);
+int mg_galerkin(mglma_ctx* c, double2* tmp);
 
 // ---------------------------------------------------------------------------
 // basis construction
@@ -163,68 +163,113 @@ template <typename R> __device__ __forceinline__ R wsum(R v) {
     return v;
 }
 
-#define NRR 8
+#define RMAXR 16   // right-hand sides per pass
 
-// coarse[r][y][a*Nv + c] = sum_{l, s'col} conj(B[y][a][c][s'col][l]) fine[r][6a + s'col][y*Vb + l]
+// coarse[r][y][p] = sum_{l, s'col} conj(B[y][p][s'col][l]) fine[r][6 alpha(p) + s'col][y*Vb + l]
+// One workgroup per block, a small GEMM (nc x 6Vb)(6Vb x nrhs) per chirality.
+// lc block sites at a time, the basis rows (padded against LDS bank
+// conflicts) and the field values are staged in LDS with coalesced loads;
+// thread t owns basis vector p = t % nc and right-hand sides
+// r = t / nc + G*q (G = 256 / nc).
 template <typename S, typename R>
 __global__ __launch_bounds__(256) void k_restrict(Geo g, int Nv, const S* __restrict__ B, const S* __restrict__ fine,
-                                                  S* __restrict__ coarse, int nrhs) {
+                                                  S* __restrict__ coarse, int nrhs, int lc, int rc) {
+    extern __shared__ char shraw[];
     const int y = blockIdx.x;
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int Vb = g.Vb, nc = 2 * Nv;
-    const size_t V = g.V, K = (size_t)6 * Vb;
-    for (int r0 = 0; r0 < nrhs; r0 += NRR) {
-        const int nr = nrhs - r0 < NRR ? nrhs - r0 : NRR;
-        for (int pair = w; pair < nc; pair += 4) {
-            const int a = pair / Nv;
-            const S* bv = B + ((size_t)y * nc + pair) * K;
-            cx<R> acc[NRR];
+    const int Vb = g.Vb, nc = 2 * Nv, G = 256 / nc;
+    const int bstride = 6 * lc + 1;
+    cx<R>* Bs = (cx<R>*)shraw;                       // [nc][bstride]
+    cx<R>* Fs = Bs + (size_t)nc * bstride;           // [lc][12][rc]
+    const size_t V = g.V;
+    const int p = threadIdx.x % nc, grp = threadIdx.x / nc;
+    const bool act = grp < G;
+    const int a = p / Nv;
+    const S* Bblk = B + (size_t)y * nc * 6 * Vb;
+    for (int r0 = 0; r0 < nrhs; r0 += rc) {
+        const int nr = nrhs - r0 < rc ? nrhs - r0 : rc;
+        cx<R> acc[RMAXR / 2];
 #pragma unroll
-            for (int q = 0; q < NRR; ++q) acc[q] = cmk((R)0, (R)0);
-            for (int scl = 0; scl < 6; ++scl) {
-                const S* fr = fine + ((size_t)r0 * 12 + 6 * a + scl) * V + (size_t)y * Vb;
-                for (int l = lane; l < Vb; l += 64) {
-                    cx<R> b = ldc<S, R>(bv + (size_t)scl * Vb + l);
+        for (int q = 0; q < RMAXR / 2; ++q) acc[q] = cmk((R)0, (R)0);
+        for (int l0 = 0; l0 < Vb; l0 += lc) {
+            const int nl = Vb - l0 < lc ? Vb - l0 : lc;
+            __syncthreads();
+            for (int e = threadIdx.x; e < nc * 6 * nl; e += blockDim.x) {
+                const int pp = e / (6 * nl), rem = e - pp * 6 * nl, scl = rem / nl, ll = rem - scl * nl;
+                Bs[pp * bstride + scl * lc + ll] = conj(ldc<S, R>(Bblk + ((size_t)pp * 6 + scl) * Vb + l0 + ll));
+            }
+            for (int e = threadIdx.x; e < nl * 12 * nr; e += blockDim.x) {
+                const int ll = e % nl, t = e / nl, sc = t % 12, r = t / 12;
+                Fs[(ll * 12 + sc) * rc + r] =
+                    ldc<S, R>(fine + ((size_t)(r0 + r) * 12 + sc) * V + (size_t)y * Vb + l0 + ll);
+            }
+            __syncthreads();
+            if (act) {
+                const cx<R>* bp = Bs + p * bstride;
+                for (int ll = 0; ll < nl; ++ll) {
 #pragma unroll
-                    for (int q = 0; q < NRR; ++q)
-                        if (q < nr) cjmac(acc[q], b, ldc<S, R>(fr + (size_t)q * 12 * V + l));
+                    for (int scl = 0; scl < 6; ++scl) {
+                        const cx<R> b = bp[scl * lc + ll];
+                        const cx<R>* f = Fs + (ll * 12 + 6 * a + scl) * rc;
+#pragma unroll
+                        for (int q = 0; q < RMAXR / 2; ++q) {
+                            const int r = grp + G * q;
+                            if (r < nr) cmac(acc[q], b, f[r]);
+                        }
+                    }
                 }
             }
+        }
+        if (act) {
 #pragma unroll
-            for (int q = 0; q < NRR; ++q) {
-                R re = wsum(acc[q].re), im = wsum(acc[q].im);
-                if (lane == 0 && q < nr) stc<S, R>(coarse + ((size_t)(r0 + q) * g.V1 + y) * nc + pair, cmk(re, im));
+            for (int q = 0; q < RMAXR / 2; ++q) {
+                const int r = grp + G * q;
+                if (r < nr) stc<S, R>(coarse + ((size_t)(r0 + r) * g.V1 + y) * nc + p, acc[q]);
             }
         }
     }
 }
 
 // fine[r][6a + s'col][i] = sum_c B[y][a][c][s'col][l] coarse[r][y][a*Nv + c]
+// One thread per fine site; the coarse vectors of the workgroup's blocks are
+// staged in LDS (RMAXR right-hand sides per pass).
 template <typename S, typename R>
 __global__ __launch_bounds__(256) void k_prolong(Geo g, int Nv, const S* __restrict__ B, const S* __restrict__ coarse,
-                                                 S* __restrict__ fine, int nrhs) {
+                                                 S* __restrict__ fine, int nrhs, int nbw, int rc) {
+    extern __shared__ char shraw[];
+    cx<R>* CS = (cx<R>*)shraw;    // [nbw][nc][rc], rc <= RMAXR right-hand sides per pass
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= g.V) return;
     const int Vb = g.Vb, nc = 2 * Nv;
+    const int yfirst = (blockIdx.x * blockDim.x) / Vb;
     const int y = i / Vb, l = i - y * Vb;
     const size_t V = g.V;
-    for (int r0 = 0; r0 < nrhs; r0 += NRR) {
-        const int nr = nrhs - r0 < NRR ? nrhs - r0 : NRR;
-        for (int a = 0; a < 2; ++a) {
-            for (int scl = 0; scl < 6; ++scl) {
-                cx<R> acc[NRR];
+    for (int r0 = 0; r0 < nrhs; r0 += rc) {
+        const int nr = nrhs - r0 < rc ? nrhs - r0 : rc;
+        __syncthreads();
+        for (int e = threadIdx.x; e < nbw * nc * nr; e += blockDim.x) {
+            const int r = e % nr, t = e / nr, j = t % nc, yb = t / nc;
+            const int yy = yfirst + yb;
+            CS[(yb * nc + j) * rc + r] =
+                yy < g.V1 ? ldc<S, R>(coarse + ((size_t)(r0 + r) * g.V1 + yy) * nc + j) : cmk((R)0, (R)0);
+        }
+        __syncthreads();
+        if (i < g.V) {
+            const cx<R>* cy = CS + (size_t)(y - yfirst) * nc * rc;
+            for (int a = 0; a < 2; ++a) {
+                for (int scl = 0; scl < 6; ++scl) {
+                    cx<R> acc[RMAXR];
 #pragma unroll
-                for (int q = 0; q < NRR; ++q) acc[q] = cmk((R)0, (R)0);
-                for (int c = 0; c < Nv; ++c) {
-                    cx<R> b = ldc<S, R>(B + (((size_t)y * nc + a * Nv + c) * 6 + scl) * Vb + l);
-                    const S* cr = coarse + ((size_t)r0 * g.V1 + y) * nc + a * Nv + c;
+                    for (int q = 0; q < RMAXR; ++q) acc[q] = cmk((R)0, (R)0);
+                    for (int c = 0; c < Nv; ++c) {
+                        const cx<R> b = ldc<S, R>(B + (((size_t)y * nc + a * Nv + c) * 6 + scl) * Vb + l);
+                        const cx<R>* cv = cy + (a * Nv + c) * rc;
 #pragma unroll
-                    for (int q = 0; q < NRR; ++q)
-                        if (q < nr) cmac(acc[q], b, ldc<S, R>(cr + (size_t)q * g.V1 * nc));
+                        for (int q = 0; q < RMAXR; ++q)
+                            if (q < nr) cmac(acc[q], b, cv[q]);
+                    }
+#pragma unroll
+                    for (int q = 0; q < RMAXR; ++q)
+                        if (q < nr) stc<S, R>(fine + ((size_t)(r0 + q) * 12 + 6 * a + scl) * V + i, acc[q]);
                 }
-#pragma unroll
-                for (int q = 0; q < NRR; ++q)
-                    if (q < nr) stc<S, R>(fine + ((size_t)(r0 + q) * 12 + 6 * a + scl) * V + i, acc[q]);
             }
         }
     }
@@ -233,14 +278,25 @@ __global__ __launch_bounds__(256) void k_prolong(Geo g, int Nv, const S* __restr
 int mg_restrict(mglma_ctx* c, int prec, const void* fine, void* coarse, int nrhs) {
     if (nrhs <= 0) return MGLMA_OK;
     const Geo& g = c->geo;
+    // LDS budget: 32 KiB of basis rows, 24 KiB of field values
+    const int nc = c->nc;
+    const size_t cb = prec == MGLMA_F64 ? 16 : 8;
+    int lc = (int)(32768 / (6 * nc * cb));
+    if (lc > 16) lc = 16;
+    if (lc > g.Vb) lc = g.Vb;
+    if (lc < 1) lc = 1;
+    int rc = (int)(24576 / ((size_t)lc * 12 * cb));
+    if (rc > RMAXR) rc = RMAXR;
+    if (rc < 1) return MGLMA_ERR_SHAPE;
+    const size_t shb = ((size_t)nc * (6 * lc + 1) + (size_t)lc * 12 * rc) * cb;
     switch (prec) {
         case MGLMA_F64:
-            hipLaunchKernelGGL((k_restrict<double2, double>), dim3(g.V1), dim3(256), 0, c->stream, g, c->Nv, c->B64,
-                               (const double2*)fine, (double2*)coarse, nrhs);
+            hipLaunchKernelGGL((k_restrict<double2, double>), dim3(g.V1), dim3(256), shb, c->stream, g, c->Nv, c->B64,
+                               (const double2*)fine, (double2*)coarse, nrhs, lc, rc);
             break;
         case MGLMA_F32:
-            hipLaunchKernelGGL((k_restrict<float2, float>), dim3(g.V1), dim3(256), 0, c->stream, g, c->Nv, c->B32,
-                               (const float2*)fine, (float2*)coarse, nrhs);
+            hipLaunchKernelGGL((k_restrict<float2, float>), dim3(g.V1), dim3(256), shb, c->stream, g, c->Nv, c->B32,
+                               (const float2*)fine, (float2*)coarse, nrhs, lc, rc);
             break;
         default: return MGLMA_ERR_ARG;
     }
@@ -252,14 +308,20 @@ int mg_prolong(mglma_ctx* c, int prec, const void* coarse, void* fine, int nrhs)
     if (nrhs <= 0) return MGLMA_OK;
     const Geo& g = c->geo;
     dim3 grid((g.V + 255) / 256);
+    const int nbw = 255 / g.Vb + 2;   // blocks a 256-site workgroup can touch
+    const size_t cb = prec == MGLMA_F64 ? sizeof(cx<double>) : sizeof(cx<float>);
+    int rc = (int)((48 * 1024) / ((size_t)nbw * c->nc * cb));
+    if (rc > RMAXR) rc = RMAXR;
+    if (rc < 1) return MGLMA_ERR_SHAPE;
+    const size_t shb = (size_t)nbw * c->nc * rc * cb;
     switch (prec) {
         case MGLMA_F64:
-            hipLaunchKernelGGL((k_prolong<double2, double>), grid, dim3(256), 0, c->stream, g, c->Nv, c->B64,
-                               (const double2*)coarse, (double2*)fine, nrhs);
+            hipLaunchKernelGGL((k_prolong<double2, double>), grid, dim3(256), shb, c->stream, g, c->Nv, c->B64,
+                               (const double2*)coarse, (double2*)fine, nrhs, nbw, rc);
             break;
         case MGLMA_F32:
-            hipLaunchKernelGGL((k_prolong<float2, float>), grid, dim3(256), 0, c->stream, g, c->Nv, c->B32,
-                               (const float2*)coarse, (float2*)fine, nrhs);
+            hipLaunchKernelGGL((k_prolong<float2, float>), grid, dim3(256), shb, c->stream, g, c->Nv, c->B32,
+                               (const float2*)coarse, (float2*)fine, nrhs, nbw, rc);
             break;
         default: return MGLMA_ERR_ARG;
     }
@@ -282,28 +344,6 @@ extern "C" int mglma_prolong(mglma_ctx* c, int prec, const void* coarse, void* f
 // ---------------------------------------------------------------------------
 // Galerkin operator
 // ---------------------------------------------------------------------------
-__global__ void k_unit_coarse(int V1, int nc, int j0, int nj, double2* __restrict__ out) {
-    size_t n = (size_t)nj * V1 * nc;
-    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-        int i = (int)(e % nc);
-        int jj = (int)(e / ((size_t)V1 * nc));
-        out[e] = make_double2(i == j0 + jj ? 1.0 : 0.0, 0.0);
-    }
-}
-
-// D[y][dir][i][j0+jj] = Rc[jj][y][i]
-__global__ void k_scatter_op(int V1, int nc, int dir, int j0, int nj, const double2* __restrict__ Rc,
-                             double2* __restrict__ D) {
-    size_t n = (size_t)nj * V1 * nc;
-    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-        int i = (int)(e % nc);
-        size_t t = e / nc;
-        int y = (int)(t % V1);
-        int jj = (int)(t / V1);
-        D[(((size_t)y * 9 + dir) * nc + i) * nc + j0 + jj] = Rc[e];
-    }
-}
-
 __global__ void k_op_copies(size_t nblk, int nc, const double2* __restrict__ D, double2* __restrict__ D64t,
                             float2* __restrict__ D32t, bf16_t* __restrict__ Dbf) {
     // D64t, D32t: column-major copies [blk][j][i]; Dbf[blk][0 = re, 1 = im][i][j]
@@ -423,25 +463,8 @@ extern "C" int mglma_build_subspace(mglma_ctx* c, int Nv, const double* tv) {
     MG_TRY(cholqr_pass(c, Gb, Rb, bad));
     MG_TRY(mg_convert(c, MGLMA_F64, c->B64, MGLMA_F32, c->B32, nb, 1, nullptr, 0));
 
-    // 3. Galerkin operator, JB coarse unit vectors at a time
-    const int JB = nc < 16 ? nc : 16;
-    double2 *cu, *Phi, *Tmp, *Rc;
-    MG_TRY(mg_scratch(c, 2, (size_t)JB * g.V1 * nc * 16, (void**)&cu));
-    MG_TRY(mg_scratch(c, 3, (size_t)JB * g.V * 12 * 16, (void**)&Phi));
-    MG_TRY(mg_scratch(c, 4, (size_t)JB * g.V * 12 * 16, (void**)&Tmp));
-    MG_TRY(mg_scratch(c, 5, (size_t)JB * g.V1 * nc * 16, (void**)&Rc));
-    for (int j0 = 0; j0 < nc; j0 += JB) {
-        int nj = nc - j0 < JB ? nc - j0 : JB;
-        hipLaunchKernelGGL(k_unit_coarse, dim3(512), dim3(256), 0, c->stream, g.V1, nc, j0, nj, cu);
-        HIP_TRY(hipGetLastError());
-        MG_TRY(mg_prolong(c, MGLMA_F64, cu, Phi, nj));
-        for (int dir = 0; dir < 9; ++dir) {
-            MG_TRY(mg_dslash_piece(c, dir, Phi, Tmp, nj));
-            MG_TRY(mg_restrict(c, MGLMA_F64, Tmp, Rc, nj));
-            hipLaunchKernelGGL(k_scatter_op, dim3(1024), dim3(256), 0, c->stream, g.V1, nc, dir, j0, nj, Rc, c->D64);
-            HIP_TRY(hipGetLastError());
-        }
-    }
+    // 3. Galerkin operator, block by block (the column-major FP64 copy is the scratch of the pieces)
+    MG_TRY(mg_galerkin(c, c->D64t));
     hipLaunchKernelGGL(k_op_copies, dim3(2048), dim3(256), 0, c->stream, (size_t)g.V1 * 9, nc, c->D64, c->D64t, c->D32,
                        c->Dbf);
     HIP_TRY(hipGetLastError());

@@ -94,30 +94,52 @@ __global__ void k_split_modes(int Nlm, int V1, int nc, const double2* __restrict
     }
 }
 
-// Gamma2 partial: A[x0][k][a][b] = sum_{y in row(x0)} W0_y^+ Gb_y(t) W1_y   (W0/W1: alpha=0/1 rows)
-// grid (L0, 3), block 256; thread per (a, b)
+// Gamma2 partial: A[x0][k][a][b] = sum_{y in row(x0)} W0_y^+ (Gb_y(t) W1_y)  (W0/W1: alpha=0/1 rows).
+// grid (L0, 3), block 256.  For every coarse site of the time row the product
+// T = Gb W1 (Nv x 32 column tile) is staged in LDS, then each thread adds
+// W0^+ T into the outputs it owns.  Needs Nv <= 64 and r <= 128.
+#define TBW 32
 __global__ __launch_bounds__(256) void k_top_gamma(Geo g, int Nv, int r, const double2* __restrict__ W,
                                                    const double2* __restrict__ G1, double2* __restrict__ A) {
     const int x0 = blockIdx.x, k = blockIdx.y;
     const int b0 = g.b[0], y0 = x0 / b0, t = x0 % b0;
     const int nc = 2 * Nv, rowsz = g.V1 / g.L1[0];
     const size_t V1 = g.V1;
-    for (int ab = threadIdx.x; ab < r * r; ab += blockDim.x) {
-        const int a = ab / r, b = ab % r;
-        cx<double> acc = cmk(0.0, 0.0);
+    __shared__ double2 T[64 * TBW];
+    for (int bt = 0; bt < r; bt += TBW) {
+        const int nb = r - bt < TBW ? r - bt : TBW;
+        cx<double> acc[16];
+        for (int q = 0; q < 16; ++q) acc[q] = cmk(0.0, 0.0);
         for (int ys = 0; ys < rowsz; ++ys) {
             const int y = y0 * rowsz + ys;
             const double2* Gb = G1 + (((size_t)y * b0 + t) * 3 + k) * Nv * Nv;
-            const double2* wa = W + ((size_t)a * V1 + y) * nc;          // alpha = 0 rows at [0, Nv)
-            const double2* wb = W + ((size_t)b * V1 + y) * nc + Nv;     // alpha = 1 rows at [Nv, 2Nv)
-            for (int cc = 0; cc < Nv; ++cc) {
+            __syncthreads();
+            for (int e = threadIdx.x; e < Nv * nb; e += blockDim.x) {
+                const int cc = e / nb, bb = e % nb;
+                const double2* w1 = W + ((size_t)(bt + bb) * V1 + y) * nc + Nv;
                 cx<double> s = cmk(0.0, 0.0);
                 for (int d = 0; d < Nv; ++d)
-                    cmac(s, ldc<double2, double>(Gb + cc * Nv + d), ldc<double2, double>(wb + d));
-                cjmac(acc, ldc<double2, double>(wa + cc), s);
+                    cmac(s, ldc<double2, double>(Gb + cc * Nv + d), ldc<double2, double>(w1 + d));
+                T[cc * TBW + bb] = make_double2(s.re, s.im);
+            }
+            __syncthreads();
+            for (int q = 0; q < 16; ++q) {
+                const int o = threadIdx.x + 256 * q;
+                if (o >= r * nb) break;
+                const int a = o / nb, bb = o % nb;
+                const double2* w0 = W + ((size_t)a * V1 + y) * nc;
+                cx<double> s = acc[q];
+                for (int cc = 0; cc < Nv; ++cc)
+                    cjmac(s, ldc<double2, double>(w0 + cc), cmk(T[cc * TBW + bb].x, T[cc * TBW + bb].y));
+                acc[q] = s;
             }
         }
-        A[(((size_t)x0 * 3 + k) * r + a) * r + b] = make_double2(acc.re, acc.im);
+        for (int q = 0; q < 16; ++q) {
+            const int o = threadIdx.x + 256 * q;
+            if (o >= r * nb) break;
+            const int a = o / nb, bb = o % nb;
+            A[(((size_t)x0 * 3 + k) * r + a) * r + bt + bb] = make_double2(acc[q].re, acc[q].im);
+        }
     }
 }
 
@@ -127,7 +149,7 @@ extern "C" int mglma_set_top_modes(mglma_ctx* c, int Nlm, const double* modes) {
     const Geo& g = c->geo;
     const int nc = c->nc, r = 2 * Nlm;
     const size_t n = (size_t)g.V1 * nc;
-    if (r > 256 || Nlm > (long)g.V1 * c->Nv) return MGLMA_ERR_ARG;
+    if (r > 128 || Nlm > (long)g.V1 * c->Nv) return MGLMA_ERR_ARG;
     // release a previous top level
     mg_free(c, c->W, (size_t)c->r * n * 16);
     c->W = nullptr;

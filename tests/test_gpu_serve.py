@@ -1,0 +1,46 @@
+"""The request loop on the GPU: requests for two resident ensembles of
+different volumes arrive while others run, are batched into multi-rhs solves,
+and each result equals the same request computed alone."""
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+ENS = {
+    "8^4": dict(L=(8, 8, 8, 8), block=(4, 4, 4, 4), eps=0.3, kappa=0.124, csw=1.0, Nv=6, Nlm=2, seed=11),
+    "16x8^3": dict(L=(16, 8, 8, 8), block=(4, 4, 4, 4), eps=0.3, kappa=0.124, csw=1.0, Nv=6, Nlm=2, seed=12),
+}
+
+
+def test_serving_alone_equals_mix():
+    import torch
+    from paper_2412_06347_amd.serve import Server, Engine, poisson_arrivals
+    free, _ = torch.cuda.mem_get_info()
+    srv = Server(hbm_budget=0.5 * free, max_batch_rhs=16)
+    for name, wl in ENS.items():
+        srv.add_ensemble(name, wl)
+    srv.start()
+    arr = poisson_arrivals(10, 40.0, 5)
+    reqs = []
+    t0 = time.perf_counter()
+    for i, t in enumerate(arr):
+        while time.perf_counter() - t0 < t:
+            time.sleep(0.001)
+        reqs.append(srv.submit(list(ENS)[i % 2], 1 + i % 3, 100 + i))
+    for r in reqs:
+        r.wait(300)
+    srv.stop()
+    st = srv.stats()
+    print("serving stats", st, "batches", srv.batches)
+    assert st["n"] == len(reqs) and st["p99_s"] >= st["p50_s"] > 0
+    assert any(len(b) > 1 for b in srv.batches)          # requests were batched together
+    # each result equals the same request run alone
+    for r in reqs:
+        eng = srv.engines[r.ensemble]
+        alone = eng.run([r])[0]
+        for key in ("L0", "L1", "L2"):
+            a, b = alone[key], r.result[key]
+            assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(a)), (r.rid, key)
+        assert r.result["max_true_rel_res"] <= 1e-10
