@@ -355,6 +355,7 @@ int mg_dot_norm(mglma_ctx* c, int prec, const void* x, const void* y, size_t n, 
     switch (prec) {
         case MGLMA_F64: hipLaunchKernelGGL(k_dot_norm<double2>, grid, dim3(RB), 0, c->stream, (const double2*)x, (const double2*)y, n, c->red_part, c->red_cnt, out); break;
         case MGLMA_F32: hipLaunchKernelGGL(k_dot_norm<float2>, grid, dim3(RB), 0, c->stream, (const float2*)x, (const float2*)y, n, c->red_part, c->red_cnt, out); break;
+        case MGLMA_F16: hipLaunchKernelGGL(k_dot_norm<__half2>, grid, dim3(RB), 0, c->stream, (const __half2*)x, (const __half2*)y, n, c->red_part, c->red_cnt, out); break;
         default: return MGLMA_ERR_ARG;
     }
     HIP_TRY(hipGetLastError());
@@ -476,6 +477,32 @@ int mg_update_norm(mglma_ctx* c, int prec, const double* a, void* e, const void*
         case MGLMA_F32: hipLaunchKernelGGL((k_update_norm<float2, float>), grid, dim3(RB), 0, c->stream, a, (float2*)e, (const float2*)z, (float2*)r, (const float2*)w, n, c->red_part, c->red_cnt, out); break;
         default: return MGLMA_ERR_ARG;
     }
+    HIP_TRY(hipGetLastError());
+    return MGLMA_OK;
+}
+
+// half-precision smoother step: z += (a*scale) s16 ; s16 -= a t16   (z FP32, s16/t16 FP16)
+__global__ void k_mr_update_h(const double* __restrict__ a, const double* __restrict__ scale, float2* __restrict__ z,
+                              __half2* __restrict__ s, const __half2* __restrict__ t, size_t n) {
+    const int r = blockIdx.y;
+    const size_t roff = (size_t)r * n;
+    const cx<float> w = cmk((float)a[2 * r], (float)a[2 * r + 1]);
+    const cx<float> ws = cmk((float)(a[2 * r] * scale[r]), (float)(a[2 * r + 1] * scale[r]));
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        cx<float> sv = ldc<__half2, float>(s + roff + e), zv = ldc<float2, float>(z + roff + e);
+        cx<float> tv = ldc<__half2, float>(t + roff + e);
+        cmac(zv, ws, sv);
+        cmac(sv, -w, tv);
+        stc<float2, float>(z + roff + e, zv);
+        stc<__half2, float>(s + roff + e, sv);
+    }
+}
+
+int mg_mr_update_h(mglma_ctx* c, const double* a, const double* scale, void* z, void* s16, const void* t16, size_t n,
+                   int nrhs) {
+    if (nrhs <= 0) return MGLMA_OK;
+    hipLaunchKernelGGL(k_mr_update_h, ew_grid(n, nrhs), dim3(256), 0, c->stream, a, scale, (float2*)z, (__half2*)s16,
+                       (const __half2*)t16, n);
     HIP_TRY(hipGetLastError());
     return MGLMA_OK;
 }

@@ -277,3 +277,5 @@ int mg_multiaxpy2(mglma_ctx* c, int prec, const void* x1, const void* x2, size_t
                   void* y1, void* y2, size_t n, int nrhs);
 int mg_update_norm(mglma_ctx* c, int prec, const double* a, void* e, const void* z, void* r, const void* w, size_t n,
                    int nrhs, double* out);
+int mg_mr_update_h(mglma_ctx* c, const double* a, const double* scale, void* z, void* s16, const void* t16, size_t n,
+                   int nrhs);

@@ -215,28 +215,33 @@ static int precondition(SolveCtx& S, int vp, const void* r, void* z) {
     const int sp = (vp == MGLMA_F32 && p->smoother == MGLMA_F16) ? MGLMA_F16 : vp;
     MG_TRY(mg_dslash(c, vp, 0, z, t, nrhs));
     MG_TRY(mg_sub(c, vp, r, t, s, n, nrhs));
-    void* s16 = nullptr;
-    if (sp == MGLMA_F16) MG_TRY(mg_scratch(c, WS_X16, (size_t)nrhs * n * 4 * 2, &s16));
-    for (int it = 0; it < p->nu_post; ++it) {
-        if (sp == MGLMA_F16) {
-            // half-precision operator application on a rescaled copy of s
-            void* t16 = (char*)s16 + (size_t)nrhs * n * 4;
-            MG_TRY(mg_norm2(c, vp, s, n, nrhs, S.s.tt()));
-            // hscale[r] = rms entry of s: s/hscale has entries of order one in half precision
-            hipLaunchKernelGGL(k_rms, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, S.s.tt(), (double)n,
-                               S.s.hscale(), nrhs);
-            MG_TRY(mg_convert(c, vp, s, MGLMA_F16, s16, n, nrhs, S.s.hscale(), 1));
+    if (sp == MGLMA_F16) {
+        // half-precision storage: s16 = s / scale (entries of order one), t16 = M s16;
+        // omega = <t16,s16>/<t16,t16>; z += omega*scale*s16 ; s16 -= omega t16
+        void* s16;
+        MG_TRY(mg_scratch(c, WS_X16, (size_t)nrhs * n * 4 * 2, &s16));
+        void* t16 = (char*)s16 + (size_t)nrhs * n * 4;
+        MG_TRY(mg_norm2(c, vp, s, n, nrhs, S.s.tt()));
+        hipLaunchKernelGGL(k_rms, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, S.s.tt(), (double)n, S.s.hscale(),
+                           nrhs);
+        MG_TRY(mg_convert(c, vp, s, MGLMA_F16, s16, n, nrhs, S.s.hscale(), 1));
+        for (int it = 0; it < p->nu_post; ++it) {
             MG_TRY(mg_dslash(c, MGLMA_F16, 0, s16, t16, nrhs));
-            MG_TRY(mg_convert(c, MGLMA_F16, t16, vp, t, n, nrhs, S.s.hscale(), 0));
-        } else {
-            MG_TRY(mg_dslash(c, vp, 0, s, t, nrhs));
+            MG_TRY(mg_dot_norm(c, MGLMA_F16, t16, s16, n, nrhs, S.s.dn3()));
+            hipLaunchKernelGGL(k_alpha, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, S.s.dn3(), S.s.omega(),
+                               (double*)nullptr, (const int*)nullptr, nrhs);
+            MG_TRY(mg_mr_update_h(c, S.s.omega(), S.s.hscale(), z, s16, t16, n, nrhs));
         }
-        // omega = <t,s>/<t,t>; z += omega s; s -= omega t
-        MG_TRY(mg_dot_norm(c, vp, t, s, n, nrhs, S.s.dn3()));
-        hipLaunchKernelGGL(k_alpha, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, S.s.dn3(), S.s.omega(),
-                           (double*)nullptr, (const int*)nullptr, nrhs);
-        if (it + 1 < p->nu_post) MG_TRY(mg_mr_update(c, vp, S.s.omega(), z, s, t, n, nrhs));
-        else MG_TRY(mg_multiaxpy(c, vp, s, 0, 1, S.s.omega(), 1.0, z, n, nrhs));
+    } else {
+        for (int it = 0; it < p->nu_post; ++it) {
+            MG_TRY(mg_dslash(c, vp, 0, s, t, nrhs));
+            // omega = <t,s>/<t,t>; z += omega s; s -= omega t
+            MG_TRY(mg_dot_norm(c, vp, t, s, n, nrhs, S.s.dn3()));
+            hipLaunchKernelGGL(k_alpha, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, S.s.dn3(), S.s.omega(),
+                               (double*)nullptr, (const int*)nullptr, nrhs);
+            if (it + 1 < p->nu_post) MG_TRY(mg_mr_update(c, vp, S.s.omega(), z, s, t, n, nrhs));
+            else MG_TRY(mg_multiaxpy(c, vp, s, 0, 1, S.s.omega(), 1.0, z, n, nrhs));
+        }
     }
     HIP_TRY(hipGetLastError());
     return MGLMA_OK;

@@ -114,8 +114,8 @@ class Engine:
             self.G_top = ctx.contract_top()
         self.stream.synchronize()
         self.params = params or mglma.default_params(tol=1e-10, max_outer=10, max_inner=120, gcr_m=8,
-                                                     inner_tol=1e-5, nu_post=6, coarse_iters=16,
-                                                     inner=mglma.F32, coarse=mglma.BF16)
+                                                     inner_tol=1e-5, nu_post=8, coarse_iters=8,
+                                                     smoother=mglma.F16, inner=mglma.F32, coarse=mglma.BF16)
         self.coarse_params = coarse_params or mglma.default_params(tol=1e-10, coarse=mglma.F32, coarse_iters=24)
         self.resident = ctx.resident_bytes() + self.U.numel() * 8
 
