@@ -6,23 +6,115 @@
 // (inner products, coefficients) stay in device memory so that the solver
 // loops do not wait on the host.
 //
+// Memory access: when n and every pointer allow it, a thread moves C complex
+// numbers per access (16 bytes of the widest operand) and keeps U such
+// packets in flight per loop step; otherwise C = 1.  These kernels are pure
+// HBM streams, so the number of bytes in flight per wave is what sets their
+// speed.
+//
 // Reductions: each workgroup reduces a fixed slice of a right-hand side in a
-// fixed order (wavefront shuffles, then LDS across the four wavefronts) and
-// writes an FP64 partial; the last workgroup to finish (device-scope atomic
-// counter) adds the partials in index order.  The grid depends on n only, so
-// every right-hand side gets bitwise the same result whatever the batch.
+// fixed order (per thread, then wavefront shuffles, then LDS across the four
+// wavefronts) and writes an FP64 partial; a second small kernel adds the
+// partials of each right-hand side, its threads taking a fixed strided share
+// followed by the same tree.  The grid depends on n (and the packet width)
+// only, so every right-hand side gets bitwise the same result whatever the
+// batch.  (Two launches instead of a last-workgroup counter: device-scope
+// atomics from thousands of workgroups on one counter line serialise.)
 #include "mglma_internal.h"
+#include <type_traits>
 
 #define RB 256          // threads per reduction workgroup
 #define MAXK 8          // vectors per multi-dot / multi-axpy launch
 
-static int red_blocks(size_t n) {
-    size_t b = (n + 4 * RB - 1) / (4 * RB);
+// ---------------------------------------------------------------------------
+// packets
+// ---------------------------------------------------------------------------
+template <int B> struct Bytes;
+template <> struct Bytes<4> { typedef unsigned T; };
+template <> struct Bytes<8> { typedef uint2 T; };
+template <> struct Bytes<16> { typedef uint4 T; };
+
+// v[0..C) = p[0..C), p aligned to C * sizeof(S) (at most 16 bytes per access)
+template <typename S, typename R, int C>
+__device__ __forceinline__ void ldp(const S* __restrict__ p, cx<R> (&v)[C]) {
+    constexpr int B = C * (int)sizeof(S);
+    if constexpr (C == 1) {
+        v[0] = ldc<S, R>(p);
+    } else if constexpr (B <= 16) {
+        typename Bytes<B>::T q = *(const typename Bytes<B>::T*)p;
+        const S* h = (const S*)&q;
+#pragma unroll
+        for (int k = 0; k < C; ++k) v[k] = ldc<S, R>(h + k);
+    } else {
+        static_assert(B % 16 == 0, "packet size");
+        uint4 q[B / 16];
+#pragma unroll
+        for (int k = 0; k < B / 16; ++k) q[k] = ((const uint4*)p)[k];
+        const S* h = (const S*)q;
+#pragma unroll
+        for (int k = 0; k < C; ++k) v[k] = ldc<S, R>(h + k);
+    }
+}
+
+template <typename S, typename R, int C>
+__device__ __forceinline__ void stp(S* __restrict__ p, const cx<R> (&v)[C]) {
+    constexpr int B = C * (int)sizeof(S);
+    if constexpr (C == 1) {
+        stc<S, R>(p, v[0]);
+    } else if constexpr (B <= 16) {
+        typename Bytes<B>::T q;
+        S* h = (S*)&q;
+#pragma unroll
+        for (int k = 0; k < C; ++k) stc<S, R>(h + k, v[k]);
+        *(typename Bytes<B>::T*)p = q;
+    } else {
+        uint4 q[B / 16];
+        S* h = (S*)q;
+#pragma unroll
+        for (int k = 0; k < C; ++k) stc<S, R>(h + k, v[k]);
+#pragma unroll
+        for (int k = 0; k < B / 16; ++k) ((uint4*)p)[k] = q[k];
+    }
+}
+
+// complex numbers per packet: 16 bytes of the widest storage type involved
+template <typename S> constexpr int pk() { return 16 / (int)sizeof(S); }
+
+static bool al(const void* p, size_t bytes) { return ((uintptr_t)p % bytes) == 0; }
+
+// Packet loop over np packets of one right-hand side: this thread's packets
+// are p0 + u*blockDim + k*stride; U of them per step, issued together.
+template <int U, typename F>
+__device__ __forceinline__ void for_packets(size_t np, F&& body) {
+    const size_t bd = blockDim.x;
+    const size_t stride = (size_t)gridDim.x * U * bd;
+    size_t p = (size_t)blockIdx.x * U * bd + threadIdx.x;
+    for (; p + (U - 1) * bd < np; p += stride) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) body(p + u * bd);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if (p + u * bd < np) body(p + u * bd);
+}
+
+static int red_blocks(size_t np, int U) {
+    size_t b = (np + (size_t)U * RB - 1) / ((size_t)U * RB);
     if (b > 1024) b = 1024;
     if (b < 1) b = 1;
     return (int)b;
 }
 
+static dim3 ew_grid(size_t np, int nrhs, int U) {
+    size_t b = (np + (size_t)U * 256 - 1) / ((size_t)U * 256);
+    if (b > 2048) b = 2048;
+    if (b < 1) b = 1;
+    return dim3((unsigned)b, nrhs);
+}
+
+// ---------------------------------------------------------------------------
+// deterministic reduction tail
+// ---------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -45,91 +137,49 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds /* [4][NV
     }
 }
 
-// write partial, and let the last block of this rhs sum partials in order
+// Reduce this workgroup's values and write them as its partial
+// part[rhs][block][k].
 template <int NV>
-__device__ __forceinline__ void finish(double (&v)[NV], double* part, unsigned* cnt, double* out, int nvals) {
-    __shared__ bool last;
-    const int r = blockIdx.y, nb = gridDim.x;
-    if (threadIdx.x == 0) {
-        for (int k = 0; k < nvals; ++k) part[((size_t)r * nb + blockIdx.x) * NV + k] = v[k];
-        __threadfence();
-        unsigned t = atomicAdd(&cnt[r], 1u);
-        last = (t == (unsigned)nb - 1);
-    }
-    __syncthreads();
-    if (last) {
-        __threadfence();
-        for (int k = threadIdx.x; k < nvals; k += blockDim.x) {
-            double s = 0.0;
-            for (int b = 0; b < nb; ++b) s += part[((size_t)r * nb + b) * NV + k];
-            out[(size_t)r * nvals + k] = s;
-        }
-        if (threadIdx.x == 0) cnt[r] = 0;
-    }
+__device__ __forceinline__ void write_partial(double (&v)[NV], double* lds, double* part, int nvals) {
+    block_sum<NV>(v, lds);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < nvals; ++k) part[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * NV + k] = v[k];
 }
 
-template <typename S>
-__global__ __launch_bounds__(RB) void k_norm2(const S* __restrict__ x, size_t n, double* part, unsigned* cnt,
-                                              double* out) {
-    __shared__ double lds[4];
-    const S* xr = x + (size_t)blockIdx.y * n;
-    double v[1] = {0.0};
-    for (size_t e = (size_t)blockIdx.x * RB + threadIdx.x; e < n; e += (size_t)gridDim.x * RB) {
-        cx<double> a = ldc<S, double>(xr + e);
-        v[0] = fma(a.re, a.re, v[0]);
-        v[0] = fma(a.im, a.im, v[0]);
-    }
-    block_sum<1>(v, lds);
-    finish<1>(v, part, cnt, out, 1);
-}
-
-// out[j][r] = sum_e conj(x_j[e]) y[e]   (complex, j < K)
-template <typename S, int K>
-__global__ __launch_bounds__(RB) void k_multidot(const S* __restrict__ x, size_t xstride, const S* __restrict__ y,
-                                                 size_t n, int k, double* part, unsigned* cnt, double* out,
-                                                 int ostride) {
-    __shared__ double lds[4 * 2 * K];
-    const size_t roff = (size_t)blockIdx.y * n;
-    double v[2 * K];
+// Second pass, one workgroup per rhs: add the nb partials (each thread a
+// fixed strided share, then the same tree as above).  mode 0 writes
+// out[r][k]; mode 1 (multi-dot) writes the complex out[k / 2][ostride][r].
+template <int NV>
+__global__ __launch_bounds__(RB) void k_finish(const double* __restrict__ part, int nb, int nvals,
+                                               double* __restrict__ out, int mode, int ostride) {
+    __shared__ double lds[4 * NV];
+    const int r = blockIdx.x;
+    double s[NV];
 #pragma unroll
-    for (int j = 0; j < 2 * K; ++j) v[j] = 0.0;
-    for (size_t e = (size_t)blockIdx.x * RB + threadIdx.x; e < n; e += (size_t)gridDim.x * RB) {
-        cx<double> b = ldc<S, double>(y + roff + e);
+    for (int k = 0; k < NV; ++k) s[k] = 0.0;
+    for (int b = threadIdx.x; b < nb; b += RB) {
+        const double* pb = part + ((size_t)r * nb + b) * NV;
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            if (j < k) {
-                cx<double> a = ldc<S, double>(x + (size_t)j * xstride + roff + e);
-                v[2 * j] = fma(a.re, b.re, v[2 * j]);
-                v[2 * j] = fma(a.im, b.im, v[2 * j]);
-                v[2 * j + 1] = fma(a.re, b.im, v[2 * j + 1]);
-                v[2 * j + 1] = fma(-a.im, b.re, v[2 * j + 1]);
-            }
-        }
+        for (int k = 0; k < NV; ++k)
+            if (k < nvals) s[k] += pb[k];
     }
-    block_sum<2 * K>(v, lds);
-    // partials laid out [r][block][2K]; final sums [r][2k] then scattered to out[j][r]
-    __shared__ bool last;
-    const int r = blockIdx.y, nb = gridDim.x;
+    block_sum<NV>(s, lds);
     if (threadIdx.x == 0) {
-        for (int q = 0; q < 2 * k; ++q) part[((size_t)r * nb + blockIdx.x) * (2 * K) + q] = v[q];
-        __threadfence();
-        unsigned t = atomicAdd(&cnt[r], 1u);
-        last = (t == (unsigned)nb - 1);
-    }
-    __syncthreads();
-    if (last) {
-        __threadfence();
-        for (int q = threadIdx.x; q < 2 * k; q += blockDim.x) {
-            double s = 0.0;
-            for (int b = 0; b < nb; ++b) s += part[((size_t)r * nb + b) * (2 * K) + q];
-            // out is complex [j][ostride], element (j, r)
-            out[((size_t)(q >> 1) * ostride + r) * 2 + (q & 1)] = s;
+        for (int k = 0; k < nvals; ++k) {
+            if (mode == 0) out[(size_t)r * nvals + k] = s[k];
+            else out[((size_t)(k >> 1) * ostride + r) * 2 + (k & 1)] = s[k];
         }
-        if (threadIdx.x == 0) cnt[r] = 0;
     }
 }
 
-static int ensure_red(mglma_ctx* c, size_t ndouble, size_t ncnt) {
+template <int NV>
+static int launch_finish(mglma_ctx* c, int nb, int nrhs, int nvals, double* out, int mode = 0, int ostride = 0) {
+    hipLaunchKernelGGL(k_finish<NV>, dim3(nrhs), dim3(RB), 0, c->stream, c->red_part, nb, nvals, out, mode, ostride);
+    HIP_TRY(hipGetLastError());
+    return MGLMA_OK;
+}
+
+static int ensure_red(mglma_ctx* c, size_t ndouble) {
     if (c->red_part_n < ndouble) {
         if (c->red_part) {
             HIP_TRY(hipStreamSynchronize(c->stream));
@@ -139,50 +189,111 @@ static int ensure_red(mglma_ctx* c, size_t ndouble, size_t ncnt) {
         MG_TRY(mg_malloc(c, (void**)&c->red_part, nn * sizeof(double)));
         c->red_part_n = nn;
     }
-    if (c->red_cnt_n < ncnt) {
-        if (c->red_cnt) {
-            HIP_TRY(hipStreamSynchronize(c->stream));
-            mg_free(c, c->red_cnt, c->red_cnt_n * sizeof(unsigned));
-        }
-        size_t nn = ncnt + 256;
-        MG_TRY(mg_malloc(c, (void**)&c->red_cnt, nn * sizeof(unsigned)));
-        HIP_TRY(hipMemsetAsync(c->red_cnt, 0, nn * sizeof(unsigned), c->stream));
-        c->red_cnt_n = nn;
-    }
     return MGLMA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// norms and inner products
+// ---------------------------------------------------------------------------
+#define U_NORM 4
+#define U_DOT 2
+
+// out[r] = |x_r|^2
+template <typename S, int C>
+__global__ __launch_bounds__(RB) void k_norm2(const S* __restrict__ x, size_t n, double* part) {
+    __shared__ double lds[4];
+    const S* xr = x + (size_t)blockIdx.y * n;
+    double v[1] = {0.0};
+    for_packets<U_NORM>(n / C, [&](size_t p) {
+        cx<double> a[C];
+        ldp<S, double, C>(xr + p * C, a);
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            v[0] = fma(a[k].re, a[k].re, v[0]);
+            v[0] = fma(a[k].im, a[k].im, v[0]);
+        }
+    });
+    write_partial<1>(v, lds, part, 1);
+}
+
+template <typename S>
+static int norm2_t(mglma_ctx* c, const S* x, size_t n, int nrhs, double* out) {
+    constexpr int C = pk<S>();
+    const bool vec = n % C == 0 && al(x, 16);
+    const size_t np = vec ? n / C : n;
+    const int nb = red_blocks(np, U_NORM);
+    MG_TRY(ensure_red(c, (size_t)nb * nrhs));
+    dim3 grid(nb, nrhs);
+    if (vec) hipLaunchKernelGGL((k_norm2<S, C>), grid, dim3(RB), 0, c->stream, x, n, c->red_part);
+    else hipLaunchKernelGGL((k_norm2<S, 1>), grid, dim3(RB), 0, c->stream, x, n, c->red_part);
+    HIP_TRY(hipGetLastError());
+    return launch_finish<1>(c, nb, nrhs, 1, out);
 }
 
 int mg_norm2(mglma_ctx* c, int prec, const void* x, size_t n, int nrhs, double* out) {
     if (nrhs <= 0) return MGLMA_OK;
-    int nb = red_blocks(n);
-    MG_TRY(ensure_red(c, (size_t)nb * nrhs, nrhs));
-    dim3 grid(nb, nrhs);
     switch (prec) {
-        case MGLMA_F64: hipLaunchKernelGGL(k_norm2<double2>, grid, dim3(RB), 0, c->stream, (const double2*)x, n, c->red_part, c->red_cnt, out); break;
-        case MGLMA_F32: hipLaunchKernelGGL(k_norm2<float2>, grid, dim3(RB), 0, c->stream, (const float2*)x, n, c->red_part, c->red_cnt, out); break;
-        case MGLMA_F16: hipLaunchKernelGGL(k_norm2<__half2>, grid, dim3(RB), 0, c->stream, (const __half2*)x, n, c->red_part, c->red_cnt, out); break;
+        case MGLMA_F64: return norm2_t(c, (const double2*)x, n, nrhs, out);
+        case MGLMA_F32: return norm2_t(c, (const float2*)x, n, nrhs, out);
+        case MGLMA_F16: return norm2_t(c, (const __half2*)x, n, nrhs, out);
         default: return MGLMA_ERR_ARG;
     }
-    HIP_TRY(hipGetLastError());
-    return MGLMA_OK;
+}
+
+// out[j][r] = sum_e conj(x_j[e]) y[e]   (complex, j < k <= K; out row stride ostride)
+template <typename S, int K, int C>
+__global__ __launch_bounds__(RB) void k_multidot(const S* __restrict__ x, size_t xstride, const S* __restrict__ y,
+                                                 size_t n, int k, double* part) {
+    __shared__ double lds[4 * 2 * K];
+    const size_t roff = (size_t)blockIdx.y * n;
+    double v[2 * K];
+#pragma unroll
+    for (int j = 0; j < 2 * K; ++j) v[j] = 0.0;
+    for_packets<1>(n / C, [&](size_t p) {
+        cx<double> b[C];
+        ldp<S, double, C>(y + roff + p * C, b);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            if (j < k) {
+                cx<double> a[C];
+                ldp<S, double, C>(x + (size_t)j * xstride + roff + p * C, a);
+#pragma unroll
+                for (int q = 0; q < C; ++q) {
+                    v[2 * j] = fma(a[q].re, b[q].re, v[2 * j]);
+                    v[2 * j] = fma(a[q].im, b[q].im, v[2 * j]);
+                    v[2 * j + 1] = fma(a[q].re, b[q].im, v[2 * j + 1]);
+                    v[2 * j + 1] = fma(-a[q].im, b[q].re, v[2 * j + 1]);
+                }
+            }
+        }
+    });
+    write_partial<2 * K>(v, lds, part, 2 * k);
 }
 
 template <typename S>
 static int multidot_t(mglma_ctx* c, const S* x, size_t xstride, int k, const S* y, size_t n, int nrhs, double* out) {
-    int nb = red_blocks(n);
-    MG_TRY(ensure_red(c, (size_t)nb * nrhs * 2 * MAXK, nrhs));
+    constexpr int C = pk<S>();
+    const bool vec = n % C == 0 && xstride % C == 0 && al(x, 16) && al(y, 16);
+    const size_t np = vec ? n / C : n;
+    const int nb = red_blocks(np, 1);
+    MG_TRY(ensure_red(c, (size_t)nb * nrhs * 2 * MAXK));
     for (int j0 = 0; j0 < k; j0 += MAXK) {
         int kk = k - j0 < MAXK ? k - j0 : MAXK;
         dim3 grid(nb, nrhs);
         const S* xj = x + (size_t)j0 * xstride;
         double* oj = out + (size_t)j0 * nrhs * 2;
-        if (kk == 1)
-            hipLaunchKernelGGL((k_multidot<S, 1>), grid, dim3(RB), 0, c->stream, xj, xstride, y, n, kk, c->red_part, c->red_cnt, oj, nrhs);
-        else if (kk <= 4)
-            hipLaunchKernelGGL((k_multidot<S, 4>), grid, dim3(RB), 0, c->stream, xj, xstride, y, n, kk, c->red_part, c->red_cnt, oj, nrhs);
-        else
-            hipLaunchKernelGGL((k_multidot<S, MAXK>), grid, dim3(RB), 0, c->stream, xj, xstride, y, n, kk, c->red_part, c->red_cnt, oj, nrhs);
+#define MD_LAUNCH(KK, CC) \
+        hipLaunchKernelGGL((k_multidot<S, KK, CC>), grid, dim3(RB), 0, c->stream, xj, xstride, y, n, kk, c->red_part)
+        if (vec) {
+            if (kk == 1) MD_LAUNCH(1, C); else if (kk <= 4) MD_LAUNCH(4, C); else MD_LAUNCH(MAXK, C);
+        } else {
+            if (kk == 1) MD_LAUNCH(1, 1); else if (kk <= 4) MD_LAUNCH(4, 1); else MD_LAUNCH(MAXK, 1);
+        }
+#undef MD_LAUNCH
         HIP_TRY(hipGetLastError());
+        if (kk == 1) MG_TRY(launch_finish<2>(c, nb, nrhs, 2, oj, 1, nrhs));
+        else if (kk <= 4) MG_TRY(launch_finish<8>(c, nb, nrhs, 2 * kk, oj, 1, nrhs));
+        else MG_TRY(launch_finish<2 * MAXK>(c, nb, nrhs, 2 * kk, oj, 1, nrhs));
     }
     return MGLMA_OK;
 }
@@ -202,8 +313,120 @@ int mg_dot(mglma_ctx* c, int prec, const void* x, const void* y, size_t n, int n
     return mg_multidot(c, prec, x, 0, 1, y, n, nrhs, out);
 }
 
+// out[r] = (Re <x,y>, Im <x,y>, |x|^2)
+template <typename S, int C>
+__global__ __launch_bounds__(RB) void k_dot_norm(const S* __restrict__ x, const S* __restrict__ y, size_t n,
+                                                 double* part) {
+    __shared__ double lds[4 * 3];
+    const size_t roff = (size_t)blockIdx.y * n;
+    double v[3] = {0.0, 0.0, 0.0};
+    for_packets<U_DOT>(n / C, [&](size_t p) {
+        cx<double> a[C], b[C];
+        ldp<S, double, C>(x + roff + p * C, a);
+        ldp<S, double, C>(y + roff + p * C, b);
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            v[0] = fma(a[q].re, b[q].re, v[0]); v[0] = fma(a[q].im, b[q].im, v[0]);
+            v[1] = fma(a[q].re, b[q].im, v[1]); v[1] = fma(-a[q].im, b[q].re, v[1]);
+            v[2] = fma(a[q].re, a[q].re, v[2]); v[2] = fma(a[q].im, a[q].im, v[2]);
+        }
+    });
+    write_partial<3>(v, lds, part, 3);
+}
+
+template <typename S>
+static int dot_norm_t(mglma_ctx* c, const S* x, const S* y, size_t n, int nrhs, double* out) {
+    constexpr int C = pk<S>();
+    const bool vec = n % C == 0 && al(x, 16) && al(y, 16);
+    const size_t np = vec ? n / C : n;
+    const int nb = red_blocks(np, U_DOT);
+    MG_TRY(ensure_red(c, (size_t)nb * nrhs * 3));
+    dim3 grid(nb, nrhs);
+    if (vec) hipLaunchKernelGGL((k_dot_norm<S, C>), grid, dim3(RB), 0, c->stream, x, y, n, c->red_part);
+    else hipLaunchKernelGGL((k_dot_norm<S, 1>), grid, dim3(RB), 0, c->stream, x, y, n, c->red_part);
+    HIP_TRY(hipGetLastError());
+    return launch_finish<3>(c, nb, nrhs, 3, out);
+}
+
+int mg_dot_norm(mglma_ctx* c, int prec, const void* x, const void* y, size_t n, int nrhs, double* out) {
+    if (nrhs <= 0) return MGLMA_OK;
+    switch (prec) {
+        case MGLMA_F64: return dot_norm_t(c, (const double2*)x, (const double2*)y, n, nrhs, out);
+        case MGLMA_F32: return dot_norm_t(c, (const float2*)x, (const float2*)y, n, nrhs, out);
+        case MGLMA_F16: return dot_norm_t(c, (const __half2*)x, (const __half2*)y, n, nrhs, out);
+        default: return MGLMA_ERR_ARG;
+    }
+}
+
+// e += a z ; r -= a w ; out[r] = |r|^2 after the update (of the stored values)
+template <typename S, typename R, int C>
+__global__ __launch_bounds__(RB) void k_update_norm(const double* __restrict__ a, S* __restrict__ e, const S* __restrict__ z,
+                                                    S* __restrict__ rr, const S* __restrict__ w, size_t n,
+                                                    double* part) {
+    __shared__ double lds[4];
+    const int r = blockIdx.y;
+    const size_t roff = (size_t)r * n;
+    const cx<R> al_ = cmk((R)a[2 * r], (R)a[2 * r + 1]);
+    double v[1] = {0.0};
+    for_packets<U_DOT>(n / C, [&](size_t p) {
+        const size_t o = roff + p * C;
+        cx<R> ev[C], rv[C], zv[C], wv[C];
+        ldp<S, R, C>(e + o, ev);
+        ldp<S, R, C>(rr + o, rv);
+        ldp<S, R, C>(z + o, zv);
+        ldp<S, R, C>(w + o, wv);
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            cmac(ev[q], al_, zv[q]);
+            cmac(rv[q], -al_, wv[q]);
+        }
+        stp<S, R, C>(e + o, ev);
+        stp<S, R, C>(rr + o, rv);
+        cx<double> rs[C];
+        ldp<S, double, C>(rr + o, rs);   // the stored (rounded) values
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            v[0] = fma(rs[q].re, rs[q].re, v[0]);
+            v[0] = fma(rs[q].im, rs[q].im, v[0]);
+        }
+    });
+    write_partial<1>(v, lds, part, 1);
+}
+
+template <typename S, typename R>
+static int update_norm_t(mglma_ctx* c, const double* a, S* e, const S* z, S* r, const S* w, size_t n, int nrhs,
+                         double* out) {
+    constexpr int C = pk<S>();
+    const bool vec = n % C == 0 && al(e, 16) && al(z, 16) && al(r, 16) && al(w, 16);
+    const size_t np = vec ? n / C : n;
+    const int nb = red_blocks(np, U_DOT);
+    MG_TRY(ensure_red(c, (size_t)nb * nrhs));
+    dim3 grid(nb, nrhs);
+    if (vec)
+        hipLaunchKernelGGL((k_update_norm<S, R, C>), grid, dim3(RB), 0, c->stream, a, e, z, r, w, n, c->red_part);
+    else
+        hipLaunchKernelGGL((k_update_norm<S, R, 1>), grid, dim3(RB), 0, c->stream, a, e, z, r, w, n, c->red_part);
+    HIP_TRY(hipGetLastError());
+    return launch_finish<1>(c, nb, nrhs, 1, out);
+}
+
+int mg_update_norm(mglma_ctx* c, int prec, const double* a, void* e, const void* z, void* r, const void* w, size_t n,
+                   int nrhs, double* out) {
+    if (nrhs <= 0) return MGLMA_OK;
+    switch (prec) {
+        case MGLMA_F64: return update_norm_t<double2, double>(c, a, (double2*)e, (const double2*)z, (double2*)r, (const double2*)w, n, nrhs, out);
+        case MGLMA_F32: return update_norm_t<float2, float>(c, a, (float2*)e, (const float2*)z, (float2*)r, (const float2*)w, n, nrhs, out);
+        default: return MGLMA_ERR_ARG;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// elementwise updates
+// ---------------------------------------------------------------------------
+#define U_EW 2
+
 // y += sign * sum_j coef[j][r] x_j       (coef complex [k][nrhs])
-template <typename S, typename R, int K>
+template <typename S, typename R, int K, int C>
 __global__ void k_multiaxpy(const S* __restrict__ x, size_t xstride, int k, const double* __restrict__ coef,
                             R sign, S* __restrict__ y, size_t n, int nrhs) {
     const int r = blockIdx.y;
@@ -214,35 +437,40 @@ __global__ void k_multiaxpy(const S* __restrict__ x, size_t xstride, int k, cons
         if (j < k) a[j] = cmk((R)(sign * coef[((size_t)j * nrhs + r) * 2]), (R)(sign * coef[((size_t)j * nrhs + r) * 2 + 1]));
         else a[j] = cmk((R)0, (R)0);
     }
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-        cx<R> v = ldc<S, R>(y + roff + e);
+    for_packets<1>(n / C, [&](size_t p) {
+        const size_t o = roff + p * C;
+        cx<R> v[C];
+        ldp<S, R, C>(y + o, v);
 #pragma unroll
         for (int j = 0; j < K; ++j)
-            if (j < k) cmac(v, a[j], ldc<S, R>(x + (size_t)j * xstride + roff + e));
-        stc<S, R>(y + roff + e, v);
-    }
-}
-
-static dim3 ew_grid(size_t n, int nrhs) {
-    size_t b = (n + 1023) / 1024;
-    if (b > 2048) b = 2048;
-    if (b < 1) b = 1;
-    return dim3((unsigned)b, nrhs);
+            if (j < k) {
+                cx<R> xv[C];
+                ldp<S, R, C>(x + (size_t)j * xstride + o, xv);
+#pragma unroll
+                for (int q = 0; q < C; ++q) cmac(v[q], a[j], xv[q]);
+            }
+        stp<S, R, C>(y + o, v);
+    });
 }
 
 template <typename S, typename R>
 static int multiaxpy_t(mglma_ctx* c, const S* x, size_t xstride, int k, const double* coef, double sign, S* y,
                        size_t n, int nrhs) {
+    constexpr int C = pk<S>();
+    const bool vec = n % C == 0 && xstride % C == 0 && al(x, 16) && al(y, 16);
+    const dim3 grid = ew_grid(vec ? n / C : n, nrhs, 1);
     for (int j0 = 0; j0 < k; j0 += MAXK) {
         int kk = k - j0 < MAXK ? k - j0 : MAXK;
         const S* xj = x + (size_t)j0 * xstride;
         const double* cj = coef + (size_t)j0 * nrhs * 2;
-        if (kk == 1)
-            hipLaunchKernelGGL((k_multiaxpy<S, R, 1>), ew_grid(n, nrhs), dim3(256), 0, c->stream, xj, xstride, kk, cj, (R)sign, y, n, nrhs);
-        else if (kk <= 4)
-            hipLaunchKernelGGL((k_multiaxpy<S, R, 4>), ew_grid(n, nrhs), dim3(256), 0, c->stream, xj, xstride, kk, cj, (R)sign, y, n, nrhs);
-        else
-            hipLaunchKernelGGL((k_multiaxpy<S, R, MAXK>), ew_grid(n, nrhs), dim3(256), 0, c->stream, xj, xstride, kk, cj, (R)sign, y, n, nrhs);
+#define MA_LAUNCH(KK, CC) \
+        hipLaunchKernelGGL((k_multiaxpy<S, R, KK, CC>), grid, dim3(256), 0, c->stream, xj, xstride, kk, cj, (R)sign, y, n, nrhs)
+        if (vec) {
+            if (kk == 1) MA_LAUNCH(1, C); else if (kk <= 4) MA_LAUNCH(4, C); else MA_LAUNCH(MAXK, C);
+        } else {
+            if (kk == 1) MA_LAUNCH(1, 1); else if (kk <= 4) MA_LAUNCH(4, 1); else MA_LAUNCH(MAXK, 1);
+        }
+#undef MA_LAUNCH
         HIP_TRY(hipGetLastError());
     }
     return MGLMA_OK;
@@ -260,35 +488,50 @@ int mg_multiaxpy(mglma_ctx* c, int prec, const void* x, size_t xstride, int k, c
 }
 
 // y = a*x + b*y, a and b complex per rhs from device arrays (null a -> 0, null b -> 1)
-template <typename S, typename R>
+template <typename S, typename R, int C>
 __global__ void k_axpby(const double* __restrict__ a, const S* __restrict__ x, const double* __restrict__ b,
                         S* __restrict__ y, size_t n) {
     const int r = blockIdx.y;
     const size_t roff = (size_t)r * n;
-    cx<R> ca = a ? cmk((R)a[2 * r], (R)a[2 * r + 1]) : cmk((R)0, (R)0);
-    cx<R> cb = b ? cmk((R)b[2 * r], (R)b[2 * r + 1]) : cmk((R)1, (R)0);
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-        cx<R> v = cb * ldc<S, R>(y + roff + e);
-        if (a) cmac(v, ca, ldc<S, R>(x + roff + e));
-        stc<S, R>(y + roff + e, v);
-    }
+    const cx<R> ca = a ? cmk((R)a[2 * r], (R)a[2 * r + 1]) : cmk((R)0, (R)0);
+    const cx<R> cb = b ? cmk((R)b[2 * r], (R)b[2 * r + 1]) : cmk((R)1, (R)0);
+    for_packets<U_EW>(n / C, [&](size_t p) {
+        const size_t o = roff + p * C;
+        cx<R> v[C], xv[C];
+        ldp<S, R, C>(y + o, v);
+        if (a) ldp<S, R, C>(x + o, xv);
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            v[q] = cb * v[q];
+            if (a) cmac(v[q], ca, xv[q]);
+        }
+        stp<S, R, C>(y + o, v);
+    });
 }
 
-int mg_axpby(mglma_ctx* c, int prec, const double* a, const void* x, const double* b, void* y, size_t n, int nrhs) {
-    if (nrhs <= 0) return MGLMA_OK;
-    dim3 grid = ew_grid(n, nrhs);
-    switch (prec) {
-        case MGLMA_F64: hipLaunchKernelGGL((k_axpby<double2, double>), grid, dim3(256), 0, c->stream, a, (const double2*)x, b, (double2*)y, n); break;
-        case MGLMA_F32: hipLaunchKernelGGL((k_axpby<float2, float>), grid, dim3(256), 0, c->stream, a, (const float2*)x, b, (float2*)y, n); break;
-        case MGLMA_F16: hipLaunchKernelGGL((k_axpby<__half2, float>), grid, dim3(256), 0, c->stream, a, (const __half2*)x, b, (__half2*)y, n); break;
-        default: return MGLMA_ERR_ARG;
-    }
+template <typename S, typename R>
+static int axpby_t(mglma_ctx* c, const double* a, const S* x, const double* b, S* y, size_t n, int nrhs) {
+    constexpr int C = pk<S>();
+    const bool vec = n % C == 0 && (!a || al(x, 16)) && al(y, 16);
+    const dim3 grid = ew_grid(vec ? n / C : n, nrhs, U_EW);
+    if (vec) hipLaunchKernelGGL((k_axpby<S, R, C>), grid, dim3(256), 0, c->stream, a, x, b, y, n);
+    else hipLaunchKernelGGL((k_axpby<S, R, 1>), grid, dim3(256), 0, c->stream, a, x, b, y, n);
     HIP_TRY(hipGetLastError());
     return MGLMA_OK;
 }
 
+int mg_axpby(mglma_ctx* c, int prec, const double* a, const void* x, const double* b, void* y, size_t n, int nrhs) {
+    if (nrhs <= 0) return MGLMA_OK;
+    switch (prec) {
+        case MGLMA_F64: return axpby_t<double2, double>(c, a, (const double2*)x, b, (double2*)y, n, nrhs);
+        case MGLMA_F32: return axpby_t<float2, float>(c, a, (const float2*)x, b, (float2*)y, n, nrhs);
+        case MGLMA_F16: return axpby_t<__half2, float>(c, a, (const __half2*)x, b, (__half2*)y, n, nrhs);
+        default: return MGLMA_ERR_ARG;
+    }
+}
+
 // y = s_r * x (or x / s_r), converting precision
-template <typename SI, typename SO>
+template <typename SI, typename SO, int C>
 __global__ void k_convert(const SI* __restrict__ x, SO* __restrict__ y, size_t n, const double* __restrict__ scale,
                           int invert) {
     const int r = blockIdx.y;
@@ -298,23 +541,35 @@ __global__ void k_convert(const SI* __restrict__ x, SO* __restrict__ y, size_t n
         s = scale[r];
         if (invert) s = s != 0.0 ? 1.0 / s : 0.0;
     }
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-        cx<double> v = ldc<SI, double>(x + roff + e);
-        stc<SO, double>(y + roff + e, s * v);
-    }
+    for_packets<U_EW>(n / C, [&](size_t p) {
+        const size_t o = roff + p * C;
+        cx<double> v[C];
+        ldp<SI, double, C>(x + o, v);
+#pragma unroll
+        for (int q = 0; q < C; ++q) v[q] = s * v[q];
+        stp<SO, double, C>(y + o, v);
+    });
+}
+
+template <typename SI, typename SO>
+static int convert_t(mglma_ctx* c, const SI* x, SO* y, size_t n, int nrhs, const double* s, int inv) {
+    constexpr int C = pk<SI>() < pk<SO>() ? pk<SI>() : pk<SO>();
+    const bool vec = n % C == 0 && al(x, C * sizeof(SI)) && al(y, C * sizeof(SO));
+    const dim3 grid = ew_grid(vec ? n / C : n, nrhs, U_EW);
+    if (vec) hipLaunchKernelGGL((k_convert<SI, SO, C>), grid, dim3(256), 0, c->stream, x, y, n, s, inv);
+    else hipLaunchKernelGGL((k_convert<SI, SO, 1>), grid, dim3(256), 0, c->stream, x, y, n, s, inv);
+    HIP_TRY(hipGetLastError());
+    return MGLMA_OK;
 }
 
 template <typename SI>
 static int convert_out(mglma_ctx* c, const SI* x, int pout, void* y, size_t n, int nrhs, const double* s, int inv) {
-    dim3 grid = ew_grid(n, nrhs);
     switch (pout) {
-        case MGLMA_F64: hipLaunchKernelGGL((k_convert<SI, double2>), grid, dim3(256), 0, c->stream, x, (double2*)y, n, s, inv); break;
-        case MGLMA_F32: hipLaunchKernelGGL((k_convert<SI, float2>), grid, dim3(256), 0, c->stream, x, (float2*)y, n, s, inv); break;
-        case MGLMA_F16: hipLaunchKernelGGL((k_convert<SI, __half2>), grid, dim3(256), 0, c->stream, x, (__half2*)y, n, s, inv); break;
+        case MGLMA_F64: return convert_t(c, x, (double2*)y, n, nrhs, s, inv);
+        case MGLMA_F32: return convert_t(c, x, (float2*)y, n, nrhs, s, inv);
+        case MGLMA_F16: return convert_t(c, x, (__half2*)y, n, nrhs, s, inv);
         default: return MGLMA_ERR_ARG;
     }
-    HIP_TRY(hipGetLastError());
-    return MGLMA_OK;
 }
 
 int mg_convert(mglma_ctx* c, int pin, const void* x, int pout, void* y, size_t n, int nrhs, const double* s, int inv) {
@@ -327,71 +582,51 @@ int mg_convert(mglma_ctx* c, int pin, const void* x, int pout, void* y, size_t n
     }
 }
 
-// ---------------------------------------------------------------------------
-// fused kernels for the solver loops
-// ---------------------------------------------------------------------------
-// out[r] = (Re <x,y>, Im <x,y>, |x|^2)
-template <typename S>
-__global__ __launch_bounds__(RB) void k_dot_norm(const S* __restrict__ x, const S* __restrict__ y, size_t n,
-                                                 double* part, unsigned* cnt, double* out) {
-    __shared__ double lds[4 * 3];
-    const size_t roff = (size_t)blockIdx.y * n;
-    double v[3] = {0.0, 0.0, 0.0};
-    for (size_t e = (size_t)blockIdx.x * RB + threadIdx.x; e < n; e += (size_t)gridDim.x * RB) {
-        cx<double> a = ldc<S, double>(x + roff + e), b = ldc<S, double>(y + roff + e);
-        v[0] = fma(a.re, b.re, v[0]); v[0] = fma(a.im, b.im, v[0]);
-        v[1] = fma(a.re, b.im, v[1]); v[1] = fma(-a.im, b.re, v[1]);
-        v[2] = fma(a.re, a.re, v[2]); v[2] = fma(a.im, a.im, v[2]);
-    }
-    block_sum<3>(v, lds);
-    finish<3>(v, part, cnt, out, 3);
-}
-
-int mg_dot_norm(mglma_ctx* c, int prec, const void* x, const void* y, size_t n, int nrhs, double* out) {
-    if (nrhs <= 0) return MGLMA_OK;
-    int nb = red_blocks(n);
-    MG_TRY(ensure_red(c, (size_t)nb * nrhs * 3, nrhs));
-    dim3 grid(nb, nrhs);
-    switch (prec) {
-        case MGLMA_F64: hipLaunchKernelGGL(k_dot_norm<double2>, grid, dim3(RB), 0, c->stream, (const double2*)x, (const double2*)y, n, c->red_part, c->red_cnt, out); break;
-        case MGLMA_F32: hipLaunchKernelGGL(k_dot_norm<float2>, grid, dim3(RB), 0, c->stream, (const float2*)x, (const float2*)y, n, c->red_part, c->red_cnt, out); break;
-        case MGLMA_F16: hipLaunchKernelGGL(k_dot_norm<__half2>, grid, dim3(RB), 0, c->stream, (const __half2*)x, (const __half2*)y, n, c->red_part, c->red_cnt, out); break;
-        default: return MGLMA_ERR_ARG;
-    }
-    HIP_TRY(hipGetLastError());
-    return MGLMA_OK;
-}
-
 // z += a s ; s -= a t    (a complex per rhs)
-template <typename S, typename R>
+template <typename S, typename R, int C>
 __global__ void k_mr_update(const double* __restrict__ a, S* __restrict__ z, S* __restrict__ s,
                             const S* __restrict__ t, size_t n) {
     const int r = blockIdx.y;
     const size_t roff = (size_t)r * n;
     const cx<R> w = cmk((R)a[2 * r], (R)a[2 * r + 1]);
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-        cx<R> sv = ldc<S, R>(s + roff + e), zv = ldc<S, R>(z + roff + e), tv = ldc<S, R>(t + roff + e);
-        cmac(zv, w, sv);
-        cmac(sv, -w, tv);
-        stc<S, R>(z + roff + e, zv);
-        stc<S, R>(s + roff + e, sv);
-    }
+    for_packets<U_EW>(n / C, [&](size_t p) {
+        const size_t o = roff + p * C;
+        cx<R> sv[C], zv[C], tv[C];
+        ldp<S, R, C>(s + o, sv);
+        ldp<S, R, C>(z + o, zv);
+        ldp<S, R, C>(t + o, tv);
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            cmac(zv[q], w, sv[q]);
+            cmac(sv[q], -w, tv[q]);
+        }
+        stp<S, R, C>(z + o, zv);
+        stp<S, R, C>(s + o, sv);
+    });
 }
 
-int mg_mr_update(mglma_ctx* c, int prec, const double* a, void* z, void* s, const void* t, size_t n, int nrhs) {
-    if (nrhs <= 0) return MGLMA_OK;
-    dim3 grid = ew_grid(n, nrhs);
-    switch (prec) {
-        case MGLMA_F64: hipLaunchKernelGGL((k_mr_update<double2, double>), grid, dim3(256), 0, c->stream, a, (double2*)z, (double2*)s, (const double2*)t, n); break;
-        case MGLMA_F32: hipLaunchKernelGGL((k_mr_update<float2, float>), grid, dim3(256), 0, c->stream, a, (float2*)z, (float2*)s, (const float2*)t, n); break;
-        default: return MGLMA_ERR_ARG;
-    }
+template <typename S, typename R>
+static int mr_update_t(mglma_ctx* c, const double* a, S* z, S* s, const S* t, size_t n, int nrhs) {
+    constexpr int C = pk<S>();
+    const bool vec = n % C == 0 && al(z, 16) && al(s, 16) && al(t, 16);
+    const dim3 grid = ew_grid(vec ? n / C : n, nrhs, U_EW);
+    if (vec) hipLaunchKernelGGL((k_mr_update<S, R, C>), grid, dim3(256), 0, c->stream, a, z, s, t, n);
+    else hipLaunchKernelGGL((k_mr_update<S, R, 1>), grid, dim3(256), 0, c->stream, a, z, s, t, n);
     HIP_TRY(hipGetLastError());
     return MGLMA_OK;
 }
 
+int mg_mr_update(mglma_ctx* c, int prec, const double* a, void* z, void* s, const void* t, size_t n, int nrhs) {
+    if (nrhs <= 0) return MGLMA_OK;
+    switch (prec) {
+        case MGLMA_F64: return mr_update_t<double2, double>(c, a, (double2*)z, (double2*)s, (const double2*)t, n, nrhs);
+        case MGLMA_F32: return mr_update_t<float2, float>(c, a, (float2*)z, (float2*)s, (const float2*)t, n, nrhs);
+        default: return MGLMA_ERR_ARG;
+    }
+}
+
 // y1 -= sum_j coef[j][r] x1_j ;  y2 -= sum_j coef[j][r] x2_j
-template <typename S, typename R, int K>
+template <typename S, typename R, int K, int C>
 __global__ void k_multiaxpy2(const S* __restrict__ x1, const S* __restrict__ x2, size_t xstride, int k,
                              const double* __restrict__ coef, S* __restrict__ y1, S* __restrict__ y2, size_t n,
                              int nrhs) {
@@ -402,31 +637,47 @@ __global__ void k_multiaxpy2(const S* __restrict__ x1, const S* __restrict__ x2,
     for (int j = 0; j < K; ++j)
         a[j] = j < k ? cmk((R)-coef[((size_t)j * nrhs + r) * 2], (R)-coef[((size_t)j * nrhs + r) * 2 + 1])
                      : cmk((R)0, (R)0);
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-        cx<R> v1 = ldc<S, R>(y1 + roff + e), v2 = ldc<S, R>(y2 + roff + e);
+    for_packets<1>(n / C, [&](size_t p) {
+        const size_t o = roff + p * C;
+        cx<R> v1[C], v2[C];
+        ldp<S, R, C>(y1 + o, v1);
+        ldp<S, R, C>(y2 + o, v2);
 #pragma unroll
         for (int j = 0; j < K; ++j)
             if (j < k) {
-                cmac(v1, a[j], ldc<S, R>(x1 + (size_t)j * xstride + roff + e));
-                cmac(v2, a[j], ldc<S, R>(x2 + (size_t)j * xstride + roff + e));
+                cx<R> u1[C], u2[C];
+                ldp<S, R, C>(x1 + (size_t)j * xstride + o, u1);
+                ldp<S, R, C>(x2 + (size_t)j * xstride + o, u2);
+#pragma unroll
+                for (int q = 0; q < C; ++q) {
+                    cmac(v1[q], a[j], u1[q]);
+                    cmac(v2[q], a[j], u2[q]);
+                }
             }
-        stc<S, R>(y1 + roff + e, v1);
-        stc<S, R>(y2 + roff + e, v2);
-    }
+        stp<S, R, C>(y1 + o, v1);
+        stp<S, R, C>(y2 + o, v2);
+    });
 }
 
 template <typename S, typename R>
 static int multiaxpy2_t(mglma_ctx* c, const S* x1, const S* x2, size_t xstride, int k, const double* coef, S* y1,
                         S* y2, size_t n, int nrhs) {
+    constexpr int C = pk<S>();
+    const bool vec = n % C == 0 && xstride % C == 0 && al(x1, 16) && al(x2, 16) && al(y1, 16) && al(y2, 16);
+    const dim3 grid = ew_grid(vec ? n / C : n, nrhs, 1);
     for (int j0 = 0; j0 < k; j0 += MAXK) {
         int kk = k - j0 < MAXK ? k - j0 : MAXK;
         const double* cj = coef + (size_t)j0 * nrhs * 2;
         const S* a1 = x1 + (size_t)j0 * xstride;
         const S* a2 = x2 + (size_t)j0 * xstride;
-        if (kk <= 4)
-            hipLaunchKernelGGL((k_multiaxpy2<S, R, 4>), ew_grid(n, nrhs), dim3(256), 0, c->stream, a1, a2, xstride, kk, cj, y1, y2, n, nrhs);
-        else
-            hipLaunchKernelGGL((k_multiaxpy2<S, R, MAXK>), ew_grid(n, nrhs), dim3(256), 0, c->stream, a1, a2, xstride, kk, cj, y1, y2, n, nrhs);
+#define M2_LAUNCH(KK, CC) \
+        hipLaunchKernelGGL((k_multiaxpy2<S, R, KK, CC>), grid, dim3(256), 0, c->stream, a1, a2, xstride, kk, cj, y1, y2, n, nrhs)
+        if (vec) {
+            if (kk <= 4) M2_LAUNCH(4, C); else M2_LAUNCH(MAXK, C);
+        } else {
+            if (kk <= 4) M2_LAUNCH(4, 1); else M2_LAUNCH(MAXK, 1);
+        }
+#undef M2_LAUNCH
         HIP_TRY(hipGetLastError());
     }
     return MGLMA_OK;
@@ -442,67 +693,41 @@ int mg_multiaxpy2(mglma_ctx* c, int prec, const void* x1, const void* x2, size_t
     }
 }
 
-// e += a z ; r -= a w ; out[r] = |r|^2 after the update
-template <typename S, typename R>
-__global__ __launch_bounds__(RB) void k_update_norm(const double* __restrict__ a, S* __restrict__ e, const S* __restrict__ z,
-                                                    S* __restrict__ rr, const S* __restrict__ w, size_t n,
-                                                    double* part, unsigned* cnt, double* out) {
-    __shared__ double lds[4];
-    const int r = blockIdx.y;
-    const size_t roff = (size_t)r * n;
-    const cx<R> al = cmk((R)a[2 * r], (R)a[2 * r + 1]);
-    double v[1] = {0.0};
-    for (size_t k = (size_t)blockIdx.x * RB + threadIdx.x; k < n; k += (size_t)gridDim.x * RB) {
-        cx<R> ev = ldc<S, R>(e + roff + k), rv = ldc<S, R>(rr + roff + k);
-        cmac(ev, al, ldc<S, R>(z + roff + k));
-        cmac(rv, -al, ldc<S, R>(w + roff + k));
-        stc<S, R>(e + roff + k, ev);
-        stc<S, R>(rr + roff + k, rv);
-        cx<double> rs = ldc<S, double>(rr + roff + k);   // the stored (rounded) value
-        v[0] = fma(rs.re, rs.re, v[0]);
-        v[0] = fma(rs.im, rs.im, v[0]);
-    }
-    block_sum<1>(v, lds);
-    finish<1>(v, part, cnt, out, 1);
-}
-
-int mg_update_norm(mglma_ctx* c, int prec, const double* a, void* e, const void* z, void* r, const void* w, size_t n,
-                   int nrhs, double* out) {
-    if (nrhs <= 0) return MGLMA_OK;
-    int nb = red_blocks(n);
-    MG_TRY(ensure_red(c, (size_t)nb * nrhs, nrhs));
-    dim3 grid(nb, nrhs);
-    switch (prec) {
-        case MGLMA_F64: hipLaunchKernelGGL((k_update_norm<double2, double>), grid, dim3(RB), 0, c->stream, a, (double2*)e, (const double2*)z, (double2*)r, (const double2*)w, n, c->red_part, c->red_cnt, out); break;
-        case MGLMA_F32: hipLaunchKernelGGL((k_update_norm<float2, float>), grid, dim3(RB), 0, c->stream, a, (float2*)e, (const float2*)z, (float2*)r, (const float2*)w, n, c->red_part, c->red_cnt, out); break;
-        default: return MGLMA_ERR_ARG;
-    }
-    HIP_TRY(hipGetLastError());
-    return MGLMA_OK;
-}
-
 // half-precision smoother step: z += (a*scale) s16 ; s16 -= a t16   (z FP32, s16/t16 FP16)
+template <int C>
 __global__ void k_mr_update_h(const double* __restrict__ a, const double* __restrict__ scale, float2* __restrict__ z,
                               __half2* __restrict__ s, const __half2* __restrict__ t, size_t n) {
     const int r = blockIdx.y;
     const size_t roff = (size_t)r * n;
     const cx<float> w = cmk((float)a[2 * r], (float)a[2 * r + 1]);
     const cx<float> ws = cmk((float)(a[2 * r] * scale[r]), (float)(a[2 * r + 1] * scale[r]));
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-        cx<float> sv = ldc<__half2, float>(s + roff + e), zv = ldc<float2, float>(z + roff + e);
-        cx<float> tv = ldc<__half2, float>(t + roff + e);
-        cmac(zv, ws, sv);
-        cmac(sv, -w, tv);
-        stc<float2, float>(z + roff + e, zv);
-        stc<__half2, float>(s + roff + e, sv);
-    }
+    for_packets<U_EW>(n / C, [&](size_t p) {
+        const size_t o = roff + p * C;
+        cx<float> sv[C], zv[C], tv[C];
+        ldp<__half2, float, C>(s + o, sv);
+        ldp<float2, float, C>(z + o, zv);
+        ldp<__half2, float, C>(t + o, tv);
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            cmac(zv[q], ws, sv[q]);
+            cmac(sv[q], -w, tv[q]);
+        }
+        stp<float2, float, C>(z + o, zv);
+        stp<__half2, float, C>(s + o, sv);
+    });
 }
 
 int mg_mr_update_h(mglma_ctx* c, const double* a, const double* scale, void* z, void* s16, const void* t16, size_t n,
                    int nrhs) {
     if (nrhs <= 0) return MGLMA_OK;
-    hipLaunchKernelGGL(k_mr_update_h, ew_grid(n, nrhs), dim3(256), 0, c->stream, a, scale, (float2*)z, (__half2*)s16,
-                       (const __half2*)t16, n);
+    const bool vec = n % 2 == 0 && al(z, 16) && al(s16, 8) && al(t16, 8);
+    const dim3 grid = ew_grid(vec ? n / 2 : n, nrhs, U_EW);
+    if (vec)
+        hipLaunchKernelGGL(k_mr_update_h<2>, grid, dim3(256), 0, c->stream, a, scale, (float2*)z, (__half2*)s16,
+                           (const __half2*)t16, n);
+    else
+        hipLaunchKernelGGL(k_mr_update_h<1>, grid, dim3(256), 0, c->stream, a, scale, (float2*)z, (__half2*)s16,
+                           (const __half2*)t16, n);
     HIP_TRY(hipGetLastError());
     return MGLMA_OK;
 }

@@ -4,9 +4,9 @@
 // with gamma5 = 1 giving Q_1 = (gamma5)_1 D_1 (rows of the alpha = 1
 // chirality negated).
 //
-// * FP64 / FP32 (VALU): one thread per (coarse site, row); the operator is
-//   read from a column-major copy so that a wavefront's loads are contiguous,
-//   the vector entries are wavefront-uniform loads.
+// * FP64 / FP32 (matrix cores, v_mfma_f64_16x16x4 / v_mfma_f32_16x16x4):
+//   same tiling as BF16 below, operator from a planar copy in the working
+//   precision, vectors loaded as they are.
 // * BF16 (matrix cores): each wavefront owns a 16-row x 16-rhs output tile and
 //   runs v_mfma_f32_16x16x16_bf16 over (direction, 16-column) steps.  The
 //   complex product uses the planar real form
@@ -27,52 +27,84 @@ __device__ __forceinline__ int coarse_nbr(const Geo& g, int y, int dir) {
     return y + (nmu - cmu) * stride;
 }
 
-#define NRC 16
-
-// One thread per (coarse site, row i); ny = 256 / nc coarse sites per
-// workgroup.  For each direction the neighbours' vectors (rc right-hand sides)
-// are staged in LDS; the operator column D[j][i] is read coalesced from the
-// column-major copy and used for all staged right-hand sides.
-template <typename S, typename R>
-__global__ __launch_bounds__(256) void k_coarse_valu(Geo g, int nc, const S* __restrict__ Dt, const S* __restrict__ in,
-                                                     S* __restrict__ out, int nrhs, int gamma5, int rc) {
-    extern __shared__ char shraw[];
-    cx<R>* VS = (cx<R>*)shraw;   // [ny][nc][rc]
-    const int ny = 256 / nc;
-    const int ysub = threadIdx.x / nc, i = threadIdx.x - ysub * nc;
-    const int y = blockIdx.x * ny + ysub;
-    const bool act = ysub < ny && y < g.V1;
-    const size_t V1 = g.V1;
-    const R sg = (gamma5 && i >= nc / 2) ? (R)-1 : (R)1;
-    for (int r0 = 0; r0 < nrhs; r0 += rc) {
-        const int nr = nrhs - r0 < rc ? nrhs - r0 : rc;
-        cx<R> acc[NRC];
+// FP64 / FP32 on the matrix cores (v_mfma_*_16x16x4).
+// grid: (V1, ceil(nrhs/16)); block: 64 * ceil(nc/16) threads, wave w owns
+// output rows 16w..16w+15 and the 16 right-hand sides of blockIdx.y.
+// Operator: planar copy P[y][dir][0 = re, 1 = im][i][j] in precision R.
+// In an MFMA lane (lr, lq) supplies A[row lr][k] and B[k][col lr] for one k
+// of four; over four successive MFMAs the lane walks k = k0 + 4 lq + s,
+// s = 0..3, so that its four operator entries and its four vector entries
+// are each one contiguous load (the sum over k does not care which lane
+// supplies which k as long as A and B agree).  VEC: nc % 4 == 0, so those
+// loads are aligned and either wholly inside or wholly outside the matrix.
+template <typename R, bool VEC>
+__global__ __launch_bounds__(512) void k_coarse_mfma(Geo g, int nc, const R* __restrict__ P,
+                                                     const typename VT<R>::c2* __restrict__ in,
+                                                     typename VT<R>::c2* __restrict__ out, int nrhs, int gamma5) {
+    typedef typename VT<R>::c2 C2;
+    typedef typename Mfma<R>::v4 V4;
+    const int y = blockIdx.x;
+    const int n0 = blockIdx.y * 16;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int m0 = w * 16;
+    const int lr = lane & 15, lq = lane >> 4;
+    const size_t V1 = g.V1, nn = (size_t)nc * nc;
+    const int n = n0 + lr, m = m0 + lr;
+    const bool nok = n < nrhs, mok = m < nc;
+    V4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+    for (int dir = 0; dir < 9; ++dir) {
+        const int z = coarse_nbr(g, y, dir);
+        const R* Pr = P + ((size_t)y * 9 + dir) * 2 * nn + (size_t)(mok ? m : 0) * nc;
+        const R* Pi = Pr + nn;
+        const C2* v = in + ((size_t)(nok ? n : 0) * V1 + z) * nc;
+        for (int k0 = 0; k0 < nc; k0 += 16) {
+            const int kb = k0 + 4 * lq;
+            R ar[4], ai[4], br[4], bi[4];
+            if (VEC) {
+                const bool ka = kb < nc;
+                if (ka && mok) {
+                    ld4(Pr + kb, ar);
+                    ld4(Pi + kb, ai);
+                } else {
 #pragma unroll
-        for (int q = 0; q < NRC; ++q) acc[q] = cmk((R)0, (R)0);
-        for (int dir = 0; dir < 9; ++dir) {
-            __syncthreads();
-            for (int e = threadIdx.x; e < ny * nc * nr; e += blockDim.x) {
-                const int r = e % nr, t = e / nr, j = t % nc, ys = t / nc;
-                const int yy = blockIdx.x * ny + ys;
-                VS[(ys * nc + j) * rc + r] = yy < g.V1
-                    ? ldc<S, R>(in + ((size_t)(r0 + r) * V1 + coarse_nbr(g, yy, dir)) * nc + j) : cmk((R)0, (R)0);
-            }
-            __syncthreads();
-            if (act) {
-                const S* dcol = Dt + ((size_t)y * 9 + dir) * nc * nc + i;
-                const cx<R>* vs = VS + (size_t)ysub * nc * rc;
-                for (int j = 0; j < nc; ++j) {
-                    const cx<R> d = ldc<S, R>(dcol + (size_t)j * nc);
+                    for (int s = 0; s < 4; ++s) ar[s] = ai[s] = (R)0;
+                }
+                if (ka && nok) {
+                    ld4c(v + kb, br, bi);
+                } else {
 #pragma unroll
-                    for (int q = 0; q < NRC; ++q)
-                        if (q < nr) cmac(acc[q], d, vs[j * rc + q]);
+                    for (int s = 0; s < 4; ++s) br[s] = bi[s] = (R)0;
+                }
+            } else {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const bool ok = kb + s < nc;
+                    ar[s] = (ok && mok) ? Pr[kb + s] : (R)0;
+                    ai[s] = (ok && mok) ? Pi[kb + s] : (R)0;
+                    C2 x = (ok && nok) ? v[kb + s] : C2{0, 0};
+                    br[s] = x.x;
+                    bi[s] = x.y;
                 }
             }
-        }
-        if (act) {
 #pragma unroll
-            for (int q = 0; q < NRC; ++q)
-                if (q < nr) stc<S, R>(out + ((size_t)(r0 + q) * V1 + y) * nc + i, sg * acc[q]);
+            for (int s = 0; s < 4; ++s) {
+                cr = Mfma<R>::mac(ar[s], br[s], cr);
+                cr = Mfma<R>::mac(-ai[s], bi[s], cr);
+                ci = Mfma<R>::mac(ar[s], bi[s], ci);
+                ci = Mfma<R>::mac(ai[s], br[s], ci);
+            }
+        }
+    }
+    // register t of this lane holds C[row(lq, t)][col lr]
+    if (nok) {
+        C2* o = out + ((size_t)n * V1 + y) * nc;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int row = m0 + Mfma<R>::row(lq, t);
+            if (row < nc) {
+                const R sg = (gamma5 && row >= nc / 2) ? (R)-1 : (R)1;
+                o[row] = C2{sg * cr[t], sg * ci[t]};
+            }
         }
     }
 }
@@ -177,20 +209,25 @@ int mg_coarse_apply(mglma_ctx* c, int prec, int gamma5, const void* in, void* ou
         HIP_TRY(hipGetLastError());
         return MGLMA_OK;
     }
-    const int ny = 256 / nc;
-    dim3 grid((g.V1 + ny - 1) / ny);
-    const size_t cb = prec == MGLMA_F64 ? 16 : 8;
-    int rc = (int)((48 * 1024) / ((size_t)ny * nc * cb));
-    if (rc > NRC) rc = NRC;
-    const size_t shb = (size_t)ny * nc * rc * cb;
+    dim3 grid(g.V1, (nrhs + 15) / 16);
+    dim3 block(64 * ((nc + 15) / 16));
+    const bool vec = nc % 4 == 0;
     switch (prec) {
         case MGLMA_F64:
-            hipLaunchKernelGGL((k_coarse_valu<double2, double>), grid, dim3(256), shb, c->stream, g, nc, c->D64t,
-                               (const double2*)in, (double2*)out, nrhs, gamma5, rc);
+            if (vec)
+                hipLaunchKernelGGL((k_coarse_mfma<double, true>), grid, block, 0, c->stream, g, nc, c->D64p,
+                                   (const double2*)in, (double2*)out, nrhs, gamma5);
+            else
+                hipLaunchKernelGGL((k_coarse_mfma<double, false>), grid, block, 0, c->stream, g, nc, c->D64p,
+                                   (const double2*)in, (double2*)out, nrhs, gamma5);
             break;
         case MGLMA_F32:
-            hipLaunchKernelGGL((k_coarse_valu<float2, float>), grid, dim3(256), shb, c->stream, g, nc, c->D32,
-                               (const float2*)in, (float2*)out, nrhs, gamma5, rc);
+            if (vec)
+                hipLaunchKernelGGL((k_coarse_mfma<float, true>), grid, block, 0, c->stream, g, nc, c->D32p,
+                                   (const float2*)in, (float2*)out, nrhs, gamma5);
+            else
+                hipLaunchKernelGGL((k_coarse_mfma<float, false>), grid, block, 0, c->stream, g, nc, c->D32p,
+                                   (const float2*)in, (float2*)out, nrhs, gamma5);
             break;
         default: return MGLMA_ERR_ARG;
     }

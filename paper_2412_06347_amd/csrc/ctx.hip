@@ -173,8 +173,8 @@ void mg_free_subspace(mglma_ctx* c) {
     mg_free(c, c->B32, nb * 8); c->B32 = nullptr;
     size_t nd = (size_t)g.V1 * 9 * c->nc * c->nc;
     mg_free(c, c->D64, nd * 16); c->D64 = nullptr;
-    mg_free(c, c->D64t, nd * 16); c->D64t = nullptr;
-    mg_free(c, c->D32, nd * 8); c->D32 = nullptr;
+    mg_free(c, c->D64p, nd * 16); c->D64p = nullptr;
+    mg_free(c, c->D32p, nd * 8); c->D32p = nullptr;
     mg_free(c, c->Dbf, nd * 4); c->Dbf = nullptr;
     mg_free(c, c->G1, (size_t)g.V1 * g.b[0] * 3 * c->Nv * c->Nv * 16); c->G1 = nullptr;
     c->have_subspace = false;
@@ -199,7 +199,6 @@ extern "C" void mglma_destroy(mglma_ctx* c) {
     free_gauge(c);
     for (int i = 0; i < 32; ++i) mg_free(c, c->scr[i].ptr, c->scr[i].bytes);
     mg_free(c, c->red_part, c->red_part_n * sizeof(double));
-    mg_free(c, c->red_cnt, c->red_cnt_n * sizeof(unsigned));
     if (c->hbuf) (void)hipHostFree(c->hbuf);
     delete c;
 }

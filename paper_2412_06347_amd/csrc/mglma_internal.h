@@ -173,6 +173,54 @@ template <typename S, typename R> __device__ __forceinline__ void stc(S* p, cx<R
 }
 
 // ---------------------------------------------------------------------------
+// matrix-core helpers (FP32 / FP64 16x16x4 MFMA) and aligned 4-wide loads
+// ---------------------------------------------------------------------------
+template <typename R> struct VT;
+template <> struct VT<float> { typedef float2 c2; };
+template <> struct VT<double> { typedef double2 c2; };
+
+// four consecutive reals / complex numbers from 16-byte aligned addresses
+__device__ __forceinline__ void ld4(const float* p, float (&a)[4]) {
+    float4 q = *(const float4*)p;
+    a[0] = q.x; a[1] = q.y; a[2] = q.z; a[3] = q.w;
+}
+__device__ __forceinline__ void ld4(const double* p, double (&a)[4]) {
+    double2 q0 = *(const double2*)p, q1 = *(const double2*)(p + 2);
+    a[0] = q0.x; a[1] = q0.y; a[2] = q1.x; a[3] = q1.y;
+}
+__device__ __forceinline__ void ld4c(const float2* p, float (&re)[4], float (&im)[4]) {
+    float4 q0 = *(const float4*)p, q1 = *(const float4*)(p + 2);
+    re[0] = q0.x; im[0] = q0.y; re[1] = q0.z; im[1] = q0.w;
+    re[2] = q1.x; im[2] = q1.y; re[3] = q1.z; im[3] = q1.w;
+}
+__device__ __forceinline__ void ld4c(const double2* p, double (&re)[4], double (&im)[4]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        double2 q = p[s];
+        re[s] = q.x; im[s] = q.y;
+    }
+}
+
+// In both, lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; result
+// register t of lane l is D[row(l / 16, t)][l % 16], and the two differ in
+// row(): 4 q + t for FP32, q + 4 t for FP64 (measured on gfx950).
+template <typename R> struct Mfma;
+template <> struct Mfma<float> {
+    static __device__ __forceinline__ int row(int q, int t) { return 4 * q + t; }
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 mac(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Mfma<double> {
+    static __device__ __forceinline__ int row(int q, int t) { return q + 4 * t; }
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 mac(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+
+// ---------------------------------------------------------------------------
 // the context
 // ---------------------------------------------------------------------------
 struct Scratch {
@@ -195,7 +243,7 @@ struct mglma_ctx {
     // subspace: basis [V1][2][Nv][6][Vb], coarse operator [V1][9][nc][nc]
     int Nv = 0, nc = 0;
     double2* B64 = nullptr; float2* B32 = nullptr;
-    double2* D64 = nullptr; double2* D64t = nullptr; float2* D32 = nullptr;   // D32 column-major
+    double2* D64 = nullptr; double* D64p = nullptr; float* D32p = nullptr;   // planar [blk][re/im][i][j] copies
     bf16_t* Dbf = nullptr;       // [V1][9][2][nc][nc] planar re/im bfloat16
     double2* G1 = nullptr;       // coarse gammas [V1][b0][3][Nv][Nv] (alpha=0 rows, alpha=1 cols)
     bool have_subspace = false;
@@ -210,7 +258,7 @@ struct mglma_ctx {
     // reusable scratch (grown on demand) and reduction buffers
     Scratch scr[32];
     double* red_part = nullptr; size_t red_part_n = 0;
-    unsigned* red_cnt = nullptr; size_t red_cnt_n = 0;
+
     double* hbuf = nullptr; size_t hbuf_n = 0;     // pinned host staging
 
     size_t resident = 0;

@@ -229,6 +229,103 @@ __global__ __launch_bounds__(256) void k_restrict(Geo g, int Nv, const S* __rest
     }
 }
 
+// Matrix-core restrictor (v_mfma_*_16x16x4), the same sum as k_restrict.
+// grid (V1, 2 chiralities, ceil(nrhs/16)); 256 threads.  Per (block,
+// chirality) the product is (Nv x 6Vb)(6Vb x 16 rhs): rows p in tiles of 16
+// (at most RMT tiles), the 6Vb columns in chunks of 16 dealt round-robin to
+// the four wavefronts, whose partial tiles are added in LDS in wave order.
+// In an MFMA, lane (lr, lq) takes k = chunk + 4 lq + s for s = 0..3, so its
+// four basis entries and its four field entries are contiguous (needs
+// Vb % 4 == 0 and 16-byte aligned fields, checked by the launcher).
+#define RMT 4
+template <typename R>
+__global__ __launch_bounds__(256) void k_restrict_mfma(Geo g, int Nv, const typename VT<R>::c2* __restrict__ B,
+                                                       const typename VT<R>::c2* __restrict__ fine,
+                                                       typename VT<R>::c2* __restrict__ coarse, int nrhs) {
+    typedef typename VT<R>::c2 C2;
+    typedef typename Mfma<R>::v4 V4;
+    extern __shared__ char shraw[];
+    R* red = (R*)shraw;                       // [4 waves][ntr tiles][re, im][64 lanes][4]
+    const int y = blockIdx.x, a = blockIdx.y, n0 = blockIdx.z * 16;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane & 15, lq = lane >> 4;
+    const int Vb = g.Vb, K = 6 * Vb, nc = 2 * Nv;
+    const int ntr = (Nv + 15) / 16;
+    const size_t V = g.V;
+    const int n = n0 + lr;
+    const bool nok = n < nrhs;
+    V4 cr[RMT], ci[RMT];
+#pragma unroll
+    for (int t = 0; t < RMT; ++t) {
+        cr[t] = V4{0, 0, 0, 0};
+        ci[t] = V4{0, 0, 0, 0};
+    }
+    const C2* Bya = B + (size_t)(y * 2 + a) * Nv * K;
+    const C2* F = fine + ((size_t)(nok ? n : 0) * 12 + 6 * a) * V + (size_t)y * Vb;
+    const int nchunk = (K + 15) / 16;
+    for (int q = w; q < nchunk; q += 4) {
+        const int kb = q * 16 + 4 * lq;
+        const bool kok = kb < K;
+        R fr[4], fi[4];
+        if (kok && nok) {
+            const int scl = kb / Vb, l = kb - scl * Vb;
+            ld4c(F + (size_t)scl * V + l, fr, fi);
+        } else {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) fr[s] = fi[s] = (R)0;
+        }
+#pragma unroll
+        for (int t = 0; t < RMT; ++t) {
+            if (t < ntr) {
+                const int p = t * 16 + lr;
+                R br[4], bi[4];
+                if (kok && p < Nv) {
+                    ld4c(Bya + (size_t)p * K + kb, br, bi);
+                } else {
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) br[s] = bi[s] = (R)0;
+                }
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    // conj(b) f
+                    cr[t] = Mfma<R>::mac(br[s], fr[s], cr[t]);
+                    cr[t] = Mfma<R>::mac(bi[s], fi[s], cr[t]);
+                    ci[t] = Mfma<R>::mac(br[s], fi[s], ci[t]);
+                    ci[t] = Mfma<R>::mac(-bi[s], fr[s], ci[t]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < RMT; ++t) {
+        if (t < ntr) {
+            R* o = red + (((size_t)w * ntr + t) * 2) * 256 + lane * 4;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                o[j] = cr[t][j];
+                o[256 + j] = ci[t][j];
+            }
+        }
+    }
+    __syncthreads();
+    // thread -> (lane l, register j): output row 16 t + row(l / 16, j), rhs n0 + l % 16
+    const int l = threadIdx.x & 63, j = threadIdx.x >> 6;
+    const int nn = n0 + (l & 15);
+    for (int t = 0; t < ntr; ++t) {
+        const int p = t * 16 + Mfma<R>::row(l >> 4, j);
+        if (p < Nv && nn < nrhs) {
+            R sr = 0, si = 0;
+#pragma unroll
+            for (int ww = 0; ww < 4; ++ww) {
+                const R* o = red + (((size_t)ww * ntr + t) * 2) * 256 + l * 4 + j;
+                sr += o[0];
+                si += o[256];
+            }
+            coarse[((size_t)nn * g.V1 + y) * nc + a * Nv + p] = C2{sr, si};
+        }
+    }
+}
+
 // fine[r][6a + s'col][i] = sum_c B[y][a][c][s'col][l] coarse[r][y][a*Nv + c]
 // One thread per fine site; the coarse vectors of the workgroup's blocks are
 // staged in LDS (RMAXR right-hand sides per pass).
@@ -278,9 +375,23 @@ __global__ __launch_bounds__(256) void k_prolong(Geo g, int Nv, const S* __restr
 int mg_restrict(mglma_ctx* c, int prec, const void* fine, void* coarse, int nrhs) {
     if (nrhs <= 0) return MGLMA_OK;
     const Geo& g = c->geo;
-    // LDS budget: 32 KiB of basis rows, 24 KiB of field values
     const int nc = c->nc;
+    if (prec != MGLMA_F64 && prec != MGLMA_F32) return MGLMA_ERR_ARG;
     const size_t cb = prec == MGLMA_F64 ? 16 : 8;
+    if (g.Vb % 4 == 0 && c->Nv <= 16 * RMT && (uintptr_t)fine % 16 == 0) {
+        dim3 grid(g.V1, 2, (nrhs + 15) / 16);
+        const size_t shb = (size_t)4 * ((c->Nv + 15) / 16) * 2 * 256 * (cb / 2);
+        if (prec == MGLMA_F64)
+            hipLaunchKernelGGL(k_restrict_mfma<double>, grid, dim3(256), shb, c->stream, g, c->Nv, c->B64,
+                               (const double2*)fine, (double2*)coarse, nrhs);
+        else
+            hipLaunchKernelGGL(k_restrict_mfma<float>, grid, dim3(256), shb, c->stream, g, c->Nv, c->B32,
+                               (const float2*)fine, (float2*)coarse, nrhs);
+        HIP_TRY(hipGetLastError());
+        return MGLMA_OK;
+    }
+    // general block shapes: LDS-staged VALU kernel.
+    // LDS budget: 32 KiB of basis rows, 24 KiB of field values
     int lc = (int)(32768 / (6 * nc * cb));
     if (lc > 16) lc = 16;
     if (lc > g.Vb) lc = g.Vb;
@@ -289,17 +400,12 @@ int mg_restrict(mglma_ctx* c, int prec, const void* fine, void* coarse, int nrhs
     if (rc > RMAXR) rc = RMAXR;
     if (rc < 1) return MGLMA_ERR_SHAPE;
     const size_t shb = ((size_t)nc * (6 * lc + 1) + (size_t)lc * 12 * rc) * cb;
-    switch (prec) {
-        case MGLMA_F64:
-            hipLaunchKernelGGL((k_restrict<double2, double>), dim3(g.V1), dim3(256), shb, c->stream, g, c->Nv, c->B64,
-                               (const double2*)fine, (double2*)coarse, nrhs, lc, rc);
-            break;
-        case MGLMA_F32:
-            hipLaunchKernelGGL((k_restrict<float2, float>), dim3(g.V1), dim3(256), shb, c->stream, g, c->Nv, c->B32,
-                               (const float2*)fine, (float2*)coarse, nrhs, lc, rc);
-            break;
-        default: return MGLMA_ERR_ARG;
-    }
+    if (prec == MGLMA_F64)
+        hipLaunchKernelGGL((k_restrict<double2, double>), dim3(g.V1), dim3(256), shb, c->stream, g, c->Nv, c->B64,
+                           (const double2*)fine, (double2*)coarse, nrhs, lc, rc);
+    else
+        hipLaunchKernelGGL((k_restrict<float2, float>), dim3(g.V1), dim3(256), shb, c->stream, g, c->Nv, c->B32,
+                           (const float2*)fine, (float2*)coarse, nrhs, lc, rc);
     HIP_TRY(hipGetLastError());
     return MGLMA_OK;
 }
@@ -344,24 +450,25 @@ extern "C" int mglma_prolong(mglma_ctx* c, int prec, const void* coarse, void* f
 // ---------------------------------------------------------------------------
 // Galerkin operator
 // ---------------------------------------------------------------------------
-__global__ void k_op_copies(size_t nblk, int nc, const double2* __restrict__ D, double2* __restrict__ D64t,
-                            float2* __restrict__ D32t, bf16_t* __restrict__ Dbf) {
-    // D64t, D32t: column-major copies [blk][j][i]; Dbf[blk][0 = re, 1 = im][i][j]
+__global__ void k_op_copies(size_t nblk, int nc, const double2* __restrict__ D, double* __restrict__ D64p,
+                            float* __restrict__ D32p, bf16_t* __restrict__ Dbf) {
+    // planar copies [blk][0 = re, 1 = im][i][j] in FP64, FP32 and BF16
     size_t n = nblk * nc * nc;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
         double2 v = D[e];
         size_t blk = e / ((size_t)nc * nc), ij = e % ((size_t)nc * nc);
-        size_t i = ij / nc, j = ij % nc;
-        size_t et = blk * nc * nc + j * nc + i;
-        D64t[et] = v;
-        D32t[et] = make_float2((float)v.x, (float)v.y);
+        const size_t er = (blk * 2 + 0) * nc * nc + ij, ei = er + (size_t)nc * nc;
+        D64p[er] = v.x;
+        D64p[ei] = v.y;
         float fr = (float)v.x, fi = (float)v.y;
+        D32p[er] = fr;
+        D32p[ei] = fi;
         // round to nearest even
         uint32_t ur = __float_as_uint(fr), ui = __float_as_uint(fi);
         ur += 0x7fff + ((ur >> 16) & 1);
         ui += 0x7fff + ((ui >> 16) & 1);
-        Dbf[(blk * 2 + 0) * nc * nc + ij] = (bf16_t)(ur >> 16);
-        Dbf[(blk * 2 + 1) * nc * nc + ij] = (bf16_t)(ui >> 16);
+        Dbf[er] = (bf16_t)(ur >> 16);
+        Dbf[ei] = (bf16_t)(ui >> 16);
     }
 }
 
@@ -438,8 +545,8 @@ extern "C" int mglma_build_subspace(mglma_ctx* c, int Nv, const double* tv) {
     MG_TRY(mg_malloc(c, (void**)&c->B64, nb * 16));
     MG_TRY(mg_malloc(c, (void**)&c->B32, nb * 8));
     MG_TRY(mg_malloc(c, (void**)&c->D64, nd * 16));
-    MG_TRY(mg_malloc(c, (void**)&c->D64t, nd * 16));
-    MG_TRY(mg_malloc(c, (void**)&c->D32, nd * 8));
+    MG_TRY(mg_malloc(c, (void**)&c->D64p, nd * 16));
+    MG_TRY(mg_malloc(c, (void**)&c->D32p, nd * 8));
     MG_TRY(mg_malloc(c, (void**)&c->Dbf, nd * 4));
     MG_TRY(mg_malloc(c, (void**)&c->G1, (size_t)g.V1 * g.b[0] * 3 * Nv * Nv * 16));
 
@@ -464,8 +571,8 @@ extern "C" int mglma_build_subspace(mglma_ctx* c, int Nv, const double* tv) {
     MG_TRY(mg_convert(c, MGLMA_F64, c->B64, MGLMA_F32, c->B32, nb, 1, nullptr, 0));
 
     // 3. Galerkin operator, block by block (the column-major FP64 copy is the scratch of the pieces)
-    MG_TRY(mg_galerkin(c, c->D64t));
-    hipLaunchKernelGGL(k_op_copies, dim3(2048), dim3(256), 0, c->stream, (size_t)g.V1 * 9, nc, c->D64, c->D64t, c->D32,
+    MG_TRY(mg_galerkin(c, (double2*)c->D64p));
+    hipLaunchKernelGGL(k_op_copies, dim3(2048), dim3(256), 0, c->stream, (size_t)g.V1 * 9, nc, c->D64, c->D64p, c->D32p,
                        c->Dbf);
     HIP_TRY(hipGetLastError());
 

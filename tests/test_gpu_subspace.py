@@ -13,10 +13,11 @@ CASES = [
     ((4, 4, 4, 4), (2, 2, 2, 2), 8),        # the 4^4 workload: 2^4 blocks, 8 test vectors
     ((6, 4, 6, 2), (3, 2, 3, 1), 3),        # odd blocks, coarse extents 2/3, nc = 6
     ((8, 8, 4, 4), (4, 4, 4, 4), 8),        # 4^4 blocks, coarse extent 1 in space
+    ((4, 4, 4, 8), (2, 2, 2, 4), 20),       # nc = 40: partial 16-row / 16-column matrix-core tiles
 ]
 
 
-@pytest.fixture(scope="module", params=CASES, ids=["4^4", "odd", "b4"])
+@pytest.fixture(scope="module", params=CASES, ids=["4^4", "odd", "b4", "nc40"])
 def pair(request):
     L, b, Nv = request.param
     return Pair(L, b, Nv)
@@ -58,7 +59,7 @@ def test_coarse_gammas_parity(pair):
 def test_restrict_prolong_parity(pair, prec, tol):
     import torch
     from paper_2412_06347_amd import mglma
-    n = 5
+    n = 19    # more than one 16-wide tile of right-hand sides
     psi = synth.gaussian_fields(n, pair.L, 77)
     ref_c = pair.B.restrict(pair.lat(psi))
     x = pair.fine_dev(psi, prec)
