@@ -123,6 +123,30 @@ class Pipeline:
         return stats, levels
 
 
+def dslash_alg_bytes(V, nrhs, b):
+    """Algorithmic HBM bytes of one Wilson-clover apply on nrhs right-hand
+    sides with b-byte reals: per site the four links (4 x 18 reals) and the
+    clover term (2 x 36 reals) once, and per right-hand side one spinor read
+    and one written (2 x 24 reals)."""
+    return V * (144 + 48 * nrhs) * b
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of the FP16 12-RHS apply from the committed
+    hardware-counter summary, or None when the kernel source has changed
+    since the counters were taken."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", "dslash_traffic_%s.json" % workload)
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(here, "paper_2412_06347_amd", "csrc", "dslash.hip"), "rb").read()
+    if hashlib.sha256(src).hexdigest() != rec.get("dslash_source_sha256"):
+        return None
+    return rec.get("f16_12rhs_hbm_bytes_per_launch")
+
+
 def kernel_time(torch, fn, reps, stream):
     """Average duration of fn() in ms, timed with HIP events on `stream`."""
     e0 = torch.cuda.Event(enable_timing=True)
@@ -137,12 +161,22 @@ def kernel_time(torch, fn, reps, stream):
     return e0.elapsed_time(e1) / reps
 
 
-def cpu_baseline(wl, budget_s=20.0):
+def plain_gcr_iterations(P, mglma):
+    """Iterations the restarted GCR(16) without preconditioner needs for the
+    first point-source system to reach 1e-10, run in FP64 on the GPU (an
+    algorithmic count, used to scale the host timing of the oracle)."""
+    x = P.ctx.fine(1)
+    p = mglma.default_params(tol=1e-10, max_outer=1, max_inner=5000, gcr_m=16, inner_tol=1e-10, use_mg=0,
+                             inner=mglma.F64, smoother=mglma.F64, coarse=mglma.F64)
+    rc, st = P.ctx.solve(P.src[:1].contiguous(), x, p, raise_on_error=False)
+    return int(st[0]["inner"]), float(st[0]["true_rel_res"])
+
+
+def cpu_baseline(wl, n_iter_needed, budget_s=20.0):
     """The oracle (numpy FP64, one thread) on a bounded sample of the same
-    workload: the oracle's restarted GCR(16) on one point-source system of the
-    same lattice, stopped after about `budget_s` seconds; the time of a full
-    solve to 1e-10 is extrapolated from the time per iteration and the
-    observed residual reduction rate."""
+    workload: its restarted GCR(16) on one point-source system of the same
+    lattice for about `budget_s` seconds; solves/s = 1 / (time per iteration
+    x the iterations that GCR(16) needs for this system to reach 1e-10)."""
     from threadpoolctl import threadpool_limits
     from oracle import dirac, estimators, solvers
     from paper_2412_06347_amd import synth
@@ -158,17 +192,13 @@ def cpu_baseline(wl, budget_s=20.0):
         t0 = time.time()
         x, it, res = solvers.gcr(D.M, b, tol=1e-10, m=16, max_iter=n_it)
         t = time.time() - t0
-    res = float(res[0])
     t_it = t / max(it, 1)
-    rate = np.log(res) / max(it, 1)
-    iters_needed = np.log(1e-10) / rate if rate < 0 else float("inf")
-    return dict(value=float(1.0 / (t_it * iters_needed)), unit="solves/s", cores=1, kind="oracle",
+    cpu = open("/proc/cpuinfo").read().split("model name")[1].split(":")[1].split("\n")[0].strip()
+    return dict(value=float(1.0 / (t_it * n_iter_needed)), unit="solves/s", cores=1, kind="oracle",
                 sample="numpy FP64 oracle on 1 thread (%s): %d iterations of its restarted GCR(16) on one "
-                       "point-source system of the %s lattice took %.1f s and reduced the residual to %.2e; the "
-                       "full solve to 1e-10 is extrapolated at that rate (%.0f iterations)" % (
-                           os.uname().nodename and (open("/proc/cpuinfo").read().split("model name")[1]
-                                                    .split(":")[1].split("\n")[0].strip()),
-                           it, "x".join(map(str, L)), t, res, iters_needed))
+                       "point-source system of the %s lattice took %.1f s (%.2f s per iteration, residual %.2e); "
+                       "one solve to 1e-10 = %d iterations of the same GCR(16) (count from an FP64 run to "
+                       "convergence)" % (cpu, it, "x".join(map(str, L)), t, t_it, float(res[0]), n_iter_needed))
 
 
 def main():
@@ -204,13 +234,14 @@ def main():
         U = torch.from_numpy(synth.gauge_field(L, wl["eps"], wl["seed"]).view(np.float64)).cuda()
         ctx = mglma.Context(L, wl["block"], wl["kappa"], wl["csw"])
         ctx.load_gauge(U)
-        for prec, nr in [(mglma.F32, 12), (mglma.F64, 1), (mglma.F32, 1), (mglma.F16, 1)]:
+        for prec, nr in [(mglma.F16, 12), (mglma.F32, 12), (mglma.F64, 1), (mglma.F32, 1), (mglma.F16, 1)]:
             x, y = ctx.fine(nr, prec), ctx.fine(nr, prec)
-            x.normal_()
+            x.copy_(torch.randn(x.shape, device="cuda").to(x.dtype))
             for _ in range(5):
                 ctx.apply_D(x, y, prec)
         torch.cuda.synchronize()
-        print(json.dumps({"dslash_only": True, "V": ctx.V, "launches": "5 x (f32 12rhs, f64 1rhs, f32 1rhs, f16 1rhs)"}))
+        print(json.dumps({"dslash_only": True, "V": ctx.V,
+                          "launches": "5 x (f16 12rhs, f32 12rhs, f64 1rhs, f32 1rhs, f16 1rhs)"}))
         return
     P = Pipeline(wl)
     stream = torch.cuda.current_stream()
@@ -244,41 +275,37 @@ def main():
                     corr_L0_rel_diff_vs_mixed=float(np.linalg.norm(lv64["L0"] - levels["L0"]) /
                                                     np.linalg.norm(lv64["L0"])))
         log("fp64: %.3f s/step" % t64)
-    # dominant kernel: FP32 Wilson-clover apply on the 12-RHS batch, HIP events on the library's stream
+    # Dominant kernel of the step: the FP16 Wilson-clover apply of the MR
+    # smoother on the 12-RHS batch.  HIP events on the library's stream.
     ctx = P.ctx
     V = ctx.V
-    x32 = ctx.fine(12, mglma.F32)
-    y32 = ctx.fine(12, mglma.F32)
-    x32.normal_()
-    ms32 = kernel_time(torch, lambda: ctx.apply_D(x32, y32, mglma.F32), 20, stream)
     nr = 12
-    alg_bytes_32 = V * (144 + 48 * nr) * 4
-    ach = alg_bytes_32 / (ms32 * 1e-3) / 1e9
-    x64 = ctx.fine(1, mglma.F64)
-    y64 = ctx.fine(1, mglma.F64)
-    x64.normal_()
-    ms64 = kernel_time(torch, lambda: ctx.apply_D(x64, y64, mglma.F64), 20, stream)
-    x16 = ctx.fine(1, mglma.F16)
-    y16 = ctx.fine(1, mglma.F16)
-    x16.normal_()
-    ms16 = kernel_time(torch, lambda: ctx.apply_D(x16, y16, mglma.F16), 20, stream)
-    x1 = ctx.fine(1, mglma.F32)
-    y1 = ctx.fine(1, mglma.F32)
-    x1.normal_()
-    ms1 = kernel_time(torch, lambda: ctx.apply_D(x1, y1, mglma.F32), 20, stream)
+
+    def apply_ms(prec, nrhs):
+        x = ctx.fine(nrhs, prec)
+        y = ctx.fine(nrhs, prec)
+        x.copy_(torch.randn(x.shape, device="cuda").to(x.dtype))
+        return kernel_time(torch, lambda: ctx.apply_D(x, y, prec), 20, stream)
+
+    ms16 = apply_ms(mglma.F16, nr)
+    ms32 = apply_ms(mglma.F32, nr)
+    ms64_1 = apply_ms(mglma.F64, 1)
+    ms32_1 = apply_ms(mglma.F32, 1)
+    ms16_1 = apply_ms(mglma.F16, 1)
     dslash_gbs = {
-        "f64_1rhs": V * 192 * 8 / (ms64 * 1e-3) / 1e9,
-        "f32_1rhs": V * 192 * 4 / (ms1 * 1e-3) / 1e9,
-        "f16_1rhs": V * 192 * 2 / (ms16 * 1e-3) / 1e9,
-        "f32_12rhs": ach,
+        "f16_12rhs": dslash_alg_bytes(V, nr, 2) / (ms16 * 1e-3) / 1e9,
+        "f32_12rhs": dslash_alg_bytes(V, nr, 4) / (ms32 * 1e-3) / 1e9,
+        "f64_1rhs": dslash_alg_bytes(V, 1, 8) / (ms64_1 * 1e-3) / 1e9,
+        "f32_1rhs": dslash_alg_bytes(V, 1, 4) / (ms32_1 * 1e-3) / 1e9,
+        "f16_1rhs": dslash_alg_bytes(V, 1, 2) / (ms16_1 * 1e-3) / 1e9,
     }
-    traffic = None
-    tf = os.environ.get("MGLMA_TRAFFIC_JSON")
-    if tf and os.path.exists(tf):
-        traffic = json.load(open(tf)).get("dslash_f32_12rhs_bytes")
+    ach = dslash_gbs["f16_12rhs"]
+    traffic = measured_traffic(args.workload)
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(wl, args.cpu_budget)
+        n_plain, res_plain = plain_gcr_iterations(P, mglma)
+        log("plain FP64 GCR(16): %d iterations to %.2e" % (n_plain, res_plain))
+        cpu = cpu_baseline(wl, n_plain, args.cpu_budget)
     L = wl["L"]
     line = {
         "metric": "MG solves/s to rel. residual 1e-10 (mixed vs FP64); Dslash HBM GB/s; p50/p99 latency",
@@ -303,9 +330,10 @@ def main():
         "fp64_path": fp64,
         "speedup_mixed_vs_fp64": (value / fp64["solves_per_s"]) if fp64 else None,
         "dslash_GBs": dslash_gbs,
-        "roofline": {"bound": "hbm", "kernel": "k_dslash<float2,float2,float> (12 RHS)", "achieved": ach,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                     "traffic": traffic, "avg_ms": ms32},
+        "roofline": {"bound": "hbm", "kernel": "k_dslash_multi<__half2,__half2,float,2> (FP16, 12 RHS)",
+                     "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                     "traffic": traffic, "avg_ms": ms16,
+                     "alg_bytes_per_launch": dslash_alg_bytes(V, nr, 2)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
