@@ -513,6 +513,95 @@ __global__ __launch_bounds__(256) void k_coarse_gamma(Geo g, int Nv, const doubl
     }
 }
 
+// Matrix-core version (v_mfma_f64_16x16x4), one workgroup per (block, time
+// slice).  With O_{s s'}[c][d] = sum_{col, l in slice} conj(phi_{0c}(s, col))
+// phi_{1d}(s', col) for the four spin pairs (one per wavefront, a GEMM of
+// Nv x 3 n_s by 3 n_s x Nv), gamma5 gamma_k being monomial gives
+// G_k = sum_s coef_k(s) O_{s, pi_k(s) - 2}.  Lane (lr, lq) takes k runs of
+// four consecutive sites, so its operand loads are contiguous (needs the slice
+// size n_s % 4 == 0, Nv <= 32).
+__global__ __launch_bounds__(256) void k_coarse_gamma_mfma(Geo g, int Nv, const double2* __restrict__ B,
+                                                           double2* __restrict__ G1) {
+    typedef Mfma<double>::v4 V4;
+    extern __shared__ double2 Os[];                    // [4 spin pairs][Nv][Nv]
+    const int y = blockIdx.x / g.b[0], t = blockIdx.x % g.b[0];
+    const int Vb = g.Vb, ns = Vb / g.b[0];
+    const size_t K6 = (size_t)6 * Vb;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lq = lane >> 4;
+    const int s0 = w >> 1, s1 = w & 1;                 // spin inside chirality 0 / 1
+    const int ntr = (Nv + 15) / 16;
+    const double2* P0 = B + ((size_t)y * 2 + 0) * Nv * K6 + (size_t)t * ns;
+    const double2* P1 = B + ((size_t)y * 2 + 1) * Nv * K6 + (size_t)t * ns;
+    V4 cr[2][2], ci[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            cr[a][b] = V4{0, 0, 0, 0};
+            ci[a][b] = V4{0, 0, 0, 0};
+        }
+    const int K = 3 * ns;
+    for (int kc = 0; kc < K; kc += 16) {
+        const int kb = kc + 4 * lq;
+        const bool kok = kb < K;
+        const int col = kok ? kb / ns : 0, ls = kok ? kb - col * ns : 0;
+        double ar[2][4], ai[2][4], br[2][4], bi[2][4];
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt) {
+            const int c = 16 * tt + lr;
+            if (tt < ntr && kok && c < Nv) {
+                ld4c(P0 + ((size_t)c * 6 + 3 * s0 + col) * Vb + ls, ar[tt], ai[tt]);
+                ld4c(P1 + ((size_t)c * 6 + 3 * s1 + col) * Vb + ls, br[tt], bi[tt]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) ar[tt][q] = ai[tt][q] = br[tt][q] = bi[tt][q] = 0.0;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < 2; ++ct) {
+                    if (rt < ntr && ct < ntr) {
+                        // conj(a) b
+                        cr[rt][ct] = Mfma<double>::mac(ar[rt][q], br[ct][q], cr[rt][ct]);
+                        cr[rt][ct] = Mfma<double>::mac(ai[rt][q], bi[ct][q], cr[rt][ct]);
+                        ci[rt][ct] = Mfma<double>::mac(ar[rt][q], bi[ct][q], ci[rt][ct]);
+                        ci[rt][ct] = Mfma<double>::mac(-ai[rt][q], br[ct][q], ci[rt][ct]);
+                    }
+                }
+    }
+    const int nn = Nv * Nv;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+            if (rt < ntr && ct < ntr) {
+                const int d = 16 * ct + lr;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int c = 16 * rt + Mfma<double>::row(lq, r);
+                    if (c < Nv && d < Nv) Os[(size_t)w * nn + c * Nv + d] = make_double2(cr[rt][ct][r], ci[rt][ct][r]);
+                }
+            }
+        }
+    __syncthreads();
+    for (int o = threadIdx.x; o < 3 * nn; o += blockDim.x) {
+        const int k = o / nn, cd = o - k * nn;
+        cx<double> acc = cmk(0.0, 0.0);
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp) {
+            int tc;
+            double cre, cim;
+            gk_row(k + 1, sp, &tc, &cre, &cim);
+            const double2 v = Os[(size_t)(sp * 2 + (tc - 2)) * nn + cd];
+            acc = acc + cmk(cre, cim) * cmk(v.x, v.y);
+        }
+        G1[(((size_t)y * g.b[0] + t) * 3 + k) * nn + cd] = make_double2(acc.re, acc.im);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // ABI: build the subspace
 // ---------------------------------------------------------------------------
@@ -577,7 +666,11 @@ extern "C" int mglma_build_subspace(mglma_ctx* c, int Nv, const double* tv) {
     HIP_TRY(hipGetLastError());
 
     // 4. coarse gamma matrices
-    hipLaunchKernelGGL(k_coarse_gamma, dim3(g.V1 * g.b[0]), dim3(256), 0, c->stream, g, Nv, c->B64, c->G1);
+    if ((g.Vb / g.b[0]) % 4 == 0 && Nv <= 32)
+        hipLaunchKernelGGL(k_coarse_gamma_mfma, dim3(g.V1 * g.b[0]), dim3(256), (size_t)4 * Nv * Nv * sizeof(double2),
+                           c->stream, g, Nv, c->B64, c->G1);
+    else
+        hipLaunchKernelGGL(k_coarse_gamma, dim3(g.V1 * g.b[0]), dim3(256), 0, c->stream, g, Nv, c->B64, c->G1);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->have_subspace = true;

@@ -14,10 +14,11 @@ CASES = [
     ((6, 4, 6, 2), (3, 2, 3, 1), 3),        # odd blocks, coarse extents 2/3, nc = 6
     ((8, 8, 4, 4), (4, 4, 4, 4), 8),        # 4^4 blocks, coarse extent 1 in space
     ((4, 4, 4, 8), (2, 2, 2, 4), 20),       # nc = 40: partial 16-row / 16-column matrix-core tiles
+    ((4, 4, 4, 4), (2, 2, 2, 2), 40),       # nc = 80: the VALU Galerkin kernel (n_c > 64)
 ]
 
 
-@pytest.fixture(scope="module", params=CASES, ids=["4^4", "odd", "b4", "nc40"])
+@pytest.fixture(scope="module", params=CASES, ids=["4^4", "odd", "b4", "nc40", "nc80"])
 def pair(request):
     L, b, Nv = request.param
     return Pair(L, b, Nv)
