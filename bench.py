@@ -39,8 +39,8 @@ def log(*a):
 
 
 def mixed_params(mglma, **kw):
-    p = dict(tol=1e-10, max_outer=10, max_inner=120, gcr_m=8, inner_tol=1e-5, nu_post=8, coarse_iters=8,
-             smoother=mglma.F16, inner=mglma.F32, coarse=mglma.BF16, use_mg=1)
+    p = dict(tol=1e-10, max_outer=10, max_inner=120, gcr_m=8, inner_tol=1e-5, nu_post=6, coarse_iters=8,
+             smoother=mglma.F16, inner=mglma.F32, coarse=mglma.BF16, use_mg=1, smoother_alg=mglma.SMOOTH_CAGCR)
     p.update(kw)
     return mglma.default_params(**p)
 
@@ -318,7 +318,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 Krylov + f16 smoother + bf16 coarse, f64 outer",
+        "dtype": "f32 Krylov + f16 CA-GCR smoother + bf16 coarse, f64 outer",
         "data": "synthetic",
         "config": {"workload": "%dx%d^3 Wilson-clover, eps=%g, kappa=%g, c_sw=%g, %d^4 blocks, Nv=%d, Nlm=%d, "
                                "12 point-source RHS batched, mixed-precision MG-GCR to 1e-10" %

@@ -76,14 +76,23 @@ typedef struct {
     int    max_inner;    /* inner FGCR iterations per cycle                    */
     int    gcr_m;        /* inner FGCR restart length                          */
     double inner_tol;    /* relative reduction asked of each inner solve       */
-    int    nu_post;      /* MR smoothing steps after the coarse correction     */
+    int    nu_post;      /* smoothing steps after the coarse correction: MR
+                            steps, or the Krylov dimension of the CA-GCR
+                            smoother (then 1..8)                            */
     int    coarse_iters; /* GCR steps of the coarse solve in the preconditioner
                             (0: no coarse correction, smoother only)        */
     int    smoother;     /* precision of the smoother Dslash (mglma_prec)      */
     int    inner;        /* precision of the inner Krylov vectors (F32 or F64) */
     int    coarse;       /* precision of the preconditioner's coarse operator  */
     int    use_mg;       /* 1: MG preconditioner, 0: unpreconditioned GCR      */
+    int    smoother_alg; /* MGLMA_SMOOTH_MR: nu_post minimal-residual steps;
+                            MGLMA_SMOOTH_CAGCR: one GCR step over the Krylov
+                            space {s, M s, .., M^(nu_post-1) s}, its basis
+                            built without reductions in between (one FP64
+                            Gram matrix per right-hand side)               */
 } mglma_solve_params;
+
+enum { MGLMA_SMOOTH_MR = 0, MGLMA_SMOOTH_CAGCR = 1 };
 
 typedef struct {
     int    outer;        /* defect-correction cycles done                      */
@@ -169,7 +178,7 @@ int mglma_set_top_modes(mglma_ctx* ctx, int Nlm, const double* modes_dev);
 /* x = M^{-1} b for nrhs fields (device layout, F64) to the true relative
  * residual p->tol.  Mixed precision: inner FGCR on p->inner vectors with the
  * multigrid preconditioner (coarse correction with p->coarse operator, then
- * p->nu_post MR smoothing steps in p->smoother precision) inside an FP64
+ * smoothing in p->smoother precision, MR or CA-GCR) inside an FP64
  * defect-correction loop.  stats may be NULL or hold nrhs entries.
  * Synchronising.  Errors: NO_GAUGE, NO_SUBSPACE (use_mg), NONFINITE,
  * NOT_CONVERGED (x holds the last iterate).                                 */

@@ -731,3 +731,174 @@ int mg_mr_update_h(mglma_ctx* c, const double* a, const double* scale, void* z, 
     HIP_TRY(hipGetLastError());
     return MGLMA_OK;
 }
+
+// ---------------------------------------------------------------------------
+// CA-GCR smoother: Gram matrix of the Krylov basis and the correction
+// ---------------------------------------------------------------------------
+// Basis P_0 .. P_k (P_i at P + i * pstride, each nrhs vectors of n).  Per
+// rhs the packed FP64 values
+//   [0, CA_K)                 G[q][q] = |P_{q+1}|^2
+//   [CA_K, CA_K + 2 npairs)   G[q][j] = <P_{q+1}, P_{j+1}>, q < j, (re, im)
+//   [.., + 2 CA_K)            b[q] = <P_{q+1}, P_0>, (re, im)
+// in a layout fixed by CA_K (entries past k stay zero).
+// The CA_NV values are split over the four wavefronts of a workgroup (wave 0:
+// the diagonal and b, waves 1..3: a third of the off-diagonal pairs each);
+// all four walk the same elements (the repeated loads hit L1), so each lane
+// holds at most 2 CA_K + CA_K accumulators.
+#define CA_NPAIR (CA_K * (CA_K - 1) / 2)
+#define CA_PG ((CA_NPAIR + 2) / 3)          // pairs per wave 1..3
+
+template <int G>
+__device__ __forceinline__ void ca_accum(const cx<double> (&x)[CA_K + 1], double (&v)[3 * CA_K]) {
+    if (G == 0) {
+#pragma unroll
+        for (int i = 0; i < CA_K; ++i) {
+            const cx<double> a = x[i + 1], b0 = x[0];
+            v[i] = fma(a.re, a.re, fma(a.im, a.im, v[i]));
+            v[CA_K + 2 * i] = fma(a.re, b0.re, fma(a.im, b0.im, v[CA_K + 2 * i]));
+            v[CA_K + 2 * i + 1] = fma(a.re, b0.im, fma(-a.im, b0.re, v[CA_K + 2 * i + 1]));
+        }
+    } else {
+        int o = 0, q = 0;
+#pragma unroll
+        for (int i = 0; i < CA_K; ++i)
+#pragma unroll
+            for (int j = i + 1; j < CA_K; ++j) {
+                if (o >= (G - 1) * CA_PG && o < G * CA_PG) {
+                    const cx<double> a = x[i + 1], b = x[j + 1];
+                    v[2 * q] = fma(a.re, b.re, fma(a.im, b.im, v[2 * q]));
+                    v[2 * q + 1] = fma(a.re, b.im, fma(-a.im, b.re, v[2 * q + 1]));
+                    ++q;
+                }
+                ++o;
+            }
+    }
+}
+
+// position in the packed CA_NV layout of value e of wave G
+template <int G>
+__device__ __forceinline__ int ca_slot(int e) {
+    if (G == 0) return e < CA_K ? e : CA_K + 2 * CA_NPAIR + (e - CA_K);
+    return CA_K + 2 * (G - 1) * CA_PG + e;
+}
+
+template <typename S, int C, int G>
+__device__ __forceinline__ void ca_gram_wave(const S* __restrict__ P, size_t pstride, int k, size_t n, double* lds) {
+    // values held by this wave (the last pair group may be short)
+    constexpr int NPG = (G * CA_PG < CA_NPAIR ? G * CA_PG : CA_NPAIR) - (G - 1) * CA_PG;
+    constexpr int NVG = G == 0 ? 3 * CA_K : 2 * NPG;
+    const int lane = threadIdx.x & 63;
+    const size_t roff = (size_t)blockIdx.y * n, np = n / C;
+    double v[3 * CA_K];
+#pragma unroll
+    for (int e = 0; e < 3 * CA_K; ++e) v[e] = 0.0;
+    for (size_t p = (size_t)blockIdx.x * 64 + lane; p < np; p += (size_t)gridDim.x * 64) {
+        cx<double> xx[CA_K + 1][C];
+#pragma unroll
+        for (int i = 0; i <= CA_K; ++i) {
+            if (i <= k) {
+                ldp<S, double, C>(P + (size_t)i * pstride + roff + p * C, xx[i]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < C; ++q) xx[i][q] = cmk(0.0, 0.0);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            cx<double> x[CA_K + 1];
+#pragma unroll
+            for (int i = 0; i <= CA_K; ++i) x[i] = xx[i][q];
+            ca_accum<G>(x, v);
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < NVG; ++e) {
+        const double t = wave_sum(v[e]);
+        if (lane == 0) lds[ca_slot<G>(e)] = t;
+    }
+}
+
+template <typename S, int C>
+__global__ __launch_bounds__(RB) void k_ca_gram(const S* __restrict__ P, size_t pstride, int k, size_t n,
+                                                double* part) {
+    __shared__ double lds[CA_NV];
+    const int w = threadIdx.x >> 6;
+    if (w == 0) ca_gram_wave<S, C, 0>(P, pstride, k, n, lds);
+    else if (w == 1) ca_gram_wave<S, C, 1>(P, pstride, k, n, lds);
+    else if (w == 2) ca_gram_wave<S, C, 2>(P, pstride, k, n, lds);
+    else ca_gram_wave<S, C, 3>(P, pstride, k, n, lds);
+    __syncthreads();
+    for (int e = threadIdx.x; e < CA_NV; e += blockDim.x)
+        part[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * CA_NV + e] = lds[e];
+}
+
+template <typename S>
+static int ca_gram_t(mglma_ctx* c, const S* P, size_t pstride, int k, size_t n, int nrhs, double* out) {
+    const bool vec = n % 2 == 0 && pstride % 2 == 0 && al(P, 2 * sizeof(S));
+    const size_t np = vec ? n / 2 : n;
+    size_t nb = (np + 63) / 64;
+    if (nb > 1024) nb = 1024;
+    MG_TRY(ensure_red(c, nb * nrhs * CA_NV));
+    dim3 grid(nb, nrhs);
+    if (vec) hipLaunchKernelGGL((k_ca_gram<S, 2>), grid, dim3(RB), 0, c->stream, P, pstride, k, n, c->red_part);
+    else hipLaunchKernelGGL((k_ca_gram<S, 1>), grid, dim3(RB), 0, c->stream, P, pstride, k, n, c->red_part);
+    HIP_TRY(hipGetLastError());
+    return launch_finish<CA_NV>(c, (int)nb, nrhs, CA_NV, out);
+}
+
+int mg_ca_gram(mglma_ctx* c, int prec, const void* P, size_t pstride, int k, size_t n, int nrhs, double* out) {
+    if (nrhs <= 0) return MGLMA_OK;
+    if (k < 1 || k > CA_K) return MGLMA_ERR_ARG;
+    switch (prec) {
+        case MGLMA_F64: return ca_gram_t(c, (const double2*)P, pstride, k, n, nrhs, out);
+        case MGLMA_F32: return ca_gram_t(c, (const float2*)P, pstride, k, n, nrhs, out);
+        case MGLMA_F16: return ca_gram_t(c, (const __half2*)P, pstride, k, n, nrhs, out);
+        default: return MGLMA_ERR_ARG;
+    }
+}
+
+// z (FP32) += sum_{i<k} coef[i][r] P_i (P in FP16)
+template <int C>
+__global__ void k_ca_update_h(const __half2* __restrict__ P, size_t pstride, int k, const double* __restrict__ coef,
+                              float2* __restrict__ z, size_t n, int nrhs) {
+    const int r = blockIdx.y;
+    const size_t roff = (size_t)r * n;
+    cx<float> a[CA_K];
+#pragma unroll
+    for (int i = 0; i < CA_K; ++i)
+        a[i] = i < k ? cmk((float)coef[((size_t)i * nrhs + r) * 2], (float)coef[((size_t)i * nrhs + r) * 2 + 1])
+                     : cmk(0.f, 0.f);
+    for_packets<1>(n / C, [&](size_t p) {
+        const size_t o = roff + p * C;
+        cx<float> zv[C];
+        ldp<float2, float, C>(z + o, zv);
+#pragma unroll
+        for (int i = 0; i < CA_K; ++i) {
+            if (i < k) {
+                cx<float> xv[C];
+                ldp<__half2, float, C>(P + (size_t)i * pstride + o, xv);
+#pragma unroll
+                for (int q = 0; q < C; ++q) cmac(zv[q], a[i], xv[q]);
+            }
+        }
+        stp<float2, float, C>(z + o, zv);
+    });
+}
+
+int mg_ca_update(mglma_ctx* c, int pprec, const void* P, size_t pstride, int k, const double* coef, int zprec,
+                 void* z, size_t n, int nrhs) {
+    if (nrhs <= 0 || k <= 0) return MGLMA_OK;
+    if (k > CA_K) return MGLMA_ERR_ARG;
+    if (pprec == zprec) return mg_multiaxpy(c, zprec, P, pstride, k, coef, 1.0, z, n, nrhs);
+    if (pprec != MGLMA_F16 || zprec != MGLMA_F32) return MGLMA_ERR_ARG;
+    const bool vec = n % 2 == 0 && pstride % 2 == 0 && al(P, 8) && al(z, 16);
+    const dim3 grid = ew_grid(vec ? n / 2 : n, nrhs, 1);
+    if (vec)
+        hipLaunchKernelGGL(k_ca_update_h<2>, grid, dim3(256), 0, c->stream, (const __half2*)P, pstride, k, coef,
+                           (float2*)z, n, nrhs);
+    else
+        hipLaunchKernelGGL(k_ca_update_h<1>, grid, dim3(256), 0, c->stream, (const __half2*)P, pstride, k, coef,
+                           (float2*)z, n, nrhs);
+    HIP_TRY(hipGetLastError());
+    return MGLMA_OK;
+}

@@ -15,7 +15,7 @@
 
 enum {
     WS_SCAL = 8, WS_R64, WS_T64, WS_RIN, WS_E, WS_Z, WS_W, WS_RC, WS_EC, WS_CP, WS_CQ, WS_CR, WS_SS, WS_ST, WS_X16,
-    WS_CX64, WS_CR64, WS_CT64, WS_PIECE, WS_COUNT
+    WS_CX64, WS_CR64, WS_CT64, WS_PIECE, WS_CAP, WS_COUNT
 };
 
 // ---------------------------------------------------------------------------
@@ -106,7 +106,9 @@ struct Scal {
     double* cbeta() { return at(20 + 2 * m); }        // complex [m][nrhs]
     double* nw2() { return at(20 + 4 * m); }          // [m][nrhs] squared norms of the fine directions
     double* cnw2() { return at(20 + 5 * m); }         // [m][nrhs] squared norms of the coarse directions
-    static size_t bytes(int nrhs, int m) { return (size_t)(20 + 6 * m) * nrhs * 8 + 256; }
+    double* cagram() { return at(20 + 6 * m); }       // [nrhs][CA_NV] packed Gram values of the CA smoother
+    double* cacoef() { return at(20 + 6 * m + CA_NV); }   // complex [CA_K][nrhs] smoother coefficients
+    static size_t bytes(int nrhs, int m) { return (size_t)(20 + 6 * m + CA_NV + 2 * CA_K) * nrhs * 8 + 256; }
 };
 
 // beta[j][r] /= nw2[j][r]   (projection coefficients of unnormalised directions)
@@ -128,6 +130,79 @@ __global__ void k_alpha(const double* dn3, double* alpha, double* nw2j, const in
     alpha[2 * r] = on ? dn3[3 * r] / d : 0.0;
     alpha[2 * r + 1] = on ? dn3[3 * r + 1] / d : 0.0;
     if (nw2j) nw2j[r] = d;
+}
+
+// CA-GCR smoother coefficients, one thread per rhs: solve the normal
+// equations G c = b of min || P_0 - sum_j c_j P_{j+1} || by Cholesky in FP64
+// (basis truncated at the first pivot below 1e-12 of its diagonal entry, so a
+// rank-deficient Krylov space is handled), coef[i][r] = scale[r] c_i.
+__global__ void k_ca_solve(const double* __restrict__ gram, int k, const double* __restrict__ scale,
+                           double* __restrict__ coef, int nrhs) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    const double* gp = gram + (size_t)r * CA_NV;
+    cx<double> G[CA_K][CA_K], b[CA_K], L[CA_K][CA_K], y[CA_K], cv[CA_K];
+    int o = CA_K;
+#pragma unroll
+    for (int i = 0; i < CA_K; ++i) {
+        G[i][i] = cmk(gp[i], 0.0);
+#pragma unroll
+        for (int j = i + 1; j < CA_K; ++j) {
+            G[i][j] = cmk(gp[o], gp[o + 1]);
+            G[j][i] = conj(G[i][j]);
+            o += 2;
+        }
+        b[i] = cmk(gp[CA_K + CA_K * (CA_K - 1) + 2 * i], gp[CA_K + CA_K * (CA_K - 1) + 2 * i + 1]);
+    }
+    int m = k;
+#pragma unroll
+    for (int j = 0; j < CA_K; ++j) {
+        L[j][j] = cmk(0.0, 0.0);
+        if (j < m) {
+            double d = G[j][j].re;
+#pragma unroll
+            for (int l = 0; l < CA_K; ++l)
+                if (l < j) d -= L[j][l].re * L[j][l].re + L[j][l].im * L[j][l].im;
+            if (!(d > 1e-12 * G[j][j].re)) {
+                m = j;
+            } else {
+                const double dj = sqrt(d);
+                L[j][j] = cmk(dj, 0.0);
+#pragma unroll
+                for (int i = 0; i < CA_K; ++i) {
+                    if (i > j && i < m) {
+                        cx<double> t = G[i][j];
+#pragma unroll
+                        for (int l = 0; l < CA_K; ++l)
+                            if (l < j) t = t - L[i][l] * conj(L[j][l]);
+                        L[i][j] = cmk(t.re / dj, t.im / dj);
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < CA_K; ++i) {
+        cx<double> t = b[i];
+#pragma unroll
+        for (int l = 0; l < CA_K; ++l)
+            if (l < i) t = t - L[i][l] * y[l];
+        y[i] = i < m ? cmk(t.re / L[i][i].re, t.im / L[i][i].re) : cmk(0.0, 0.0);
+    }
+#pragma unroll
+    for (int i = CA_K - 1; i >= 0; --i) {
+        cx<double> t = y[i];
+#pragma unroll
+        for (int l = 0; l < CA_K; ++l)
+            if (l > i && l < m) t = t - conj(L[l][i]) * cv[l];
+        cv[i] = i < m ? cmk(t.re / L[i][i].re, t.im / L[i][i].re) : cmk(0.0, 0.0);
+    }
+    const double sc = scale[r];
+#pragma unroll
+    for (int i = 0; i < CA_K; ++i) {
+        coef[((size_t)i * nrhs + r) * 2] = sc * cv[i].re;
+        coef[((size_t)i * nrhs + r) * 2 + 1] = sc * cv[i].im;
+    }
 }
 
 struct SolveCtx {
@@ -215,7 +290,26 @@ static int precondition(SolveCtx& S, int vp, const void* r, void* z) {
     const int sp = (vp == MGLMA_F32 && p->smoother == MGLMA_F16) ? MGLMA_F16 : vp;
     MG_TRY(mg_dslash(c, vp, 0, z, t, nrhs));
     MG_TRY(mg_sub(c, vp, r, t, s, n, nrhs));
-    if (sp == MGLMA_F16) {
+    if (p->smoother_alg == MGLMA_SMOOTH_CAGCR) {
+        // one GCR step over span{s, M s, .., M^(k-1) s}: P_0 = s / scale,
+        // P_{i+1} = M P_i (no reductions in between), c from the FP64 Gram
+        // matrix, z += scale sum_i c_i P_i
+        const int k = p->nu_post;
+        const size_t setsz = (size_t)nrhs * n, sb = prec_cbytes(sp);
+        void* P;
+        MG_TRY(mg_scratch(c, WS_CAP, (size_t)(k + 1) * setsz * sb, &P));
+        MG_TRY(mg_norm2(c, vp, s, n, nrhs, S.s.tt()));
+        hipLaunchKernelGGL(k_rms, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, S.s.tt(), (double)n, S.s.hscale(),
+                           nrhs);
+        MG_TRY(mg_convert(c, vp, s, sp, P, n, nrhs, S.s.hscale(), 1));
+        for (int i = 0; i < k; ++i)
+            MG_TRY(mg_dslash(c, sp, 0, (char*)P + (size_t)i * setsz * sb, (char*)P + (size_t)(i + 1) * setsz * sb,
+                             nrhs));
+        MG_TRY(mg_ca_gram(c, sp, P, setsz, k, n, nrhs, S.s.cagram()));
+        hipLaunchKernelGGL(k_ca_solve, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, S.s.cagram(), k, S.s.hscale(),
+                           S.s.cacoef(), nrhs);
+        MG_TRY(mg_ca_update(c, sp, P, setsz, k, S.s.cacoef(), vp, z, n, nrhs));
+    } else if (sp == MGLMA_F16) {
         // half-precision storage: s16 = s / scale (entries of order one), t16 = M s16;
         // omega = <t16,s16>/<t16,t16>; z += omega*scale*s16 ; s16 -= omega t16
         void* s16;
@@ -318,6 +412,9 @@ extern "C" int mglma_solve(mglma_ctx* c, const mglma_solve_params* p, const doub
     if (!c->have_gauge) return MGLMA_ERR_NO_GAUGE;
     if (p->use_mg && !c->have_subspace) return MGLMA_ERR_NO_SUBSPACE;
     if (p->gcr_m < 1 || p->gcr_m > 64 || p->max_inner < 1 || p->max_outer < 1) return MGLMA_ERR_ARG;
+    if (p->smoother_alg != MGLMA_SMOOTH_MR && p->smoother_alg != MGLMA_SMOOTH_CAGCR) return MGLMA_ERR_ARG;
+    if (p->use_mg && p->smoother_alg == MGLMA_SMOOTH_CAGCR && (p->nu_post < 0 || p->nu_post > CA_K))
+        return MGLMA_ERR_ARG;
     const int vp = p->inner == MGLMA_F64 ? MGLMA_F64 : MGLMA_F32;
     const size_t n = fine_n(c), setsz = (size_t)nrhs * n;
     SolveCtx S;

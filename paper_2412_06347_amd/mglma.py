@@ -15,6 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmglma.so")
 
 F64, F32, F16, BF16 = 0, 1, 2, 3
+SMOOTH_MR, SMOOTH_CAGCR = 0, 1
 
 SYMBOLS = [
     "mglma_create", "mglma_destroy", "mglma_set_stream", "mglma_strerror", "mglma_query",
@@ -39,7 +40,7 @@ class SolveParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_outer", C.c_int), ("max_inner", C.c_int),
                 ("gcr_m", C.c_int), ("inner_tol", C.c_double), ("nu_post", C.c_int),
                 ("coarse_iters", C.c_int), ("smoother", C.c_int), ("inner", C.c_int),
-                ("coarse", C.c_int), ("use_mg", C.c_int)]
+                ("coarse", C.c_int), ("use_mg", C.c_int), ("smoother_alg", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -84,7 +85,8 @@ def _ptr(t):
 
 def default_params(**kw):
     p = SolveParams(tol=1e-10, max_outer=12, max_inner=200, gcr_m=16, inner_tol=1e-5,
-                    nu_post=4, coarse_iters=16, smoother=F32, inner=F32, coarse=F32, use_mg=1)
+                    nu_post=4, coarse_iters=16, smoother=F32, inner=F32, coarse=F32, use_mg=1,
+                    smoother_alg=SMOOTH_MR)
     for k, v in kw.items():
         setattr(p, k, v)
     return p

@@ -63,10 +63,11 @@ class AdmissionError(RuntimeError):
     pass
 
 
-def workspace_bytes_per_rhs(V, gcr_m=8):
+def workspace_bytes_per_rhs(V, gcr_m=8, nu_post=6):
     """Device bytes the solve needs per right-hand side: 2*gcr_m + 8 FP32 and
-    8 FP64 fine fields (Krylov directions, residuals, smoother, outputs)."""
-    return V * 12 * ((2 * gcr_m + 8) * 8 + 8 * 16)
+    8 FP64 fine fields (Krylov directions, residuals, smoother, outputs) and
+    the nu_post + 1 FP16 Krylov basis vectors of the CA-GCR smoother."""
+    return V * 12 * ((2 * gcr_m + 8) * 8 + 8 * 16 + (nu_post + 1) * 4)
 
 
 class Engine:
@@ -114,8 +115,9 @@ class Engine:
             self.G_top = ctx.contract_top()
         self.stream.synchronize()
         self.params = params or mglma.default_params(tol=1e-10, max_outer=10, max_inner=120, gcr_m=8,
-                                                     inner_tol=1e-5, nu_post=8, coarse_iters=8,
-                                                     smoother=mglma.F16, inner=mglma.F32, coarse=mglma.BF16)
+                                                     inner_tol=1e-5, nu_post=6, coarse_iters=8,
+                                                     smoother=mglma.F16, inner=mglma.F32, coarse=mglma.BF16,
+                                                     smoother_alg=mglma.SMOOTH_CAGCR)
         self.coarse_params = coarse_params or mglma.default_params(tol=1e-10, coarse=mglma.F32, coarse_iters=24)
         self.resident = ctx.resident_bytes() + self.U.numel() * 8
 

@@ -22,11 +22,20 @@ def _true_res(pair, x, b):
     return np.linalg.norm(r.reshape(len(b), -1), axis=1) / np.linalg.norm(b.reshape(len(b), -1), axis=1)
 
 
-@pytest.mark.parametrize("mode", ["fp64_gcr", "fp64_mg", "mixed_mg", "mixed_mg_bf16", "mixed_mg_f16smooth"])
+@pytest.mark.parametrize("mode", ["fp64_gcr", "fp64_mg", "mixed_mg", "mixed_mg_bf16", "mixed_mg_f16smooth",
+                                  "fp64_mg_cagcr", "mixed_mg_cagcr", "mixed_mg_f16_cagcr"])
 def test_fine_solve(pair, mode):
     from paper_2412_06347_amd import mglma
     kw = dict(tol=1e-10, gcr_m=8, max_inner=400, max_outer=10)
-    if mode == "fp64_gcr":
+    if mode == "fp64_mg_cagcr":
+        kw.update(inner=mglma.F64, coarse=mglma.F64, smoother=mglma.F64, inner_tol=1e-11,
+                  smoother_alg=mglma.SMOOTH_CAGCR, nu_post=6)
+    elif mode == "mixed_mg_cagcr":
+        kw.update(inner=mglma.F32, coarse=mglma.BF16, inner_tol=1e-5, smoother_alg=mglma.SMOOTH_CAGCR, nu_post=4)
+    elif mode == "mixed_mg_f16_cagcr":
+        kw.update(inner=mglma.F32, coarse=mglma.BF16, smoother=mglma.F16, inner_tol=1e-5,
+                  smoother_alg=mglma.SMOOTH_CAGCR, nu_post=8)
+    elif mode == "fp64_gcr":
         kw.update(inner=mglma.F64, use_mg=0, inner_tol=1e-11, max_inner=2000, gcr_m=16)
     elif mode == "fp64_mg":
         kw.update(inner=mglma.F64, coarse=mglma.F64, inner_tol=1e-11)
@@ -58,12 +67,16 @@ def test_solution_matches_oracle_gcr(pair):
     assert relerr(pair.fine_host(xd), pair.canon(xo)) < 1e-9
 
 
-def test_batch_independence(pair):
+@pytest.mark.parametrize("alg", ["mr", "cagcr"])
+def test_batch_independence(pair, alg):
     """A right-hand side solved alone and inside a batch gives the same answer
     to the solve tolerance."""
     from paper_2412_06347_amd import mglma
     b = synth.gaussian_fields(4, pair.L, 55)
     p = mglma.default_params(inner=mglma.F32, coarse=mglma.BF16, tol=1e-10)
+    if alg == "cagcr":
+        p = mglma.default_params(inner=mglma.F32, coarse=mglma.BF16, tol=1e-10, smoother=mglma.F16,
+                                 smoother_alg=mglma.SMOOTH_CAGCR, nu_post=8)
     xa = pair.ctx.fine(4)
     pair.ctx.solve(pair.fine_dev(b), xa, p)
     x1 = pair.ctx.fine(1)
@@ -105,3 +118,7 @@ def test_error_paths(pair):
     rc, st = pair.ctx.solve(pair.fine_dev(b), xd, mglma.default_params(max_outer=1, max_inner=1),
                             raise_on_error=False)
     assert rc == -6 and st[0]["status"] == -6 and st[0]["true_rel_res"] > 1e-10
+    # the CA-GCR smoother takes a Krylov dimension of at most 8
+    rc, _ = pair.ctx.solve(pair.fine_dev(b), xd, mglma.default_params(smoother_alg=mglma.SMOOTH_CAGCR, nu_post=9),
+                           raise_on_error=False)
+    assert rc == -1
