@@ -141,7 +141,8 @@ def measured_traffic(workload):
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = open(os.path.join(here, "paper_2412_06347_amd", "csrc", "dslash.hip"), "rb").read()
+    csrc = os.path.join(here, "paper_2412_06347_amd", "csrc")
+    src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("dslash.hip", "wilson.h"))
     if hashlib.sha256(src).hexdigest() != rec.get("dslash_source_sha256"):
         return None
     return rec.get("f16_12rhs_hbm_bytes_per_launch")

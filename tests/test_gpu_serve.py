@@ -22,7 +22,9 @@ def test_serving_alone_equals_mix():
     for name, wl in ENS.items():
         srv.add_ensemble(name, wl)
     srv.start()
-    arr = poisson_arrivals(10, 40.0, 5)
+    # arrivals a few milliseconds apart, well inside one batch's service time,
+    # so requests arrive while others are on the GPU
+    arr = poisson_arrivals(12, 400.0, 5)
     reqs = []
     t0 = time.perf_counter()
     for i, t in enumerate(arr):
