@@ -735,36 +735,40 @@ int mg_mr_update_h(mglma_ctx* c, const double* a, const double* scale, void* z, 
 // ---------------------------------------------------------------------------
 // CA-GCR smoother: Gram matrix of the Krylov basis and the correction
 // ---------------------------------------------------------------------------
-// Basis P_0 .. P_k (P_i at P + i * pstride, each nrhs vectors of n).  Per
-// rhs the packed FP64 values
-//   [0, CA_K)                 G[q][q] = |P_{q+1}|^2
-//   [CA_K, CA_K + 2 npairs)   G[q][j] = <P_{q+1}, P_{j+1}>, q < j, (re, im)
-//   [.., + 2 CA_K)            b[q] = <P_{q+1}, P_0>, (re, im)
-// in a layout fixed by CA_K (entries past k stay zero).
-// The CA_NV values are split over the four wavefronts of a workgroup (wave 0:
-// the diagonal and b, waves 1..3: a third of the off-diagonal pairs each);
-// all four walk the same elements (the repeated loads hit L1), so each lane
-// holds at most 2 CA_K + CA_K accumulators.
-#define CA_NPAIR (CA_K * (CA_K - 1) / 2)
-#define CA_PG ((CA_NPAIR + 2) / 3)          // pairs per wave 1..3
+// Basis P_0 .. P_k (P_i at P + i * pstride, each nrhs vectors of n):
+// G[q][j] = <P_{q+1}, P_{j+1}> and b[q] = <P_{q+1}, P_0>, q, j < k.
+// Krylov dimension K (compile time).  Packed FP64 values per rhs, layout of
+// dimension K: [0, K) G[q][q]; [K, K^2) G[q][j] for q < j (re, im) in
+// lexicographic order; [K^2, K^2 + 2K) b[q] (re, im).
+// The values are split over the four wavefronts of a workgroup (wave 0: the
+// diagonal and b, waves 1..3: a third of the pairs each), so each lane holds
+// at most 3 K accumulators.  A workgroup stages CaTile elements of every
+// basis vector in LDS per step (every thread loads distinct elements, the next
+// step's loads are issued before the current step is computed), then each
+// wave accumulates its values from LDS.
+template <int K> struct CaK {
+    static constexpr int NPAIR = K * (K - 1) / 2;
+    static constexpr int PG = (NPAIR + 2) / 3;
+    static constexpr int NV = K * K + 2 * K;
+};
 
-template <int G>
-__device__ __forceinline__ void ca_accum(const cx<double> (&x)[CA_K + 1], double (&v)[3 * CA_K]) {
+template <int G, int K>
+__device__ __forceinline__ void ca_accum(const cx<double> (&x)[K + 1], double (&v)[3 * K]) {
     if (G == 0) {
 #pragma unroll
-        for (int i = 0; i < CA_K; ++i) {
+        for (int i = 0; i < K; ++i) {
             const cx<double> a = x[i + 1], b0 = x[0];
             v[i] = fma(a.re, a.re, fma(a.im, a.im, v[i]));
-            v[CA_K + 2 * i] = fma(a.re, b0.re, fma(a.im, b0.im, v[CA_K + 2 * i]));
-            v[CA_K + 2 * i + 1] = fma(a.re, b0.im, fma(-a.im, b0.re, v[CA_K + 2 * i + 1]));
+            v[K + 2 * i] = fma(a.re, b0.re, fma(a.im, b0.im, v[K + 2 * i]));
+            v[K + 2 * i + 1] = fma(a.re, b0.im, fma(-a.im, b0.re, v[K + 2 * i + 1]));
         }
     } else {
         int o = 0, q = 0;
 #pragma unroll
-        for (int i = 0; i < CA_K; ++i)
+        for (int i = 0; i < K; ++i)
 #pragma unroll
-            for (int j = i + 1; j < CA_K; ++j) {
-                if (o >= (G - 1) * CA_PG && o < G * CA_PG) {
+            for (int j = i + 1; j < K; ++j) {
+                if (o >= (G - 1) * CaK<K>::PG && o < G * CaK<K>::PG) {
                     const cx<double> a = x[i + 1], b = x[j + 1];
                     v[2 * q] = fma(a.re, b.re, fma(a.im, b.im, v[2 * q]));
                     v[2 * q + 1] = fma(a.re, b.im, fma(-a.im, b.re, v[2 * q + 1]));
@@ -775,77 +779,109 @@ __device__ __forceinline__ void ca_accum(const cx<double> (&x)[CA_K + 1], double
     }
 }
 
-// position in the packed CA_NV layout of value e of wave G
-template <int G>
-__device__ __forceinline__ int ca_slot(int e) {
-    if (G == 0) return e < CA_K ? e : CA_K + 2 * CA_NPAIR + (e - CA_K);
-    return CA_K + 2 * (G - 1) * CA_PG + e;
-}
-
-template <typename S, int C, int G>
-__device__ __forceinline__ void ca_gram_wave(const S* __restrict__ P, size_t pstride, int k, size_t n, double* lds) {
-    // values held by this wave (the last pair group may be short)
-    constexpr int NPG = (G * CA_PG < CA_NPAIR ? G * CA_PG : CA_NPAIR) - (G - 1) * CA_PG;
-    constexpr int NVG = G == 0 ? 3 * CA_K : 2 * NPG;
+template <int G, int K>
+__device__ __forceinline__ void ca_store(const double (&v)[3 * K], double* red) {
+    constexpr int PG = CaK<K>::PG, NPAIR = CaK<K>::NPAIR;
+    constexpr int NPG = G == 0 ? 0 : ((G * PG < NPAIR ? G * PG : NPAIR) - (G - 1) * PG > 0
+                                          ? (G * PG < NPAIR ? G * PG : NPAIR) - (G - 1) * PG : 0);
+    constexpr int NVG = G == 0 ? 3 * K : 2 * NPG;
     const int lane = threadIdx.x & 63;
-    const size_t roff = (size_t)blockIdx.y * n, np = n / C;
-    double v[3 * CA_K];
-#pragma unroll
-    for (int e = 0; e < 3 * CA_K; ++e) v[e] = 0.0;
-    for (size_t p = (size_t)blockIdx.x * 64 + lane; p < np; p += (size_t)gridDim.x * 64) {
-        cx<double> xx[CA_K + 1][C];
-#pragma unroll
-        for (int i = 0; i <= CA_K; ++i) {
-            if (i <= k) {
-                ldp<S, double, C>(P + (size_t)i * pstride + roff + p * C, xx[i]);
-            } else {
-#pragma unroll
-                for (int q = 0; q < C; ++q) xx[i][q] = cmk(0.0, 0.0);
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < C; ++q) {
-            cx<double> x[CA_K + 1];
-#pragma unroll
-            for (int i = 0; i <= CA_K; ++i) x[i] = xx[i][q];
-            ca_accum<G>(x, v);
-        }
-    }
 #pragma unroll
     for (int e = 0; e < NVG; ++e) {
         const double t = wave_sum(v[e]);
-        if (lane == 0) lds[ca_slot<G>(e)] = t;
+        const int slot = G == 0 ? (e < K ? e : K * K + (e - K)) : K + 2 * (G - 1) * PG + e;
+        if (lane == 0) red[slot] = t;
     }
 }
 
-template <typename S, int C>
-__global__ __launch_bounds__(RB) void k_ca_gram(const S* __restrict__ P, size_t pstride, int k, size_t n,
-                                                double* part) {
-    __shared__ double lds[CA_NV];
+template <typename S> struct CaTile { static constexpr int C = sizeof(S) == 16 ? 1 : 2, E = 256 * C; };
+
+template <typename S, int K, int G>
+__device__ __forceinline__ void ca_tile(const S* tile, double (&v)[3 * K]) {
+    constexpr int E = CaTile<S>::E;
+    const int lane = threadIdx.x & 63;
+#pragma unroll 2
+    for (int e = lane; e < E; e += 64) {
+        cx<double> x[K + 1];
+#pragma unroll
+        for (int i = 0; i <= K; ++i) x[i] = ldc<S, double>(tile + (size_t)i * E + e);
+        ca_accum<G, K>(x, v);
+    }
+}
+
+template <typename S, int K>
+__global__ __launch_bounds__(RB) void k_ca_gram(const S* __restrict__ P, size_t pstride, size_t n, double* part) {
+    constexpr int E = CaTile<S>::E, C = CaTile<S>::C, NV = CaK<K>::NV;
+    __shared__ S tile[(K + 1) * E];
+    __shared__ double red[NV];
     const int w = threadIdx.x >> 6;
-    if (w == 0) ca_gram_wave<S, C, 0>(P, pstride, k, n, lds);
-    else if (w == 1) ca_gram_wave<S, C, 1>(P, pstride, k, n, lds);
-    else if (w == 2) ca_gram_wave<S, C, 2>(P, pstride, k, n, lds);
-    else ca_gram_wave<S, C, 3>(P, pstride, k, n, lds);
+    const size_t roff = (size_t)blockIdx.y * n, stride = (size_t)gridDim.x * E;
+    double v[3 * K];
+#pragma unroll
+    for (int e = 0; e < 3 * K; ++e) v[e] = 0.0;
+    S pre[K + 1][C];
+    size_t base = (size_t)blockIdx.x * E;
+    auto load = [&](size_t b0) {
+#pragma unroll
+        for (int i = 0; i <= K; ++i)
+#pragma unroll
+            for (int q = 0; q < C; ++q) {
+                const size_t e = b0 + (size_t)threadIdx.x * C + q;
+                pre[i][q] = e < n ? P[(size_t)i * pstride + roff + e] : S{};
+            }
+    };
+    if (base < n) load(base);
+    for (; base < n; base += stride) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i <= K; ++i)
+#pragma unroll
+            for (int q = 0; q < C; ++q) tile[(size_t)i * E + threadIdx.x * C + q] = pre[i][q];
+        __syncthreads();
+        if (base + stride < n) load(base + stride);
+        if (w == 0) ca_tile<S, K, 0>(tile, v);
+        else if (w == 1) ca_tile<S, K, 1>(tile, v);
+        else if (w == 2) ca_tile<S, K, 2>(tile, v);
+        else ca_tile<S, K, 3>(tile, v);
+    }
+    if (w == 0) ca_store<0, K>(v, red);
+    else if (w == 1) ca_store<1, K>(v, red);
+    else if (w == 2) ca_store<2, K>(v, red);
+    else ca_store<3, K>(v, red);
     __syncthreads();
-    for (int e = threadIdx.x; e < CA_NV; e += blockDim.x)
-        part[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * CA_NV + e] = lds[e];
+    for (int e = threadIdx.x; e < NV; e += blockDim.x)
+        part[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * NV + e] = red[e];
+}
+
+template <typename S, int K>
+static int ca_gram_k(mglma_ctx* c, const S* P, size_t pstride, size_t n, int nrhs, double* out) {
+    constexpr int NV = CaK<K>::NV;
+    const size_t E = CaTile<S>::E;
+    size_t nb = (n + E - 1) / E;
+    if (nb > 1024) nb = 1024;
+    MG_TRY(ensure_red(c, nb * nrhs * NV));
+    hipLaunchKernelGGL((k_ca_gram<S, K>), dim3((unsigned)nb, nrhs), dim3(RB), 0, c->stream, P, pstride, n,
+                       c->red_part);
+    HIP_TRY(hipGetLastError());
+    return launch_finish<NV>(c, (int)nb, nrhs, NV, out);
 }
 
 template <typename S>
 static int ca_gram_t(mglma_ctx* c, const S* P, size_t pstride, int k, size_t n, int nrhs, double* out) {
-    const bool vec = n % 2 == 0 && pstride % 2 == 0 && al(P, 2 * sizeof(S));
-    const size_t np = vec ? n / 2 : n;
-    size_t nb = (np + 63) / 64;
-    if (nb > 1024) nb = 1024;
-    MG_TRY(ensure_red(c, nb * nrhs * CA_NV));
-    dim3 grid(nb, nrhs);
-    if (vec) hipLaunchKernelGGL((k_ca_gram<S, 2>), grid, dim3(RB), 0, c->stream, P, pstride, k, n, c->red_part);
-    else hipLaunchKernelGGL((k_ca_gram<S, 1>), grid, dim3(RB), 0, c->stream, P, pstride, k, n, c->red_part);
-    HIP_TRY(hipGetLastError());
-    return launch_finish<CA_NV>(c, (int)nb, nrhs, CA_NV, out);
+    switch (k) {
+        case 1: return ca_gram_k<S, 1>(c, P, pstride, n, nrhs, out);
+        case 2: return ca_gram_k<S, 2>(c, P, pstride, n, nrhs, out);
+        case 3: return ca_gram_k<S, 3>(c, P, pstride, n, nrhs, out);
+        case 4: return ca_gram_k<S, 4>(c, P, pstride, n, nrhs, out);
+        case 5: return ca_gram_k<S, 5>(c, P, pstride, n, nrhs, out);
+        case 6: return ca_gram_k<S, 6>(c, P, pstride, n, nrhs, out);
+        case 7: return ca_gram_k<S, 7>(c, P, pstride, n, nrhs, out);
+        case 8: return ca_gram_k<S, 8>(c, P, pstride, n, nrhs, out);
+        default: return MGLMA_ERR_ARG;
+    }
 }
 
+// Packed Gram values of dimension k per rhs (k^2 + 2k doubles, layout above).
 int mg_ca_gram(mglma_ctx* c, int prec, const void* P, size_t pstride, int k, size_t n, int nrhs, double* out) {
     if (nrhs <= 0) return MGLMA_OK;
     if (k < 1 || k > CA_K) return MGLMA_ERR_ARG;

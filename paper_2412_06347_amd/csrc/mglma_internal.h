@@ -328,7 +328,7 @@ int mg_update_norm(mglma_ctx* c, int prec, const double* a, void* e, const void*
 int mg_mr_update_h(mglma_ctx* c, const double* a, const double* scale, void* z, void* s16, const void* t16, size_t n,
                    int nrhs);
 // CA-GCR smoother (Krylov dimension k <= CA_K): packed FP64 Gram values per
-// rhs (CA_NV doubles, layout in blas.hip) and z += sum_i coef[i][r] P_i
+// rhs (k^2 + 2k <= CA_NV doubles, layout in blas.hip) and z += sum_i coef[i][r] P_i
 #define CA_K 8
 #define CA_NV (CA_K * CA_K + 2 * CA_K)
 int mg_ca_gram(mglma_ctx* c, int prec, const void* P, size_t pstride, int k, size_t n, int nrhs, double* out);

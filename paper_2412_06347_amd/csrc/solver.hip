@@ -136,23 +136,24 @@ __global__ void k_alpha(const double* dn3, double* alpha, double* nw2j, const in
 // equations G c = b of min || P_0 - sum_j c_j P_{j+1} || by Cholesky in FP64
 // (basis truncated at the first pivot below 1e-12 of its diagonal entry, so a
 // rank-deficient Krylov space is handled), coef[i][r] = scale[r] c_i.
-__global__ void k_ca_solve(const double* __restrict__ gram, int k, const double* __restrict__ scale,
+__global__ void k_ca_solve(const double* __restrict__ gram, int k, int kl, const double* __restrict__ scale,
                            double* __restrict__ coef, int nrhs) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrhs) return;
-    const double* gp = gram + (size_t)r * CA_NV;
+    // packed layout of dimension kl (>= k): diagonal, pairs i < j, then b
+    const double* gp = gram + (size_t)r * (kl * kl + 2 * kl);
     cx<double> G[CA_K][CA_K], b[CA_K], L[CA_K][CA_K], y[CA_K], cv[CA_K];
-    int o = CA_K;
+    int o = kl;
 #pragma unroll
     for (int i = 0; i < CA_K; ++i) {
-        G[i][i] = cmk(gp[i], 0.0);
+        G[i][i] = cmk(i < kl ? gp[i] : 0.0, 0.0);
 #pragma unroll
         for (int j = i + 1; j < CA_K; ++j) {
-            G[i][j] = cmk(gp[o], gp[o + 1]);
+            G[i][j] = j < kl ? cmk(gp[o], gp[o + 1]) : cmk(0.0, 0.0);
             G[j][i] = conj(G[i][j]);
-            o += 2;
+            if (j < kl) o += 2;
         }
-        b[i] = cmk(gp[CA_K + CA_K * (CA_K - 1) + 2 * i], gp[CA_K + CA_K * (CA_K - 1) + 2 * i + 1]);
+        b[i] = i < kl ? cmk(gp[kl * kl + 2 * i], gp[kl * kl + 2 * i + 1]) : cmk(0.0, 0.0);
     }
     int m = k;
 #pragma unroll
@@ -306,8 +307,8 @@ static int precondition(SolveCtx& S, int vp, const void* r, void* z) {
             MG_TRY(mg_dslash(c, sp, 0, (char*)P + (size_t)i * setsz * sb, (char*)P + (size_t)(i + 1) * setsz * sb,
                              nrhs));
         MG_TRY(mg_ca_gram(c, sp, P, setsz, k, n, nrhs, S.s.cagram()));
-        hipLaunchKernelGGL(k_ca_solve, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, S.s.cagram(), k, S.s.hscale(),
-                           S.s.cacoef(), nrhs);
+        hipLaunchKernelGGL(k_ca_solve, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, S.s.cagram(), k,
+                           k, S.s.hscale(), S.s.cacoef(), nrhs);
         MG_TRY(mg_ca_update(c, sp, P, setsz, k, S.s.cacoef(), vp, z, n, nrhs));
     } else if (sp == MGLMA_F16) {
         // half-precision storage: s16 = s / scale (entries of order one), t16 = M s16;
