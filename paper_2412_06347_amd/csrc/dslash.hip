@@ -171,10 +171,14 @@ __device__ __forceinline__ void clover_block_multi(const G* __restrict__ C, size
     (void)nb;
 }
 
-template <typename S, typename G, typename R, int NB>
-__global__ __launch_bounds__(256) void k_dslash_multi(Geo g, const S* __restrict__ in, S* __restrict__ out,
+// SO: output storage.  With rsub != null the output is (rsub - M in) / scale[rhs]
+// (the residual of an approximate solution, stored rescaled in SO).
+template <typename S, typename G, typename R, int NB, typename SO = S>
+__global__ __launch_bounds__(256) void k_dslash_multi(Geo g, const S* __restrict__ in, SO* __restrict__ out,
                                                       const G* __restrict__ U, const G* __restrict__ C, R kappa,
-                                                      int gamma5, int nrhs, int ngroups, int ntp) {
+                                                      int gamma5, int nrhs, int ngroups, int ntp,
+                                                      const S* __restrict__ rsub = nullptr,
+                                                      const double* __restrict__ scale = nullptr) {
     const int bid = blockIdx.x, xcd = bid & 7, pos = bid >> 3;
     const int tile = xcd * (ntp >> 3) + pos / ngroups, grp = pos - (pos / ngroups) * ngroups;
     const int i = tile * 256 + threadIdx.x;
@@ -198,7 +202,10 @@ __global__ __launch_bounds__(256) void k_dslash_multi(Geo g, const S* __restrict
     hop_multi<2, false, S, G, R, NB>(g, i, lc, yc, pin, rstride, nb, U, acc);
     hop_multi<3, true, S, G, R, NB>(g, i, lc, yc, pin, rstride, nb, U, acc);
     hop_multi<3, false, S, G, R, NB>(g, i, lc, yc, pin, rstride, nb, U, acc);
-    S* po = out + (size_t)r0 * rstride;
+    SO* po = out + (size_t)r0 * rstride;
+    R isc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) isc[b] = (rsub && b < nb) ? (R)(1.0 / scale[r0 + b]) : (R)1;
 #pragma unroll
     for (int ch = 0; ch < 2; ++ch) {
         cx<R> p[NB][6], res[NB][6];
@@ -216,7 +223,9 @@ __global__ __launch_bounds__(256) void k_dslash_multi(Geo g, const S* __restrict
             for (int k = 0; k < 6; ++k) {
                 cx<R> v = res[b][k] - kappa * acc[b][6 * ch + k];
                 if (gamma5 && ch == 1) v = -v;
-                stc<S, R>(po + (size_t)b * rstride + (size_t)(6 * ch + k) * V + i, v);
+                const size_t o = (size_t)b * rstride + (size_t)(6 * ch + k) * V + i;
+                if (rsub) v = isc[b] * (ldc<S, R>(rsub + (size_t)r0 * rstride + o) - v);
+                stc<SO, R>(po + o, v);
             }
         }
     }
@@ -267,6 +276,21 @@ int mg_dslash(mglma_ctx* c, int prec, int gamma5, const void* in, void* out, int
             break;
         default: return MGLMA_ERR_ARG;
     }
+    HIP_TRY(hipGetLastError());
+    return MGLMA_OK;
+}
+
+// p16 = (r - M z) / scale[rhs] in FP16, from FP32 z and r (the rescaled
+// residual that starts the FP16 smoother), one launch.
+int mg_dslash_resid16(mglma_ctx* c, const void* z, const void* r, void* p16, const double* scale, int nrhs) {
+    if (nrhs <= 0) return MGLMA_OK;
+    const Geo& g = c->geo;
+    const int ntp = ((g.V + 255) / 256 + 7) / 8 * 8;
+    const int ng = (nrhs + 1) / 2;
+    if ((size_t)ntp * ng > 0x7fffffffu) return MGLMA_ERR_SHAPE;
+    hipLaunchKernelGGL((k_dslash_multi<float2, float2, float, 2, __half2>), dim3(ntp * ng), dim3(256), 0, c->stream,
+                       g, (const float2*)z, (__half2*)p16, c->U32, c->C32, (float)c->kappa, 0, nrhs, ng, ntp,
+                       (const float2*)r, scale);
     HIP_TRY(hipGetLastError());
     return MGLMA_OK;
 }

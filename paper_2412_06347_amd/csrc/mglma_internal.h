@@ -274,6 +274,7 @@ int mg_host(mglma_ctx* c, size_t ndoubles, double** out);
 // kernel launchers shared between translation units
 // ---------------------------------------------------------------------------
 int mg_dslash(mglma_ctx* c, int prec, int gamma5, const void* in, void* out, int nrhs);
+int mg_dslash_resid16(mglma_ctx* c, const void* z, const void* r, void* p16, const double* scale, int nrhs);
 
 // BLAS-1 on fine or coarse vectors of `n` complex per right-hand side
 // (prec F64 or F32 or F16 storage).  Scalars live in device memory.

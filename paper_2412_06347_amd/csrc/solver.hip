@@ -285,10 +285,30 @@ static int precondition(SolveCtx& S, int vp, const void* r, void* z) {
     }
     if (p->nu_post <= 0) return MGLMA_OK;
     // MR smoothing on M z = r: s = r - M z; t = M s; omega = <t,s>/<t,t>; z += omega s; s -= omega t
+    const int sp = (vp == MGLMA_F32 && p->smoother == MGLMA_F16) ? MGLMA_F16 : vp;
+    if (p->smoother_alg == MGLMA_SMOOTH_CAGCR && sp == MGLMA_F16) {
+        // FP16 CA-GCR: P_0 = (r - M z) / scale straight from the FP32 apply,
+        // scale = rms of r (its norm is on the device already)
+        const int k = p->nu_post;
+        const size_t setsz = (size_t)nrhs * n, sb = prec_cbytes(sp);
+        void* P;
+        MG_TRY(mg_scratch(c, WS_CAP, (size_t)(k + 1) * setsz * sb, &P));
+        hipLaunchKernelGGL(k_rms, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, S.s.rn2(), (double)n, S.s.hscale(),
+                           nrhs);
+        MG_TRY(mg_dslash_resid16(c, z, r, P, S.s.hscale(), nrhs));
+        for (int i = 0; i < k; ++i)
+            MG_TRY(mg_dslash(c, sp, 0, (char*)P + (size_t)i * setsz * sb, (char*)P + (size_t)(i + 1) * setsz * sb,
+                             nrhs));
+        MG_TRY(mg_ca_gram(c, sp, P, setsz, k, n, nrhs, S.s.cagram()));
+        hipLaunchKernelGGL(k_ca_solve, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, S.s.cagram(), k, k,
+                           S.s.hscale(), S.s.cacoef(), nrhs);
+        MG_TRY(mg_ca_update(c, sp, P, setsz, k, S.s.cacoef(), vp, z, n, nrhs));
+        HIP_TRY(hipGetLastError());
+        return MGLMA_OK;
+    }
     void *s, *t;
     MG_TRY(mg_scratch(c, WS_SS, (size_t)nrhs * n * vb, &s));
     MG_TRY(mg_scratch(c, WS_ST, (size_t)nrhs * n * vb, &t));
-    const int sp = (vp == MGLMA_F32 && p->smoother == MGLMA_F16) ? MGLMA_F16 : vp;
     MG_TRY(mg_dslash(c, vp, 0, z, t, nrhs));
     MG_TRY(mg_sub(c, vp, r, t, s, n, nrhs));
     if (p->smoother_alg == MGLMA_SMOOTH_CAGCR) {
