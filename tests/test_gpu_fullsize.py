@@ -1,0 +1,141 @@
+"""The 48 x 24^3 workload of the benchmark at full size, in the launch
+configuration it times (12 right-hand sides, 4^4 blocks, N_v = 24), checked
+against the oracle on sampled outputs and by properties that hold at any size:
+
+* the FP64 apply against the oracle's M on two fields, and the FP32 / FP16
+  12-RHS applies on the same two fields placed among ten others;
+* the block basis of sampled blocks against the oracle's Gram-Schmidt of the
+  same test vectors, orthonormality of every block;
+* the Galerkin identity D_1 v = R M T v in FP64;
+* the benchmark's own pipeline and solver settings: every right-hand side to a
+  true relative residual of 1e-10, two of them re-checked with the oracle's M.
+"""
+import numpy as np
+import pytest
+
+from oracle import dirac, estimators, subspace
+from paper_2412_06347_amd import synth
+from tests.gpu_util import to_dev, from_dev, relerr
+
+pytestmark = pytest.mark.gpu
+
+L = (48, 24, 24, 24)
+B = (4, 4, 4, 4)
+EPS, KAPPA, CSW, SEED = 0.25, 0.125, 1.0, 3
+
+
+@pytest.fixture(scope="module")
+def ens():
+    U = synth.gauge_field(L, EPS, SEED)
+    D = dirac.WilsonClover(U, L, KAPPA, CSW)
+    return U, D
+
+
+def _ctx(U):
+    from paper_2412_06347_amd import mglma
+    ctx = mglma.Context(L, B, KAPPA, CSW)
+    ctx.load_gauge(to_dev(U))
+    return ctx
+
+
+def test_fullsize_applies(ens):
+    import torch
+    from paper_2412_06347_amd import mglma
+    U, D = ens
+    psi = synth.gaussian_fields(2, L, 91)
+    ref = dirac.fields_to_canonical(D.M(dirac.fields_to_lattice(psi, L)))
+    ctx = _ctx(U)
+    # FP64, two right-hand sides
+    x = ctx.fine(2)
+    ctx.import_fields(to_dev(psi), x)
+    y = ctx.fine(2)
+    ctx.apply_D(x, y)
+    out = torch.empty((2, ctx.V, 4, 3, 2), dtype=torch.float64, device="cuda")
+    ctx.export_fields(y, out)
+    assert relerr(from_dev(out), ref) < 1e-12
+    # the 12-RHS launches the solver runs, the two fields at slots 3 and 8
+    batch = synth.gaussian_fields(12, L, 92)
+    batch[3], batch[8] = psi[0], psi[1]
+    xb = ctx.fine(12)
+    ctx.import_fields(to_dev(batch), xb)
+    for prec, tol in ((mglma.F32, 2e-6), (mglma.F16, 5e-3)):
+        xp = ctx.fine(12, prec)
+        ctx.import_fields(to_dev(batch), xp, prec)
+        yp = ctx.fine(12, prec)
+        ctx.apply_D(xp, yp, prec)
+        o = torch.empty((12, ctx.V, 4, 3, 2), dtype=torch.float64, device="cuda")
+        ctx.export_fields(yp, o, prec)
+        got = from_dev(o)[[3, 8]]
+        err = relerr(got, ref)
+        print("12-rhs apply prec %d rel err %.2e" % (prec, err))
+        assert err < tol
+
+
+def test_fullsize_basis_and_galerkin(ens):
+    import torch
+    U, D = ens
+    Nv = 24
+    ctx = _ctx(U)
+    tv = synth.gaussian_fields(Nv, L, 1003)
+    x = ctx.fine(Nv)
+    ctx.import_fields(to_dev(tv), x)
+    ctx.build_subspace(x)
+    bl = subspace.Blocking(L, B)
+    nc = 2 * Nv
+    out = torch.empty((bl.V1, nc, bl.Vb, 4, 3, 2), dtype=torch.float64, device="cuda")
+    ctx.export_basis(out)
+    # orthonormality of every block (each chirality half, on the device)
+    ob = out[..., 0] + 1j * out[..., 1]
+    ob = ob.reshape(bl.V1, nc, -1)
+    G = torch.einsum("yik,yjk->yij", ob.conj(), ob)
+    eye = torch.eye(nc, dtype=G.dtype, device=G.device)
+    assert float((G - eye).abs().max()) < 1e-12
+    # sampled blocks against the oracle's Gram-Schmidt of the same test vectors
+    ys = [0, 1, 777, bl.V1 - 1]
+    tb = bl.to_blocks(dirac.fields_to_lattice(tv, L))[:, ys]          # [Nv][ns][b..][4][3]
+    tb = np.moveaxis(tb, 0, 1)                                         # [ns][Nv][b..][4][3]
+    got = from_dev(out[ys])                                            # [ns][nc][Vb][4][3]
+    for a in range(2):
+        w = tb[..., 2 * a:2 * a + 2, :].reshape(len(ys), Nv, -1)
+        q = subspace.gram_schmidt(w).reshape(len(ys), Nv, bl.Vb, 2, 3)
+        g = got[:, a * Nv:(a + 1) * Nv, :, 2 * a:2 * a + 2, :]
+        assert np.abs(g - q).max() < 1e-12
+        assert np.abs(got[:, a * Nv:(a + 1) * Nv, :, 2 - 2 * a:4 - 2 * a, :]).max() == 0.0
+    del out, ob, G
+    # Galerkin identity D_1 v = R M T v, FP64
+    v = synth.gaussian_coarse(2, bl.V1, nc, 93)
+    vd = to_dev(v)
+    y1 = torch.empty_like(vd)
+    ctx.coarse_apply(vd, y1)
+    f = ctx.fine(2)
+    ctx.prolong(vd, f)
+    g2 = ctx.fine(2)
+    ctx.apply_D(f, g2)
+    y2 = torch.empty_like(vd)
+    ctx.restrict(g2, y2)
+    assert relerr(from_dev(y1), from_dev(y2)) < 1e-12
+
+
+def test_fullsize_bench_solve(ens):
+    """The benchmark's pipeline and mixed-precision settings."""
+    import torch
+    import bench
+    from paper_2412_06347_amd import mglma
+    U, D = ens
+    P = bench.Pipeline(bench.WORKLOADS["24c48"], log_setup=False)
+    stats, levels = P.step(bench.mixed_params(mglma))
+    torch.cuda.synchronize()
+    res = [s["true_rel_res"] for s in stats]
+    print("true rel res", max(res), "inner", [s["inner"] for s in stats][:1])
+    assert len(stats) == 12 and max(res) <= 1e-10 and all(s["status"] == 0 for s in stats)
+    # two of the twelve re-checked with the oracle's operator
+    b = estimators.point_sources(L, (0, 0, 0, 0))
+    out = torch.empty((12, P.ctx.V, 4, 3, 2), dtype=torch.float64, device="cuda")
+    P.ctx.export_fields(P.x, out)
+    xs = from_dev(out)[[0, 7]]
+    bs = dirac.fields_to_canonical(b[[0, 7]])
+    r = dirac.fields_to_canonical(D.M(dirac.fields_to_lattice(xs, L))) - bs
+    rel = np.linalg.norm(r.reshape(2, -1), axis=1) / np.linalg.norm(bs.reshape(2, -1), axis=1)
+    print("oracle true rel res", rel)
+    assert np.all(rel <= 1.05e-10)
+    assert all(np.all(np.isfinite(v)) for v in levels.values())
