@@ -113,7 +113,7 @@ class Pipeline:
         ctx.set_top_modes(self.modes)                  # W, D_2, (gamma5 gamma_k)_2
         ctx.point_sources((0, 0, 0, 0), self.src)      # 12 point sources
         rc, stats = ctx.solve(self.src, self.x, params)
-        cp = mglma.default_params(tol=1e-10, coarse=mglma.F32, coarse_iters=24)
+        cp = mglma.default_params(tol=1e-10, coarse=mglma.BF16, coarse_iters=16, max_outer=40)
         ctx.coarse_pieces(self.src, self.cg, self.ct, cp)
         C_all = ctx.contract_point(self.x, self.x, 0)
         C_ge1 = ctx.contract_point_coarse(self.cg, self.cg, 0)

@@ -226,7 +226,8 @@ static int coarse_gcr_fixed(SolveCtx& S, int vp, int op, const void* b, void* x,
     const int nrhs = S.nrhs;
     const size_t n = coarse_n(c);
     const size_t vb = prec_cbytes(vp);
-    const int mc = iters < 8 ? iters : 8;
+    // restart length: all iterations up to the direction storage of S.s (>= 8)
+    const int mc = iters < S.s.m ? iters : S.s.m;
     void *P, *Q, *r;
     MG_TRY(mg_scratch(c, WS_CP, (size_t)mc * nrhs * n * vb, &P));
     MG_TRY(mg_scratch(c, WS_CQ, (size_t)mc * nrhs * n * vb, &Q));
@@ -532,7 +533,8 @@ int mg_coarse_solve(mglma_ctx* c, const mglma_solve_params* p, const double* b, 
     SolveCtx S;
     S.c = c; S.p = p; S.nrhs = nrhs;
     S.s.nrhs = nrhs;
-    S.s.m = 8;
+    // coarse GCR without restarts for up to 32 steps per defect-correction cycle
+    S.s.m = p->coarse_iters < 8 ? 8 : (p->coarse_iters > 32 ? 32 : p->coarse_iters);
     MG_TRY(mg_scratch(c, WS_SCAL, Scal::bytes(nrhs, S.s.m), (void**)&S.s.base));
     const int vp = p->inner == MGLMA_F64 ? MGLMA_F64 : MGLMA_F32;
     double2 *r64, *t64;

@@ -118,7 +118,8 @@ class Engine:
                                                      inner_tol=1e-5, nu_post=6, coarse_iters=8,
                                                      smoother=mglma.F16, inner=mglma.F32, coarse=mglma.BF16,
                                                      smoother_alg=mglma.SMOOTH_CAGCR)
-        self.coarse_params = coarse_params or mglma.default_params(tol=1e-10, coarse=mglma.F32, coarse_iters=24)
+        self.coarse_params = coarse_params or mglma.default_params(tol=1e-10, coarse=mglma.BF16, coarse_iters=16,
+                                                                   max_outer=40)
         self.resident = ctx.resident_bytes() + self.U.numel() * 8
 
     @property
