@@ -171,9 +171,9 @@ __device__ __forceinline__ void clover_block_multi(const G* __restrict__ C, size
     (void)nb;
 }
 
-// SO: output storage.  With rsub != null the output is (rsub - M in) / scale[rhs]
-// (the residual of an approximate solution, stored rescaled in SO).
-template <typename S, typename G, typename R, int NB, typename SO = S>
+// SO: output storage.  RESID: the output is (rsub - M in) / scale[rhs] (the
+// residual of an approximate solution, stored rescaled in SO).
+template <typename S, typename G, typename R, int NB, typename SO = S, bool RESID = false>
 __global__ __launch_bounds__(256) void k_dslash_multi(Geo g, const S* __restrict__ in, SO* __restrict__ out,
                                                       const G* __restrict__ U, const G* __restrict__ C, R kappa,
                                                       int gamma5, int nrhs, int ngroups, int ntp,
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(256) void k_dslash_multi(Geo g, const S* __restrict
     SO* po = out + (size_t)r0 * rstride;
     R isc[NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) isc[b] = (rsub && b < nb) ? (R)(1.0 / scale[r0 + b]) : (R)1;
+    for (int b = 0; b < NB; ++b) isc[b] = (RESID && b < nb) ? (R)(1.0 / scale[r0 + b]) : (R)1;
 #pragma unroll
     for (int ch = 0; ch < 2; ++ch) {
         cx<R> p[NB][6], res[NB][6];
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(256) void k_dslash_multi(Geo g, const S* __restrict
                 cx<R> v = res[b][k] - kappa * acc[b][6 * ch + k];
                 if (gamma5 && ch == 1) v = -v;
                 const size_t o = (size_t)b * rstride + (size_t)(6 * ch + k) * V + i;
-                if (rsub) v = isc[b] * (ldc<S, R>(rsub + (size_t)r0 * rstride + o) - v);
+                if (RESID) v = isc[b] * (ldc<S, R>(rsub + (size_t)r0 * rstride + o) - v);
                 stc<SO, R>(po + o, v);
             }
         }
@@ -288,7 +288,7 @@ int mg_dslash_resid16(mglma_ctx* c, const void* z, const void* r, void* p16, con
     const int ntp = ((g.V + 255) / 256 + 7) / 8 * 8;
     const int ng = (nrhs + 1) / 2;
     if ((size_t)ntp * ng > 0x7fffffffu) return MGLMA_ERR_SHAPE;
-    hipLaunchKernelGGL((k_dslash_multi<float2, float2, float, 2, __half2>), dim3(ntp * ng), dim3(256), 0, c->stream,
+    hipLaunchKernelGGL((k_dslash_multi<float2, float2, float, 2, __half2, true>), dim3(ntp * ng), dim3(256), 0, c->stream,
                        g, (const float2*)z, (__half2*)p16, c->U32, c->C32, (float)c->kappa, 0, nrhs, ng, ntp,
                        (const float2*)r, scale);
     HIP_TRY(hipGetLastError());
