@@ -331,7 +331,7 @@ def main():
         "fp64_path": fp64,
         "speedup_mixed_vs_fp64": (value / fp64["solves_per_s"]) if fp64 else None,
         "dslash_GBs": dslash_gbs,
-        "roofline": {"bound": "hbm", "kernel": "k_dslash_multi<__half2,__half2,float,2,__half2,false> (FP16, 12 RHS)",
+        "roofline": {"bound": "hbm", "kernel": "k_dslash_h<3> (FP16 packed, 12 RHS)",
                      "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                      "traffic": traffic, "avg_ms": ms16,
                      "alg_bytes_per_launch": dslash_alg_bytes(V, nr, 2)},

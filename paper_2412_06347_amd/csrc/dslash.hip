@@ -10,7 +10,9 @@
 // are stored site-innermost, so every load of a wavefront is one contiguous
 // run.  Each hop is spin-projected to a half spinor (rank-2 projector
 // 1 -/+ gamma_mu in the chiral basis), multiplied by the link and expanded.
-// Storage is FP64, FP32 or FP16; FP16 and FP32 compute in FP32.
+// Storage is FP64, FP32 or FP16; FP32 computes in FP32.  FP16 computes in
+// FP32 for one right-hand side and on the packed FP16 data with FP32
+// accumulation for batches (k_dslash_h).
 #include "mglma_internal.h"
 #include "wilson.h"
 
@@ -231,6 +233,229 @@ __global__ __launch_bounds__(256) void k_dslash_multi(Geo g, const S* __restrict
     }
 }
 
+// ---------------------------------------------------------------------------
+// FP16 storage computed on the packed FP16 data.  A complex number z = (x, y)
+// stays one packed register; the spin projection is one packed FP16 add per
+// entry (the sign and swap variants below are operand modifiers of that add),
+// and every complex product is two v_dot2_f32_f16, each the sum of two FP16
+// products added to an FP32 accumulator.  Links, clover and spinors are
+// never unpacked; all sums over colour, spin and hops are FP32.
+// ---------------------------------------------------------------------------
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float dot2(h2 a, h2 b, float c) { return __builtin_amdgcn_fdot2(a, b, c, false); }
+
+// forms of z = (x, y) that turn complex products into two dot products:
+//   u z:        re = u.(x,-y)  im = u.(y,x)
+//   conj(u) z:  re = u.(x,y)   im = u.(y,-x)
+enum { FZ = 0, FN = 1, FS = 2, FSN = 3 };
+template <int F> __device__ __forceinline__ h2 form(h2 z) {
+    if (F == FZ) return z;
+    if (F == FN) return h2{z.x, -z.y};
+    if (F == FS) return h2{z.y, z.x};
+    return h2{z.y, -z.x};
+}
+// SG * q (I = false) or SG * i q (I = true)
+template <bool I, int SG> __device__ __forceinline__ h2 tq(h2 q) {
+    if (!I) return SG > 0 ? q : h2{-q.x, -q.y};
+    return SG > 0 ? h2{-q.y, q.x} : h2{q.y, -q.x};
+}
+// form F of p0 + SG (i) q: one packed add, the form applied to both operands
+template <int F, bool I, int SG> __device__ __forceinline__ h2 proj_f(h2 p0, h2 q) {
+    return form<F>(p0) + form<F>(tq<I, SG>(q));
+}
+
+// Half spinor of the hop (the projection of the scalar code, spin by spin):
+// upper spin s = 0 pairs with lower spin Q0, s = 1 with Q1, signs S0, S1,
+// times i for mu = 1, 3.  Forward hops need the forms FN, FS of every entry,
+// backward hops FZ, FSN.
+template <int MU, bool FWD, int F>
+__device__ __forceinline__ void proj_h(const h2 p[12], h2 h[6]) {
+    constexpr int s = FWD ? 1 : -1;
+    constexpr bool I = (MU == 1 || MU == 3);
+    constexpr int Q0 = (MU == 0 || MU == 3) ? 2 : 3, Q1 = (MU == 0 || MU == 3) ? 3 : 2;
+    constexpr int S0 = s, S1 = (MU >= 2) ? -s : s;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        h[a] = proj_f<F, I, S0>(p[a], p[3 * Q0 + a]);
+        h[3 + a] = proj_f<F, I, S1>(p[3 + a], p[3 * Q1 + a]);
+    }
+}
+
+// acc += sg * (full spinor reconstructed from the link-multiplied half spinor o)
+template <int MU, bool FWD>
+__device__ __forceinline__ void recon_h(cx<float> acc[12], const cx<float> o[6], float sg) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const cx<float> h0 = o[a], h1 = o[3 + a];
+        cx<float> l2, l3;
+        if (MU == 0) { l2 = FWD ? h0 : -h0; l3 = FWD ? h1 : -h1; }
+        else if (MU == 1) { l2 = FWD ? mul_mi(h1) : mul_i(h1); l3 = FWD ? mul_mi(h0) : mul_i(h0); }
+        else if (MU == 2) { l2 = FWD ? -h1 : h1; l3 = FWD ? h0 : -h0; }
+        else { l2 = FWD ? mul_mi(h0) : mul_i(h0); l3 = FWD ? mul_i(h1) : mul_mi(h1); }
+        acc[a].re = fmaf(sg, h0.re, acc[a].re); acc[a].im = fmaf(sg, h0.im, acc[a].im);
+        acc[3 + a].re = fmaf(sg, h1.re, acc[3 + a].re); acc[3 + a].im = fmaf(sg, h1.im, acc[3 + a].im);
+        acc[6 + a].re = fmaf(sg, l2.re, acc[6 + a].re); acc[6 + a].im = fmaf(sg, l2.im, acc[6 + a].im);
+        acc[9 + a].re = fmaf(sg, l3.re, acc[9 + a].re); acc[9 + a].im = fmaf(sg, l3.im, acc[9 + a].im);
+    }
+}
+
+// Buffer loads and stores: the per-component offset (component x V) is
+// uniform and goes in a scalar register, the site offset is the only vector
+// operand, so no load or store needs a 64-bit vector address.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+__device__ __forceinline__ rsrc_t mk_rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ h2 bld(rsrc_t r, uint32_t site, uint32_t comp) {
+    return __builtin_bit_cast(h2, __builtin_amdgcn_raw_buffer_load_b32(r, site * 4u, comp * 4u, 0));
+}
+__device__ __forceinline__ void bst(rsrc_t r, uint32_t site, uint32_t comp, h2 v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, site * 4u, comp * 4u, 0);
+}
+
+// One hop for the nb <= NB right-hand sides of a group.  pin: spinors of the
+// group, right-hand side b at component offset b * 12 V; U: links, component
+// (mu * 9 + e) V.
+template <int MU, bool FWD, int NB>
+__device__ __forceinline__ void hop_h(const Geo& g, int i, const int lc[4], const int yc[4], rsrc_t pin, uint32_t V,
+                                      int nb, rsrc_t U, cx<float> acc[NB][12]) {
+    bool wrap;
+    const int j = FWD ? geo_fwd(g, i, MU, lc, yc, &wrap) : geo_bwd(g, i, MU, lc, yc, &wrap);
+    const uint32_t us = FWD ? i : j;
+    h2 u[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) u[e] = bld(U, us, (MU * 9 + e) * V);
+    const float sg = (wrap && g.bcneg[MU]) ? -1.f : 1.f;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        if (b >= nb) break;   // uniform; also keeps each hop's loads next to their use
+        h2 p[12];
+#pragma unroll
+        for (int sc = 0; sc < 12; ++sc) p[sc] = bld(pin, j, (b * 12 + sc) * V);
+        h2 hre[6], him[6];
+        proj_h<MU, FWD, FWD ? FN : FZ>(p, hre);
+        proj_h<MU, FWD, FWD ? FS : FSN>(p, him);
+        cx<float> o[6];
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                float re = 0.f, im = 0.f;
+#pragma unroll
+                for (int c2 = 0; c2 < 3; ++c2) {
+                    const h2 uu = FWD ? u[a * 3 + c2] : u[c2 * 3 + a];
+                    re = dot2(uu, hre[sp * 3 + c2], re);
+                    im = dot2(uu, him[sp * 3 + c2], im);
+                }
+                o[sp * 3 + a] = cmk(re, im);
+            }
+        recon_h<MU, FWD>(acc[b], o, sg);
+    }
+}
+
+// res[b] += C_ch p[b] for one chiral block (packed Hermitian 6x6 at component
+// offset ch * 18 V)
+template <int NB>
+__device__ __forceinline__ void clover_h(rsrc_t C, uint32_t V, int ch, int i, const h2 (*p)[6], cx<float> (*res)[6]) {
+    const uint32_t c0 = ch * 18;
+    h2 d[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) d[m] = bld(C, i, (c0 + m) * V);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const _Float16 z = (_Float16)0;
+        const h2 xr = h2{d[m].x, z}, xi = h2{z, d[m].x}, yr = h2{d[m].y, z}, yi = h2{z, d[m].y};
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            res[b][2 * m].re = dot2(xr, p[b][2 * m], res[b][2 * m].re);
+            res[b][2 * m].im = dot2(xi, p[b][2 * m], res[b][2 * m].im);
+            res[b][2 * m + 1].re = dot2(yr, p[b][2 * m + 1], res[b][2 * m + 1].re);
+            res[b][2 * m + 1].im = dot2(yi, p[b][2 * m + 1], res[b][2 * m + 1].im);
+        }
+    }
+    uint32_t k = 3;
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+        for (int c = r + 1; c < 6; ++c) {
+            const h2 a = bld(C, i, (c0 + k) * V);
+            ++k;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                res[b][r].re = dot2(a, form<FN>(p[b][c]), res[b][r].re);
+                res[b][r].im = dot2(a, form<FS>(p[b][c]), res[b][r].im);
+                res[b][c].re = dot2(a, p[b][r], res[b][c].re);
+                res[b][c].im = dot2(a, form<FSN>(p[b][r]), res[b][c].im);
+            }
+        }
+}
+
+// NB right-hand sides per thread.  The host guarantees NB * 12 * V * 4 bytes
+// and 36 * V * 4 bytes fit the 32-bit range of a buffer resource.
+template <int NB>
+__global__ __launch_bounds__(256) void k_dslash_h(Geo g, const h2* __restrict__ in, h2* __restrict__ out,
+                                                  const h2* __restrict__ U, const h2* __restrict__ C, float kappa,
+                                                  int gamma5, int nrhs, int ngroups, int ntp) {
+    const int bid = blockIdx.x, xcd = bid & 7, pos = bid >> 3;
+    const int tile = xcd * (ntp >> 3) + pos / ngroups, grp = pos - (pos / ngroups) * ngroups;
+    const int i = tile * 256 + threadIdx.x;
+    if (i >= g.V) return;
+    const uint32_t V = g.V;
+    const int r0 = grp * NB;
+    const int nb = nrhs - r0 < NB ? nrhs - r0 : NB;
+    // the clover step loads right-hand sides past the end of the batch as the
+    // group's first (valid memory) and does not store them
+    int rb[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) rb[b] = b < nb ? b : 0;
+    const rsrc_t pin = mk_rsrc(in + (size_t)r0 * 12 * V, (uint32_t)nb * 12u * V * 4u);
+    const rsrc_t po = mk_rsrc(out + (size_t)r0 * 12 * V, (uint32_t)nb * 12u * V * 4u);
+    const rsrc_t ru = mk_rsrc(U, 36u * V * 4u), rc = mk_rsrc(C, 36u * V * 4u);
+    int lc[4], yc[4];
+    geo_coords(g, i, lc, yc);
+    cx<float> acc[NB][12];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[b][k] = cmk(0.f, 0.f);
+    hop_h<0, true, NB>(g, i, lc, yc, pin, V, nb, ru, acc);
+    hop_h<0, false, NB>(g, i, lc, yc, pin, V, nb, ru, acc);
+    hop_h<1, true, NB>(g, i, lc, yc, pin, V, nb, ru, acc);
+    hop_h<1, false, NB>(g, i, lc, yc, pin, V, nb, ru, acc);
+    hop_h<2, true, NB>(g, i, lc, yc, pin, V, nb, ru, acc);
+    hop_h<2, false, NB>(g, i, lc, yc, pin, V, nb, ru, acc);
+    hop_h<3, true, NB>(g, i, lc, yc, pin, V, nb, ru, acc);
+    hop_h<3, false, NB>(g, i, lc, yc, pin, V, nb, ru, acc);
+#pragma unroll
+    for (int ch = 0; ch < 2; ++ch) {
+        h2 p[NB][6];
+        cx<float> res[NB][6];
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                p[b][k] = bld(pin, i, (rb[b] * 12 + 6 * ch + k) * V);
+                res[b][k] = -kappa * acc[b][6 * ch + k];
+            }
+        clover_h<NB>(rc, V, ch, i, p, res);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            if (b >= nb) break;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                cx<float> v = res[b][k];
+                if (gamma5 && ch == 1) v = -v;
+                bst(po, i, (b * 12 + 6 * ch + k) * V, h2{(_Float16)v.re, (_Float16)v.im});
+            }
+        }
+    }
+}
+
+// The packed kernel addresses a group of three right-hand sides (3 * 12 * V
+// values) and the 36 V link and clover values through 32-bit buffer offsets.
+static bool dslash_h_fits(size_t V) { return V * 36 * 4 < ((size_t)1 << 31); }
+
 int mg_dslash(mglma_ctx* c, int prec, int gamma5, const void* in, void* out, int nrhs) {
     if (nrhs == 0) return MGLMA_OK;
     const Geo& g = c->geo;
@@ -251,9 +476,17 @@ int mg_dslash(mglma_ctx* c, int prec, int gamma5, const void* in, void* out, int
                                    ntp);
                 break;
             case MGLMA_F16:
-                hipLaunchKernelGGL((k_dslash_multi<__half2, __half2, float, 2>), gm, dim3(256), 0, c->stream, g,
-                                   (const __half2*)in, (__half2*)out, c->U16, c->C16, (float)c->kappa, gamma5, nrhs,
-                                   ng, ntp);
+                if (dslash_h_fits(g.V)) {
+                    // packed FP16 arithmetic, three right-hand sides per thread
+                    const int ng3 = (nrhs + 2) / 3;
+                    hipLaunchKernelGGL((k_dslash_h<3>), dim3(ntp * ng3), dim3(256), 0, c->stream, g, (const h2*)in,
+                                       (h2*)out, (const h2*)c->U16, (const h2*)c->C16, (float)c->kappa, gamma5, nrhs,
+                                       ng3, ntp);
+                } else {
+                    hipLaunchKernelGGL((k_dslash_multi<__half2, __half2, float, 2>), gm, dim3(256), 0, c->stream, g,
+                                       (const __half2*)in, (__half2*)out, c->U16, c->C16, (float)c->kappa, gamma5,
+                                       nrhs, ng, ntp);
+                }
                 break;
             default: return MGLMA_ERR_ARG;
         }

@@ -67,6 +67,36 @@ def test_apply_parity(case, gamma5):
         assert err < tol
 
 
+@pytest.mark.parametrize("nrhs", [2, 4, 7])
+def test_apply_f16_batches(nrhs):
+    """FP16 batches go through the packed kernel in groups of three right-hand
+    sides; ragged last groups (4 = 3 + 1, 7 = 3 + 3 + 1) and a lattice whose
+    volume is not a multiple of the 256-site tile (6 x 4 x 6 x 2 = 288)."""
+    import torch
+    from paper_2412_06347_amd import mglma
+    case = CASES[1]
+    L = case[0]
+    ctx, U = _ctx(*case)
+    D = dirac.WilsonClover(U, L, case[2], case[3])
+    psi = synth.gaussian_fields(nrhs, L, seed=70 + nrhs)
+    for gamma5 in (0, 1):
+        ref = D.M(dirac.fields_to_lattice(psi, L))
+        if gamma5:
+            ref = dirac.gamma5_field(ref)
+        ref = dirac.fields_to_canonical(ref)
+        x = ctx.fine(nrhs, mglma.F16)
+        y = ctx.fine(nrhs, mglma.F16)
+        ctx.import_fields(to_dev(psi), x, mglma.F16)
+        ctx.apply_D(x, y, mglma.F16, gamma5)
+        out = torch.empty((nrhs, ctx.V, 4, 3, 2), dtype=torch.float64, device="cuda")
+        ctx.export_fields(y, out, mglma.F16)
+        got = from_dev(out)
+        for r in range(nrhs):
+            err = relerr(got[r], ref[r])
+            print("nrhs=%d rhs=%d gamma5=%d rel err %.3e" % (nrhs, r, gamma5, err))
+            assert err < 2e-3
+
+
 def test_import_export_roundtrip():
     import torch
     from paper_2412_06347_amd import mglma
