@@ -148,10 +148,16 @@ __device__ __forceinline__ void write_partial(double (&v)[NV], double* lds, doub
 
 // Second pass, one workgroup per rhs: add the nb partials (each thread a
 // fixed strided share, then the same tree as above).  mode 0 writes
-// out[r][k]; mode 1 (multi-dot) writes the complex out[k / 2][ostride][r].
+// out[r][k]; mode 1 (multi-dot) writes the complex out[k / 2][ostride][r],
+// divided by div[k / 2][ostride][r] when div is given (0 where that is not
+// positive); mode 2 takes (Re <w,r>, Im <w,r>, |w|^2) and writes the step
+// alpha = <w,r> / |w|^2 to out[r] (complex; 0 where |w|^2 is not positive or
+// mask[r] == 0) and |w|^2 to aux[r].
 template <int NV>
 __global__ __launch_bounds__(RB) void k_finish(const double* __restrict__ part, int nb, int nvals,
-                                               double* __restrict__ out, int mode, int ostride) {
+                                               double* __restrict__ out, int mode, int ostride,
+                                               const double* __restrict__ div, double* __restrict__ aux,
+                                               const int* __restrict__ mask) {
     __shared__ double lds[4 * NV];
     const int r = blockIdx.x;
     double s[NV];
@@ -165,16 +171,32 @@ __global__ __launch_bounds__(RB) void k_finish(const double* __restrict__ part, 
     }
     block_sum<NV>(s, lds);
     if (threadIdx.x == 0) {
+        if (mode == 2) {
+            const double d = s[NV > 2 ? 2 : 0];
+            const bool on = (mask == nullptr || mask[r]) && d > 0.0;
+            out[2 * r] = on ? s[0] / d : 0.0;
+            out[2 * r + 1] = on ? s[NV > 1 ? 1 : 0] / d : 0.0;
+            if (aux) aux[r] = d;
+            return;
+        }
         for (int k = 0; k < nvals; ++k) {
-            if (mode == 0) out[(size_t)r * nvals + k] = s[k];
-            else out[((size_t)(k >> 1) * ostride + r) * 2 + (k & 1)] = s[k];
+            if (mode == 0) {
+                out[(size_t)r * nvals + k] = s[k];
+            } else {
+                const size_t o = (size_t)(k >> 1) * ostride + r;
+                double v = s[k];
+                if (div) v = div[o] > 0.0 ? v / div[o] : 0.0;
+                out[o * 2 + (k & 1)] = v;
+            }
         }
     }
 }
 
 template <int NV>
-static int launch_finish(mglma_ctx* c, int nb, int nrhs, int nvals, double* out, int mode = 0, int ostride = 0) {
-    hipLaunchKernelGGL(k_finish<NV>, dim3(nrhs), dim3(RB), 0, c->stream, c->red_part, nb, nvals, out, mode, ostride);
+static int launch_finish(mglma_ctx* c, int nb, int nrhs, int nvals, double* out, int mode = 0, int ostride = 0,
+                         const double* div = nullptr, double* aux = nullptr, const int* mask = nullptr) {
+    hipLaunchKernelGGL(k_finish<NV>, dim3(nrhs), dim3(RB), 0, c->stream, c->red_part, nb, nvals, out, mode, ostride,
+                       div, aux, mask);
     HIP_TRY(hipGetLastError());
     return MGLMA_OK;
 }
@@ -271,7 +293,8 @@ __global__ __launch_bounds__(RB) void k_multidot(const S* __restrict__ x, size_t
 }
 
 template <typename S>
-static int multidot_t(mglma_ctx* c, const S* x, size_t xstride, int k, const S* y, size_t n, int nrhs, double* out) {
+static int multidot_t(mglma_ctx* c, const S* x, size_t xstride, int k, const S* y, size_t n, int nrhs, double* out,
+                      const double* div) {
     constexpr int C = pk<S>();
     const bool vec = n % C == 0 && xstride % C == 0 && al(x, 16) && al(y, 16);
     const size_t np = vec ? n / C : n;
@@ -282,6 +305,7 @@ static int multidot_t(mglma_ctx* c, const S* x, size_t xstride, int k, const S* 
         dim3 grid(nb, nrhs);
         const S* xj = x + (size_t)j0 * xstride;
         double* oj = out + (size_t)j0 * nrhs * 2;
+        const double* dj = div ? div + (size_t)j0 * nrhs : nullptr;
 #define MD_LAUNCH(KK, CC) \
         hipLaunchKernelGGL((k_multidot<S, KK, CC>), grid, dim3(RB), 0, c->stream, xj, xstride, y, n, kk, c->red_part)
         if (vec) {
@@ -291,20 +315,20 @@ static int multidot_t(mglma_ctx* c, const S* x, size_t xstride, int k, const S* 
         }
 #undef MD_LAUNCH
         HIP_TRY(hipGetLastError());
-        if (kk == 1) MG_TRY(launch_finish<2>(c, nb, nrhs, 2, oj, 1, nrhs));
-        else if (kk <= 4) MG_TRY(launch_finish<8>(c, nb, nrhs, 2 * kk, oj, 1, nrhs));
-        else MG_TRY(launch_finish<2 * MAXK>(c, nb, nrhs, 2 * kk, oj, 1, nrhs));
+        if (kk == 1) MG_TRY(launch_finish<2>(c, nb, nrhs, 2, oj, 1, nrhs, dj));
+        else if (kk <= 4) MG_TRY(launch_finish<8>(c, nb, nrhs, 2 * kk, oj, 1, nrhs, dj));
+        else MG_TRY(launch_finish<2 * MAXK>(c, nb, nrhs, 2 * kk, oj, 1, nrhs, dj));
     }
     return MGLMA_OK;
 }
 
 int mg_multidot(mglma_ctx* c, int prec, const void* x, size_t xstride, int k, const void* y, size_t n, int nrhs,
-                double* out) {
+                double* out, const double* div) {
     if (nrhs <= 0 || k <= 0) return MGLMA_OK;
     switch (prec) {
-        case MGLMA_F64: return multidot_t(c, (const double2*)x, xstride, k, (const double2*)y, n, nrhs, out);
-        case MGLMA_F32: return multidot_t(c, (const float2*)x, xstride, k, (const float2*)y, n, nrhs, out);
-        case MGLMA_F16: return multidot_t(c, (const __half2*)x, xstride, k, (const __half2*)y, n, nrhs, out);
+        case MGLMA_F64: return multidot_t(c, (const double2*)x, xstride, k, (const double2*)y, n, nrhs, out, div);
+        case MGLMA_F32: return multidot_t(c, (const float2*)x, xstride, k, (const float2*)y, n, nrhs, out, div);
+        case MGLMA_F16: return multidot_t(c, (const __half2*)x, xstride, k, (const __half2*)y, n, nrhs, out, div);
         default: return MGLMA_ERR_ARG;
     }
 }
@@ -359,7 +383,8 @@ int mg_dot_norm(mglma_ctx* c, int prec, const void* x, const void* y, size_t n, 
 }
 
 // e += a z ; r -= a w ; out[r] = |r|^2 after the update (of the stored values)
-template <typename S, typename R, int C>
+// (NORM = false: the update alone)
+template <typename S, typename R, int C, bool NORM = true>
 __global__ __launch_bounds__(RB) void k_update_norm(const double* __restrict__ a, S* __restrict__ e, const S* __restrict__ z,
                                                     S* __restrict__ rr, const S* __restrict__ w, size_t n,
                                                     double* part) {
@@ -382,15 +407,17 @@ __global__ __launch_bounds__(RB) void k_update_norm(const double* __restrict__ a
         }
         stp<S, R, C>(e + o, ev);
         stp<S, R, C>(rr + o, rv);
-        cx<double> rs[C];
-        ldp<S, double, C>(rr + o, rs);   // the stored (rounded) values
+        if (NORM) {
+            cx<double> rs[C];
+            ldp<S, double, C>(rr + o, rs);   // the stored (rounded) values
 #pragma unroll
-        for (int q = 0; q < C; ++q) {
-            v[0] = fma(rs[q].re, rs[q].re, v[0]);
-            v[0] = fma(rs[q].im, rs[q].im, v[0]);
+            for (int q = 0; q < C; ++q) {
+                v[0] = fma(rs[q].re, rs[q].re, v[0]);
+                v[0] = fma(rs[q].im, rs[q].im, v[0]);
+            }
         }
     });
-    write_partial<1>(v, lds, part, 1);
+    if (NORM) write_partial<1>(v, lds, part, 1);
 }
 
 template <typename S, typename R>
@@ -400,8 +427,18 @@ static int update_norm_t(mglma_ctx* c, const double* a, S* e, const S* z, S* r, 
     const bool vec = n % C == 0 && al(e, 16) && al(z, 16) && al(r, 16) && al(w, 16);
     const size_t np = vec ? n / C : n;
     const int nb = red_blocks(np, U_DOT);
-    MG_TRY(ensure_red(c, (size_t)nb * nrhs));
     dim3 grid(nb, nrhs);
+    if (!out) {
+        if (vec)
+            hipLaunchKernelGGL((k_update_norm<S, R, C, false>), grid, dim3(RB), 0, c->stream, a, e, z, r, w, n,
+                               (double*)nullptr);
+        else
+            hipLaunchKernelGGL((k_update_norm<S, R, 1, false>), grid, dim3(RB), 0, c->stream, a, e, z, r, w, n,
+                               (double*)nullptr);
+        HIP_TRY(hipGetLastError());
+        return MGLMA_OK;
+    }
+    MG_TRY(ensure_red(c, (size_t)nb * nrhs));
     if (vec)
         hipLaunchKernelGGL((k_update_norm<S, R, C>), grid, dim3(RB), 0, c->stream, a, e, z, r, w, n, c->red_part);
     else
@@ -625,10 +662,10 @@ int mg_mr_update(mglma_ctx* c, int prec, const double* a, void* z, void* s, cons
     }
 }
 
-// y1 -= sum_j coef[j][r] x1_j ;  y2 -= sum_j coef[j][r] x2_j
+// y1 -= sum_j coef[j][r] x1_j ;  y2 = y2s - sum_j coef[j][r] x2_j  (y2s: y2 itself or another source)
 template <typename S, typename R, int K, int C>
 __global__ void k_multiaxpy2(const S* __restrict__ x1, const S* __restrict__ x2, size_t xstride, int k,
-                             const double* __restrict__ coef, S* __restrict__ y1, S* __restrict__ y2, size_t n,
+                             const double* __restrict__ coef, S* __restrict__ y1, S* y2, const S* y2s, size_t n,
                              int nrhs) {
     const int r = blockIdx.y;
     const size_t roff = (size_t)r * n;
@@ -641,7 +678,7 @@ __global__ void k_multiaxpy2(const S* __restrict__ x1, const S* __restrict__ x2,
         const size_t o = roff + p * C;
         cx<R> v1[C], v2[C];
         ldp<S, R, C>(y1 + o, v1);
-        ldp<S, R, C>(y2 + o, v2);
+        ldp<S, R, C>(y2s + o, v2);
 #pragma unroll
         for (int j = 0; j < K; ++j)
             if (j < k) {
@@ -659,26 +696,103 @@ __global__ void k_multiaxpy2(const S* __restrict__ x1, const S* __restrict__ x2,
     });
 }
 
+// k_multiaxpy2 that also reduces, over the updated y1, the partials
+// (Re <y1,d>, Im <y1,d>, |y1|^2) (the inner products of the next GCR step)
+template <typename S, typename R, int K, int C>
+__global__ __launch_bounds__(RB) void k_orth_dot(const S* __restrict__ x1, const S* __restrict__ x2, size_t xstride,
+                                                 int k, const double* __restrict__ coef, S* __restrict__ y1, S* y2,
+                                                 const S* y2s, const S* __restrict__ d, size_t n, int nrhs,
+                                                 double* part) {
+    __shared__ double lds[4 * 3];
+    const int r = blockIdx.y;
+    const size_t roff = (size_t)r * n;
+    cx<R> a[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        a[j] = j < k ? cmk((R)-coef[((size_t)j * nrhs + r) * 2], (R)-coef[((size_t)j * nrhs + r) * 2 + 1])
+                     : cmk((R)0, (R)0);
+    double v[3] = {0.0, 0.0, 0.0};
+    for_packets<1>(n / C, [&](size_t p) {
+        const size_t o = roff + p * C;
+        cx<R> v1[C], v2[C];
+        ldp<S, R, C>(y1 + o, v1);
+        ldp<S, R, C>(y2s + o, v2);
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (j < k) {
+                cx<R> u1[C], u2[C];
+                ldp<S, R, C>(x1 + (size_t)j * xstride + o, u1);
+                ldp<S, R, C>(x2 + (size_t)j * xstride + o, u2);
+#pragma unroll
+                for (int q = 0; q < C; ++q) {
+                    cmac(v1[q], a[j], u1[q]);
+                    cmac(v2[q], a[j], u2[q]);
+                }
+            }
+        stp<S, R, C>(y1 + o, v1);
+        stp<S, R, C>(y2 + o, v2);
+        cx<double> w[C], b[C];
+        ldp<S, double, C>(y1 + o, w);     // the stored values
+        ldp<S, double, C>(d + o, b);
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            v[0] = fma(w[q].re, b[q].re, v[0]); v[0] = fma(w[q].im, b[q].im, v[0]);
+            v[1] = fma(w[q].re, b[q].im, v[1]); v[1] = fma(-w[q].im, b[q].re, v[1]);
+            v[2] = fma(w[q].re, w[q].re, v[2]); v[2] = fma(w[q].im, w[q].im, v[2]);
+        }
+    });
+    write_partial<3>(v, lds, part, 3);
+}
+
+// Chunks of MAXK directions; the first chunk reads y2 from y2s (if given),
+// later ones update y2 in place.  With d given, the last chunk also reduces
+// (Re <y1,d>, Im <y1,d>, |y1|^2) and a finish turns them into the GCR step
+// alpha[r] (complex, 0 where mask[r] == 0) and nw2j[r] = |y1|^2.  k may be 0
+// (then only y2 = y2s and the reduction).
 template <typename S, typename R>
 static int multiaxpy2_t(mglma_ctx* c, const S* x1, const S* x2, size_t xstride, int k, const double* coef, S* y1,
-                        S* y2, size_t n, int nrhs) {
+                        S* y2, const S* y2s, const S* d, size_t n, int nrhs, double* alpha, double* nw2j,
+                        const int* mask) {
     constexpr int C = pk<S>();
-    const bool vec = n % C == 0 && xstride % C == 0 && al(x1, 16) && al(x2, 16) && al(y1, 16) && al(y2, 16);
-    const dim3 grid = ew_grid(vec ? n / C : n, nrhs, 1);
-    for (int j0 = 0; j0 < k; j0 += MAXK) {
-        int kk = k - j0 < MAXK ? k - j0 : MAXK;
+    const bool vec = n % C == 0 && xstride % C == 0 && al(x1, 16) && al(x2, 16) && al(y1, 16) && al(y2, 16) &&
+                     (!y2s || al(y2s, 16)) && (!d || al(d, 16));
+    const size_t np = vec ? n / C : n;
+    const dim3 grid = ew_grid(np, nrhs, 1);
+    const int nchunk = k > 0 ? (k + MAXK - 1) / MAXK : 1;
+    for (int ch = 0; ch < nchunk; ++ch) {
+        const int j0 = ch * MAXK;
+        const int kk = k - j0 < MAXK ? k - j0 : MAXK;
         const double* cj = coef + (size_t)j0 * nrhs * 2;
         const S* a1 = x1 + (size_t)j0 * xstride;
         const S* a2 = x2 + (size_t)j0 * xstride;
-#define M2_LAUNCH(KK, CC) \
-        hipLaunchKernelGGL((k_multiaxpy2<S, R, KK, CC>), grid, dim3(256), 0, c->stream, a1, a2, xstride, kk, cj, y1, y2, n, nrhs)
-        if (vec) {
-            if (kk <= 4) M2_LAUNCH(4, C); else M2_LAUNCH(MAXK, C);
+        const S* src = (ch == 0 && y2s) ? y2s : y2;
+        if (d && ch == nchunk - 1) {
+            const int nb = red_blocks(np, 1);
+            MG_TRY(ensure_red(c, (size_t)nb * nrhs * 3));
+            const dim3 rg(nb, nrhs);
+#define OD_LAUNCH(KK, CC)                                                                                  \
+            hipLaunchKernelGGL((k_orth_dot<S, R, KK, CC>), rg, dim3(RB), 0, c->stream, a1, a2, xstride, kk, cj, y1, \
+                               y2, src, d, n, nrhs, c->red_part)
+            if (vec) {
+                if (kk <= 0) OD_LAUNCH(1, C); else if (kk <= 4) OD_LAUNCH(4, C); else OD_LAUNCH(MAXK, C);
+            } else {
+                if (kk <= 0) OD_LAUNCH(1, 1); else if (kk <= 4) OD_LAUNCH(4, 1); else OD_LAUNCH(MAXK, 1);
+            }
+#undef OD_LAUNCH
+            HIP_TRY(hipGetLastError());
+            MG_TRY(launch_finish<3>(c, nb, nrhs, 3, alpha, 2, 0, nullptr, nw2j, mask));
         } else {
-            if (kk <= 4) M2_LAUNCH(4, 1); else M2_LAUNCH(MAXK, 1);
-        }
+#define M2_LAUNCH(KK, CC) \
+            hipLaunchKernelGGL((k_multiaxpy2<S, R, KK, CC>), grid, dim3(256), 0, c->stream, a1, a2, xstride, kk, cj, y1, \
+                               y2, src, n, nrhs)
+            if (vec) {
+                if (kk <= 4) M2_LAUNCH(4, C); else M2_LAUNCH(MAXK, C);
+            } else {
+                if (kk <= 4) M2_LAUNCH(4, 1); else M2_LAUNCH(MAXK, 1);
+            }
 #undef M2_LAUNCH
-        HIP_TRY(hipGetLastError());
+            HIP_TRY(hipGetLastError());
+        }
     }
     return MGLMA_OK;
 }
@@ -687,8 +801,20 @@ int mg_multiaxpy2(mglma_ctx* c, int prec, const void* x1, const void* x2, size_t
                   void* y1, void* y2, size_t n, int nrhs) {
     if (nrhs <= 0 || k <= 0) return MGLMA_OK;
     switch (prec) {
-        case MGLMA_F64: return multiaxpy2_t<double2, double>(c, (const double2*)x1, (const double2*)x2, xstride, k, coef, (double2*)y1, (double2*)y2, n, nrhs);
-        case MGLMA_F32: return multiaxpy2_t<float2, float>(c, (const float2*)x1, (const float2*)x2, xstride, k, coef, (float2*)y1, (float2*)y2, n, nrhs);
+        case MGLMA_F64: return multiaxpy2_t<double2, double>(c, (const double2*)x1, (const double2*)x2, xstride, k, coef, (double2*)y1, (double2*)y2, nullptr, nullptr, n, nrhs, nullptr, nullptr, nullptr);
+        case MGLMA_F32: return multiaxpy2_t<float2, float>(c, (const float2*)x1, (const float2*)x2, xstride, k, coef, (float2*)y1, (float2*)y2, nullptr, nullptr, n, nrhs, nullptr, nullptr, nullptr);
+        default: return MGLMA_ERR_ARG;
+    }
+}
+
+int mg_orth_step(mglma_ctx* c, int prec, const void* x1, const void* x2, size_t xstride, int k, const double* coef,
+                 void* y1, void* y2, const void* y2s, const void* d, size_t n, int nrhs, double* alpha, double* nw2j,
+                 const int* mask) {
+    if (nrhs <= 0) return MGLMA_OK;
+    if (!d || !alpha) return MGLMA_ERR_ARG;
+    switch (prec) {
+        case MGLMA_F64: return multiaxpy2_t<double2, double>(c, (const double2*)x1, (const double2*)x2, xstride, k, coef, (double2*)y1, (double2*)y2, (const double2*)y2s, (const double2*)d, n, nrhs, alpha, nw2j, mask);
+        case MGLMA_F32: return multiaxpy2_t<float2, float>(c, (const float2*)x1, (const float2*)x2, xstride, k, coef, (float2*)y1, (float2*)y2, (const float2*)y2s, (const float2*)d, n, nrhs, alpha, nw2j, mask);
         default: return MGLMA_ERR_ARG;
     }
 }

@@ -109,6 +109,9 @@ __global__ __launch_bounds__(512) void k_coarse_mfma(Geo g, int nc, const R* __r
     }
 }
 
+#ifndef COARSE_DG
+#define COARSE_DG 3
+#endif
 typedef short bf4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 
@@ -118,15 +121,21 @@ __device__ __forceinline__ short f2bf(float f) {
     return (short)(u >> 16);
 }
 
-// grid: (V1, ceil(nrhs/16)); block: 64 * ceil(nc/16) threads, wave w = row tile.
-// FULL: nc is a multiple of 16, so every fragment load is in range and can be
-// one 8-byte (operator) / two 16-byte (vector) load per lane.
-template <bool FULL>
+// grid: (V1, ceil(nrhs/16)); block: 64 * ceil(nc/16) * DG threads.  Wave w
+// owns row tile w % ntr and the directions dir = w / ntr + DG * k of the nine
+// stencil entries; with DG > 1 the DG partial sums of a row tile are added in
+// LDS in a fixed order.  FULL: nc is a multiple of 16, so every fragment load
+// is in range and can be one 8-byte (operator) / two 16-byte (vector) load
+// per lane.
+template <bool FULL, int DG>
 __global__ void k_coarse_bf16(Geo g, int nc, const bf16_t* __restrict__ Dbf, const float2* __restrict__ in,
                               float2* __restrict__ out, int nrhs, int gamma5) {
+    __shared__ f4_t part[DG > 1 ? 2 * 4 * 64 * (DG - 1) : 1];   // DG > 1 only with <= 4 row tiles
     const int y = blockIdx.x;
     const int n0 = blockIdx.y * 16;
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int ntr = (nc + 15) / 16;
+    const int wall = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = wall % ntr, dg = wall / ntr;
     const int m0 = w * 16;
     const int lr = lane & 15, lq = lane >> 4;          // row/col within the tile, k quarter
     const size_t V1 = g.V1, nn = (size_t)nc * nc;
@@ -134,7 +143,7 @@ __global__ void k_coarse_bf16(Geo g, int nc, const bf16_t* __restrict__ Dbf, con
     const int n = n0 + lr;                            // rhs of this lane's B column
     const int m = m0 + lr;                            // row of this lane's A fragment
     const bool nok = n < nrhs;
-    for (int dir = 0; dir < 9; ++dir) {
+    for (int dir = dg; dir < 9; dir += DG) {
         const int z = coarse_nbr(g, y, dir);
         const bf16_t* Dr = Dbf + ((size_t)y * 9 + dir) * 2 * nn;
         const bf16_t* Di = Dr + nn;
@@ -170,6 +179,20 @@ __global__ void k_coarse_bf16(Geo g, int nc, const bf16_t* __restrict__ Dbf, con
             ci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, br, ci, 0, 0, 0);
         }
     }
+    if (DG > 1) {
+        // partial sums of direction groups 1..DG-1 to LDS, group 0 adds them in order
+        if (dg > 0) {
+            part[((dg - 1) * 4 + w) * 2 * 64 + lane] = cr;
+            part[((dg - 1) * 4 + w) * 2 * 64 + 64 + lane] = ci;
+        }
+        __syncthreads();
+        if (dg > 0) return;
+#pragma unroll
+        for (int q = 1; q < DG; ++q) {
+            cr += part[((q - 1) * 4 + w) * 2 * 64 + lane];
+            ci += part[((q - 1) * 4 + w) * 2 * 64 + 64 + lane];
+        }
+    }
     // C[row = 4*lq + t][col = lr]
     if (nok) {
         const int row0 = m0 + 4 * lq;
@@ -198,14 +221,28 @@ int mg_coarse_apply(mglma_ctx* c, int prec, int gamma5, const void* in, void* ou
     const Geo& g = c->geo;
     const int nc = c->nc;
     if (prec == MGLMA_BF16) {
+        // up to four row tiles: three direction groups, three times the wavefronts
+        // in flight per coarse site
+        constexpr int DG = COARSE_DG;
+        const int ntr = (nc + 15) / 16;
         dim3 grid(g.V1, (nrhs + 15) / 16);
-        dim3 block(64 * ((nc + 15) / 16));
-        if (nc % 16 == 0)
-            hipLaunchKernelGGL(k_coarse_bf16<true>, grid, block, 0, c->stream, g, nc, c->Dbf, (const float2*)in,
-                               (float2*)out, nrhs, gamma5);
-        else
-            hipLaunchKernelGGL(k_coarse_bf16<false>, grid, block, 0, c->stream, g, nc, c->Dbf, (const float2*)in,
-                               (float2*)out, nrhs, gamma5);
+        if (ntr <= 4) {
+            dim3 block(64 * ntr * DG);
+            if (nc % 16 == 0)
+                hipLaunchKernelGGL((k_coarse_bf16<true, DG>), grid, block, 0, c->stream, g, nc, c->Dbf,
+                                   (const float2*)in, (float2*)out, nrhs, gamma5);
+            else
+                hipLaunchKernelGGL((k_coarse_bf16<false, DG>), grid, block, 0, c->stream, g, nc, c->Dbf,
+                                   (const float2*)in, (float2*)out, nrhs, gamma5);
+        } else {
+            dim3 block(64 * ntr);
+            if (nc % 16 == 0)
+                hipLaunchKernelGGL((k_coarse_bf16<true, 1>), grid, block, 0, c->stream, g, nc, c->Dbf,
+                                   (const float2*)in, (float2*)out, nrhs, gamma5);
+            else
+                hipLaunchKernelGGL((k_coarse_bf16<false, 1>), grid, block, 0, c->stream, g, nc, c->Dbf,
+                                   (const float2*)in, (float2*)out, nrhs, gamma5);
+        }
         HIP_TRY(hipGetLastError());
         return MGLMA_OK;
     }

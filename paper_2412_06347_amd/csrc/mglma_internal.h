@@ -280,9 +280,10 @@ int mg_dslash_resid16(mglma_ctx* c, const void* z, const void* r, void* p16, con
 // (prec F64 or F32 or F16 storage).  Scalars live in device memory.
 int mg_norm2(mglma_ctx* c, int prec, const void* x, size_t n, int nrhs, double* out_dev);
 int mg_dot(mglma_ctx* c, int prec, const void* x, const void* y, size_t n, int nrhs, double* out_dev);
-// out[j][r] = <x_j, y>_r for j < k, x_j = x + j*stride (stride in complex elements, per vector set)
+// out[j][r] = <x_j, y>_r for j < k, x_j = x + j*stride (stride in complex elements, per vector set);
+// divided by div_dev[j][r] when div_dev is given (0 where that is not positive)
 int mg_multidot(mglma_ctx* c, int prec, const void* x, size_t xstride, int k, const void* y, size_t n, int nrhs,
-                double* out_dev);
+                double* out_dev, const double* div_dev = nullptr);
 // y_r += sum_j coef[j][r] * x_j,r  (coef complex, multiplied by `sign`)
 int mg_multiaxpy(mglma_ctx* c, int prec, const void* x, size_t xstride, int k, const double* coef_dev, double sign,
                  void* y, size_t n, int nrhs);
@@ -324,8 +325,15 @@ int mg_dot_norm(mglma_ctx* c, int prec, const void* x, const void* y, size_t n, 
 int mg_mr_update(mglma_ctx* c, int prec, const double* a, void* z, void* s, const void* t, size_t n, int nrhs);
 int mg_multiaxpy2(mglma_ctx* c, int prec, const void* x1, const void* x2, size_t xstride, int k, const double* coef,
                   void* y1, void* y2, size_t n, int nrhs);
+// e += a z ; r -= a w ; out[r] = |r|^2 (out = NULL: the update alone)
 int mg_update_norm(mglma_ctx* c, int prec, const double* a, void* e, const void* z, void* r, const void* w, size_t n,
                    int nrhs, double* out);
+// One GCR orthogonalisation step: y1 -= sum_j coef[j] x1_j, y2 = y2s - sum_j coef[j] x2_j
+// (y2s = NULL: y2 in place; k may be 0), then alpha[r] = <y1,d>/|y1|^2 (complex; 0 where
+// mask[r] == 0 or |y1| = 0) and nw2j[r] = |y1|^2, all on the device
+int mg_orth_step(mglma_ctx* c, int prec, const void* x1, const void* x2, size_t xstride, int k, const double* coef,
+                 void* y1, void* y2, const void* y2s, const void* d, size_t n, int nrhs, double* alpha, double* nw2j,
+                 const int* mask);
 int mg_mr_update_h(mglma_ctx* c, const double* a, const double* scale, void* z, void* s16, const void* t16, size_t n,
                    int nrhs);
 // CA-GCR smoother (Krylov dimension k <= CA_K): packed FP64 Gram values per

@@ -111,14 +111,6 @@ struct Scal {
     static size_t bytes(int nrhs, int m) { return (size_t)(20 + 6 * m + CA_NV + 2 * CA_K) * nrhs * 8 + 256; }
 };
 
-// beta[j][r] /= nw2[j][r]   (projection coefficients of unnormalised directions)
-__global__ void k_div_norms(double* beta, const double* nw2, int k, int nrhs) {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= k * nrhs) return;
-    double d = nw2[e];
-    beta[2 * e] = d > 0.0 ? beta[2 * e] / d : 0.0;
-    beta[2 * e + 1] = d > 0.0 ? beta[2 * e + 1] / d : 0.0;
-}
 // alpha[r] = <w,r>/|w|^2 from dn3 = (Re, Im, |w|^2); also store |w|^2 in nw2j.
 // Right-hand sides with mask[r] == 0 get alpha = 0 (frozen: their iterate no
 // longer changes, so each one follows the same path alone or in a batch).
@@ -235,26 +227,21 @@ static int coarse_gcr_fixed(SolveCtx& S, int vp, int op, const void* b, void* x,
     MG_TRY(mg_zero(c, x, (size_t)nrhs * n * vb));
     MG_TRY(mg_copy(c, r, b, (size_t)nrhs * n * vb));
     const size_t setsz = (size_t)nrhs * n;   // elements per vector set
-    const dim3 sg((nrhs + 63) / 64), sb(64);
     for (int k = 0; k < iters; ++k) {
         int j = k % mc;
         char* pj = (char*)P + (size_t)j * setsz * vb;
         char* qj = (char*)Q + (size_t)j * setsz * vb;
-        MG_TRY(mg_copy(c, pj, r, setsz * vb));
         int opp = op;
         if (vp == MGLMA_F64) opp = MGLMA_F64;
-        MG_TRY(mg_coarse_apply(c, opp, 0, pj, qj, nrhs));
+        // q_j = D1 r, then p_j = r - sum_i beta_i p_i and q_j -= sum_i beta_i q_i with
+        // beta_i = <q_i, q_j>/|q_i|^2, and alpha = <q_j, r>/|q_j|^2 in the same pass
+        MG_TRY(mg_coarse_apply(c, opp, 0, r, qj, nrhs));
         S.coarse_applies++;
-        if (j > 0) {
-            MG_TRY(mg_multidot(c, vp, Q, setsz, j, qj, n, nrhs, S.s.cbeta()));
-            hipLaunchKernelGGL(k_div_norms, dim3((j * nrhs + 63) / 64), sb, 0, c->stream, S.s.cbeta(), S.s.cnw2(), j,
-                               nrhs);
-            MG_TRY(mg_multiaxpy2(c, vp, Q, P, setsz, j, S.s.cbeta(), qj, pj, n, nrhs));
-        }
-        MG_TRY(mg_dot_norm(c, vp, qj, r, n, nrhs, S.s.cdn3()));
-        hipLaunchKernelGGL(k_alpha, sg, sb, 0, c->stream, S.s.cdn3(), S.s.calpha(), S.s.cnw2() + (size_t)j * nrhs,
-                           (const int*)nullptr, nrhs);
-        MG_TRY(mg_update_norm(c, vp, S.s.calpha(), x, pj, r, qj, n, nrhs, S.s.cn2()));
+        if (j > 0) MG_TRY(mg_multidot(c, vp, Q, setsz, j, qj, n, nrhs, S.s.cbeta(), S.s.cnw2()));
+        MG_TRY(mg_orth_step(c, vp, Q, P, setsz, j, S.s.cbeta(), qj, pj, r, r, n, nrhs, S.s.calpha(),
+                            S.s.cnw2() + (size_t)j * nrhs, nullptr));
+        // x += alpha p_j ; r -= alpha q_j (a fixed number of steps: no norm)
+        MG_TRY(mg_update_norm(c, vp, S.s.calpha(), x, pj, r, qj, n, nrhs, nullptr));
     }
     HIP_TRY(hipGetLastError());
     return MGLMA_OK;
@@ -396,17 +383,17 @@ static int inner_fgcr(SolveCtx& S, int vp, const void* rin, void* e, const std::
         char* wj = (char*)W + (size_t)j * setsz * vb;
         MG_TRY(precondition(S, vp, r, zj));
         MG_TRY(mg_dslash(c, vp, 0, zj, wj, nrhs));
-        // unnormalised directions: w_j -= sum_i <w_i,w_j>/|w_i|^2 w_i (same on z_j)
+        // unnormalised directions: w_j -= sum_i <w_i,w_j>/|w_i|^2 w_i (same on z_j), and in
+        // the same pass alpha = <w_j, r>/|w_j|^2 ; then e += alpha z_j ; r -= alpha w_j ; |r|^2
         if (j > 0) {
-            MG_TRY(mg_multidot(c, vp, W, setsz, j, wj, n, nrhs, S.s.beta()));
-            hipLaunchKernelGGL(k_div_norms, dim3((j * nrhs + 63) / 64), dim3(64), 0, c->stream, S.s.beta(), S.s.nw2(),
-                               j, nrhs);
-            MG_TRY(mg_multiaxpy2(c, vp, W, Z, setsz, j, S.s.beta(), wj, zj, n, nrhs));
+            MG_TRY(mg_multidot(c, vp, W, setsz, j, wj, n, nrhs, S.s.beta(), S.s.nw2()));
+            MG_TRY(mg_orth_step(c, vp, W, Z, setsz, j, S.s.beta(), wj, zj, nullptr, r, n, nrhs, S.s.alpha(),
+                                S.s.nw2() + (size_t)j * nrhs, S.s.imask()));
+        } else {
+            MG_TRY(mg_dot_norm(c, vp, wj, r, n, nrhs, S.s.dn3()));
+            hipLaunchKernelGGL(k_alpha, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, S.s.dn3(), S.s.alpha(),
+                               S.s.nw2() + (size_t)j * nrhs, S.s.imask(), nrhs);
         }
-        // alpha = <w_j, r>/|w_j|^2 ; e += alpha z_j ; r -= alpha w_j ; |r|^2
-        MG_TRY(mg_dot_norm(c, vp, wj, r, n, nrhs, S.s.dn3()));
-        hipLaunchKernelGGL(k_alpha, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, S.s.dn3(), S.s.alpha(),
-                           S.s.nw2() + (size_t)j * nrhs, S.s.imask(), nrhs);
         MG_TRY(mg_update_norm(c, vp, S.s.alpha(), e, zj, r, wj, n, nrhs, S.s.rn2()));
         HIP_TRY(hipMemcpyAsync(h, S.s.rn2(), nrhs * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(hipStreamSynchronize(c->stream));
