@@ -174,6 +174,43 @@ int mglma_coarse_apply(mglma_ctx* ctx, int prec, int gamma5, const void* in_dev,
  * Errors: NO_SUBSPACE, ARG, RANK.                                          */
 int mglma_set_top_modes(mglma_ctx* ctx, int Nlm, const double* modes_dev);
 
+/* ---- low modes of Q_1 ----------------------------------------------------- */
+/* The nev eigenpairs of the Hermitian coarse operator Q_1 = (gamma5)_1 D_1
+ * with the smallest |lambda|: the low modes that low-mode averaging and the
+ * exact top level are built from (sec. "Low-mode averaging for the current
+ * correlator"; exact modes have |Q psi - lambda psi| <= 1e-12 |psi|, footnote
+ * in sec. "Local coherence and block decomposition").  Chebyshev-filtered
+ * subspace iteration on Q_1^2 over a block of nblk = nev + nguard coarse
+ * vectors, FP64 throughout, with a Rayleigh-Ritz step on Q_1 per iteration.
+ *   p->nev      wanted pairs (>= 1); p->nguard extra block vectors (>= 0),
+ *               nblk <= 64 and nblk <= V1 nc
+ *   p->degree   Chebyshev degree in Q_1^2 per iteration (0: 40)
+ *   p->max_iter filter iterations (0: 100)
+ *   p->tol      converged when |Q_1 v - lambda v| <= tol for every wanted
+ *               pair (|v| = 1)
+ *   init_dev    [nblk][V1][nc] complex128, the start block (its random
+ *               numbers are the caller's; any block of full rank), read only
+ *   evals       host array [nev]: eigenvalues of Q_1 in order of |lambda|
+ *   evecs_dev   [nev][V1][nc] complex128: orthonormal eigenvectors
+ *   stats       may be NULL
+ * Allocates five blocks of nblk coarse vectors for the duration of the call.
+ * Synchronising.  Errors: NO_SUBSPACE, ARG, NONFINITE, NOT_CONVERGED (the
+ * outputs and stats hold the last iterate).                                 */
+typedef struct {
+    int nev, nguard, degree, max_iter;
+    double tol;
+} mglma_eig_params;
+typedef struct {
+    int iters;              /* filter iterations                              */
+    int applies;            /* Q_1 applications (vectors)                     */
+    int nconv;              /* wanted pairs within tol                        */
+    double max_res;         /* largest |Q_1 v - lambda v| of the wanted pairs  */
+    double spectrum_bound;  /* the bound b >= lambda_max(Q_1^2) used          */
+    double seconds;
+} mglma_eig_stats;
+int mglma_coarse_eigs(mglma_ctx* ctx, const mglma_eig_params* p, const double* init_dev, double* evals,
+                      double* evecs_dev, mglma_eig_stats* stats);
+
 /* ---- solves -------------------------------------------------------------- */
 /* x = M^{-1} b for nrhs fields (device layout, F64) to the true relative
  * residual p->tol.  Mixed precision: inner FGCR on p->inner vectors with the

@@ -133,3 +133,20 @@ class TopLevel:
             for y in range(V1):
                 out[y0[y] * b0 + t] += m[y]
         return out
+
+
+def low_modes(D1, nbr, Nv, nev):
+    """The nev eigenpairs of Q_1 = (gamma5)_1 D_1 with the smallest |lambda|
+    (sec. "Low-mode averaging for the current correlator": the low modes are
+    eigenvectors of the Hermitian operator with the smallest-magnitude
+    eigenvalues).  Dense: Q_1 assembled column by column, numpy's Hermitian
+    eigensolver, eigenvalues ordered by |lambda| (ties keep numpy's order).
+    Returns (lam[nev], vecs[nev][V1][nc]).  For small coarse lattices."""
+    V1, nc = D1.shape[0], D1.shape[2]
+    A = coarse_dense(D1, nbr)
+    g5c = np.tile(coarse_gamma5(Nv), V1)
+    Q = g5c[:, None] * A
+    Q = 0.5 * (Q + Q.conj().T)
+    w, v = np.linalg.eigh(Q)
+    idx = np.argsort(np.abs(w), kind="stable")[:nev]
+    return w[idx], v[:, idx].T.reshape(nev, V1, nc)

@@ -1,0 +1,363 @@
+// Low modes of the Hermitian coarse operator Q_1 = (gamma5)_1 D_1: the nev
+// eigenpairs of smallest |lambda| (the modes the low-mode decomposition and
+// the exact top level are built from, sec. "Low-mode averaging for the
+// current correlator"; exact modes are those with |Q psi - lambda psi| <=
+// 1e-12 |psi|, footnote in sec. "Local coherence and block decomposition").
+//
+// Chebyshev-filtered subspace iteration on A = Q_1^2 = D_1^+ D_1, whose
+// smallest eigenvalues belong to the smallest |lambda| of Q_1, over a block
+// of nblk = nev + nguard coarse vectors, all in FP64:
+//   1. b >= lambda_max(A) from a short Lanczos run (largest Ritz value plus
+//      the last off-diagonal element);
+//   2. per iteration: Y = T_d((A - c)/e) X, the degree-d Chebyshev polynomial
+//      that is bounded by one on [a, b] (c = (a+b)/2, e = (b-a)/2) and grows
+//      fast below a; a = the largest Ritz value of A in the block (those of
+//      A, not of Q_1: the indefinite Q_1 can have Ritz values in the gap
+//      around zero, A cannot);
+//   3. orthonormalise Y (two passes of Y <- Y U s^{-1/2} from the eigen-
+//      decomposition U s U^+ of its Gram matrix);
+//   4. Rayleigh-Ritz with Q_1 itself: H = Y^+ Q_1 Y = V diag(theta) V^+,
+//      X = Y V ordered by |theta|, residuals |Q_1 x_i - theta_i x_i|.
+// The block operations are coarse applies on nblk right-hand sides, the
+// deterministic multi-dot reductions and one block-combine kernel; the
+// nblk x nblk eigenproblems run on the host (Jacobi).
+#include "mglma_internal.h"
+#include "dense_small.h"
+#include <algorithm>
+#include <chrono>
+#include <numeric>
+
+using dense::zc;
+
+// out = a x + b y + d z (real scalars; z may be null), n complex entries
+__global__ void k_lincomb3(double2* __restrict__ out, const double2* __restrict__ x, double a,
+                           const double2* __restrict__ y, double b, const double2* __restrict__ z, double d,
+                           size_t n) {
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        double2 v = x[e], w = y[e];
+        double re = a * v.x + b * w.x, im = a * v.y + b * w.y;
+        if (z) {
+            const double2 u = z[e];
+            re += d * u.x;
+            im += d * u.y;
+        }
+        out[e] = make_double2(re, im);
+    }
+}
+
+// out_j = qx_j - theta_j x_j for the nb vectors of a block (n entries each)
+__global__ void k_ritz_resid(double2* __restrict__ out, const double2* __restrict__ qx,
+                             const double2* __restrict__ x, const double* __restrict__ theta, size_t n, int nb) {
+    const size_t tot = n * nb;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x) {
+        const double t = theta[e / n];
+        const double2 q = qx[e], v = x[e];
+        out[e] = make_double2(q.x - t * v.x, q.y - t * v.y);
+    }
+}
+
+// Z_j = sum_i X_i M[i][j] for j < nb <= 64 (M complex, row-major nb x nb,
+// staged in LDS); each thread one entry index of all nb output vectors.
+__global__ __launch_bounds__(256) void k_block_combine(double2* __restrict__ Z, const double2* __restrict__ X,
+                                                       const double2* __restrict__ M, size_t n, int nb) {
+    extern __shared__ double2 sm[];
+    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) sm[e] = M[e];
+    __syncthreads();
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        for (int j0 = 0; j0 < nb; j0 += 8) {
+            double2 acc[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc[q] = make_double2(0.0, 0.0);
+            for (int i = 0; i < nb; ++i) {
+                const double2 x = X[(size_t)i * n + e];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    if (j0 + q < nb) {
+                        const double2 m = sm[i * nb + j0 + q];
+                        acc[q].x = fma(x.x, m.x, fma(-x.y, m.y, acc[q].x));
+                        acc[q].y = fma(x.x, m.y, fma(x.y, m.x, acc[q].y));
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (j0 + q < nb) Z[(size_t)(j0 + q) * n + e] = acc[q];
+        }
+    }
+}
+
+namespace {
+
+struct Eig {
+    mglma_ctx* c;
+    size_t n;      // complex entries per coarse vector
+    int nb;        // block size
+    double2 *M = nullptr, *G = nullptr;   // device nb x nb matrices
+    double* th = nullptr;                  // device nb values
+    int applies = 0;
+
+    int grid_for(size_t tot) const {
+        size_t g = (tot + 255) / 256;
+        return (int)(g > 4096 ? 4096 : (g < 1 ? 1 : g));
+    }
+    // y = Q_1 x for k vectors
+    int q1(const double2* x, double2* y, int k) {
+        applies += k;
+        return mg_coarse_apply(c, MGLMA_F64, 1, x, y, k);
+    }
+    // host G[i][j] = <X_i, Y_j> for i < kx, j < ky
+    int gram(const double2* X, int kx, const double2* Y, int ky, std::vector<zc>& Gh) {
+        for (int j = 0; j < ky; ++j)
+            MG_TRY(mg_multidot(c, MGLMA_F64, X, n, kx, Y + (size_t)j * n, n, 1, (double*)(G + (size_t)j * kx)));
+        std::vector<double2> tmp((size_t)kx * ky);
+        HIP_TRY(hipMemcpyAsync(tmp.data(), G, tmp.size() * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        Gh.resize((size_t)kx * ky);
+        for (int j = 0; j < ky; ++j)
+            for (int i = 0; i < kx; ++i) Gh[(size_t)i * ky + j] = zc(tmp[(size_t)j * kx + i].x, tmp[(size_t)j * kx + i].y);
+        return MGLMA_OK;
+    }
+    // Z = X Mh (Mh host, nb x nb row-major)
+    int combine(double2* Z, const double2* X, const std::vector<zc>& Mh) {
+        std::vector<double2> tmp((size_t)nb * nb);
+        for (size_t e = 0; e < tmp.size(); ++e) tmp[e] = make_double2(Mh[e].real(), Mh[e].imag());
+        HIP_TRY(hipMemcpyAsync(M, tmp.data(), tmp.size() * sizeof(double2), hipMemcpyHostToDevice, c->stream));
+        hipLaunchKernelGGL(k_block_combine, dim3(grid_for(n)), dim3(256), (size_t)nb * nb * sizeof(double2),
+                           c->stream, Z, X, M, n, nb);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipStreamSynchronize(c->stream));   // tmp is a host stack buffer
+        return MGLMA_OK;
+    }
+    // orthonormalise the block Y in place (T scratch): two passes of
+    // Y <- Y U s^{-1/2} with G = U s U^+; near-null directions are lifted to
+    // the same small floor (they are filtered again later).
+    int orthonormalise(double2*& Y, double2*& T) {
+        for (int pass = 0; pass < 2; ++pass) {
+            std::vector<zc> Gh, U;
+            std::vector<double> s;
+            MG_TRY(gram(Y, nb, Y, nb, Gh));
+            dense::herm_eig(nb, Gh, s, U);
+            double smax = 0.0;
+            for (double v : s) smax = std::max(smax, v);
+            if (!(smax > 0.0) || !std::isfinite(smax)) return MGLMA_ERR_NONFINITE;
+            std::vector<zc> Mh((size_t)nb * nb);
+            for (int k = 0; k < nb; ++k) {
+                const double sk = std::max(s[k], smax * 1e-28);
+                const double f = 1.0 / std::sqrt(sk);
+                for (int i = 0; i < nb; ++i) Mh[(size_t)i * nb + k] = U[(size_t)i * nb + k] * f;
+            }
+            MG_TRY(combine(T, Y, Mh));
+            std::swap(Y, T);
+        }
+        return MGLMA_OK;
+    }
+};
+
+}  // namespace
+
+extern "C" int mglma_coarse_eigs(mglma_ctx* c, const mglma_eig_params* p, const double* init, double* evals,
+                                 double* evecs, mglma_eig_stats* stats) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!c || !p || !init || !evals || !evecs) return MGLMA_ERR_ARG;
+    if (!c->have_subspace) return MGLMA_ERR_NO_SUBSPACE;
+    const size_t n = (size_t)c->geo.V1 * c->nc;
+    const int nev = p->nev, nb = p->nev + p->nguard;
+    const int deg = p->degree > 0 ? p->degree : 40;
+    const int maxit = p->max_iter > 0 ? p->max_iter : 100;
+    if (nev < 1 || p->nguard < 0 || nb > 64 || (size_t)nb > n || !(p->tol > 0.0) || deg > 10000)
+        return MGLMA_ERR_ARG;
+    Eig E;
+    E.c = c; E.n = n; E.nb = nb;
+    const size_t blk = (size_t)nb * n * sizeof(double2);
+    double2 *X = nullptr, *Y = nullptr, *Yp = nullptr, *T = nullptr, *W = nullptr;
+    int rc = MGLMA_OK;
+    auto cleanup = [&]() {
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        double2* bufs[] = {X, Y, Yp, T, W};
+        for (double2* b : bufs)
+            if (b) mg_free(c, b, blk);
+        if (E.M) mg_free(c, E.M, (size_t)nb * nb * sizeof(double2));
+        if (E.G) mg_free(c, E.G, (size_t)nb * nb * sizeof(double2));
+        if (E.th) mg_free(c, E.th, (size_t)nb * sizeof(double));
+        return MGLMA_OK;
+    };
+#define EG_TRY(expr)                      \
+    do {                                  \
+        rc = (expr);                      \
+        if (rc != MGLMA_OK) {             \
+            cleanup();                    \
+            return rc;                    \
+        }                                 \
+    } while (0)
+    EG_TRY(mg_malloc(c, (void**)&X, blk));
+    EG_TRY(mg_malloc(c, (void**)&Y, blk));
+    EG_TRY(mg_malloc(c, (void**)&Yp, blk));
+    EG_TRY(mg_malloc(c, (void**)&T, blk));
+    EG_TRY(mg_malloc(c, (void**)&W, blk));
+    EG_TRY(mg_malloc(c, (void**)&E.M, (size_t)nb * nb * sizeof(double2)));
+    EG_TRY(mg_malloc(c, (void**)&E.G, (size_t)nb * nb * sizeof(double2)));
+    EG_TRY(mg_malloc(c, (void**)&E.th, (size_t)nb * sizeof(double)));
+    const int g1 = E.grid_for(n), gb = E.grid_for((size_t)nb * n);
+
+    // ---- 1. spectral bound of A = Q_1^2: Lanczos on the first start vector
+    double bnd = 0.0;
+    {
+        const int m = (int)std::min<size_t>(24, n);
+        double* h;
+        EG_TRY(mg_host(c, 2, &h));
+        double2 *v = Y, *vp = Yp, *w = T, *t = W;   // single vectors in block scratch
+        EG_TRY(mg_copy(c, v, init, n * sizeof(double2)));
+        EG_TRY(mg_norm2(c, MGLMA_F64, v, n, 1, E.th));
+        HIP_TRY(hipMemcpyAsync(h, E.th, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        if (!(h[0] > 0.0) || !std::isfinite(h[0])) { cleanup(); return MGLMA_ERR_NONFINITE; }
+        hipLaunchKernelGGL(k_lincomb3, dim3(g1), dim3(256), 0, c->stream, v, v, 1.0 / std::sqrt(h[0]), v, 0.0,
+                           (const double2*)nullptr, 0.0, n);
+        EG_TRY(mg_zero(c, vp, n * sizeof(double2)));
+        std::vector<double> al, be;
+        double bprev = 0.0;
+        for (int j = 0; j < m; ++j) {
+            EG_TRY(E.q1(v, t, 1));
+            EG_TRY(E.q1(t, w, 1));
+            EG_TRY(mg_dot(c, MGLMA_F64, v, w, n, 1, E.th));
+            HIP_TRY(hipMemcpyAsync(h, E.th, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(hipStreamSynchronize(c->stream));
+            const double a = h[0];
+            // w = w - a v - bprev vp
+            hipLaunchKernelGGL(k_lincomb3, dim3(g1), dim3(256), 0, c->stream, w, w, 1.0, v, -a, vp, -bprev, n);
+            EG_TRY(mg_norm2(c, MGLMA_F64, w, n, 1, E.th));
+            HIP_TRY(hipMemcpyAsync(h, E.th, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(hipStreamSynchronize(c->stream));
+            const double bj = std::sqrt(std::max(h[0], 0.0));
+            if (!std::isfinite(a) || !std::isfinite(bj)) { cleanup(); return MGLMA_ERR_NONFINITE; }
+            al.push_back(a);
+            be.push_back(bj);
+            if (bj <= 1e-300) break;
+            // vp <- v ; v <- w / bj
+            std::swap(vp, v);
+            hipLaunchKernelGGL(k_lincomb3, dim3(g1), dim3(256), 0, c->stream, v, w, 1.0 / bj, w, 0.0,
+                               (const double2*)nullptr, 0.0, n);
+            bprev = bj;
+        }
+        const int k = (int)al.size();
+        std::vector<zc> Tm((size_t)k * k, zc(0.0, 0.0)), U;
+        std::vector<double> th;
+        for (int i = 0; i < k; ++i) {
+            Tm[(size_t)i * k + i] = al[i];
+            if (i + 1 < k) Tm[(size_t)i * k + i + 1] = Tm[(size_t)(i + 1) * k + i] = be[i];
+        }
+        dense::herm_eig(k, Tm, th, U);
+        double tmax = 0.0;
+        for (double v2 : th) tmax = std::max(tmax, v2);
+        bnd = 1.01 * (tmax + be[k - 1]);
+    }
+
+    // ---- 2. start block: orthonormalise init, first Rayleigh-Ritz for the cutoff
+    EG_TRY(mg_copy(c, X, init, blk));
+    EG_TRY(E.orthonormalise(X, T));
+    std::vector<double> theta(nb), res(nb, 0.0);
+    double cut = bnd;                     // a: largest Ritz value of A in the block
+    int it = 0, nconv = 0;
+    double maxres = 0.0;
+    auto rayleigh_ritz = [&](double2* Yb) -> int {
+        // QY -> W ; H = Y^+ Q_1 Y ; X = Y V ; QX = W V (into Yp)
+        MG_TRY(E.q1(Yb, W, nb));
+        std::vector<zc> H, V;
+        MG_TRY(E.gram(Yb, nb, W, nb, H));
+        for (int i = 0; i < nb; ++i)                  // Hermitian part (rounding)
+            for (int j = i; j < nb; ++j) {
+                const zc hij = 0.5 * (H[(size_t)i * nb + j] + std::conj(H[(size_t)j * nb + i]));
+                H[(size_t)i * nb + j] = hij;
+                H[(size_t)j * nb + i] = std::conj(hij);
+            }
+        std::vector<double> w;
+        dense::herm_eig(nb, H, w, V);
+        std::vector<int> ord(nb);
+        std::iota(ord.begin(), ord.end(), 0);
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return std::fabs(w[a]) < std::fabs(w[b]); });
+        std::vector<zc> Vs((size_t)nb * nb);
+        for (int k = 0; k < nb; ++k) {
+            theta[k] = w[ord[k]];
+            for (int i = 0; i < nb; ++i) Vs[(size_t)i * nb + k] = V[(size_t)i * nb + ord[k]];
+        }
+        MG_TRY(E.combine(X, Yb, Vs));
+        MG_TRY(E.combine(Yp, W, Vs));
+        // residuals |Q_1 x_k - theta_k x_k|
+        HIP_TRY(hipMemcpyAsync(E.th, theta.data(), nb * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        hipLaunchKernelGGL(k_ritz_resid, dim3(gb), dim3(256), 0, c->stream, T, Yp, X, E.th, n, nb);
+        HIP_TRY(hipGetLastError());
+        double* h;
+        MG_TRY(mg_host(c, (size_t)nb, &h));
+        MG_TRY(mg_norm2(c, MGLMA_F64, T, n, nb, E.th));
+        HIP_TRY(hipMemcpyAsync(h, E.th, nb * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        nconv = 0;
+        maxres = 0.0;
+        for (int k = 0; k < nb; ++k) {
+            res[k] = std::sqrt(std::max(h[k], 0.0));
+            if (!std::isfinite(res[k]) || !std::isfinite(theta[k])) return MGLMA_ERR_NONFINITE;
+        }
+        for (int k = 0; k < nev; ++k) {
+            maxres = std::max(maxres, res[k]);
+            if (res[k] <= p->tol) ++nconv;
+        }
+        // the cutoff comes from the Ritz values of A = Q_1^2 (W^+ W = Y^+ A Y), which
+        // lie inside the spectrum of A; the Ritz values of the indefinite Q_1 can fall
+        // into the gap around zero while the block is far from converged
+        std::vector<zc> H2, V2;
+        MG_TRY(E.gram(W, nb, W, nb, H2));
+        for (int i = 0; i < nb; ++i)
+            for (int j = i; j < nb; ++j) {
+                const zc hij = 0.5 * (H2[(size_t)i * nb + j] + std::conj(H2[(size_t)j * nb + i]));
+                H2[(size_t)i * nb + j] = hij;
+                H2[(size_t)j * nb + i] = std::conj(hij);
+            }
+        std::vector<double> w2;
+        dense::herm_eig(nb, H2, w2, V2);
+        double tmax = 0.0;
+        for (double v2 : w2) tmax = std::max(tmax, v2);
+        cut = std::min(tmax, 0.98 * bnd);
+        return MGLMA_OK;
+    };
+    EG_TRY(rayleigh_ritz(X));
+    // ---- 3. filter, orthonormalise, Rayleigh-Ritz
+    while (nconv < nev && it < maxit) {
+        ++it;
+        const double cc = 0.5 * (bnd + cut), ee = 0.5 * (bnd - cut);
+        // Y_1 = (A X - c X)/e ; Y_{k+1} = 2 (A Y_k - c Y_k)/e - Y_{k-1}
+        double2 *y0 = Yp, *y1 = Y;
+        EG_TRY(mg_copy(c, y0, X, blk));
+        EG_TRY(E.q1(y0, T, nb));
+        EG_TRY(E.q1(T, W, nb));
+        hipLaunchKernelGGL(k_lincomb3, dim3(gb), dim3(256), 0, c->stream, y1, W, 1.0 / ee, y0, -cc / ee,
+                           (const double2*)nullptr, 0.0, (size_t)nb * n);
+        for (int k = 1; k < deg; ++k) {
+            EG_TRY(E.q1(y1, T, nb));
+            EG_TRY(E.q1(T, W, nb));
+            // y0 <- 2/e (A y1 - c y1) - y0, then swap roles
+            hipLaunchKernelGGL(k_lincomb3, dim3(gb), dim3(256), 0, c->stream, y0, W, 2.0 / ee, y1, -2.0 * cc / ee,
+                               y0, -1.0, (size_t)nb * n);
+            std::swap(y0, y1);
+        }
+        HIP_TRY(hipGetLastError());
+        // the filtered block is y1: orthonormalise (y0 as scratch) and do Rayleigh-Ritz
+        EG_TRY(E.orthonormalise(y1, y0));
+        Y = y1;
+        Yp = y0;
+        EG_TRY(rayleigh_ritz(Y));
+    }
+    // ---- outputs
+    HIP_TRY(hipMemcpyAsync(evecs, X, (size_t)nev * n * sizeof(double2), hipMemcpyDeviceToDevice, c->stream));
+    for (int k = 0; k < nev; ++k) evals[k] = theta[k];
+    if (stats) {
+        stats->iters = it;
+        stats->applies = E.applies;
+        stats->nconv = nconv;
+        stats->max_res = maxres;
+        stats->spectrum_bound = bnd;
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    cleanup();
+    return nconv < nev ? MGLMA_ERR_NOT_CONVERGED : MGLMA_OK;
+#undef EG_TRY
+}

@@ -27,7 +27,7 @@ SYMBOLS = [
     "mglma_solve", "mglma_coarse_solve", "mglma_coarse_pieces",
     "mglma_point_sources", "mglma_noise_sources",
     "mglma_contract_point", "mglma_contract_point_coarse", "mglma_contract_stoch",
-    "mglma_contract_stoch_coarse", "mglma_contract_top",
+    "mglma_contract_stoch_coarse", "mglma_contract_top", "mglma_coarse_eigs",
 ]
 
 
@@ -46,6 +46,16 @@ class SolveParams(C.Structure):
 class SolveStats(C.Structure):
     _fields_ = [("outer", C.c_int), ("inner", C.c_int), ("coarse", C.c_int),
                 ("true_rel_res", C.c_double), ("seconds", C.c_double), ("status", C.c_int)]
+
+
+class EigParams(C.Structure):
+    _fields_ = [("nev", C.c_int), ("nguard", C.c_int), ("degree", C.c_int), ("max_iter", C.c_int),
+                ("tol", C.c_double)]
+
+
+class EigStats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("applies", C.c_int), ("nconv", C.c_int), ("max_res", C.c_double),
+                ("spectrum_bound", C.c_double), ("seconds", C.c_double)]
 
 
 class MglmaError(RuntimeError):
@@ -217,6 +227,23 @@ class Context:
     def coarse_pieces(self, eta, ge1, top=None, params=None):
         _check(lib().mglma_coarse_pieces(self._ctx, C.byref(params or default_params()), _ptr(eta),
                                          _ptr(ge1), _ptr(top), eta.shape[0]))
+
+    def coarse_eigs(self, init, nev, tol=1e-12, degree=0, max_iter=0, raise_on_error=True):
+        """Low modes of Q_1: init is the [nblk][V1][nc] complex128 start block
+        (nguard = nblk - nev).  Returns (rc, eigenvalues, eigenvectors, stats)."""
+        import torch
+        nb = init.shape[0]
+        par = EigParams(nev=nev, nguard=nb - nev, degree=degree, max_iter=max_iter, tol=tol)
+        ev = np.zeros(max(nev, 1), dtype=np.float64)
+        vec = torch.empty((max(nev, 1), self.V1, self.nc, 2), dtype=torch.float64, device=init.device)
+        st = EigStats()
+        rc = lib().mglma_coarse_eigs(self._ctx, C.byref(par), _ptr(init), ev.ctypes.data_as(C.c_void_p),
+                                     _ptr(vec), C.byref(st))
+        if raise_on_error:
+            _check(rc)
+        return rc, ev[:nev], vec[:nev], dict(iters=st.iters, applies=st.applies, nconv=st.nconv,
+                                             max_res=st.max_res, spectrum_bound=st.spectrum_bound,
+                                             seconds=st.seconds)
 
     # ---- sources and contractions --------------------------------------------
     def point_sources(self, y, out):

@@ -101,17 +101,11 @@ class Engine:
                 x = (y / nrm[:, None, None, None]).contiguous()
             del y
             ctx.build_subspace(x)
-            m = ctx.coarse(Nv)
-            ctx.restrict(x, m)
-            m = m[:Nlm].contiguous()
             del x
-            cp = mglma.default_params(tol=1e-3, coarse=mglma.BF16, coarse_iters=16)
-            for _ in range(2):
-                z = torch.empty_like(m)
-                ctx.coarse_solve(m, z, cp)
-                nrm = torch.linalg.vector_norm(z.reshape(Nlm, -1), dim=1)
-                m = (z / nrm[:, None, None, None]).contiguous()
-            ctx.set_top_modes(m)
+            # top level: the Nlm lowest eigenvectors of Q_1 (device eigensolver)
+            init = torch.from_numpy(synth.gaussian_coarse(2 * Nlm, ctx.V1, ctx.nc, wl["seed"] + 4242).view(np.float64))
+            rc, lam, m, st = ctx.coarse_eigs(init.cuda(), Nlm, tol=1e-12)
+            ctx.set_top_modes(m.contiguous())
             self.G_top = ctx.contract_top()
         self.stream.synchronize()
         self.params = params or mglma.default_params(tol=1e-10, max_outer=10, max_inner=120, gcr_m=8,

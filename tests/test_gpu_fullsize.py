@@ -8,7 +8,9 @@ against the oracle on sampled outputs and by properties that hold at any size:
   same test vectors, orthonormality of every block;
 * the Galerkin identity D_1 v = R M T v in FP64;
 * the benchmark's own pipeline and solver settings: every right-hand side to a
-  true relative residual of 1e-10, two of them re-checked with the oracle's M.
+  true relative residual of 1e-10, two of them re-checked with the oracle's M;
+  two of its top modes (device eigensolver) re-checked as eigenvectors of Q_1
+  with the oracle's stencil apply to 1e-12.
 """
 import numpy as np
 import pytest
@@ -123,6 +125,23 @@ def test_fullsize_bench_solve(ens):
     from paper_2412_06347_amd import mglma
     U, D = ens
     P = bench.Pipeline(bench.WORKLOADS["24c48"], log_setup=False)
+    # the top modes came from the device eigensolver: two of them re-checked with
+    # the oracle's stencil apply on the exported D_1
+    assert P.eig["max_res"] <= 1e-12
+    D1 = torch.empty((P.ctx.V1, 9, P.ctx.nc, P.ctx.nc, 2), dtype=torch.float64, device="cuda")
+    P.ctx.export_coarse_op(D1)
+    D1h = from_dev(D1)
+    del D1
+    from oracle import coarse as ocoarse, subspace as osub
+    nbr = osub.Blocking(L, B).neighbour_table()
+    modes = from_dev(P.modes)[[0, 15]]
+    g5 = osub.coarse_gamma5(P.ctx.nc // 2)[None, None, :]
+    Qm = g5 * ocoarse.coarse_apply(D1h, nbr, modes)
+    lam = np.einsum("nyi,nyi->n", modes.conj(), Qm).real
+    res = np.linalg.norm((Qm - lam[:, None, None] * modes).reshape(2, -1), axis=1)
+    print("eigensolver modes 0, 15: lambda", lam, "oracle residual", res)
+    assert res.max() <= 1e-12
+    del D1h, Qm
     stats, levels = P.step(bench.mixed_params(mglma))
     torch.cuda.synchronize()
     res = [s["true_rel_res"] for s in stats]

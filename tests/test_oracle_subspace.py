@@ -2,7 +2,8 @@
 operator and top level: partition of the lattice, QR uniqueness against
 numpy's Householder QR, RT = 1, the chirality relations of the appendix,
 the Galerkin identity against a dense R M T, (gamma5)_1 D_1 Hermitian,
-exact eigenvalue reproduction and gauge invariance of D_1."""
+exact eigenvalue reproduction and gauge invariance of D_1, and the low modes
+of Q_1 against the singular values of D_1."""
 import numpy as np
 import pytest
 
@@ -139,3 +140,25 @@ def test_top_level():
     A = coarse.coarse_dense(D1, nbr)
     assert np.abs(top.D2 - W.conj().T @ A @ W).max() < 1e-12
     assert np.abs(top.Q2 - top.Q2.conj().T).max() < 1e-12
+
+
+def test_low_modes():
+    """The oracle's low modes of Q_1 = (gamma5)_1 D_1: since (gamma5)_1 is a
+    unitary diagonal sign matrix, |lambda| of Q_1 are the singular values of
+    D_1 (an independent factorisation that never uses gamma5); the pairs come
+    ordered by |lambda|, orthonormal, and satisfy Q_1 v = lambda v with the
+    stencil apply (not the dense matrix the eigensolver saw)."""
+    L, b, Nv = (4, 2, 4, 2), (2, 2, 2, 2), 3
+    U, D, bl, tv, B = _setup(L, b, Nv, seed=6)
+    D1 = coarse.galerkin(D, B)
+    nbr = bl.neighbour_table()
+    nev = 7
+    lam, vec = coarse.low_modes(D1, nbr, Nv, nev)
+    sv = np.sort(np.linalg.svd(coarse.coarse_dense(D1, nbr), compute_uv=False))
+    assert np.abs(np.sort(np.abs(lam)) - sv[:nev]).max() < 1e-12
+    assert np.all(np.diff(np.abs(lam)) >= -1e-14)
+    V = vec.reshape(nev, -1)
+    assert np.abs(V.conj() @ V.T - np.eye(nev)).max() < 1e-12
+    g5 = subspace.coarse_gamma5(Nv)[None, None, :]
+    Qv = g5 * coarse.coarse_apply(D1, nbr, vec)
+    assert np.abs(Qv - lam[:, None, None] * vec).max() < 1e-12
