@@ -210,6 +210,18 @@ typedef struct {
 } mglma_eig_stats;
 int mglma_coarse_eigs(mglma_ctx* ctx, const mglma_eig_params* p, const double* init_dev, double* evals,
                       double* evecs_dev, mglma_eig_stats* stats);
+/* The same for the fine operator Q = gamma5 M (the paper's low modes of Q,
+ * from which its block basis is built): init_dev and evecs_dev are fine
+ * fields in the device layout (F64, [nblk] and [nev] of them), the limits
+ * nblk <= 64 and nblk <= 12 V.  Allocates five blocks of nblk fine fields.
+ * Errors: NO_GAUGE, ARG, NONFINITE, NOT_CONVERGED.                         */
+int mglma_fine_eigs(mglma_ctx* ctx, const mglma_eig_params* p, const double* init_dev, double* evals,
+                    double* evecs_dev, mglma_eig_stats* stats);
+/* Local-coherence deficits (eq:cdeficit): eps[r] = |(1 - P) psi_r| / |psi_r|
+ * for nrhs fine fields psi (device layout, F64), P = T R the projector on
+ * the block subspace; 0 for a zero field.  eps is a host array [nrhs].
+ * Synchronising.  Errors: NO_SUBSPACE, ARG, OOM, NONFINITE.                 */
+int mglma_deficit(mglma_ctx* ctx, int nrhs, const double* fine_dev, double* eps);
 
 /* ---- solves -------------------------------------------------------------- */
 /* x = M^{-1} b for nrhs fields (device layout, F64) to the true relative

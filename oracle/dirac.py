@@ -213,3 +213,20 @@ class WilsonClover:
 def gamma5_field(psi):
     _, g5 = gammas()
     return spin_mul(g5, psi)
+
+
+def low_modes(D, nev):
+    """The nev eigenpairs of Q = gamma5 M with the smallest |lambda| (sec.
+    "Low-mode averaging for the current correlator": the low modes are
+    eigenvectors of the Hermitian operator with the smallest-magnitude
+    eigenvalues).  Dense Q = gamma5 M (the dense M above, gamma5 acting on
+    the spin index), numpy's Hermitian eigensolver, ordered by |lambda|.
+    Returns (lam[nev], vecs[nev][V][4][3] canonical).  Tiny lattices only."""
+    n = 12 * D.V
+    Mdense = D.dense()
+    g5 = np.tile(np.repeat(np.array([1.0, 1.0, -1.0, -1.0]), 3), D.V)
+    Q = g5[:, None] * Mdense
+    Q = 0.5 * (Q + Q.conj().T)
+    w, v = np.linalg.eigh(Q)
+    idx = np.argsort(np.abs(w), kind="stable")[:nev]
+    return w[idx], v[:, idx].T.reshape(nev, D.V, 4, 3)

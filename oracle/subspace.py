@@ -143,6 +143,15 @@ class BlockBasis:
             pb[..., 2 * a:2 * a + 2, :] = v.reshape(n, self.bl.V1, *self.bl.b, 2, 3)
         return self.bl.from_blocks(pb)
 
+    def deficit(self, psi_lat):
+        """eq:cdeficit: |(1 - P) psi| / |psi| per field, P = T R the projector on
+        the block subspace ([n][L..][4][3] -> [n])."""
+        d = psi_lat - self.prolong(self.restrict(psi_lat))
+        n = psi_lat.shape[0]
+        num = np.linalg.norm(d.reshape(n, -1), axis=1)
+        den = np.linalg.norm(psi_lat.reshape(n, -1), axis=1)
+        return np.where(den > 0, num / np.where(den > 0, den, 1.0), 0.0)
+
     def basis_canonical(self):
         """The basis as canonical fine fields, [V1][2*Nv][V][4][3] (tiny lattices)."""
         V1, nc = self.bl.V1, self.nc

@@ -1,12 +1,14 @@
-// Low modes of the Hermitian coarse operator Q_1 = (gamma5)_1 D_1: the nev
-// eigenpairs of smallest |lambda| (the modes the low-mode decomposition and
-// the exact top level are built from, sec. "Low-mode averaging for the
-// current correlator"; exact modes are those with |Q psi - lambda psi| <=
-// 1e-12 |psi|, footnote in sec. "Local coherence and block decomposition").
+// Low modes of the Hermitian operators Q = gamma5 M (fine) and Q_1 =
+// (gamma5)_1 D_1 (coarse): the nev eigenpairs of smallest |lambda| (the
+// modes low-mode averaging, the block basis and the exact top level are built
+// from, sec. "Low-mode averaging for the current correlator"; exact modes are
+// those with |Q psi - lambda psi| <= 1e-12 |psi|, footnote in sec. "Local
+// coherence and block decomposition"), and the local-coherence deficits
+// eps = |(1 - P) psi| of that section.
 //
-// Chebyshev-filtered subspace iteration on A = Q_1^2 = D_1^+ D_1, whose
-// smallest eigenvalues belong to the smallest |lambda| of Q_1, over a block
-// of nblk = nev + nguard coarse vectors, all in FP64:
+// Chebyshev-filtered subspace iteration on A = Q^2 (= D_1^+ D_1 on the
+// coarse level), whose smallest eigenvalues belong to the smallest |lambda|
+// of Q, over a block of nblk = nev + nguard vectors, all in FP64:
 //   1. b >= lambda_max(A) from a short Lanczos run (largest Ritz value plus
 //      the last off-diagonal element);
 //   2. per iteration: Y = T_d((A - c)/e) X, the degree-d Chebyshev polynomial
@@ -16,9 +18,9 @@
 //      around zero, A cannot);
 //   3. orthonormalise Y (two passes of Y <- Y U s^{-1/2} from the eigen-
 //      decomposition U s U^+ of its Gram matrix);
-//   4. Rayleigh-Ritz with Q_1 itself: H = Y^+ Q_1 Y = V diag(theta) V^+,
-//      X = Y V ordered by |theta|, residuals |Q_1 x_i - theta_i x_i|.
-// The block operations are coarse applies on nblk right-hand sides, the
+//   4. Rayleigh-Ritz with Q itself: H = Y^+ Q Y = V diag(theta) V^+,
+//      X = Y V ordered by |theta|, residuals |Q x_i - theta_i x_i|.
+// The block operations are operator applies on nblk right-hand sides, the
 // deterministic multi-dot reductions and one block-combine kernel; the
 // nblk x nblk eigenproblems run on the host (Jacobi).
 #include "mglma_internal.h"
@@ -30,9 +32,9 @@
 using dense::zc;
 
 // out = a x + b y + d z (real scalars; z may be null), n complex entries
-__global__ void k_lincomb3(double2* __restrict__ out, const double2* __restrict__ x, double a,
-                           const double2* __restrict__ y, double b, const double2* __restrict__ z, double d,
-                           size_t n) {
+// (out may be one of the inputs: each entry is read before it is written)
+__global__ void k_lincomb3(double2* out, const double2* x, double a, const double2* y, double b, const double2* z,
+                           double d, size_t n) {
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
         double2 v = x[e], w = y[e];
         double re = a * v.x + b * w.x, im = a * v.y + b * w.y;
@@ -90,7 +92,8 @@ namespace {
 
 struct Eig {
     mglma_ctx* c;
-    size_t n;      // complex entries per coarse vector
+    int level;     // 0: fine Q = gamma5 M, 1: coarse Q_1
+    size_t n;      // complex entries per vector
     int nb;        // block size
     double2 *M = nullptr, *G = nullptr;   // device nb x nb matrices
     double* th = nullptr;                  // device nb values
@@ -100,10 +103,10 @@ struct Eig {
         size_t g = (tot + 255) / 256;
         return (int)(g > 4096 ? 4096 : (g < 1 ? 1 : g));
     }
-    // y = Q_1 x for k vectors
+    // y = Q x for k vectors
     int q1(const double2* x, double2* y, int k) {
         applies += k;
-        return mg_coarse_apply(c, MGLMA_F64, 1, x, y, k);
+        return level == 1 ? mg_coarse_apply(c, MGLMA_F64, 1, x, y, k) : mg_dslash(c, MGLMA_F64, 1, x, y, k);
     }
     // host G[i][j] = <X_i, Y_j> for i < kx, j < ky
     int gram(const double2* X, int kx, const double2* Y, int ky, std::vector<zc>& Gh) {
@@ -155,19 +158,20 @@ struct Eig {
 
 }  // namespace
 
-extern "C" int mglma_coarse_eigs(mglma_ctx* c, const mglma_eig_params* p, const double* init, double* evals,
-                                 double* evecs, mglma_eig_stats* stats) {
+static int eigs_run(mglma_ctx* c, int level, const mglma_eig_params* p, const double* init, double* evals,
+                    double* evecs, mglma_eig_stats* stats) {
     auto t0 = std::chrono::steady_clock::now();
     if (!c || !p || !init || !evals || !evecs) return MGLMA_ERR_ARG;
-    if (!c->have_subspace) return MGLMA_ERR_NO_SUBSPACE;
-    const size_t n = (size_t)c->geo.V1 * c->nc;
+    if (level == 1 && !c->have_subspace) return MGLMA_ERR_NO_SUBSPACE;
+    if (level == 0 && !c->have_gauge) return MGLMA_ERR_NO_GAUGE;
+    const size_t n = level == 1 ? (size_t)c->geo.V1 * c->nc : (size_t)12 * c->geo.V;
     const int nev = p->nev, nb = p->nev + p->nguard;
     const int deg = p->degree > 0 ? p->degree : 40;
     const int maxit = p->max_iter > 0 ? p->max_iter : 100;
     if (nev < 1 || p->nguard < 0 || nb > 64 || (size_t)nb > n || !(p->tol > 0.0) || deg > 10000)
         return MGLMA_ERR_ARG;
     Eig E;
-    E.c = c; E.n = n; E.nb = nb;
+    E.c = c; E.level = level; E.n = n; E.nb = nb;
     const size_t blk = (size_t)nb * n * sizeof(double2);
     double2 *X = nullptr, *Y = nullptr, *Yp = nullptr, *T = nullptr, *W = nullptr;
     int rc = MGLMA_OK;
@@ -360,4 +364,54 @@ extern "C" int mglma_coarse_eigs(mglma_ctx* c, const mglma_eig_params* p, const 
     cleanup();
     return nconv < nev ? MGLMA_ERR_NOT_CONVERGED : MGLMA_OK;
 #undef EG_TRY
+}
+
+extern "C" int mglma_coarse_eigs(mglma_ctx* c, const mglma_eig_params* p, const double* init, double* evals,
+                                 double* evecs, mglma_eig_stats* stats) {
+    return eigs_run(c, 1, p, init, evals, evecs, stats);
+}
+
+extern "C" int mglma_fine_eigs(mglma_ctx* c, const mglma_eig_params* p, const double* init, double* evals,
+                               double* evecs, mglma_eig_stats* stats) {
+    return eigs_run(c, 0, p, init, evals, evecs, stats);
+}
+
+// ---------------------------------------------------------------------------
+// local coherence: eps_r = |(1 - P) psi_r| / |psi_r| with P = T R the
+// projector on the block subspace
+// ---------------------------------------------------------------------------
+extern "C" int mglma_deficit(mglma_ctx* c, int nrhs, const double* fine, double* eps) {
+    if (!c || !fine || !eps || nrhs < 1 || nrhs > 4096) return MGLMA_ERR_ARG;
+    if (!c->have_subspace) return MGLMA_ERR_NO_SUBSPACE;
+    const size_t n = (size_t)12 * c->geo.V, ncs = (size_t)c->geo.V1 * c->nc;
+    double2 *cv = nullptr, *pv = nullptr;
+    double* nrm = nullptr;
+    int rc = mg_malloc(c, (void**)&cv, (size_t)nrhs * ncs * sizeof(double2));
+    if (rc == MGLMA_OK) rc = mg_malloc(c, (void**)&pv, (size_t)nrhs * n * sizeof(double2));
+    if (rc == MGLMA_OK) rc = mg_malloc(c, (void**)&nrm, (size_t)2 * nrhs * sizeof(double));
+    if (rc == MGLMA_OK) rc = mg_restrict(c, MGLMA_F64, fine, cv, nrhs);
+    if (rc == MGLMA_OK) rc = mg_prolong(c, MGLMA_F64, cv, pv, nrhs);
+    if (rc == MGLMA_OK) {
+        size_t g = ((size_t)nrhs * n + 255) / 256;
+        hipLaunchKernelGGL(k_lincomb3, dim3((unsigned)(g > 4096 ? 4096 : g)), dim3(256), 0, c->stream, pv,
+                           (const double2*)fine, 1.0, (const double2*)pv, -1.0, (const double2*)nullptr, 0.0,
+                           (size_t)nrhs * n);
+        if (hipGetLastError() != hipSuccess) rc = MGLMA_ERR_HIP;
+    }
+    if (rc == MGLMA_OK) rc = mg_norm2(c, MGLMA_F64, pv, n, nrhs, nrm);
+    if (rc == MGLMA_OK) rc = mg_norm2(c, MGLMA_F64, fine, n, nrhs, nrm + nrhs);
+    std::vector<double> h(2 * (size_t)nrhs);
+    if (rc == MGLMA_OK && hipMemcpyAsync(h.data(), nrm, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                         c->stream) != hipSuccess)
+        rc = MGLMA_ERR_HIP;
+    if (hipStreamSynchronize(c->stream) != hipSuccess && rc == MGLMA_OK) rc = MGLMA_ERR_HIP;
+    if (cv) mg_free(c, cv, (size_t)nrhs * ncs * sizeof(double2));
+    if (pv) mg_free(c, pv, (size_t)nrhs * n * sizeof(double2));
+    if (nrm) mg_free(c, nrm, (size_t)2 * nrhs * sizeof(double));
+    if (rc != MGLMA_OK) return rc;
+    for (int r = 0; r < nrhs; ++r) {
+        if (!std::isfinite(h[r]) || !std::isfinite(h[nrhs + r])) return MGLMA_ERR_NONFINITE;
+        eps[r] = h[nrhs + r] > 0.0 ? std::sqrt(h[r] / h[nrhs + r]) : 0.0;
+    }
+    return MGLMA_OK;
 }

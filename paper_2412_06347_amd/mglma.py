@@ -27,7 +27,8 @@ SYMBOLS = [
     "mglma_solve", "mglma_coarse_solve", "mglma_coarse_pieces",
     "mglma_point_sources", "mglma_noise_sources",
     "mglma_contract_point", "mglma_contract_point_coarse", "mglma_contract_stoch",
-    "mglma_contract_stoch_coarse", "mglma_contract_top", "mglma_coarse_eigs",
+    "mglma_contract_stoch_coarse", "mglma_contract_top", "mglma_coarse_eigs", "mglma_fine_eigs",
+    "mglma_deficit",
 ]
 
 
@@ -231,19 +232,35 @@ class Context:
     def coarse_eigs(self, init, nev, tol=1e-12, degree=0, max_iter=0, raise_on_error=True):
         """Low modes of Q_1: init is the [nblk][V1][nc] complex128 start block
         (nguard = nblk - nev).  Returns (rc, eigenvalues, eigenvectors, stats)."""
+        return self._eigs(lib().mglma_coarse_eigs, (self.V1, self.nc, 2), init, nev, tol, degree, max_iter,
+                          raise_on_error)
+
+    def fine_eigs(self, init, nev, tol=1e-12, degree=0, max_iter=0, raise_on_error=True):
+        """Low modes of Q = gamma5 M: init is [nblk][12][V][2] float64 (device
+        layout).  Returns (rc, eigenvalues, eigenvectors, stats)."""
+        return self._eigs(lib().mglma_fine_eigs, (12, self.V, 2), init, nev, tol, degree, max_iter,
+                          raise_on_error)
+
+    def _eigs(self, fn, shape, init, nev, tol, degree, max_iter, raise_on_error):
         import torch
         nb = init.shape[0]
         par = EigParams(nev=nev, nguard=nb - nev, degree=degree, max_iter=max_iter, tol=tol)
         ev = np.zeros(max(nev, 1), dtype=np.float64)
-        vec = torch.empty((max(nev, 1), self.V1, self.nc, 2), dtype=torch.float64, device=init.device)
+        vec = torch.empty((max(nev, 1),) + shape, dtype=torch.float64, device=init.device)
         st = EigStats()
-        rc = lib().mglma_coarse_eigs(self._ctx, C.byref(par), _ptr(init), ev.ctypes.data_as(C.c_void_p),
-                                     _ptr(vec), C.byref(st))
+        rc = fn(self._ctx, C.byref(par), _ptr(init), ev.ctypes.data_as(C.c_void_p), _ptr(vec), C.byref(st))
         if raise_on_error:
             _check(rc)
         return rc, ev[:nev], vec[:nev], dict(iters=st.iters, applies=st.applies, nconv=st.nconv,
                                              max_res=st.max_res, spectrum_bound=st.spectrum_bound,
                                              seconds=st.seconds)
+
+    def deficit(self, fine):
+        """Local-coherence deficits |(1 - P) psi| / |psi| of nrhs fine fields."""
+        n = fine.shape[0]
+        eps = np.zeros(max(n, 1), dtype=np.float64)
+        _check(lib().mglma_deficit(self._ctx, n, _ptr(fine), eps.ctypes.data_as(C.c_void_p)))
+        return eps[:n]
 
     # ---- sources and contractions --------------------------------------------
     def point_sources(self, y, out):

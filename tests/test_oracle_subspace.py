@@ -162,3 +162,49 @@ def test_low_modes():
     g5 = subspace.coarse_gamma5(Nv)[None, None, :]
     Qv = g5 * coarse.coarse_apply(D1, nbr, vec)
     assert np.abs(Qv - lam[:, None, None] * vec).max() < 1e-12
+
+
+def test_fine_low_modes():
+    """The oracle's low modes of Q = gamma5 M: |lambda| equal the singular
+    values of M (gamma5 unitary), ordered, orthonormal, Q psi = lambda psi with
+    the stencil M (not the dense matrix the eigensolver saw); on unit links the
+    smallest |lambda| is the free-field closed form min_p |1 - 2 kappa sum cos p
+    +- 2 i kappa |sin p|| (antiperiodic time)."""
+    L = (4, 2, 2, 4)
+    U = synth.gauge_field(L, 0.3, 8)
+    D = dirac.WilsonClover(U, L, 0.124, 1.0)
+    nev = 6
+    lam, vec = dirac.low_modes(D, nev)
+    sv = np.sort(np.linalg.svd(D.dense(), compute_uv=False))
+    assert np.abs(np.sort(np.abs(lam)) - sv[:nev]).max() < 1e-12
+    assert np.all(np.diff(np.abs(lam)) >= -1e-14)
+    V = vec.reshape(nev, -1)
+    assert np.abs(V.conj() @ V.T - np.eye(nev)).max() < 1e-12
+    Qv = dirac.fields_to_canonical(dirac.gamma5_field(D.M(dirac.fields_to_lattice(vec, L))))
+    assert np.abs(Qv - lam[:, None, None, None] * vec).max() < 1e-12
+    # free field: |lambda| of Q = |eigenvalues of M| = |1 - 2k sum_mu cos p_mu +- 2ik |sin p||
+    Uf = np.tile(np.eye(3, dtype=np.complex128), (int(np.prod(L)), 4, 1, 1))
+    kap = 0.11
+    Df = dirac.WilsonClover(Uf, L, kap, 1.0)
+    lamf, _ = dirac.low_modes(Df, 1)
+    ps = [2 * np.pi * (np.arange(L[0]) + 0.5) / L[0]] + [2 * np.pi * np.arange(l) / l for l in L[1:]]
+    P = np.meshgrid(*ps, indexing="ij")
+    re = 1 - 2 * kap * sum(np.cos(p) for p in P)
+    im = 2 * kap * np.sqrt(sum(np.sin(p) ** 2 for p in P))
+    assert abs(abs(lamf[0]) - np.sqrt(re ** 2 + im ** 2).min()) < 1e-12
+
+
+def test_deficit():
+    """eq:cdeficit: 0 for the test vectors (each lies in the span of its block
+    projections), 1 for a field orthogonal to the block subspace, and
+    |P psi|^2 + |(1 - P) psi|^2 = |psi|^2 (P an orthogonal projector)."""
+    L, b, Nv = (4, 2, 4, 2), (2, 2, 2, 2), 3
+    U, D, bl, tv, B = _setup(L, b, Nv, seed=9)
+    assert np.abs(B.deficit(tv)).max() < 1e-13
+    psi = dirac.fields_to_lattice(synth.gaussian_fields(2, L, 44), L)
+    ort = psi - B.prolong(B.restrict(psi))
+    assert np.abs(B.deficit(ort) - 1.0).max() < 1e-13
+    eps = B.deficit(psi)
+    pn = np.linalg.norm(B.prolong(B.restrict(psi)).reshape(2, -1), axis=1)
+    n = np.linalg.norm(psi.reshape(2, -1), axis=1)
+    assert np.abs((pn / n) ** 2 + eps ** 2 - 1.0).max() < 1e-13
