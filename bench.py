@@ -199,6 +199,43 @@ def cpu_baseline(wl, n_iter_needed, budget_s=20.0):
                        "convergence)" % (cpu, it, "x".join(map(str, L)), t, t_it, float(res[0]), n_iter_needed))
 
 
+def local_coherence(wl, degree=64):
+    """fig:lc on a synthetic ensemble: the 2 Nv lowest modes of Q to a residual
+    of 1e-12 from the device eigensolver, the block basis built from the Nv
+    lowest (sec. "Local coherence and block decomposition"), and 1 - eps_c for
+    every computed mode c."""
+    import torch
+    from paper_2412_06347_amd import mglma, synth
+    L, Nv = wl["L"], wl["Nv"]
+    U = torch.from_numpy(synth.gauge_field(L, wl["eps"], wl["seed"]).view(np.float64)).cuda()
+    ctx = mglma.Context(L, wl["block"], wl["kappa"], wl["csw"])
+    ctx.load_gauge(U)
+    nev, nblk = 2 * Nv, min(64, 2 * Nv + 16)
+    init = ctx.fine(nblk)
+    for k0 in range(0, nblk, 8):      # seeded start block, a few fields at a time (host memory)
+        k1 = min(nblk, k0 + 8)
+        ctx.import_fields(torch.from_numpy(synth.gaussian_fields(k1 - k0, L, 9000 + k0).view(np.float64)).cuda(),
+                          init[k0:k1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, lam, modes, st = ctx.fine_eigs(init, nev, tol=1e-12, degree=degree, max_iter=300, raise_on_error=False)
+    torch.cuda.synchronize()
+    t_eig = time.perf_counter() - t0
+    del init
+    ctx.build_subspace(modes[:Nv].contiguous())
+    eps = ctx.deficit(modes)
+    print(json.dumps({
+        "diagnostic": "local coherence (fig:lc) on synthetic fields",
+        "workload": "%dx%d^3, eps=%g, kappa=%g, c_sw=%g, %d^4 blocks, Nv=%d" %
+                    (L[0], L[1], wl["eps"], wl["kappa"], wl["csw"], wl["block"][0], Nv),
+        "eigensolver": {"rc": rc, "nev": nev, "nblk": nblk, "degree": degree, "seconds": round(t_eig, 2),
+                        "iters": st["iters"], "vector_applies": st["applies"], "max_res": st["max_res"],
+                        "spectrum_bound": st["spectrum_bound"]},
+        "lambda": [round(float(x), 8) for x in lam],
+        "one_minus_eps": [round(float(1 - e), 6) for e in eps],
+    }), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -211,6 +248,10 @@ def main():
     ap.add_argument("--calib-copy", action="store_true", help="only run a plain 1 GiB device copy (counter scale)")
     ap.add_argument("--dslash-only", action="store_true",
                     help="only run the Wilson-clover apply of the workload (for hardware-counter runs)")
+    ap.add_argument("--lc", action="store_true",
+                    help="local-coherence diagnostic instead of the bench: the 2 Nv lowest exact modes of Q "
+                         "(device eigensolver), the block basis from the Nv lowest, the deficits of all "
+                         "(default workload 16c32)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one MI355X only: the hot path runs on a single GPU "
@@ -226,6 +267,9 @@ def main():
         print(json.dumps({"calib_copy_bytes_read": a.numel() * 8, "copies": 3}))
         return
     from paper_2412_06347_amd import mglma, synth
+    if args.lc:
+        local_coherence(WORKLOADS["16c32" if args.workload == "24c48" else args.workload])
+        return
     wl = WORKLOADS[args.workload]
     if args.dslash_only:
         L = wl["L"]
