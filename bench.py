@@ -39,8 +39,9 @@ def log(*a):
 
 
 def mixed_params(mglma, **kw):
-    p = dict(tol=1e-10, max_outer=10, max_inner=120, gcr_m=8, inner_tol=1e-5, nu_post=6, coarse_iters=8,
-             smoother=mglma.F16, inner=mglma.F32, coarse=mglma.BF16, use_mg=1, smoother_alg=mglma.SMOOTH_CAGCR)
+    p = dict(tol=1e-10, max_outer=10, max_inner=120, gcr_m=8, inner_tol=1e-5, nu_post=6, coarse_iters=4,
+             smoother=mglma.F16, inner=mglma.F32, coarse=mglma.BF16, use_mg=1, smoother_alg=mglma.SMOOTH_CAGCR,
+             coarse_eo=1)
     p.update(kw)
     return mglma.default_params(**p)
 
@@ -110,7 +111,7 @@ class Pipeline:
         ctx.set_top_modes(self.modes)                  # W, D_2, (gamma5 gamma_k)_2
         ctx.point_sources((0, 0, 0, 0), self.src)      # 12 point sources
         rc, stats = ctx.solve(self.src, self.x, params)
-        cp = mglma.default_params(tol=1e-10, coarse=mglma.BF16, coarse_iters=16, max_outer=40)
+        cp = mglma.default_params(tol=1e-10, coarse=mglma.BF16, coarse_iters=12, max_outer=40, coarse_eo=1)
         ctx.coarse_pieces(self.src, self.cg, self.ct, cp)
         C_all = ctx.contract_point(self.x, self.x, 0)
         C_ge1 = ctx.contract_point_coarse(self.cg, self.cg, 0)

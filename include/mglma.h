@@ -90,6 +90,13 @@ typedef struct {
                             space {s, M s, .., M^(nu_post-1) s}, its basis
                             built without reductions in between (one FP64
                             Gram matrix per right-hand side)               */
+    int    coarse_eo;    /* 1: coarse GCR on the even-odd reduced system
+                            S = 1 - D_ee^{-1} D_eo D_oo^{-1} D_oe when every
+                            coarse extent is even, nc <= 64, the coarse
+                            operator is BF16 and the vectors FP32 (sec.
+                            "Comparison of the cost": even-odd preconditioned
+                            coarse operator); coarse_iters then counts
+                            applications of S.  0: GCR on D_1.          */
 } mglma_solve_params;
 
 enum { MGLMA_SMOOTH_MR = 0, MGLMA_SMOOTH_CAGCR = 1 };
@@ -110,7 +117,9 @@ int  mglma_create(mglma_ctx** ctx, const mglma_lattice* lat, void* stream);
 void mglma_destroy(mglma_ctx* ctx);
 int  mglma_set_stream(mglma_ctx* ctx, void* stream);
 const char* mglma_strerror(int code);
-/* Sizes: 0 V, 1 V1, 2 Vb, 3 Nv, 4 nc, 5 Nlm, 6 r = 2 Nlm, 7 spatial volume. */
+/* Sizes: 0 V, 1 V1, 2 Vb, 3 Nv, 4 nc, 5 Nlm, 6 r = 2 Nlm, 7 spatial volume;
+ * 8: 1 if the even-odd reduced coarse operator is set up (every coarse extent
+ * even, nc <= 64, non-singular self blocks), else 0.                        */
 long mglma_query(const mglma_ctx* ctx, int what);
 /* Device bytes held by the context (gauge, clover, basis, coarse op, ...). */
 size_t mglma_resident_bytes(const mglma_ctx* ctx);
@@ -164,6 +173,18 @@ int mglma_prolong(mglma_ctx* ctx, int prec, const void* coarse_dev, void* fine_d
 /* out = D_1 in (gamma5 = 0) or Q_1 in (gamma5 = 1).  prec F64, F32 (FP32
  * operator) or BF16 (bfloat16 operator on the matrix cores, FP32 vectors). */
 int mglma_coarse_apply(mglma_ctx* ctx, int prec, int gamma5, const void* in_dev, void* out_dev, int nrhs);
+/* Even-odd reduced coarse operator (sec. "Comparison of the cost": the coarse
+ * solves use the even-odd preconditioned coarse operator).  With the coarse
+ * sites split by parity (y_0+y_1+y_2+y_3 mod 2) and each parity's sites in
+ * increasing order of y:
+ *   out = S in,  S = 1 - D_ee^{-1} D_eo D_oo^{-1} D_oe,
+ * in/out FP32 complex [nrhs][V1/2][nc] on the even sites (distinct buffers).
+ * The hop blocks D_yy^{-1} D_y,dir are built in FP64 with the subspace and
+ * applied in bfloat16 on the matrix cores (FP32 accumulation).  For tests;
+ * allocates a temporary.  Synchronising.  Errors: ARG, NO_SUBSPACE, SHAPE
+ * (no even-odd form: a coarse extent odd, nc > 64 or a singular self
+ * block).                                                                   */
+int mglma_coarse_schur_apply(mglma_ctx* ctx, const void* in_dev, void* out_dev, int nrhs);
 
 /* ---- top (exact) level -------------------------------------------------- */
 /* Set the exact top level from Nlm coarse vectors modes_dev ([Nlm][V1][nc]

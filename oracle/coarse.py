@@ -150,3 +150,52 @@ def low_modes(D1, nbr, Nv, nev):
     w, v = np.linalg.eigh(Q)
     idx = np.argsort(np.abs(w), kind="stable")[:nev]
     return w[idx], v[:, idx].T.reshape(nev, V1, nc)
+
+
+def parity_sites(L1):
+    """Even and odd coarse sites, each in increasing order of the block index
+    y (C order over L1, last direction fastest); parity = sum of the block
+    coordinates mod 2.  Returns (even, odd) index arrays."""
+    y = np.arange(int(np.prod(L1)))
+    par = np.sum(np.stack(np.unravel_index(y, tuple(L1))), axis=0) % 2
+    return y[par == 0], y[par == 1]
+
+
+def _site_rows(sites, nc):
+    return (sites[:, None] * nc + np.arange(nc)[None, :]).reshape(-1)
+
+
+def eo_split(D1, nbr, L1):
+    """The four parity blocks (A_ee, A_eo, A_oe, A_oo) of the dense coarse
+    operator, rows and columns in the order of parity_sites (even-odd
+    preconditioning of the coarse operator, sec. "Comparison of the cost")."""
+    nc = D1.shape[2]
+    A = coarse_dense(D1, nbr)
+    e, o = parity_sites(L1)
+    re, ro = _site_rows(e, nc), _site_rows(o, nc)
+    return A[np.ix_(re, re)], A[np.ix_(re, ro)], A[np.ix_(ro, re)], A[np.ix_(ro, ro)]
+
+
+def schur_even(D1, nbr, L1):
+    """S = 1 - A_ee^{-1} A_eo A_oo^{-1} A_oe on the even sites (dense; the
+    Schur complement of A_oo, multiplied from the left by A_ee^{-1})."""
+    Aee, Aeo, Aoe, Aoo = eo_split(D1, nbr, L1)
+    return np.eye(Aee.shape[0]) - np.linalg.solve(Aee, Aeo @ np.linalg.solve(Aoo, Aoe))
+
+
+def solve_eo(D1, nbr, L1, b):
+    """x = D_1^{-1} b through the reduced system: S x_e = A_ee^{-1} (b_e -
+    A_eo A_oo^{-1} b_o), then x_o = A_oo^{-1} (b_o - A_oe x_e).
+    b: [V1][nc]; returns [V1][nc]."""
+    V1, nc = b.shape
+    Aee, Aeo, Aoe, Aoo = eo_split(D1, nbr, L1)
+    e, o = parity_sites(L1)
+    be, bo = b[e].reshape(-1), b[o].reshape(-1)
+    S = schur_even(D1, nbr, L1)
+    rhs = np.linalg.solve(Aee, be - Aeo @ np.linalg.solve(Aoo, bo))
+    xe = np.linalg.solve(S, rhs)
+    xo = np.linalg.solve(Aoo, bo - Aoe @ xe)
+    x = np.zeros_like(b)
+    x[e] = xe.reshape(-1, nc)
+    x[o] = xo.reshape(-1, nc)
+    return x

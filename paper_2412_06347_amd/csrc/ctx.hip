@@ -168,6 +168,7 @@ static void free_top(mglma_ctx* c) {
 void mg_free_subspace(mglma_ctx* c) {
     const Geo& g = c->geo;
     free_top(c);
+    mg_eo_free(c);
     size_t nb = (size_t)g.V * 12 * c->Nv;
     mg_free(c, c->B64, nb * 16); c->B64 = nullptr;
     mg_free(c, c->B32, nb * 8); c->B32 = nullptr;
@@ -220,6 +221,7 @@ extern "C" long mglma_query(const mglma_ctx* c, int what) {
         case 5: return c->Nlm;
         case 6: return c->r;
         case 7: return c->geo.V3;
+        case 8: return c->eo_ok ? 1 : 0;
         default: return MGLMA_ERR_ARG;
     }
 }

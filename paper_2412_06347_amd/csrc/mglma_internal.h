@@ -248,6 +248,14 @@ struct mglma_ctx {
     double2* G1 = nullptr;       // coarse gammas [V1][b0][3][Nv][Nv] (alpha=0 rows, alpha=1 cols)
     bool have_subspace = false;
 
+    // even-odd reduced coarse operator (all coarse extents even, nc <= 64)
+    bool eo_ok = false;
+    int eo_Vh = 0;                 // sites per parity
+    int* eo_site = nullptr;        // [2][Vh] coarse site of compressed index k, increasing y
+    int* eo_nbr = nullptr;         // [2][Vh][8] compressed index of neighbour dir 1+d (other parity)
+    float* eo_Dinv32 = nullptr;    // [V1][re/im][nc][nc] inverse self blocks, FP32 planar
+    bf16_t* eo_Hbf = nullptr;      // [V1][8][2][nc][nc] D_yy^{-1} D_y,dir planar bfloat16
+
     // top level
     int Nlm = 0, r = 0;
     double2* W = nullptr;                          // [r][V1][nc]
@@ -306,6 +314,19 @@ static inline size_t prec_cbytes(int prec) {
     return prec == MGLMA_F64 ? 16 : prec == MGLMA_F32 ? 8 : 4;
 }
 void mg_free_subspace(mglma_ctx* c);
+
+// even-odd reduced coarse operator; vectors on one parity are compressed,
+// [nrhs][Vh][nc] FP32 complex
+int mg_eo_setup(mglma_ctx* c);
+void mg_eo_free(mglma_ctx* c);
+// out_p = [xs -] H_{p,1-p} in   (xs NULL: no subtraction; xs may alias out)
+int mg_eo_hop(mglma_ctx* c, int po, const void* in, const void* xs, void* out, int nrhs);
+// out_e / out_o = D_yy^{-1} in_full restricted to the even / odd sites (either may be NULL)
+int mg_eo_diag_inv(mglma_ctx* c, const void* in_full, void* out_e, void* out_o, int nrhs);
+// full vector from its two parity halves
+int mg_eo_scatter(mglma_ctx* c, const void* xe, const void* xo, void* x_full, int nrhs);
+// out = (1 - H_eo H_oe) x; tmp holds one odd-parity vector set
+int mg_eo_schur(mglma_ctx* c, const void* x, void* out, void* tmp, int nrhs);
 
 // ---------------------------------------------------------------------------
 // gamma5 gamma_k in the chiral basis: one entry per row

@@ -17,6 +17,7 @@ enum {
     WS_SCAL = 8, WS_R64, WS_T64, WS_RIN, WS_E, WS_Z, WS_W, WS_RC, WS_EC, WS_CP, WS_CQ, WS_CR, WS_SS, WS_ST, WS_X16,
     WS_CX64, WS_CR64, WS_CT64, WS_PIECE, WS_CAP, WS_COUNT
 };
+enum { WS_EO = 30 };   // odd right-hand side, odd scratch and even iterate of the even-odd coarse GCR
 
 // ---------------------------------------------------------------------------
 // scalar kernels (per right-hand side)
@@ -213,8 +214,11 @@ static inline size_t coarse_n(mglma_ctx* c) { return (size_t)c->geo.V1 * c->nc; 
 // coarse GCR with a fixed number of steps (preconditioner use, no host sync)
 //   vectors in precision vp (F32 or F64), operator precision op
 // ---------------------------------------------------------------------------
+static int coarse_gcr_eo(SolveCtx& S, const void* b, void* x, int iters);
+
 static int coarse_gcr_fixed(SolveCtx& S, int vp, int op, const void* b, void* x, int iters) {
     mglma_ctx* c = S.c;
+    if (c->eo_ok && S.p->coarse_eo && vp == MGLMA_F32 && op == MGLMA_BF16) return coarse_gcr_eo(S, b, x, iters);
     const int nrhs = S.nrhs;
     const size_t n = coarse_n(c);
     const size_t vb = prec_cbytes(vp);
@@ -244,6 +248,44 @@ static int coarse_gcr_fixed(SolveCtx& S, int vp, int op, const void* b, void* x,
         MG_TRY(mg_update_norm(c, vp, S.s.calpha(), x, pj, r, qj, n, nrhs, nullptr));
     }
     HIP_TRY(hipGetLastError());
+    return MGLMA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the same on the even-odd reduced system (all coarse extents even, BF16 hops,
+// FP32 vectors): S x_e = D_ee^{-1} b_e - H_eo D_oo^{-1} b_o with
+// S = 1 - H_eo H_oe, then x_o = D_oo^{-1} b_o - H_oe x_e
+// ---------------------------------------------------------------------------
+static int coarse_gcr_eo(SolveCtx& S, const void* b, void* x, int iters) {
+    mglma_ctx* c = S.c;
+    const int nrhs = S.nrhs;
+    const size_t n = (size_t)c->eo_Vh * c->nc, vb = 8;
+    const size_t setsz = (size_t)nrhs * n;
+    const int mc = iters < S.s.m ? iters : S.s.m;
+    void *P, *Q, *r, *w;
+    MG_TRY(mg_scratch(c, WS_CP, (size_t)mc * setsz * vb, &P));
+    MG_TRY(mg_scratch(c, WS_CQ, (size_t)mc * setsz * vb, &Q));
+    MG_TRY(mg_scratch(c, WS_CR, setsz * vb, &r));
+    MG_TRY(mg_scratch(c, WS_EO, 3 * setsz * vb, &w));
+    char* to = (char*)w;             // D_oo^{-1} b_o, at the end x_o
+    char* tmp = to + setsz * vb;     // odd vector of the Schur apply
+    char* xe = tmp + setsz * vb;
+    MG_TRY(mg_eo_diag_inv(c, b, r, to, nrhs));
+    MG_TRY(mg_eo_hop(c, 0, to, r, r, nrhs));
+    MG_TRY(mg_zero(c, xe, setsz * vb));
+    for (int k = 0; k < iters; ++k) {
+        int j = k % mc;
+        char* pj = (char*)P + (size_t)j * setsz * vb;
+        char* qj = (char*)Q + (size_t)j * setsz * vb;
+        MG_TRY(mg_eo_schur(c, r, qj, tmp, nrhs));
+        S.coarse_applies++;
+        if (j > 0) MG_TRY(mg_multidot(c, MGLMA_F32, Q, setsz, j, qj, n, nrhs, S.s.cbeta(), S.s.cnw2()));
+        MG_TRY(mg_orth_step(c, MGLMA_F32, Q, P, setsz, j, S.s.cbeta(), qj, pj, r, r, n, nrhs, S.s.calpha(),
+                            S.s.cnw2() + (size_t)j * nrhs, nullptr));
+        MG_TRY(mg_update_norm(c, MGLMA_F32, S.s.calpha(), xe, pj, r, qj, n, nrhs, nullptr));
+    }
+    MG_TRY(mg_eo_hop(c, 1, xe, to, to, nrhs));
+    MG_TRY(mg_eo_scatter(c, xe, to, x, nrhs));
     return MGLMA_OK;
 }
 

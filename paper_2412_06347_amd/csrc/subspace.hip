@@ -673,6 +673,9 @@ extern "C" int mglma_build_subspace(mglma_ctx* c, int Nv, const double* tv) {
         hipLaunchKernelGGL(k_coarse_gamma, dim3(g.V1 * g.b[0]), dim3(256), 0, c->stream, g, Nv, c->B64, c->G1);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(c->stream));
+
+    // 5. even-odd reduced form of D_1 where the coarse lattice allows it
+    MG_TRY(mg_eo_setup(c));
     c->have_subspace = true;
     return MGLMA_OK;
 }

@@ -28,7 +28,7 @@ SYMBOLS = [
     "mglma_point_sources", "mglma_noise_sources",
     "mglma_contract_point", "mglma_contract_point_coarse", "mglma_contract_stoch",
     "mglma_contract_stoch_coarse", "mglma_contract_top", "mglma_coarse_eigs", "mglma_fine_eigs",
-    "mglma_deficit",
+    "mglma_deficit", "mglma_coarse_schur_apply",
 ]
 
 
@@ -41,7 +41,8 @@ class SolveParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_outer", C.c_int), ("max_inner", C.c_int),
                 ("gcr_m", C.c_int), ("inner_tol", C.c_double), ("nu_post", C.c_int),
                 ("coarse_iters", C.c_int), ("smoother", C.c_int), ("inner", C.c_int),
-                ("coarse", C.c_int), ("use_mg", C.c_int), ("smoother_alg", C.c_int)]
+                ("coarse", C.c_int), ("use_mg", C.c_int), ("smoother_alg", C.c_int),
+                ("coarse_eo", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -97,7 +98,7 @@ def _ptr(t):
 def default_params(**kw):
     p = SolveParams(tol=1e-10, max_outer=12, max_inner=200, gcr_m=16, inner_tol=1e-5,
                     nu_post=4, coarse_iters=16, smoother=F32, inner=F32, coarse=F32, use_mg=1,
-                    smoother_alg=SMOOTH_MR)
+                    smoother_alg=SMOOTH_MR, coarse_eo=1)
     for k, v in kw.items():
         setattr(p, k, v)
     return p
@@ -205,6 +206,14 @@ class Context:
 
     def coarse_apply(self, x, y, prec=F64, gamma5=0):
         _check(lib().mglma_coarse_apply(self._ctx, prec, gamma5, _ptr(x), _ptr(y), x.shape[0]))
+
+    @property
+    def has_eo(self):
+        return self.query(8) == 1
+
+    def coarse_schur_apply(self, x, y):
+        """y = (1 - D_ee^-1 D_eo D_oo^-1 D_oe) x on even-site FP32 vectors [n][V1/2][nc][2]."""
+        _check(lib().mglma_coarse_schur_apply(self._ctx, _ptr(x), _ptr(y), x.shape[0]))
 
     def set_top_modes(self, modes):
         _check(lib().mglma_set_top_modes(self._ctx, modes.shape[0], _ptr(modes)))

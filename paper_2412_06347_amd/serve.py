@@ -109,11 +109,11 @@ class Engine:
             self.G_top = ctx.contract_top()
         self.stream.synchronize()
         self.params = params or mglma.default_params(tol=1e-10, max_outer=10, max_inner=120, gcr_m=8,
-                                                     inner_tol=1e-5, nu_post=6, coarse_iters=8,
+                                                     inner_tol=1e-5, nu_post=6, coarse_iters=4,
                                                      smoother=mglma.F16, inner=mglma.F32, coarse=mglma.BF16,
-                                                     smoother_alg=mglma.SMOOTH_CAGCR)
-        self.coarse_params = coarse_params or mglma.default_params(tol=1e-10, coarse=mglma.BF16, coarse_iters=16,
-                                                                   max_outer=40)
+                                                     smoother_alg=mglma.SMOOTH_CAGCR, coarse_eo=1)
+        self.coarse_params = coarse_params or mglma.default_params(tol=1e-10, coarse=mglma.BF16, coarse_iters=12,
+                                                                   max_outer=40, coarse_eo=1)
         self.resident = ctx.resident_bytes() + self.U.numel() * 8
 
     @property

@@ -208,3 +208,52 @@ def test_deficit():
     pn = np.linalg.norm(B.prolong(B.restrict(psi)).reshape(2, -1), axis=1)
     n = np.linalg.norm(psi.reshape(2, -1), axis=1)
     assert np.abs((pn / n) ** 2 + eps ** 2 - 1.0).max() < 1e-13
+
+
+def test_even_odd_split():
+    """The oracle's even-odd reduction of D_1 (coarse solves with the even-odd
+    preconditioned coarse operator, sec. "Comparison of the cost"), pinned by
+    * the parity lists against coordinates taken from fine sites through
+      Blocking.block_of (an independent route to the block index),
+    * the stencil (fig:A): with every coarse extent even, the same-parity
+      blocks of the dense D_1 are block diagonal (one nc x nc block per site),
+    * the Schur determinant identity det D_1 = det A_ee det A_oo det S,
+    * the reduced solve plus reconstruction against a dense solve of D_1."""
+    L, b, Nv = (4, 4, 8, 4), (2, 2, 2, 2), 3
+    U, D, bl, tv, B = _setup(L, b, Nv, seed=12)
+    D1 = coarse.galerkin(D, B)
+    nbr = bl.neighbour_table()
+    L1 = bl.L1
+    nc = 2 * Nv
+    e, o = coarse.parity_sites(L1)
+    assert len(e) == len(o) == bl.V1 // 2
+    assert np.all(np.diff(e) > 0) and np.all(np.diff(o) > 0)
+    for y, par in [(int(s), 0) for s in e] + [(int(s), 1) for s in o]:
+        yc = None
+        for x0 in range(L[0]):
+            for x1 in range(L[1]):
+                for x2 in range(L[2]):
+                    for x3 in range(L[3]):
+                        if bl.block_of((x0, x1, x2, x3)) == y and yc is None:
+                            yc = (x0 // b[0], x1 // b[1], x2 // b[2], x3 // b[3])
+        assert sum(yc) % 2 == par
+    Aee, Aeo, Aoe, Aoo = coarse.eo_split(D1, nbr, L1)
+    Vh = bl.V1 // 2
+    for M in (Aee, Aoo):
+        blk = M.reshape(Vh, nc, Vh, nc)
+        off = blk * (1 - np.eye(Vh))[:, None, :, None]
+        assert np.abs(off).max() == 0.0
+    A = coarse.coarse_dense(D1, nbr)
+    # the split covers A exactly
+    assert abs(np.linalg.norm(A) ** 2 - sum(np.linalg.norm(M) ** 2 for M in (Aee, Aeo, Aoe, Aoo))) < 1e-9
+    S = coarse.schur_even(D1, nbr, L1)
+    s_a, l_a = np.linalg.slogdet(A)
+    parts = [np.linalg.slogdet(M) for M in (Aee, Aoo, S)]
+    assert abs(l_a - sum(p[1] for p in parts)) < 1e-9
+    assert abs(s_a - np.prod([p[0] for p in parts])) < 1e-9
+    rhs = synth.gaussian_coarse(1, bl.V1, nc, 3)[0]
+    x = coarse.solve_eo(D1, nbr, L1, rhs)
+    ref = np.linalg.solve(A, rhs.reshape(-1)).reshape(bl.V1, nc)
+    assert np.abs(x - ref).max() < 1e-11 * np.abs(ref).max()
+    # the reduced system is better conditioned than D_1 on this operator
+    assert np.linalg.cond(S) < np.linalg.cond(A)
