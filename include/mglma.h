@@ -119,7 +119,8 @@ int  mglma_set_stream(mglma_ctx* ctx, void* stream);
 const char* mglma_strerror(int code);
 /* Sizes: 0 V, 1 V1, 2 Vb, 3 Nv, 4 nc, 5 Nlm, 6 r = 2 Nlm, 7 spatial volume;
  * 8: 1 if the even-odd reduced coarse operator is set up (every coarse extent
- * even, nc <= 64, non-singular self blocks), else 0.                        */
+ * even, nc <= 64, non-singular self blocks), else 0; 9: V2, the number of
+ * level-2 blocks (0 before mglma_build_level2).                            */
 long mglma_query(const mglma_ctx* ctx, int what);
 /* Device bytes held by the context (gauge, clover, basis, coarse op, ...). */
 size_t mglma_resident_bytes(const mglma_ctx* ctx);
@@ -185,6 +186,43 @@ int mglma_coarse_apply(mglma_ctx* ctx, int prec, int gamma5, const void* in_dev,
  * (no even-odd form: a coarse extent odd, nc > 64 or a singular self
  * block).                                                                   */
 int mglma_coarse_schur_apply(mglma_ctx* ctx, const void* in_dev, void* out_dev, int nrhs);
+
+/* ---- level 2 of the nested hierarchy ------------------------------------- */
+/* Nested block decomposition (sec. "Multigrid low-mode averaging",
+ * eq:block_nested_decomp): level-2 blocks of b2[mu] fine sites, each b2[mu]
+ * a multiple of the level-1 block size and a divisor of L[mu], i.e. each the
+ * union of r_mu = b2_mu / b_mu level-1 blocks per direction.  The inner-level
+ * restrictor sums a level-1 coarse field over the level-1 sites of a level-2
+ * block with weight sqrt(V2/V1) (component by component), the prolongator
+ * is its adjoint (R_1 T_1 = 1), and D_2 = R_1 D_1 T_1 (the recursion
+ * Q_{l+1} = R_l Q_l T_l) as a nine-entry stencil on the level-2 grid, same
+ * layout and direction convention as D_1, FP64 with FP32 / BF16 copies.
+ * Level-2 fields: [nrhs][V2][nc] complex, sites in C order of the level-2
+ * coordinates (time slowest).  Building a new subspace drops level 2.
+ * Synchronising.  Errors: ARG, NO_SUBSPACE, SHAPE.                          */
+int mglma_build_level2(mglma_ctx* ctx, const int b2[4]);
+/* D_2 as [V2][9][nc][nc] complex128 (row index = output).  Errors:
+ * NO_SUBSPACE (no level 2).                                                 */
+int mglma_export_level2_op(mglma_ctx* ctx, double* out_dev);
+/* out2 = R_1 in1 (level-1 -> level-2 fields), out1 = T_1 in2; F64 or F32.  */
+int mglma_level2_restrict(mglma_ctx* ctx, int prec, const void* in1_dev, void* out2_dev, int nrhs);
+int mglma_level2_prolong(mglma_ctx* ctx, int prec, const void* in2_dev, void* out1_dev, int nrhs);
+/* out = D_2 in (gamma5 = 0) or Q_2 in (gamma5 = 1); prec as in
+ * mglma_coarse_apply.                                                       */
+int mglma_level2_apply(mglma_ctx* ctx, int prec, int gamma5, const void* in_dev, void* out_dev, int nrhs);
+/* x = D_2^{-1} b (level-2 fields, F64) to relative residual p->tol: FP64
+ * defect correction around p->coarse_iters GCR steps with the p->coarse
+ * operator (the level-1 even-odd form does not apply).  Synchronising.
+ * Errors: ARG, NO_SUBSPACE, NONFINITE, NOT_CONVERGED.                       */
+int mglma_level2_solve(mglma_ctx* ctx, const mglma_solve_params* p, const double* b_dev,
+                       double* x_dev, int nrhs, mglma_solve_stats* stats);
+/* The level-2 propagator piece for fine sources eta (device layout, F64):
+ * ge2_dev = T_1 D_2^{-1} R_1 R_0 eta as level-1 coarse fields (F64), so that
+ * T_0 ge2 = T_0 T_1 D_2^{-1} R_1 R_0 eta and the level-1 contractions apply
+ * (level sums by bilinearity: S_1 = T_0 (ge1 - ge2), S_2 = T_0 ge2 - top).
+ * Synchronising.  Errors: ARG, NO_SUBSPACE, NOT_CONVERGED.                  */
+int mglma_level2_pieces(mglma_ctx* ctx, const mglma_solve_params* p, const double* eta_dev,
+                        double* ge2_dev, int nrhs);
 
 /* ---- top (exact) level -------------------------------------------------- */
 /* Set the exact top level from Nlm coarse vectors modes_dev ([Nlm][V1][nc]

@@ -199,3 +199,38 @@ def solve_eo(D1, nbr, L1, b):
     x[e] = xe.reshape(-1, nc)
     x[o] = xo.reshape(-1, nc)
     return x
+
+
+# ---- nested hierarchy: inner levels (sec. "Multigrid low-mode averaging") ----
+
+def level2_of(L1, r):
+    """For every level-1 site y (C order over L1) the index z of the level-2
+    block that contains it (eq:block_nested_decomp: blocks of r_mu level-1
+    sites per direction, z in C order over L1 / r)."""
+    L2 = tuple(L1[mu] // r[mu] for mu in range(4))
+    yc = np.stack(np.unravel_index(np.arange(int(np.prod(L1))), tuple(L1)))
+    zc = yc // np.asarray(r)[:, None]
+    return np.ravel_multi_index(tuple(zc), L2)
+
+
+def inner_restrictor(L1, r, nc):
+    """Dense R_l (V2 nc x V1 nc) of an inner level: (R psi)_a(z) =
+    sqrt(V2/V1) sum_{y in z} psi_a(y), component by component.  The
+    prolongator T_l is its (real) transpose."""
+    V1 = int(np.prod(L1))
+    V2 = V1 // int(np.prod(r))
+    z = level2_of(L1, r)
+    R = np.zeros((V2 * nc, V1 * nc))
+    w = np.sqrt(V2 / V1)
+    for y in range(V1):
+        for a in range(nc):
+            R[z[y] * nc + a, y * nc + a] = w
+    return R
+
+
+def level2_dense(D1, nbr, L1, r):
+    """D_2 = R_1 D_1 T_1 (the recursion Q_{l+1} = R_l Q_l T_l; R_1 acts
+    component-wise, so it commutes with the coarse gamma5), dense."""
+    nc = D1.shape[2]
+    R = inner_restrictor(L1, r, nc)
+    return R @ coarse_dense(D1, nbr) @ R.T

@@ -217,9 +217,14 @@ __global__ void k_coarse_bf16(Geo g, int nc, const bf16_t* __restrict__ Dbf, con
 }
 
 int mg_coarse_apply(mglma_ctx* c, int prec, int gamma5, const void* in, void* out, int nrhs) {
+    return mg_stencil_apply(c, c->geo, c->nc, c->D64p, c->D32p, c->Dbf, prec, gamma5, in, out, nrhs);
+}
+
+// any level: the stencil of the grid g.L1 (block grid of a Geo) with planar
+// copies P64 / P32 / Pbf [V][9][re/im][nc][nc]
+int mg_stencil_apply(mglma_ctx* c, const Geo& g, int nc, const double* P64, const float* P32, const bf16_t* Pbf,
+                     int prec, int gamma5, const void* in, void* out, int nrhs) {
     if (nrhs <= 0) return MGLMA_OK;
-    const Geo& g = c->geo;
-    const int nc = c->nc;
     if (prec == MGLMA_BF16) {
         // up to four row tiles: three direction groups, three times the wavefronts
         // in flight per coarse site
@@ -229,18 +234,18 @@ int mg_coarse_apply(mglma_ctx* c, int prec, int gamma5, const void* in, void* ou
         if (ntr <= 4) {
             dim3 block(64 * ntr * DG);
             if (nc % 16 == 0)
-                hipLaunchKernelGGL((k_coarse_bf16<true, DG>), grid, block, 0, c->stream, g, nc, c->Dbf,
+                hipLaunchKernelGGL((k_coarse_bf16<true, DG>), grid, block, 0, c->stream, g, nc, Pbf,
                                    (const float2*)in, (float2*)out, nrhs, gamma5);
             else
-                hipLaunchKernelGGL((k_coarse_bf16<false, DG>), grid, block, 0, c->stream, g, nc, c->Dbf,
+                hipLaunchKernelGGL((k_coarse_bf16<false, DG>), grid, block, 0, c->stream, g, nc, Pbf,
                                    (const float2*)in, (float2*)out, nrhs, gamma5);
         } else {
             dim3 block(64 * ntr);
             if (nc % 16 == 0)
-                hipLaunchKernelGGL((k_coarse_bf16<true, 1>), grid, block, 0, c->stream, g, nc, c->Dbf,
+                hipLaunchKernelGGL((k_coarse_bf16<true, 1>), grid, block, 0, c->stream, g, nc, Pbf,
                                    (const float2*)in, (float2*)out, nrhs, gamma5);
             else
-                hipLaunchKernelGGL((k_coarse_bf16<false, 1>), grid, block, 0, c->stream, g, nc, c->Dbf,
+                hipLaunchKernelGGL((k_coarse_bf16<false, 1>), grid, block, 0, c->stream, g, nc, Pbf,
                                    (const float2*)in, (float2*)out, nrhs, gamma5);
         }
         HIP_TRY(hipGetLastError());
@@ -252,18 +257,18 @@ int mg_coarse_apply(mglma_ctx* c, int prec, int gamma5, const void* in, void* ou
     switch (prec) {
         case MGLMA_F64:
             if (vec)
-                hipLaunchKernelGGL((k_coarse_mfma<double, true>), grid, block, 0, c->stream, g, nc, c->D64p,
+                hipLaunchKernelGGL((k_coarse_mfma<double, true>), grid, block, 0, c->stream, g, nc, P64,
                                    (const double2*)in, (double2*)out, nrhs, gamma5);
             else
-                hipLaunchKernelGGL((k_coarse_mfma<double, false>), grid, block, 0, c->stream, g, nc, c->D64p,
+                hipLaunchKernelGGL((k_coarse_mfma<double, false>), grid, block, 0, c->stream, g, nc, P64,
                                    (const double2*)in, (double2*)out, nrhs, gamma5);
             break;
         case MGLMA_F32:
             if (vec)
-                hipLaunchKernelGGL((k_coarse_mfma<float, true>), grid, block, 0, c->stream, g, nc, c->D32p,
+                hipLaunchKernelGGL((k_coarse_mfma<float, true>), grid, block, 0, c->stream, g, nc, P32,
                                    (const float2*)in, (float2*)out, nrhs, gamma5);
             else
-                hipLaunchKernelGGL((k_coarse_mfma<float, false>), grid, block, 0, c->stream, g, nc, c->D32p,
+                hipLaunchKernelGGL((k_coarse_mfma<float, false>), grid, block, 0, c->stream, g, nc, P32,
                                    (const float2*)in, (float2*)out, nrhs, gamma5);
             break;
         default: return MGLMA_ERR_ARG;

@@ -169,6 +169,7 @@ void mg_free_subspace(mglma_ctx* c) {
     const Geo& g = c->geo;
     free_top(c);
     mg_eo_free(c);
+    mg_free_level2(c);
     size_t nb = (size_t)g.V * 12 * c->Nv;
     mg_free(c, c->B64, nb * 16); c->B64 = nullptr;
     mg_free(c, c->B32, nb * 8); c->B32 = nullptr;
@@ -222,6 +223,7 @@ extern "C" long mglma_query(const mglma_ctx* c, int what) {
         case 6: return c->r;
         case 7: return c->geo.V3;
         case 8: return c->eo_ok ? 1 : 0;
+        case 9: return c->have_l2 ? c->g2.V1 : 0;
         default: return MGLMA_ERR_ARG;
     }
 }

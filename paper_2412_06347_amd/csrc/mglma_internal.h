@@ -256,6 +256,13 @@ struct mglma_ctx {
     float* eo_Dinv32 = nullptr;    // [V1][re/im][nc][nc] inverse self blocks, FP32 planar
     bf16_t* eo_Hbf = nullptr;      // [V1][8][2][nc][nc] D_yy^{-1} D_y,dir planar bfloat16
 
+    // level 2 of the nested hierarchy: blocks of b2 fine sites (multiples of b),
+    // D_2 = R_1 D_1 T_1 with the aggregating R_1 (same nc, grid g2.L1, V2 = g2.V1)
+    bool have_l2 = false;
+    int b2[4] = {0, 0, 0, 0};
+    Geo g2;
+    double2* L2D64 = nullptr; double* L2D64p = nullptr; float* L2D32p = nullptr; bf16_t* L2Dbf = nullptr;
+
     // top level
     int Nlm = 0, r = 0;
     double2* W = nullptr;                          // [r][V1][nc]
@@ -308,12 +315,22 @@ int mg_copy(mglma_ctx* c, void* dst, const void* src, size_t bytes);
 int mg_restrict(mglma_ctx* c, int prec, const void* fine, void* coarse, int nrhs);
 int mg_prolong(mglma_ctx* c, int prec, const void* coarse, void* fine, int nrhs);
 int mg_coarse_apply(mglma_ctx* c, int prec, int gamma5, const void* in, void* out, int nrhs);
+int mg_stencil_apply(mglma_ctx* c, const Geo& g, int nc, const double* P64, const float* P32, const bf16_t* Pbf,
+                     int prec, int gamma5, const void* in, void* out, int nrhs);
 
 // sizes
 static inline size_t prec_cbytes(int prec) {
     return prec == MGLMA_F64 ? 16 : prec == MGLMA_F32 ? 8 : 4;
 }
 void mg_free_subspace(mglma_ctx* c);
+void mg_free_level2(mglma_ctx* c);
+int mg_op_copies(mglma_ctx* c, size_t nblk, int nc, const double2* D, double* D64p, float* D32p, bf16_t* Dbf);
+// solve D_level x = b (level 1 or 2; coarse fields F64) to p->tol
+int mg_coarse_solve(mglma_ctx* c, const mglma_solve_params* p, const double* b, double* x, int nrhs,
+                    mglma_solve_stats* stats, int level = 1);
+// level-1 <-> level-2 coarse fields (aggregation with weight sqrt(V2/V1)); F64 or F32
+int mg_l2_restrict(mglma_ctx* c, int prec, const void* in1, void* out2, int nrhs);
+int mg_l2_prolong(mglma_ctx* c, int prec, const void* in2, void* out1, int nrhs);
 
 // even-odd reduced coarse operator; vectors on one parity are compressed,
 // [nrhs][Vh][nc] FP32 complex

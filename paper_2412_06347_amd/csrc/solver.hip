@@ -205,10 +205,19 @@ struct SolveCtx {
     int nrhs;
     Scal s;
     int coarse_applies = 0;
+    int level = 1;   // coarse GCR on D_1 or on the level-2 operator D_2
 };
 
 static inline size_t fine_n(mglma_ctx* c) { return (size_t)c->geo.V * 12; }
 static inline size_t coarse_n(mglma_ctx* c) { return (size_t)c->geo.V1 * c->nc; }
+static inline size_t level_n(mglma_ctx* c, int level) {
+    return (size_t)(level == 2 ? c->g2.V1 : c->geo.V1) * c->nc;
+}
+static int level_apply(mglma_ctx* c, int level, int prec, const void* in, void* out, int nrhs) {
+    if (level == 2)
+        return mg_stencil_apply(c, c->g2, c->nc, c->L2D64p, c->L2D32p, c->L2Dbf, prec, 0, in, out, nrhs);
+    return mg_coarse_apply(c, prec, 0, in, out, nrhs);
+}
 
 // ---------------------------------------------------------------------------
 // coarse GCR with a fixed number of steps (preconditioner use, no host sync)
@@ -218,9 +227,10 @@ static int coarse_gcr_eo(SolveCtx& S, const void* b, void* x, int iters);
 
 static int coarse_gcr_fixed(SolveCtx& S, int vp, int op, const void* b, void* x, int iters) {
     mglma_ctx* c = S.c;
-    if (c->eo_ok && S.p->coarse_eo && vp == MGLMA_F32 && op == MGLMA_BF16) return coarse_gcr_eo(S, b, x, iters);
+    if (S.level == 1 && c->eo_ok && S.p->coarse_eo && vp == MGLMA_F32 && op == MGLMA_BF16)
+        return coarse_gcr_eo(S, b, x, iters);
     const int nrhs = S.nrhs;
-    const size_t n = coarse_n(c);
+    const size_t n = level_n(c, S.level);
     const size_t vb = prec_cbytes(vp);
     // restart length: all iterations up to the direction storage of S.s (>= 8)
     const int mc = iters < S.s.m ? iters : S.s.m;
@@ -239,7 +249,7 @@ static int coarse_gcr_fixed(SolveCtx& S, int vp, int op, const void* b, void* x,
         if (vp == MGLMA_F64) opp = MGLMA_F64;
         // q_j = D1 r, then p_j = r - sum_i beta_i p_i and q_j -= sum_i beta_i q_i with
         // beta_i = <q_i, q_j>/|q_i|^2, and alpha = <q_j, r>/|q_j|^2 in the same pass
-        MG_TRY(mg_coarse_apply(c, opp, 0, r, qj, nrhs));
+        MG_TRY(level_apply(c, S.level, opp, r, qj, nrhs));
         S.coarse_applies++;
         if (j > 0) MG_TRY(mg_multidot(c, vp, Q, setsz, j, qj, n, nrhs, S.s.cbeta(), S.s.cnw2()));
         MG_TRY(mg_orth_step(c, vp, Q, P, setsz, j, S.s.cbeta(), qj, pj, r, r, n, nrhs, S.s.calpha(),
@@ -557,10 +567,10 @@ extern "C" int mglma_solve(mglma_ctx* c, const mglma_solve_params* p, const doub
 // operator p->coarse) in rounds of coarse_iters steps
 // ---------------------------------------------------------------------------
 int mg_coarse_solve(mglma_ctx* c, const mglma_solve_params* p, const double* b, double* x, int nrhs,
-                    mglma_solve_stats* stats) {
-    const size_t n = coarse_n(c), setsz = (size_t)nrhs * n;
+                    mglma_solve_stats* stats, int level) {
+    const size_t n = level_n(c, level), setsz = (size_t)nrhs * n;
     SolveCtx S;
-    S.c = c; S.p = p; S.nrhs = nrhs;
+    S.c = c; S.p = p; S.nrhs = nrhs; S.level = level;
     S.s.nrhs = nrhs;
     // coarse GCR without restarts for up to 32 steps per defect-correction cycle
     S.s.m = p->coarse_iters < 8 ? 8 : (p->coarse_iters > 32 ? 32 : p->coarse_iters);
@@ -606,7 +616,7 @@ int mg_coarse_solve(mglma_ctx* c, const mglma_solve_params* p, const double* b, 
             hipLaunchKernelGGL((k_accum<float2, float>), dim3(256, nrhs), dim3(256), 0, c->stream, (double2*)x,
                                (const float2*)e, S.s.scale(), n);
         HIP_TRY(hipGetLastError());
-        MG_TRY(mg_coarse_apply(c, MGLMA_F64, 0, x, t64, nrhs));
+        MG_TRY(level_apply(c, level, MGLMA_F64, x, t64, nrhs));
         hipLaunchKernelGGL(k_xmy, grid1(setsz), dim3(256), 0, c->stream, (const double2*)b, t64, r64, setsz);
         MG_TRY(mg_norm2(c, MGLMA_F64, r64, n, nrhs, S.s.rn2()));
         HIP_TRY(hipMemcpyAsync(h, S.s.rn2(), nrhs * sizeof(double), hipMemcpyDeviceToHost, c->stream));

@@ -661,9 +661,7 @@ extern "C" int mglma_build_subspace(mglma_ctx* c, int Nv, const double* tv) {
 
     // 3. Galerkin operator, block by block (the column-major FP64 copy is the scratch of the pieces)
     MG_TRY(mg_galerkin(c, (double2*)c->D64p));
-    hipLaunchKernelGGL(k_op_copies, dim3(2048), dim3(256), 0, c->stream, (size_t)g.V1 * 9, nc, c->D64, c->D64p, c->D32p,
-                       c->Dbf);
-    HIP_TRY(hipGetLastError());
+    MG_TRY(mg_op_copies(c, (size_t)g.V1 * 9, nc, c->D64, c->D64p, c->D32p, c->Dbf));
 
     // 4. coarse gamma matrices
     if ((g.Vb / g.b[0]) % 4 == 0 && Nv <= 32)
@@ -677,6 +675,12 @@ extern "C" int mglma_build_subspace(mglma_ctx* c, int Nv, const double* tv) {
     // 5. even-odd reduced form of D_1 where the coarse lattice allows it
     MG_TRY(mg_eo_setup(c));
     c->have_subspace = true;
+    return MGLMA_OK;
+}
+
+int mg_op_copies(mglma_ctx* c, size_t nblk, int nc, const double2* D, double* D64p, float* D32p, bf16_t* Dbf) {
+    hipLaunchKernelGGL(k_op_copies, dim3(2048), dim3(256), 0, c->stream, nblk, nc, D, D64p, D32p, Dbf);
+    HIP_TRY(hipGetLastError());
     return MGLMA_OK;
 }
 

@@ -16,8 +16,7 @@
 
 typedef std::complex<double> zc;
 
-int mg_coarse_solve(mglma_ctx* c, const mglma_solve_params* p, const double* b, double* x, int nrhs,
-                    mglma_solve_stats* stats);
+
 
 // out[a*ld + r] += sum_e conj(W[a][e]) v[r][e]  via the batched multi-dot
 static int wdot(mglma_ctx* c, const double2* W, int ncols, const double2* v, int nv, double* out_dev) {

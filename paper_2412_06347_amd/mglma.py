@@ -29,6 +29,8 @@ SYMBOLS = [
     "mglma_contract_point", "mglma_contract_point_coarse", "mglma_contract_stoch",
     "mglma_contract_stoch_coarse", "mglma_contract_top", "mglma_coarse_eigs", "mglma_fine_eigs",
     "mglma_deficit", "mglma_coarse_schur_apply",
+    "mglma_build_level2", "mglma_export_level2_op", "mglma_level2_restrict", "mglma_level2_prolong",
+    "mglma_level2_apply", "mglma_level2_solve", "mglma_level2_pieces",
 ]
 
 
@@ -206,6 +208,41 @@ class Context:
 
     def coarse_apply(self, x, y, prec=F64, gamma5=0):
         _check(lib().mglma_coarse_apply(self._ctx, prec, gamma5, _ptr(x), _ptr(y), x.shape[0]))
+
+    @property
+    def V2(self):
+        return self.query(9)
+
+    # ---- level 2 of the nested hierarchy -------------------------------------
+    def build_level2(self, b2):
+        _check(lib().mglma_build_level2(self._ctx, (C.c_int * 4)(*[int(v) for v in b2])))
+
+    def export_level2_op(self, out):
+        _check(lib().mglma_export_level2_op(self._ctx, _ptr(out)))
+
+    def level2_restrict(self, x1, y2, prec=F64):
+        _check(lib().mglma_level2_restrict(self._ctx, prec, _ptr(x1), _ptr(y2), x1.shape[0]))
+
+    def level2_prolong(self, x2, y1, prec=F64):
+        _check(lib().mglma_level2_prolong(self._ctx, prec, _ptr(x2), _ptr(y1), x2.shape[0]))
+
+    def level2_apply(self, x, y, prec=F64, gamma5=0):
+        _check(lib().mglma_level2_apply(self._ctx, prec, gamma5, _ptr(x), _ptr(y), x.shape[0]))
+
+    def level2_solve(self, b, x, params=None):
+        n = b.shape[0]
+        st = (SolveStats * max(n, 1))()
+        _check(lib().mglma_level2_solve(self._ctx, C.byref(params or default_params()), _ptr(b), _ptr(x), n, st))
+        return [dict(outer=s.outer, inner=s.inner, true_rel_res=s.true_rel_res) for s in st[:n]]
+
+    def level2_pieces(self, eta, ge2, params=None):
+        _check(lib().mglma_level2_pieces(self._ctx, C.byref(params or default_params()), _ptr(eta), _ptr(ge2),
+                                         eta.shape[0]))
+
+    def level2_field(self, nrhs, prec=F64, device="cuda"):
+        import torch
+        per = {F64: torch.float64, F32: torch.float32}[prec]
+        return torch.empty((nrhs, self.V2, self.nc, 2), dtype=per, device=device)
 
     @property
     def has_eo(self):

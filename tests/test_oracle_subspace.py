@@ -257,3 +257,49 @@ def test_even_odd_split():
     assert np.abs(x - ref).max() < 1e-11 * np.abs(ref).max()
     # the reduced system is better conditioned than D_1 on this operator
     assert np.linalg.cond(S) < np.linalg.cond(A)
+
+
+def test_inner_level():
+    """Inner-level R_1, T_1 and D_2 = R_1 D_1 T_1 (nested hierarchy), pinned by
+    * the level-2 block index of every level-1 site against Blocking.block_of
+      on the fine lattice with the level-2 block size (an independent route),
+    * R_1 T_1 = 1 and T_1 R_1 a projector,
+    * the nearest-neighbour structure: D_2 couples a level-2 block only to
+      itself and its eight neighbours on the level-2 grid,
+    * the limit of one level-2 block (the coarsest lattice of fig:nesting):
+      D_2 equals the top level spanned by the constant coarse vectors, one per
+      coarse component, built by the TopLevel route (chiral split, Gram-Schmidt,
+      stencil apply)."""
+    L, b, Nv = (8, 4, 4, 8), (2, 2, 2, 2), 2
+    U, D, bl, tv, B = _setup(L, b, Nv, seed=21)
+    D1 = coarse.galerkin(D, B)
+    nbr = bl.neighbour_table()
+    nc = 2 * Nv
+    r = (2, 1, 2, 2)
+    b2 = tuple(b[mu] * r[mu] for mu in range(4))
+    bl2 = subspace.Blocking(L, b2)
+    z = coarse.level2_of(bl.L1, r)
+    for y in range(bl.V1):
+        yc = np.unravel_index(y, bl.L1)
+        x = tuple(int(yc[mu]) * b[mu] for mu in range(4))
+        assert z[y] == bl2.block_of(x)
+    R = coarse.inner_restrictor(bl.L1, r, nc)
+    assert np.abs(R @ R.T - np.eye(R.shape[0])).max() < 1e-14
+    P = R.T @ R
+    assert np.abs(P @ P - P).max() < 1e-14
+    D2 = coarse.level2_dense(D1, nbr, bl.L1, r)
+    nbr2 = bl2.neighbour_table()
+    V2 = bl2.V1
+    for zz in range(V2):
+        for zp in range(V2):
+            if zp not in nbr2[zz]:
+                assert np.abs(D2[zz * nc:(zz + 1) * nc, zp * nc:(zp + 1) * nc]).max() == 0.0
+    # one level-2 block: the top level from the constant coarse vectors
+    rall = bl.L1
+    D2one = coarse.level2_dense(D1, nbr, bl.L1, rall)
+    modes = np.zeros((Nv, bl.V1, nc), dtype=np.complex128)
+    for c in range(Nv):
+        modes[c, :, c] = 1.0
+        modes[c, :, Nv + c] = 1.0
+    top = coarse.TopLevel(modes, D1, nbr, Nv)
+    assert np.abs(D2one - top.D2).max() < 1e-12
