@@ -237,6 +237,58 @@ def local_coherence(wl, degree=64):
     }), flush=True)
 
 
+def hierarchy(wl, reps=3):
+    """The paper's four-level estimator structure (tab:blocks: level-1 blocks,
+    level-2 blocks of twice their size, one level-3 block spanned by the
+    constant coarse vectors, evaluated exactly) on the bench workload: time of
+    the level-2 operator build and of the level-2 propagator pieces for the 12
+    point sources, and the four level contributions of the point correlator."""
+    import torch
+    from paper_2412_06347_amd import mglma
+    P = Pipeline(wl, log_setup=False)
+    ctx = P.ctx
+    P.step(mixed_params(mglma))
+    Nv, nc, V1 = ctx.query(3), ctx.nc, ctx.V1
+    b2 = [2 * b for b in wl["block"]]
+
+    def timed(f):
+        f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            f()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    t_build = timed(lambda: ctx.build_level2(b2))
+    modes = np.zeros((Nv, V1, nc), dtype=np.complex128)
+    for c in range(Nv):
+        modes[c, :, c] = 1.0
+        modes[c, :, Nv + c] = 1.0
+    ctx.set_top_modes(torch.from_numpy(modes.view(np.float64).reshape(Nv, V1, nc, 2)).cuda())
+    cp = mglma.default_params(tol=1e-10, coarse=mglma.BF16, coarse_iters=12, max_outer=40, coarse_eo=1)
+    cg1, ct, cg2 = ctx.coarse(12), ctx.coarse(12), ctx.coarse(12)
+    t_p1 = timed(lambda: ctx.coarse_pieces(P.src, cg1, ct, cp))
+    t_p2 = timed(lambda: ctx.level2_pieces(P.src, cg2, cp))
+    C = dict(all=ctx.contract_point(P.x, P.x, 0), ge1=ctx.contract_point_coarse(cg1, cg1, 0),
+             ge2=ctx.contract_point_coarse(cg2, cg2, 0), top=ctx.contract_point_coarse(ct, ct, 0))
+    G3 = ctx.contract_top()
+    L0 = wl["L"][0]
+    lv = dict(L0=C["all"] - C["ge1"], L1=C["ge1"] - C["ge2"], L2=C["ge2"] - C["top"], L3_point=C["top"])
+    print(json.dumps({
+        "diagnostic": "four-level hierarchy (nested blocks, eq:mglma:decomp) on the bench workload",
+        "levels": {"1": "%s blocks, V1=%d, nc=%d" % ("x".join(map(str, wl["block"])), V1, nc),
+                   "2": "%s blocks, V2=%d" % ("x".join(map(str, b2)), ctx.V2),
+                   "3": "one block: the %d constant coarse vectors, exact (eq:G_LL:exact)" % nc},
+        "build_level2_ms": round(1e3 * t_build, 2),
+        "level1_pieces_ms_12rhs": round(1e3 * t_p1, 2),
+        "level2_pieces_ms_12rhs": round(1e3 * t_p2, 2),
+        "point_correlator_t": list(range(0, L0, max(1, L0 // 8))),
+        "C_levels_real": {k: [float(v[t].real) for t in range(0, L0, max(1, L0 // 8))] for k, v in lv.items()},
+        "G_L3_exact_real": [float(G3[t].real) for t in range(0, L0, max(1, L0 // 8))],
+    }), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -253,6 +305,9 @@ def main():
                     help="local-coherence diagnostic instead of the bench: the 2 Nv lowest exact modes of Q "
                          "(device eigensolver), the block basis from the Nv lowest, the deficits of all "
                          "(default workload 16c32)")
+    ap.add_argument("--hier", action="store_true",
+                    help="four-level hierarchy diagnostic instead of the bench: level-2 build and pieces timed, "
+                         "level contributions of the point correlator")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one MI355X only: the hot path runs on a single GPU "
@@ -272,6 +327,9 @@ def main():
         local_coherence(WORKLOADS["16c32" if args.workload == "24c48" else args.workload])
         return
     wl = WORKLOADS[args.workload]
+    if args.hier:
+        hierarchy(wl)
+        return
     if args.dslash_only:
         L = wl["L"]
         U = torch.from_numpy(synth.gauge_field(L, wl["eps"], wl["seed"]).view(np.float64)).cuda()
