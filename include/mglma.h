@@ -74,7 +74,7 @@ typedef struct {
     double tol;          /* target true relative residual ||b-Mx||/||b||      */
     int    max_outer;    /* FP64 defect-correction cycles                      */
     int    max_inner;    /* inner FGCR iterations per cycle                    */
-    int    gcr_m;        /* inner FGCR restart length                          */
+    int    gcr_m;        /* inner FGCR restart length (1..32)                  */
     double inner_tol;    /* relative reduction asked of each inner solve       */
     int    nu_post;      /* smoothing steps after the coarse correction: MR
                             steps, or the Krylov dimension of the CA-GCR

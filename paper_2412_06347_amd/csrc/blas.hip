@@ -384,7 +384,8 @@ int mg_dot_norm(mglma_ctx* c, int prec, const void* x, const void* y, size_t n, 
 
 // e += a z ; r -= a w ; out[r] = |r|^2 after the update (of the stored values)
 // (NORM = false: the update alone)
-template <typename S, typename R, int C, bool NORM = true>
+// (E = false: no e / z, the residual update alone)
+template <typename S, typename R, int C, bool NORM = true, bool E = true>
 __global__ __launch_bounds__(RB) void k_update_norm(const double* __restrict__ a, S* __restrict__ e, const S* __restrict__ z,
                                                     S* __restrict__ rr, const S* __restrict__ w, size_t n,
                                                     double* part) {
@@ -396,16 +397,18 @@ __global__ __launch_bounds__(RB) void k_update_norm(const double* __restrict__ a
     for_packets<U_DOT>(n / C, [&](size_t p) {
         const size_t o = roff + p * C;
         cx<R> ev[C], rv[C], zv[C], wv[C];
-        ldp<S, R, C>(e + o, ev);
+        if (E) {
+            ldp<S, R, C>(e + o, ev);
+            ldp<S, R, C>(z + o, zv);
+        }
         ldp<S, R, C>(rr + o, rv);
-        ldp<S, R, C>(z + o, zv);
         ldp<S, R, C>(w + o, wv);
 #pragma unroll
         for (int q = 0; q < C; ++q) {
-            cmac(ev[q], al_, zv[q]);
+            if (E) cmac(ev[q], al_, zv[q]);
             cmac(rv[q], -al_, wv[q]);
         }
-        stp<S, R, C>(e + o, ev);
+        if (E) stp<S, R, C>(e + o, ev);
         stp<S, R, C>(rr + o, rv);
         if (NORM) {
             cx<double> rs[C];
@@ -424,10 +427,23 @@ template <typename S, typename R>
 static int update_norm_t(mglma_ctx* c, const double* a, S* e, const S* z, S* r, const S* w, size_t n, int nrhs,
                          double* out) {
     constexpr int C = pk<S>();
-    const bool vec = n % C == 0 && al(e, 16) && al(z, 16) && al(r, 16) && al(w, 16);
+    const bool vec = n % C == 0 && (!e || al(e, 16)) && (!z || al(z, 16)) && al(r, 16) && al(w, 16);
     const size_t np = vec ? n / C : n;
     const int nb = red_blocks(np, U_DOT);
     dim3 grid(nb, nrhs);
+    if (!e) {
+        // residual update and norm only (the caller forms the iterate itself)
+        if (!out) return MGLMA_ERR_ARG;
+        MG_TRY(ensure_red(c, (size_t)nb * nrhs));
+        if (vec)
+            hipLaunchKernelGGL((k_update_norm<S, R, C, true, false>), grid, dim3(RB), 0, c->stream, a, e, z, r, w, n,
+                               c->red_part);
+        else
+            hipLaunchKernelGGL((k_update_norm<S, R, 1, true, false>), grid, dim3(RB), 0, c->stream, a, e, z, r, w, n,
+                               c->red_part);
+        HIP_TRY(hipGetLastError());
+        return launch_finish<1>(c, nb, nrhs, 1, out);
+    }
     if (!out) {
         if (vec)
             hipLaunchKernelGGL((k_update_norm<S, R, C, false>), grid, dim3(RB), 0, c->stream, a, e, z, r, w, n,
@@ -663,7 +679,8 @@ int mg_mr_update(mglma_ctx* c, int prec, const double* a, void* z, void* s, cons
 }
 
 // y1 -= sum_j coef[j][r] x1_j ;  y2 = y2s - sum_j coef[j][r] x2_j  (y2s: y2 itself or another source)
-template <typename S, typename R, int K, int C>
+// (TWO = false: the first set alone; x2, y2, y2s unused)
+template <typename S, typename R, int K, int C, bool TWO = true>
 __global__ void k_multiaxpy2(const S* __restrict__ x1, const S* __restrict__ x2, size_t xstride, int k,
                              const double* __restrict__ coef, S* __restrict__ y1, S* y2, const S* y2s, size_t n,
                              int nrhs) {
@@ -678,27 +695,27 @@ __global__ void k_multiaxpy2(const S* __restrict__ x1, const S* __restrict__ x2,
         const size_t o = roff + p * C;
         cx<R> v1[C], v2[C];
         ldp<S, R, C>(y1 + o, v1);
-        ldp<S, R, C>(y2s + o, v2);
+        if (TWO) ldp<S, R, C>(y2s + o, v2);
 #pragma unroll
         for (int j = 0; j < K; ++j)
             if (j < k) {
                 cx<R> u1[C], u2[C];
                 ldp<S, R, C>(x1 + (size_t)j * xstride + o, u1);
-                ldp<S, R, C>(x2 + (size_t)j * xstride + o, u2);
+                if (TWO) ldp<S, R, C>(x2 + (size_t)j * xstride + o, u2);
 #pragma unroll
                 for (int q = 0; q < C; ++q) {
                     cmac(v1[q], a[j], u1[q]);
-                    cmac(v2[q], a[j], u2[q]);
+                    if (TWO) cmac(v2[q], a[j], u2[q]);
                 }
             }
         stp<S, R, C>(y1 + o, v1);
-        stp<S, R, C>(y2 + o, v2);
+        if (TWO) stp<S, R, C>(y2 + o, v2);
     });
 }
 
 // k_multiaxpy2 that also reduces, over the updated y1, the partials
 // (Re <y1,d>, Im <y1,d>, |y1|^2) (the inner products of the next GCR step)
-template <typename S, typename R, int K, int C>
+template <typename S, typename R, int K, int C, bool TWO = true>
 __global__ __launch_bounds__(RB) void k_orth_dot(const S* __restrict__ x1, const S* __restrict__ x2, size_t xstride,
                                                  int k, const double* __restrict__ coef, S* __restrict__ y1, S* y2,
                                                  const S* y2s, const S* __restrict__ d, size_t n, int nrhs,
@@ -716,21 +733,21 @@ __global__ __launch_bounds__(RB) void k_orth_dot(const S* __restrict__ x1, const
         const size_t o = roff + p * C;
         cx<R> v1[C], v2[C];
         ldp<S, R, C>(y1 + o, v1);
-        ldp<S, R, C>(y2s + o, v2);
+        if (TWO) ldp<S, R, C>(y2s + o, v2);
 #pragma unroll
         for (int j = 0; j < K; ++j)
             if (j < k) {
                 cx<R> u1[C], u2[C];
                 ldp<S, R, C>(x1 + (size_t)j * xstride + o, u1);
-                ldp<S, R, C>(x2 + (size_t)j * xstride + o, u2);
+                if (TWO) ldp<S, R, C>(x2 + (size_t)j * xstride + o, u2);
 #pragma unroll
                 for (int q = 0; q < C; ++q) {
                     cmac(v1[q], a[j], u1[q]);
-                    cmac(v2[q], a[j], u2[q]);
+                    if (TWO) cmac(v2[q], a[j], u2[q]);
                 }
             }
         stp<S, R, C>(y1 + o, v1);
-        stp<S, R, C>(y2 + o, v2);
+        if (TWO) stp<S, R, C>(y2 + o, v2);
         cx<double> w[C], b[C];
         ldp<S, double, C>(y1 + o, w);     // the stored values
         ldp<S, double, C>(d + o, b);
@@ -754,8 +771,10 @@ static int multiaxpy2_t(mglma_ctx* c, const S* x1, const S* x2, size_t xstride, 
                         S* y2, const S* y2s, const S* d, size_t n, int nrhs, double* alpha, double* nw2j,
                         const int* mask) {
     constexpr int C = pk<S>();
-    const bool vec = n % C == 0 && xstride % C == 0 && al(x1, 16) && al(x2, 16) && al(y1, 16) && al(y2, 16) &&
-                     (!y2s || al(y2s, 16)) && (!d || al(d, 16));
+    const bool two = x2 != nullptr;
+    if (two != (y2 != nullptr)) return MGLMA_ERR_ARG;
+    const bool vec = n % C == 0 && xstride % C == 0 && al(x1, 16) && (!x2 || al(x2, 16)) && al(y1, 16) &&
+                     (!y2 || al(y2, 16)) && (!y2s || al(y2s, 16)) && (!d || al(d, 16));
     const size_t np = vec ? n / C : n;
     const dim3 grid = ew_grid(np, nrhs, 1);
     const int nchunk = k > 0 ? (k + MAXK - 1) / MAXK : 1;
@@ -764,15 +783,19 @@ static int multiaxpy2_t(mglma_ctx* c, const S* x1, const S* x2, size_t xstride, 
         const int kk = k - j0 < MAXK ? k - j0 : MAXK;
         const double* cj = coef + (size_t)j0 * nrhs * 2;
         const S* a1 = x1 + (size_t)j0 * xstride;
-        const S* a2 = x2 + (size_t)j0 * xstride;
+        const S* a2 = two ? x2 + (size_t)j0 * xstride : nullptr;
         const S* src = (ch == 0 && y2s) ? y2s : y2;
         if (d && ch == nchunk - 1) {
             const int nb = red_blocks(np, 1);
             MG_TRY(ensure_red(c, (size_t)nb * nrhs * 3));
             const dim3 rg(nb, nrhs);
 #define OD_LAUNCH(KK, CC)                                                                                  \
-            hipLaunchKernelGGL((k_orth_dot<S, R, KK, CC>), rg, dim3(RB), 0, c->stream, a1, a2, xstride, kk, cj, y1, \
-                               y2, src, d, n, nrhs, c->red_part)
+            do if (two)                                                                                        \
+                hipLaunchKernelGGL((k_orth_dot<S, R, KK, CC, true>), rg, dim3(RB), 0, c->stream, a1, a2, xstride, kk, \
+                                   cj, y1, y2, src, d, n, nrhs, c->red_part);                                    \
+            else                                                                                               \
+                hipLaunchKernelGGL((k_orth_dot<S, R, KK, CC, false>), rg, dim3(RB), 0, c->stream, a1, a2, xstride,  \
+                                   kk, cj, y1, y2, src, d, n, nrhs, c->red_part); while (0)
             if (vec) {
                 if (kk <= 0) OD_LAUNCH(1, C); else if (kk <= 4) OD_LAUNCH(4, C); else OD_LAUNCH(MAXK, C);
             } else {
@@ -783,8 +806,12 @@ static int multiaxpy2_t(mglma_ctx* c, const S* x1, const S* x2, size_t xstride, 
             MG_TRY(launch_finish<3>(c, nb, nrhs, 3, alpha, 2, 0, nullptr, nw2j, mask));
         } else {
 #define M2_LAUNCH(KK, CC) \
-            hipLaunchKernelGGL((k_multiaxpy2<S, R, KK, CC>), grid, dim3(256), 0, c->stream, a1, a2, xstride, kk, cj, y1, \
-                               y2, src, n, nrhs)
+            do if (two) \
+                hipLaunchKernelGGL((k_multiaxpy2<S, R, KK, CC, true>), grid, dim3(256), 0, c->stream, a1, a2, xstride, kk, \
+                                   cj, y1, y2, src, n, nrhs); \
+            else \
+                hipLaunchKernelGGL((k_multiaxpy2<S, R, KK, CC, false>), grid, dim3(256), 0, c->stream, a1, a2, xstride, \
+                                   kk, cj, y1, y2, src, n, nrhs); while (0)
             if (vec) {
                 if (kk <= 4) M2_LAUNCH(4, C); else M2_LAUNCH(MAXK, C);
             } else {

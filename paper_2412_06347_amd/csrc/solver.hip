@@ -109,8 +109,42 @@ struct Scal {
     double* cnw2() { return at(20 + 5 * m); }         // [m][nrhs] squared norms of the coarse directions
     double* cagram() { return at(20 + 6 * m); }       // [nrhs][CA_NV] packed Gram values of the CA smoother
     double* cacoef() { return at(20 + 6 * m + CA_NV); }   // complex [CA_K][nrhs] smoother coefficients
-    static size_t bytes(int nrhs, int m) { return (size_t)(20 + 6 * m + CA_NV + 2 * CA_K) * nrhs * 8 + 256; }
+    // fine FGCR cycle history: beta[j][i][nrhs] (complex, i < j), alpha[j][nrhs], gamma[j][nrhs]
+    int hoff() const { return 20 + 6 * m + CA_NV + 2 * CA_K; }
+    double* fbeta() { return at(hoff()); }
+    double* falpha() { return at(hoff() + 2 * m * m); }
+    double* fgamma() { return at(hoff() + 2 * m * m + 2 * m); }
+    static size_t bytes(int nrhs, int m) {
+        return (size_t)(20 + 6 * m + CA_NV + 2 * CA_K + 2 * m * m + 4 * m) * nrhs * 8 + 256;
+    }
 };
+
+// Coefficients of the FGCR iterate on the stored preconditioned vectors z_j.
+// The directions are p_j = z_j - sum_{i<j} beta_ij p_i (never formed) and the
+// iterate gains sum_j alpha_j p_j; eliminating p from the last direction down
+// gives sum_j gamma_j z_j: c = alpha, then for j = jn-1..0: gamma_j = c_j and
+// c_i -= gamma_j beta_ij for i < j.  One thread per right-hand side.
+__global__ void k_gcr_gamma(const double* __restrict__ beta, const double* __restrict__ alpha, int jn, int m,
+                            double* __restrict__ gamma, int nrhs) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    double cr[32], ci[32];
+    for (int j = 0; j < jn; ++j) {
+        cr[j] = alpha[((size_t)j * nrhs + r) * 2];
+        ci[j] = alpha[((size_t)j * nrhs + r) * 2 + 1];
+    }
+    for (int j = jn - 1; j >= 0; --j) {
+        const double gr = cr[j], gi = ci[j];
+        gamma[((size_t)j * nrhs + r) * 2] = gr;
+        gamma[((size_t)j * nrhs + r) * 2 + 1] = gi;
+        const double* bj = beta + (size_t)j * m * nrhs * 2;
+        for (int i = 0; i < j; ++i) {
+            const double br = bj[((size_t)i * nrhs + r) * 2], bi = bj[((size_t)i * nrhs + r) * 2 + 1];
+            cr[i] -= gr * br - gi * bi;
+            ci[i] -= gr * bi + gi * br;
+        }
+    }
+}
 
 // alpha[r] = <w,r>/|w|^2 from dn3 = (Re, Im, |w|^2); also store |w|^2 in nw2j.
 // Right-hand sides with mask[r] == 0 get alpha = 0 (frozen: their iterate no
@@ -428,25 +462,36 @@ static int inner_fgcr(SolveCtx& S, int vp, const void* rin, void* e, const std::
     std::vector<int> mask(nrhs);
     for (int q = 0; q < nrhs; ++q) mask[q] = (active[q] && r0[q] > 0.0) ? 1 : 0;
     HIP_TRY(hipMemcpyAsync(S.s.imask(), mask.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    // e += sum_j gamma_j z_j for the jn directions of the current cycle
+    auto flush = [&](int jn) -> int {
+        hipLaunchKernelGGL(k_gcr_gamma, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, S.s.fbeta(), S.s.falpha(), jn,
+                           m, S.s.fgamma(), nrhs);
+        HIP_TRY(hipGetLastError());
+        return mg_multiaxpy(c, vp, Z, setsz, jn, S.s.fgamma(), 1.0, e, n, nrhs);
+    };
     int k = 0;
     for (; k < p->max_inner; ++k) {
         const int j = k % m;
         char* zj = (char*)Z + (size_t)j * setsz * vb;
         char* wj = (char*)W + (size_t)j * setsz * vb;
+        double* bj = S.s.fbeta() + (size_t)j * m * nrhs * 2;
+        double* aj = S.s.falpha() + (size_t)j * nrhs * 2;
         MG_TRY(precondition(S, vp, r, zj));
         MG_TRY(mg_dslash(c, vp, 0, zj, wj, nrhs));
-        // unnormalised directions: w_j -= sum_i <w_i,w_j>/|w_i|^2 w_i (same on z_j), and in
-        // the same pass alpha = <w_j, r>/|w_j|^2 ; then e += alpha z_j ; r -= alpha w_j ; |r|^2
+        // w_j -= sum_i beta_ij w_i, beta_ij = <w_i,w_j>/|w_i|^2, and in the same pass
+        // alpha_j = <w_j, r>/|w_j|^2 ; then r -= alpha_j w_j ; |r|^2.  z_j stays as the
+        // preconditioner returned it: the iterate is formed from the z_j at the end of the
+        // cycle (k_gcr_gamma), so no pass over the z vectors is needed per step.
         if (j > 0) {
-            MG_TRY(mg_multidot(c, vp, W, setsz, j, wj, n, nrhs, S.s.beta(), S.s.nw2()));
-            MG_TRY(mg_orth_step(c, vp, W, Z, setsz, j, S.s.beta(), wj, zj, nullptr, r, n, nrhs, S.s.alpha(),
+            MG_TRY(mg_multidot(c, vp, W, setsz, j, wj, n, nrhs, bj, S.s.nw2()));
+            MG_TRY(mg_orth_step(c, vp, W, nullptr, setsz, j, bj, wj, nullptr, nullptr, r, n, nrhs, aj,
                                 S.s.nw2() + (size_t)j * nrhs, S.s.imask()));
         } else {
             MG_TRY(mg_dot_norm(c, vp, wj, r, n, nrhs, S.s.dn3()));
-            hipLaunchKernelGGL(k_alpha, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, S.s.dn3(), S.s.alpha(),
+            hipLaunchKernelGGL(k_alpha, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, S.s.dn3(), aj,
                                S.s.nw2() + (size_t)j * nrhs, S.s.imask(), nrhs);
         }
-        MG_TRY(mg_update_norm(c, vp, S.s.alpha(), e, zj, r, wj, n, nrhs, S.s.rn2()));
+        MG_TRY(mg_update_norm(c, vp, aj, nullptr, nullptr, r, wj, n, nrhs, S.s.rn2()));
         HIP_TRY(hipMemcpyAsync(h, S.s.rn2(), nrhs * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(hipStreamSynchronize(c->stream));
         bool done = true, changed = false;
@@ -455,6 +500,7 @@ static int inner_fgcr(SolveCtx& S, int vp, const void* rin, void* e, const std::
             if (mask[q] && h[q] <= p->inner_tol * p->inner_tol * r0[q]) { mask[q] = 0; changed = true; }
             if (mask[q]) done = false;
         }
+        if (done || j == m - 1 || k + 1 == p->max_inner) MG_TRY(flush(j + 1));
         if (done) { ++k; break; }
         if (changed)
             HIP_TRY(hipMemcpyAsync(S.s.imask(), mask.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, c->stream));
@@ -472,7 +518,7 @@ extern "C" int mglma_solve(mglma_ctx* c, const mglma_solve_params* p, const doub
     if (!c || !p || !b || !x || nrhs < 1 || nrhs > 4096) return MGLMA_ERR_ARG;
     if (!c->have_gauge) return MGLMA_ERR_NO_GAUGE;
     if (p->use_mg && !c->have_subspace) return MGLMA_ERR_NO_SUBSPACE;
-    if (p->gcr_m < 1 || p->gcr_m > 64 || p->max_inner < 1 || p->max_outer < 1) return MGLMA_ERR_ARG;
+    if (p->gcr_m < 1 || p->gcr_m > 32 || p->max_inner < 1 || p->max_outer < 1) return MGLMA_ERR_ARG;
     if (p->smoother_alg != MGLMA_SMOOTH_MR && p->smoother_alg != MGLMA_SMOOTH_CAGCR) return MGLMA_ERR_ARG;
     if (p->use_mg && p->smoother_alg == MGLMA_SMOOTH_CAGCR && (p->nu_post < 0 || p->nu_post > CA_K))
         return MGLMA_ERR_ARG;
