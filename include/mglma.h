@@ -96,7 +96,10 @@ typedef struct {
                             operator is BF16 and the vectors FP32 (sec.
                             "Comparison of the cost": even-odd preconditioned
                             coarse operator); coarse_iters then counts
-                            applications of S.  0: GCR on D_1.          */
+                            applications of S.  2: the same GCR deflated
+                            with the nc constant even-site vectors (one per
+                            coarse component; one more S application per
+                            solve).  0: GCR on D_1.                      */
 } mglma_solve_params;
 
 enum { MGLMA_SMOOTH_MR = 0, MGLMA_SMOOTH_CAGCR = 1 };

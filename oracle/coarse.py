@@ -234,3 +234,27 @@ def level2_dense(D1, nbr, L1, r):
     nc = D1.shape[2]
     R = inner_restrictor(L1, r, nc)
     return R @ coarse_dense(D1, nbr) @ R.T
+
+
+def eo_constant_vectors(L1, nc):
+    """Y: (Vh nc) x nc, column a = component a equal to 1/sqrt(Vh) on every
+    even site (the subspace a one-block coarser level spans, restricted to the
+    even sites), the deflation subspace of the even-odd coarse GCR."""
+    Vh = int(np.prod(L1)) // 2
+    Y = np.zeros((Vh * nc, nc))
+    for a in range(nc):
+        Y[a::nc, a] = 1.0 / np.sqrt(Vh)
+    return Y
+
+
+def solve_eo_deflated(S, Y, bh):
+    """S x = bh through the deflated system: x0 = Y E^-1 Y^+ bh (E = Y^+ S Y),
+    z from P_L S z = P_L bh (least squares: P_L S is singular on range Y),
+    x = x0 + P_R z with P_L = 1 - S Y E^-1 Y^+, P_R = 1 - Y E^-1 Y^+ S."""
+    E = Y.conj().T @ S @ Y
+    Ei = np.linalg.inv(E)
+    PL = np.eye(S.shape[0]) - S @ Y @ Ei @ Y.conj().T
+    PR = np.eye(S.shape[0]) - Y @ Ei @ Y.conj().T @ S
+    x0 = Y @ (Ei @ (Y.conj().T @ bh))
+    z = np.linalg.lstsq(PL @ S, PL @ bh, rcond=None)[0]
+    return x0 + PR @ z

@@ -10,6 +10,39 @@ namespace dense {
 
 typedef std::complex<double> zc;
 
+// inv = A^{-1} (n x n, row-major) by Gauss-Jordan elimination with partial
+// pivoting; false if a pivot is exactly zero.
+inline bool inverse(std::vector<zc> A, int n, std::vector<zc>& inv) {
+    inv.assign((size_t)n * n, zc(0));
+    for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < n; ++r)
+            if (std::abs(A[(size_t)r * n + col]) > std::abs(A[(size_t)piv * n + col])) piv = r;
+        if (std::abs(A[(size_t)piv * n + col]) == 0.0) return false;
+        if (piv != col)
+            for (int k = 0; k < n; ++k) {
+                std::swap(A[(size_t)col * n + k], A[(size_t)piv * n + k]);
+                std::swap(inv[(size_t)col * n + k], inv[(size_t)piv * n + k]);
+            }
+        const zc d = 1.0 / A[(size_t)col * n + col];
+        for (int k = 0; k < n; ++k) {
+            A[(size_t)col * n + k] *= d;
+            inv[(size_t)col * n + k] *= d;
+        }
+        for (int r = 0; r < n; ++r) {
+            if (r == col) continue;
+            const zc f = A[(size_t)r * n + col];
+            if (f == zc(0)) continue;
+            for (int k = 0; k < n; ++k) {
+                A[(size_t)r * n + k] -= f * A[(size_t)col * n + k];
+                inv[(size_t)r * n + k] -= f * inv[(size_t)col * n + k];
+            }
+        }
+    }
+    return true;
+}
+
 // A: n x n Hermitian, row-major (destroyed).  On return w[k] are the
 // eigenvalues and column k of V (row-major, V[i * n + k]) the eigenvectors;
 // unsorted.  Each rotation zeroes one off-diagonal pair: with

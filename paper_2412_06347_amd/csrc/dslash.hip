@@ -452,6 +452,11 @@ __global__ __launch_bounds__(256) void k_dslash_h(Geo g, const h2* __restrict__ 
     }
 }
 
+// right-hand sides per thread of the FP32 multi-RHS applies
+#ifndef DSLASH_F32_NB
+#define DSLASH_F32_NB 2
+#endif
+
 // The packed kernel addresses a group of three right-hand sides (3 * 12 * V
 // values) and the 36 V link and clover values through 32-bit buffer offsets.
 static bool dslash_h_fits(size_t V) { return V * 36 * 4 < ((size_t)1 << 31); }
@@ -470,11 +475,14 @@ int mg_dslash(mglma_ctx* c, int prec, int gamma5, const void* in, void* out, int
                 hipLaunchKernelGGL((k_dslash_multi<double2, double2, double, 2>), gm, dim3(256), 0, c->stream, g,
                                    (const double2*)in, (double2*)out, c->U64, c->C64, c->kappa, gamma5, nrhs, ng, ntp);
                 break;
-            case MGLMA_F32:
-                hipLaunchKernelGGL((k_dslash_multi<float2, float2, float, 2>), gm, dim3(256), 0, c->stream, g,
-                                   (const float2*)in, (float2*)out, c->U32, c->C32, (float)c->kappa, gamma5, nrhs, ng,
-                                   ntp);
+            case MGLMA_F32: {
+                constexpr int NBF = DSLASH_F32_NB;
+                const int ngf = (nrhs + NBF - 1) / NBF;
+                hipLaunchKernelGGL((k_dslash_multi<float2, float2, float, NBF>), dim3(ntp * ngf), dim3(256), 0,
+                                   c->stream, g, (const float2*)in, (float2*)out, c->U32, c->C32, (float)c->kappa,
+                                   gamma5, nrhs, ngf, ntp);
                 break;
+            }
             case MGLMA_F16:
                 if (dslash_h_fits(g.V)) {
                     // packed FP16 arithmetic, three right-hand sides per thread
@@ -519,9 +527,10 @@ int mg_dslash_resid16(mglma_ctx* c, const void* z, const void* r, void* p16, con
     if (nrhs <= 0) return MGLMA_OK;
     const Geo& g = c->geo;
     const int ntp = ((g.V + 255) / 256 + 7) / 8 * 8;
-    const int ng = (nrhs + 1) / 2;
+    constexpr int NBF = DSLASH_F32_NB;
+    const int ng = (nrhs + NBF - 1) / NBF;
     if ((size_t)ntp * ng > 0x7fffffffu) return MGLMA_ERR_SHAPE;
-    hipLaunchKernelGGL((k_dslash_multi<float2, float2, float, 2, __half2, true>), dim3(ntp * ng), dim3(256), 0, c->stream,
+    hipLaunchKernelGGL((k_dslash_multi<float2, float2, float, NBF, __half2, true>), dim3(ntp * ng), dim3(256), 0, c->stream,
                        g, (const float2*)z, (__half2*)p16, c->U32, c->C32, (float)c->kappa, 0, nrhs, ng, ntp,
                        (const float2*)r, scale);
     HIP_TRY(hipGetLastError());

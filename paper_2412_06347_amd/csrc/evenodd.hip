@@ -20,6 +20,9 @@
 // of the BF16 coarse operator); D_yy^{-1} in FP32 for the right-hand side and
 // the reconstruction.
 #include "mglma_internal.h"
+#include "dense_small.h"
+
+#include <cmath>
 
 typedef short bf4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
@@ -321,10 +324,144 @@ __global__ void k_coarse_hop_bf16(int nc, int Vh, const int* __restrict__ site, 
 }
 
 // ---------------------------------------------------------------------------
+// deflation with the constant even-site vectors y_a (component a = 1/sqrt(Vh)
+// on every even site, 0 elsewhere): the subspace that a one-block coarser
+// level spans (the coarsest level of tab:blocks restricted to the even sites)
+// ---------------------------------------------------------------------------
+// out[n][a] = sum_k v[n][k][a] / sqrt(Vh) in FP64, two passes.  Pass 1: grid
+// (nrhs, YCH chunks of sites), the 256 threads split into G = 256 / nc groups
+// that stride over the chunk's sites, the G partial sums of a component added
+// in LDS in group order -> part[n][chunk][a].  Pass 2: the chunks in order.
+#define YCH 64
+__global__ __launch_bounds__(256) void k_ydot_part(const float2* __restrict__ v, int Vh, int nc,
+                                                   double2* __restrict__ part) {
+    __shared__ double2 lds[256];
+    const int n = blockIdx.x, ch = blockIdx.y, t = threadIdx.x;
+    const int G = 256 / nc;
+    const int a = t % nc, grp = t / nc;
+    const int k0 = (int)((long)Vh * ch / YCH), k1 = (int)((long)Vh * (ch + 1) / YCH);
+    double re = 0.0, im = 0.0;
+    if (grp < G) {
+        const float2* p = v + (size_t)n * Vh * nc + a;
+        for (int k = k0 + grp; k < k1; k += G) {
+            const float2 x = p[(size_t)k * nc];
+            re += x.x;
+            im += x.y;
+        }
+    }
+    lds[t] = make_double2(re, im);
+    __syncthreads();
+    if (t < nc) {
+        double sr = 0.0, si = 0.0;
+        for (int q = 0; q < G; ++q) {
+            sr += lds[q * nc + t].x;
+            si += lds[q * nc + t].y;
+        }
+        part[((size_t)n * YCH + ch) * nc + t] = make_double2(sr, si);
+    }
+}
+
+__global__ void k_ydot_fin(const double2* __restrict__ part, int nc, int nrhs, double w, double2* __restrict__ out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nrhs * nc) return;
+    const int n = e / nc, a = e - n * nc;
+    double sr = 0.0, si = 0.0;
+    for (int ch = 0; ch < YCH; ++ch) {
+        const double2 x = part[((size_t)n * YCH + ch) * nc + a];
+        sr += x.x;
+        si += x.y;
+    }
+    out[e] = make_double2(w * sr, w * si);
+}
+
+// g[n][a] = sum_b Einv[a][b] c[n][b]   (one thread per (n, a))
+__global__ void k_defl_solve(const double2* __restrict__ Einv, const double2* __restrict__ cin, int nc, int nrhs,
+                             double2* __restrict__ g) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nrhs * nc) return;
+    const int n = e / nc, a = e - n * nc;
+    double re = 0.0, im = 0.0;
+    for (int b = 0; b < nc; ++b) {
+        const double2 m = Einv[(size_t)a * nc + b], x = cin[(size_t)n * nc + b];
+        re += m.x * x.x - m.y * x.y;
+        im += m.x * x.y + m.y * x.x;
+    }
+    g[e] = make_double2(re, im);
+}
+
+// v[n][e] -= sum_b g[n][b] SY[b][e]   (e over Vh * nc): each SY entry is loaded
+// once and applied to up to 16 right-hand sides held in registers; g (FP32)
+// staged in LDS, read as broadcasts
+#define DEFL_MAXR 16
+__global__ __launch_bounds__(256) void k_defl_sub_sy(const float2* __restrict__ SY, const double2* __restrict__ g,
+                                                     float2* __restrict__ v, size_t ne, int nc, int nrhs) {
+    __shared__ float2 gs[DEFL_MAXR * 64];
+    for (int n0 = 0; n0 < nrhs; n0 += DEFL_MAXR) {
+        const int nr = nrhs - n0 < DEFL_MAXR ? nrhs - n0 : DEFL_MAXR;
+        __syncthreads();
+        for (int t = threadIdx.x; t < nr * nc; t += blockDim.x) {
+            const double2 gg = g[(size_t)n0 * nc + t];
+            gs[t] = make_float2((float)gg.x, (float)gg.y);
+        }
+        __syncthreads();
+        for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < ne; e += (size_t)gridDim.x * blockDim.x) {
+            float ar[DEFL_MAXR], ai[DEFL_MAXR];
+#pragma unroll
+            for (int q = 0; q < DEFL_MAXR; ++q) ar[q] = ai[q] = 0.f;
+            for (int b = 0; b < nc; ++b) {
+                const float2 sv = SY[(size_t)b * ne + e];
+#pragma unroll
+                for (int q = 0; q < DEFL_MAXR; ++q)
+                    if (q < nr) {
+                        const float2 gg = gs[q * nc + b];
+                        ar[q] = fmaf(gg.x, sv.x, fmaf(-gg.y, sv.y, ar[q]));
+                        ai[q] = fmaf(gg.x, sv.y, fmaf(gg.y, sv.x, ai[q]));
+                    }
+            }
+#pragma unroll
+            for (int q = 0; q < DEFL_MAXR; ++q)
+                if (q < nr) {
+                    float2* o = v + (size_t)(n0 + q) * ne + e;
+                    const float2 x = *o;
+                    *o = make_float2(x.x - ar[q], x.y - ai[q]);
+                }
+        }
+    }
+}
+
+// v[n][k][a] += w g[n][a]
+__global__ void k_defl_add_y(const double2* __restrict__ g, double w, float2* __restrict__ v, int Vh, int nc,
+                             int nrhs) {
+    const size_t tot = (size_t)nrhs * Vh * nc;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x) {
+        const int a = (int)(e % nc);
+        const int n = (int)(e / ((size_t)Vh * nc));
+        const double2 gg = g[(size_t)n * nc + a];
+        const float2 x = v[e];
+        v[e] = make_float2(x.x + (float)(w * gg.x), x.y + (float)(w * gg.y));
+    }
+}
+
+// Y as an even-site vector set [nc][Vh][nc]
+__global__ void k_defl_y(float2* __restrict__ Y, int Vh, int nc, float w) {
+    const size_t tot = (size_t)nc * Vh * nc;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x) {
+        const int a = (int)(e % nc);
+        const int b = (int)(e / ((size_t)Vh * nc));
+        Y[e] = make_float2(a == b ? w : 0.f, 0.f);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 void mg_eo_free(mglma_ctx* c) {
     const size_t V1 = c->geo.V1, nn = (size_t)c->nc * c->nc;
+    if (c->eo_SY) mg_free(c, c->eo_SY, (size_t)c->nc * c->eo_Vh * c->nc * sizeof(float2));
+    if (c->eo_Einv) mg_free(c, c->eo_Einv, nn * sizeof(double2));
+    c->eo_SY = nullptr;
+    c->eo_Einv = nullptr;
+    c->eo_defl = false;
     if (c->eo_site) mg_free(c, c->eo_site, 2 * (size_t)c->eo_Vh * sizeof(int));
     if (c->eo_nbr) mg_free(c, c->eo_nbr, 2 * (size_t)c->eo_Vh * 8 * sizeof(int));
     if (c->eo_Dinv32) mg_free(c, c->eo_Dinv32, V1 * 2 * nn * sizeof(float));
@@ -334,6 +471,52 @@ void mg_eo_free(mglma_ctx* c) {
     c->eo_Hbf = nullptr;
     c->eo_ok = false;
     c->eo_Vh = 0;
+}
+
+static int grid_el(size_t tot);
+
+// out[n][a] = (Y^+ v_n)_a, FP64
+static int ydot(mglma_ctx* c, const void* v, int nrhs, double2* out) {
+    const int nc = c->nc, Vh = c->eo_Vh;
+    double2* part;
+    MG_TRY(mg_scratch(c, 4, (size_t)nrhs * YCH * nc * sizeof(double2), (void**)&part));
+    hipLaunchKernelGGL(k_ydot_part, dim3(nrhs, YCH), dim3(256), 0, c->stream, (const float2*)v, Vh, nc, part);
+    hipLaunchKernelGGL(k_ydot_fin, dim3((nrhs * nc + 255) / 256), dim3(256), 0, c->stream, part, nc, nrhs,
+                       1.0 / std::sqrt((double)Vh), out);
+    HIP_TRY(hipGetLastError());
+    return MGLMA_OK;
+}
+
+// S Y and E^{-1} = (Y^+ S Y)^{-1} with the solver's S (BF16 hops); E inverted
+// on the host in FP64.  A singular E leaves the deflation off.
+static int defl_setup(mglma_ctx* c) {
+    const int nc = c->nc, Vh = c->eo_Vh;
+    const size_t ne = (size_t)Vh * nc;
+    MG_TRY(mg_malloc(c, (void**)&c->eo_SY, (size_t)nc * ne * sizeof(float2)));
+    MG_TRY(mg_malloc(c, (void**)&c->eo_Einv, (size_t)nc * nc * sizeof(double2)));
+    float2 *Y, *tmp;
+    double2* E;
+    MG_TRY(mg_scratch(c, 0, (size_t)nc * ne * sizeof(float2), (void**)&Y));
+    MG_TRY(mg_scratch(c, 1, (size_t)nc * ne * sizeof(float2), (void**)&tmp));
+    MG_TRY(mg_scratch(c, 2, (size_t)nc * nc * sizeof(double2), (void**)&E));
+    const double w = 1.0 / std::sqrt((double)Vh);
+    hipLaunchKernelGGL(k_defl_y, dim3(grid_el((size_t)nc * ne)), dim3(256), 0, c->stream, Y, Vh, nc, (float)w);
+    HIP_TRY(hipGetLastError());
+    MG_TRY(mg_eo_schur(c, Y, c->eo_SY, tmp, nc));
+    // row b of the Y^+ output: (Y^+ S y_b)_a = E[a][b]
+    MG_TRY(ydot(c, c->eo_SY, nc, E));
+    std::vector<double2> h((size_t)nc * nc);
+    HIP_TRY(hipMemcpyAsync(h.data(), E, h.size() * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    std::vector<dense::zc> A((size_t)nc * nc), Ai;
+    for (int b = 0; b < nc; ++b)
+        for (int a = 0; a < nc; ++a) A[(size_t)a * nc + b] = dense::zc(h[(size_t)b * nc + a].x, h[(size_t)b * nc + a].y);
+    if (!dense::inverse(A, nc, Ai)) return MGLMA_OK;
+    for (size_t e = 0; e < Ai.size(); ++e) h[e] = make_double2(Ai[e].real(), Ai[e].imag());
+    HIP_TRY(hipMemcpyAsync(c->eo_Einv, h.data(), h.size() * sizeof(double2), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->eo_defl = true;
+    return MGLMA_OK;
 }
 
 // Called after the Galerkin operator is built.  Leaves eo_ok false (and
@@ -396,12 +579,43 @@ int mg_eo_setup(mglma_ctx* c) {
         return MGLMA_OK;
     }
     c->eo_ok = true;
-    return MGLMA_OK;
+    return defl_setup(c);
 }
 
 static int grid_el(size_t tot) {
     size_t g = (tot + 255) / 256;
     return (int)(g > 4096 ? 4096 : (g < 1 ? 1 : g));
+}
+
+int mg_eo_defl_coef(mglma_ctx* c, const void* v, double* g, int nrhs) {
+    if (!c->eo_defl) return MGLMA_ERR_ARG;
+    const int nc = c->nc, Vh = c->eo_Vh;
+    double2* cc;
+    MG_TRY(mg_scratch(c, 3, (size_t)nrhs * nc * sizeof(double2), (void**)&cc));
+    (void)Vh;
+    MG_TRY(ydot(c, v, nrhs, cc));
+    hipLaunchKernelGGL(k_defl_solve, dim3((nrhs * nc + 255) / 256), dim3(256), 0, c->stream, c->eo_Einv, cc, nc, nrhs,
+                       (double2*)g);
+    HIP_TRY(hipGetLastError());
+    return MGLMA_OK;
+}
+
+int mg_eo_defl_sub_sy(mglma_ctx* c, const double* g, void* v, int nrhs) {
+    if (!c->eo_defl) return MGLMA_ERR_ARG;
+    const size_t ne = (size_t)c->eo_Vh * c->nc;
+    hipLaunchKernelGGL(k_defl_sub_sy, dim3(grid_el(ne)), dim3(256), 0, c->stream, c->eo_SY, (const double2*)g,
+                       (float2*)v, ne, c->nc, nrhs);
+    HIP_TRY(hipGetLastError());
+    return MGLMA_OK;
+}
+
+int mg_eo_defl_add_y(mglma_ctx* c, const double* g, double sign, void* v, int nrhs) {
+    if (!c->eo_defl) return MGLMA_ERR_ARG;
+    const size_t tot = (size_t)nrhs * c->eo_Vh * c->nc;
+    hipLaunchKernelGGL(k_defl_add_y, dim3(grid_el(tot)), dim3(256), 0, c->stream, (const double2*)g,
+                       sign / std::sqrt((double)c->eo_Vh), (float2*)v, c->eo_Vh, c->nc, nrhs);
+    HIP_TRY(hipGetLastError());
+    return MGLMA_OK;
 }
 
 // out (parity po, compressed) = [xs -] H_{po, 1-po} in

@@ -255,6 +255,10 @@ struct mglma_ctx {
     int* eo_nbr = nullptr;         // [2][Vh][8] compressed index of neighbour dir 1+d (other parity)
     float* eo_Dinv32 = nullptr;    // [V1][re/im][nc][nc] inverse self blocks, FP32 planar
     bf16_t* eo_Hbf = nullptr;      // [V1][8][2][nc][nc] D_yy^{-1} D_y,dir planar bfloat16
+    // deflation of S with the nc constant even-site vectors Y (y_a = e_a / sqrt(Vh) on every even site)
+    bool eo_defl = false;
+    float2* eo_SY = nullptr;       // [nc][Vh][nc] S y_a (the BF16 S of the solver)
+    double2* eo_Einv = nullptr;    // [nc][nc] (Y^+ S Y)^{-1}
 
     // level 2 of the nested hierarchy: blocks of b2 fine sites (multiples of b),
     // D_2 = R_1 D_1 T_1 with the aggregating R_1 (same nc, grid g2.L1, V2 = g2.V1)
@@ -344,6 +348,11 @@ int mg_eo_diag_inv(mglma_ctx* c, const void* in_full, void* out_e, void* out_o, 
 int mg_eo_scatter(mglma_ctx* c, const void* xe, const void* xo, void* x_full, int nrhs);
 // out = (1 - H_eo H_oe) x; tmp holds one odd-parity vector set
 int mg_eo_schur(mglma_ctx* c, const void* x, void* out, void* tmp, int nrhs);
+// deflation with the constant even-site vectors: g = E^{-1} Y^+ v (device, complex [nrhs][nc]);
+// v -= S Y g ; v += sign * Y g
+int mg_eo_defl_coef(mglma_ctx* c, const void* v, double* g, int nrhs);
+int mg_eo_defl_sub_sy(mglma_ctx* c, const double* g, void* v, int nrhs);
+int mg_eo_defl_add_y(mglma_ctx* c, const double* g, double sign, void* v, int nrhs);
 
 // ---------------------------------------------------------------------------
 // gamma5 gamma_k in the chiral basis: one entry per row

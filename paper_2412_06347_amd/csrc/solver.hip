@@ -18,6 +18,7 @@ enum {
     WS_CX64, WS_CR64, WS_CT64, WS_PIECE, WS_CAP, WS_COUNT
 };
 enum { WS_EO = 30 };   // odd right-hand side, odd scratch and even iterate of the even-odd coarse GCR
+enum { WS_DEFL = 31 }; // deflation coefficients of the even-odd coarse GCR
 
 // ---------------------------------------------------------------------------
 // scalar kernels (per right-hand side)
@@ -317,16 +318,39 @@ static int coarse_gcr_eo(SolveCtx& S, const void* b, void* x, int iters) {
     MG_TRY(mg_eo_diag_inv(c, b, r, to, nrhs));
     MG_TRY(mg_eo_hop(c, 0, to, r, r, nrhs));
     MG_TRY(mg_zero(c, xe, setsz * vb));
+    // deflated (coarse_eo = 2): x_e starts at Y E^{-1} Y^+ b^, the GCR runs on
+    // P_L S with P_L = 1 - S Y E^{-1} Y^+, and x_e gets - Y E^{-1} Y^+ S z at
+    // the end (z: what the GCR added), so that S x_e = b^
+    const bool defl = S.p->coarse_eo == 2 && c->eo_defl;
+    double *g0 = nullptr, *g = nullptr;
+    if (defl) {
+        MG_TRY(mg_scratch(c, WS_DEFL, (size_t)2 * nrhs * c->nc * 16, (void**)&g0));
+        g = g0 + (size_t)2 * nrhs * c->nc;
+        MG_TRY(mg_eo_defl_coef(c, r, g0, nrhs));
+        MG_TRY(mg_eo_defl_add_y(c, g0, 1.0, xe, nrhs));
+        MG_TRY(mg_eo_defl_sub_sy(c, g0, r, nrhs));
+    }
     for (int k = 0; k < iters; ++k) {
         int j = k % mc;
         char* pj = (char*)P + (size_t)j * setsz * vb;
         char* qj = (char*)Q + (size_t)j * setsz * vb;
         MG_TRY(mg_eo_schur(c, r, qj, tmp, nrhs));
+        if (defl) {
+            MG_TRY(mg_eo_defl_coef(c, qj, g, nrhs));
+            MG_TRY(mg_eo_defl_sub_sy(c, g, qj, nrhs));
+        }
         S.coarse_applies++;
         if (j > 0) MG_TRY(mg_multidot(c, MGLMA_F32, Q, setsz, j, qj, n, nrhs, S.s.cbeta(), S.s.cnw2()));
         MG_TRY(mg_orth_step(c, MGLMA_F32, Q, P, setsz, j, S.s.cbeta(), qj, pj, r, r, n, nrhs, S.s.calpha(),
                             S.s.cnw2() + (size_t)j * nrhs, nullptr));
         MG_TRY(mg_update_norm(c, MGLMA_F32, S.s.calpha(), xe, pj, r, qj, n, nrhs, nullptr));
+    }
+    if (defl) {
+        // S z = S x_e - S Y g0 ; x_e -= Y E^{-1} Y^+ S z
+        MG_TRY(mg_eo_schur(c, xe, Q, tmp, nrhs));
+        MG_TRY(mg_eo_defl_sub_sy(c, g0, Q, nrhs));
+        MG_TRY(mg_eo_defl_coef(c, Q, g, nrhs));
+        MG_TRY(mg_eo_defl_add_y(c, g, -1.0, xe, nrhs));
     }
     MG_TRY(mg_eo_hop(c, 1, xe, to, to, nrhs));
     MG_TRY(mg_eo_scatter(c, xe, to, x, nrhs));

@@ -11,6 +11,7 @@
 // The small r x r algebra (Cholesky, inverse, traces) runs on the host in
 // FP64; everything touching coarse vectors runs on the device.
 #include "mglma_internal.h"
+#include "dense_small.h"
 
 #include <cmath>
 
@@ -55,29 +56,8 @@ static int chol_inv(std::vector<zc>& G, int n, std::vector<zc>& X) {
 }
 
 // dense inverse by Gauss-Jordan with partial pivoting
-static int inverse(std::vector<zc> A, int n, std::vector<zc>& inv) {
-    inv.assign((size_t)n * n, zc(0));
-    for (int i = 0; i < n; ++i) inv[i * n + i] = 1.0;
-    for (int col = 0; col < n; ++col) {
-        int piv = col;
-        for (int r = col + 1; r < n; ++r)
-            if (std::abs(A[r * n + col]) > std::abs(A[piv * n + col])) piv = r;
-        if (std::abs(A[piv * n + col]) == 0.0) return MGLMA_ERR_RANK;
-        if (piv != col)
-            for (int k = 0; k < n; ++k) {
-                std::swap(A[col * n + k], A[piv * n + k]);
-                std::swap(inv[col * n + k], inv[piv * n + k]);
-            }
-        zc d = 1.0 / A[col * n + col];
-        for (int k = 0; k < n; ++k) { A[col * n + k] *= d; inv[col * n + k] *= d; }
-        for (int r = 0; r < n; ++r) {
-            if (r == col) continue;
-            zc f = A[r * n + col];
-            if (f == zc(0)) continue;
-            for (int k = 0; k < n; ++k) { A[r * n + k] -= f * A[col * n + k]; inv[r * n + k] -= f * inv[col * n + k]; }
-        }
-    }
-    return MGLMA_OK;
+static int inverse(const std::vector<zc>& A, int n, std::vector<zc>& inv) {
+    return dense::inverse(A, n, inv) ? MGLMA_OK : MGLMA_ERR_RANK;
 }
 
 // W[a][y][i] = modes[a % Nlm][y][i] if chirality(i) == a / Nlm else 0

@@ -108,7 +108,7 @@ class Engine:
             ctx.set_top_modes(m.contiguous())
             self.G_top = ctx.contract_top()
         self.stream.synchronize()
-        self.params = params or mglma.default_params(tol=1e-10, max_outer=10, max_inner=120, gcr_m=8,
+        self.params = params or mglma.default_params(tol=1e-10, max_outer=10, max_inner=120, gcr_m=4,
                                                      inner_tol=1e-5, nu_post=6, coarse_iters=4,
                                                      smoother=mglma.F16, inner=mglma.F32, coarse=mglma.BF16,
                                                      smoother_alg=mglma.SMOOTH_CAGCR, coarse_eo=1)

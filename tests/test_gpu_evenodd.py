@@ -125,6 +125,35 @@ def test_coarse_solve_even_odd(pair):
     assert rounds[1] <= rounds[0]
 
 
+def test_coarse_solve_deflated(pair):
+    """The even-odd coarse GCR deflated with the constant even-site vectors
+    (coarse_eo = 2) solves to 1e-11, matches the dense solution and needs no
+    more defect-correction rounds than the undeflated reduced system."""
+    import torch
+    from paper_2412_06347_amd import mglma
+    A = coarse.coarse_dense(pair.D1, pair.nbr)
+    v = synth.gaussian_coarse(3, pair.bl.V1, 2 * pair.Nv, 19)
+    ref = np.linalg.solve(A, v.reshape(3, -1).T).T.reshape(v.shape)
+    rounds = {}
+    for eo in (2, 1):
+        x = torch.empty((3, pair.bl.V1, 2 * pair.Nv, 2), dtype=torch.float64, device="cuda")
+        p = mglma.default_params(tol=1e-11, coarse=mglma.BF16, coarse_iters=8, coarse_eo=eo)
+        st = pair.ctx.coarse_solve(to_dev(v), x, p)
+        assert relerr(from_dev(x), ref) < 1e-9
+        assert max(s["true_rel_res"] for s in st) <= 1e-11
+        rounds[eo] = st[0]["outer"]
+    print("defect-correction rounds: deflated %d, even-odd %d" % (rounds[2], rounds[1]))
+    assert rounds[2] <= rounds[1]
+    # and as the coarse solve of the preconditioner
+    b = synth.gaussian_fields(2, pair.L, 24)
+    xd = pair.ctx.fine(2)
+    p = mglma.default_params(tol=1e-10, inner=mglma.F32, coarse=mglma.BF16, coarse_iters=4, coarse_eo=2)
+    pair.ctx.solve(pair.fine_dev(b), xd, p)
+    x = pair.fine_host(xd)
+    r = pair.canon(pair.D.M(pair.lat(x))) - b
+    assert (np.linalg.norm(r.reshape(2, -1), axis=1) / np.linalg.norm(b.reshape(2, -1), axis=1)).max() <= 1e-10
+
+
 def test_fine_solve_even_odd(pair):
     """The MG-preconditioned fine solve with the even-odd coarse GCR reaches
     1e-10 in the oracle's FP64 residual, in no more inner iterations than

@@ -257,6 +257,18 @@ def test_even_odd_split():
     assert np.abs(x - ref).max() < 1e-11 * np.abs(ref).max()
     # the reduced system is better conditioned than D_1 on this operator
     assert np.linalg.cond(S) < np.linalg.cond(A)
+    # deflation with the constant even-site vectors: Y orthonormal, the
+    # projector identity S P_R = P_L S, and the deflated solve reproduces S^-1 b
+    Y = coarse.eo_constant_vectors(L1, nc)
+    assert np.abs(Y.T @ Y - np.eye(nc)).max() < 1e-14
+    E = Y.T @ S @ Y
+    Ei = np.linalg.inv(E)
+    PL = np.eye(S.shape[0]) - S @ Y @ Ei @ Y.T
+    PR = np.eye(S.shape[0]) - Y @ Ei @ Y.T @ S
+    assert np.abs(S @ PR - PL @ S).max() < 1e-12
+    bh = rhs[e].reshape(-1)
+    xd = coarse.solve_eo_deflated(S, Y, bh)
+    assert np.abs(xd - np.linalg.solve(S, bh)).max() < 1e-10 * np.abs(xd).max()
 
 
 def test_inner_level():
