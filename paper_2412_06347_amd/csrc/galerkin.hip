@@ -12,10 +12,22 @@
 // TI x TJ register tile of outputs per thread.
 //
 // Pieces: 0 clover; 1..8 hops inside the block (mu = (p-1)/2, forward if p-1
-// is even); 9..16 hops through a face (mu = (p-9)/2).  Pieces 0..8 go to a
-// scratch array and are added into D_1[y][0] in a fixed order.
+// is even); 9..16 hops through a face (mu = (p-9)/2).  Only the clover and
+// the forward pieces are computed: Q = gamma5 M is Hermitian and the basis is
+// chirally split, so D_1^+ = g D_1 g with g = (gamma5)_1 (+1 on the alpha = 0
+// components, -1 on alpha = 1), and a backward hop piece is g F^+ g of the
+// forward piece F over the same links: inside the block for the self entry,
+// D_1[y][-mu] = g D_1[y - mu][+mu]^+ g across the faces (also when the
+// coarse extent is 1 or 2 and the neighbours coincide).  The clover piece and
+// the forward inside pieces go to a scratch array and are added into
+// D_1[y][0] in a fixed order.
 #include "mglma_internal.h"
 #include "wilson.h"
+
+// the computed pieces: 0, the forward inside pieces 1, 3, 5, 7 and the forward
+// face pieces 9, 11, 13, 15
+#define GAL_NPIECE 9
+__device__ __forceinline__ int gal_piece(int idx) { return idx == 0 ? 0 : 2 * idx - 1; }
 
 // Piece geometry: piece 0 is the clover term on the whole block, 1..8 the
 // hops (mu, fwd) = ((p-1)/2, (p-1)%2 == 0) between sites of the block,
@@ -156,7 +168,7 @@ __global__ __launch_bounds__(256) void k_galerkin_piece(Geo g, int Nv, const dou
                                                         double kappa, int GF, double2* __restrict__ D1,
                                                         double2* __restrict__ tmp) {
     extern __shared__ double2 sh[];
-    const int y = blockIdx.x, piece = blockIdx.y;
+    const int y = blockIdx.x, piece = gal_piece(blockIdx.y);
     const int nc = 2 * Nv;
     const int i0 = blockIdx.z * 64;                    // rows [i0, i0 + 64)
     double2* Lh = sh;                                  // [GF][6][nc]
@@ -223,7 +235,7 @@ void k_galerkin_mfma3(Geo g, int Nv, const double2* __restrict__ B, const double
                       double2* __restrict__ tmp) {
     typedef Mfma<double>::v4 V4;
     extern __shared__ double2 sh[];
-    const int y = blockIdx.x, piece = blockIdx.y;
+    const int y = blockIdx.x, piece = gal_piece(blockIdx.y);
     const int nc = 2 * Nv, ncp = 16 * NTR;
     double2* Lh = sh;                                  // [GF][6][ncp]
     double2* Rh = sh + (size_t)GF * 6 * ncp;           // [GF][6][ncp]
@@ -274,18 +286,41 @@ void k_galerkin_mfma3(Geo g, int Nv, const double2* __restrict__ B, const double
     }
 }
 
-// D1[y][0] = sum of pieces 0..8 in order
+// D1[y][0] = clover + sum_mu (F_mu + g F_mu^+ g), F_mu the forward inside
+// piece (scratch slot 1 + 2 mu), in a fixed order
 __global__ void k_galerkin_self(size_t V1, int nc, const double2* __restrict__ tmp, double2* __restrict__ D1) {
     const size_t nn2 = (size_t)nc * nc, n = V1 * nn2;
+    const int Nv = nc / 2;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
         const size_t y = e / nn2, ij = e - y * nn2;
-        double re = 0.0, im = 0.0;
-        for (int p = 0; p < 9; ++p) {
-            double2 v = tmp[(y * 9 + p) * nn2 + ij];
-            re += v.x;
-            im += v.y;
+        const int i = (int)(ij / nc), j = (int)(ij - (size_t)i * nc);
+        const double sg = ((i < Nv) == (j < Nv)) ? 1.0 : -1.0;
+        double2 v = tmp[(y * 9) * nn2 + ij];
+        double re = v.x, im = v.y;
+        for (int mu = 0; mu < 4; ++mu) {
+            const double2* F = tmp + (y * 9 + 1 + 2 * mu) * nn2;
+            const double2 f = F[ij], ft = F[(size_t)j * nc + i];
+            re += f.x + sg * ft.x;
+            im += f.y - sg * ft.y;
         }
         D1[y * 9 * nn2 + ij] = make_double2(re, im);
+    }
+}
+
+// D1[y][2 + 2 mu] = g D1[y - mu][1 + 2 mu]^+ g
+__global__ void k_galerkin_bwd_faces(Geo g, int nc, double2* __restrict__ D1) {
+    const size_t nn2 = (size_t)nc * nc, n = (size_t)g.V1 * 4 * nn2;
+    const int Nv = nc / 2;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        const size_t t = e / nn2, ij = e - t * nn2;
+        const int y = (int)(t / 4), mu = (int)(t % 4);
+        const int i = (int)(ij / nc), j = (int)(ij - (size_t)i * nc);
+        const int stride = g.sk[mu];
+        const int cmu = (y / stride) % g.L1[mu];
+        const int z = y + ((cmu == 0 ? g.L1[mu] - 1 : cmu - 1) - cmu) * stride;
+        const double2 f = D1[((size_t)z * 9 + 1 + 2 * mu) * nn2 + (size_t)j * nc + i];
+        const double sg = ((i < Nv) == (j < Nv)) ? 1.0 : -1.0;
+        D1[((size_t)y * 9 + 2 + 2 * mu) * nn2 + ij] = make_double2(sg * f.x, -sg * f.y);
     }
 }
 
@@ -304,7 +339,7 @@ int mg_galerkin(mglma_ctx* c, double2* tmp) {
         if (GF > gmax) GF = gmax;
         if (GF < 2) GF = 2;
         const size_t shb = (size_t)2 * GF * 6 * ncp * sizeof(double2);
-        dim3 grid(g.V1, 17);
+        dim3 grid(g.V1, GAL_NPIECE);
 #define GALM_LAUNCH(NTR)                                                                                        \
     hipLaunchKernelGGL((k_galerkin_mfma3<NTR>), grid, dim3(64 * NTR), shb, c->stream, g, c->Nv, c->B64, c->U64, \
                        c->C64, c->kappa, GF, c->D64, tmp)
@@ -321,7 +356,7 @@ int mg_galerkin(mglma_ctx* c, double2* tmp) {
         if (GF < 1) GF = 1;
         if (GF > 16) GF = 16;
         const size_t shb = (size_t)2 * GF * 6 * nc * sizeof(double2);
-        dim3 grid(g.V1, 17, (nc + 63) / 64);
+        dim3 grid(g.V1, GAL_NPIECE, (nc + 63) / 64);
         // register tile: ceil(nc/16) x ceil(nc/16) outputs per thread (rows capped at 4 per 64-row chunk)
         const int t = (nc + 15) / 16;
 #define GAL_LAUNCH(TI, TJ)                                                                                  \
@@ -333,6 +368,7 @@ int mg_galerkin(mglma_ctx* c, double2* tmp) {
         HIP_TRY(hipGetLastError());
     }
     hipLaunchKernelGGL(k_galerkin_self, dim3(2048), dim3(256), 0, c->stream, (size_t)g.V1, nc, tmp, c->D64);
+    hipLaunchKernelGGL(k_galerkin_bwd_faces, dim3(2048), dim3(256), 0, c->stream, g, nc, c->D64);
     HIP_TRY(hipGetLastError());
     return MGLMA_OK;
 }

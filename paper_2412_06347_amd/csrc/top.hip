@@ -74,22 +74,27 @@ __global__ void k_split_modes(int Nlm, int V1, int nc, const double2* __restrict
 }
 
 // Gamma2 partial: A[x0][k][a][b] = sum_{y in row(x0)} W0_y^+ (Gb_y(t) W1_y)  (W0/W1: alpha=0/1 rows).
-// grid (L0, 3), block 256.  For every coarse site of the time row the product
-// T = Gb W1 (Nv x 32 column tile) is staged in LDS, then each thread adds
-// W0^+ T into the outputs it owns.  Needs Nv <= 64 and r <= 128.
+// grid (L0, 3, TSPLIT), block 256: workgroup z takes the z-th of TSPLIT
+// consecutive ranges of the coarse sites of the time row and writes its own
+// partial sum (added in z order by k_sum_parts).  For every coarse site the
+// product T = Gb W1 (Nv x 32 column tile) is staged in LDS, then each thread
+// adds W0^+ T into the outputs it owns.  Needs Nv <= 64 and r <= 128.
 #define TBW 32
+#define TSPLIT 16
 __global__ __launch_bounds__(256) void k_top_gamma(Geo g, int Nv, int r, const double2* __restrict__ W,
                                                    const double2* __restrict__ G1, double2* __restrict__ A) {
-    const int x0 = blockIdx.x, k = blockIdx.y;
+    const int x0 = blockIdx.x, k = blockIdx.y, z = blockIdx.z;
     const int b0 = g.b[0], y0 = x0 / b0, t = x0 % b0;
     const int nc = 2 * Nv, rowsz = g.V1 / g.L1[0];
+    const int ys0 = (int)((long)rowsz * z / TSPLIT), ys1 = (int)((long)rowsz * (z + 1) / TSPLIT);
     const size_t V1 = g.V1;
+    A += (size_t)z * g.L[0] * 3 * r * r;
     __shared__ double2 T[64 * TBW];
     for (int bt = 0; bt < r; bt += TBW) {
         const int nb = r - bt < TBW ? r - bt : TBW;
         cx<double> acc[16];
         for (int q = 0; q < 16; ++q) acc[q] = cmk(0.0, 0.0);
-        for (int ys = 0; ys < rowsz; ++ys) {
+        for (int ys = ys0; ys < ys1; ++ys) {
             const int y = y0 * rowsz + ys;
             const double2* Gb = G1 + (((size_t)y * b0 + t) * 3 + k) * Nv * Nv;
             __syncthreads();
@@ -119,6 +124,19 @@ __global__ __launch_bounds__(256) void k_top_gamma(Geo g, int Nv, int r, const d
             const int a = o / nb, bb = o % nb;
             A[(((size_t)x0 * 3 + k) * r + a) * r + bt + bb] = make_double2(acc[q].re, acc[q].im);
         }
+    }
+}
+
+// out[e] = sum_z part[z][e], z in order
+__global__ void k_sum_parts(const double2* __restrict__ part, int nz, size_t ne, double2* __restrict__ out) {
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < ne; e += (size_t)gridDim.x * blockDim.x) {
+        double sr = 0.0, si = 0.0;
+        for (int z = 0; z < nz; ++z) {
+            const double2 v = part[(size_t)z * ne + e];
+            sr += v.x;
+            si += v.y;
+        }
+        out[e] = make_double2(sr, si);
     }
 }
 
@@ -192,9 +210,13 @@ extern "C" int mglma_set_top_modes(mglma_ctx* c, int Nlm, const double* modes) {
             for (int b = 0; b < r; ++b) Q2[a * r + b] = -Q2[a * r + b];
     MG_TRY(inverse(Q2, r, c->Q2inv));
     // Gamma2[x0][k] = A - A^+ with A = W0^+ Gb W1
-    double2* Ad;
-    MG_TRY(mg_scratch(c, 0, (size_t)g.L[0] * 3 * r * r * 16, (void**)&Ad));
-    hipLaunchKernelGGL(k_top_gamma, dim3(g.L[0], 3), dim3(256), 0, c->stream, g, c->Nv, r, c->W, c->G1, Ad);
+    double2 *Ad, *Ap;
+    const size_t na = (size_t)g.L[0] * 3 * r * r;
+    MG_TRY(mg_scratch(c, 0, na * 16, (void**)&Ad));
+    MG_TRY(mg_scratch(c, 6, (size_t)TSPLIT * na * 16, (void**)&Ap));
+    hipLaunchKernelGGL(k_top_gamma, dim3(g.L[0], 3, TSPLIT), dim3(256), 0, c->stream, g, c->Nv, r, c->W, c->G1, Ap);
+    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((na + 255) / 256 < 4096 ? (na + 255) / 256 : 4096)), dim3(256), 0,
+                       c->stream, Ap, TSPLIT, na, Ad);
     HIP_TRY(hipGetLastError());
     std::vector<double> hA((size_t)g.L[0] * 3 * r * r * 2);
     HIP_TRY(hipMemcpyAsync(hA.data(), Ad, hA.size() * 8, hipMemcpyDeviceToHost, c->stream));
