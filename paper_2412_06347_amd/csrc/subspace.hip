@@ -350,22 +350,36 @@ __global__ __launch_bounds__(256) void k_prolong(Geo g, int Nv, const S* __restr
         }
         __syncthreads();
         if (i < g.V) {
+            // three spin-colour planes per pass: each coarse value read from LDS
+            // serves three basis entries
             const cx<R>* cy = CS + (size_t)(y - yfirst) * nc * rc;
             for (int a = 0; a < 2; ++a) {
-                for (int scl = 0; scl < 6; ++scl) {
-                    cx<R> acc[RMAXR];
+                for (int s0 = 0; s0 < 6; s0 += 3) {
+                    cx<R> acc[3][RMAXR];
 #pragma unroll
-                    for (int q = 0; q < RMAXR; ++q) acc[q] = cmk((R)0, (R)0);
+                    for (int u = 0; u < 3; ++u)
+#pragma unroll
+                        for (int q = 0; q < RMAXR; ++q) acc[u][q] = cmk((R)0, (R)0);
                     for (int c = 0; c < Nv; ++c) {
-                        const cx<R> b = ldc<S, R>(B + (((size_t)y * nc + a * Nv + c) * 6 + scl) * Vb + l);
+                        const S* bp = B + (((size_t)y * nc + a * Nv + c) * 6 + s0) * Vb + l;
+                        cx<R> b[3];
+#pragma unroll
+                        for (int u = 0; u < 3; ++u) b[u] = ldc<S, R>(bp + (size_t)u * Vb);
                         const cx<R>* cv = cy + (a * Nv + c) * rc;
 #pragma unroll
                         for (int q = 0; q < RMAXR; ++q)
-                            if (q < nr) cmac(acc[q], b, cv[q]);
+                            if (q < nr) {
+                                const cx<R> x = cv[q];
+#pragma unroll
+                                for (int u = 0; u < 3; ++u) cmac(acc[u][q], b[u], x);
+                            }
                     }
 #pragma unroll
-                    for (int q = 0; q < RMAXR; ++q)
-                        if (q < nr) stc<S, R>(fine + ((size_t)(r0 + q) * 12 + 6 * a + scl) * V + i, acc[q]);
+                    for (int u = 0; u < 3; ++u)
+#pragma unroll
+                        for (int q = 0; q < RMAXR; ++q)
+                            if (q < nr)
+                                stc<S, R>(fine + ((size_t)(r0 + q) * 12 + 6 * a + s0 + u) * V + i, acc[u][q]);
                 }
             }
         }
