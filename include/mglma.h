@@ -83,7 +83,9 @@ typedef struct {
                             (0: no coarse correction, smoother only)        */
     int    smoother;     /* precision of the smoother Dslash (mglma_prec)      */
     int    inner;        /* precision of the inner Krylov vectors (F32 or F64) */
-    int    coarse;       /* precision of the preconditioner's coarse operator  */
+    int    coarse;       /* precision of the preconditioner's coarse operator;
+                            with BF16 (and FP32 inner vectors) the restrictor
+                            and prolongator read an FP16 copy of the basis */
     int    use_mg;       /* 1: MG preconditioner, 0: unpreconditioned GCR      */
     int    smoother_alg; /* MGLMA_SMOOTH_MR: nu_post minimal-residual steps;
                             MGLMA_SMOOTH_CAGCR: one GCR step over the Krylov
@@ -171,7 +173,9 @@ int mglma_export_coarse_op(mglma_ctx* ctx, double* out_dev);
  * vectors, columns = alpha 1 basis vectors (the alpha 1 x alpha 0 block is
  * minus its adjoint, the diagonal blocks vanish).  For tests.              */
 int mglma_export_coarse_gammas(mglma_ctx* ctx, double* out_dev);
-/* coarse = R fine (eq:res_mg), fine = T coarse (eq:pro_mg); F64 or F32.     */
+/* coarse = R fine (eq:res_mg), fine = T coarse (eq:pro_mg); F64 or F32, or
+ * F16: FP32 fields with the FP16 copy of the basis (what the preconditioner
+ * uses with the BF16 coarse operator).                                     */
 int mglma_restrict(mglma_ctx* ctx, int prec, const void* fine_dev, void* coarse_dev, int nrhs);
 int mglma_prolong(mglma_ctx* ctx, int prec, const void* coarse_dev, void* fine_dev, int nrhs);
 /* out = D_1 in (gamma5 = 0) or Q_1 in (gamma5 = 1).  prec F64, F32 (FP32

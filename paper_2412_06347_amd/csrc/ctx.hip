@@ -173,6 +173,7 @@ void mg_free_subspace(mglma_ctx* c) {
     size_t nb = (size_t)g.V * 12 * c->Nv;
     mg_free(c, c->B64, nb * 16); c->B64 = nullptr;
     mg_free(c, c->B32, nb * 8); c->B32 = nullptr;
+    mg_free(c, c->B16, nb * 4); c->B16 = nullptr;
     size_t nd = (size_t)g.V1 * 9 * c->nc * c->nc;
     mg_free(c, c->D64, nd * 16); c->D64 = nullptr;
     mg_free(c, c->D64p, nd * 16); c->D64p = nullptr;

@@ -193,6 +193,18 @@ __device__ __forceinline__ void ld4c(const float2* p, float (&re)[4], float (&im
     re[0] = q0.x; im[0] = q0.y; re[1] = q0.z; im[1] = q0.w;
     re[2] = q1.x; im[2] = q1.y; re[3] = q1.z; im[3] = q1.w;
 }
+__device__ __forceinline__ void ld4c(const __half2* p, float (&re)[4], float (&im)[4]) {
+    const uint4 q = *(const uint4*)p;
+    const uint32_t u[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        __half2 h;
+        __builtin_memcpy(&h, &u[s], 4);
+        const float2 f = __half22float2(h);
+        re[s] = f.x;
+        im[s] = f.y;
+    }
+}
 __device__ __forceinline__ void ld4c(const double2* p, double (&re)[4], double (&im)[4]) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -243,6 +255,7 @@ struct mglma_ctx {
     // subspace: basis [V1][2][Nv][6][Vb], coarse operator [V1][9][nc][nc]
     int Nv = 0, nc = 0;
     double2* B64 = nullptr; float2* B32 = nullptr;
+    __half2* B16 = nullptr;      // FP16 copy for the transfers of the BF16-coarse preconditioner
     double2* D64 = nullptr; double* D64p = nullptr; float* D32p = nullptr;   // planar [blk][re/im][i][j] copies
     bf16_t* Dbf = nullptr;       // [V1][9][2][nc][nc] planar re/im bfloat16
     double2* G1 = nullptr;       // coarse gammas [V1][b0][3][Nv][Nv] (alpha=0 rows, alpha=1 cols)

@@ -375,9 +375,11 @@ static int precondition(SolveCtx& S, int vp, const void* r, void* z) {
     MG_TRY(mg_scratch(c, WS_EC, (size_t)nrhs * nc * vb, &ec));
     // coarse correction (coarse_iters = 0: smoother only)
     if (p->coarse_iters > 0) {
-        MG_TRY(mg_restrict(c, vp, r, rc, nrhs));
+        // with the BF16 coarse operator the transfers read the FP16 copy of the basis
+        const int tp = (vp == MGLMA_F32 && p->coarse == MGLMA_BF16) ? MGLMA_F16 : vp;
+        MG_TRY(mg_restrict(c, tp, r, rc, nrhs));
         MG_TRY(coarse_gcr_fixed(S, vp, p->coarse, rc, ec, p->coarse_iters));
-        MG_TRY(mg_prolong(c, vp, ec, z, nrhs));
+        MG_TRY(mg_prolong(c, tp, ec, z, nrhs));
     } else {
         MG_TRY(mg_zero(c, z, (size_t)nrhs * n * vb));
     }

@@ -238,8 +238,8 @@ __global__ __launch_bounds__(256) void k_restrict(Geo g, int Nv, const S* __rest
 // four basis entries and its four field entries are contiguous (needs
 // Vb % 4 == 0 and 16-byte aligned fields, checked by the launcher).
 #define RMT 4
-template <typename R>
-__global__ __launch_bounds__(256) void k_restrict_mfma(Geo g, int Nv, const typename VT<R>::c2* __restrict__ B,
+template <typename R, typename BS = typename VT<R>::c2>
+__global__ __launch_bounds__(256) void k_restrict_mfma(Geo g, int Nv, const BS* __restrict__ B,
                                                        const typename VT<R>::c2* __restrict__ fine,
                                                        typename VT<R>::c2* __restrict__ coarse, int nrhs) {
     typedef typename VT<R>::c2 C2;
@@ -260,7 +260,7 @@ __global__ __launch_bounds__(256) void k_restrict_mfma(Geo g, int Nv, const type
         cr[t] = V4{0, 0, 0, 0};
         ci[t] = V4{0, 0, 0, 0};
     }
-    const C2* Bya = B + (size_t)(y * 2 + a) * Nv * K;
+    const BS* Bya = B + (size_t)(y * 2 + a) * Nv * K;
     const C2* F = fine + ((size_t)(nok ? n : 0) * 12 + 6 * a) * V + (size_t)y * Vb;
     const int nchunk = (K + 15) / 16;
     for (int q = w; q < nchunk; q += 4) {
@@ -329,8 +329,8 @@ __global__ __launch_bounds__(256) void k_restrict_mfma(Geo g, int Nv, const type
 // fine[r][6a + s'col][i] = sum_c B[y][a][c][s'col][l] coarse[r][y][a*Nv + c]
 // One thread per fine site; the coarse vectors of the workgroup's blocks are
 // staged in LDS (RMAXR right-hand sides per pass).
-template <typename S, typename R>
-__global__ __launch_bounds__(256) void k_prolong(Geo g, int Nv, const S* __restrict__ B, const S* __restrict__ coarse,
+template <typename S, typename R, typename BS = S>
+__global__ __launch_bounds__(256) void k_prolong(Geo g, int Nv, const BS* __restrict__ B, const S* __restrict__ coarse,
                                                  S* __restrict__ fine, int nrhs, int nbw, int rc) {
     extern __shared__ char shraw[];
     cx<R>* CS = (cx<R>*)shraw;    // [nbw][nc][rc], rc <= RMAXR right-hand sides per pass
@@ -361,10 +361,10 @@ __global__ __launch_bounds__(256) void k_prolong(Geo g, int Nv, const S* __restr
 #pragma unroll
                         for (int q = 0; q < RMAXR; ++q) acc[u][q] = cmk((R)0, (R)0);
                     for (int c = 0; c < Nv; ++c) {
-                        const S* bp = B + (((size_t)y * nc + a * Nv + c) * 6 + s0) * Vb + l;
+                        const BS* bp = B + (((size_t)y * nc + a * Nv + c) * 6 + s0) * Vb + l;
                         cx<R> b[3];
 #pragma unroll
-                        for (int u = 0; u < 3; ++u) b[u] = ldc<S, R>(bp + (size_t)u * Vb);
+                        for (int u = 0; u < 3; ++u) b[u] = ldc<BS, R>(bp + (size_t)u * Vb);
                         const cx<R>* cv = cy + (a * Nv + c) * rc;
 #pragma unroll
                         for (int q = 0; q < RMAXR; ++q)
@@ -390,6 +390,18 @@ int mg_restrict(mglma_ctx* c, int prec, const void* fine, void* coarse, int nrhs
     if (nrhs <= 0) return MGLMA_OK;
     const Geo& g = c->geo;
     const int nc = c->nc;
+    if (prec == MGLMA_F16) {
+        // FP32 fields, FP16 basis (matrix-core restrictor), else the FP32 basis
+        if (g.Vb % 4 == 0 && c->Nv <= 16 * RMT && (uintptr_t)fine % 16 == 0) {
+            dim3 grid(g.V1, 2, (nrhs + 15) / 16);
+            const size_t shb = (size_t)4 * ((c->Nv + 15) / 16) * 2 * 256 * 4;
+            hipLaunchKernelGGL((k_restrict_mfma<float, __half2>), grid, dim3(256), shb, c->stream, g, c->Nv, c->B16,
+                               (const float2*)fine, (float2*)coarse, nrhs);
+            HIP_TRY(hipGetLastError());
+            return MGLMA_OK;
+        }
+        prec = MGLMA_F32;
+    }
     if (prec != MGLMA_F64 && prec != MGLMA_F32) return MGLMA_ERR_ARG;
     const size_t cb = prec == MGLMA_F64 ? 16 : 8;
     if (g.Vb % 4 == 0 && c->Nv <= 16 * RMT && (uintptr_t)fine % 16 == 0) {
@@ -441,6 +453,10 @@ int mg_prolong(mglma_ctx* c, int prec, const void* coarse, void* fine, int nrhs)
             break;
         case MGLMA_F32:
             hipLaunchKernelGGL((k_prolong<float2, float>), grid, dim3(256), shb, c->stream, g, c->Nv, c->B32,
+                               (const float2*)coarse, (float2*)fine, nrhs, nbw, rc);
+            break;
+        case MGLMA_F16:   // FP32 fields, FP16 basis
+            hipLaunchKernelGGL((k_prolong<float2, float, __half2>), grid, dim3(256), shb, c->stream, g, c->Nv, c->B16,
                                (const float2*)coarse, (float2*)fine, nrhs, nbw, rc);
             break;
         default: return MGLMA_ERR_ARG;
@@ -647,6 +663,7 @@ extern "C" int mglma_build_subspace(mglma_ctx* c, int Nv, const double* tv) {
     size_t nd = (size_t)g.V1 * 9 * nc * nc;
     MG_TRY(mg_malloc(c, (void**)&c->B64, nb * 16));
     MG_TRY(mg_malloc(c, (void**)&c->B32, nb * 8));
+    MG_TRY(mg_malloc(c, (void**)&c->B16, nb * 4));
     MG_TRY(mg_malloc(c, (void**)&c->D64, nd * 16));
     MG_TRY(mg_malloc(c, (void**)&c->D64p, nd * 16));
     MG_TRY(mg_malloc(c, (void**)&c->D32p, nd * 8));
@@ -672,6 +689,7 @@ extern "C" int mglma_build_subspace(mglma_ctx* c, int Nv, const double* tv) {
     if (hbad) { mg_free_subspace(c); return MGLMA_ERR_RANK; }
     MG_TRY(cholqr_pass(c, Gb, Rb, bad));
     MG_TRY(mg_convert(c, MGLMA_F64, c->B64, MGLMA_F32, c->B32, nb, 1, nullptr, 0));
+    MG_TRY(mg_convert(c, MGLMA_F64, c->B64, MGLMA_F16, c->B16, nb, 1, nullptr, 0));
 
     // 3. Galerkin operator, block by block (the column-major FP64 copy is the scratch of the pieces)
     MG_TRY(mg_galerkin(c, (double2*)c->D64p));
