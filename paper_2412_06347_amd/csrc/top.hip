@@ -80,7 +80,7 @@ __global__ void k_split_modes(int Nlm, int V1, int nc, const double2* __restrict
 // product T = Gb W1 (Nv x 32 column tile) is staged in LDS, then each thread
 // adds W0^+ T into the outputs it owns.  Needs Nv <= 64 and r <= 128.
 #define TBW 32
-#define TSPLIT 16
+#define TSPLIT 48
 __global__ __launch_bounds__(256) void k_top_gamma(Geo g, int Nv, int r, const double2* __restrict__ W,
                                                    const double2* __restrict__ G1, double2* __restrict__ A) {
     const int x0 = blockIdx.x, k = blockIdx.y, z = blockIdx.z;
