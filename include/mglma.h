@@ -120,6 +120,7 @@ typedef struct {
  * a hipStream_t (NULL = default stream).  Errors: ARG, SHAPE, OOM, HIP.   */
 int  mglma_create(mglma_ctx** ctx, const mglma_lattice* lat, void* stream);
 void mglma_destroy(mglma_ctx* ctx);
+/* Switch the context's stream (synchronises the previous one first).      */
 int  mglma_set_stream(mglma_ctx* ctx, void* stream);
 const char* mglma_strerror(int code);
 /* Sizes: 0 V, 1 V1, 2 Vb, 3 Nv, 4 nc, 5 Nlm, 6 r = 2 Nlm, 7 spatial volume;
@@ -127,7 +128,9 @@ const char* mglma_strerror(int code);
  * even, nc <= 64, non-singular self blocks), else 0; 9: V2, the number of
  * level-2 blocks (0 before mglma_build_level2).                            */
 long mglma_query(const mglma_ctx* ctx, int what);
-/* Device bytes held by the context (gauge, clover, basis, coarse op, ...). */
+/* Device bytes held by the context (gauge, clover, basis, coarse op, ...),
+ * not counting freed blocks the context keeps for reuse (at most 16 GiB;
+ * rebuilding the subspace reuses them instead of calling hipMalloc).      */
 size_t mglma_resident_bytes(const mglma_ctx* ctx);
 /* Bytes of one fine / coarse field of `prec` (times nrhs).                  */
 size_t mglma_fine_bytes(const mglma_ctx* ctx, int prec, int nrhs);

@@ -51,23 +51,58 @@ Geo make_geo(const int L[4], const int b[4], const double bc[4]) {
 // ---------------------------------------------------------------------------
 // memory helpers
 // ---------------------------------------------------------------------------
+// at most this many bytes of freed blocks are kept for reuse
+static const size_t CACHE_MAX = (size_t)16 << 30;
+
+static void cache_release(mglma_ctx* c) {
+    for (auto& b : c->cache) (void)hipFree(b.first);
+    c->cache.clear();
+    c->cache_bytes = 0;
+}
+
 int mg_malloc(mglma_ctx* c, void** p, size_t bytes) {
     *p = nullptr;
     if (bytes == 0) return MGLMA_OK;
+    for (size_t k = 0; k < c->cache.size(); ++k)
+        if (c->cache[k].second == bytes) {
+            *p = c->cache[k].first;
+            c->cache.erase(c->cache.begin() + k);
+            c->cache_bytes -= bytes;
+            c->alloc_size[*p] = bytes;
+            c->resident += bytes;
+            return MGLMA_OK;
+        }
     hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess && !c->cache.empty()) {
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(c->stream);
+        cache_release(c);
+        e = hipMalloc(p, bytes);
+    }
     if (e != hipSuccess) {
         (void)hipGetLastError();
         *p = nullptr;
         return MGLMA_ERR_OOM;
     }
+    c->alloc_size[*p] = bytes;
     c->resident += bytes;
     return MGLMA_OK;
 }
 
-void mg_free(mglma_ctx* c, void* p, size_t bytes) {
-    if (p) {
+// The size recorded at allocation is what is released (the argument is
+// ignored); the block goes to the reuse list while it has room.
+void mg_free(mglma_ctx* c, void* p, size_t) {
+    if (!p) return;
+    auto it = c->alloc_size.find(p);
+    if (it == c->alloc_size.end()) return;
+    const size_t bytes = it->second;
+    c->alloc_size.erase(it);
+    c->resident -= bytes;
+    if (c->cache_bytes + bytes <= CACHE_MAX) {
+        c->cache.emplace_back(p, bytes);
+        c->cache_bytes += bytes;
+    } else {
         (void)hipFree(p);
-        c->resident -= bytes;
     }
 }
 
@@ -202,12 +237,16 @@ extern "C" void mglma_destroy(mglma_ctx* c) {
     free_gauge(c);
     for (int i = 0; i < 32; ++i) mg_free(c, c->scr[i].ptr, c->scr[i].bytes);
     mg_free(c, c->red_part, c->red_part_n * sizeof(double));
+    cache_release(c);
+    for (auto& b : c->alloc_size) (void)hipFree(b.first);   // anything not released above
     if (c->hbuf) (void)hipHostFree(c->hbuf);
     delete c;
 }
 
 extern "C" int mglma_set_stream(mglma_ctx* c, void* stream) {
     if (!c) return MGLMA_ERR_ARG;
+    // blocks on the reuse list may still be read by work queued on the old stream
+    if ((hipStream_t)stream != c->stream) HIP_TRY(hipStreamSynchronize(c->stream));
     c->stream = (hipStream_t)stream;
     return MGLMA_OK;
 }

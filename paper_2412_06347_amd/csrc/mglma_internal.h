@@ -9,6 +9,8 @@
 #include <complex>
 #include <vector>
 #include <string>
+#include <unordered_map>
+#include <utility>
 
 #include "../../include/mglma.h"
 
@@ -294,6 +296,13 @@ struct mglma_ctx {
     double* hbuf = nullptr; size_t hbuf_n = 0;     // pinned host staging
 
     size_t resident = 0;
+
+    // freed device blocks kept for reuse (same size), so that rebuilding the
+    // subspace every step does not call hipFree / hipMalloc; all work is on
+    // one stream, so a reused block is only touched after the work that used it
+    std::unordered_map<void*, size_t> alloc_size;
+    std::vector<std::pair<void*, size_t>> cache;
+    size_t cache_bytes = 0;
 };
 
 // scratch slot i of at least `bytes` bytes (contents undefined)
