@@ -1091,3 +1091,79 @@ int mg_ca_update(mglma_ctx* c, int pprec, const void* P, size_t pstride, int k, 
     HIP_TRY(hipGetLastError());
     return MGLMA_OK;
 }
+
+
+// ---------------------------------------------------------------------------
+// Gram matrix of two FP64 vector blocks: out[j][i] = <X_i, Y_j> (complex, the
+// layout of mg_multidot's output for j = 0..ky-1), kx, ky <= 64.  Pass 1:
+// GS workgroups each take a range of entries, stage 16 entries of every
+// vector in LDS at a time and accumulate the kx * ky products (up to 16 per
+// thread); pass 2 adds the GS partials in order.
+// ---------------------------------------------------------------------------
+#define GRAM_GS 128
+#define GRAM_KT 16
+__global__ __launch_bounds__(256) void k_gram64_part(const double2* __restrict__ X, int kx, const double2* __restrict__ Y,
+                                                     int ky, size_t n, double2* __restrict__ part) {
+    __shared__ double2 xs[64 * GRAM_KT], ys[64 * GRAM_KT];
+    const int gs = blockIdx.x, t = threadIdx.x;
+    const size_t k0 = n * gs / GRAM_GS, k1 = n * (gs + 1) / GRAM_GS;
+    const int nout = kx * ky;
+    double ar[16], ai[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) ar[q] = ai[q] = 0.0;
+    for (size_t kb = k0; kb < k1; kb += GRAM_KT) {
+        const int kn = (int)(k1 - kb < GRAM_KT ? k1 - kb : GRAM_KT);
+        __syncthreads();
+        for (int e = t; e < kx * GRAM_KT; e += blockDim.x) {
+            const int i = e / GRAM_KT, kk = e - i * GRAM_KT;
+            xs[e] = kk < kn ? X[(size_t)i * n + kb + kk] : make_double2(0.0, 0.0);
+        }
+        for (int e = t; e < ky * GRAM_KT; e += blockDim.x) {
+            const int j = e / GRAM_KT, kk = e - j * GRAM_KT;
+            ys[e] = kk < kn ? Y[(size_t)j * n + kb + kk] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int o = t + 256 * q;
+            if (o < nout) {
+                const int i = o % kx, j = o / kx;
+                const double2* xp = xs + i * GRAM_KT;
+                const double2* yp = ys + j * GRAM_KT;
+                for (int kk = 0; kk < GRAM_KT; ++kk) {
+                    const double2 a = xp[kk], b = yp[kk];
+                    ar[q] = fma(a.x, b.x, fma(a.y, b.y, ar[q]));
+                    ai[q] = fma(a.x, b.y, fma(-a.y, b.x, ai[q]));
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int o = t + 256 * q;
+        if (o < nout) part[(size_t)gs * nout + o] = make_double2(ar[q], ai[q]);
+    }
+}
+
+__global__ void k_gram64_sum(const double2* __restrict__ part, int nout, double2* __restrict__ out) {
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= nout) return;
+    double sr = 0.0, si = 0.0;
+    for (int gs = 0; gs < GRAM_GS; ++gs) {
+        const double2 v = part[(size_t)gs * nout + o];
+        sr += v.x;
+        si += v.y;
+    }
+    out[o] = make_double2(sr, si);
+}
+
+int mg_gram64(mglma_ctx* c, const void* X, int kx, const void* Y, int ky, size_t n, double* out_dev) {
+    if (kx < 1 || ky < 1 || kx > 64 || ky > 64) return MGLMA_ERR_ARG;
+    MG_TRY(ensure_red(c, (size_t)GRAM_GS * kx * ky * 2));
+    hipLaunchKernelGGL(k_gram64_part, dim3(GRAM_GS), dim3(256), 0, c->stream, (const double2*)X, kx,
+                       (const double2*)Y, ky, n, (double2*)c->red_part);
+    hipLaunchKernelGGL(k_gram64_sum, dim3((kx * ky + 255) / 256), dim3(256), 0, c->stream,
+                       (const double2*)c->red_part, kx * ky, (double2*)out_dev);
+    HIP_TRY(hipGetLastError());
+    return MGLMA_OK;
+}

@@ -88,6 +88,15 @@ __global__ __launch_bounds__(256) void k_block_combine(double2* __restrict__ Z, 
     }
 }
 
+int mg_block_combine(mglma_ctx* c, double2* Z, const double2* X, const double2* M_dev, size_t n, int nb) {
+    size_t g = (n + 255) / 256;
+    g = g > 4096 ? 4096 : (g < 1 ? 1 : g);
+    hipLaunchKernelGGL(k_block_combine, dim3((unsigned)g), dim3(256), (size_t)nb * nb * sizeof(double2), c->stream, Z,
+                       X, M_dev, n, nb);
+    HIP_TRY(hipGetLastError());
+    return MGLMA_OK;
+}
+
 namespace {
 
 struct Eig {
@@ -110,8 +119,7 @@ struct Eig {
     }
     // host G[i][j] = <X_i, Y_j> for i < kx, j < ky
     int gram(const double2* X, int kx, const double2* Y, int ky, std::vector<zc>& Gh) {
-        for (int j = 0; j < ky; ++j)
-            MG_TRY(mg_multidot(c, MGLMA_F64, X, n, kx, Y + (size_t)j * n, n, 1, (double*)(G + (size_t)j * kx)));
+        MG_TRY(mg_gram64(c, X, kx, Y, ky, n, (double*)G));
         std::vector<double2> tmp((size_t)kx * ky);
         HIP_TRY(hipMemcpyAsync(tmp.data(), G, tmp.size() * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(hipStreamSynchronize(c->stream));

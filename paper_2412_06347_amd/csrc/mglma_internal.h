@@ -390,6 +390,10 @@ __host__ __device__ inline void gk_row(int k, int s, int* t, double* cre, double
     *cim = im[k - 1][s];
 }
 
+// out[j][i] = <X_i, Y_j> for FP64 vector blocks (kx, ky <= 64), complex, one launch + finish
+int mg_gram64(mglma_ctx* c, const void* X, int kx, const void* Y, int ky, size_t n, double* out_dev);
+// Z_j = sum_i X_i M[i][j] (FP64, M device nb x nb row-major, nb <= 64)
+int mg_block_combine(mglma_ctx* c, double2* Z, const double2* X, const double2* M_dev, size_t n, int nb);
 int mg_dot_norm(mglma_ctx* c, int prec, const void* x, const void* y, size_t n, int nrhs, double* out);
 int mg_mr_update(mglma_ctx* c, int prec, const double* a, void* z, void* s, const void* t, size_t n, int nrhs);
 int mg_multiaxpy2(mglma_ctx* c, int prec, const void* x1, const void* x2, size_t xstride, int k, const double* coef,

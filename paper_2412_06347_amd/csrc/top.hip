@@ -22,6 +22,7 @@ typedef std::complex<double> zc;
 // out[a*ld + r] += sum_e conj(W[a][e]) v[r][e]  via the batched multi-dot
 static int wdot(mglma_ctx* c, const double2* W, int ncols, const double2* v, int nv, double* out_dev) {
     const size_t n = (size_t)c->geo.V1 * c->nc;
+    if (ncols <= 64 && nv <= 64) return mg_gram64(c, W, ncols, v, nv, n, out_dev);
     for (int q = 0; q < nv; ++q)
         MG_TRY(mg_multidot(c, MGLMA_F64, W, n, ncols, v + (size_t)q * n, n, 1, out_dev + (size_t)q * ncols * 2));
     return MGLMA_OK;
@@ -176,17 +177,15 @@ extern "C" int mglma_set_top_modes(mglma_ctx* c, int Nlm, const double* modes) {
                 for (int p = 0; p < Nlm; ++p) G[p * Nlm + q] = zc(h[(q * Nlm + p) * 2], h[(q * Nlm + p) * 2 + 1]);
             int rc = chol_inv(G, Nlm, X);
             if (rc != MGLMA_OK) { mg_free(c, c->W, (size_t)r * n * 16); c->W = nullptr; c->Nlm = c->r = 0; return rc; }
-            // new w_d = sum_{p<=d} X[p][d] w_p ; coefficients for column d at cd[(d*Nlm + p)*2]
+            // new w_d = sum_{p<=d} X[p][d] w_p: M[p][d] (row-major) = X[p][d] for p <= d, else 0
             for (int d = 0; d < Nlm; ++d)
                 for (int p = 0; p < Nlm; ++p) {
                     zc v = p <= d ? X[p * Nlm + d] : zc(0);
-                    h[(d * Nlm + p) * 2] = v.real();
-                    h[(d * Nlm + p) * 2 + 1] = v.imag();
+                    h[(p * Nlm + d) * 2] = v.real();
+                    h[(p * Nlm + d) * 2 + 1] = v.imag();
                 }
             HIP_TRY(hipMemcpyAsync(cd, h, (size_t)Nlm * Nlm * 16, hipMemcpyHostToDevice, c->stream));
-            MG_TRY(mg_zero(c, tmp, (size_t)Nlm * n * 16));
-            for (int d = 0; d < Nlm; ++d)
-                MG_TRY(mg_multiaxpy(c, MGLMA_F64, Wa, n, d + 1, cd + (size_t)d * Nlm * 2, 1.0, tmp + (size_t)d * n, n, 1));
+            MG_TRY(mg_block_combine(c, tmp, Wa, (const double2*)cd, n, Nlm));
             MG_TRY(mg_copy(c, Wa, tmp, (size_t)Nlm * n * 16));
             HIP_TRY(hipStreamSynchronize(c->stream));
         }
