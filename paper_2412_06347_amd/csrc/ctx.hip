@@ -195,6 +195,9 @@ static void free_top(mglma_ctx* c) {
     const Geo& g = c->geo;
     mg_free(c, c->W, (size_t)c->r * g.V1 * c->nc * 16);
     c->W = nullptr;
+    mg_free(c, c->topG, 0);
+    mg_free(c, c->topQi, 0);
+    c->topG = c->topQi = nullptr;
     c->D2.clear(); c->Q2inv.clear(); c->Gamma2.clear();
     c->have_top = false;
     c->Nlm = c->r = 0;

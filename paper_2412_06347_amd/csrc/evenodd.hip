@@ -462,6 +462,7 @@ void mg_eo_free(mglma_ctx* c) {
     c->eo_SY = nullptr;
     c->eo_Einv = nullptr;
     c->eo_defl = false;
+    c->eo_defl_tried = false;
     if (c->eo_site) mg_free(c, c->eo_site, 2 * (size_t)c->eo_Vh * sizeof(int));
     if (c->eo_nbr) mg_free(c, c->eo_nbr, 2 * (size_t)c->eo_Vh * 8 * sizeof(int));
     if (c->eo_Dinv32) mg_free(c, c->eo_Dinv32, V1 * 2 * nn * sizeof(float));
@@ -579,6 +580,14 @@ int mg_eo_setup(mglma_ctx* c) {
         return MGLMA_OK;
     }
     c->eo_ok = true;
+    return MGLMA_OK;
+}
+
+// the deflation subspace is set up at the first deflated solve after a
+// subspace build (it costs an S application on n_c vectors)
+int mg_eo_defl_prepare(mglma_ctx* c) {
+    if (!c->eo_ok || c->eo_defl_tried) return MGLMA_OK;
+    c->eo_defl_tried = true;
     return defl_setup(c);
 }
 

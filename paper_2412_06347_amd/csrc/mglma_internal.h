@@ -271,7 +271,7 @@ struct mglma_ctx {
     float* eo_Dinv32 = nullptr;    // [V1][re/im][nc][nc] inverse self blocks, FP32 planar
     bf16_t* eo_Hbf = nullptr;      // [V1][8][2][nc][nc] D_yy^{-1} D_y,dir planar bfloat16
     // deflation of S with the nc constant even-site vectors Y (y_a = e_a / sqrt(Vh) on every even site)
-    bool eo_defl = false;
+    bool eo_defl = false, eo_defl_tried = false;
     float2* eo_SY = nullptr;       // [nc][Vh][nc] S y_a (the BF16 S of the solver)
     double2* eo_Einv = nullptr;    // [nc][nc] (Y^+ S Y)^{-1}
 
@@ -287,6 +287,8 @@ struct mglma_ctx {
     double2* W = nullptr;                          // [r][V1][nc]
     std::vector<std::complex<double>> D2, Q2inv;   // r x r
     std::vector<std::complex<double>> Gamma2;      // [L0][3][r][r]
+    double2* topG = nullptr;                       // device copies of Gamma2 and Q2^{-1}
+    double2* topQi = nullptr;
     bool have_top = false;
 
     // reusable scratch (grown on demand) and reduction buffers
@@ -372,6 +374,7 @@ int mg_eo_scatter(mglma_ctx* c, const void* xe, const void* xo, void* x_full, in
 int mg_eo_schur(mglma_ctx* c, const void* x, void* out, void* tmp, int nrhs);
 // deflation with the constant even-site vectors: g = E^{-1} Y^+ v (device, complex [nrhs][nc]);
 // v -= S Y g ; v += sign * Y g
+int mg_eo_defl_prepare(mglma_ctx* c);   // builds S Y and E^{-1} once per subspace (eo_defl on success)
 int mg_eo_defl_coef(mglma_ctx* c, const void* v, double* g, int nrhs);
 int mg_eo_defl_sub_sy(mglma_ctx* c, const double* g, void* v, int nrhs);
 int mg_eo_defl_add_y(mglma_ctx* c, const double* g, double sign, void* v, int nrhs);

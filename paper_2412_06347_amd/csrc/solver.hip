@@ -321,6 +321,7 @@ static int coarse_gcr_eo(SolveCtx& S, const void* b, void* x, int iters) {
     // deflated (coarse_eo = 2): x_e starts at Y E^{-1} Y^+ b^, the GCR runs on
     // P_L S with P_L = 1 - S Y E^{-1} Y^+, and x_e gets - Y E^{-1} Y^+ S z at
     // the end (z: what the GCR added), so that S x_e = b^
+    if (S.p->coarse_eo == 2) MG_TRY(mg_eo_defl_prepare(c));
     const bool defl = S.p->coarse_eo == 2 && c->eo_defl;
     double *g0 = nullptr, *g = nullptr;
     if (defl) {

@@ -231,8 +231,61 @@ extern "C" int mglma_set_top_modes(mglma_ctx* c, int Nlm, const double* modes) {
                     c->Gamma2[o + a * r + b] = A_ab - std::conj(A_ba);
                 }
         }
+    // device copies for the exact contraction
+    const size_t ng = (size_t)g.L[0] * 3 * r * r;
+    MG_TRY(mg_malloc(c, (void**)&c->topG, ng * 16));
+    MG_TRY(mg_malloc(c, (void**)&c->topQi, (size_t)r * r * 16));
+    HIP_TRY(hipMemcpyAsync(c->topG, c->Gamma2.data(), ng * 16, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->topQi, c->Q2inv.data(), (size_t)r * r * 16, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
     c->have_top = true;
     return MGLMA_OK;
+}
+
+// A[x][k] = Gamma2[x][k] Q2^{-1} (r x r each) and its transpose AT.
+// grid L0 * 3, block 256.
+__global__ __launch_bounds__(256) void k_top_A(const double2* __restrict__ G, const double2* __restrict__ Qi, int r,
+                                               double2* __restrict__ A, double2* __restrict__ AT) {
+    const size_t base = (size_t)blockIdx.x * r * r;
+    for (int e = threadIdx.x; e < r * r; e += blockDim.x) {
+        const int a = e / r, b = e - a * r;
+        double re = 0.0, im = 0.0;
+        for (int q = 0; q < r; ++q) {
+            const double2 x = G[base + (size_t)a * r + q], y = Qi[(size_t)q * r + b];
+            re = fma(x.x, y.x, fma(-x.y, y.y, re));
+            im = fma(x.x, y.y, fma(x.y, y.x, im));
+        }
+        A[base + e] = make_double2(re, im);
+        AT[base + (size_t)b * r + a] = make_double2(re, im);
+    }
+}
+
+// out[t] = w sum_{y0, k} tr(A[(y0 + t) % L0][k] A[y0][k]) = w sum_{y0,k,e} A[x0][k][e] AT[y0][k][e]
+// grid L0, block 256, partial sums added in LDS in a fixed order
+__global__ __launch_bounds__(256) void k_top_corr(const double2* __restrict__ A, const double2* __restrict__ AT,
+                                                  int L0, int r, double w, double2* __restrict__ out) {
+    __shared__ double2 red[256];
+    const int t = blockIdx.x, rr = r * r;
+    const size_t tot = (size_t)L0 * 3 * rr;
+    double re = 0.0, im = 0.0;
+    for (size_t e = threadIdx.x; e < tot; e += blockDim.x) {
+        const int y0 = (int)(e / ((size_t)3 * rr));
+        const size_t rest = e - (size_t)y0 * 3 * rr;
+        const int x0 = (y0 + t) % L0;
+        const double2 p = A[(size_t)x0 * 3 * rr + rest], q = AT[(size_t)y0 * 3 * rr + rest];
+        re = fma(p.x, q.x, fma(-p.y, q.y, re));
+        im = fma(p.x, q.y, fma(p.y, q.x, im));
+    }
+    red[threadIdx.x] = make_double2(re, im);
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            red[threadIdx.x].x += red[threadIdx.x + s].x;
+            red[threadIdx.x].y += red[threadIdx.x + s].y;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[t] = make_double2(w * red[0].x, w * red[0].y);
 }
 
 extern "C" int mglma_contract_top(mglma_ctx* c, double* G_host) {
@@ -240,34 +293,16 @@ extern "C" int mglma_contract_top(mglma_ctx* c, double* G_host) {
     if (!c->have_top) return MGLMA_ERR_NO_TOP;
     const int L0 = c->L[0], r = c->r;
     const double L3 = (double)c->geo.V3;
-    // A[x0][k] = G_k(x0) Q2^-1
-    std::vector<zc> A((size_t)L0 * 3 * r * r, zc(0));
-    for (int x0 = 0; x0 < L0; ++x0)
-        for (int k = 0; k < 3; ++k) {
-            const zc* G = &c->Gamma2[((size_t)x0 * 3 + k) * r * r];
-            zc* o = &A[((size_t)x0 * 3 + k) * r * r];
-            for (int a = 0; a < r; ++a)
-                for (int e = 0; e < r; ++e) {
-                    zc gae = G[a * r + e];
-                    if (gae == zc(0)) continue;
-                    for (int b = 0; b < r; ++b) o[a * r + b] += gae * c->Q2inv[e * r + b];
-                }
-        }
-    for (int t = 0; t < L0; ++t) {
-        zc s = 0;
-        for (int y0 = 0; y0 < L0; ++y0) {
-            int x0 = (y0 + t) % L0;
-            for (int k = 0; k < 3; ++k) {
-                const zc* P = &A[((size_t)x0 * 3 + k) * r * r];
-                const zc* Q = &A[((size_t)y0 * 3 + k) * r * r];
-                for (int a = 0; a < r; ++a)
-                    for (int b = 0; b < r; ++b) s += P[a * r + b] * Q[b * r + a];
-            }
-        }
-        s *= -1.0 / (3.0 * L0 * L3);
-        G_host[2 * t] = s.real();
-        G_host[2 * t + 1] = s.imag();
-    }
+    const size_t ng = (size_t)L0 * 3 * r * r;
+    double2 *A, *out;
+    MG_TRY(mg_scratch(c, 5, 2 * ng * 16 + (size_t)L0 * 16, (void**)&A));
+    double2* AT = A + ng;
+    out = AT + ng;
+    hipLaunchKernelGGL(k_top_A, dim3(L0 * 3), dim3(256), 0, c->stream, c->topG, c->topQi, r, A, AT);
+    hipLaunchKernelGGL(k_top_corr, dim3(L0), dim3(256), 0, c->stream, A, AT, L0, r, -1.0 / (3.0 * L0 * L3), out);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(G_host, out, (size_t)L0 * 16, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
     return MGLMA_OK;
 }
 
