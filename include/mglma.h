@@ -197,6 +197,17 @@ int mglma_coarse_apply(mglma_ctx* ctx, int prec, int gamma5, const void* in_dev,
  * block).                                                                   */
 int mglma_coarse_schur_apply(mglma_ctx* ctx, const void* in_dev, void* out_dev, int nrhs);
 
+/* ---- checkpoint -------------------------------------------------------- */
+/* Save the subspace (block basis, D_1, coarse gammas) and, when set, the top
+ * level's W to a file; load it into a context of the same lattice, block,
+ * kappa, c_sw and boundary phases (with its gauge field loaded) instead of
+ * building it: the FP32/FP16 basis, the operator copies, the even-odd form
+ * and the top level are rebuilt from the saved FP64 arrays.  Level 2 is not
+ * saved.  Synchronising.  Errors: ARG (file), NO_SUBSPACE (save), NO_GAUGE
+ * (load), SHAPE (header does not match the context, short file).         */
+int mglma_save(mglma_ctx* ctx, const char* path);
+int mglma_load(mglma_ctx* ctx, const char* path);
+
 /* ---- level 2 of the nested hierarchy ------------------------------------- */
 /* Nested block decomposition (sec. "Multigrid low-mode averaging",
  * eq:block_nested_decomp): level-2 blocks of b2[mu] fine sites, each b2[mu]

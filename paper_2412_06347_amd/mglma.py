@@ -30,7 +30,7 @@ SYMBOLS = [
     "mglma_contract_stoch_coarse", "mglma_contract_top", "mglma_coarse_eigs", "mglma_fine_eigs",
     "mglma_deficit", "mglma_coarse_schur_apply",
     "mglma_build_level2", "mglma_export_level2_op", "mglma_level2_restrict", "mglma_level2_prolong",
-    "mglma_level2_apply", "mglma_level2_solve", "mglma_level2_pieces",
+    "mglma_level2_apply", "mglma_level2_solve", "mglma_level2_pieces", "mglma_save", "mglma_load",
 ]
 
 
@@ -212,6 +212,13 @@ class Context:
     @property
     def V2(self):
         return self.query(9)
+
+    # ---- checkpoint ----------------------------------------------------------
+    def save(self, path):
+        _check(lib().mglma_save(self._ctx, str(path).encode()))
+
+    def load(self, path):
+        _check(lib().mglma_load(self._ctx, str(path).encode()))
 
     # ---- level 2 of the nested hierarchy -------------------------------------
     def build_level2(self, b2):
