@@ -10,7 +10,10 @@ against the oracle on sampled outputs and by properties that hold at any size:
 * the benchmark's own pipeline and solver settings: every right-hand side to a
   true relative residual of 1e-10, two of them re-checked with the oracle's M;
   two of its top modes (device eigensolver) re-checked as eigenvectors of Q_1
-  with the oracle's stencil apply to 1e-12.
+  with the oracle's stencil apply to 1e-12;
+* the preconditioner's even-odd Schur apply on sampled even sites, its
+  FP16-basis restrictor and prolongator on sampled blocks, and the coarse
+  pieces to 1e-10 under the oracle's stencil apply.
 """
 import numpy as np
 import pytest
@@ -158,3 +161,110 @@ def test_fullsize_bench_solve(ens):
     print("oracle true rel res", rel)
     assert np.all(rel <= 1.05e-10)
     assert all(np.all(np.isfinite(v)) for v in levels.values())
+
+
+def test_fullsize_evenodd_and_transfers(ens):
+    """The preconditioner's pieces at full size: the even-odd Schur apply on
+    sampled even sites against the same product formed from the exported D_1
+    (its blocks checked by the Galerkin identity above) with FP64 inverses in
+    numpy; the FP16-basis restrictor and prolongator on sampled blocks against
+    the oracle's Gram-Schmidt basis of those blocks; the coarse pieces
+    D_1^-1 R eta with the benchmark's settings to a residual of 1e-10 under
+    the oracle's stencil apply."""
+    import torch
+    from paper_2412_06347_amd import mglma
+    from oracle import coarse as ocoarse
+    U, D = ens
+    Nv = 24
+    nc = 2 * Nv
+    ctx = _ctx(U)
+    tv = synth.gaussian_fields(Nv, L, 1003)
+    x = ctx.fine(Nv)
+    ctx.import_fields(to_dev(tv), x)
+    ctx.build_subspace(x)
+    del x
+    assert ctx.has_eo
+    bl = subspace.Blocking(L, B)
+    nbr = bl.neighbour_table()
+    D1 = torch.empty((bl.V1, 9, nc, nc, 2), dtype=torch.float64, device="cuda")
+    ctx.export_coarse_op(D1)
+    D1h = from_dev(D1)
+    del D1
+    # -- Schur apply on sampled even sites
+    e, o = ocoarse.parity_sites(bl.L1)
+    pos = np.empty(bl.V1, dtype=np.int64)
+    pos[e] = np.arange(len(e))
+    pos[o] = np.arange(len(o))
+    nr = 12
+    xs = synth.gaussian_coarse(nr, len(e), nc, 501)
+    xs = xs.real.astype(np.float32) + 1j * xs.imag.astype(np.float32)
+    xd = to_dev(xs).float()
+    yd = torch.empty_like(xd)
+    ctx.coarse_schur_apply(xd, yd)
+    y = from_dev(yd)
+    inv = {}
+
+    def dinv(site):
+        if site not in inv:
+            inv[site] = np.linalg.inv(D1h[site, 0])
+        return inv[site]
+
+    err, nrm = 0.0, 0.0
+    for k in (0, 1, 333, len(e) - 1):
+        ys = e[k]
+        acc = np.zeros((nr, nc), dtype=np.complex128)
+        for d in range(1, 9):
+            z = nbr[ys, d]
+            tz = np.zeros((nr, nc), dtype=np.complex128)
+            for d2 in range(1, 9):
+                tz += xs[:, pos[nbr[z, d2]]] @ D1h[z, d2].T
+            acc += (tz @ dinv(z).T) @ D1h[ys, d].T
+        ref = xs[:, k] - acc @ dinv(ys).T
+        err += np.linalg.norm(y[:, k] - ref) ** 2
+        nrm += np.linalg.norm(ref) ** 2
+    rel = np.sqrt(err / nrm)
+    print("Schur apply on sampled even sites vs FP64 products: %.2e" % rel)
+    assert rel < 1e-3
+    # -- FP16-basis transfers on sampled blocks
+    ys_ = [0, 1, 777, bl.V1 - 1]
+    tb = np.moveaxis(bl.to_blocks(dirac.fields_to_lattice(tv, L))[:, ys_], 0, 1)
+    phi = np.zeros((len(ys_), nc, bl.Vb, 4, 3), dtype=np.complex128)
+    for a in range(2):
+        w = tb[..., 2 * a:2 * a + 2, :].reshape(len(ys_), Nv, -1)
+        phi[:, a * Nv:(a + 1) * Nv, :, 2 * a:2 * a + 2, :] = \
+            subspace.gram_schmidt(w).reshape(len(ys_), Nv, bl.Vb, 2, 3)
+    psi = synth.gaussian_fields(nr, L, 502)
+    fd = ctx.fine(nr, mglma.F32)
+    ctx.import_fields(to_dev(psi), fd, mglma.F32)
+    cd = torch.empty((nr, bl.V1, nc, 2), dtype=torch.float32, device="cuda")
+    ctx.restrict(fd, cd, mglma.F16)
+    pb = np.moveaxis(bl.to_blocks(dirac.fields_to_lattice(psi, L))[:, ys_], 0, 1)   # [ns][nr][b..][4][3]
+    ref_c = np.einsum("yjvsc,ynvsc->nyj", phi.conj(), pb.reshape(len(ys_), nr, bl.Vb, 4, 3))
+    got_c = from_dev(cd)[:, ys_]
+    rel_r = relerr(got_c, ref_c)
+    cv = synth.gaussian_coarse(nr, bl.V1, nc, 503)
+    cvd = to_dev(cv).float()
+    fo = ctx.fine(nr, mglma.F32)
+    ctx.prolong(cvd, fo, mglma.F16)
+    out = torch.empty((nr, ctx.V, 4, 3, 2), dtype=torch.float64, device="cuda")
+    ctx.export_fields(fo, out, mglma.F32)
+    gotf = np.moveaxis(bl.to_blocks(dirac.fields_to_lattice(from_dev(out), L))[:, ys_], 0, 1)
+    del out
+    ref_f = np.einsum("yjvsc,nyj->ynvsc", phi, cv[:, ys_]).reshape(gotf.shape)
+    rel_p = relerr(gotf, ref_f)
+    print("FP16-basis restrict %.2e prolong %.2e on sampled blocks" % (rel_r, rel_p))
+    assert rel_r < 1e-3 and rel_p < 1e-3
+    # -- coarse pieces with the benchmark's settings, residual under the oracle's stencil
+    src = ctx.fine(nr)
+    ctx.point_sources((0, 0, 0, 0), src)
+    cg = ctx.coarse(nr)
+    p = mglma.default_params(tol=1e-10, coarse=mglma.BF16, coarse_iters=12, max_outer=40, coarse_eo=1)
+    ctx.coarse_pieces(src, cg, None, p)
+    re_ = ctx.coarse(nr)
+    ctx.restrict(src, re_)
+    g = from_dev(cg)
+    rh = from_dev(re_)
+    res = ocoarse.coarse_apply(D1h, nbr, g) - rh
+    rel_c = np.linalg.norm(res.reshape(nr, -1), axis=1) / np.linalg.norm(rh.reshape(nr, -1), axis=1)
+    print("coarse pieces: oracle-stencil residual", rel_c.max())
+    assert rel_c.max() <= 1.05e-10
