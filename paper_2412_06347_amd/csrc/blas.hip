@@ -252,6 +252,38 @@ static int norm2_t(mglma_ctx* c, const S* x, size_t n, int nrhs, double* out) {
     return launch_finish<1>(c, nb, nrhs, 1, out);
 }
 
+// r = b - t (FP64) and out[rhs] = |r|^2 in the same pass
+template <int C>
+__global__ __launch_bounds__(RB) void k_xmy_norm(const double2* __restrict__ b, const double2* __restrict__ t,
+                                                 double2* __restrict__ r, size_t n, double* part) {
+    __shared__ double lds[4];
+    const size_t off = (size_t)blockIdx.y * n;
+    double v[1] = {0.0};
+    for_packets<U_NORM>(n / C, [&](size_t p) {
+        cx<double> a[C], d[C];
+        ldp<double2, double, C>(b + off + p * C, a);
+        ldp<double2, double, C>(t + off + p * C, d);
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            a[k] = a[k] - d[k];
+            v[0] = fma(a[k].re, a[k].re, v[0]);
+            v[0] = fma(a[k].im, a[k].im, v[0]);
+        }
+        stp<double2, double, C>(r + off + p * C, a);
+    });
+    write_partial<1>(v, lds, part, 1);
+}
+
+int mg_xmy_norm(mglma_ctx* c, const void* b, const void* t, void* r, size_t n, int nrhs, double* out) {
+    if (nrhs <= 0) return MGLMA_OK;
+    const int nb = red_blocks(n, U_NORM);
+    MG_TRY(ensure_red(c, (size_t)nb * nrhs));
+    hipLaunchKernelGGL((k_xmy_norm<1>), dim3(nb, nrhs), dim3(RB), 0, c->stream, (const double2*)b, (const double2*)t,
+                       (double2*)r, n, c->red_part);
+    HIP_TRY(hipGetLastError());
+    return launch_finish<1>(c, nb, nrhs, 1, out);
+}
+
 int mg_norm2(mglma_ctx* c, int prec, const void* x, size_t n, int nrhs, double* out) {
     if (nrhs <= 0) return MGLMA_OK;
     switch (prec) {

@@ -124,23 +124,48 @@ __global__ __launch_bounds__(256) void k_inv_self(const double2* __restrict__ D,
 }
 
 // H[y][d] = D_yy^{-1} D[y][1 + d] (d < 8), FP64 products rounded to bfloat16,
-// planar [y][d][re/im][i][j]
+// planar [y][d][re/im][i][j].  One workgroup per site: D_yy^{-1} staged in LDS
+// once for the eight products; thread t owns column j = t % nc and the rows
+// i = g, g + G, ... (g = t / nc, G = 256 / nc groups), so each entry of D[y][d]
+// is loaded from memory once per workgroup and the inverse is read as LDS
+// broadcasts within a group.
+#define EOH_MAXR 16
 __global__ __launch_bounds__(256) void k_eo_hops(const double2* __restrict__ Dinv, const double2* __restrict__ D,
                                                  int nc, bf16_t* __restrict__ Hbf) {
-    const int y = blockIdx.x, d = blockIdx.y, nn = nc * nc;
-    const double2* Ai = Dinv + (size_t)y * nn;
-    const double2* Bd = D + ((size_t)y * 9 + 1 + d) * nn;
-    bf16_t* out = Hbf + ((size_t)y * 8 + d) * 2 * nn;
-    for (int e = threadIdx.x; e < nn; e += blockDim.x) {
-        const int i = e / nc, j = e - i * nc;
-        double re = 0.0, im = 0.0;
-        for (int m = 0; m < nc; ++m) {
-            const double2 a = Ai[i * nc + m], b = Bd[m * nc + j];
-            re = fma(a.x, b.x, fma(-a.y, b.y, re));
-            im = fma(a.x, b.y, fma(a.y, b.x, im));
+    extern __shared__ double2 Ai[];          // nc x nc
+    const int y = blockIdx.x, t = threadIdx.x, nn = nc * nc;
+    for (int e = t; e < nn; e += blockDim.x) Ai[e] = Dinv[(size_t)y * nn + e];
+    __syncthreads();
+    const int G = 256 / nc, j = t % nc, grp = t / nc;
+    if (grp >= G) return;
+    for (int d = 0; d < 8; ++d) {
+        const double2* Bd = D + ((size_t)y * 9 + 1 + d) * nn;
+        bf16_t* out = Hbf + ((size_t)y * 8 + d) * 2 * nn;
+        for (int i0 = grp; i0 < nc; i0 += G * EOH_MAXR) {
+            double ar[EOH_MAXR], ai[EOH_MAXR];
+#pragma unroll
+            for (int q = 0; q < EOH_MAXR; ++q) ar[q] = ai[q] = 0.0;
+            for (int m = 0; m < nc; ++m) {
+                const double2 bv = Bd[(size_t)m * nc + j];
+#pragma unroll
+                for (int q = 0; q < EOH_MAXR; ++q) {
+                    const int i = i0 + q * G;
+                    if (i < nc) {
+                        const double2 av = Ai[i * nc + m];
+                        ar[q] = fma(av.x, bv.x, fma(-av.y, bv.y, ar[q]));
+                        ai[q] = fma(av.x, bv.y, fma(av.y, bv.x, ai[q]));
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < EOH_MAXR; ++q) {
+                const int i = i0 + q * G;
+                if (i < nc) {
+                    out[i * nc + j] = (bf16_t)f2bf_rne((float)ar[q]);
+                    out[nn + i * nc + j] = (bf16_t)f2bf_rne((float)ai[q]);
+                }
+            }
         }
-        out[e] = (bf16_t)f2bf_rne((float)re);
-        out[nn + e] = (bf16_t)f2bf_rne((float)im);
     }
 }
 
@@ -570,7 +595,7 @@ int mg_eo_setup(mglma_ctx* c) {
     hipLaunchKernelGGL(k_inv_self, dim3(V1), dim3(256), nn * sizeof(double2), c->stream, c->D64, nc, Dinv,
                        c->eo_Dinv32, bad);
     HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_eo_hops, dim3(V1, 8), dim3(256), 0, c->stream, Dinv, c->D64, nc, c->eo_Hbf);
+    hipLaunchKernelGGL(k_eo_hops, dim3(V1), dim3(256), nn * sizeof(double2), c->stream, Dinv, c->D64, nc, c->eo_Hbf);
     HIP_TRY(hipGetLastError());
     int hbad = 0;
     HIP_TRY(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));

@@ -398,6 +398,8 @@ int mg_gram64(mglma_ctx* c, const void* X, int kx, const void* Y, int ky, size_t
 // Z_j = sum_i X_i M[i][j] (FP64, M device nb x nb row-major, nb <= 64)
 int mg_block_combine(mglma_ctx* c, double2* Z, const double2* X, const double2* M_dev, size_t n, int nb);
 int mg_dot_norm(mglma_ctx* c, int prec, const void* x, const void* y, size_t n, int nrhs, double* out);
+// r = b - t and out[rhs] = |r|^2 (FP64 fields)
+int mg_xmy_norm(mglma_ctx* c, const void* b, const void* t, void* r, size_t n, int nrhs, double* out);
 int mg_mr_update(mglma_ctx* c, int prec, const double* a, void* z, void* s, const void* t, size_t n, int nrhs);
 int mg_multiaxpy2(mglma_ctx* c, int prec, const void* x1, const void* x2, size_t xstride, int k, const double* coef,
                   void* y1, void* y2, size_t n, int nrhs);

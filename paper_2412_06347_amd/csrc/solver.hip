@@ -69,20 +69,6 @@ static int mg_sub(mglma_ctx* c, int prec, const void* a, const void* b, void* o,
     return MGLMA_OK;
 }
 
-// r = b - t
-__global__ void k_xmy(const double2* __restrict__ b, const double2* __restrict__ t, double2* __restrict__ r, size_t n) {
-    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
-        double2 u = b[k], v = t[k];
-        r[k] = make_double2(u.x - v.x, u.y - v.y);
-    }
-}
-
-static dim3 grid1(size_t n) {
-    size_t b = (n + 1023) / 1024;
-    if (b > 4096) b = 4096;
-    return dim3((unsigned)(b ? b : 1));
-}
-
 // ---------------------------------------------------------------------------
 // solver state
 // ---------------------------------------------------------------------------
@@ -468,18 +454,18 @@ static int precondition(SolveCtx& S, int vp, const void* r, void* z) {
 // number of iterations.  Stops when every active right-hand side has
 // ||r|| <= inner_tol ||rin|| (checked on the host each iteration).
 // ---------------------------------------------------------------------------
-static int inner_fgcr(SolveCtx& S, int vp, const void* rin, void* e, const std::vector<int>& active, int* iters) {
+static int inner_fgcr(SolveCtx& S, int vp, void* rin, void* e, const std::vector<int>& active, int* iters) {
     mglma_ctx* c = S.c;
     const mglma_solve_params* p = S.p;
     const int nrhs = S.nrhs;
     const size_t n = fine_n(c), vb = prec_cbytes(vp), setsz = (size_t)nrhs * n;
     const int m = p->gcr_m;
-    void *Z, *W, *r;
+    void *Z, *W;
     MG_TRY(mg_scratch(c, WS_Z, (size_t)m * setsz * vb, &Z));
     MG_TRY(mg_scratch(c, WS_W, (size_t)m * setsz * vb, &W));
-    MG_TRY(mg_scratch(c, WS_CX64, setsz * vb, &r));
+    // the residual is updated in place in rin (the caller's scratch)
+    void* r = rin;
     MG_TRY(mg_zero(c, e, setsz * vb));
-    MG_TRY(mg_copy(c, r, rin, setsz * vb));
     double* h;
     MG_TRY(mg_host(c, 2 * (size_t)nrhs, &h));
     MG_TRY(mg_norm2(c, vp, r, n, nrhs, S.s.rn2()));
@@ -605,8 +591,7 @@ extern "C" int mglma_solve(mglma_ctx* c, const mglma_solve_params* p, const doub
                                (const float2*)e, S.s.scale(), n);
         HIP_TRY(hipGetLastError());
         MG_TRY(mg_dslash(c, MGLMA_F64, 0, x, t64, nrhs));
-        hipLaunchKernelGGL(k_xmy, grid1(setsz), dim3(256), 0, c->stream, (const double2*)b, t64, r64, setsz);
-        MG_TRY(mg_norm2(c, MGLMA_F64, r64, n, nrhs, S.s.rn2()));
+        MG_TRY(mg_xmy_norm(c, b, t64, r64, n, nrhs, S.s.rn2()));
         HIP_TRY(hipMemcpyAsync(h, S.s.rn2(), nrhs * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(hipStreamSynchronize(c->stream));
         for (int q = 0; q < nrhs; ++q) {
@@ -690,8 +675,7 @@ int mg_coarse_solve(mglma_ctx* c, const mglma_solve_params* p, const double* b, 
                                (const float2*)e, S.s.scale(), n);
         HIP_TRY(hipGetLastError());
         MG_TRY(level_apply(c, level, MGLMA_F64, x, t64, nrhs));
-        hipLaunchKernelGGL(k_xmy, grid1(setsz), dim3(256), 0, c->stream, (const double2*)b, t64, r64, setsz);
-        MG_TRY(mg_norm2(c, MGLMA_F64, r64, n, nrhs, S.s.rn2()));
+        MG_TRY(mg_xmy_norm(c, b, t64, r64, n, nrhs, S.s.rn2()));
         HIP_TRY(hipMemcpyAsync(h, S.s.rn2(), nrhs * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(hipStreamSynchronize(c->stream));
         for (int q = 0; q < nrhs; ++q) {
