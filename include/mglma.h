@@ -21,6 +21,9 @@
  *   - Pointers named *_dev are device memory owned by the caller; the library
  *     never frees them and keeps no reference after the call returns.
  *   - Complex numbers are stored (re, im) interleaved.
+ *   - Batched operator calls (apply, restrict / prolong, coarse and level-2
+ *     applies and transfers) accept nrhs = 0 as a no-op (pointers must still
+ *     be valid); solves and pieces need nrhs >= 1.
  *   - Site ordering.  Canonical: s = ((x0*L1 + x1)*L2 + x2)*L3 + x3 (x0 is
  *     time).  Device ("blocked"): i = k*Vb + l with k the block index
  *     (lexicographic over the block grid, last direction fastest) and l the

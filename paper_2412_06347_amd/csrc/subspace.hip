@@ -123,8 +123,11 @@ __global__ void k_chol_inv(int Nv, double2* __restrict__ G, double2* __restrict_
 }
 
 // In place: w_d <- sum_{c<=d} w_c Rinv[c][d], d processed from the top down.
+// (B32 / B16 non-null: the result is also written in FP32 and FP16, the
+// copies the transfers read)
 __global__ __launch_bounds__(256) void k_apply_rinv(double2* __restrict__ B, int Nv, int K,
-                                                    const double2* __restrict__ Rinv) {
+                                                    const double2* __restrict__ Rinv, float2* __restrict__ B32,
+                                                    __half2* __restrict__ B16) {
     const int ya = blockIdx.x;
     double2* W = B + (size_t)ya * Nv * K;
     const double2* X = Rinv + (size_t)ya * Nv * Nv;
@@ -149,7 +152,15 @@ __global__ __launch_bounds__(256) void k_apply_rinv(double2* __restrict__ B, int
                 }
             }
             for (int q = 0; q < 16; ++q)
-                if (d0 + q < d1) W[(size_t)(d0 + q) * K + k] = make_double2(acc[q].re, acc[q].im);
+                if (d0 + q < d1) {
+                    const size_t o = (size_t)(d0 + q) * K + k;
+                    W[o] = make_double2(acc[q].re, acc[q].im);
+                    if (B32) {
+                        const size_t og = (size_t)ya * Nv * K + o;
+                        B32[og] = make_float2((float)acc[q].re, (float)acc[q].im);
+                        B16[og] = __floats2half2_rn((float)acc[q].re, (float)acc[q].im);
+                    }
+                }
         }
     }
 }
@@ -635,7 +646,7 @@ __global__ __launch_bounds__(256) void k_coarse_gamma_mfma(Geo g, int Nv, const 
 // ---------------------------------------------------------------------------
 // ABI: build the subspace
 // ---------------------------------------------------------------------------
-static int cholqr_pass(mglma_ctx* c, double2* Gb, double2* Rb, int* bad) {
+static int cholqr_pass(mglma_ctx* c, double2* Gb, double2* Rb, int* bad, bool copies) {
     const Geo& g = c->geo;
     const int Nv = c->Nv, K = 6 * g.Vb;
     const int nya = g.V1 * 2;
@@ -645,7 +656,7 @@ static int cholqr_pass(mglma_ctx* c, double2* Gb, double2* Rb, int* bad) {
     hipLaunchKernelGGL(k_chol_inv, dim3(nya), dim3(64), 0, c->stream, Nv, Gb, Rb, 3e-7, bad);
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_apply_rinv, dim3(nya), dim3(256), (size_t)Nv * Nv * sizeof(double2), c->stream, c->B64, Nv,
-                       K, (const double2*)Rb);
+                       K, (const double2*)Rb, copies ? c->B32 : nullptr, copies ? c->B16 : nullptr);
     HIP_TRY(hipGetLastError());
     return MGLMA_OK;
 }
@@ -682,14 +693,12 @@ extern "C" int mglma_build_subspace(mglma_ctx* c, int Nv, const double* tv) {
     MG_TRY(mg_scratch(c, 1, gsz, (void**)&Rb));
     MG_TRY(mg_scratch(c, 7, 64, (void**)&bad));
     HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int), c->stream));
-    MG_TRY(cholqr_pass(c, Gb, Rb, bad));
+    MG_TRY(cholqr_pass(c, Gb, Rb, bad, false));
     int hbad = 0;
     HIP_TRY(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     if (hbad) { mg_free_subspace(c); return MGLMA_ERR_RANK; }
-    MG_TRY(cholqr_pass(c, Gb, Rb, bad));
-    MG_TRY(mg_convert(c, MGLMA_F64, c->B64, MGLMA_F32, c->B32, nb, 1, nullptr, 0));
-    MG_TRY(mg_convert(c, MGLMA_F64, c->B64, MGLMA_F16, c->B16, nb, 1, nullptr, 0));
+    MG_TRY(cholqr_pass(c, Gb, Rb, bad, true));   // also writes the FP32 and FP16 copies
 
     // 3. Galerkin operator, block by block (the column-major FP64 copy is the scratch of the pieces)
     MG_TRY(mg_galerkin(c, (double2*)c->D64p));
