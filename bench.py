@@ -242,9 +242,11 @@ def hierarchy(wl, reps=3):
     level-2 blocks of twice their size, one level-3 block spanned by the
     constant coarse vectors, evaluated exactly) on the bench workload: time of
     the level-2 operator build and of the level-2 propagator pieces for the 12
-    point sources, and the four level contributions of the point correlator."""
+    point sources, the four level contributions of the point correlator, and
+    the stochastic estimator with per-level source counts (fine solves only for
+    L0) timed level by level."""
     import torch
-    from paper_2412_06347_amd import mglma
+    from paper_2412_06347_amd import mglma, synth as synth_mod
     P = Pipeline(wl, log_setup=False)
     ctx = P.ctx
     P.step(mixed_params(mglma))
@@ -275,6 +277,46 @@ def hierarchy(wl, reps=3):
     G3 = ctx.contract_top()
     L0 = wl["L"][0]
     lv = dict(L0=C["all"] - C["ge1"], L1=C["ge1"] - C["ge2"], L2=C["ge2"] - C["top"], L3_point=C["top"])
+    # stochastic estimator with per-level source counts (sec. "Stochastic estimator
+    # on level k": few sources for the level that needs fine solves, more for the
+    # coarse levels; spin-diluted time-slice noise, 4 right-hand sides per source)
+    Lat = wl["L"]
+    V3 = Lat[1] * Lat[2] * Lat[3]
+    nsrc = {"L0": 2, "L1": 8, "L2": 32}
+
+    def noise(n, seed):
+        xi = np.ascontiguousarray(synth_mod.z4_noise(n, Lat, seed))
+        t = synth_mod.time_slices(n, Lat[0], seed + 1)
+        eta = ctx.fine(4 * n)
+        ctx.noise_sources(torch.from_numpy(xi.view(np.float64).reshape(n, V3, 3, 2)).cuda(), t, eta)
+        return eta, t
+
+    def mean_stoch(fn, a, b, t, n):
+        return sum(fn(a[4 * k:4 * k + 4], b[4 * k:4 * k + 4], int(t[k])) for k in range(n)) / n
+
+    stoch, tlev = {}, {}
+    for lvname, seed in (("L0", 7100), ("L1", 7200), ("L2", 7300)):
+        n = nsrc[lvname]
+        eta, t = noise(n, seed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g1, tp, g2 = ctx.coarse(4 * n), ctx.coarse(4 * n), ctx.coarse(4 * n)
+        if lvname == "L0":
+            x = ctx.fine(4 * n)
+            ctx.solve(eta, x, mixed_params(mglma))
+            ctx.coarse_pieces(eta, g1, None, cp)
+            G = mean_stoch(ctx.contract_stoch, x, x, t, n) - mean_stoch(ctx.contract_stoch_coarse, g1, g1, t, n)
+        elif lvname == "L1":
+            ctx.coarse_pieces(eta, g1, None, cp)
+            ctx.level2_pieces(eta, g2, cp)
+            G = mean_stoch(ctx.contract_stoch_coarse, g1, g1, t, n) - mean_stoch(ctx.contract_stoch_coarse, g2, g2, t, n)
+        else:
+            ctx.coarse_pieces(eta, g1, tp, cp)
+            ctx.level2_pieces(eta, g2, cp)
+            G = mean_stoch(ctx.contract_stoch_coarse, g2, g2, t, n) - mean_stoch(ctx.contract_stoch_coarse, tp, tp, t, n)
+        torch.cuda.synchronize()
+        tlev[lvname] = time.perf_counter() - t0
+        stoch[lvname] = G
     print(json.dumps({
         "diagnostic": "four-level hierarchy (nested blocks, eq:mglma:decomp) on the bench workload",
         "levels": {"1": "%s blocks, V1=%d, nc=%d" % ("x".join(map(str, wl["block"])), V1, nc),
@@ -286,6 +328,12 @@ def hierarchy(wl, reps=3):
         "point_correlator_t": list(range(0, L0, max(1, L0 // 8))),
         "C_levels_real": {k: [float(v[t].real) for t in range(0, L0, max(1, L0 // 8))] for k, v in lv.items()},
         "G_L3_exact_real": [float(G3[t].real) for t in range(0, L0, max(1, L0 // 8))],
+        "stochastic": {"sources_per_level": nsrc,
+                       "seconds_per_level": {k: round(v, 3) for k, v in tlev.items()},
+                       "G_levels_real": {k: [float(v[t].real) for t in range(0, L0, max(1, L0 // 8))]
+                                         for k, v in stoch.items()},
+                       "G_total_real": [float((sum(stoch.values()) + G3)[t].real)
+                                        for t in range(0, L0, max(1, L0 // 8))]},
     }), flush=True)
 
 
