@@ -77,10 +77,12 @@ __global__ void k_split_modes(int Nlm, int V1, int nc, const double2* __restrict
 // Gamma2 partial: A[x0][k][a][b] = sum_{y in row(x0)} W0_y^+ (Gb_y(t) W1_y)  (W0/W1: alpha=0/1 rows).
 // grid (L0, 3, TSPLIT), block 256: workgroup z takes the z-th of TSPLIT
 // consecutive ranges of the coarse sites of the time row and writes its own
-// partial sum (added in z order by k_sum_parts).  For every coarse site the
-// product T = Gb W1 (Nv x 32 column tile) is staged in LDS, then each thread
-// adds W0^+ T into the outputs it owns.  Needs Nv <= 64 and r <= 128.
-#define TBW 32
+// partial sum (added in z order by k_sum_parts).  Columns b in tiles of TB:
+// per coarse site the W1 rows of the tile are staged in LDS (coalesced),
+// T = Gb W1 (Nv x TB) is formed in LDS, then the W0 rows in chunks of 16 and
+// each thread adds one (a, b) entry of W0^+ T per chunk.  Needs Nv <= 64 and
+// r <= 128 (at most 8 chunks).
+#define TB 16
 #define TSPLIT 48
 __global__ __launch_bounds__(256) void k_top_gamma(Geo g, int Nv, int r, const double2* __restrict__ W,
                                                    const double2* __restrict__ G1, double2* __restrict__ A) {
@@ -90,40 +92,56 @@ __global__ __launch_bounds__(256) void k_top_gamma(Geo g, int Nv, int r, const d
     const int ys0 = (int)((long)rowsz * z / TSPLIT), ys1 = (int)((long)rowsz * (z + 1) / TSPLIT);
     const size_t V1 = g.V1;
     A += (size_t)z * g.L[0] * 3 * r * r;
-    __shared__ double2 T[64 * TBW];
-    for (int bt = 0; bt < r; bt += TBW) {
-        const int nb = r - bt < TBW ? r - bt : TBW;
-        cx<double> acc[16];
-        for (int q = 0; q < 16; ++q) acc[q] = cmk(0.0, 0.0);
+    __shared__ double2 W1s[TB * 64], Ts[64 * TB], W0s[16 * 64];
+    const int tid = threadIdx.x;
+    const int la = tid / TB, lb = tid % TB;       // this thread's entry (a0 + la, bt + lb) of a chunk
+    const int nchunk = (r + 15) / 16;
+    for (int bt = 0; bt < r; bt += TB) {
+        const int nb = r - bt < TB ? r - bt : TB;
+        cx<double> acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = cmk(0.0, 0.0);
         for (int ys = ys0; ys < ys1; ++ys) {
             const int y = y0 * rowsz + ys;
             const double2* Gb = G1 + (((size_t)y * b0 + t) * 3 + k) * Nv * Nv;
             __syncthreads();
-            for (int e = threadIdx.x; e < Nv * nb; e += blockDim.x) {
-                const int cc = e / nb, bb = e % nb;
-                const double2* w1 = W + ((size_t)(bt + bb) * V1 + y) * nc + Nv;
-                cx<double> s = cmk(0.0, 0.0);
-                for (int d = 0; d < Nv; ++d)
-                    cmac(s, ldc<double2, double>(Gb + cc * Nv + d), ldc<double2, double>(w1 + d));
-                T[cc * TBW + bb] = make_double2(s.re, s.im);
+            for (int e = tid; e < nb * Nv; e += blockDim.x) {
+                const int bb = e / Nv, d = e - bb * Nv;
+                W1s[bb * 64 + d] = W[((size_t)(bt + bb) * V1 + y) * nc + Nv + d];
             }
             __syncthreads();
-            for (int q = 0; q < 16; ++q) {
-                const int o = threadIdx.x + 256 * q;
-                if (o >= r * nb) break;
-                const int a = o / nb, bb = o % nb;
-                const double2* w0 = W + ((size_t)a * V1 + y) * nc;
-                cx<double> s = acc[q];
-                for (int cc = 0; cc < Nv; ++cc)
-                    cjmac(s, ldc<double2, double>(w0 + cc), cmk(T[cc * TBW + bb].x, T[cc * TBW + bb].y));
-                acc[q] = s;
+            for (int e = tid; e < Nv * nb; e += blockDim.x) {
+                const int cc = e / nb, bb = e - cc * nb;
+                cx<double> s = cmk(0.0, 0.0);
+                for (int d = 0; d < Nv; ++d)
+                    cmac(s, ldc<double2, double>(Gb + cc * Nv + d), ldc<double2, double>(W1s + bb * 64 + d));
+                Ts[cc * TB + bb] = make_double2(s.re, s.im);
+            }
+#pragma unroll
+            for (int ch = 0; ch < 8; ++ch) {
+                if (ch >= nchunk) continue;   // uniform over the workgroup
+                const int a0 = ch * 16, na = r - a0 < 16 ? r - a0 : 16;
+                __syncthreads();
+                for (int e = tid; e < na * Nv; e += blockDim.x) {
+                    const int aa = e / Nv, cc = e - aa * Nv;
+                    W0s[aa * 64 + cc] = W[((size_t)(a0 + aa) * V1 + y) * nc + cc];
+                }
+                __syncthreads();
+                if (la < na && lb < nb) {
+                    cx<double> s = acc[ch];
+                    for (int cc = 0; cc < Nv; ++cc) {
+                        const double2 tv = Ts[cc * TB + lb];
+                        cjmac(s, ldc<double2, double>(W0s + la * 64 + cc), cmk(tv.x, tv.y));
+                    }
+                    acc[ch] = s;
+                }
             }
         }
-        for (int q = 0; q < 16; ++q) {
-            const int o = threadIdx.x + 256 * q;
-            if (o >= r * nb) break;
-            const int a = o / nb, bb = o % nb;
-            A[(((size_t)x0 * 3 + k) * r + a) * r + bt + bb] = make_double2(acc[q].re, acc[q].im);
+#pragma unroll
+        for (int ch = 0; ch < 8; ++ch) {
+            const int a = ch * 16 + la;
+            if (ch < nchunk && a < r && lb < nb)
+                A[(((size_t)x0 * 3 + k) * r + a) * r + bt + lb] = make_double2(acc[ch].re, acc[ch].im);
         }
     }
 }
