@@ -177,3 +177,15 @@ def test_basis_from_exact_low_modes():
     print("1 - eps_c:", 1 - eps)
     assert eps[:Ns].max() < 1e-12
     assert np.abs(eps - ref).max() < 1e-12
+    # exact reproduction (appendix on the coarse spectra): with the basis built
+    # from exact modes of Q, those modes lie in range T, so Q_1 = R Q T has
+    # their eigenvalues; the device coarse eigensolver finds them among the
+    # lowest of Q_1
+    nc = 2 * Ns
+    init = to_dev(synth.gaussian_coarse(2 * Ns + 4, ctx.V1, nc, 617))
+    rc1, lam1, vec1, st1 = ctx.coarse_eigs(init, 2 * Ns)
+    assert rc1 == 0
+    for l in lam[:Ns]:
+        d = np.abs(lam1 - l).min()
+        print("fine eigenvalue %.12f: nearest coarse %.2e" % (l, d))
+        assert d < 1e-10
