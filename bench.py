@@ -242,7 +242,9 @@ def hierarchy(wl, reps=3):
     level-2 blocks of twice their size, one level-3 block spanned by the
     constant coarse vectors, evaluated exactly) on the bench workload: time of
     the level-2 operator build and of the level-2 propagator pieces for the 12
-    point sources, the four level contributions of the point correlator, and
+    point sources, the cost of a solve on each level against the fine solve
+    (measured and modelled ratio Phi, level 1 also with the K-cycle), the
+    four level contributions of the point correlator, and
     the stochastic estimator with per-level source counts (fine solves only for
     L0) timed level by level."""
     import torch
@@ -253,16 +255,47 @@ def hierarchy(wl, reps=3):
     Nv, nc, V1 = ctx.query(3), ctx.nc, ctx.V1
     b2 = [2 * b for b in wl["block"]]
 
-    def timed(f):
+    def timed_out(f):
         f()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(reps):
-            f()
+            out = f()
         torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / reps
+        return (time.perf_counter() - t0) / reps, out
+
+    def timed(f):
+        return timed_out(f)[0]
 
     t_build = timed(lambda: ctx.build_level2(b2))
+    # cost of a solve on each level (App. "Performance model": Phi(Lk) = cost of
+    # the fine solve / cost of the level-k solve; the model takes equal
+    # iteration counts, Phi = 12 V / (nc V_k)): the 12 point sources batched,
+    # each level solved to 1e-10 (level k: its restriction of the sources)
+    V = int(np.prod(wl["L"]))
+    xf, Re, x1 = ctx.fine(12), ctx.coarse(12), ctx.coarse(12)
+    R2, x2 = ctx.level2_field(12), ctx.level2_field(12)
+    ctx.restrict(P.src, Re)
+    ctx.level2_restrict(Re, R2)
+    t_fine, (_, st_f) = timed_out(lambda: ctx.solve(P.src, xf, mixed_params(mglma)))
+    capped = dict(tol=1e-10, coarse=mglma.BF16, max_outer=40, max_inner=1)
+    lv_solvers = {
+        "L1 GCR on the even-odd reduced D_1 (12 steps per FP64 round)":
+            (1, mglma.default_params(coarse_iters=12, coarse_eo=1, **capped)),
+        "L1 K-cycle (4 flexible steps per round; each: 4 GCR steps on D_2, 4 MR steps on D_1)":
+            (1, mglma.default_params(coarse_iters=4, coarse_eo=0, kcycle=4, kcycle_nu=4, **capped)),
+        "L2 GCR on D_2 (8 steps per FP64 round)": (2, mglma.default_params(coarse_iters=8, **capped)),
+    }
+    cost = {"L0 MG solve (bench settings)": dict(ms=round(1e3 * t_fine, 2), iterations=st_f[0]["inner"])}
+    for name, (lev, prm) in lv_solvers.items():
+        if lev == 1:
+            t, st = timed_out(lambda: ctx.coarse_solve(Re, x1, prm))
+        else:
+            t, st = timed_out(lambda: ctx.level2_solve(R2, x2, prm))
+        Vk = V1 if lev == 1 else ctx.V2
+        cost[name] = dict(ms=round(1e3 * t, 2), rounds=st[0]["outer"], level_applies=st[0].get("coarse"),
+                          max_rel_res=max(q["true_rel_res"] for q in st), Phi=round(t_fine / t, 1),
+                          Phi_model=round(12 * V / (nc * Vk), 1))
     modes = np.zeros((Nv, V1, nc), dtype=np.complex128)
     for c in range(Nv):
         modes[c, :, c] = 1.0
@@ -323,6 +356,7 @@ def hierarchy(wl, reps=3):
                    "2": "%s blocks, V2=%d" % ("x".join(map(str, b2)), ctx.V2),
                    "3": "one block: the %d constant coarse vectors, exact (eq:G_LL:exact)" % nc},
         "build_level2_ms": round(1e3 * t_build, 2),
+        "cost_per_level_12rhs": cost,
         "level1_pieces_ms_12rhs": round(1e3 * t_p1, 2),
         "level2_pieces_ms_12rhs": round(1e3 * t_p2, 2),
         "point_correlator_t": list(range(0, L0, max(1, L0 // 8))),

@@ -105,6 +105,19 @@ typedef struct {
                             with the nc constant even-site vectors (one per
                             coarse component; one more S application per
                             solve).  0: GCR on D_1.                      */
+    int    kcycle;       /* > 0 (needs mglma_build_level2): the level-1 GCR
+                            of the coarse solve and of the preconditioner's
+                            coarse correction becomes a flexible GCR whose
+                            preconditioner is the next level's two-level
+                            method (sec. "Multigrid low-mode averaging":
+                            the nested R_1, T_1 and D_2 = R_1 D_1 T_1):
+                            z = T_1 (kcycle GCR steps on D_2) R_1 r, then
+                            kcycle_nu minimal-residual steps on D_1 z = r;
+                            coarse_iters then counts these flexible steps.
+                            Takes the place of coarse_eo on level 1; no
+                            effect on the level-2 solve.  0: off.         */
+    int    kcycle_nu;    /* minimal-residual steps on D_1 after the level-2
+                            correction of the K-cycle (0..16)               */
 } mglma_solve_params;
 
 enum { MGLMA_SMOOTH_MR = 0, MGLMA_SMOOTH_CAGCR = 1 };

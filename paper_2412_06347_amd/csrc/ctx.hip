@@ -238,7 +238,7 @@ extern "C" void mglma_destroy(mglma_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     mg_free_subspace(c);
     free_gauge(c);
-    for (int i = 0; i < 32; ++i) mg_free(c, c->scr[i].ptr, c->scr[i].bytes);
+    for (int i = 0; i < mglma_ctx::NSCR; ++i) mg_free(c, c->scr[i].ptr, c->scr[i].bytes);
     mg_free(c, c->red_part, c->red_part_n * sizeof(double));
     cache_release(c);
     for (auto& b : c->alloc_size) (void)hipFree(b.first);   // anything not released above

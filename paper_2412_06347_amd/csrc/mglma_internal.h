@@ -292,7 +292,8 @@ struct mglma_ctx {
     bool have_top = false;
 
     // reusable scratch (grown on demand) and reduction buffers
-    Scratch scr[32];
+    static constexpr int NSCR = 40;
+    Scratch scr[NSCR];
     double* red_part = nullptr; size_t red_part_n = 0;
 
     double* hbuf = nullptr; size_t hbuf_n = 0;     // pinned host staging

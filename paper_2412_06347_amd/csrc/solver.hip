@@ -19,6 +19,9 @@ enum {
 };
 enum { WS_EO = 30 };   // odd right-hand side, odd scratch and even iterate of the even-odd coarse GCR
 enum { WS_DEFL = 31 }; // deflation coefficients of the even-odd coarse GCR
+// K-cycle: level-1 directions p, q and residual, level-2 right-hand side and
+// iterate, level-1 smoother vectors, the level-2 GCR's scalars
+enum { WS_KP = 32, WS_KQ, WS_KR, WS_K2, WS_KS, WS_SCAL2 };
 
 // ---------------------------------------------------------------------------
 // scalar kernels (per right-hand side)
@@ -245,9 +248,14 @@ static int level_apply(mglma_ctx* c, int level, int prec, const void* in, void* 
 //   vectors in precision vp (F32 or F64), operator precision op
 // ---------------------------------------------------------------------------
 static int coarse_gcr_eo(SolveCtx& S, const void* b, void* x, int iters);
+static int coarse_kcycle(SolveCtx& S, int vp, int op, const void* b, void* x, int iters);
 
 static int coarse_gcr_fixed(SolveCtx& S, int vp, int op, const void* b, void* x, int iters) {
     mglma_ctx* c = S.c;
+    if (S.level == 1 && S.p->kcycle > 0) {
+        if (!c->have_l2) return MGLMA_ERR_NO_SUBSPACE;
+        return coarse_kcycle(S, vp, op, b, x, iters);
+    }
     if (S.level == 1 && c->eo_ok && S.p->coarse_eo && vp == MGLMA_F32 && op == MGLMA_BF16)
         return coarse_gcr_eo(S, b, x, iters);
     const int nrhs = S.nrhs;
@@ -341,6 +349,85 @@ static int coarse_gcr_eo(SolveCtx& S, const void* b, void* x, int iters) {
     }
     MG_TRY(mg_eo_hop(c, 1, xe, to, to, nrhs));
     MG_TRY(mg_eo_scatter(c, xe, to, x, nrhs));
+    return MGLMA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// K-cycle on level 1: flexible GCR on D_1 preconditioned by the two-level
+// method of the nested hierarchy's next level (sec. "Multigrid low-mode
+// averaging": R_1, T_1 and D_2 = R_1 D_1 T_1),
+//   z = T_1 e_2 with e_2 = kcycle GCR steps on D_2 e_2 = R_1 r,
+// then kcycle_nu minimal-residual steps on D_1 z = r.  Level-1 vectors in
+// precision vp (F32 or F64), operators in op (F64 with F64 vectors).
+// ---------------------------------------------------------------------------
+static int kcycle_precondition(SolveCtx& S, SolveCtx& S2, int vp, int op, const void* r, void* z) {
+    mglma_ctx* c = S.c;
+    const mglma_solve_params* p = S.p;
+    const int nrhs = S.nrhs;
+    const size_t n1 = level_n(c, 1), n2 = level_n(c, 2), vb = prec_cbytes(vp);
+    void* v2;
+    MG_TRY(mg_scratch(c, WS_K2, 2 * (size_t)nrhs * n2 * vb, &v2));
+    char* r2 = (char*)v2;
+    char* e2 = r2 + (size_t)nrhs * n2 * vb;
+    MG_TRY(mg_l2_restrict(c, vp, r, r2, nrhs));
+    MG_TRY(coarse_gcr_fixed(S2, vp, op, r2, e2, p->kcycle));
+    MG_TRY(mg_l2_prolong(c, vp, e2, z, nrhs));
+    if (p->kcycle_nu <= 0) return MGLMA_OK;
+    // s = r - D_1 z; then per step t = D_1 s, omega = <t,s>/<t,t>, z += omega s, s -= omega t
+    void* st;
+    MG_TRY(mg_scratch(c, WS_KS, 2 * (size_t)nrhs * n1 * vb, &st));
+    char* s = (char*)st;
+    char* t = s + (size_t)nrhs * n1 * vb;
+    MG_TRY(level_apply(c, 1, op, z, t, nrhs));
+    MG_TRY(mg_sub(c, vp, r, t, s, n1, nrhs));
+    for (int it = 0; it < p->kcycle_nu; ++it) {
+        MG_TRY(level_apply(c, 1, op, s, t, nrhs));
+        MG_TRY(mg_dot_norm(c, vp, t, s, n1, nrhs, S.s.cdn3()));
+        hipLaunchKernelGGL(k_alpha, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, S.s.cdn3(), S.s.alpha(),
+                           (double*)nullptr, (const int*)nullptr, nrhs);
+        if (it + 1 < p->kcycle_nu) MG_TRY(mg_mr_update(c, vp, S.s.alpha(), z, s, t, n1, nrhs));
+        else MG_TRY(mg_multiaxpy(c, vp, s, 0, 1, S.s.alpha(), 1.0, z, n1, nrhs));
+    }
+    S.coarse_applies += 1 + p->kcycle_nu;
+    HIP_TRY(hipGetLastError());
+    return MGLMA_OK;
+}
+
+static int coarse_kcycle(SolveCtx& S, int vp, int op, const void* b, void* x, int iters) {
+    mglma_ctx* c = S.c;
+    const mglma_solve_params* p = S.p;
+    const int nrhs = S.nrhs;
+    const size_t n = level_n(c, 1), vb = prec_cbytes(vp), setsz = (size_t)nrhs * n;
+    const int mc = iters < S.s.m ? iters : S.s.m;
+    const int opp = vp == MGLMA_F64 ? MGLMA_F64 : op;
+    // the level-2 GCR keeps its own scalars (the level-1 ones live across its calls)
+    SolveCtx S2;
+    S2.c = c; S2.p = p; S2.nrhs = nrhs; S2.level = 2;
+    S2.s.nrhs = nrhs;
+    S2.s.m = p->kcycle < 8 ? 8 : (p->kcycle > 32 ? 32 : p->kcycle);
+    MG_TRY(mg_scratch(c, WS_SCAL2, Scal::bytes(nrhs, S2.s.m), (void**)&S2.s.base));
+    void *P, *Q, *r;
+    MG_TRY(mg_scratch(c, WS_KP, (size_t)mc * setsz * vb, &P));
+    MG_TRY(mg_scratch(c, WS_KQ, (size_t)mc * setsz * vb, &Q));
+    MG_TRY(mg_scratch(c, WS_KR, setsz * vb, &r));
+    MG_TRY(mg_zero(c, x, setsz * vb));
+    MG_TRY(mg_copy(c, r, b, setsz * vb));
+    for (int k = 0; k < iters; ++k) {
+        const int j = k % mc;
+        char* pj = (char*)P + (size_t)j * setsz * vb;
+        char* qj = (char*)Q + (size_t)j * setsz * vb;
+        // p_j = B r, q_j = D_1 p_j, both orthogonalised against the cycle's
+        // earlier directions with beta_i = <q_i, q_j>/|q_i|^2; alpha = <q_j, r>/|q_j|^2
+        MG_TRY(kcycle_precondition(S, S2, vp, opp, r, pj));
+        MG_TRY(level_apply(c, 1, opp, pj, qj, nrhs));
+        S.coarse_applies++;
+        if (j > 0) MG_TRY(mg_multidot(c, vp, Q, setsz, j, qj, n, nrhs, S.s.cbeta(), S.s.cnw2()));
+        MG_TRY(mg_orth_step(c, vp, Q, P, setsz, j, S.s.cbeta(), qj, pj, nullptr, r, n, nrhs, S.s.calpha(),
+                            S.s.cnw2() + (size_t)j * nrhs, nullptr));
+        MG_TRY(mg_update_norm(c, vp, S.s.calpha(), x, pj, r, qj, n, nrhs, nullptr));
+    }
+    S.coarse_applies += S2.coarse_applies;
+    HIP_TRY(hipGetLastError());
     return MGLMA_OK;
 }
 
@@ -535,6 +622,8 @@ extern "C" int mglma_solve(mglma_ctx* c, const mglma_solve_params* p, const doub
     if (p->smoother_alg != MGLMA_SMOOTH_MR && p->smoother_alg != MGLMA_SMOOTH_CAGCR) return MGLMA_ERR_ARG;
     if (p->use_mg && p->smoother_alg == MGLMA_SMOOTH_CAGCR && (p->nu_post < 0 || p->nu_post > CA_K))
         return MGLMA_ERR_ARG;
+    if (p->kcycle < 0 || p->kcycle_nu < 0 || p->kcycle_nu > 16) return MGLMA_ERR_ARG;
+    if (p->use_mg && p->coarse_iters > 0 && p->kcycle > 0 && !c->have_l2) return MGLMA_ERR_NO_SUBSPACE;
     const int vp = p->inner == MGLMA_F64 ? MGLMA_F64 : MGLMA_F32;
     const size_t n = fine_n(c), setsz = (size_t)nrhs * n;
     SolveCtx S;
@@ -704,5 +793,7 @@ extern "C" int mglma_coarse_solve(mglma_ctx* c, const mglma_solve_params* p, con
     if (!c || !p || !b || !x || nrhs < 1 || nrhs > 65535) return MGLMA_ERR_ARG;
     if (!c->have_subspace) return MGLMA_ERR_NO_SUBSPACE;
     if (p->coarse_iters < 1 || p->max_outer < 1 || p->max_inner < 1) return MGLMA_ERR_ARG;
+    if (p->kcycle < 0 || p->kcycle_nu < 0 || p->kcycle_nu > 16) return MGLMA_ERR_ARG;
+    if (p->kcycle > 0 && !c->have_l2) return MGLMA_ERR_NO_SUBSPACE;
     return mg_coarse_solve(c, p, b, x, nrhs, stats);
 }

@@ -44,7 +44,7 @@ class SolveParams(C.Structure):
                 ("gcr_m", C.c_int), ("inner_tol", C.c_double), ("nu_post", C.c_int),
                 ("coarse_iters", C.c_int), ("smoother", C.c_int), ("inner", C.c_int),
                 ("coarse", C.c_int), ("use_mg", C.c_int), ("smoother_alg", C.c_int),
-                ("coarse_eo", C.c_int)]
+                ("coarse_eo", C.c_int), ("kcycle", C.c_int), ("kcycle_nu", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -100,7 +100,7 @@ def _ptr(t):
 def default_params(**kw):
     p = SolveParams(tol=1e-10, max_outer=12, max_inner=200, gcr_m=16, inner_tol=1e-5,
                     nu_post=4, coarse_iters=16, smoother=F32, inner=F32, coarse=F32, use_mg=1,
-                    smoother_alg=SMOOTH_MR, coarse_eo=1)
+                    smoother_alg=SMOOTH_MR, coarse_eo=1, kcycle=0, kcycle_nu=2)
     for k, v in kw.items():
         setattr(p, k, v)
     return p
@@ -240,7 +240,7 @@ class Context:
         n = b.shape[0]
         st = (SolveStats * max(n, 1))()
         _check(lib().mglma_level2_solve(self._ctx, C.byref(params or default_params()), _ptr(b), _ptr(x), n, st))
-        return [dict(outer=s.outer, inner=s.inner, true_rel_res=s.true_rel_res) for s in st[:n]]
+        return [dict(outer=s.outer, inner=s.inner, coarse=s.coarse, true_rel_res=s.true_rel_res) for s in st[:n]]
 
     def level2_pieces(self, eta, ge2, params=None):
         _check(lib().mglma_level2_pieces(self._ctx, C.byref(params or default_params()), _ptr(eta), _ptr(ge2),
@@ -276,7 +276,7 @@ class Context:
         n = b.shape[0]
         st = (SolveStats * max(n, 1))()
         _check(lib().mglma_coarse_solve(self._ctx, C.byref(params or default_params()), _ptr(b), _ptr(x), n, st))
-        return [dict(outer=s.outer, inner=s.inner, true_rel_res=s.true_rel_res) for s in st[:n]]
+        return [dict(outer=s.outer, inner=s.inner, coarse=s.coarse, true_rel_res=s.true_rel_res) for s in st[:n]]
 
     def coarse_pieces(self, eta, ge1, top=None, params=None):
         _check(lib().mglma_coarse_pieces(self._ctx, C.byref(params or default_params()), _ptr(eta),

@@ -121,6 +121,55 @@ def test_level2_pieces(lp):
     assert relerr(from_dev(ge2), ref) < 1e-9
 
 
+@pytest.mark.parametrize("vec", ["f32", "f64"])
+def test_kcycle_coarse_solve(lp, vec):
+    """The level-1 solve D_1 x = b with the K-cycle (flexible GCR on D_1, each
+    step preconditioned by R_1, GCR on D_2 and T_1 plus minimal-residual
+    smoothing on D_1) reaches the tolerance and the dense solution, and
+    needs fewer defect-correction rounds than plain GCR on D_1 with the
+    same number of steps per round."""
+    from paper_2412_06347_amd import mglma
+    ctx = lp.P.ctx
+    V1, nc = lp.P.bl.V1, lp.nc
+    A1 = coarse.coarse_dense(lp.P.D1, lp.P.nbr)
+    b = synth.gaussian_coarse(3, V1, nc, 36)
+    ref = np.linalg.solve(A1, b.reshape(3, -1).T).T.reshape(b.shape)
+    inner = mglma.F32 if vec == "f32" else mglma.F64
+    rounds = {}
+    for kc in (0, 4):
+        x = ctx.coarse(3)
+        p = mglma.default_params(tol=1e-11, inner=inner, coarse=mglma.BF16, coarse_iters=6, coarse_eo=0,
+                                 kcycle=kc, kcycle_nu=2, max_outer=100)
+        st = ctx.coarse_solve(to_dev(b), x, p)
+        assert max(s["true_rel_res"] for s in st) <= 1e-11
+        assert relerr(from_dev(x), ref) < 1e-8
+        # the residual under the oracle's stencil apply
+        xs = from_dev(x).reshape(3, -1)
+        res = np.linalg.norm(b.reshape(3, -1).T - A1 @ xs.T) / np.linalg.norm(b)
+        assert res < 1e-10
+        rounds[kc] = st[0]["outer"]
+    print("defect-correction rounds: plain GCR %d, K-cycle %d" % (rounds[0], rounds[4]))
+    assert rounds[4] <= rounds[0]
+
+
+def test_kcycle_fine_solve(lp):
+    """The fine MG solve with the K-cycle as the preconditioner's coarse
+    correction reaches 1e-10 against the oracle's operator."""
+    from paper_2412_06347_amd import mglma
+    P = lp.P
+    b = synth.gaussian_fields(2, P.L, 37)
+    x = P.ctx.fine(2)
+    p = mglma.default_params(tol=1e-10, inner=mglma.F32, coarse=mglma.BF16, coarse_iters=2, kcycle=3,
+                             kcycle_nu=1)
+    rc, st = P.ctx.solve(P.fine_dev(b), x, p)
+    assert max(s["true_rel_res"] for s in st) <= 1e-10
+    xs = P.fine_host(x)
+    r = P.canon(P.D.M(P.lat(xs))) - b
+    res = (np.linalg.norm(r.reshape(2, -1), axis=1) / np.linalg.norm(b.reshape(2, -1), axis=1)).max()
+    print("K-cycle MG solve: %d iterations, oracle residual %.2e" % (st[0]["inner"], res))
+    assert res < 2e-10
+
+
 def test_level2_arguments():
     import torch
     from paper_2412_06347_amd import mglma
@@ -134,6 +183,15 @@ def test_level2_arguments():
             P.ctx.build_level2(bad)
         assert e.value.code == -2
     assert P.ctx.V2 == 0
+    # the K-cycle needs level 2; out-of-range smoothing steps are rejected
+    b = torch.zeros((1, P.bl.V1, 4, 2), dtype=torch.float64, device="cuda")
+    for kw, code in ((dict(kcycle=2), -7), (dict(kcycle=2, kcycle_nu=17), -1), (dict(kcycle=-1), -1)):
+        with pytest.raises(mglma.MglmaError) as e:
+            P.ctx.coarse_solve(b, torch.zeros_like(b), mglma.default_params(**kw))
+        assert e.value.code == code, kw
+    with pytest.raises(mglma.MglmaError) as e:
+        P.ctx.solve(P.ctx.fine(1), P.ctx.fine(1), mglma.default_params(kcycle=2))
+    assert e.value.code == -7
 
 
 def test_four_level_point_pipeline():
