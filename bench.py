@@ -371,6 +371,67 @@ def hierarchy(wl, reps=3):
     }), flush=True)
 
 
+def setup_recipes(wl, reps=2):
+    """Test-vector preparation recipes on the bench workload (the basis should
+    span approximations of the low modes of Q, sec. "Local coherence and block
+    decomposition"): setup time and the 12 point-source MG solve that follows
+    (iterations, time), for Gaussian vectors as they are, the bench's recipe
+    (inverse iteration with unpreconditioned GCR) and the adaptive setup
+    (inverse iteration with the multigrid solver of the current subspace,
+    mglma_adaptive_setup)."""
+    import torch
+    from paper_2412_06347_amd import mglma, synth as synth_mod
+    L, Nv = wl["L"], wl["Nv"]
+    U = torch.from_numpy(synth_mod.gauge_field(L, wl["eps"], wl["seed"]).view(np.float64)).cuda()
+    ctx = mglma.Context(L, wl["block"], wl["kappa"], wl["csw"])
+    ctx.load_gauge(U)
+    src, x = ctx.fine(12), ctx.fine(12)
+    ctx.point_sources((0, 0, 0, 0), src)
+    plain = mglma.default_params(use_mg=0, inner=mglma.F32, max_outer=1, max_inner=40, gcr_m=16)
+
+    def fresh():
+        tv = ctx.fine(Nv)
+        ctx.import_fields(torch.from_numpy(synth_mod.gaussian_fields(Nv, L, wl["seed"] + 1000).view(np.float64))
+                          .cuda(), tv)
+        torch.cuda.synchronize()
+        return tv
+
+    def gaussian(tv):
+        ctx.build_subspace(tv)
+
+    def bench_recipe(tv):
+        # three rounds of 40 unpreconditioned FP32 GCR steps on M y = v, normalised
+        ctx.adaptive_setup(tv, plain, rounds=3, iters=40)
+
+    def adaptive(mg_rounds, mg_iters):
+        # one plain round of 20 steps, then multigrid rounds
+        def f(tv):
+            ctx.adaptive_setup(tv, plain, rounds=1, iters=20)
+            ctx.adaptive_setup(tv, mixed_params(mglma), rounds=mg_rounds, iters=mg_iters)
+        return f
+
+    out = {}
+    for name, f in (("gaussian", gaussian), ("inverse iteration, 3 x 40 plain GCR steps", bench_recipe),
+                    ("adaptive: 1 x 20 plain GCR steps, then 2 x 4 MG iterations", adaptive(2, 4)),
+                    ("adaptive: 1 x 20 plain GCR steps, then 3 x 6 MG iterations", adaptive(3, 6))):
+        ts, tsol = [], []
+        for _ in range(reps):
+            tv = fresh()
+            t0 = time.perf_counter()
+            f(tv)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+            t0 = time.perf_counter()
+            rc, st = ctx.solve(src, x, mixed_params(mglma, max_inner=400), raise_on_error=False)
+            torch.cuda.synchronize()
+            tsol.append(time.perf_counter() - t0)
+        out[name] = dict(setup_s=round(min(ts), 3), solve_ms=round(1e3 * min(tsol), 1), status=rc,
+                         iterations=max(q["inner"] for q in st), max_rel_res=max(q["true_rel_res"] for q in st))
+    print(json.dumps({"diagnostic": "test-vector setup recipes on the bench workload, then the 12-RHS MG solve",
+                      "workload": "%dx%d^3, %d^4 blocks, Nv=%d" % (L[0], L[1], wl["block"][0], Nv),
+                      "recipes": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -390,6 +451,9 @@ def main():
     ap.add_argument("--hier", action="store_true",
                     help="four-level hierarchy diagnostic instead of the bench: level-2 build and pieces timed, "
                          "level contributions of the point correlator")
+    ap.add_argument("--setup", action="store_true",
+                    help="test-vector setup diagnostic instead of the bench: Gaussian vectors, inverse iteration "
+                         "with plain GCR, adaptive setup with the multigrid solver; setup time and the MG solve")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one MI355X only: the hot path runs on a single GPU "
@@ -411,6 +475,9 @@ def main():
     wl = WORKLOADS[args.workload]
     if args.hier:
         hierarchy(wl)
+        return
+    if args.setup:
+        setup_recipes(wl)
         return
     if args.dslash_only:
         L = wl["L"]

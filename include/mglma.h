@@ -319,6 +319,21 @@ int mglma_fine_eigs(mglma_ctx* ctx, const mglma_eig_params* p, const double* ini
  * Synchronising.  Errors: NO_SUBSPACE, ARG, OOM, NONFINITE.                 */
 int mglma_deficit(mglma_ctx* ctx, int nrhs, const double* fine_dev, double* eps);
 
+/* Adaptive (bootstrap) refinement of the test vectors.  The block basis is
+ * meant to be spanned by approximations of the low modes of Q (sec. "Local
+ * coherence and block decomposition"); starting from any vectors, each of
+ * `rounds` rounds replaces v_c by y_c / |y_c|, where y_c is the result of
+ * `iters` inner iterations of the fine solver on M y_c = v_c with the
+ * settings of p (multigrid-preconditioned with the current subspace when
+ * p->use_mg, plain GCR otherwise; p->tol and p->inner_tol are ignored), and
+ * then rebuilds the subspace from the new vectors (mglma_build_subspace, so
+ * level 2 and the top level are dropped).  testvecs_dev: [Nv][V][12] complex
+ * F64 device layout, read and overwritten.  rounds = 0 does nothing.
+ * Synchronising.  Errors: ARG, NO_GAUGE, NO_SUBSPACE (use_mg without a
+ * subspace), NONFINITE, RANK, OOM.                                          */
+int mglma_adaptive_setup(mglma_ctx* ctx, const mglma_solve_params* p, double* testvecs_dev, int Nv,
+                         int rounds, int iters);
+
 /* ---- solves -------------------------------------------------------------- */
 /* x = M^{-1} b for nrhs fields (device layout, F64) to the true relative
  * residual p->tol.  Mixed precision: inner FGCR on p->inner vectors with the

@@ -22,6 +22,8 @@ enum { WS_DEFL = 31 }; // deflation coefficients of the even-odd coarse GCR
 // K-cycle: level-1 directions p, q and residual, level-2 right-hand side and
 // iterate, level-1 smoother vectors, the level-2 GCR's scalars
 enum { WS_KP = 32, WS_KQ, WS_KR, WS_K2, WS_KS, WS_SCAL2 };
+// adaptive setup: the approximate solutions and their norms
+enum { WS_ADAPT = 38, WS_ADAPT_N2 = 39 };
 
 // ---------------------------------------------------------------------------
 // scalar kernels (per right-hand side)
@@ -796,4 +798,50 @@ extern "C" int mglma_coarse_solve(mglma_ctx* c, const mglma_solve_params* p, con
     if (p->kcycle < 0 || p->kcycle_nu < 0 || p->kcycle_nu > 16) return MGLMA_ERR_ARG;
     if (p->kcycle > 0 && !c->have_l2) return MGLMA_ERR_NO_SUBSPACE;
     return mg_coarse_solve(c, p, b, x, nrhs, stats);
+}
+
+// ---------------------------------------------------------------------------
+// ABI: adaptive refinement of the test vectors (inverse iteration with the
+// current multigrid solver; rebuilds the subspace after every round)
+// ---------------------------------------------------------------------------
+__global__ void k_normalise(const double2* __restrict__ y, const double* __restrict__ n2, double2* __restrict__ v,
+                            size_t n) {
+    const int r = blockIdx.y;
+    const double sc = n2[r] > 0.0 ? 1.0 / sqrt(n2[r]) : 0.0;
+    const size_t off = (size_t)r * n;
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+        const double2 a = y[off + k];
+        v[off + k] = make_double2(a.x * sc, a.y * sc);
+    }
+}
+
+extern "C" int mglma_adaptive_setup(mglma_ctx* c, const mglma_solve_params* p, double* tv, int Nv, int rounds,
+                                    int iters) {
+    if (!c || !p || !tv || Nv < 1 || Nv > 64 || rounds < 0 || iters < 1) return MGLMA_ERR_ARG;
+    if (!c->have_gauge) return MGLMA_ERR_NO_GAUGE;
+    if (p->use_mg && !c->have_subspace) return MGLMA_ERR_NO_SUBSPACE;
+    const size_t n = fine_n(c);
+    // a fixed number of inner iterations: no tolerance, one defect-correction
+    // cycle; the level-2 K-cycle is not used (each rebuild drops level 2)
+    mglma_solve_params q = *p;
+    q.tol = 0.0;
+    q.inner_tol = 0.0;
+    q.max_outer = 1;
+    q.max_inner = iters;
+    q.kcycle = 0;
+    double2* y;
+    double* n2;
+    MG_TRY(mg_scratch(c, WS_ADAPT, (size_t)Nv * n * 16, (void**)&y));
+    MG_TRY(mg_scratch(c, WS_ADAPT_N2, (size_t)Nv * 8 + 256, (void**)&n2));
+    for (int k = 0; k < rounds; ++k) {
+        const int rc = mglma_solve(c, &q, tv, (double*)y, Nv, nullptr);
+        if (rc != MGLMA_OK && rc != MGLMA_ERR_NOT_CONVERGED) return rc;
+        MG_TRY(mg_norm2(c, MGLMA_F64, y, n, Nv, n2));
+        hipLaunchKernelGGL(k_normalise, dim3(1024, Nv), dim3(256), 0, c->stream, (const double2*)y, (const double*)n2,
+                           (double2*)tv, n);
+        HIP_TRY(hipGetLastError());
+        MG_TRY(mglma_build_subspace(c, Nv, tv));
+    }
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return MGLMA_OK;
 }

@@ -31,6 +31,7 @@ SYMBOLS = [
     "mglma_deficit", "mglma_coarse_schur_apply",
     "mglma_build_level2", "mglma_export_level2_op", "mglma_level2_restrict", "mglma_level2_prolong",
     "mglma_level2_apply", "mglma_level2_solve", "mglma_level2_pieces", "mglma_save", "mglma_load",
+    "mglma_adaptive_setup",
 ]
 
 
@@ -190,6 +191,12 @@ class Context:
     # ---- subspace ---------------------------------------------------------
     def build_subspace(self, testvecs):
         _check(lib().mglma_build_subspace(self._ctx, testvecs.shape[0], _ptr(testvecs)))
+
+    def adaptive_setup(self, testvecs, params=None, rounds=1, iters=8):
+        """Refine the test vectors in place (inverse iteration with the current
+        solver) and rebuild the subspace from them after every round."""
+        _check(lib().mglma_adaptive_setup(self._ctx, C.byref(params or default_params()), _ptr(testvecs),
+                                          testvecs.shape[0], int(rounds), int(iters)))
 
     def export_basis(self, out):
         _check(lib().mglma_export_basis(self._ctx, _ptr(out)))
