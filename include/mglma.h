@@ -94,7 +94,10 @@ typedef struct {
                             MGLMA_SMOOTH_CAGCR: one GCR step over the Krylov
                             space {s, M s, .., M^(nu_post-1) s}, its basis
                             built without reductions in between (one FP64
-                            Gram matrix per right-hand side)               */
+                            Gram matrix per right-hand side);
+                            MGLMA_SMOOTH_SAP: nu_post SAP cycles
+                            (mglma_sap_smooth; FP32 inner vectors, links in
+                            the smoother precision F16 or F32)            */
     int    coarse_eo;    /* 1: coarse GCR on the even-odd reduced system
                             S = 1 - D_ee^{-1} D_eo D_oo^{-1} D_oe when every
                             coarse extent is even, nc <= 64, the coarse
@@ -118,9 +121,11 @@ typedef struct {
                             effect on the level-2 solve.  0: off.         */
     int    kcycle_nu;    /* minimal-residual steps on D_1 after the level-2
                             correction of the K-cycle (0..16)               */
+    int    sap_mr;       /* MGLMA_SMOOTH_SAP: minimal-residual steps of each
+                            block solve (1..64)                             */
 } mglma_solve_params;
 
-enum { MGLMA_SMOOTH_MR = 0, MGLMA_SMOOTH_CAGCR = 1 };
+enum { MGLMA_SMOOTH_MR = 0, MGLMA_SMOOTH_CAGCR = 1, MGLMA_SMOOTH_SAP = 2 };
 
 typedef struct {
     int    outer;        /* defect-correction cycles done                      */
@@ -333,6 +338,23 @@ int mglma_deficit(mglma_ctx* ctx, int nrhs, const double* fine_dev, double* eps)
  * subspace), NONFINITE, RANK, OOM.                                          */
 int mglma_adaptive_setup(mglma_ctx* ctx, const mglma_solve_params* p, double* testvecs_dev, int Nv,
                          int rounds, int iters);
+
+/* Schwarz alternating procedure on M z = r (the smoother of the paper's
+ * fine solver, sec. "Comparison of the cost"): the aggregation blocks are
+ * coloured like a chessboard (parity of y_0+y_1+y_2+y_3); one cycle visits
+ * the blocks of colour 0, then of colour 1, and each visited block adds to z
+ * the result of nmr minimal-residual steps (from zero) on M_BB d = rho_B,
+ * where rho = r - M z is formed on the block's sites when the colour starts
+ * and M_BB couples the block's sites only (hops that leave the block are
+ * dropped; a hop that wraps back into the block, when the block spans a
+ * whole extent, keeps its boundary phase).  r_dev, z_dev: [nrhs][12][V]
+ * complex FP32 device layout (mglma_import_fields with F32); z is read as
+ * the start and overwritten.  Links and clover: the FP16 (prec F16) or FP32
+ * (prec F32) copies.  Needs every block-grid extent L_mu/b_mu even or one
+ * and at most 256 sites per block.  Asynchronous.  Errors: ARG, NO_GAUGE,
+ * SHAPE (block grid or block size), OOM.                                   */
+int mglma_sap_smooth(mglma_ctx* ctx, int prec, int ncycle, int nmr, const float* r_dev, float* z_dev,
+                     int nrhs);
 
 /* ---- solves -------------------------------------------------------------- */
 /* x = M^{-1} b for nrhs fields (device layout, F64) to the true relative

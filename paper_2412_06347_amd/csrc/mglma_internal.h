@@ -292,6 +292,10 @@ struct mglma_ctx {
     bool have_top = false;
 
     // reusable scratch (grown on demand) and reduction buffers
+    // SAP smoother: block indices ordered by colour, number of colour-0 blocks
+    int* sap_blk = nullptr;
+    int sap_n0 = 0;
+
     static constexpr int NSCR = 40;
     Scratch scr[NSCR];
     double* red_part = nullptr; size_t red_part_n = 0;
@@ -359,6 +363,10 @@ int mg_coarse_solve(mglma_ctx* c, const mglma_solve_params* p, const double* b, 
                     mglma_solve_stats* stats, int level = 1);
 // level-1 <-> level-2 coarse fields (aggregation with weight sqrt(V2/V1)); F64 or F32
 int mg_l2_restrict(mglma_ctx* c, int prec, const void* in1, void* out2, int nrhs);
+// SAP smoother: ncycle cycles on M z = r (FP32 vectors, z in place), links and
+// clover from the FP16 (prec F16) or FP32 copies; setup checks the geometry
+int mg_sap_setup(mglma_ctx* c);
+int mg_sap(mglma_ctx* c, int prec, const void* r, void* z, int nrhs, int ncycle, int nmr);
 int mg_l2_prolong(mglma_ctx* c, int prec, const void* in2, void* out1, int nrhs);
 
 // even-odd reduced coarse operator; vectors on one parity are compressed,

@@ -1,0 +1,289 @@
+// Schwarz alternating procedure (SAP) smoother on M z = r (the paper's fine
+// solver is SAP-preconditioned GCR, section "Comparison of the cost", after
+// Luscher 2003).  The aggregation blocks are coloured like a chessboard
+// (colour = parity of y_0 + y_1 + y_2 + y_3); a cycle updates the blocks of
+// colour 0, then those of colour 1.  A block update forms the residual
+// rho = r - M z on the block's sites, makes nmr minimal-residual steps on
+// M_BB d = rho_B (M_BB: all couplings between two sites of the block,
+// including the hop that wraps around the lattice when the block spans a
+// whole extent) and adds d to z.
+//
+// One workgroup per (block, right-hand side), one thread per block site.
+// The block's iterate of the minimal-residual steps lives in LDS
+// (12 complex FP32 per site); links and clover come from the FP16 or FP32
+// copies, vectors are FP32.  Blocks of one colour do not couple when every
+// block-grid extent is even or one, so one launch per colour updates them
+// all without ordering between workgroups.
+#include "mglma_internal.h"
+#include "wilson.h"
+
+#include <vector>
+
+namespace {
+
+constexpr int SAP_MAXVB = 256;
+
+// acc += (1 -/+ gamma_mu) U p for one hop whose neighbour spinor p is loaded;
+// link U_mu(x) at site ls for the forward hop, U_mu(x-mu)^+ at ls for the backward
+template <int MU, bool FWD, typename G>
+__device__ __forceinline__ void sap_hop(const cx<float> p[12], bool neg, const G* __restrict__ U, size_t V, int ls,
+                                        cx<float> acc[12]) {
+    cx<float> h[6];
+    project<MU, FWD, float>(p, h);
+    if (neg) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) h[k] = -h[k];
+    }
+    const G* ul = U + (size_t)(MU * 9) * V + ls;
+    cx<float> u[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) u[e] = ldc<G, float>(ul + (size_t)e * V);
+    cx<float> o[6];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cx<float> t = cmk(0.f, 0.f);
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                if (FWD) cmac(t, u[a * 3 + b], h[s * 3 + b]);
+                else cjmac(t, u[b * 3 + a], h[s * 3 + b]);
+            }
+            o[s * 3 + a] = t;
+        }
+    reconstruct_add<MU, FWD, float>(acc, o);
+}
+
+// hop of the full operator: neighbour read from the global field
+template <int MU, bool FWD, typename G>
+__device__ __forceinline__ void sap_hop_global(const Geo& g, int i, const int lc[4], const int yc[4],
+                                               const float2* __restrict__ f, const G* __restrict__ U,
+                                               cx<float> acc[12]) {
+    bool wrap;
+    const int j = FWD ? geo_fwd(g, i, MU, lc, yc, &wrap) : geo_bwd(g, i, MU, lc, yc, &wrap);
+    cx<float> p[12];
+#pragma unroll
+    for (int sc = 0; sc < 12; ++sc) p[sc] = ldc<float2, float>(f + (size_t)sc * g.V + j);
+    sap_hop<MU, FWD, G>(p, wrap && g.bcneg[MU], U, g.V, FWD ? i : j, acc);
+}
+
+// hop of the block operator M_BB: neighbour read from the LDS copy of the
+// block's field; hops that leave the block are dropped, a hop that wraps
+// back into the block (block-grid extent one) keeps its boundary phase
+template <int MU, bool FWD, typename G>
+__device__ __forceinline__ void sap_hop_block(const Geo& g, int blk, int l, const int lc[4],
+                                              const float2* __restrict__ sh, const G* __restrict__ U,
+                                              cx<float> acc[12]) {
+    int jl;
+    bool neg = false;
+    if (FWD) {
+        if (lc[MU] + 1 < g.b[MU]) jl = l + g.sl[MU];
+        else if (g.L1[MU] == 1) { jl = l - (g.b[MU] - 1) * g.sl[MU]; neg = g.bcneg[MU] != 0; }
+        else return;
+    } else {
+        if (lc[MU] > 0) jl = l - g.sl[MU];
+        else if (g.L1[MU] == 1) { jl = l + (g.b[MU] - 1) * g.sl[MU]; neg = g.bcneg[MU] != 0; }
+        else return;
+    }
+    // with b_mu = 1 and a block-grid extent one the site is its own neighbour
+    cx<float> p[12];
+#pragma unroll
+    for (int sc = 0; sc < 12; ++sc) {
+        const float2 v = sh[sc * SAP_MAXVB + jl];
+        p[sc] = cmk(v.x, v.y);
+    }
+    sap_hop<MU, FWD, G>(p, neg, U, g.V, FWD ? blk * g.Vb + l : blk * g.Vb + jl, acc);
+}
+
+// sum of three values over the workgroup (every thread gets the totals)
+__device__ __forceinline__ void sap_reduce3(float& a, float& b, float& c, float* red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o, 64);
+        b += __shfl_xor(b, o, 64);
+        c += __shfl_xor(c, o, 64);
+    }
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0) { red[3 * w] = a; red[3 * w + 1] = b; red[3 * w + 2] = c; }
+    __syncthreads();
+    a = b = c = 0.f;
+    for (int k = 0; k < nw; ++k) { a += red[3 * k]; b += red[3 * k + 1]; c += red[3 * k + 2]; }
+}
+
+template <typename G>
+__global__ __launch_bounds__(256) void k_sap_half(Geo g, const float2* __restrict__ rhs, float2* __restrict__ z,
+                                                  const G* __restrict__ U, const G* __restrict__ C, float kappa,
+                                                  const int* __restrict__ blist, int nblk, int nrhs, int npad,
+                                                  int nmr) {
+    __shared__ float2 sh[12 * SAP_MAXVB];
+    __shared__ float red[3 * (SAP_MAXVB / 64)];
+    // (block, rhs) items dealt to the XCDs in contiguous ranges, the right-hand
+    // sides of one block back to back on one XCD (its links read once)
+    const int bid = blockIdx.x, xcd = bid & 7, pos = bid >> 3;
+    const int item = xcd * (npad >> 3) + pos;
+    if (item >= nblk * nrhs) return;   // uniform over the workgroup
+    const int kb = item / nrhs, q = item - kb * nrhs;
+    const int blk = blist[kb];
+    const int l = threadIdx.x;
+    const bool on = l < g.Vb;
+    const int i = blk * g.Vb + l;
+    const size_t V = g.V;
+    const float2* pr = rhs + (size_t)q * 12 * V;
+    float2* pz = z + (size_t)q * 12 * V;
+    int lc[4] = {0, 0, 0, 0}, yc[4] = {0, 0, 0, 0};
+    if (on) geo_coords(g, i, lc, yc);
+
+    // rho = r - M z on the block's sites
+    cx<float> s[12];
+    if (on) {
+        cx<float> acc[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = cmk(0.f, 0.f);
+        sap_hop_global<0, true, G>(g, i, lc, yc, pz, U, acc);
+        sap_hop_global<0, false, G>(g, i, lc, yc, pz, U, acc);
+        sap_hop_global<1, true, G>(g, i, lc, yc, pz, U, acc);
+        sap_hop_global<1, false, G>(g, i, lc, yc, pz, U, acc);
+        sap_hop_global<2, true, G>(g, i, lc, yc, pz, U, acc);
+        sap_hop_global<2, false, G>(g, i, lc, yc, pz, U, acc);
+        sap_hop_global<3, true, G>(g, i, lc, yc, pz, U, acc);
+        sap_hop_global<3, false, G>(g, i, lc, yc, pz, U, acc);
+#pragma unroll
+        for (int ch = 0; ch < 2; ++ch) {
+            cx<float> p[6], res[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) p[k] = ldc<float2, float>(pz + (size_t)(6 * ch + k) * V + i);
+            clover_block<G, float>(C + (size_t)ch * 18 * V, V, i, p, res);
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                s[6 * ch + k] = ldc<float2, float>(pr + (size_t)(6 * ch + k) * V + i) - (res[k] - kappa * acc[6 * ch + k]);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) s[k] = cmk(0.f, 0.f);
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) sh[k * SAP_MAXVB + l] = make_float2(s[k].re, s[k].im);
+    cx<float> d[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) d[k] = cmk(0.f, 0.f);
+
+    // minimal-residual steps on M_BB d = rho_B: t = M_BB s, omega = <t,s>/<t,t>
+    for (int it = 0; it < nmr; ++it) {
+        __syncthreads();
+        cx<float> t[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) t[k] = cmk(0.f, 0.f);
+        if (on) {
+            sap_hop_block<0, true, G>(g, blk, l, lc, sh, U, t);
+            sap_hop_block<0, false, G>(g, blk, l, lc, sh, U, t);
+            sap_hop_block<1, true, G>(g, blk, l, lc, sh, U, t);
+            sap_hop_block<1, false, G>(g, blk, l, lc, sh, U, t);
+            sap_hop_block<2, true, G>(g, blk, l, lc, sh, U, t);
+            sap_hop_block<2, false, G>(g, blk, l, lc, sh, U, t);
+            sap_hop_block<3, true, G>(g, blk, l, lc, sh, U, t);
+            sap_hop_block<3, false, G>(g, blk, l, lc, sh, U, t);
+#pragma unroll
+            for (int ch = 0; ch < 2; ++ch) {
+                cx<float> res[6];
+                clover_block<G, float>(C + (size_t)ch * 18 * V, V, i, s + 6 * ch, res);
+#pragma unroll
+                for (int k = 0; k < 6; ++k) t[6 * ch + k] = res[k] - kappa * t[6 * ch + k];
+            }
+        }
+        float are = 0.f, aim = 0.f, tt = 0.f;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            are += t[k].re * s[k].re + t[k].im * s[k].im;
+            aim += t[k].re * s[k].im - t[k].im * s[k].re;
+            tt += t[k].re * t[k].re + t[k].im * t[k].im;
+        }
+        sap_reduce3(are, aim, tt, red);   // also orders this step's LDS reads before the writes below
+        const cx<float> om = tt > 0.f ? cmk(are / tt, aim / tt) : cmk(0.f, 0.f);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            cmac(d[k], om, s[k]);
+            s[k] = s[k] - om * t[k];
+            sh[k * SAP_MAXVB + l] = make_float2(s[k].re, s[k].im);
+        }
+    }
+    __syncthreads();   // every residual read of z (own block included) before the update
+    if (on) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            float2* a = pz + (size_t)k * V + i;
+            const float2 v = *a;
+            *a = make_float2(v.x + d[k].re, v.y + d[k].im);
+        }
+    }
+}
+
+}  // namespace
+
+// Block order by colour (lazy; depends on the geometry only).  SAP needs
+// every block-grid extent even or one (then blocks of one colour never
+// couple) and at most 256 sites per block.
+int mg_sap_setup(mglma_ctx* c) {
+    if (c->sap_blk) return MGLMA_OK;
+    const Geo& g = c->geo;
+    for (int mu = 0; mu < 4; ++mu)
+        if (g.L1[mu] != 1 && g.L1[mu] % 2) return MGLMA_ERR_SHAPE;
+    if (g.Vb > SAP_MAXVB) return MGLMA_ERR_SHAPE;
+    std::vector<int> order;
+    order.reserve(g.V1);
+    int n0 = 0;
+    for (int colour = 0; colour < 2; ++colour) {
+        if (colour == 1) n0 = (int)order.size();
+        for (int y = 0; y < g.V1; ++y) {
+            int k = y, par = 0;
+            for (int mu = 3; mu >= 0; --mu) {
+                par += k % g.L1[mu];
+                k /= g.L1[mu];
+            }
+            if (par % 2 == colour) order.push_back(y);
+        }
+    }
+    int* d = nullptr;
+    MG_TRY(mg_malloc(c, (void**)&d, (size_t)g.V1 * sizeof(int)));
+    HIP_TRY(hipMemcpyAsync(d, order.data(), (size_t)g.V1 * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->sap_blk = d;
+    c->sap_n0 = n0;
+    return MGLMA_OK;
+}
+
+// ncycle SAP cycles on M z = r (FP32 vectors, z updated in place); links and
+// clover from the FP16 (prec F16) or FP32 (prec F32) copies
+int mg_sap(mglma_ctx* c, int prec, const void* r, void* z, int nrhs, int ncycle, int nmr) {
+    if (nrhs == 0 || ncycle == 0) return MGLMA_OK;
+    MG_TRY(mg_sap_setup(c));
+    const Geo& g = c->geo;
+    const int nthr = (g.Vb + 63) / 64 * 64;
+    for (int cyc = 0; cyc < ncycle; ++cyc)
+        for (int colour = 0; colour < 2; ++colour) {
+            const int nblk = colour == 0 ? c->sap_n0 : g.V1 - c->sap_n0;
+            if (nblk == 0) continue;
+            const int* bl = c->sap_blk + (colour == 0 ? 0 : c->sap_n0);
+            const long long nitem = (long long)nblk * nrhs;
+            const long long npad = (nitem + 7) / 8 * 8;
+            if (npad > 0x7fffffffLL) return MGLMA_ERR_SHAPE;
+            if (prec == MGLMA_F16)
+                hipLaunchKernelGGL((k_sap_half<__half2>), dim3((unsigned)npad), dim3(nthr), 0, c->stream, g,
+                                   (const float2*)r, (float2*)z, (const __half2*)c->U16, (const __half2*)c->C16,
+                                   (float)c->kappa, bl, nblk, nrhs, (int)npad, nmr);
+            else
+                hipLaunchKernelGGL((k_sap_half<float2>), dim3((unsigned)npad), dim3(nthr), 0, c->stream, g,
+                                   (const float2*)r, (float2*)z, (const float2*)c->U32, (const float2*)c->C32,
+                                   (float)c->kappa, bl, nblk, nrhs, (int)npad, nmr);
+            HIP_TRY(hipGetLastError());
+        }
+    return MGLMA_OK;
+}
+
+extern "C" int mglma_sap_smooth(mglma_ctx* c, int prec, int ncycle, int nmr, const float* r_dev, float* z_dev,
+                                int nrhs) {
+    if (!c || !r_dev || !z_dev || nrhs < 0 || nrhs > 65535 || ncycle < 0 || nmr < 0 || nmr > 64)
+        return MGLMA_ERR_ARG;
+    if (prec != MGLMA_F16 && prec != MGLMA_F32) return MGLMA_ERR_ARG;
+    if (!c->have_gauge) return MGLMA_ERR_NO_GAUGE;
+    return mg_sap(c, prec, r_dev, z_dev, nrhs, ncycle, nmr);
+}

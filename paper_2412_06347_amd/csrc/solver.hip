@@ -460,6 +460,8 @@ static int precondition(SolveCtx& S, int vp, const void* r, void* z) {
         MG_TRY(mg_zero(c, z, (size_t)nrhs * n * vb));
     }
     if (p->nu_post <= 0) return MGLMA_OK;
+    if (p->smoother_alg == MGLMA_SMOOTH_SAP)
+        return mg_sap(c, p->smoother == MGLMA_F16 ? MGLMA_F16 : MGLMA_F32, r, z, nrhs, p->nu_post, p->sap_mr);
     // MR smoothing on M z = r: s = r - M z; t = M s; omega = <t,s>/<t,t>; z += omega s; s -= omega t
     const int sp = (vp == MGLMA_F32 && p->smoother == MGLMA_F16) ? MGLMA_F16 : vp;
     if (p->smoother_alg == MGLMA_SMOOTH_CAGCR && sp == MGLMA_F16) {
@@ -621,7 +623,14 @@ extern "C" int mglma_solve(mglma_ctx* c, const mglma_solve_params* p, const doub
     if (!c->have_gauge) return MGLMA_ERR_NO_GAUGE;
     if (p->use_mg && !c->have_subspace) return MGLMA_ERR_NO_SUBSPACE;
     if (p->gcr_m < 1 || p->gcr_m > 32 || p->max_inner < 1 || p->max_outer < 1) return MGLMA_ERR_ARG;
-    if (p->smoother_alg != MGLMA_SMOOTH_MR && p->smoother_alg != MGLMA_SMOOTH_CAGCR) return MGLMA_ERR_ARG;
+    if (p->smoother_alg != MGLMA_SMOOTH_MR && p->smoother_alg != MGLMA_SMOOTH_CAGCR &&
+        p->smoother_alg != MGLMA_SMOOTH_SAP)
+        return MGLMA_ERR_ARG;
+    if (p->use_mg && p->smoother_alg == MGLMA_SMOOTH_SAP && p->nu_post > 0) {
+        // FP32 vectors; the geometry check and block order once per context
+        if (p->inner != MGLMA_F32 || p->sap_mr < 1 || p->sap_mr > 64) return MGLMA_ERR_ARG;
+        MG_TRY(mg_sap_setup(c));
+    }
     if (p->use_mg && p->smoother_alg == MGLMA_SMOOTH_CAGCR && (p->nu_post < 0 || p->nu_post > CA_K))
         return MGLMA_ERR_ARG;
     if (p->kcycle < 0 || p->kcycle_nu < 0 || p->kcycle_nu > 16) return MGLMA_ERR_ARG;

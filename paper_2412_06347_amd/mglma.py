@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmglma.so")
 
 F64, F32, F16, BF16 = 0, 1, 2, 3
-SMOOTH_MR, SMOOTH_CAGCR = 0, 1
+SMOOTH_MR, SMOOTH_CAGCR, SMOOTH_SAP = 0, 1, 2
 
 SYMBOLS = [
     "mglma_create", "mglma_destroy", "mglma_set_stream", "mglma_strerror", "mglma_query",
@@ -31,7 +31,7 @@ SYMBOLS = [
     "mglma_deficit", "mglma_coarse_schur_apply",
     "mglma_build_level2", "mglma_export_level2_op", "mglma_level2_restrict", "mglma_level2_prolong",
     "mglma_level2_apply", "mglma_level2_solve", "mglma_level2_pieces", "mglma_save", "mglma_load",
-    "mglma_adaptive_setup",
+    "mglma_adaptive_setup", "mglma_sap_smooth",
 ]
 
 
@@ -45,7 +45,8 @@ class SolveParams(C.Structure):
                 ("gcr_m", C.c_int), ("inner_tol", C.c_double), ("nu_post", C.c_int),
                 ("coarse_iters", C.c_int), ("smoother", C.c_int), ("inner", C.c_int),
                 ("coarse", C.c_int), ("use_mg", C.c_int), ("smoother_alg", C.c_int),
-                ("coarse_eo", C.c_int), ("kcycle", C.c_int), ("kcycle_nu", C.c_int)]
+                ("coarse_eo", C.c_int), ("kcycle", C.c_int), ("kcycle_nu", C.c_int),
+                ("sap_mr", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -101,7 +102,7 @@ def _ptr(t):
 def default_params(**kw):
     p = SolveParams(tol=1e-10, max_outer=12, max_inner=200, gcr_m=16, inner_tol=1e-5,
                     nu_post=4, coarse_iters=16, smoother=F32, inner=F32, coarse=F32, use_mg=1,
-                    smoother_alg=SMOOTH_MR, coarse_eo=1, kcycle=0, kcycle_nu=2)
+                    smoother_alg=SMOOTH_MR, coarse_eo=1, kcycle=0, kcycle_nu=2, sap_mr=4)
     for k, v in kw.items():
         setattr(p, k, v)
     return p
@@ -197,6 +198,10 @@ class Context:
         solver) and rebuild the subspace from them after every round."""
         _check(lib().mglma_adaptive_setup(self._ctx, C.byref(params or default_params()), _ptr(testvecs),
                                           testvecs.shape[0], int(rounds), int(iters)))
+
+    def sap_smooth(self, r, z, ncycle=1, nmr=4, prec=F16):
+        """ncycle SAP cycles on M z = r (FP32 device fields, z in place)."""
+        _check(lib().mglma_sap_smooth(self._ctx, prec, int(ncycle), int(nmr), _ptr(r), _ptr(z), r.shape[0]))
 
     def export_basis(self, out):
         _check(lib().mglma_export_basis(self._ctx, _ptr(out)))

@@ -1,0 +1,90 @@
+"""GPU parity of the SAP smoother (the smoother of the paper's fine solver,
+sec. "Comparison of the cost") against the oracle's SAP cycles, and the
+multigrid solve with SAP smoothing against the oracle's operator."""
+import numpy as np
+import pytest
+
+from oracle import dirac, subspace, sap
+from paper_2412_06347_amd import synth
+from tests.gpu_util import relerr
+from tests.gpu_setup import Pair
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # L, block: block grids (2,1,1,2) with 2^4 blocks, (2,2,2,4), and (2,1,1,2) with 4^4 blocks
+    ((4, 2, 2, 4), (2, 2, 2, 2)),
+    ((4, 4, 4, 8), (2, 2, 2, 2)),
+    ((8, 4, 4, 8), (4, 4, 4, 4)),
+]
+
+
+@pytest.fixture(scope="module", params=CASES, ids=["2^4_ext1", "2^4", "4^4_ext1"])
+def pair(request):
+    L, b = request.param
+    return Pair(L, b, 2, kappa=0.124, oracle_galerkin=False)
+
+
+@pytest.mark.parametrize("prec,tol", [(1, 2e-6), (2, 5e-3)], ids=["f32", "f16"])
+def test_sap_cycles_parity(pair, prec, tol):
+    from paper_2412_06347_amd import mglma
+    nrhs, ncycle, nmr = 2, 2, 4
+    r = synth.gaussian_fields(nrhs, pair.L, 51)
+    z0 = 0.1 * synth.gaussian_fields(nrhs, pair.L, 52)
+    rd, zd = pair.fine_dev(r, mglma.F32), pair.fine_dev(z0, mglma.F32)
+    pair.ctx.sap_smooth(rd, zd, ncycle=ncycle, nmr=nmr, prec=prec)
+    got = pair.fine_host(zd, mglma.F32)
+    bl = subspace.Blocking(pair.L, pair.b)
+    ref = []
+    for q in range(nrhs):
+        z = pair.lat(z0)[q]
+        for _ in range(ncycle):
+            z = sap.sap_cycle(pair.D, bl, pair.lat(r)[q], z, nmr)
+        ref.append(z)
+    ref = pair.canon(np.stack(ref))
+    e = relerr(got, ref)
+    print("SAP %d cycles, %d MR steps, prec %d: rel. error %.2e" % (ncycle, nmr, prec, e))
+    assert e < tol
+
+
+def test_sap_smoothed_solve(pair):
+    from paper_2412_06347_amd import mglma
+    b = synth.gaussian_fields(2, pair.L, 53)
+    for sm in (mglma.F32, mglma.F16):
+        x = pair.ctx.fine(2)
+        p = mglma.default_params(tol=1e-10, inner=mglma.F32, coarse=mglma.BF16, smoother=sm,
+                                 smoother_alg=mglma.SMOOTH_SAP, nu_post=1, sap_mr=4)
+        rc, st = pair.ctx.solve(pair.fine_dev(b), x, p)
+        xs = pair.fine_host(x)
+        r = pair.canon(pair.D.M(pair.lat(xs))) - b
+        res = (np.linalg.norm(r.reshape(2, -1), axis=1) / np.linalg.norm(b.reshape(2, -1), axis=1)).max()
+        print("SAP-smoothed MG solve (smoother prec %d): %d iterations, oracle residual %.2e"
+              % (sm, st[0]["inner"], res))
+        assert rc == 0 and res < 1.05e-10
+
+
+def test_sap_arguments():
+    import torch
+    from paper_2412_06347_amd import mglma
+    P = Pair((6, 4, 4, 4), (2, 2, 2, 2), 2, oracle_galerkin=False)   # block grid (3,2,2,2): odd extent
+    r = P.ctx.fine(1, mglma.F32)
+    z = P.ctx.fine(1, mglma.F32)
+    with pytest.raises(mglma.MglmaError) as e:
+        P.ctx.sap_smooth(r, z)
+    assert e.value.code == -2
+    with pytest.raises(mglma.MglmaError) as e:
+        P.ctx.solve(P.ctx.fine(1), P.ctx.fine(1), mglma.default_params(smoother_alg=mglma.SMOOTH_SAP))
+    assert e.value.code == -2
+    Q = Pair((4, 4, 4, 4), (2, 2, 2, 2), 2, oracle_galerkin=False)
+    r = Q.ctx.fine(1, mglma.F32)
+    z = Q.ctx.fine(1, mglma.F32)
+    for kw in (dict(prec=mglma.F64), dict(nmr=65), dict(ncycle=-1)):
+        with pytest.raises(mglma.MglmaError) as e:
+            Q.ctx.sap_smooth(r, z, **kw)
+        assert e.value.code == -1
+    for kw in (dict(inner=mglma.F64), dict(sap_mr=0)):
+        with pytest.raises(mglma.MglmaError) as e:
+            Q.ctx.solve(Q.ctx.fine(1), Q.ctx.fine(1), mglma.default_params(smoother_alg=mglma.SMOOTH_SAP, **kw))
+        assert e.value.code == -1
+    # no right-hand sides: nothing to do (pointers still valid)
+    assert mglma.lib().mglma_sap_smooth(Q.ctx._ctx, mglma.F16, 1, 4, mglma._ptr(r), mglma._ptr(z), 0) == 0
