@@ -39,9 +39,9 @@ def log(*a):
 
 
 def mixed_params(mglma, **kw):
-    p = dict(tol=1e-10, max_outer=10, max_inner=120, gcr_m=4, inner_tol=1e-5, nu_post=6, coarse_iters=4,
-             smoother=mglma.F16, inner=mglma.F32, coarse=mglma.BF16, use_mg=1, smoother_alg=mglma.SMOOTH_CAGCR,
-             coarse_eo=1)
+    p = dict(tol=1e-10, max_outer=10, max_inner=120, gcr_m=8, inner_tol=1e-5, nu_post=2, sap_mr=4,
+             coarse_iters=4, smoother=mglma.F16, inner=mglma.F32, coarse=mglma.BF16, use_mg=1,
+             smoother_alg=mglma.SMOOTH_SAP, coarse_eo=1)
     p.update(kw)
     return mglma.default_params(**p)
 
@@ -144,6 +144,46 @@ def measured_traffic(workload):
     if hashlib.sha256(src).hexdigest() != rec.get("dslash_source_sha256"):
         return None
     return rec.get("f16_12rhs_hbm_bytes_per_launch")
+
+
+# FP32 peak without packed FP32 instructions (the library is built without
+# them): 256 CUs x 64 FP32 FMA lanes x 2 flop x 2.4 GHz
+FP32_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+
+# flops per site and right-hand side: one Wilson-clover apply 1824 (clover
+# 504, each of the 8 hops 165), the minimal-residual vector work of one SAP
+# block step 336 (<t,s>, <t,t>, d += omega s, s -= omega t), the residual
+# subtraction 24
+HOP_FLOPS, CLOVER_FLOPS, MR_VEC_FLOPS, RESID_FLOPS = 165, 504, 336, 24
+
+
+def sap_alg_flops(V, block, L, nrhs, nmr):
+    """Algorithmic flops of one SAP half-sweep launch (the blocks of one
+    colour: V/2 sites): per site and right-hand side the residual
+    r - M z (a full apply) and nmr block steps (the block operator keeps the
+    hops that stay inside the block: 2 (b_mu - 1) / b_mu per direction on
+    average, 2 when the block spans the extent)."""
+    hops = sum(2.0 if L[mu] == block[mu] else 2.0 * (block[mu] - 1) / block[mu] for mu in range(4))
+    per_site = (8 * HOP_FLOPS + CLOVER_FLOPS + RESID_FLOPS
+                + nmr * (hops * HOP_FLOPS + CLOVER_FLOPS + MR_VEC_FLOPS))
+    return V / 2 * nrhs * per_site
+
+
+def measured_sap_traffic(workload):
+    """HBM bytes per SAP half-sweep launch (FP16 links, 12 RHS) from the
+    committed hardware-counter summary, or None when the kernel source has
+    changed since the counters were taken."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", "sap_traffic_%s.json" % workload)
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    csrc = os.path.join(here, "paper_2412_06347_amd", "csrc")
+    src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("sap.hip", "wilson.h"))
+    if hashlib.sha256(src).hexdigest() != rec.get("sap_source_sha256"):
+        return None
+    return rec.get("hbm_bytes_per_launch")
 
 
 def kernel_time(torch, fn, reps, stream):
@@ -451,6 +491,8 @@ def main():
     ap.add_argument("--hier", action="store_true",
                     help="four-level hierarchy diagnostic instead of the bench: level-2 build and pieces timed, "
                          "level contributions of the point correlator")
+    ap.add_argument("--sap-only", action="store_true",
+                    help="only run SAP smoother cycles of the workload (for hardware-counter runs)")
     ap.add_argument("--setup", action="store_true",
                     help="test-vector setup diagnostic instead of the bench: Gaussian vectors, inverse iteration "
                          "with plain GCR, adaptive setup with the multigrid solver; setup time and the MG solve")
@@ -478,6 +520,21 @@ def main():
         return
     if args.setup:
         setup_recipes(wl)
+        return
+    if args.sap_only:
+        # the SAP smoother of the step (FP16 links, 12 RHS, the bench's block
+        # steps), 5 cycles = 10 half-sweep launches, for hardware-counter runs
+        L = wl["L"]
+        U = torch.from_numpy(synth.gauge_field(L, wl["eps"], wl["seed"]).view(np.float64)).cuda()
+        ctx = mglma.Context(L, wl["block"], wl["kappa"], wl["csw"])
+        ctx.load_gauge(U)
+        r, z = ctx.fine(12, mglma.F32), ctx.fine(12, mglma.F32)
+        r.copy_(torch.randn(r.shape, device="cuda"))
+        z.zero_()
+        nmr = mixed_params(mglma).sap_mr
+        ctx.sap_smooth(r, z, 5, nmr, mglma.F16)
+        torch.cuda.synchronize()
+        print(json.dumps({"sap_only": True, "V": ctx.V, "launches": "10 SAP half-sweeps, 12 rhs, %d block steps" % nmr}))
         return
     if args.dslash_only:
         L = wl["L"]
@@ -525,11 +582,20 @@ def main():
                     corr_L0_rel_diff_vs_mixed=float(np.linalg.norm(lv64["L0"] - levels["L0"]) /
                                                     np.linalg.norm(lv64["L0"])))
         log("fp64: %.3f s/step" % t64)
-    # Dominant kernel of the step: the FP16 Wilson-clover apply of the MR
-    # smoother on the 12-RHS batch.  HIP events on the library's stream.
+    # Wilson-clover applies (the metric's Dslash GB/s) and the dominant kernel
+    # of the step, the SAP half-sweep of the smoother on the 12-RHS batch.
+    # HIP events on the library's stream.
     ctx = P.ctx
     V = ctx.V
     nr = 12
+    sr, sz = ctx.fine(nr, mglma.F32), ctx.fine(nr, mglma.F32)
+    sr.copy_(torch.randn(sr.shape, device="cuda"))
+    sz.zero_()
+    nmr = params.sap_mr
+    ms_sap = kernel_time(torch, lambda: ctx.sap_smooth(sr, sz, 1, nmr, mglma.F16), 10, stream) / 2
+    sap_flops = sap_alg_flops(V, wl["block"], wl["L"], nr, nmr)
+    ach_sap = sap_flops / (ms_sap * 1e-3) / 1e12
+    del sr, sz
 
     def apply_ms(prec, nrhs):
         x = ctx.fine(nrhs, prec)
@@ -549,8 +615,8 @@ def main():
         "f32_1rhs": dslash_alg_bytes(V, 1, 4) / (ms32_1 * 1e-3) / 1e9,
         "f16_1rhs": dslash_alg_bytes(V, 1, 2) / (ms16_1 * 1e-3) / 1e9,
     }
-    ach = dslash_gbs["f16_12rhs"]
-    traffic = measured_traffic(args.workload)
+    traffic16 = measured_traffic(args.workload)
+    traffic_sap = measured_sap_traffic(args.workload)
     cpu = None
     if not args.no_cpu:
         n_plain, res_plain = plain_gcr_iterations(P, mglma)
@@ -568,7 +634,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 Krylov + f16 CA-GCR smoother + bf16 coarse, f64 outer",
+        "dtype": "f32 Krylov + SAP smoother (f32, f16 links) + bf16 coarse, f64 outer",
         "data": "synthetic",
         "config": {"workload": "%dx%d^3 Wilson-clover, eps=%g, kappa=%g, c_sw=%g, %d^4 blocks, Nv=%d, Nlm=%d, "
                                "12 point-source RHS batched, mixed-precision MG-GCR to 1e-10" %
@@ -580,10 +646,13 @@ def main():
         "fp64_path": fp64,
         "speedup_mixed_vs_fp64": (value / fp64["solves_per_s"]) if fp64 else None,
         "dslash_GBs": dslash_gbs,
-        "roofline": {"bound": "hbm", "kernel": "k_dslash_h<3> (FP16 packed, 12 RHS)",
-                     "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                     "traffic": traffic, "avg_ms": ms16,
-                     "alg_bytes_per_launch": dslash_alg_bytes(V, nr, 2)},
+        "dslash_f16_12rhs": {"kernel": "k_dslash_h<3> (FP16 packed, 12 RHS)", "avg_ms": ms16,
+                             "alg_bytes_per_launch": dslash_alg_bytes(V, nr, 2),
+                             "frac_hbm_peak": dslash_gbs["f16_12rhs"] / HBM_PEAK_GBS, "traffic": traffic16},
+        "roofline": {"bound": "alu", "kernel": "k_sap_half<__half2, 3> (SAP half-sweep, 12 RHS, %d block steps)" % nmr,
+                     "achieved": ach_sap, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": ach_sap / FP32_PEAK_TFLOPS, "traffic": traffic_sap, "avg_ms": ms_sap,
+                     "alg_flops_per_launch": sap_flops},
         "cpu_baseline": cpu,
         "top_modes_setup": P.eig,
     }

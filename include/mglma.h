@@ -79,9 +79,9 @@ typedef struct {
     int    max_inner;    /* inner FGCR iterations per cycle                    */
     int    gcr_m;        /* inner FGCR restart length (1..32)                  */
     double inner_tol;    /* relative reduction asked of each inner solve       */
-    int    nu_post;      /* smoothing steps after the coarse correction: MR
-                            steps, or the Krylov dimension of the CA-GCR
-                            smoother (then 1..8)                            */
+    int    nu_post;      /* smoothing after the coarse correction: MR
+                            steps, the Krylov dimension of the CA-GCR
+                            smoother (then 1..8), or SAP cycles            */
     int    coarse_iters; /* GCR steps of the coarse solve in the preconditioner
                             (0: no coarse correction, smoother only)        */
     int    smoother;     /* precision of the smoother Dslash (mglma_prec)      */

@@ -9,9 +9,10 @@
 // whole extent) and adds d to z.
 //
 // One workgroup per (block, right-hand side), one thread per block site.
-// The block's iterate of the minimal-residual steps lives in LDS
-// (12 complex FP32 per site); links and clover come from the FP16 or FP32
-// copies, vectors are FP32.  Blocks of one colour do not couple when every
+// The block's minimal-residual vectors s and d live in LDS (12 complex FP32
+// per site each); links and clover come from the FP16 or FP32 copies
+// (L2-resident while the right-hand sides of a block run back to back),
+// vectors are FP32.  Blocks of one colour do not couple when every
 // block-grid extent is even or one, so one launch per colour updates them
 // all without ordering between workgroups.
 #include "mglma_internal.h"
@@ -52,6 +53,8 @@ __device__ __forceinline__ void sap_hop(const cx<float> p[12], bool neg, const G
             o[s * 3 + a] = t;
         }
     reconstruct_add<MU, FWD, float>(acc, o);
+    // keep the next hop's loads after this one (bounded register use)
+    __builtin_amdgcn_sched_barrier(0);
 }
 
 // hop of the full operator: neighbour read from the global field
@@ -110,13 +113,16 @@ __device__ __forceinline__ void sap_reduce3(float& a, float& b, float& c, float*
     for (int k = 0; k < nw; ++k) { a += red[3 * k]; b += red[3 * k + 1]; c += red[3 * k + 2]; }
 }
 
-template <typename G>
-__global__ __launch_bounds__(256) void k_sap_half(Geo g, const float2* __restrict__ rhs, float2* __restrict__ z,
+// W: waves per SIMD the register allocation is held to (LDS allows three
+// workgroups per compute unit)
+template <typename G, int W>
+__global__ __launch_bounds__(256, W) void k_sap_half(Geo g, const float2* __restrict__ rhs, float2* __restrict__ z,
                                                   const G* __restrict__ U, const G* __restrict__ C, float kappa,
                                                   const int* __restrict__ blist, int nblk, int nrhs, int npad,
                                                   int nmr) {
     __shared__ float2 sh[12 * SAP_MAXVB];
     __shared__ float red[3 * (SAP_MAXVB / 64)];
+    __shared__ float2 dsh[12 * SAP_MAXVB];
     // (block, rhs) items dealt to the XCDs in contiguous ranges, the right-hand
     // sides of one block back to back on one XCD (its links read once)
     const int bid = blockIdx.x, xcd = bid & 7, pos = bid >> 3;
@@ -163,29 +169,35 @@ __global__ __launch_bounds__(256) void k_sap_half(Geo g, const float2* __restric
     }
 #pragma unroll
     for (int k = 0; k < 12; ++k) sh[k * SAP_MAXVB + l] = make_float2(s[k].re, s[k].im);
-    cx<float> d[12];
 #pragma unroll
-    for (int k = 0; k < 12; ++k) d[k] = cmk(0.f, 0.f);
+    for (int k = 0; k < 12; ++k) dsh[k * SAP_MAXVB + l] = make_float2(0.f, 0.f);
 
     // minimal-residual steps on M_BB d = rho_B: t = M_BB s, omega = <t,s>/<t,t>
     for (int it = 0; it < nmr; ++it) {
         __syncthreads();
+        // links and clover are re-read every step: an offset opaque to the
+        // compiler keeps their loads inside the loop instead of holding all
+        // of them in registers across the steps
+        int zoff = 0;
+        asm volatile("" : "+s"(zoff));
+        const G* Ui = U + zoff;
+        const G* Ci = C + zoff;
         cx<float> t[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) t[k] = cmk(0.f, 0.f);
         if (on) {
-            sap_hop_block<0, true, G>(g, blk, l, lc, sh, U, t);
-            sap_hop_block<0, false, G>(g, blk, l, lc, sh, U, t);
-            sap_hop_block<1, true, G>(g, blk, l, lc, sh, U, t);
-            sap_hop_block<1, false, G>(g, blk, l, lc, sh, U, t);
-            sap_hop_block<2, true, G>(g, blk, l, lc, sh, U, t);
-            sap_hop_block<2, false, G>(g, blk, l, lc, sh, U, t);
-            sap_hop_block<3, true, G>(g, blk, l, lc, sh, U, t);
-            sap_hop_block<3, false, G>(g, blk, l, lc, sh, U, t);
+            sap_hop_block<0, true, G>(g, blk, l, lc, sh, Ui, t);
+            sap_hop_block<0, false, G>(g, blk, l, lc, sh, Ui, t);
+            sap_hop_block<1, true, G>(g, blk, l, lc, sh, Ui, t);
+            sap_hop_block<1, false, G>(g, blk, l, lc, sh, Ui, t);
+            sap_hop_block<2, true, G>(g, blk, l, lc, sh, Ui, t);
+            sap_hop_block<2, false, G>(g, blk, l, lc, sh, Ui, t);
+            sap_hop_block<3, true, G>(g, blk, l, lc, sh, Ui, t);
+            sap_hop_block<3, false, G>(g, blk, l, lc, sh, Ui, t);
 #pragma unroll
             for (int ch = 0; ch < 2; ++ch) {
                 cx<float> res[6];
-                clover_block<G, float>(C + (size_t)ch * 18 * V, V, i, s + 6 * ch, res);
+                clover_block<G, float>(Ci + (size_t)ch * 18 * V, V, i, s + 6 * ch, res);
 #pragma unroll
                 for (int k = 0; k < 6; ++k) t[6 * ch + k] = res[k] - kappa * t[6 * ch + k];
             }
@@ -201,7 +213,10 @@ __global__ __launch_bounds__(256) void k_sap_half(Geo g, const float2* __restric
         const cx<float> om = tt > 0.f ? cmk(are / tt, aim / tt) : cmk(0.f, 0.f);
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-            cmac(d[k], om, s[k]);
+            const float2 dv = dsh[k * SAP_MAXVB + l];
+            cx<float> dk = cmk(dv.x, dv.y);
+            cmac(dk, om, s[k]);
+            dsh[k * SAP_MAXVB + l] = make_float2(dk.re, dk.im);
             s[k] = s[k] - om * t[k];
             sh[k * SAP_MAXVB + l] = make_float2(s[k].re, s[k].im);
         }
@@ -211,8 +226,8 @@ __global__ __launch_bounds__(256) void k_sap_half(Geo g, const float2* __restric
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             float2* a = pz + (size_t)k * V + i;
-            const float2 v = *a;
-            *a = make_float2(v.x + d[k].re, v.y + d[k].im);
+            const float2 v = *a, dv = dsh[k * SAP_MAXVB + l];
+            *a = make_float2(v.x + dv.x, v.y + dv.y);
         }
     }
 }
@@ -267,11 +282,11 @@ int mg_sap(mglma_ctx* c, int prec, const void* r, void* z, int nrhs, int ncycle,
             const long long npad = (nitem + 7) / 8 * 8;
             if (npad > 0x7fffffffLL) return MGLMA_ERR_SHAPE;
             if (prec == MGLMA_F16)
-                hipLaunchKernelGGL((k_sap_half<__half2>), dim3((unsigned)npad), dim3(nthr), 0, c->stream, g,
+                hipLaunchKernelGGL((k_sap_half<__half2, 3>), dim3((unsigned)npad), dim3(nthr), 0, c->stream, g,
                                    (const float2*)r, (float2*)z, (const __half2*)c->U16, (const __half2*)c->C16,
                                    (float)c->kappa, bl, nblk, nrhs, (int)npad, nmr);
             else
-                hipLaunchKernelGGL((k_sap_half<float2>), dim3((unsigned)npad), dim3(nthr), 0, c->stream, g,
+                hipLaunchKernelGGL((k_sap_half<float2, 2>), dim3((unsigned)npad), dim3(nthr), 0, c->stream, g,
                                    (const float2*)r, (float2*)z, (const float2*)c->U32, (const float2*)c->C32,
                                    (float)c->kappa, bl, nblk, nrhs, (int)npad, nmr);
             HIP_TRY(hipGetLastError());

@@ -13,7 +13,11 @@ against the oracle on sampled outputs and by properties that hold at any size:
   with the oracle's stencil apply to 1e-12;
 * the preconditioner's even-odd Schur apply on sampled even sites, its
   FP16-basis restrictor and prolongator on sampled blocks, and the coarse
-  pieces to 1e-10 under the oracle's stencil apply.
+  pieces to 1e-10 under the oracle's stencil apply;
+* the SAP smoother of the benchmark (12 right-hand sides, FP16 links, its
+  block steps): one cycle, compared on a sampled colour-0 block of the last
+  right-hand side (the colour-1 half-sweep does not change colour-0 blocks)
+  with the oracle's block solve.
 """
 import numpy as np
 import pytest
@@ -268,3 +272,37 @@ def test_fullsize_evenodd_and_transfers(ens):
     rel_c = np.linalg.norm(res.reshape(nr, -1), axis=1) / np.linalg.norm(rh.reshape(nr, -1), axis=1)
     print("coarse pieces: oracle-stencil residual", rel_c.max())
     assert rel_c.max() <= 1.05e-10
+
+
+def test_fullsize_sap_cycle(ens):
+    import torch
+    import bench
+    from oracle import sap
+    from paper_2412_06347_amd import mglma
+    U, D = ens
+    nmr = bench.mixed_params(mglma).sap_mr
+    ctx = _ctx(U)
+    r = synth.gaussian_fields(12, L, 95)
+    z0 = 0.1 * synth.gaussian_fields(12, L, 96)
+    rd, zd = ctx.fine(12, mglma.F32), ctx.fine(12, mglma.F32)
+    ctx.import_fields(to_dev(r), rd, mglma.F32)
+    ctx.import_fields(to_dev(z0), zd, mglma.F32)
+    ctx.sap_smooth(rd, zd, 1, nmr, mglma.F16)
+    out = torch.empty((12, ctx.V, 4, 3, 2), dtype=torch.float64, device="cuda")
+    ctx.export_fields(zd, out, mglma.F32)
+    got = from_dev(out)
+    del out, rd, zd
+    bl = subspace.Blocking(L, B)
+    rng = np.random.default_rng(97)
+    blocks = [y for y in rng.permutation(bl.V1) if sap.block_colour(bl, y) == 0][:1]
+    for q in (11,):
+        rl = dirac.fields_to_lattice(r[q:q + 1], L)[0]
+        zl = dirac.fields_to_lattice(z0[q:q + 1], L)[0]
+        rho = rl - D.M(zl[None])[0]
+        gl = dirac.fields_to_lattice(got[q:q + 1], L)[0]
+        for y in blocks:
+            mask = sap.block_mask(bl, y)
+            ref = zl[mask] + sap.mr_block(D, mask, rho, nmr)[mask]
+            e = np.linalg.norm(gl[mask] - ref) / np.linalg.norm(ref)
+            print("rhs %d block %d: SAP cycle vs oracle %.2e" % (q, y, e))
+            assert e < 5e-3
