@@ -39,7 +39,7 @@ def log(*a):
 
 
 def mixed_params(mglma, **kw):
-    p = dict(tol=1e-10, max_outer=10, max_inner=120, gcr_m=8, inner_tol=1e-5, nu_post=2, sap_mr=4,
+    p = dict(tol=1e-10, max_outer=10, max_inner=120, gcr_m=6, inner_tol=1e-5, nu_post=2, sap_mr=4,
              coarse_iters=4, smoother=mglma.F16, inner=mglma.F32, coarse=mglma.BF16, use_mg=1,
              smoother_alg=mglma.SMOOTH_SAP, coarse_eo=1)
     p.update(kw)
