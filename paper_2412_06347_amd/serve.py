@@ -108,10 +108,16 @@ class Engine:
             ctx.set_top_modes(m.contiguous())
             self.G_top = ctx.contract_top()
         self.stream.synchronize()
-        self.params = params or mglma.default_params(tol=1e-10, max_outer=10, max_inner=120, gcr_m=4,
-                                                     inner_tol=1e-5, nu_post=6, coarse_iters=4,
-                                                     smoother=mglma.F16, inner=mglma.F32, coarse=mglma.BF16,
-                                                     smoother_alg=mglma.SMOOTH_CAGCR, coarse_eo=1)
+        # SAP smoothing (FGCR(6), 2 cycles of 4 block steps) where the block
+        # grid allows it (every extent even or one), CA-GCR(6) otherwise
+        grid = [L[mu] // wl["block"][mu] for mu in range(4)]
+        if all(e == 1 or e % 2 == 0 for e in grid) and int(np.prod(wl["block"])) <= 256:
+            smooth = dict(gcr_m=6, nu_post=2, sap_mr=4, smoother_alg=mglma.SMOOTH_SAP)
+        else:
+            smooth = dict(gcr_m=4, nu_post=6, smoother_alg=mglma.SMOOTH_CAGCR)
+        self.params = params or mglma.default_params(tol=1e-10, max_outer=10, max_inner=120, inner_tol=1e-5,
+                                                     coarse_iters=4, smoother=mglma.F16, inner=mglma.F32,
+                                                     coarse=mglma.BF16, coarse_eo=1, **smooth)
         self.coarse_params = coarse_params or mglma.default_params(tol=1e-10, coarse=mglma.BF16, coarse_iters=12,
                                                                    max_outer=40, coarse_eo=1)
         self.resident = ctx.resident_bytes() + self.U.numel() * 8
