@@ -13,7 +13,9 @@ against the oracle on sampled outputs and by properties that hold at any size:
   with the oracle's stencil apply to 1e-12;
 * the preconditioner's even-odd Schur apply on sampled even sites, its
   FP16-basis restrictor and prolongator on sampled blocks, and the coarse
-  pieces to 1e-10 under the oracle's stencil apply;
+  pieces to 1e-10 under the oracle's stencil apply; with level 2 (8^4
+  blocks): D_2 on sampled columns against R_1 D_1 T_1, the K-cycle level-1
+  solve and the level-2 solve to 1e-10 under the oracle's stencil applies;
 * the SAP smoother of the benchmark (12 right-hand sides, FP16 links, its
   block steps): one cycle, compared on a sampled colour-0 block of the last
   right-hand side (the colour-1 half-sweep does not change colour-0 blocks)
@@ -272,6 +274,49 @@ def test_fullsize_evenodd_and_transfers(ens):
     rel_c = np.linalg.norm(res.reshape(nr, -1), axis=1) / np.linalg.norm(rh.reshape(nr, -1), axis=1)
     print("coarse pieces: oracle-stencil residual", rel_c.max())
     assert rel_c.max() <= 1.05e-10
+    # -- level 2 (8^4 blocks): the K-cycle level-1 solve of the same right-hand
+    # sides, and the level-2 solve of their restriction, residuals under the
+    # oracle's stencil applies (D_1 above, D_2 exported and checked against
+    # the oracle's R_1 D_1 T_1 on sampled columns)
+    b2 = tuple(2 * x for x in B)
+    ctx.build_level2(b2)
+    pk = mglma.default_params(tol=1e-10, coarse=mglma.BF16, coarse_iters=4, coarse_eo=0, kcycle=4, kcycle_nu=4,
+                              max_outer=40, max_inner=1)
+    xk = ctx.coarse(nr)
+    st = ctx.coarse_solve(re_, xk, pk)
+    res = ocoarse.coarse_apply(D1h, nbr, from_dev(xk)) - rh
+    rel_k = np.linalg.norm(res.reshape(nr, -1), axis=1) / np.linalg.norm(rh.reshape(nr, -1), axis=1)
+    print("K-cycle level-1 solve: %d rounds, oracle-stencil residual %.2e" % (st[0]["outer"], rel_k.max()))
+    assert rel_k.max() <= 1.05e-10
+    V2 = ctx.V2
+    D2 = torch.empty((V2, 9, ctx.nc, ctx.nc, 2), dtype=torch.float64, device="cuda")
+    ctx.export_level2_op(D2)
+    D2h = from_dev(D2)
+    bl2 = subspace.Blocking(L, b2)
+    nbr2 = bl2.neighbour_table()
+    # R_1 sums the level-1 sites of a level-2 block with weight sqrt(V2/V1), T_1 = R_1^T
+    zmap = ocoarse.level2_of(bl.L1, tuple(b2[m] // B[m] for m in range(4)))
+    w = np.sqrt(V2 / bl.V1)
+    for j in np.random.default_rng(98).choice(V2 * ctx.nc, 3, replace=False):
+        zj, a = divmod(int(j), ctx.nc)
+        t1e = np.zeros((1, bl.V1, ctx.nc), dtype=np.complex128)
+        t1e[0, zmap == zj, a] = w
+        d1 = ocoarse.coarse_apply(D1h, nbr, t1e)[0]
+        col = np.zeros((V2, ctx.nc), dtype=np.complex128)
+        np.add.at(col, zmap, w * d1)
+        e2 = np.zeros((1, V2, ctx.nc), dtype=np.complex128)
+        e2[0, zj, a] = 1.0
+        got = ocoarse.coarse_apply(D2h, nbr2, e2)[0]
+        assert np.linalg.norm(got - col) <= 1e-12 * np.linalg.norm(col)
+    rb2 = ctx.level2_field(nr)
+    ctx.level2_restrict(re_, rb2)
+    x2 = ctx.level2_field(nr)
+    ctx.level2_solve(rb2, x2, mglma.default_params(tol=1e-10, coarse=mglma.BF16, coarse_iters=8, max_outer=40))
+    rb2h = from_dev(rb2)
+    res2 = ocoarse.coarse_apply(D2h, nbr2, from_dev(x2)) - rb2h
+    rel_2 = np.linalg.norm(res2.reshape(nr, -1), axis=1) / np.linalg.norm(rb2h.reshape(nr, -1), axis=1)
+    print("level-2 solve: oracle-stencil residual %.2e" % rel_2.max())
+    assert rel_2.max() <= 1.05e-10
 
 
 def test_fullsize_sap_cycle(ens):
