@@ -472,6 +472,59 @@ def setup_recipes(wl, reps=2):
                       "recipes": out}), flush=True)
 
 
+def serving(reqs_n=60, seed=7):
+    """Serving mix (a reduced version of the serving workload: two resident
+    ensembles, 16^3 x 32 and 24^3 x 48): requests of 1-8 stochastic
+    time-slice sources (x 4 spin-diluted right-hand sides) on a uniformly
+    drawn ensemble.  Capacity from a closed burst (all requests at once), then a
+    Poisson stream at 0.8 of it; solves/s and p50/p99 latency (arrival to
+    the returned correlator levels)."""
+    import torch
+    from paper_2412_06347_amd.serve import Server, poisson_arrivals
+    free, _ = torch.cuda.mem_get_info()
+    ens = {"16c32": WORKLOADS["16c32"], "24c48": WORKLOADS["24c48"]}
+    g = np.random.default_rng(seed)
+
+    def draw(n):
+        return [(list(ens)[int(g.integers(len(ens)))], int(g.integers(1, 9))) for _ in range(n)]
+
+    def run(srv, items, arrivals):
+        reqs = []
+        t0 = time.perf_counter()
+        for k, ((name, n_src), t) in enumerate(zip(items, arrivals)):
+            while time.perf_counter() - t0 < t:
+                time.sleep(0.0005)
+            reqs.append(srv.submit(name, n_src, 1000 + k))
+        for r in reqs:
+            r.wait(600)
+        return reqs
+
+    srv = Server(hbm_budget=0.8 * free, max_batch_rhs=48)
+    t0 = time.perf_counter()
+    for name, wl in ens.items():
+        srv.add_ensemble(name, wl)
+    setup = time.perf_counter() - t0
+    srv.start()
+    burst = draw(24)
+    run(srv, burst, [0.0] * len(burst))
+    cap = srv.stats()
+    srv.completed.clear()
+    srv.batches.clear()
+    mean_rhs = 4 * np.mean([n for _, n in burst])
+    rate = 0.8 * cap["solves_per_s"] / mean_rhs
+    stream = draw(reqs_n)
+    reqs = run(srv, stream, poisson_arrivals(reqs_n, rate, seed + 1))
+    srv.stop()
+    st = srv.stats()
+    res = max(r.result["max_true_rel_res"] for r in reqs)
+    print(json.dumps({"diagnostic": "serving mix: resident 16^3x32 and 24^3x48 ensembles, continuous batching",
+                      "setup_s": round(setup, 1), "slots": srv.slots,
+                      "capacity_burst": {k: cap[k] for k in ("n", "solves", "solves_per_s", "p50_s", "p99_s")},
+                      "poisson": {"requests_per_s": rate, "offered_solves_per_s": rate * mean_rhs,
+                                  **{k: st[k] for k in ("n", "solves", "solves_per_s", "p50_s", "p99_s", "batches")}},
+                      "max_true_rel_res": res}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -493,6 +546,9 @@ def main():
                          "level contributions of the point correlator")
     ap.add_argument("--sap-only", action="store_true",
                     help="only run SAP smoother cycles of the workload (for hardware-counter runs)")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving diagnostic instead of the bench: two resident ensembles, a closed burst for the "
+                         "capacity, then a Poisson stream at 0.8 of it; solves/s and p50/p99 latency")
     ap.add_argument("--setup", action="store_true",
                     help="test-vector setup diagnostic instead of the bench: Gaussian vectors, inverse iteration "
                          "with plain GCR, adaptive setup with the multigrid solver; setup time and the MG solve")
@@ -520,6 +576,9 @@ def main():
         return
     if args.setup:
         setup_recipes(wl)
+        return
+    if args.serve:
+        serving()
         return
     if args.sap_only:
         # the SAP smoother of the step (FP16 links, 12 RHS, the bench's block
