@@ -355,6 +355,16 @@ int mglma_adaptive_setup(mglma_ctx* ctx, const mglma_solve_params* p, double* te
  * SHAPE (block grid or block size), OOM.                                   */
 int mglma_sap_smooth(mglma_ctx* ctx, int prec, int ncycle, int nmr, const float* r_dev, float* z_dev,
                      int nrhs);
+/* Launch timing of the SAP half-sweeps (for measurement): with enable = 1
+ * every half-sweep launched afterwards, by mglma_sap_smooth or inside the
+ * solves, is bracketed by a pair of HIP events on the context's stream (the
+ * context owns them; they are destroyed with it).  mglma_sap_timing
+ * synchronises the stream and clears the recorded launches; enable = 0
+ * stops recording.  mglma_sap_elapsed synchronises, returns the summed
+ * durations in ms and the number of launches recorded since the last call
+ * (host pointers), and clears them.  Errors: ARG, HIP.                      */
+int mglma_sap_timing(mglma_ctx* ctx, int enable);
+int mglma_sap_elapsed(mglma_ctx* ctx, double* ms, int* launches);
 
 /* ---- solves -------------------------------------------------------------- */
 /* x = M^{-1} b for nrhs fields (device layout, F64) to the true relative

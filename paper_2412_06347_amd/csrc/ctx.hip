@@ -239,6 +239,7 @@ extern "C" void mglma_destroy(mglma_ctx* c) {
     mg_free_subspace(c);
     free_gauge(c);
     mg_free(c, c->sap_blk, (size_t)c->geo.V1 * sizeof(int));
+    for (hipEvent_t e : c->sap_ev) (void)hipEventDestroy(e);
     for (int i = 0; i < mglma_ctx::NSCR; ++i) mg_free(c, c->scr[i].ptr, c->scr[i].bytes);
     mg_free(c, c->red_part, c->red_part_n * sizeof(double));
     cache_release(c);

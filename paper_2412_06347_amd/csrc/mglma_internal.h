@@ -295,6 +295,10 @@ struct mglma_ctx {
     // SAP smoother: block indices ordered by colour, number of colour-0 blocks
     int* sap_blk = nullptr;
     int sap_n0 = 0;
+    // optional launch timing of the SAP half-sweeps: event pairs on the stream
+    bool sap_timing = false;
+    std::vector<hipEvent_t> sap_ev;
+    size_t sap_ev_used = 0;
 
     static constexpr int NSCR = 40;
     Scratch scr[NSCR];

@@ -281,6 +281,18 @@ int mg_sap(mglma_ctx* c, int prec, const void* r, void* z, int nrhs, int ncycle,
             const long long nitem = (long long)nblk * nrhs;
             const long long npad = (nitem + 7) / 8 * 8;
             if (npad > 0x7fffffffLL) return MGLMA_ERR_SHAPE;
+            hipEvent_t ev[2] = {nullptr, nullptr};
+            if (c->sap_timing) {
+                while (c->sap_ev.size() < c->sap_ev_used + 2) {
+                    hipEvent_t e;
+                    HIP_TRY(hipEventCreate(&e));
+                    c->sap_ev.push_back(e);
+                }
+                ev[0] = c->sap_ev[c->sap_ev_used];
+                ev[1] = c->sap_ev[c->sap_ev_used + 1];
+                c->sap_ev_used += 2;
+                HIP_TRY(hipEventRecord(ev[0], c->stream));
+            }
             if (prec == MGLMA_F16)
                 hipLaunchKernelGGL((k_sap_half<__half2, 3>), dim3((unsigned)npad), dim3(nthr), 0, c->stream, g,
                                    (const float2*)r, (float2*)z, (const __half2*)c->U16, (const __half2*)c->C16,
@@ -290,7 +302,31 @@ int mg_sap(mglma_ctx* c, int prec, const void* r, void* z, int nrhs, int ncycle,
                                    (const float2*)r, (float2*)z, (const float2*)c->U32, (const float2*)c->C32,
                                    (float)c->kappa, bl, nblk, nrhs, (int)npad, nmr);
             HIP_TRY(hipGetLastError());
+            if (ev[1]) HIP_TRY(hipEventRecord(ev[1], c->stream));
         }
+    return MGLMA_OK;
+}
+
+extern "C" int mglma_sap_timing(mglma_ctx* c, int enable) {
+    if (!c) return MGLMA_ERR_ARG;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->sap_timing = enable != 0;
+    c->sap_ev_used = 0;
+    return MGLMA_OK;
+}
+
+extern "C" int mglma_sap_elapsed(mglma_ctx* c, double* ms, int* launches) {
+    if (!c || !ms || !launches) return MGLMA_ERR_ARG;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    double tot = 0.0;
+    for (size_t k = 0; k + 1 < c->sap_ev_used; k += 2) {
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, c->sap_ev[k], c->sap_ev[k + 1]));
+        tot += t;
+    }
+    *ms = tot;
+    *launches = (int)(c->sap_ev_used / 2);
+    c->sap_ev_used = 0;
     return MGLMA_OK;
 }
 

@@ -31,7 +31,7 @@ SYMBOLS = [
     "mglma_deficit", "mglma_coarse_schur_apply",
     "mglma_build_level2", "mglma_export_level2_op", "mglma_level2_restrict", "mglma_level2_prolong",
     "mglma_level2_apply", "mglma_level2_solve", "mglma_level2_pieces", "mglma_save", "mglma_load",
-    "mglma_adaptive_setup", "mglma_sap_smooth",
+    "mglma_adaptive_setup", "mglma_sap_smooth", "mglma_sap_timing", "mglma_sap_elapsed",
 ]
 
 
@@ -202,6 +202,16 @@ class Context:
     def sap_smooth(self, r, z, ncycle=1, nmr=4, prec=F16):
         """ncycle SAP cycles on M z = r (FP32 device fields, z in place)."""
         _check(lib().mglma_sap_smooth(self._ctx, prec, int(ncycle), int(nmr), _ptr(r), _ptr(z), r.shape[0]))
+
+    def sap_timing(self, enable=True):
+        """Start (or stop) recording the launch durations of the SAP half-sweeps."""
+        _check(lib().mglma_sap_timing(self._ctx, int(bool(enable))))
+
+    def sap_elapsed(self):
+        """(summed ms, launches) of the SAP half-sweeps recorded since the last call."""
+        ms, n = C.c_double(0.0), C.c_int(0)
+        _check(lib().mglma_sap_elapsed(self._ctx, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
 
     def export_basis(self, out):
         _check(lib().mglma_export_basis(self._ctx, _ptr(out)))

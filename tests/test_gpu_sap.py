@@ -88,3 +88,20 @@ def test_sap_arguments():
         assert e.value.code == -1
     # no right-hand sides: nothing to do (pointers still valid)
     assert mglma.lib().mglma_sap_smooth(Q.ctx._ctx, mglma.F16, 1, 4, mglma._ptr(r), mglma._ptr(z), 0) == 0
+
+
+def test_sap_launch_timing():
+    """The launch timing records one event pair per half-sweep while enabled."""
+    from paper_2412_06347_amd import mglma
+    P = Pair((4, 4, 4, 4), (2, 2, 2, 2), 2, oracle_galerkin=False)
+    r, z = P.ctx.fine(3, mglma.F32), P.ctx.fine(3, mglma.F32)
+    r.normal_()
+    z.zero_()
+    P.ctx.sap_timing(True)
+    P.ctx.sap_smooth(r, z, ncycle=2, nmr=4)
+    ms, n = P.ctx.sap_elapsed()
+    assert n == 4 and ms > 0.0
+    assert P.ctx.sap_elapsed() == (0.0, 0)          # cleared by the previous call
+    P.ctx.sap_timing(False)
+    P.ctx.sap_smooth(r, z, ncycle=1, nmr=4)
+    assert P.ctx.sap_elapsed()[1] == 0
