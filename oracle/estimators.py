@@ -161,3 +161,24 @@ def level_sums(Cij):
     """C_Lk = C_kk + sum_{i>k} (C_ik + C_ki) for a dict or array Cij[i][j]."""
     n = len(Cij)
     return [Cij[k][k] + sum(Cij[i][k] + Cij[k][i] for i in range(k + 1, n)) for k in range(n)]
+
+
+def level_estimates(pair, pieces, t_src):
+    """Level terms averaged over sources (eq:C_stoch for stochastic sources;
+    for point sources at time y0 = t_src[n] the average over the source times
+    is eq:timetrans).
+
+    pair(Si, Sj, t) returns the one-source two-point function of the pieces
+    Si, Sj in the frame t = 0..L0-1 relative to the source time (stochastic_pair
+    or point_correlator).  pieces[n][i] holds S_i applied to the columns of
+    source n (the level pieces S_0, S_1, ... of eq:mglma:decomp).  For each
+    source the C_ij are formed, reduced to the level sums C_Lk (level_sums),
+    and the result is the mean over the sources, one row per level."""
+    nsrc = len(pieces)
+    out = None
+    for n in range(nsrc):
+        P = pieces[n]
+        Cij = [[pair(P[i], P[j], int(t_src[n])) for j in range(len(P))] for i in range(len(P))]
+        CL = np.array(level_sums(Cij))
+        out = CL if out is None else out + CL
+    return out / nsrc

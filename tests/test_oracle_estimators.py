@@ -71,6 +71,11 @@ def test_telescoping_sum(small):
     assert np.abs(tot - C).max() < 1e-12 * np.abs(C).max()
     CL = est.level_sums(Cij)
     assert np.abs(sum(CL) - C).max() < 1e-12 * np.abs(C).max()
+    # each level against the assignment of fig:C written out term by term
+    tol = 1e-12 * np.abs(C).max()
+    assert np.abs(CL[0] - (Cij[0][0] + Cij[0][1] + Cij[1][0] + Cij[0][2] + Cij[2][0])).max() < tol
+    assert np.abs(CL[1] - (Cij[1][1] + Cij[1][2] + Cij[2][1])).max() < tol
+    assert np.abs(CL[2] - Cij[2][2]).max() < tol
     # C is real up to rounding for the isovector vector current
     assert np.abs(C.imag).max() < 1e-10 * np.abs(C).max()
 
@@ -173,3 +178,55 @@ def test_free_field_point_correlator_closed_form():
         m = np.einsum("...ab,bc,...dc,de->...ae", Sx, Gs, Sx.conj(), Gk)
         expect += -np.trace(m, axis1=-2, axis2=-1).sum(axis=(1, 2, 3))
     assert np.abs(got - expect).max() < 1e-10 * np.abs(expect).max()
+
+
+def test_level_sums_by_bilinearity(small):
+    """Each level sum equals a difference of correlators of cumulative pieces
+    S_{>=k} = sum_{i>=k} S_i, computed from the dense propagators alone:
+    C_Lk = C(S_{>=k}, S_{>=k}) - C(S_{>=k+1}, S_{>=k+1}).  A level sum that
+    took i < k instead of i > k, or dropped a cross term, fails here."""
+    L, P = small["L"], small["pieces"]
+    Cij = [[est.exact_correlator(P[i], P[j], L) for j in range(3)] for i in range(3)]
+    CL = est.level_sums(Cij)
+    cum = [P[0] + P[1] + P[2], P[1] + P[2], P[2]]
+    Ccum = [est.exact_correlator(Sk, Sk, L) for Sk in cum] + [0.0]
+    scale = np.abs(Ccum[0]).max()
+    for k in range(3):
+        assert np.abs(CL[k] - (Ccum[k] - Ccum[k + 1])).max() < 1e-12 * scale
+    # the levels are not all equal to the diagonal terms (the cross terms matter)
+    assert np.abs(CL[0] - Cij[0][0]).max() > 1e-6 * scale
+
+
+def test_level_estimates_point_average(small):
+    """Point sources at every site, averaged level by level, give the
+    time-averaged level sums of the brute-force C_ij (eq:timetrans)."""
+    L, P = small["L"], small["pieces"]
+    Cij = [[est.exact_correlator(P[i], P[j], L) for j in range(3)] for i in range(3)]
+    expect = np.array([est.timeavg(c) for c in est.level_sums(Cij)])
+    pieces, t_src = [], []
+    for y in np.ndindex(*L):
+        pieces.append([np.stack([_col(Pk, L, y, a) for a in range(12)]) for Pk in P])
+        t_src.append(y[0])
+    got = est.level_estimates(est.point_correlator, pieces, t_src)
+    assert np.abs(got - expect).max() < 1e-12 * np.abs(expect).max()
+
+
+def test_level_estimates_exact_dilution(small):
+    """Unit-vector noise on one slice: N times the source mean of the
+    stochastic level estimates equals the brute-force level sums at that
+    source time (eq:C_stoch with exact dilution)."""
+    L, P = small["L"], small["pieces"]
+    tn = 2
+    L3 = L[1] * L[2] * L[3]
+    Cij = [[est.exact_correlator(P[i], P[j], L) for j in range(3)] for i in range(3)]
+    CL = est.level_sums(Cij)
+    expect = np.array([[c[(tn + t) % L[0], tn] for t in range(L[0])] for c in CL])
+    pieces = []
+    for xs in range(L3):
+        for c in range(3):
+            xi = np.zeros((L3, 3), dtype=complex)
+            xi[xs, c] = 1.0
+            eta = est.spin_diluted_sources(L, xi, tn).reshape(4, -1)
+            pieces.append([(Pk @ eta.T).T.reshape(4, *L, 4, 3) for Pk in P])
+    got = est.level_estimates(lambda a, b, t: est.stochastic_pair(a, b, t, L), pieces, [tn] * len(pieces))
+    assert np.abs(len(pieces) * got - expect).max() < 1e-12 * np.abs(expect).max()
