@@ -113,11 +113,10 @@ class Pipeline:
         rc, stats = ctx.solve(self.src, self.x, params)
         cp = mglma.default_params(tol=1e-10, coarse=mglma.BF16, coarse_iters=12, max_outer=40, coarse_eo=1)
         ctx.coarse_pieces(self.src, self.cg, self.ct, cp)
-        C_all = ctx.contract_point(self.x, self.x, 0)
-        C_ge1 = ctx.contract_point_coarse(self.cg, self.cg, 0)
-        C_top = ctx.contract_point_coarse(self.ct, self.ct, 0)
-        G_exact = ctx.contract_top()
-        levels = dict(L0=C_all - C_ge1, L1=C_ge1 - C_top, L2pt=C_top, L2exact=G_exact)
+        # level terms in the library: G(S) - G(S_>=1), G(S_>=1) - G(S_2), the
+        # point estimate G(S_2) and eq:G_LL:exact
+        lv = ctx.contract_levels(mglma.SRC_POINT, [0], fine=self.x, coarse=[self.cg, self.ct], exact_top=True)
+        levels = dict(L0=lv[0], L1=lv[1], L2pt=lv[2], L2exact=lv[3])
         return stats, levels
 
 
@@ -345,11 +344,10 @@ def hierarchy(wl, reps=3):
     cg1, ct, cg2 = ctx.coarse(12), ctx.coarse(12), ctx.coarse(12)
     t_p1 = timed(lambda: ctx.coarse_pieces(P.src, cg1, ct, cp))
     t_p2 = timed(lambda: ctx.level2_pieces(P.src, cg2, cp))
-    C = dict(all=ctx.contract_point(P.x, P.x, 0), ge1=ctx.contract_point_coarse(cg1, cg1, 0),
-             ge2=ctx.contract_point_coarse(cg2, cg2, 0), top=ctx.contract_point_coarse(ct, ct, 0))
-    G3 = ctx.contract_top()
+    rows = ctx.contract_levels(mglma.SRC_POINT, [0], fine=P.x, coarse=[cg1, cg2, ct], exact_top=True)
+    G3 = rows[4]
     L0 = wl["L"][0]
-    lv = dict(L0=C["all"] - C["ge1"], L1=C["ge1"] - C["ge2"], L2=C["ge2"] - C["top"], L3_point=C["top"])
+    lv = dict(L0=rows[0], L1=rows[1], L2=rows[2], L3_point=rows[3])
     # stochastic estimator with per-level source counts (sec. "Stochastic estimator
     # on level k": few sources for the level that needs fine solves, more for the
     # coarse levels; spin-diluted time-slice noise, 4 right-hand sides per source)
@@ -364,9 +362,6 @@ def hierarchy(wl, reps=3):
         ctx.noise_sources(torch.from_numpy(xi.view(np.float64).reshape(n, V3, 3, 2)).cuda(), t, eta)
         return eta, t
 
-    def mean_stoch(fn, a, b, t, n):
-        return sum(fn(a[4 * k:4 * k + 4], b[4 * k:4 * k + 4], int(t[k])) for k in range(n)) / n
-
     stoch, tlev = {}, {}
     for lvname, seed in (("L0", 7100), ("L1", 7200), ("L2", 7300)):
         n = nsrc[lvname]
@@ -374,19 +369,21 @@ def hierarchy(wl, reps=3):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         g1, tp, g2 = ctx.coarse(4 * n), ctx.coarse(4 * n), ctx.coarse(4 * n)
+        # the level's estimator from its own sources: row 0 of the level
+        # assembly over the two cumulative pieces that bound it
         if lvname == "L0":
             x = ctx.fine(4 * n)
             ctx.solve(eta, x, mixed_params(mglma))
             ctx.coarse_pieces(eta, g1, None, cp)
-            G = mean_stoch(ctx.contract_stoch, x, x, t, n) - mean_stoch(ctx.contract_stoch_coarse, g1, g1, t, n)
+            G = ctx.contract_levels(mglma.SRC_STOCH, t, fine=x, coarse=[g1])[0]
         elif lvname == "L1":
             ctx.coarse_pieces(eta, g1, None, cp)
             ctx.level2_pieces(eta, g2, cp)
-            G = mean_stoch(ctx.contract_stoch_coarse, g1, g1, t, n) - mean_stoch(ctx.contract_stoch_coarse, g2, g2, t, n)
+            G = ctx.contract_levels(mglma.SRC_STOCH, t, coarse=[g1, g2])[0]
         else:
             ctx.coarse_pieces(eta, g1, tp, cp)
             ctx.level2_pieces(eta, g2, cp)
-            G = mean_stoch(ctx.contract_stoch_coarse, g2, g2, t, n) - mean_stoch(ctx.contract_stoch_coarse, tp, tp, t, n)
+            G = ctx.contract_levels(mglma.SRC_STOCH, t, coarse=[g2, tp])[0]
         torch.cuda.synchronize()
         tlev[lvname] = time.perf_counter() - t0
         stoch[lvname] = G

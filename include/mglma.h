@@ -370,8 +370,8 @@ int mglma_sap_elapsed(mglma_ctx* ctx, double* ms, int* launches);
 /* x = M^{-1} b for nrhs fields (device layout, F64) to the true relative
  * residual p->tol.  Mixed precision: inner FGCR on p->inner vectors with the
  * multigrid preconditioner (coarse correction with p->coarse operator, then
- * smoothing in p->smoother precision, MR or CA-GCR) inside an FP64
- * defect-correction loop.  stats may be NULL or hold nrhs entries.
+ * smoothing in p->smoother precision: MR, CA-GCR or SAP, p->smoother_alg)
+ * inside an FP64 defect-correction loop.  stats may be NULL or hold nrhs entries.
  * Synchronising.  Errors: NO_GAUGE, NO_SUBSPACE (use_mg), NONFINITE,
  * NOT_CONVERGED (x holds the last iterate).                                 */
 int mglma_solve(mglma_ctx* ctx, const mglma_solve_params* p, const double* b_dev,
@@ -420,6 +420,47 @@ int mglma_contract_stoch_coarse(mglma_ctx* ctx, const double* ci_dev, const doub
                                 int tn, double* C_host);
 /* Exact top-level term eq:G_LL:exact, G(t) for t = 0..L0-1 (complex).     */
 int mglma_contract_top(mglma_ctx* ctx, double* G_host);
+
+/* ---- source averages and level assembly (eq:C_ij, eq:cdecomp, eq:C_stoch,
+ *      eq:timetrans) -------------------------------------------------------- */
+/* Source kinds: MGLMA_SRC_POINT: 12 columns per source (S(., y) for the 12
+ * spin-colour components at one point y, column 3*s + c), t_src[n] = y_0 of
+ * source n, each source contributing C(y0 + t, y0) of eq:tmr with one source
+ * position, so that sources at every y_0 give the time average eq:timetrans;
+ * MGLMA_SRC_STOCH: 4 columns per source (the spin-diluted wall source
+ * eta_n^{(s)}, s = 0..3, column s), t_src[n] = t_n, each source contributing
+ * G^n(t_n + t, t_n) of eq:C_stoch2, so that the mean is eq:C_stoch.       */
+enum { MGLMA_SRC_POINT = 0, MGLMA_SRC_STOCH = 1 };
+/* Two-point function of the propagator pieces S_i and S_j averaged over
+ * nsrc sources: G_host[t] = (1/nsrc) sum_n G^n_ij(t_n + t, t_n), t = 0..L0-1
+ * (complex).  psi_i_dev / psi_j_dev hold S_i and S_j applied to the columns
+ * of every source, source n at columns [n*ncol, (n+1)*ncol): fine fields in
+ * the device layout (coarse = 0) or coarse fields c with S eta = T c,
+ * contracted on the coarse grid through (gamma5 gamma_k)_1 (coarse = 1,
+ * eq:coarse:gamma); all F64.  1 <= nsrc <= 512, 0 <= t_src[n] < L0 (host
+ * array).  Every time slice is a fixed-order sum that does not depend on
+ * the other sources of the call.  Synchronising.  Errors: ARG,
+ * NO_SUBSPACE.                                                             */
+int mglma_contract_pair(mglma_ctx* ctx, int kind, int nsrc, const int* t_src, int coarse, const double* psi_i_dev,
+                        const double* psi_j_dev, double* G_host);
+/* Level terms of the correlator from cumulative propagator pieces, averaged
+ * over nsrc sources (eq:C_ij level sums by bilinearity).  The pieces are
+ * P_0 = fine_dev (S eta as fine fields; may be NULL) followed by the coarse
+ * fields coarse_dev[k], k < ncoarse, with P_k eta = S_{>=k} eta = sum_{i>=k}
+ * S_i eta (for two levels and a top level: S eta, D_1^{-1} R eta from
+ * mglma_coarse_pieces, W D_2^{-1} W^+ R eta; with level 2 the level-2 piece
+ * from mglma_level2_pieces before the top).  Column layout and t_src as in
+ * mglma_contract_pair; 1 <= number of pieces m <= 8.  Result G_host
+ * [nrow][L0] complex with, for the source average <.>,
+ *   row k < m-1:  G_Lk(t) = <G(P_k, P_k)> - <G(P_k+1, P_k+1)>
+ *                 (= C_kk + sum_{i>k} (C_ik + C_ki), eq:cdecomp),
+ *   row m-1:      <G(P_m-1, P_m-1)> (the stochastic or point estimate of the
+ *                 levels the last piece spans),
+ *   row m (when exact_top = 1): eq:G_LL:exact of the top level
+ *                 (mglma_contract_top),
+ * nrow = m + exact_top.  Synchronising.  Errors: ARG, NO_SUBSPACE, NO_TOP. */
+int mglma_contract_levels(mglma_ctx* ctx, int kind, int nsrc, const int* t_src, const double* fine_dev,
+                          int ncoarse, const double* const* coarse_dev, int exact_top, double* G_host);
 
 #ifdef __cplusplus
 }

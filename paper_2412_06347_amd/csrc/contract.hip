@@ -244,3 +244,292 @@ extern "C" int mglma_contract_stoch_coarse(mglma_ctx* c, const double* ci, const
     if (!c->have_subspace) return MGLMA_ERR_NO_SUBSPACE;
     return coarse_contract(c, ci, cj, stoch_terms((double)c->geo.V3), tn, C);
 }
+
+// ---------------------------------------------------------------------------
+// Source-averaged two-point functions and level terms (eq:C_ij level sums,
+// eq:cdecomp, eq:C_stoch, eq:timetrans).
+//
+// Stage 1 (one launch per route): workgroup (x0, chunk, source n, pair p)
+// adds the weighted densities of the sites of time slice x0 in its chunk
+// and writes one partial sum part[p][n][x0][chunk].  The chunking depends on
+// the lattice only, so a source's partials do not depend on which other
+// sources share the launch.
+// Stage 2: one thread per (row, t) adds the partials of every source in
+// source order at x0 = (t_src[n] + t) mod L0, forms the level difference
+// G(P_row) - G(P_row+1) where asked, and scales by 1/nsrc.
+// ---------------------------------------------------------------------------
+#define LV_MAXPAIR 8
+#define LV_MAXCHUNK 32
+#define LV_MAXSRC 512
+
+struct PairSet {
+    const double2* pi[LV_MAXPAIR];
+    const double2* pj[LV_MAXPAIR];
+};
+struct SrcTimes {
+    int t[LV_MAXSRC];
+};
+
+// chunks per time slice: about 1024 fine sites or 16 coarse sites per chunk
+static int fine_chunks(const Geo& g) {
+    int n = g.V3 / 1024;
+    return n < 1 ? 1 : (n > LV_MAXCHUNK ? LV_MAXCHUNK : n);
+}
+static int coarse_chunks(const Geo& g) {
+    int n = (g.V1 / g.L1[0]) / 16;
+    return n < 1 ? 1 : (n > LV_MAXCHUNK ? LV_MAXCHUNK : n);
+}
+
+// workgroup sum of one complex per thread (256 threads), fixed order
+__device__ __forceinline__ double2 wg_sum256(double re, double im) {
+    __shared__ double sre[256], sim[256];
+    sre[threadIdx.x] = re;
+    sim[threadIdx.x] = im;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            sre[threadIdx.x] += sre[threadIdx.x + o];
+            sim[threadIdx.x] += sim[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    return make_double2(sre[0], sim[0]);
+}
+
+// grid (L0 * nchunk, nsrc, npair), block 256; fields of source n start at
+// column n * ncol of each piece; part index ((pair0 + p) * nsrc + n) * L0 + x0,
+// times LV_MAXCHUNK, plus the chunk
+__global__ __launch_bounds__(256) void k_fine_slice_part(Geo g, int nchunk, int ncol, int nsrc, int pair0, PairSet P,
+                                                         TermList T, double2* __restrict__ part) {
+    const int x0 = blockIdx.x / nchunk, ch = blockIdx.x - x0 * nchunk;
+    const int n = blockIdx.y, p = blockIdx.z;
+    const int b0 = g.b[0], y0 = x0 / b0, l0 = x0 - y0 * b0;
+    const int b123 = g.b[1] * g.b[2] * g.b[3], rowsz = g.V1 / g.L1[0];
+    const long tot = (long)rowsz * b123;
+    const int e0 = (int)(tot * ch / nchunk), e1 = (int)(tot * (ch + 1) / nchunk);
+    const size_t V = g.V;
+    const double2* pi = P.pi[p] + (size_t)n * ncol * 12 * V;
+    const double2* pj = P.pj[p] + (size_t)n * ncol * 12 * V;
+    double re = 0.0, im = 0.0;
+    for (int e = e0 + (int)threadIdx.x; e < e1; e += 256) {
+        const int kb = e / b123, lo = e - kb * b123;
+        const int i = (y0 * rowsz + kb) * g.Vb + l0 * b123 + lo;
+        cx<double> tot_s = cmk(0.0, 0.0);
+        for (int q = 0; q < T.n; ++q) {
+            const Term tm = T.t[q];
+            const double2* A = pi + (size_t)tm.a * 12 * V + i;
+            const double2* B = pj + (size_t)tm.b * 12 * V + i;
+            cx<double> s = cmk(0.0, 0.0);
+            for (int sp = 0; sp < 4; ++sp) {
+                int tc;
+                double cr, ci;
+                gk_row(tm.k, sp, &tc, &cr, &ci);
+                cx<double> acc = cmk(0.0, 0.0);
+                for (int col = 0; col < 3; ++col)
+                    cjmac(acc, ldc<double2, double>(B + (size_t)(3 * sp + col) * V),
+                          ldc<double2, double>(A + (size_t)(3 * tc + col) * V));
+                s = s + cmk(cr, ci) * acc;
+            }
+            tot_s = tot_s + cmk(tm.cre, tm.cim) * s;
+        }
+        re += tot_s.re;
+        im += tot_s.im;
+    }
+    const double2 v = wg_sum256(re, im);
+    if (threadIdx.x == 0)
+        part[((((size_t)(pair0 + p) * nsrc + n) * g.L[0] + x0) * LV_MAXCHUNK) + ch] = v;
+}
+
+// grid (L0 * nchunk, nsrc, npair), block 256 (4 wavefronts over the coarse
+// sites of the chunk, lanes over the Nv x Nv entries of (gamma5 gamma_k)_1)
+__global__ __launch_bounds__(256) void k_coarse_slice_part(Geo g, int Nv, int nchunk, int ncol, int nsrc, int pair0,
+                                                           const double2* __restrict__ G1, PairSet P, TermList T,
+                                                           double2* __restrict__ part) {
+    const int x0 = blockIdx.x / nchunk, ch = blockIdx.x - x0 * nchunk;
+    const int n = blockIdx.y, p = blockIdx.z;
+    const int b0 = g.b[0], y0 = x0 / b0, t = x0 - y0 * b0;
+    const int rowsz = g.V1 / g.L1[0];
+    const int ys0 = (int)((long)rowsz * ch / nchunk), ys1 = (int)((long)rowsz * (ch + 1) / nchunk);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nc = 2 * Nv;
+    const size_t V1 = g.V1;
+    const double2* ci = P.pi[p] + (size_t)n * ncol * V1 * nc;
+    const double2* cj = P.pj[p] + (size_t)n * ncol * V1 * nc;
+    double re = 0.0, im = 0.0;
+    for (int ys = ys0 + w; ys < ys1; ys += 4) {
+        const int y = y0 * rowsz + ys;
+        for (int q = 0; q < T.n; ++q) {
+            const Term tm = T.t[q];
+            const double2* Gb = G1 + (((size_t)y * b0 + t) * 3 + (tm.k - 1)) * Nv * Nv;
+            const double2* u = cj + ((size_t)tm.b * V1 + y) * nc;
+            const double2* v = ci + ((size_t)tm.a * V1 + y) * nc;
+            // u^+ Gamma v = u0^+ Gb v1 - conj(v0^+ Gb u1), lane share
+            cx<double> s1 = cmk(0.0, 0.0), s2 = cmk(0.0, 0.0);
+            for (int cd = lane; cd < Nv * Nv; cd += 64) {
+                const int c = cd / Nv, d = cd - c * Nv;
+                const cx<double> gcd = ldc<double2, double>(Gb + cd);
+                cjmac(s1, ldc<double2, double>(u + c), gcd * ldc<double2, double>(v + Nv + d));
+                cjmac(s2, ldc<double2, double>(v + c), gcd * ldc<double2, double>(u + Nv + d));
+            }
+            const cx<double> val = cmk(tm.cre, tm.cim) * (s1 - conj(s2));
+            re += val.re;
+            im += val.im;
+        }
+    }
+    const double2 v = wg_sum256(re, im);
+    if (threadIdx.x == 0)
+        part[((((size_t)(pair0 + p) * nsrc + n) * g.L[0] + x0) * LV_MAXCHUNK) + ch] = v;
+}
+
+// out[row][t] (+)= (1/ntot) sum_n [S(row, n, x_n) - diff * S(row + 1, n, x_n)],
+// S(p, n, x) = sum_{c < nch[p]} part[p][n][x][c], x_n = (t_src[n] + t) mod L0
+struct PairChunks {
+    int nch[LV_MAXPAIR];
+};
+__global__ void k_levels_finish(int L0, int nrow, int npair, int nsrc, int diff, SrcTimes ts, PairChunks pc,
+                                const double2* __restrict__ part, double scale, int accumulate,
+                                double2* __restrict__ out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nrow * L0) return;
+    const int row = e / L0, t = e - row * L0;
+    double re = 0.0, im = 0.0;
+    for (int n = 0; n < nsrc; ++n) {
+        int x = ts.t[n] + t;
+        x = x >= L0 ? x - L0 : x;
+        for (int q = 0; q < 2; ++q) {
+            const int p = row + q;
+            if (q == 1 && (!diff || p >= npair)) break;
+            const double sg = q == 0 ? 1.0 : -1.0;
+            const double2* pp = part + (((size_t)p * nsrc + n) * L0 + x) * LV_MAXCHUNK;
+            for (int c = 0; c < pc.nch[p]; ++c) {
+                re += sg * pp[c].x;
+                im += sg * pp[c].y;
+            }
+        }
+    }
+    double2 o = make_double2(scale * re, scale * im);
+    if (accumulate) {
+        o.x += out[e].x;
+        o.y += out[e].y;
+    }
+    out[e] = o;
+}
+
+// Partials of every pair for sources [0, nsrc) of the given pieces into part
+// (npair * nsrc * L0 * LV_MAXCHUNK complex) and the chunk counts.
+static int slice_partials(mglma_ctx* c, const TermList& T, int ncol, int nsrc, int nfine, int npair,
+                          const PairSet& P, double2* part, PairChunks* pc) {
+    const Geo& g = c->geo;
+    const int nchf = fine_chunks(g), nchc = coarse_chunks(g);
+    for (int p = 0; p < npair; ++p) pc->nch[p] = p < nfine ? nchf : nchc;
+    if (nfine > 0) {
+        hipLaunchKernelGGL(k_fine_slice_part, dim3(g.L[0] * nchf, nsrc, nfine), dim3(256), 0, c->stream, g, nchf,
+                           ncol, nsrc, 0, P, T, part);
+        HIP_TRY(hipGetLastError());
+    }
+    if (npair > nfine) {
+        PairSet Q;
+        for (int p = 0; p < LV_MAXPAIR; ++p) {
+            Q.pi[p] = p + nfine < LV_MAXPAIR ? P.pi[p + nfine] : nullptr;
+            Q.pj[p] = p + nfine < LV_MAXPAIR ? P.pj[p + nfine] : nullptr;
+        }
+        hipLaunchKernelGGL(k_coarse_slice_part, dim3(g.L[0] * nchc, nsrc, npair - nfine), dim3(256), 0, c->stream, g,
+                           c->Nv, nchc, ncol, nsrc, nfine, (const double2*)c->G1, Q, T, part);
+        HIP_TRY(hipGetLastError());
+    }
+    return MGLMA_OK;
+}
+
+static int check_sources(mglma_ctx* c, int kind, int nsrc, const int* t_src, TermList* T, int* ncol) {
+    if (kind != MGLMA_SRC_POINT && kind != MGLMA_SRC_STOCH) return MGLMA_ERR_ARG;
+    if (nsrc < 1 || nsrc > LV_MAXSRC || !t_src) return MGLMA_ERR_ARG;
+    for (int n = 0; n < nsrc; ++n)
+        if (t_src[n] < 0 || t_src[n] >= c->L[0]) return MGLMA_ERR_ARG;
+    *T = kind == MGLMA_SRC_POINT ? point_terms() : stoch_terms((double)c->geo.V3);
+    *ncol = kind == MGLMA_SRC_POINT ? 12 : 4;
+    return MGLMA_OK;
+}
+
+// Shared body of mglma_contract_levels and its allocation-free variant:
+// part holds at least npair * nsb * L0 * LV_MAXCHUNK complex, out_dev the
+// nrow * L0 result; sources are processed nsb at a time.
+static int levels_body(mglma_ctx* c, const TermList& T, int ncol, int nsrc, const int* t_src, int nfine, int npair,
+                       const PairSet& P, int diff, int nrow, int nsb, double2* part, double2* out_dev) {
+    const int L0 = c->L[0];
+    for (int n0 = 0; n0 < nsrc; n0 += nsb) {
+        const int nb = nsrc - n0 < nsb ? nsrc - n0 : nsb;
+        PairSet Pn;
+        const size_t fstride = (size_t)ncol * 12 * c->geo.V, cstride = (size_t)ncol * c->geo.V1 * c->nc;
+        for (int p = 0; p < LV_MAXPAIR; ++p) {
+            const size_t off = (size_t)n0 * (p < nfine ? fstride : cstride);
+            Pn.pi[p] = p < npair ? P.pi[p] + off : nullptr;
+            Pn.pj[p] = p < npair ? P.pj[p] + off : nullptr;
+        }
+        PairChunks pc;
+        MG_TRY(slice_partials(c, T, ncol, nb, nfine, npair, Pn, part, &pc));
+        SrcTimes ts;
+        for (int n = 0; n < nb; ++n) ts.t[n] = t_src[n0 + n];
+        hipLaunchKernelGGL(k_levels_finish, dim3((nrow * L0 + 127) / 128), dim3(128), 0, c->stream, L0, nrow, npair,
+                           nb, diff, ts, pc, (const double2*)part, 1.0 / nsrc, n0 > 0 ? 1 : 0, out_dev);
+        HIP_TRY(hipGetLastError());
+    }
+    return MGLMA_OK;
+}
+
+static int levels_args(mglma_ctx* c, int kind, int nsrc, const int* t_src, const double* fine, int ncoarse,
+                       const double* const* coarse, int exact_top, double* G_host, TermList* T, int* ncol,
+                       PairSet* P, int* nfine, int* npair) {
+    if (!c || !G_host || ncoarse < 0 || (ncoarse > 0 && !coarse)) return MGLMA_ERR_ARG;
+    MG_TRY(check_sources(c, kind, nsrc, t_src, T, ncol));
+    *nfine = fine ? 1 : 0;
+    *npair = *nfine + ncoarse;
+    if (*npair < 1 || *npair > LV_MAXPAIR) return MGLMA_ERR_ARG;
+    if (ncoarse > 0 && !c->have_subspace) return MGLMA_ERR_NO_SUBSPACE;
+    if (exact_top && !c->have_top) return MGLMA_ERR_NO_TOP;
+    for (int k = 0; k < ncoarse; ++k)
+        if (!coarse[k]) return MGLMA_ERR_ARG;
+    for (int p = 0; p < LV_MAXPAIR; ++p) {
+        const double* f = p < *nfine ? fine : (p < *npair ? coarse[p - *nfine] : nullptr);
+        P->pi[p] = P->pj[p] = (const double2*)f;
+    }
+    return MGLMA_OK;
+}
+
+extern "C" int mglma_contract_levels(mglma_ctx* c, int kind, int nsrc, const int* t_src, const double* fine,
+                                     int ncoarse, const double* const* coarse, int exact_top, double* G_host) {
+    TermList T;
+    PairSet P;
+    int ncol, nfine, npair;
+    MG_TRY(levels_args(c, kind, nsrc, t_src, fine, ncoarse, coarse, exact_top, G_host, &T, &ncol, &P, &nfine,
+                       &npair));
+    const int L0 = c->L[0], nrow = npair + (exact_top ? 1 : 0);
+    double2 *part, *out;
+    MG_TRY(mg_scratch(c, 28, (size_t)npair * nsrc * L0 * LV_MAXCHUNK * 16, (void**)&part));
+    MG_TRY(mg_scratch(c, 29, (size_t)nrow * L0 * 16 + 256, (void**)&out));
+    MG_TRY(levels_body(c, T, ncol, nsrc, t_src, nfine, npair, P, 1, npair, nsrc, part, out));
+    if (exact_top) MG_TRY(mg_top_corr(c, out + (size_t)npair * L0));
+    HIP_TRY(hipMemcpyAsync(G_host, out, (size_t)nrow * L0 * 16, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return MGLMA_OK;
+}
+
+extern "C" int mglma_contract_pair(mglma_ctx* c, int kind, int nsrc, const int* t_src, int coarse,
+                                   const double* psi_i, const double* psi_j, double* G_host) {
+    if (!c || !psi_i || !psi_j || !G_host || (coarse != 0 && coarse != 1)) return MGLMA_ERR_ARG;
+    TermList T;
+    int ncol;
+    MG_TRY(check_sources(c, kind, nsrc, t_src, &T, &ncol));
+    if (coarse && !c->have_subspace) return MGLMA_ERR_NO_SUBSPACE;
+    PairSet P;
+    for (int p = 0; p < LV_MAXPAIR; ++p) P.pi[p] = P.pj[p] = nullptr;
+    P.pi[0] = (const double2*)psi_i;
+    P.pj[0] = (const double2*)psi_j;
+    const int L0 = c->L[0];
+    double2 *part, *out;
+    MG_TRY(mg_scratch(c, 28, (size_t)nsrc * L0 * LV_MAXCHUNK * 16, (void**)&part));
+    MG_TRY(mg_scratch(c, 29, (size_t)L0 * 16 + 256, (void**)&out));
+    MG_TRY(levels_body(c, T, ncol, nsrc, t_src, coarse ? 0 : 1, 1, P, 0, 1, nsrc, part, out));
+    HIP_TRY(hipMemcpyAsync(G_host, out, (size_t)L0 * 16, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return MGLMA_OK;
+}

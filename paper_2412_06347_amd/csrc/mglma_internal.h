@@ -298,7 +298,9 @@ struct mglma_ctx {
     // optional launch timing of the SAP half-sweeps: event pairs on the stream
     bool sap_timing = false;
     std::vector<hipEvent_t> sap_ev;
-    size_t sap_ev_used = 0;
+    size_t sap_ev_used = 0;          // events of complete (recorded) pairs
+    double sap_ms_acc = 0.0;         // durations of pairs folded in before reuse
+    long sap_n_acc = 0;
 
     static constexpr int NSCR = 40;
     Scratch scr[NSCR];
@@ -405,6 +407,9 @@ __host__ __device__ inline void gk_row(int k, int s, int* t, double* cre, double
     *cre = re[k - 1][s];
     *cim = im[k - 1][s];
 }
+
+// eq:G_LL:exact into out_dev[L0] (complex, device), enqueued on the context's stream
+int mg_top_corr(mglma_ctx* c, double2* out_dev);
 
 // out[j][i] = <X_i, Y_j> for FP64 vector blocks (kx, ky <= 64), complex, one launch + finish
 int mg_gram64(mglma_ctx* c, const void* X, int kx, const void* Y, int ky, size_t n, double* out_dev);

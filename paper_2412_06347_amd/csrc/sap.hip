@@ -268,6 +268,9 @@ int mg_sap_setup(mglma_ctx* c) {
 
 // ncycle SAP cycles on M z = r (FP32 vectors, z updated in place); links and
 // clover from the FP16 (prec F16) or FP32 (prec F32) copies
+#define SAP_EV_MAX 4096
+static int sap_fold_events(mglma_ctx* c);
+
 int mg_sap(mglma_ctx* c, int prec, const void* r, void* z, int nrhs, int ncycle, int nmr) {
     if (nrhs == 0 || ncycle == 0) return MGLMA_OK;
     MG_TRY(mg_sap_setup(c));
@@ -283,6 +286,9 @@ int mg_sap(mglma_ctx* c, int prec, const void* r, void* z, int nrhs, int ncycle,
             if (npad > 0x7fffffffLL) return MGLMA_ERR_SHAPE;
             hipEvent_t ev[2] = {nullptr, nullptr};
             if (c->sap_timing) {
+                // at most SAP_EV_MAX recorded pairs: fold the finished ones
+                // into the running sum before reusing their events
+                if (c->sap_ev_used + 2 > 2 * SAP_EV_MAX) MG_TRY(sap_fold_events(c));
                 while (c->sap_ev.size() < c->sap_ev_used + 2) {
                     hipEvent_t e;
                     HIP_TRY(hipEventCreate(&e));
@@ -290,7 +296,6 @@ int mg_sap(mglma_ctx* c, int prec, const void* r, void* z, int nrhs, int ncycle,
                 }
                 ev[0] = c->sap_ev[c->sap_ev_used];
                 ev[1] = c->sap_ev[c->sap_ev_used + 1];
-                c->sap_ev_used += 2;
                 HIP_TRY(hipEventRecord(ev[0], c->stream));
             }
             if (prec == MGLMA_F16)
@@ -302,31 +307,52 @@ int mg_sap(mglma_ctx* c, int prec, const void* r, void* z, int nrhs, int ncycle,
                                    (const float2*)r, (float2*)z, (const float2*)c->U32, (const float2*)c->C32,
                                    (float)c->kappa, bl, nblk, nrhs, (int)npad, nmr);
             HIP_TRY(hipGetLastError());
-            if (ev[1]) HIP_TRY(hipEventRecord(ev[1], c->stream));
+            if (ev[1]) {
+                HIP_TRY(hipEventRecord(ev[1], c->stream));
+                c->sap_ev_used += 2;   // counted once both events are recorded
+            }
         }
+    return MGLMA_OK;
+}
+
+static void sap_clear_timing(mglma_ctx* c) {
+    c->sap_ev_used = 0;
+    c->sap_ms_acc = 0.0;
+    c->sap_n_acc = 0;
+}
+
+// add the durations of the recorded pairs to the running sum and free the pairs
+static int sap_fold_events(mglma_ctx* c) {
+    hipError_t e = hipStreamSynchronize(c->stream);
+    for (size_t k = 0; e == hipSuccess && k + 1 < c->sap_ev_used; k += 2) {
+        float t = 0.f;
+        e = hipEventElapsedTime(&t, c->sap_ev[k], c->sap_ev[k + 1]);
+        c->sap_ms_acc += t;
+        c->sap_n_acc += 1;
+    }
+    c->sap_ev_used = 0;
+    if (e != hipSuccess) {
+        sap_clear_timing(c);
+        mg_last_hip_error(e, "SAP launch timing", __FILE__, __LINE__);
+        return MGLMA_ERR_HIP;
+    }
     return MGLMA_OK;
 }
 
 extern "C" int mglma_sap_timing(mglma_ctx* c, int enable) {
     if (!c) return MGLMA_ERR_ARG;
+    sap_clear_timing(c);
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->sap_timing = enable != 0;
-    c->sap_ev_used = 0;
     return MGLMA_OK;
 }
 
 extern "C" int mglma_sap_elapsed(mglma_ctx* c, double* ms, int* launches) {
     if (!c || !ms || !launches) return MGLMA_ERR_ARG;
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    double tot = 0.0;
-    for (size_t k = 0; k + 1 < c->sap_ev_used; k += 2) {
-        float t = 0.f;
-        HIP_TRY(hipEventElapsedTime(&t, c->sap_ev[k], c->sap_ev[k + 1]));
-        tot += t;
-    }
-    *ms = tot;
-    *launches = (int)(c->sap_ev_used / 2);
-    c->sap_ev_used = 0;
+    MG_TRY(sap_fold_events(c));
+    *ms = c->sap_ms_acc;
+    *launches = (int)c->sap_n_acc;
+    sap_clear_timing(c);
     return MGLMA_OK;
 }
 

@@ -306,19 +306,29 @@ __global__ __launch_bounds__(256) void k_top_corr(const double2* __restrict__ A,
     if (threadIdx.x == 0) out[t] = make_double2(w * red[0].x, w * red[0].y);
 }
 
-extern "C" int mglma_contract_top(mglma_ctx* c, double* G_host) {
-    if (!c || !G_host) return MGLMA_ERR_ARG;
+// eq:G_LL:exact into out_dev[L0] (complex, device), enqueued on the stream
+int mg_top_corr(mglma_ctx* c, double2* out_dev) {
     if (!c->have_top) return MGLMA_ERR_NO_TOP;
     const int L0 = c->L[0], r = c->r;
     const double L3 = (double)c->geo.V3;
     const size_t ng = (size_t)L0 * 3 * r * r;
-    double2 *A, *out;
-    MG_TRY(mg_scratch(c, 5, 2 * ng * 16 + (size_t)L0 * 16, (void**)&A));
+    double2* A;
+    MG_TRY(mg_scratch(c, 5, 2 * ng * 16, (void**)&A));
     double2* AT = A + ng;
-    out = AT + ng;
     hipLaunchKernelGGL(k_top_A, dim3(L0 * 3), dim3(256), 0, c->stream, c->topG, c->topQi, r, A, AT);
-    hipLaunchKernelGGL(k_top_corr, dim3(L0), dim3(256), 0, c->stream, A, AT, L0, r, -1.0 / (3.0 * L0 * L3), out);
+    hipLaunchKernelGGL(k_top_corr, dim3(L0), dim3(256), 0, c->stream, A, AT, L0, r, -1.0 / (3.0 * L0 * L3),
+                       out_dev);
     HIP_TRY(hipGetLastError());
+    return MGLMA_OK;
+}
+
+extern "C" int mglma_contract_top(mglma_ctx* c, double* G_host) {
+    if (!c || !G_host) return MGLMA_ERR_ARG;
+    if (!c->have_top) return MGLMA_ERR_NO_TOP;
+    const int L0 = c->L[0];
+    double2* out;
+    MG_TRY(mg_scratch(c, 29, (size_t)L0 * 16 + 256, (void**)&out));
+    MG_TRY(mg_top_corr(c, out));
     HIP_TRY(hipMemcpyAsync(G_host, out, (size_t)L0 * 16, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     return MGLMA_OK;

@@ -15,6 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmglma.so")
 
 F64, F32, F16, BF16 = 0, 1, 2, 3
+SRC_POINT, SRC_STOCH = 0, 1
 SMOOTH_MR, SMOOTH_CAGCR, SMOOTH_SAP = 0, 1, 2
 
 SYMBOLS = [
@@ -32,6 +33,7 @@ SYMBOLS = [
     "mglma_build_level2", "mglma_export_level2_op", "mglma_level2_restrict", "mglma_level2_prolong",
     "mglma_level2_apply", "mglma_level2_solve", "mglma_level2_pieces", "mglma_save", "mglma_load",
     "mglma_adaptive_setup", "mglma_sap_smooth", "mglma_sap_timing", "mglma_sap_elapsed",
+    "mglma_contract_pair", "mglma_contract_levels",
 ]
 
 
@@ -367,3 +369,26 @@ class Context:
         out = np.zeros((self.L[0], 2), dtype=np.float64)
         _check(lib().mglma_contract_top(self._ctx, out.ctypes.data_as(C.c_void_p)))
         return out[:, 0] + 1j * out[:, 1]
+
+    def contract_pair(self, kind, t_src, psi_i, psi_j, coarse=False):
+        """Source-averaged two-point function of two pieces (eq:C_stoch2 /
+        eq:tmr columns of nsrc = len(t_src) sources)."""
+        t = np.ascontiguousarray(t_src, dtype=np.int32)
+        out = np.zeros((self.L[0], 2), dtype=np.float64)
+        _check(lib().mglma_contract_pair(self._ctx, int(kind), len(t), t.ctypes.data_as(C.POINTER(C.c_int)),
+                                         int(bool(coarse)), _ptr(psi_i), _ptr(psi_j),
+                                         out.ctypes.data_as(C.c_void_p)))
+        return out[:, 0] + 1j * out[:, 1]
+
+    def contract_levels(self, kind, t_src, fine=None, coarse=(), exact_top=False):
+        """Level terms from cumulative pieces [fine] + coarse, averaged over the
+        sources; rows as documented for mglma_contract_levels."""
+        t = np.ascontiguousarray(t_src, dtype=np.int32)
+        nco = len(coarse)
+        arr = (C.c_void_p * max(nco, 1))(*[c.data_ptr() for c in coarse])
+        nrow = (1 if fine is not None else 0) + nco + (1 if exact_top else 0)
+        out = np.zeros((max(nrow, 1), self.L[0], 2), dtype=np.float64)
+        _check(lib().mglma_contract_levels(self._ctx, int(kind), len(t), t.ctypes.data_as(C.POINTER(C.c_int)),
+                                           _ptr(fine), nco, arr, int(bool(exact_top)),
+                                           out.ctypes.data_as(C.c_void_p)))
+        return out[:nrow, :, 0] + 1j * out[:nrow, :, 1]

@@ -142,18 +142,10 @@ class Engine:
             ctx.coarse_pieces(eta, cg, ct, self.coarse_params)
             out, k = [], 0
             for r in reqs:
-                L0 = np.zeros(L[0], dtype=complex)
-                L1 = np.zeros(L[0], dtype=complex)
-                for n in range(r.n_src):
-                    s = slice(4 * (k + n), 4 * (k + n) + 4)
-                    t = int(tn[k + n])
-                    g_all = ctx.contract_stoch(x[s], x[s], t)
-                    g_ge1 = ctx.contract_stoch_coarse(cg[s], cg[s], t)
-                    g_top = ctx.contract_stoch_coarse(ct[s], ct[s], t)
-                    L0 += g_all - g_ge1
-                    L1 += g_ge1 - g_top
-                L0 /= r.n_src
-                L1 /= r.n_src
+                # level terms and source mean in the library (eq:C_stoch)
+                s = slice(4 * k, 4 * (k + r.n_src))
+                lv = ctx.contract_levels(mglma.SRC_STOCH, tn[k:k + r.n_src], fine=x[s], coarse=[cg[s], ct[s]])
+                L0, L1 = lv[0], lv[1]
                 st = stats[4 * k: 4 * (k + r.n_src)]
                 out.append(dict(L0=L0, L1=L1, L2=self.G_top.copy(), G=L0 + L1 + self.G_top,
                                 max_true_rel_res=max(q["true_rel_res"] for q in st),

@@ -52,3 +52,12 @@ def test_strerror_and_argument_errors_without_gpu():
                         (ctypes.c_double * 4)(-1, 1, 1, 1))
     h = ctypes.c_void_p()
     assert lib.mglma_create(ctypes.byref(h), ctypes.byref(lat), None) == -2   # 4 does not divide 6
+
+
+def test_level_calls_reject_null_context_without_gpu():
+    from paper_2412_06347_amd import mglma
+    lib = mglma.lib()
+    t = (ctypes.c_int * 1)(0)
+    out = (ctypes.c_double * 64)()
+    assert lib.mglma_contract_levels(None, 1, 1, t, None, 0, None, 0, out) == -1
+    assert lib.mglma_contract_pair(None, 1, 1, t, 0, None, None, out) == -1
