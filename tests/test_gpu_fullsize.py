@@ -16,9 +16,15 @@ against the oracle on sampled outputs and by properties that hold at any size:
   pieces to 1e-10 under the oracle's stencil apply; with level 2 (8^4
   blocks): D_2 on sampled columns against R_1 D_1 T_1, the K-cycle level-1
   solve and the level-2 solve to 1e-10 under the oracle's stencil applies;
+* the step's contractions slice by slice: the full point correlator against
+  the oracle's contraction of the re-checked solution on sampled slices,
+  (gamma5 gamma_k)_1 on 32 sampled blocks against the oracle's coarse gammas
+  of its own Gram-Schmidt basis, and eq:G_LL:exact against the oracle's
+  formula from Q_2 and (gamma5 gamma_k)_2 built in numpy from the exported
+  D_1 and coarse gammas;
 * the SAP smoother of the benchmark (12 right-hand sides, FP16 links, its
-  block steps): one cycle, compared on a sampled colour-0 block of the last
-  right-hand side (the colour-1 half-sweep does not change colour-0 blocks)
+  block steps): one cycle, compared on four sampled colour-0 blocks of three
+  right-hand sides (the colour-1 half-sweep does not change colour-0 blocks)
   with the oracle's block solve.
 """
 import numpy as np
@@ -150,7 +156,8 @@ def test_fullsize_bench_solve(ens):
     res = np.linalg.norm((Qm - lam[:, None, None] * modes).reshape(2, -1), axis=1)
     print("eigensolver modes 0, 15: lambda", lam, "oracle residual", res)
     assert res.max() <= 1e-12
-    del D1h, Qm
+    D1h_keep = D1h
+    del Qm
     stats, levels = P.step(bench.mixed_params(mglma))
     torch.cuda.synchronize()
     res = [s["true_rel_res"] for s in stats]
@@ -166,7 +173,67 @@ def test_fullsize_bench_solve(ens):
     rel = np.linalg.norm(r.reshape(2, -1), axis=1) / np.linalg.norm(bs.reshape(2, -1), axis=1)
     print("oracle true rel res", rel)
     assert np.all(rel <= 1.05e-10)
-    assert all(np.all(np.isfinite(v)) for v in levels.values())
+    # -- the step's contractions, slice by slice
+    # (a) the full correlator G(S) = L0 + L1 + L2pt (the library's level rows
+    #     of the point source) against the oracle's point contraction of the
+    #     same (re-checked) solution on sampled time slices
+    xall = from_dev(out).reshape(12, *L, 4, 3)
+    del out
+    ts = [0, 1, 17, 47]
+    ref = estimators.point_correlator(xall[:, ts], xall[:, ts], 0)
+    got = (levels["L0"] + levels["L1"] + levels["L2pt"])[ts]
+    err = np.abs(got - ref) / np.abs(ref)
+    print("point correlator per slice vs oracle", err)
+    assert err.max() < 1e-11
+    del xall
+    # (b) (gamma5 gamma_k)_1 on 32 sampled blocks against the oracle's
+    #     coarse gammas of the oracle's Gram-Schmidt basis of those blocks
+    Nv, nc = P.ctx.nc // 2, P.ctx.nc
+    bl = osub.Blocking(L, B)
+    tvc = torch.empty((Nv, P.ctx.V, 4, 3, 2), dtype=torch.float64, device="cuda")
+    P.ctx.export_fields(P.tv, tvc)
+    tvl = from_dev(tvc).reshape(Nv, *L, 4, 3)
+    del tvc
+    ys = np.random.default_rng(99).choice(bl.V1, 32, replace=False)
+    yc = np.array(np.unravel_index(ys, bl.L1)).T
+    tb = np.stack([tvl[:, y[0] * B[0]:(y[0] + 1) * B[0], y[1] * B[1]:(y[1] + 1) * B[1],
+                       y[2] * B[2]:(y[2] + 1) * B[2], y[3] * B[3]:(y[3] + 1) * B[3]] for y in yc])
+    del tvl
+    phi = np.empty((len(ys), 2, Nv, *B, 2, 3), dtype=np.complex128)
+    for a in range(2):
+        q = osub.gram_schmidt(tb[..., 2 * a:2 * a + 2, :].reshape(len(ys), Nv, -1))
+        phi[:, a] = q.reshape(len(ys), Nv, *B, 2, 3)
+    import types
+    sub = types.SimpleNamespace(bl=types.SimpleNamespace(V1=len(ys), b=B), phi=phi, Nv=Nv, nc=nc)
+    G1o = ocoarse.coarse_gammas(sub)
+    G1d = torch.empty((bl.V1, B[0], 3, Nv, Nv, 2), dtype=torch.float64, device="cuda")
+    P.ctx.export_coarse_gammas(G1d)
+    G1h = from_dev(G1d)
+    del G1d
+    e_g = np.abs(G1h[ys] - G1o[..., :Nv, Nv:]).max() / np.abs(G1o).max()
+    print("coarse gammas on 32 sampled blocks vs oracle %.2e" % e_g)
+    assert e_g < 1e-12
+    # (c) eq:G_LL:exact from Q_2 and (gamma5 gamma_k)_2 built in numpy from the
+    #     exported D_1 (Galerkin identity checked above), the step's top modes
+    #     and the exported coarse gammas
+    top = ocoarse.TopLevel(from_dev(P.modes), D1h_keep, nbr, Nv)
+    r = top.r
+    Wy = top.W.reshape(bl.V1, nc, r)
+    W0, W1 = Wy[:, :Nv], Wy[:, Nv:]
+    y0 = np.unravel_index(np.arange(bl.V1), bl.L1)[0]
+    G2 = np.zeros((L[0], 3, r, r), dtype=np.complex128)
+    for t in range(B[0]):
+        # W^+ [[0, Gb], [-Gb^+, 0]] W = A - A^+ with A = W0^+ Gb W1 (matrix products per site)
+        A = np.matmul(np.conj(np.swapaxes(W0, 1, 2))[:, None], np.matmul(G1h[:, t], W1[:, None]))
+        M = A - np.conj(np.swapaxes(A, -1, -2))
+        for yt in range(bl.L1[0]):
+            G2[yt * B[0] + t] = M[y0 == yt].sum(axis=0)
+    del G1h
+    ref = estimators.exact_top(top.Q2, G2, L)
+    got = levels["L2exact"]
+    err = np.abs(got - ref) / (np.abs(ref) + 1e-14 * np.abs(ref).max())
+    print("exact top per slice vs oracle: max %.2e" % err.max())
+    assert err.max() < 1e-10
 
 
 def test_fullsize_evenodd_and_transfers(ens):
@@ -339,8 +406,8 @@ def test_fullsize_sap_cycle(ens):
     del out, rd, zd
     bl = subspace.Blocking(L, B)
     rng = np.random.default_rng(97)
-    blocks = [y for y in rng.permutation(bl.V1) if sap.block_colour(bl, y) == 0][:1]
-    for q in (11,):
+    blocks = [y for y in rng.permutation(bl.V1) if sap.block_colour(bl, y) == 0][:4]
+    for q in (0, 5, 11):
         rl = dirac.fields_to_lattice(r[q:q + 1], L)[0]
         zl = dirac.fields_to_lattice(z0[q:q + 1], L)[0]
         rho = rl - D.M(zl[None])[0]
