@@ -461,6 +461,24 @@ int mglma_contract_pair(mglma_ctx* ctx, int kind, int nsrc, const int* t_src, in
  * nrow = m + exact_top.  Synchronising.  Errors: ARG, NO_SUBSPACE, NO_TOP. */
 int mglma_contract_levels(mglma_ctx* ctx, int kind, int nsrc, const int* t_src, const double* fine_dev,
                           int ncoarse, const double* const* coarse_dev, int exact_top, double* G_host);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * level rows as mglma_contract_levels with exact_top = 0 (rows 0..m-1,
+ * G_host [m][L0] complex; the exact top row needs a workspace of
+ * 6 L0 r^2 complex and stays with mglma_contract_levels / mglma_contract_top).
+ * The call allocates nothing: its partial sums and result live in a fixed
+ * 8 MiB device array that every context on the device shares (each device
+ * the library runs on holds one for the life of the process; its address is
+ * looked up when the first context on the device is created).  Sources are
+ * processed in passes that fit the array; m L0 (32 s + 1) complex values
+ * must fit 8 MiB for at least one source s, else SHAPE (m = number of
+ * pieces, 32 partial sums per time slice and piece), e.g. m L0 <= 15880.
+ * The array keeps the last call's contents; every value a call reads is
+ * written by that call first.  Calls that overlap on one device (two
+ * streams, two host threads) race on the array and must be serialised by
+ * the caller.  Synchronising.  Errors: ARG, SHAPE, NO_SUBSPACE, HIP.      */
+int mglma_contract_levels_noalloc(mglma_ctx* ctx, int kind, int nsrc, const int* t_src, const double* fine_dev,
+                                  int ncoarse, const double* const* coarse_dev, double* G_host);
 
 #ifdef __cplusplus
 }

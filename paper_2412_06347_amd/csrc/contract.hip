@@ -19,6 +19,8 @@
 // result does not depend on launch or batch composition.
 #include "mglma_internal.h"
 
+#include <mutex>
+
 struct Term {
     int a, b, k;      // field of set i, field of set j, gamma index
     double cre, cim;  // weight
@@ -530,6 +532,59 @@ extern "C" int mglma_contract_pair(mglma_ctx* c, int kind, int nsrc, const int* 
     MG_TRY(mg_scratch(c, 29, (size_t)L0 * 16 + 256, (void**)&out));
     MG_TRY(levels_body(c, T, ncol, nsrc, t_src, coarse ? 0 : 1, 1, P, 0, 1, nsrc, part, out));
     HIP_TRY(hipMemcpyAsync(G_host, out, (size_t)L0 * 16, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return MGLMA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free level assembly: the partial sums and the result live in a
+// fixed device array (each device that the library runs on holds its own
+// copy for the life of the process).  Its device address is looked up once
+// per device when the first context on that device is created; host code
+// uses only that address, never the array's name.
+// ---------------------------------------------------------------------------
+#define NOALLOC_BYTES ((size_t)8 << 20)
+#define NOALLOC_MAXDEV 64
+static __device__ __align__(256) double2 scratch[NOALLOC_BYTES / sizeof(double2)];
+static double2* noalloc_ptr[NOALLOC_MAXDEV];
+static std::mutex noalloc_mu;
+
+int mg_noalloc_init(int device) {
+    if (device < 0 || device >= NOALLOC_MAXDEV) return MGLMA_ERR_ARG;
+    std::lock_guard<std::mutex> lk(noalloc_mu);
+    if (noalloc_ptr[device]) return MGLMA_OK;
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return MGLMA_ERR_HIP;
+    noalloc_ptr[device] = (double2*)p;
+    return MGLMA_OK;
+}
+
+extern "C" int mglma_contract_levels_noalloc(mglma_ctx* c, int kind, int nsrc, const int* t_src,
+                                             const double* fine, int ncoarse, const double* const* coarse,
+                                             double* G_host) {
+    TermList T;
+    PairSet P;
+    int ncol, nfine, npair;
+    MG_TRY(levels_args(c, kind, nsrc, t_src, fine, ncoarse, coarse, 0, G_host, &T, &ncol, &P, &nfine, &npair));
+    if (c->device < 0 || c->device >= NOALLOC_MAXDEV) return MGLMA_ERR_ARG;
+    double2* base;
+    {
+        std::lock_guard<std::mutex> lk(noalloc_mu);
+        base = noalloc_ptr[c->device];
+    }
+    if (!base) return MGLMA_ERR_HIP;
+    const int L0 = c->L[0], nrow = npair;
+    const size_t cap = NOALLOC_BYTES / sizeof(double2);
+    const size_t out_n = ((size_t)nrow * L0 + 15) / 16 * 16;    // result first, 256-byte aligned partials
+    const size_t per_src = (size_t)npair * L0 * LV_MAXCHUNK;
+    if (out_n + per_src > cap) return MGLMA_ERR_SHAPE;            // L0 too long for the fixed workspace
+    size_t nsb = (cap - out_n) / per_src;
+    if (nsb > (size_t)nsrc) nsb = (size_t)nsrc;
+    double2* out = base;
+    double2* part = base + out_n;
+    MG_TRY(levels_body(c, T, ncol, nsrc, t_src, nfine, npair, P, 1, nrow, (int)nsb, part, out));
+    HIP_TRY(hipMemcpyAsync(G_host, out, (size_t)nrow * L0 * 16, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     return MGLMA_OK;
 }

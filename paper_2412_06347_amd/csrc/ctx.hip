@@ -187,6 +187,10 @@ extern "C" int mglma_create(mglma_ctx** out, const mglma_lattice* lat, void* str
     c->geo = make_geo(c->L, c->b, c->bc);
     c->stream = (hipStream_t)stream;
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return MGLMA_ERR_HIP; }
+    // device address of the fixed workspace of the allocation-free calls,
+    // looked up once per device (with that device current)
+    const int rc = mg_noalloc_init(c->device);
+    if (rc != MGLMA_OK) { delete c; return rc; }
     *out = c;
     return MGLMA_OK;
 }

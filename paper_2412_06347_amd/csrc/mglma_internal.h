@@ -408,6 +408,10 @@ __host__ __device__ inline void gk_row(int k, int s, int* t, double* cre, double
     *cim = im[k - 1][s];
 }
 
+// resolve (once per device, the device current) the address of the fixed
+// device workspace that the allocation-free entry points use
+int mg_noalloc_init(int device);
+
 // eq:G_LL:exact into out_dev[L0] (complex, device), enqueued on the context's stream
 int mg_top_corr(mglma_ctx* c, double2* out_dev);
 

@@ -33,7 +33,7 @@ SYMBOLS = [
     "mglma_build_level2", "mglma_export_level2_op", "mglma_level2_restrict", "mglma_level2_prolong",
     "mglma_level2_apply", "mglma_level2_solve", "mglma_level2_pieces", "mglma_save", "mglma_load",
     "mglma_adaptive_setup", "mglma_sap_smooth", "mglma_sap_timing", "mglma_sap_elapsed",
-    "mglma_contract_pair", "mglma_contract_levels",
+    "mglma_contract_pair", "mglma_contract_levels", "mglma_contract_levels_noalloc",
 ]
 
 
@@ -391,4 +391,16 @@ class Context:
         _check(lib().mglma_contract_levels(self._ctx, int(kind), len(t), t.ctypes.data_as(C.POINTER(C.c_int)),
                                            _ptr(fine), nco, arr, int(bool(exact_top)),
                                            out.ctypes.data_as(C.c_void_p)))
+        return out[:nrow, :, 0] + 1j * out[:nrow, :, 1]
+
+    def contract_levels_noalloc(self, kind, t_src, fine=None, coarse=()):
+        """contract_levels without the exact top row, through the entry point
+        that allocates nothing (fixed device workspace)."""
+        t = np.ascontiguousarray(t_src, dtype=np.int32)
+        nco = len(coarse)
+        arr = (C.c_void_p * max(nco, 1))(*[c.data_ptr() for c in coarse])
+        nrow = (1 if fine is not None else 0) + nco
+        out = np.zeros((max(nrow, 1), self.L[0], 2), dtype=np.float64)
+        _check(lib().mglma_contract_levels_noalloc(self._ctx, int(kind), len(t), t.ctypes.data_as(C.POINTER(C.c_int)),
+                                                   _ptr(fine), nco, arr, out.ctypes.data_as(C.c_void_p)))
         return out[:nrow, :, 0] + 1j * out[:nrow, :, 1]
