@@ -514,11 +514,12 @@ def serving(reqs_n=60, seed=7):
     srv.stop()
     st = srv.stats()
     res = max(r.result["max_true_rel_res"] for r in reqs)
-    print(json.dumps({"diagnostic": "serving mix: resident 16^3x32 and 24^3x48 ensembles, continuous batching",
+    print(json.dumps({"diagnostic": "serving mix: resident 16^3x32 and 24^3x48 ensembles, continuous batching "
+                                    "(right-hand sides join and leave between outer cycles)",
                       "setup_s": round(setup, 1), "slots": srv.slots,
                       "capacity_burst": {k: cap[k] for k in ("n", "solves", "solves_per_s", "p50_s", "p99_s")},
                       "poisson": {"requests_per_s": rate, "offered_solves_per_s": rate * mean_rhs,
-                                  **{k: st[k] for k in ("n", "solves", "solves_per_s", "p50_s", "p99_s", "batches")}},
+                                  **{k: st[k] for k in ("n", "solves", "solves_per_s", "p50_s", "p99_s", "cycles")}},
                       "max_true_rel_res": res}), flush=True)
 
 

@@ -376,6 +376,39 @@ int mglma_sap_elapsed(mglma_ctx* ctx, double* ms, int* launches);
  * NOT_CONVERGED (x holds the last iterate).                                 */
 int mglma_solve(mglma_ctx* ctx, const mglma_solve_params* p, const double* b_dev,
                 double* x_dev, int nrhs, mglma_solve_stats* stats);
+/* ---- resident right-hand-side slots (continuous batching) --------------- */
+/* A pool of nslots right-hand sides that join and leave a running solve
+ * between its outer cycles: the serving loop of the multigrid solves
+ * (requests that arrive while others are on the GPU join at the next cycle,
+ * converged right-hand sides leave at once).  Each slot holds its b, x and
+ * FP64 residual on the device (3 fine FP64 fields per slot, allocated at
+ * create and freed at destroy).
+ *   mglma_slots_load: copy nrhs sources b_dev (device layout, F64, [nrhs]
+ *     fields) into free slots, x = 0; their slot ids (0..nslots-1) are
+ *     written to the host array ids.  Synchronising.  Errors: ARG, SHAPE
+ *     (fewer than nrhs free slots).
+ *   mglma_slots_step: one outer cycle of mglma_solve for every running slot:
+ *     r / |r| in the p->inner precision, at most p->max_inner iterations of
+ *     the preconditioned FGCR (stopping early per right-hand side at the
+ *     relative reduction p->inner_tol), x += |r| e and r = b - M x in FP64.
+ *     A slot finishes when |r| <= p->tol |b| (state 2), with
+ *     MGLMA_ERR_NOT_CONVERGED after p->max_outer cycles or
+ *     MGLMA_ERR_NONFINITE; a slot's arithmetic is that of mglma_solve on it
+ *     alone whatever else runs.  status (host, may be NULL) receives the
+ *     state of every slot id: 0 free, 1 running, 2 converged, < 0 failed.
+ *     Synchronising.  Errors: ARG, NO_SUBSPACE (use_mg), HIP.
+ *   mglma_slots_take: copy the solutions of n finished slots to x_dev
+ *     ([n] fields, device layout, F64, in the order of ids) with their stats
+ *     (may be NULL) and free the slots.  Synchronising.  Errors: ARG (an id
+ *     free, running or repeated).
+ * A pool belongs to one context and is used from one host thread at a time.*/
+typedef struct mglma_slots mglma_slots;
+int  mglma_slots_create(mglma_ctx* ctx, int nslots, mglma_slots** out);
+void mglma_slots_destroy(mglma_slots* slots);
+int  mglma_slots_load(mglma_slots* slots, int nrhs, const double* b_dev, int* ids);
+int  mglma_slots_step(mglma_slots* slots, const mglma_solve_params* p, int* status);
+int  mglma_slots_take(mglma_slots* slots, int n, const int* ids, double* x_dev, mglma_solve_stats* stats);
+
 /* x = D_1^{-1} b on the coarse level (coarse fields, F64) to relative
  * residual p->tol; inner GCR uses the p->coarse operator inside FP64 defect
  * correction.  Synchronising.                                               */
@@ -461,6 +494,17 @@ int mglma_contract_pair(mglma_ctx* ctx, int kind, int nsrc, const int* t_src, in
  * nrow = m + exact_top.  Synchronising.  Errors: ARG, NO_SUBSPACE, NO_TOP. */
 int mglma_contract_levels(mglma_ctx* ctx, int kind, int nsrc, const int* t_src, const double* fine_dev,
                           int ncoarse, const double* const* coarse_dev, int exact_top, double* G_host);
+/* Source averages split over several calls (sources that are solved in
+ * parts, e.g. a request larger than the free right-hand-side slots): the
+ * rows 0..m-1 of mglma_contract_levels for the nsrc sources of this call,
+ * each source's rows multiplied by `weight` (1 / total number of sources for
+ * the mean of eq:C_stoch), added to the device array G_dev ([m][L0]
+ * complex) when accumulate = 1 or written to it when accumulate = 0.
+ * Asynchronous (enqueued on the context's stream).  Errors: ARG,
+ * NO_SUBSPACE.                                                             */
+int mglma_contract_levels_acc(mglma_ctx* ctx, int kind, int nsrc, const int* t_src, const double* fine_dev,
+                              int ncoarse, const double* const* coarse_dev, double weight, int accumulate,
+                              double* G_dev);
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * level rows as mglma_contract_levels with exact_top = 0 (rows 0..m-1,

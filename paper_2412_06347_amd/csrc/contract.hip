@@ -456,7 +456,9 @@ static int check_sources(mglma_ctx* c, int kind, int nsrc, const int* t_src, Ter
 // part holds at least npair * nsb * L0 * LV_MAXCHUNK complex, out_dev the
 // nrow * L0 result; sources are processed nsb at a time.
 static int levels_body(mglma_ctx* c, const TermList& T, int ncol, int nsrc, const int* t_src, int nfine, int npair,
-                       const PairSet& P, int diff, int nrow, int nsb, double2* part, double2* out_dev) {
+                       const PairSet& P, int diff, int nrow, int nsb, double2* part, double2* out_dev,
+                       double scale = 0.0, int accumulate = 0) {
+    if (scale == 0.0) scale = 1.0 / nsrc;
     const int L0 = c->L[0];
     for (int n0 = 0; n0 < nsrc; n0 += nsb) {
         const int nb = nsrc - n0 < nsb ? nsrc - n0 : nsb;
@@ -472,7 +474,8 @@ static int levels_body(mglma_ctx* c, const TermList& T, int ncol, int nsrc, cons
         SrcTimes ts;
         for (int n = 0; n < nb; ++n) ts.t[n] = t_src[n0 + n];
         hipLaunchKernelGGL(k_levels_finish, dim3((nrow * L0 + 127) / 128), dim3(128), 0, c->stream, L0, nrow, npair,
-                           nb, diff, ts, pc, (const double2*)part, 1.0 / nsrc, n0 > 0 ? 1 : 0, out_dev);
+                           nb, diff, ts, pc, (const double2*)part, scale, (n0 > 0 || accumulate) ? 1 : 0,
+                           out_dev);
         HIP_TRY(hipGetLastError());
     }
     return MGLMA_OK;
@@ -513,6 +516,23 @@ extern "C" int mglma_contract_levels(mglma_ctx* c, int kind, int nsrc, const int
     HIP_TRY(hipMemcpyAsync(G_host, out, (size_t)nrow * L0 * 16, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     return MGLMA_OK;
+}
+
+extern "C" int mglma_contract_levels_acc(mglma_ctx* c, int kind, int nsrc, const int* t_src, const double* fine,
+                                         int ncoarse, const double* const* coarse, double weight, int accumulate,
+                                         double* G_dev) {
+    if (!G_dev || !(weight == weight)) return MGLMA_ERR_ARG;
+    TermList T;
+    PairSet P;
+    int ncol, nfine, npair;
+    double dummy;
+    MG_TRY(levels_args(c, kind, nsrc, t_src, fine, ncoarse, coarse, 0, &dummy, &T, &ncol, &P, &nfine, &npair));
+    if (weight == 0.0) return MGLMA_ERR_ARG;
+    const int L0 = c->L[0];
+    double2* part;
+    MG_TRY(mg_scratch(c, 28, (size_t)npair * nsrc * L0 * LV_MAXCHUNK * 16, (void**)&part));
+    return levels_body(c, T, ncol, nsrc, t_src, nfine, npair, P, 1, npair, nsrc, part, (double2*)G_dev, weight,
+                       accumulate ? 1 : 0);
 }
 
 extern "C" int mglma_contract_pair(mglma_ctx* c, int kind, int nsrc, const int* t_src, int coarse,

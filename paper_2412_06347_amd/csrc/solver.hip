@@ -545,7 +545,8 @@ static int precondition(SolveCtx& S, int vp, const void* r, void* z) {
 // number of iterations.  Stops when every active right-hand side has
 // ||r|| <= inner_tol ||rin|| (checked on the host each iteration).
 // ---------------------------------------------------------------------------
-static int inner_fgcr(SolveCtx& S, int vp, void* rin, void* e, const std::vector<int>& active, int* iters) {
+static int inner_fgcr(SolveCtx& S, int vp, void* rin, void* e, const std::vector<int>& active, int* iters,
+                      std::vector<int>* nonfinite = nullptr) {
     mglma_ctx* c = S.c;
     const mglma_solve_params* p = S.p;
     const int nrhs = S.nrhs;
@@ -600,7 +601,13 @@ static int inner_fgcr(SolveCtx& S, int vp, void* rin, void* e, const std::vector
         HIP_TRY(hipStreamSynchronize(c->stream));
         bool done = true, changed = false;
         for (int q = 0; q < nrhs; ++q) {
-            if (!std::isfinite(h[q])) return MGLMA_ERR_NONFINITE;
+            if (!std::isfinite(h[q])) {
+                // with `nonfinite` given the right-hand side is frozen and
+                // reported; the others go on unaffected (per-rhs arithmetic)
+                if (!nonfinite) return MGLMA_ERR_NONFINITE;
+                if (mask[q]) { (*nonfinite)[q] = 1; mask[q] = 0; changed = true; }
+                continue;
+            }
             if (mask[q] && h[q] <= p->inner_tol * p->inner_tol * r0[q]) { mask[q] = 0; changed = true; }
             if (mask[q]) done = false;
         }
@@ -852,5 +859,255 @@ extern "C" int mglma_adaptive_setup(mglma_ctx* c, const mglma_solve_params* p, d
         MG_TRY(mglma_build_subspace(c, Nv, tv));
     }
     HIP_TRY(hipStreamSynchronize(c->stream));
+    return MGLMA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Resident right-hand-side slots: solves that right-hand sides join and leave
+// between outer cycles (continuous batching of the serving loop).
+//
+// Storage positions [0, nact) hold running right-hand sides (b, x, r in
+// FP64), [nact, nused) finished ones (x only), [nused, nslots) are free;
+// position nslots is swap space.  A step is one outer cycle of mglma_solve
+// for the running positions: r / |r| in the inner precision, at most
+// p->max_inner FGCR iterations with the multigrid preconditioner, x += |r| e,
+// r = b - M x in FP64.  Every right-hand side follows the arithmetic of
+// mglma_solve alone (per-rhs Krylov scalars and masks, fixed-order
+// reductions), whatever else shares the step.
+// ---------------------------------------------------------------------------
+struct mglma_slots {
+    mglma_ctx* c = nullptr;
+    int nslots = 0, nact = 0, nused = 0;
+    double2 *B = nullptr, *X = nullptr, *R = nullptr;
+    size_t bytes = 0;
+    std::vector<int> pos2id, id2pos, state, outer, inner;
+    std::vector<double> bn2, rn2;
+};
+
+static inline size_t slot_n(mglma_slots* s) { return (size_t)s->c->geo.V * 12; }
+static inline double2* slot_at(mglma_slots* s, double2* base, int pos) { return base + (size_t)pos * slot_n(s); }
+
+extern "C" int mglma_slots_create(mglma_ctx* c, int nslots, mglma_slots** out) {
+    if (!c || !out || nslots < 1 || nslots > 4096) return MGLMA_ERR_ARG;
+    if (!c->have_gauge) return MGLMA_ERR_NO_GAUGE;
+    mglma_slots* s = new mglma_slots();
+    s->c = c;
+    s->nslots = nslots;
+    const size_t fb = (size_t)c->geo.V * 12 * 16;
+    s->bytes = fb * (nslots + 1);
+    int rc = mg_malloc(c, (void**)&s->B, s->bytes);
+    if (rc == MGLMA_OK) rc = mg_malloc(c, (void**)&s->X, s->bytes);
+    if (rc == MGLMA_OK) rc = mg_malloc(c, (void**)&s->R, s->bytes);
+    if (rc != MGLMA_OK) {
+        mg_free(c, s->B, s->bytes);
+        mg_free(c, s->X, s->bytes);
+        mg_free(c, s->R, s->bytes);
+        delete s;
+        return rc;
+    }
+    s->pos2id.assign(nslots + 1, -1);
+    s->id2pos.assign(nslots, -1);
+    s->state.assign(nslots, 0);
+    s->outer.assign(nslots, 0);
+    s->inner.assign(nslots, 0);
+    s->bn2.assign(nslots, 0.0);
+    s->rn2.assign(nslots, 0.0);
+    *out = s;
+    return MGLMA_OK;
+}
+
+extern "C" void mglma_slots_destroy(mglma_slots* s) {
+    if (!s) return;
+    (void)hipStreamSynchronize(s->c->stream);
+    mg_free(s->c, s->B, s->bytes);
+    mg_free(s->c, s->X, s->bytes);
+    mg_free(s->c, s->R, s->bytes);
+    delete s;
+}
+
+// move the slot at position `from` to the free position `to` (fields given by mask: 1 b, 2 x, 4 r)
+static int slot_move(mglma_slots* s, int from, int to, int fields) {
+    const size_t fb = slot_n(s) * 16;
+    if (fields & 1) MG_TRY(mg_copy(s->c, slot_at(s, s->B, to), slot_at(s, s->B, from), fb));
+    if (fields & 2) MG_TRY(mg_copy(s->c, slot_at(s, s->X, to), slot_at(s, s->X, from), fb));
+    if (fields & 4) MG_TRY(mg_copy(s->c, slot_at(s, s->R, to), slot_at(s, s->R, from), fb));
+    const int id = s->pos2id[from];
+    s->pos2id[to] = id;
+    s->pos2id[from] = -1;
+    if (id >= 0) s->id2pos[id] = to;
+    return MGLMA_OK;
+}
+
+static int slots_retire(mglma_slots* s);
+
+extern "C" int mglma_slots_load(mglma_slots* s, int nrhs, const double* b, int* ids) {
+    if (!s || !b || !ids || nrhs < 1) return MGLMA_ERR_ARG;
+    if (nrhs > s->nslots - s->nused) return MGLMA_ERR_SHAPE;
+    mglma_ctx* c = s->c;
+    // the new right-hand sides take positions [nact, nact + nrhs); finished
+    // slots there move to the free positions from max(nused, nact + nrhs) on,
+    // so that finished slots end up in [nact + nrhs, nused + nrhs)
+    const int win_end = s->nact + nrhs;
+    int dst = s->nused > win_end ? s->nused : win_end;
+    for (int pos = s->nact; pos < win_end && pos < s->nused; ++pos) MG_TRY(slot_move(s, pos, dst++, 2));
+    // free ids for the new right-hand sides
+    int next = 0;
+    const size_t n = slot_n(s), fb = n * 16;
+    for (int q = 0; q < nrhs; ++q) {
+        while (next < s->nslots && s->state[next] != 0) ++next;
+        if (next >= s->nslots) return MGLMA_ERR_SHAPE;
+        const int pos = s->nact + q, id = next++;
+        ids[q] = id;
+        s->pos2id[pos] = id;
+        s->id2pos[id] = pos;
+        s->state[id] = 1;
+        s->outer[id] = s->inner[id] = 0;
+    }
+    double2* Bq = slot_at(s, s->B, s->nact);
+    MG_TRY(mg_copy(c, Bq, b, (size_t)nrhs * fb));
+    MG_TRY(mg_copy(c, slot_at(s, s->R, s->nact), b, (size_t)nrhs * fb));
+    MG_TRY(mg_zero(c, slot_at(s, s->X, s->nact), (size_t)nrhs * fb));
+    double *d, *h;
+    MG_TRY(mg_scratch(c, WS_CAP, (size_t)nrhs * 8 + 256, (void**)&d));
+    MG_TRY(mg_norm2(c, MGLMA_F64, Bq, n, nrhs, d));
+    MG_TRY(mg_host(c, (size_t)nrhs, &h));
+    HIP_TRY(hipMemcpyAsync(h, d, (size_t)nrhs * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int q = 0; q < nrhs; ++q) {
+        const int id = ids[q];
+        s->bn2[id] = s->rn2[id] = h[q];
+        if (!std::isfinite(h[q])) s->state[id] = MGLMA_ERR_NONFINITE;
+        else if (!(h[q] > 0.0)) s->state[id] = 2;      // zero source: x = 0 is exact
+    }
+    s->nact += nrhs;
+    s->nused += nrhs;
+    // zero or non-finite sources are finished already
+    return slots_retire(s);
+}
+
+// running positions whose state is no longer "running" become finished:
+// each swaps with the last running position
+static int slots_retire(mglma_slots* s) {
+    const int spare = s->nslots;
+    for (int pos = s->nact - 1; pos >= 0; --pos) {
+        const int id = s->pos2id[pos];
+        if (s->state[id] == 1) continue;
+        const int last = s->nact - 1;
+        if (pos != last) {
+            MG_TRY(slot_move(s, pos, spare, 2));         // finished: x only
+            MG_TRY(slot_move(s, last, pos, 7));          // running: b, x, r
+            MG_TRY(slot_move(s, spare, last, 2));
+        }
+        s->nact--;
+    }
+    return MGLMA_OK;
+}
+
+extern "C" int mglma_slots_step(mglma_slots* s, const mglma_solve_params* p, int* status) {
+    if (!s || !p) return MGLMA_ERR_ARG;
+    mglma_ctx* c = s->c;
+    if (p->use_mg && !c->have_subspace) return MGLMA_ERR_NO_SUBSPACE;
+    if (p->gcr_m < 1 || p->gcr_m > 32 || p->max_inner < 1 || p->max_outer < 1) return MGLMA_ERR_ARG;
+    if (p->smoother_alg != MGLMA_SMOOTH_MR && p->smoother_alg != MGLMA_SMOOTH_CAGCR &&
+        p->smoother_alg != MGLMA_SMOOTH_SAP)
+        return MGLMA_ERR_ARG;
+    if (p->use_mg && p->smoother_alg == MGLMA_SMOOTH_SAP && p->nu_post > 0) {
+        if (p->inner != MGLMA_F32 || p->sap_mr < 1 || p->sap_mr > 64) return MGLMA_ERR_ARG;
+        MG_TRY(mg_sap_setup(c));
+    }
+    if (p->use_mg && p->smoother_alg == MGLMA_SMOOTH_CAGCR && (p->nu_post < 0 || p->nu_post > CA_K))
+        return MGLMA_ERR_ARG;
+    if (p->kcycle < 0 || p->kcycle_nu < 0 || p->kcycle_nu > 16) return MGLMA_ERR_ARG;
+    if (p->use_mg && p->coarse_iters > 0 && p->kcycle > 0 && !c->have_l2) return MGLMA_ERR_NO_SUBSPACE;
+    // finished-at-load slots (zero or non-finite sources) leave the running range first
+    MG_TRY(slots_retire(s));
+    const int nrhs = s->nact;
+    if (nrhs > 0) {
+        const int vp = p->inner == MGLMA_F64 ? MGLMA_F64 : MGLMA_F32;
+        const size_t n = slot_n(s), setsz = (size_t)nrhs * n;
+        SolveCtx S;
+        S.c = c; S.p = p; S.nrhs = nrhs;
+        S.s.nrhs = nrhs;
+        S.s.m = p->gcr_m > 8 ? p->gcr_m : 8;
+        MG_TRY(mg_scratch(c, WS_SCAL, Scal::bytes(nrhs, S.s.m), (void**)&S.s.base));
+        double2* t64;
+        void *rin, *e;
+        MG_TRY(mg_scratch(c, WS_T64, setsz * 16, (void**)&t64));
+        MG_TRY(mg_scratch(c, WS_RIN, setsz * prec_cbytes(vp), &rin));
+        MG_TRY(mg_scratch(c, WS_E, setsz * prec_cbytes(vp), &e));
+        std::vector<int> active(nrhs, 1), bad(nrhs, 0);
+        std::vector<double> rn2(nrhs);
+        for (int q = 0; q < nrhs; ++q) rn2[q] = s->rn2[s->pos2id[q]];
+        HIP_TRY(hipMemcpyAsync(S.s.active(), active.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipMemcpyAsync(S.s.rn2(), rn2.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        hipLaunchKernelGGL(k_sqrt_masked, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, S.s.rn2(), S.s.active(),
+                           S.s.scale(), nrhs);
+        MG_TRY(mg_convert(c, MGLMA_F64, s->R, vp, rin, n, nrhs, S.s.scale(), 1));
+        int it = 0;
+        MG_TRY(inner_fgcr(S, vp, rin, e, active, &it, &bad));
+        if (vp == MGLMA_F64)
+            hipLaunchKernelGGL((k_accum<double2, double>), dim3(1024, nrhs), dim3(256), 0, c->stream, s->X,
+                               (const double2*)e, S.s.scale(), n);
+        else
+            hipLaunchKernelGGL((k_accum<float2, float>), dim3(1024, nrhs), dim3(256), 0, c->stream, s->X,
+                               (const float2*)e, S.s.scale(), n);
+        HIP_TRY(hipGetLastError());
+        MG_TRY(mg_dslash(c, MGLMA_F64, 0, s->X, t64, nrhs));
+        MG_TRY(mg_xmy_norm(c, s->B, t64, s->R, n, nrhs, S.s.rn2()));
+        double* h;
+        MG_TRY(mg_host(c, (size_t)nrhs, &h));
+        HIP_TRY(hipMemcpyAsync(h, S.s.rn2(), nrhs * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        const double tol2 = p->tol * p->tol;
+        for (int q = 0; q < nrhs; ++q) {
+            const int id = s->pos2id[q];
+            s->outer[id]++;
+            s->inner[id] += it;
+            s->rn2[id] = h[q];
+            if (bad[q] || !std::isfinite(h[q])) s->state[id] = MGLMA_ERR_NONFINITE;
+            else if (h[q] <= tol2 * s->bn2[id]) s->state[id] = 2;
+            else if (s->outer[id] >= p->max_outer) s->state[id] = MGLMA_ERR_NOT_CONVERGED;
+        }
+        MG_TRY(slots_retire(s));
+    }
+    if (status)
+        for (int id = 0; id < s->nslots; ++id) status[id] = s->state[id];
+    return MGLMA_OK;
+}
+
+extern "C" int mglma_slots_take(mglma_slots* s, int n, const int* ids, double* x, mglma_solve_stats* stats) {
+    if (!s || n < 0 || (n > 0 && (!ids || !x))) return MGLMA_ERR_ARG;
+    for (int k = 0; k < n; ++k) {
+        if (ids[k] < 0 || ids[k] >= s->nslots) return MGLMA_ERR_ARG;
+        const int st = s->state[ids[k]];
+        if (st == 0 || st == 1) return MGLMA_ERR_ARG;     // free or still running
+        for (int j = 0; j < k; ++j)
+            if (ids[j] == ids[k]) return MGLMA_ERR_ARG;
+    }
+    const size_t fb = slot_n(s) * 16;
+    for (int k = 0; k < n; ++k) {
+        const int id = ids[k], pos = s->id2pos[id];
+        MG_TRY(mg_copy(s->c, (char*)x + (size_t)k * fb, slot_at(s, s->X, pos), fb));
+        if (stats) {
+            const double rel = s->bn2[id] > 0 ? std::sqrt(s->rn2[id] / s->bn2[id]) : 0.0;
+            stats[k].outer = s->outer[id];
+            stats[k].inner = s->inner[id];
+            stats[k].coarse = 0;
+            stats[k].true_rel_res = rel;
+            stats[k].seconds = 0.0;
+            stats[k].status = s->state[id] == 2 ? MGLMA_OK : s->state[id];
+        }
+    }
+    // release: the last used position fills the hole (finished slots only)
+    for (int k = 0; k < n; ++k) {
+        const int id = ids[k], pos = s->id2pos[id];
+        const int last = s->nused - 1;
+        s->pos2id[pos] = -1;
+        s->id2pos[id] = -1;
+        s->state[id] = 0;
+        if (pos != last) MG_TRY(slot_move(s, last, pos, 2));
+        s->nused--;
+    }
+    HIP_TRY(hipStreamSynchronize(s->c->stream));
     return MGLMA_OK;
 }

@@ -34,6 +34,7 @@ SYMBOLS = [
     "mglma_level2_apply", "mglma_level2_solve", "mglma_level2_pieces", "mglma_save", "mglma_load",
     "mglma_adaptive_setup", "mglma_sap_smooth", "mglma_sap_timing", "mglma_sap_elapsed",
     "mglma_contract_pair", "mglma_contract_levels", "mglma_contract_levels_noalloc",
+    "mglma_contract_levels_acc", "mglma_slots_create", "mglma_slots_destroy", "mglma_slots_load", "mglma_slots_step", "mglma_slots_take",
 ]
 
 
@@ -393,6 +394,16 @@ class Context:
                                            out.ctypes.data_as(C.c_void_p)))
         return out[:nrow, :, 0] + 1j * out[:nrow, :, 1]
 
+    def contract_levels_acc(self, kind, t_src, out, weight, accumulate, fine=None, coarse=()):
+        """out (device, [m][L0][2] float64) (+)= weight * the level rows of
+        these sources (asynchronous)."""
+        t = np.ascontiguousarray(t_src, dtype=np.int32)
+        nco = len(coarse)
+        arr = (C.c_void_p * max(nco, 1))(*[c.data_ptr() for c in coarse])
+        _check(lib().mglma_contract_levels_acc(self._ctx, int(kind), len(t), t.ctypes.data_as(C.POINTER(C.c_int)),
+                                               _ptr(fine), nco, arr, C.c_double(weight), int(bool(accumulate)),
+                                               _ptr(out)))
+
     def contract_levels_noalloc(self, kind, t_src, fine=None, coarse=()):
         """contract_levels without the exact top row, through the entry point
         that allocates nothing (fixed device workspace)."""
@@ -404,3 +415,45 @@ class Context:
         _check(lib().mglma_contract_levels_noalloc(self._ctx, int(kind), len(t), t.ctypes.data_as(C.POINTER(C.c_int)),
                                                    _ptr(fine), nco, arr, out.ctypes.data_as(C.c_void_p)))
         return out[:nrow, :, 0] + 1j * out[:nrow, :, 1]
+
+
+class Slots:
+    """Resident right-hand-side slots of one context (continuous batching):
+    load() sources into free slots, step() one outer cycle of every running
+    slot, take() finished solutions."""
+
+    def __init__(self, ctx, nslots):
+        self.ctx, self.nslots = ctx, int(nslots)
+        self._h = C.c_void_p()
+        _check(lib().mglma_slots_create(ctx._ctx, self.nslots, C.byref(self._h)))
+        self.status = np.zeros(self.nslots, dtype=np.int32)
+
+    def close(self):
+        if self._h:
+            lib().mglma_slots_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load(self, b):
+        ids = np.zeros(b.shape[0], dtype=np.int32)
+        _check(lib().mglma_slots_load(self._h, b.shape[0], _ptr(b), ids.ctypes.data_as(C.POINTER(C.c_int))))
+        return ids
+
+    def step(self, params):
+        """One outer cycle; returns the state of every slot id (0 free,
+        1 running, 2 converged, < 0 failed)."""
+        _check(lib().mglma_slots_step(self._h, C.byref(params),
+                                      self.status.ctypes.data_as(C.POINTER(C.c_int))))
+        return self.status.copy()
+
+    def take(self, ids, x):
+        ids = np.ascontiguousarray(ids, dtype=np.int32)
+        n = len(ids)
+        st = (SolveStats * max(n, 1))()
+        _check(lib().mglma_slots_take(self._h, n, ids.ctypes.data_as(C.POINTER(C.c_int)), _ptr(x), st))
+        return [dict(outer=s.outer, inner=s.inner, true_rel_res=s.true_rel_res, status=s.status) for s in st[:n]]

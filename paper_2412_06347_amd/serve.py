@@ -8,25 +8,33 @@ spin-diluted wall sources (4 right-hand sides each, section "Stochastic
 estimator on level k") and receives the level terms G_L0, G_L1 (stochastic,
 eq:C_stoch with the level sums) and G_L2 (exact, eq:G_LL:exact).
 
-Batching: every ensemble has a worker thread with its own HIP stream.  While
-a batch of that ensemble is on the GPU, newly arriving requests wait in its
-queue; when the batch retires, the worker admits as many queued requests as
-fit the ensemble's right-hand-side slots and HBM share into the next
-multi-right-hand-side batch.  Workers of different ensembles run
-concurrently, so their kernels overlap on the device.  Every right-hand side
-follows the same arithmetic alone or in a batch (per-rhs Krylov scalars,
-fixed-order reductions, frozen once converged), so a request's result does
-not depend on what it was batched with.
+Continuous batching: every ensemble has a worker thread with its own HIP
+stream and a pool of resident right-hand-side slots in the library
+(mglma_slots_*).  The worker loops over outer cycles of the multigrid solve:
+before each cycle it admits queued requests whose right-hand sides fit the
+free slots (their sources and coarse pieces are formed and loaded into the
+pool), runs one cycle for every running right-hand side (at most one FGCR
+restart cycle), and completes each request whose right-hand sides have all
+converged (solutions taken from the pool, level terms contracted in the
+library), which frees its slots for the queue.  A request that arrives while
+others are on the GPU therefore starts at the next cycle, not after the
+running ones finish.  Workers of different ensembles run concurrently, so
+their kernels overlap on the device.  Every right-hand side follows the
+arithmetic of a solve alone (per-rhs Krylov scalars, fixed-order reductions,
+frozen once converged), so a request's result does not depend on what ran
+beside it.
 
 Admission: ensembles are admitted while their resident bytes plus the
-workspace of their largest batch fit the HBM budget; a batch is formed only
-from requests whose right-hand sides fit the ensemble's slot count.
+workspace of their slot pool fit the HBM budget; the request at the head of
+an ensemble's queue joins with as many of its sources as fit the free slots
+(4 right-hand sides per source) and keeps the head until all have joined, so
+a request larger than the pool is solved in parts whose level terms are
+added to its source mean in the library (mglma_contract_levels_acc).
 """
 from __future__ import annotations
 
 import collections
 import dataclasses
-import queue
 import threading
 import time
 from typing import Callable, Dict, List, Optional
@@ -43,6 +51,10 @@ class Request:
     t_arrival: float
     t_start: float = 0.0
     t_done: float = 0.0
+    joined_running: int = 0          # requests already running when this one was admitted
+    next_src: int = 0                # sources admitted so far (a request may join in parts)
+    done_src: int = 0                # sources whose solves have finished
+    work: Optional[dict] = None      # the engine's per-request state while running
     result: Optional[dict] = None
     error: Optional[BaseException] = None
     done: threading.Event = dataclasses.field(default_factory=threading.Event)
@@ -63,11 +75,13 @@ class AdmissionError(RuntimeError):
     pass
 
 
-def workspace_bytes_per_rhs(V, gcr_m=8, nu_post=6):
-    """Device bytes the solve needs per right-hand side: 2*gcr_m + 8 FP32 and
-    8 FP64 fine fields (Krylov directions, residuals, smoother, outputs) and
-    the nu_post + 1 FP16 Krylov basis vectors of the CA-GCR smoother."""
-    return V * 12 * ((2 * gcr_m + 8) * 8 + 8 * 16 + (nu_post + 1) * 4)
+def workspace_bytes_per_rhs(V, gcr_m=6):
+    """Device bytes per right-hand side slot: b, x and the FP64 residual held
+    by the slot (3 FP64 fine fields), the FGCR directions and preconditioned
+    vectors with the inner residual, correction and smoother vectors (2 gcr_m
+    + 4 FP32 fields), the FP64 apply of the outer cycle, and the source and
+    its coarse pieces while a request is admitted (3 FP64 fields)."""
+    return V * 12 * (3 * 16 + (2 * gcr_m + 4) * 8 + 16 + 3 * 16)
 
 
 class Engine:
@@ -115,9 +129,12 @@ class Engine:
             smooth = dict(gcr_m=6, nu_post=2, sap_mr=4, smoother_alg=mglma.SMOOTH_SAP)
         else:
             smooth = dict(gcr_m=4, nu_post=6, smoother_alg=mglma.SMOOTH_CAGCR)
-        self.params = params or mglma.default_params(tol=1e-10, max_outer=10, max_inner=120, inner_tol=1e-5,
-                                                     coarse_iters=4, smoother=mglma.F16, inner=mglma.F32,
-                                                     coarse=mglma.BF16, coarse_eo=1, **smooth)
+        # an outer cycle is one FGCR restart cycle (max_inner = gcr_m): the
+        # granularity at which right-hand sides join and leave the pool
+        self.params = params or mglma.default_params(tol=1e-10, max_outer=60, max_inner=smooth["gcr_m"],
+                                                     inner_tol=1e-5, coarse_iters=4, smoother=mglma.F16,
+                                                     inner=mglma.F32, coarse=mglma.BF16, coarse_eo=1, **smooth)
+        self.pool = None
         self.coarse_params = coarse_params or mglma.default_params(tol=1e-10, coarse=mglma.BF16, coarse_iters=12,
                                                                    max_outer=40, coarse_eo=1)
         self.resident = ctx.resident_bytes() + self.U.numel() * 8
@@ -126,31 +143,96 @@ class Engine:
     def V(self):
         return self.ctx.V
 
+    # -- continuous batching through the library's slot pool -----------------
+    def open_pool(self, nslots):
+        self.pool = self.mglma.Slots(self.ctx, nslots)
+
+    def _noise(self, r):
+        """The request's seeded sources (all of them, drawn once)."""
+        if r.work is None:
+            L = self.L
+            r.work = dict(xi=np.ascontiguousarray(self.synth.z4_noise(r.n_src, L, r.seed)),
+                          tn=self.synth.time_slices(r.n_src, L[0], r.seed), acc=None, stats=[])
+        return r.work
+
+    def _pieces(self, xi, tn):
+        torch, ctx = self.torch, self.ctx
+        xid = torch.from_numpy(np.ascontiguousarray(xi).view(np.float64)).cuda()
+        eta = ctx.fine(4 * len(tn))
+        ctx.noise_sources(xid, tn, eta)
+        cg, ct = ctx.coarse(4 * len(tn)), ctx.coarse(4 * len(tn))
+        ctx.coarse_pieces(eta, cg, ct, self.coarse_params)
+        return eta, cg, ct
+
+    def admit(self, parts):
+        """parts: (request, first source, end source) admitted together; their
+        sources and coarse pieces are formed and the right-hand sides join the
+        pool."""
+        with self.torch.cuda.stream(self.stream):
+            xi = np.concatenate([self._noise(r)["xi"][a:b] for r, a, b in parts])
+            tn = np.concatenate([r.work["tn"][a:b] for r, a, b in parts])
+            eta, cg, ct = self._pieces(xi, tn)
+            ids = self.pool.load(eta)
+        out, k = [], 0
+        for r, a, b in parts:
+            n = 4 * (b - a)
+            out.append(dict(req=r, a=a, b=b, ids=ids[k:k + n], tn=tn[k // 4:k // 4 + b - a], cg=cg[k:k + n],
+                            ct=ct[k:k + n]))
+            k += n
+        return out
+
+    def step(self):
+        """One outer cycle of every running right-hand side; slot states."""
+        with self.torch.cuda.stream(self.stream):
+            return self.pool.step(self.params)
+
+    def done(self, part, status):
+        return all(status[i] != 1 for i in part["ids"])
+
+    def finish(self, part):
+        """Take a part's solutions from the pool and add its level terms to the
+        request's source mean (in the library); returns the request's result
+        once every source is done, else None."""
+        r = part["req"]
+        w = r.work
+        with self.torch.cuda.stream(self.stream):
+            x = self.ctx.fine(len(part["ids"]))
+            st = self.pool.take(part["ids"], x)
+            bad = [q["status"] for q in st if q["status"] != 0]
+            if bad:
+                raise RuntimeError("request %d: solve failed (status %d)" % (r.rid, bad[0]))
+            if w["acc"] is None:
+                w["acc"] = self.torch.empty((3, self.L[0], 2), dtype=self.torch.float64, device="cuda")
+            self.ctx.contract_levels_acc(self.mglma.SRC_STOCH, part["tn"], w["acc"], 1.0 / r.n_src,
+                                         r.done_src > 0, fine=x, coarse=[part["cg"], part["ct"]])
+            w["stats"] += st
+            r.done_src += part["b"] - part["a"]
+            if r.done_src < r.n_src:
+                return None
+            lv = w["acc"].cpu().numpy()
+        lv = lv[..., 0] + 1j * lv[..., 1]
+        res = self._result(lv, w["stats"])
+        r.work = None
+        return res
+
+    def _result(self, lv, st):
+        return dict(L0=lv[0], L1=lv[1], L2=self.G_top.copy(), G=lv[0] + lv[1] + self.G_top,
+                    max_true_rel_res=max(q["true_rel_res"] for q in st), inner=max(q["inner"] for q in st))
+
     def run(self, reqs: List[Request]) -> List[dict]:
-        torch, mglma, synth = self.torch, self.mglma, self.synth
-        ctx, L = self.ctx, self.L
-        nsrc = sum(r.n_src for r in reqs)
-        with torch.cuda.stream(self.stream):
-            xi = np.concatenate([synth.z4_noise(r.n_src, L, r.seed) for r in reqs])
-            tn = np.concatenate([synth.time_slices(r.n_src, L[0], r.seed) for r in reqs])
-            xid = torch.from_numpy(np.ascontiguousarray(xi).view(np.float64)).cuda()
-            eta = ctx.fine(4 * nsrc)
-            ctx.noise_sources(xid, tn, eta)
-            x = ctx.fine(4 * nsrc)
-            rc, stats = ctx.solve(eta, x, self.params)
-            cg, ct = ctx.coarse(4 * nsrc), ctx.coarse(4 * nsrc)
-            ctx.coarse_pieces(eta, cg, ct, self.coarse_params)
-            out, k = [], 0
+        """The requests solved on their own (mglma_solve with the same
+        settings, all sources of a request at once), for comparisons with the
+        results of the request loop."""
+        out = []
+        with self.torch.cuda.stream(self.stream):
             for r in reqs:
-                # level terms and source mean in the library (eq:C_stoch)
-                s = slice(4 * k, 4 * (k + r.n_src))
-                lv = ctx.contract_levels(mglma.SRC_STOCH, tn[k:k + r.n_src], fine=x[s], coarse=[cg[s], ct[s]])
-                L0, L1 = lv[0], lv[1]
-                st = stats[4 * k: 4 * (k + r.n_src)]
-                out.append(dict(L0=L0, L1=L1, L2=self.G_top.copy(), G=L0 + L1 + self.G_top,
-                                max_true_rel_res=max(q["true_rel_res"] for q in st),
-                                inner=max(q["inner"] for q in st)))
-                k += r.n_src
+                xi = self.synth.z4_noise(r.n_src, self.L, r.seed)
+                tn = self.synth.time_slices(r.n_src, self.L[0], r.seed)
+                eta, cg, ct = self._pieces(xi, tn)
+                x = self.ctx.fine(4 * r.n_src)
+                rc, st = self.ctx.solve(eta, x, self.params)
+                lv = self.ctx.contract_levels(self.mglma.SRC_STOCH, tn, fine=x, coarse=[cg, ct])
+                out.append(self._result(lv, st))
         self.stream.synchronize()
         return out
 
@@ -158,8 +240,10 @@ class Engine:
 class Server:
     """Continuous-batching request loop over several resident ensembles.
 
-    engine_factory(name, wl) builds the GPU side of an ensemble; tests of the
-    host logic pass a stand-in."""
+    engine_factory(name, wl) builds the GPU side of an ensemble (open_pool,
+    admit, step, done, finish); tests of the host logic pass a stand-in.
+    `batches` records, per outer cycle of an ensemble, the requests that
+    shared it."""
 
     def __init__(self, hbm_budget: float, max_batch_rhs: int = 48,
                  engine_factory: Callable = Engine, bytes_per_rhs: Callable = workspace_bytes_per_rhs):
@@ -190,6 +274,7 @@ class Server:
         if slots <= 0:
             raise AdmissionError("ensemble %s does not fit the HBM budget (%.2f GB resident, %.2f GB per rhs, "
                                  "%.2f GB left)" % (name, eng.resident / 1e9, per / 1e9, (self.budget - self.used) / 1e9))
+        eng.open_pool(slots)
         with self.cv:
             self.engines[name] = eng
             self.slots[name] = slots
@@ -204,50 +289,94 @@ class Server:
         with self.cv:
             if ensemble not in self.engines:
                 raise KeyError(ensemble)
-            if 4 * n_src > self.slots[ensemble]:
-                raise AdmissionError("request needs %d right-hand sides, ensemble %s has %d slots"
-                                     % (4 * n_src, ensemble, self.slots[ensemble]))
+            if n_src < 1 or self.slots[ensemble] < 4:
+                raise AdmissionError("request of %d sources on ensemble %s with %d slots"
+                                     % (n_src, ensemble, self.slots[ensemble]))
             self._rid += 1
             r = Request(self._rid, ensemble, int(n_src), int(seed), time.perf_counter())
             self.queues[ensemble].append(r)
             self.cv.notify_all()
             return r
 
-    def _take_batch(self, name):
+    def _admit_from_queue(self, name, free):
+        """Parts (request, first source, end source) that fit `free` slots, in
+        arrival order; a request larger than the free slots joins in parts
+        and keeps the head of the queue until all its sources are in."""
         q = self.queues[name]
-        batch, rhs = [], 0
-        while q and rhs + q[0].nrhs <= self.slots[name]:
-            r = q.popleft()
-            batch.append(r)
-            rhs += r.nrhs
-        return batch
+        parts = []
+        while q and free >= 4:
+            r = q[0]
+            k = min(r.n_src - r.next_src, free // 4)
+            parts.append((r, r.next_src, r.next_src + k))
+            r.next_src += k
+            free -= 4 * k
+            if r.next_src == r.n_src:
+                q.popleft()
+        return parts
+
+    def _complete(self, reqs, results, err):
+        t1 = time.perf_counter()
+        with self.cv:
+            for r, res in zip(reqs, results):
+                if r.done.is_set():
+                    continue
+                r.result, r.error, r.t_done = res, err, t1
+                self.completed.append(r)
+                r.done.set()
 
     def _worker(self, name):
         eng = self.engines[name]
+        running = []            # parts on the GPU
+        failed = set()
         while True:
             with self.cv:
-                while self.running and not self.queues[name]:
+                while self.running and not self.queues[name] and not running:
                     self.cv.wait(0.05)
-                if not self.running and not self.queues[name]:
+                if not self.running and not self.queues[name] and not running:
                     return
-                batch = self._take_batch(name)
-            if not batch:
+                free = self.slots[name] - sum(4 * (b - a) for (_, a, b) in (p["key"] for p in running))
+                admitted = self._admit_from_queue(name, free)
+            if admitted:
+                t0 = time.perf_counter()
+                n_run = len({id(p["req"]) for p in running})
+                for r, a, b in admitted:
+                    if a == 0:
+                        r.t_start = t0
+                        r.joined_running = n_run
+                try:
+                    for p, key in zip(eng.admit(admitted), admitted):
+                        p["key"] = key
+                        running.append(p)
+                except BaseException as e:   # a failing admission fails its requests, not the server
+                    bad = [r for r, _, _ in admitted]
+                    failed |= {r.rid for r in bad}
+                    self._complete(bad, [None] * len(bad), e)
+            if not running:
                 continue
-            t0 = time.perf_counter()
-            for r in batch:
-                r.t_start = t0
             try:
-                results = eng.run(batch)
-                err = None
-            except BaseException as e:  # a failing batch fails its requests, not the server
-                results, err = [None] * len(batch), e
-            t1 = time.perf_counter()
+                status = eng.step()
+            except BaseException as e:
+                reqs = list({id(p["req"]): p["req"] for p in running}.values())
+                failed |= {r.rid for r in reqs}
+                self._complete(reqs, [None] * len(reqs), e)
+                running = []
+                continue
             with self.cv:
-                self.batches.append([r.rid for r in batch])
-                for r, res in zip(batch, results):
-                    r.result, r.error, r.t_done = res, err, t1
-                    self.completed.append(r)
-                    r.done.set()
+                self.batches.append(sorted({p["req"].rid for p in running}))
+            still = []
+            for p in running:
+                r = p["req"]
+                if not eng.done(p, status):
+                    still.append(p)
+                    continue
+                try:
+                    res = eng.finish(p)
+                    if res is not None and r.rid not in failed:
+                        self._complete([r], [res], None)
+                except BaseException as e:
+                    failed.add(r.rid)
+                    self._complete([r], [None], e)
+            running = still
 
     def _spawn(self, name):
         th = threading.Thread(target=self._worker, args=(name,), daemon=True)
@@ -280,7 +409,7 @@ class Server:
         solves = sum(r.nrhs for r in done)
         return dict(n=len(done), solves=solves, wall_s=t1 - t0, solves_per_s=solves / max(t1 - t0, 1e-9),
                     p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
-                    batches=len(self.batches))
+                    cycles=len(self.batches))
 
 
 def poisson_arrivals(n, rate, seed):

@@ -1,6 +1,8 @@
 """The request loop on the GPU: requests for two resident ensembles of
-different volumes arrive while others run, are batched into multi-rhs solves,
-and each result equals the same request computed alone."""
+different volumes arrive while others run, join the running multi-rhs solves
+between outer cycles (continuous batching through the library's slot pool,
+requests larger than the free slots in parts), and each result equals the
+same request computed alone."""
 import time
 
 import numpy as np
@@ -37,7 +39,12 @@ def test_serving_alone_equals_mix():
     st = srv.stats()
     print("serving stats", st, "batches", srv.batches)
     assert st["n"] == len(reqs) and st["p99_s"] >= st["p50_s"] > 0
-    assert any(len(b) > 1 for b in srv.batches)          # requests were batched together
+    assert any(len(b) > 1 for b in srv.batches)          # requests shared outer cycles
+    # a request admitted while another was running started before that one ended
+    joined = [(r, q) for r in reqs for q in reqs
+              if r.ensemble == q.ensemble and q.t_start < r.t_start < q.t_done and r.joined_running > 0]
+    print("requests that joined a running solve:", len(joined))
+    assert joined
     # each result equals the same request run alone
     for r in reqs:
         eng = srv.engines[r.ensemble]

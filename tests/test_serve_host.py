@@ -10,18 +10,51 @@ from paper_2412_06347_amd.serve import Server, AdmissionError, poisson_arrivals
 
 
 class FakeEngine:
+    """Stand-in for the GPU side: a part of a request needs as many outer
+    cycles as the request has sources; a cycle takes 5 ms; a negative seed
+    fails at completion."""
+
     def __init__(self, name, wl):
         self.name, self.V, self.resident = name, wl["V"], wl["resident"]
-        self.calls = []
         self.lock = threading.Lock()
 
-    def run(self, reqs):
-        with self.lock:
-            self.calls.append([r.rid for r in reqs])
-        time.sleep(0.02)
-        if any(r.seed < 0 for r in reqs):
-            raise RuntimeError("failing batch")
-        return [dict(G=np.full(4, r.seed, dtype=float), n=r.n_src) for r in reqs]
+    def open_pool(self, nslots):
+        self.nslots = nslots
+        self.left = {}
+        self.nid = 0
+        self.in_use = 0
+        self.max_in_use = 0
+
+    def admit(self, parts):
+        out = []
+        for r, a, b in parts:
+            self.nid += 1
+            self.left[self.nid] = r.n_src
+            self.in_use += 4 * (b - a)
+            self.max_in_use = max(self.max_in_use, self.in_use)
+            assert self.in_use <= self.nslots
+            out.append(dict(req=r, a=a, b=b, pid=self.nid))
+        return out
+
+    def step(self):
+        time.sleep(0.005)
+        for pid in list(self.left):
+            self.left[pid] -= 1
+        return dict(self.left)
+
+    def done(self, part, status):
+        return status[part["pid"]] <= 0
+
+    def finish(self, part):
+        del self.left[part["pid"]]
+        r = part["req"]
+        self.in_use -= 4 * (part["b"] - part["a"])
+        r.done_src += part["b"] - part["a"]
+        if r.seed < 0:
+            raise RuntimeError("failing request")
+        if r.done_src < r.n_src:
+            return None
+        return dict(G=np.full(4, r.seed, dtype=float), n=r.n_src)
 
 
 def per_rhs(V):
@@ -41,10 +74,26 @@ def test_batching_and_stats():
     st = srv.stats()
     assert st["n"] == 20 and st["solves"] == sum(r.nrhs for r in reqs)
     assert 0 < st["p50_s"] <= st["p99_s"]
-    # batches never exceed the slot count and queued requests joined batches
-    for b in srv.batches:
-        assert sum(next(r for r in reqs if r.rid == i).nrhs for i in b) <= 16
-    assert len(srv.batches) < 20
+    # the right-hand sides in the pool never exceed the slot count, and
+    # requests shared cycles
+    assert all(e.max_in_use <= 16 and e.in_use == 0 for e in srv.engines.values())
+    assert any(len(b) > 1 for b in srv.batches)
+
+
+def test_request_joins_running_solve():
+    """A short request submitted while a long one runs starts at the next
+    cycle and finishes first (continuous batching, not batch at a time)."""
+    srv = Server(hbm_budget=1e9, max_batch_rhs=32, engine_factory=FakeEngine, bytes_per_rhs=per_rhs)
+    srv.add_ensemble("a", dict(V=1000, resident=1e6))
+    srv.start()
+    long = srv.submit("a", 6, 1)               # 24 right-hand sides, 6 cycles
+    time.sleep(0.007)                          # inside its first or second cycle
+    short = srv.submit("a", 1, 2)              # 4 right-hand sides, 1 cycle
+    short.wait(5)
+    long.wait(5)
+    srv.stop()
+    assert short.t_start < long.t_done and short.joined_running == 1
+    assert short.t_done < long.t_done
 
 
 def test_admission_by_hbm_budget():
@@ -54,8 +103,18 @@ def test_admission_by_hbm_budget():
     # the second ensemble gets the slots that are left (0.02 MB -> none)
     with pytest.raises(AdmissionError):
         srv.add_ensemble("b", dict(V=1000, resident=4.8e5))
-    with pytest.raises(AdmissionError):
-        srv.submit("a", 13, 1)                # 52 right-hand sides > 48 slots
+
+
+def test_request_larger_than_the_pool_runs_in_parts():
+    srv = Server(hbm_budget=1e9, max_batch_rhs=8, engine_factory=FakeEngine, bytes_per_rhs=per_rhs)
+    srv.add_ensemble("a", dict(V=1000, resident=1e6))
+    srv.start()
+    big = srv.submit("a", 5, 4)               # 20 right-hand sides, 8 slots: three parts
+    small = srv.submit("a", 1, 5)
+    assert big.wait(5)["n"] == 5 and small.wait(5)["n"] == 1
+    srv.stop()
+    eng = srv.engines["a"]
+    assert eng.max_in_use <= 8 and eng.in_use == 0
 
 
 def test_failure_is_per_request():
