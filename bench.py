@@ -27,6 +27,10 @@ WORKLOADS = {
                   seed=3),
     # 16^3 x 32, eps = 0.3, kappa = 0.124
     "16c32": dict(L=(32, 16, 16, 16), block=(4, 4, 4, 4), eps=0.3, kappa=0.124, csw=1.0, Nv=24, Nlm=16, seed=2),
+    # 48^3 x 96, eps = 0.25, kappa = 0.125, 4^4 blocks, Nv = 32, Nlm = 64, 48 time-diluted
+    # spin-diluted sources (192 right-hand sides); run by --c4
+    "48c96": dict(L=(96, 48, 48, 48), block=(4, 4, 4, 4), eps=0.25, kappa=0.125, csw=1.0, Nv=32, Nlm=64, seed=4,
+                  nsrc=48),
     # 4^4, eps = 0.3, kappa = 0.120, 2^4 blocks
     "4c4": dict(L=(4, 4, 4, 4), block=(2, 2, 2, 2), eps=0.3, kappa=0.120, csw=1.0, Nv=8, Nlm=4, seed=1),
 }
@@ -145,9 +149,11 @@ def measured_traffic(workload):
     return rec.get("f16_12rhs_hbm_bytes_per_launch")
 
 
-# FP32 peak without packed FP32 instructions (the library is built without
-# them): 256 CUs x 64 FP32 FMA lanes x 2 flop x 2.4 GHz
-FP32_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+# MI355X published dense FP32 vector peak (it counts packed FP32 issue)
+FP32_PEAK_TFLOPS = 157.3
+# the FP32 rate without packed FP32 instructions, which the library is built
+# without: 256 CUs x 64 FP32 FMA lanes x 2 flop x 2.4 GHz
+FP32_NONPACKED_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 
 # flops per site and right-hand side: one Wilson-clover apply 1824 (clover
 # 504, each of the 8 hops 165), the minimal-residual vector work of one SAP
@@ -211,32 +217,69 @@ def plain_gcr_iterations(P, mglma):
 
 
 def cpu_baseline(wl, n_iter_needed, budget_s=20.0):
-    """The oracle (numpy FP64, one thread) on a bounded sample of the same
-    workload: its restarted GCR(16) on one point-source system of the same
-    lattice for about `budget_s` seconds; solves/s = 1 / (time per iteration
-    x the iterations that GCR(16) needs for this system to reach 1e-10)."""
+    """The oracle (numpy FP64) on a bounded sample of the same workload: its
+    restarted GCR(16) on one point-source system of the same lattice, timed
+    per iteration (median of the repetitions) with one thread and with every
+    host thread allowed; solves/s = 1 / (time per iteration x the iterations
+    that GCR(16) needs for this system to reach 1e-10).  Also, as a complete
+    (not extrapolated) figure: the median of five full oracle solves to
+    1e-10 of the 4^4 workload."""
     from threadpoolctl import threadpool_limits
     from oracle import dirac, estimators, solvers
     from paper_2412_06347_amd import synth
     L = wl["L"]
+    U = synth.gauge_field(L, wl["eps"], wl["seed"])
+    D = dirac.WilsonClover(U, L, wl["kappa"], wl["csw"])
+    b = estimators.point_sources(L, (0, 0, 0, 0))[:1]
+    ncpu = os.cpu_count() or 1
+
+    def per_iter(threads, budget):
+        with threadpool_limits(threads):
+            t0 = time.time()
+            D.M(b)
+            t_apply = time.time() - t0
+            n_it = max(5, int(budget / (1.2 * t_apply)))
+            # one GCR(16) run of n_it iterations (one operator apply each); the
+            # per-iteration times are the differences of the apply start times
+            stamps = []
+
+            def timed_apply(v):
+                stamps.append(time.time())
+                return D.M(v)
+
+            t0 = time.time()
+            x, it, res = solvers.gcr(timed_apply, b, tol=1e-10, m=16, max_iter=n_it)
+            t = time.time() - t0
+            stamps.append(t0 + t)
+        dt = np.diff(stamps) if len(stamps) > 1 else np.array([t / max(it, 1)])
+        return float(np.median(dt)), it, float(res[0]), t
+
+    t1, it1, res1, tt1 = per_iter(1, budget_s / 2)
+    tn, itn, resn, ttn = per_iter(ncpu, budget_s / 2)
+    best, cores = (tn, ncpu) if tn < t1 else (t1, 1)
+    # complete oracle solves of the 4^4 workload (W1), median of five
+    w1 = WORKLOADS["4c4"]
+    U1 = synth.gauge_field(w1["L"], w1["eps"], w1["seed"])
+    D1 = dirac.WilsonClover(U1, w1["L"], w1["kappa"], w1["csw"])
+    b1 = estimators.point_sources(w1["L"], (0, 0, 0, 0))[:1]
     with threadpool_limits(1):
-        U = synth.gauge_field(L, wl["eps"], wl["seed"])
-        D = dirac.WilsonClover(U, L, wl["kappa"], wl["csw"])
-        b = estimators.point_sources(L, (0, 0, 0, 0))[:1]
-        t0 = time.time()
-        D.M(b)
-        t_apply = time.time() - t0
-        n_it = max(4, int(budget_s / (1.3 * t_apply)))
-        t0 = time.time()
-        x, it, res = solvers.gcr(D.M, b, tol=1e-10, m=16, max_iter=n_it)
-        t = time.time() - t0
-    t_it = t / max(it, 1)
+        ts, its = [], []
+        for _ in range(6):
+            t0 = time.time()
+            x1, k1, r1 = solvers.gcr(D1.M, b1, tol=1e-10, m=16, max_iter=5000)
+            ts.append(time.time() - t0)
+            its.append(k1)
     cpu = open("/proc/cpuinfo").read().split("model name")[1].split(":")[1].split("\n")[0].strip()
-    return dict(value=float(1.0 / (t_it * n_iter_needed)), unit="solves/s", cores=1, kind="oracle",
-                sample="numpy FP64 oracle on 1 thread (%s): %d iterations of its restarted GCR(16) on one "
-                       "point-source system of the %s lattice took %.1f s (%.2f s per iteration, residual %.2e); "
-                       "one solve to 1e-10 = %d iterations of the same GCR(16) (count from an FP64 run to "
-                       "convergence)" % (cpu, it, "x".join(map(str, L)), t, t_it, float(res[0]), n_iter_needed))
+    return dict(value=float(1.0 / (best * n_iter_needed)), unit="solves/s", cores=cores, kind="oracle",
+                sample="numpy FP64 oracle (%s, %d host threads): its restarted GCR(16) on one point-source system "
+                       "of the %s lattice, median time per iteration %.2f s with 1 thread (%d iterations, %.1f s) "
+                       "and %.2f s with %d threads allowed (%d iterations, %.1f s); one solve to 1e-10 = %d "
+                       "iterations of the same GCR(16) (count from an FP64 run of it to convergence)"
+                       % (cpu, ncpu, "x".join(map(str, L)), t1, it1, tt1, tn, ncpu, itn, ttn, n_iter_needed),
+                per_iteration_s={"1": t1, str(ncpu): tn},
+                w1_full_solve={"workload": "4^4, kappa=0.120, point source, GCR(16) to 1e-10, 1 thread",
+                               "median_s": float(np.median(ts[1:])), "runs": len(ts) - 1,
+                               "iterations": int(np.median(its)), "solves_per_s": float(1.0 / np.median(ts[1:]))})
 
 
 def local_coherence(wl, degree=64):
@@ -408,6 +451,125 @@ def hierarchy(wl, reps=3):
     }), flush=True)
 
 
+def config4(wl, gb_per_rhs=23.0):
+    """The largest configuration as stated: 48^3 x 96 (seeded synthetic field,
+    eps = 0.25, kappa = 0.125), 4^4 blocks, Nv = 32 test vectors (nc = 64),
+    Nlm = 64 coarse low modes (r = 128), 48 time-diluted Z4 sources x 4
+    spins = 192 right-hand sides solved as multi-RHS batches sized by the
+    free HBM, and the translation-averaged low-mode contraction eq:G_LL:exact.
+    Test vectors: Gaussian fields drawn on the device (seeded torch
+    generator), improved by two rounds of 20 plain FP32 GCR(8) steps in
+    batches of four.  Prints one JSON line with the times and sizes."""
+    import torch
+    from paper_2412_06347_amd import mglma, synth as synth_mod
+    L, Nv, Nlm, nsrc = wl["L"], wl["Nv"], wl["Nlm"], wl["nsrc"]
+    out = {"diagnostic": "48^3x96 configuration (N_v = %d, N_lm = %d, %d sources x 4 spins)" % (Nv, Nlm, nsrc)}
+    t0 = time.time()
+    U = synth_mod.gauge_field(L, wl["eps"], wl["seed"])
+    out["gauge_host_s"] = round(time.time() - t0, 1)
+    ctx = mglma.Context(L, wl["block"], wl["kappa"], wl["csw"])
+    Ud = torch.from_numpy(U.view(np.float64)).cuda()
+    del U
+    ctx.load_gauge(Ud)
+    del Ud
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    log("c4: gauge loaded (%.1f s), resident %.1f GB" % (time.time() - t0, ctx.resident_bytes() / 1e9))
+    # test vectors
+    t1 = time.time()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(wl["seed"] + 1000)
+    tv = ctx.fine(Nv)
+    tv.normal_(generator=gen)
+    p = mglma.default_params(use_mg=0, inner=mglma.F32, max_outer=1, max_inner=20, gcr_m=8, tol=1e-30,
+                             inner_tol=1e-30)
+    y = ctx.fine(4)
+    for _ in range(2):
+        for k0 in range(0, Nv, 4):
+            ctx.solve(tv[k0:k0 + 4], y, p, raise_on_error=False)
+            nrm = torch.linalg.vector_norm(y.reshape(4, -1), dim=1)
+            tv[k0:k0 + 4] = y / nrm[:, None, None, None]
+    del y
+    torch.cuda.synchronize()
+    out["testvec_s"] = round(time.time() - t1, 1)
+    t1 = time.time()
+    ctx.build_subspace(tv)
+    torch.cuda.synchronize()
+    out["build_subspace_s"] = round(time.time() - t1, 2)
+    del tv
+    torch.cuda.empty_cache()
+    out["resident_GB_after_subspace"] = round(ctx.resident_bytes() / 1e9, 1)
+    log("c4: subspace built (%.1f s), resident %.1f GB" % (time.time() - t1, ctx.resident_bytes() / 1e9))
+    # top level: Nlm low modes of Q_1 from the device eigensolver
+    t1 = time.time()
+    init = torch.from_numpy(synth_mod.gaussian_coarse(Nlm, ctx.V1, ctx.nc, 4242).view(np.float64)).cuda()
+    rc, lam, modes, st = ctx.coarse_eigs(init, Nlm, tol=1e-12, max_iter=40, raise_on_error=False)
+    del init
+    torch.cuda.synchronize()
+    out["eigs"] = dict(rc=rc, seconds=round(time.time() - t1, 1), iters=st["iters"], nconv=st["nconv"],
+                       max_res=st["max_res"])
+    t1 = time.time()
+    ctx.set_top_modes(modes.contiguous())
+    torch.cuda.synchronize()
+    out["set_top_modes_s"] = round(time.time() - t1, 3)
+    del modes
+    t1 = time.time()
+    G_exact = ctx.contract_top()
+    out["contract_top_ms"] = round(1e3 * (time.time() - t1), 2)
+    torch.cuda.empty_cache()
+    free, total = torch.cuda.mem_get_info()
+    nb = int(max(1, min(3, (0.8 * free / 1e9) // (4 * gb_per_rhs))))     # sources per batch
+    out["free_GB_before_solves"] = round(free / 1e9, 1)
+    out["rhs_per_batch"] = 4 * nb
+    log("c4: top level set; %.1f GB free, %d right-hand sides per batch" % (free / 1e9, 4 * nb))
+    # stochastic sources, multi-RHS MG solves, coarse pieces, level assembly
+    V3 = L[1] * L[2] * L[3]
+    xi = np.ascontiguousarray(synth_mod.z4_noise(nsrc, L, 7400))
+    tn = synth_mod.time_slices(nsrc, L[0], 7401)
+    params = mixed_params(mglma, max_inner=200)
+    cp = mglma.default_params(tol=1e-10, coarse=mglma.BF16, coarse_iters=12, max_outer=40, coarse_eo=1)
+    acc = torch.zeros((3, L[0], 2), dtype=torch.float64, device="cuda")
+    eta, x = ctx.fine(4 * nb), ctx.fine(4 * nb)
+    cg, ct = ctx.coarse(4 * nb), ctx.coarse(4 * nb)
+    res, iters, t_solve, t_pieces, t_con = [], [], 0.0, 0.0, 0.0
+    torch.cuda.synchronize()
+    t1 = time.time()
+    for n0 in range(0, nsrc, nb):
+        k = min(nb, nsrc - n0)
+        ta = time.time()
+        ctx.noise_sources(torch.from_numpy(xi[n0:n0 + k].view(np.float64).reshape(k, V3, 3, 2)).cuda(),
+                          tn[n0:n0 + k], eta[:4 * k])
+        rcs, st = ctx.solve(eta[:4 * k], x[:4 * k], params, raise_on_error=False)
+        torch.cuda.synchronize()
+        tb = time.time()
+        ctx.coarse_pieces(eta[:4 * k], cg[:4 * k], ct[:4 * k], cp)
+        torch.cuda.synchronize()
+        tc = time.time()
+        ctx.contract_levels_acc(mglma.SRC_STOCH, tn[n0:n0 + k], acc, 1.0 / nsrc, n0 > 0, fine=x[:4 * k],
+                                coarse=[cg[:4 * k], ct[:4 * k]])
+        torch.cuda.synchronize()
+        td = time.time()
+        t_solve += tb - ta
+        t_pieces += tc - tb
+        t_con += td - tc
+        res += [q["true_rel_res"] for q in st]
+        iters += [q["inner"] for q in st]
+        if n0 == 0:
+            log("c4: first batch: solve %.2f s, pieces %.2f s, contraction %.3f s, res %.2e" %
+                (tb - ta, tc - tb, td - tc, max(res)))
+    total = time.time() - t1
+    lv = acc.cpu().numpy()
+    lv = lv[..., 0] + 1j * lv[..., 1]
+    ts = list(range(0, L[0], L[0] // 8))
+    out.update({"solves": 4 * nsrc, "seconds_total": round(total, 2), "solves_per_s": 4 * nsrc / total,
+                "fine_solve_s": round(t_solve, 2), "coarse_pieces_s": round(t_pieces, 2),
+                "contraction_s": round(t_con, 3), "max_true_rel_res": max(res),
+                "inner_iterations_max": max(iters),
+                "G_L0_real": [float(lv[0][t].real) for t in ts], "G_L1_real": [float(lv[1][t].real) for t in ts],
+                "G_L2_exact_real": [float(G_exact[t].real) for t in ts], "t": ts})
+    print(json.dumps(out), flush=True)
+
+
 def setup_recipes(wl, reps=2):
     """Test-vector preparation recipes on the bench workload (the basis should
     span approximations of the low modes of Q, sec. "Local coherence and block
@@ -469,7 +631,7 @@ def setup_recipes(wl, reps=2):
                       "recipes": out}), flush=True)
 
 
-def serving(reqs_n=60, seed=7):
+def serving(reqs_n=60, seed=7, burst_n=24, max_src=8, emit=True):
     """Serving mix (a reduced version of the serving workload: two resident
     ensembles, 16^3 x 32 and 24^3 x 48): requests of 1-8 stochastic
     time-slice sources (x 4 spin-diluted right-hand sides) on a uniformly
@@ -483,7 +645,7 @@ def serving(reqs_n=60, seed=7):
     g = np.random.default_rng(seed)
 
     def draw(n):
-        return [(list(ens)[int(g.integers(len(ens)))], int(g.integers(1, 9))) for _ in range(n)]
+        return [(list(ens)[int(g.integers(len(ens)))], int(g.integers(1, max_src + 1))) for _ in range(n)]
 
     def run(srv, items, arrivals):
         reqs = []
@@ -502,7 +664,7 @@ def serving(reqs_n=60, seed=7):
         srv.add_ensemble(name, wl)
     setup = time.perf_counter() - t0
     srv.start()
-    burst = draw(24)
+    burst = draw(burst_n)
     run(srv, burst, [0.0] * len(burst))
     cap = srv.stats()
     srv.completed.clear()
@@ -514,6 +676,17 @@ def serving(reqs_n=60, seed=7):
     srv.stop()
     st = srv.stats()
     res = max(r.result["max_true_rel_res"] for r in reqs)
+    for eng in srv.engines.values():
+        eng.pool.close()
+        eng.ctx.close()
+    out = {"workload": "requests of 1-%d spin-diluted time-slice sources on resident 16^3x32 and 24^3x48 "
+                       "ensembles, mixed-precision MG to 1e-10, right-hand sides join and leave between outer "
+                       "cycles" % max_src,
+           "capacity_burst_solves_per_s": cap["solves_per_s"], "poisson_requests": st["n"],
+           "offered_solves_per_s": rate * mean_rhs, "solves_per_s": st["solves_per_s"],
+           "p50_s": st["p50_s"], "p99_s": st["p99_s"], "max_true_rel_res": res}
+    if not emit:
+        return out
     print(json.dumps({"diagnostic": "serving mix: resident 16^3x32 and 24^3x48 ensembles, continuous batching "
                                     "(right-hand sides join and leave between outer cycles)",
                       "setup_s": round(setup, 1), "slots": srv.slots,
@@ -532,6 +705,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison step")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-serve", action="store_true", help="skip the bounded serving leg")
     ap.add_argument("--calib-copy", action="store_true", help="only run a plain 1 GiB device copy (counter scale)")
     ap.add_argument("--dslash-only", action="store_true",
                     help="only run the Wilson-clover apply of the workload (for hardware-counter runs)")
@@ -547,6 +721,8 @@ def main():
     ap.add_argument("--serve", action="store_true",
                     help="serving diagnostic instead of the bench: two resident ensembles, a closed burst for the "
                          "capacity, then a Poisson stream at 0.8 of it; solves/s and p50/p99 latency")
+    ap.add_argument("--c4", action="store_true",
+                    help="the 48^3x96 configuration (Nv = 32, Nlm = 64, 48 sources x 4 spins) instead of the bench")
     ap.add_argument("--setup", action="store_true",
                     help="test-vector setup diagnostic instead of the bench: Gaussian vectors, inverse iteration "
                          "with plain GCR, adaptive setup with the multigrid solver; setup time and the MG solve")
@@ -574,6 +750,9 @@ def main():
         return
     if args.setup:
         setup_recipes(wl)
+        return
+    if args.c4:
+        config4(WORKLOADS["48c96"])
         return
     if args.serve:
         serving()
@@ -668,6 +847,7 @@ def main():
         x.copy_(torch.randn(x.shape, device="cuda").to(x.dtype))
         return kernel_time(torch, lambda: ctx.apply_D(x, y, prec), 20, stream)
 
+    n_plain_it = plain_gcr_iterations(P, mglma) if not args.no_cpu else None
     ms16 = apply_ms(mglma.F16, nr)
     ms32 = apply_ms(mglma.F32, nr)
     ms64_1 = apply_ms(mglma.F64, 1)
@@ -682,9 +862,20 @@ def main():
     }
     traffic16 = measured_traffic(args.workload)
     traffic_sap = measured_sap_traffic(args.workload)
+    # bounded serving leg (continuous batching): the step's context is freed
+    # first; two resident ensembles, a short burst for the capacity and a
+    # Poisson stream of 40 requests at 0.8 of it
+    eig_info = P.eig
+    serve = None
+    if not args.no_serve:
+        P.ctx.close()
+        del P
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        serve = serving(reqs_n=40, burst_n=12, max_src=8, emit=False)
     cpu = None
     if not args.no_cpu:
-        n_plain, res_plain = plain_gcr_iterations(P, mglma)
+        n_plain, res_plain = n_plain_it
         log("plain FP64 GCR(16): %d iterations to %.2e" % (n_plain, res_plain))
         cpu = cpu_baseline(wl, n_plain, args.cpu_budget)
     L = wl["L"]
@@ -707,20 +898,27 @@ def main():
                    "lattice": list(L), "block": list(wl["block"]), "nrhs": 12},
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                       "unit": "s per 12-RHS step"},
+        "serving": serve,
         "max_true_rel_res": res,
         "fp64_path": fp64,
         "speedup_mixed_vs_fp64": (value / fp64["solves_per_s"]) if fp64 else None,
         "dslash_GBs": dslash_gbs,
-        "dslash_f16_12rhs": {"kernel": "k_dslash_h<3> (FP16 packed, 12 RHS)", "avg_ms": ms16,
-                             "alg_bytes_per_launch": dslash_alg_bytes(V, nr, 2),
-                             "frac_hbm_peak": dslash_gbs["f16_12rhs"] / HBM_PEAK_GBS, "traffic": traffic16},
         "roofline": {"bound": "alu", "kernel": "k_sap_half<__half2, 3> (SAP half-sweep, 12 RHS, %d block steps)" % nmr,
                      "achieved": ach_sap, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": ach_sap / FP32_PEAK_TFLOPS, "traffic": traffic_sap, "avg_ms": ms_sap,
+                     "peak_kind": "MI355X published FP32 vector peak",
+                     "peak_nonpacked": FP32_NONPACKED_TFLOPS, "frac_nonpacked": ach_sap / FP32_NONPACKED_TFLOPS,
+                     "peak_nonpacked_kind": "FP32 FMA without packed FP32 instructions (the library's build): "
+                                            "256 CUs x 64 lanes x 2 flop x 2.4 GHz",
                      "launches_timed": sap_launches, "avg_ms_back_to_back": ms_sap_b2b,
                      "alg_flops_per_launch": sap_flops},
+        # the Wilson-clover multi-RHS apply, HBM-bound (Dslash HBM GB/s of the metric)
+        "roofline_dslash": {"bound": "hbm", "kernel": "k_dslash_h<3> (FP16 storage, FP32 sums, 12 RHS)",
+                            "achieved": dslash_gbs["f16_12rhs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": dslash_gbs["f16_12rhs"] / HBM_PEAK_GBS, "traffic": traffic16,
+                            "avg_ms": ms16, "alg_bytes_per_launch": dslash_alg_bytes(V, nr, 2)},
         "cpu_baseline": cpu,
-        "top_modes_setup": P.eig,
+        "top_modes_setup": eig_info,
     }
     print(json.dumps(line), flush=True)
 

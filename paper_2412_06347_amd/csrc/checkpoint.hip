@@ -122,11 +122,8 @@ extern "C" int mglma_load(mglma_ctx* c, const char* path) {
     c->nc = nc;
     const size_t nb = (size_t)g.V * 12 * Nv, nd = (size_t)g.V1 * 9 * nc * nc;
     rc = mg_malloc(c, (void**)&c->B64, nb * 16);
-    if (rc == MGLMA_OK) rc = mg_malloc(c, (void**)&c->B32, nb * 8);
     if (rc == MGLMA_OK) rc = mg_malloc(c, (void**)&c->B16, nb * 4);
     if (rc == MGLMA_OK) rc = mg_malloc(c, (void**)&c->D64, nd * 16);
-    if (rc == MGLMA_OK) rc = mg_malloc(c, (void**)&c->D64p, nd * 16);
-    if (rc == MGLMA_OK) rc = mg_malloc(c, (void**)&c->D32p, nd * 8);
     if (rc == MGLMA_OK) rc = mg_malloc(c, (void**)&c->Dbf, nd * 4);
     if (rc == MGLMA_OK) rc = mg_malloc(c, (void**)&c->G1, h.ngam);
     if (rc == MGLMA_OK) rc = read_dev(f, c, c->B64, h.nbasis);
@@ -145,9 +142,8 @@ extern "C" int mglma_load(mglma_ctx* c, const char* path) {
         }
     }
     fclose(f);
-    if (rc == MGLMA_OK) rc = mg_convert(c, MGLMA_F64, c->B64, MGLMA_F32, c->B32, nb, 1, nullptr, 0);
     if (rc == MGLMA_OK) rc = mg_convert(c, MGLMA_F64, c->B64, MGLMA_F16, c->B16, nb, 1, nullptr, 0);
-    if (rc == MGLMA_OK) rc = mg_op_copies(c, (size_t)g.V1 * 9, nc, c->D64, c->D64p, c->D32p, c->Dbf);
+    if (rc == MGLMA_OK) rc = mg_op_copies(c, (size_t)g.V1 * 9, nc, c->D64, nullptr, nullptr, c->Dbf);
     if (rc == MGLMA_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = MGLMA_ERR_HIP;
     if (rc == MGLMA_OK) rc = mg_eo_setup(c);
     if (rc != MGLMA_OK) {

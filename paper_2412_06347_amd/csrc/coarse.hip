@@ -37,7 +37,10 @@ __device__ __forceinline__ int coarse_nbr(const Geo& g, int y, int dir) {
 // are each one contiguous load (the sum over k does not care which lane
 // supplies which k as long as A and B agree).  VEC: nc % 4 == 0, so those
 // loads are aligned and either wholly inside or wholly outside the matrix.
-template <typename R, bool VEC>
+// IL: the operator is the interleaved complex array [y][dir][i][j] (FP64:
+// the library's D_1 itself, no planar copy); a lane's four k entries are
+// then one 64-byte run of complex values.
+template <typename R, bool VEC, bool IL = false>
 __global__ __launch_bounds__(512) void k_coarse_mfma(Geo g, int nc, const R* __restrict__ P,
                                                      const typename VT<R>::c2* __restrict__ in,
                                                      typename VT<R>::c2* __restrict__ out, int nrhs, int gamma5) {
@@ -54,8 +57,10 @@ __global__ __launch_bounds__(512) void k_coarse_mfma(Geo g, int nc, const R* __r
     V4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
     for (int dir = 0; dir < 9; ++dir) {
         const int z = coarse_nbr(g, y, dir);
-        const R* Pr = P + ((size_t)y * 9 + dir) * 2 * nn + (size_t)(mok ? m : 0) * nc;
+        const R* Pr = IL ? P + (((size_t)y * 9 + dir) * nn + (size_t)(mok ? m : 0) * nc) * 2
+                         : P + ((size_t)y * 9 + dir) * 2 * nn + (size_t)(mok ? m : 0) * nc;
         const R* Pi = Pr + nn;
+        const C2* Pc = (const C2*)Pr;
         const C2* v = in + ((size_t)(nok ? n : 0) * V1 + z) * nc;
         for (int k0 = 0; k0 < nc; k0 += 16) {
             const int kb = k0 + 4 * lq;
@@ -63,8 +68,12 @@ __global__ __launch_bounds__(512) void k_coarse_mfma(Geo g, int nc, const R* __r
             if (VEC) {
                 const bool ka = kb < nc;
                 if (ka && mok) {
-                    ld4(Pr + kb, ar);
-                    ld4(Pi + kb, ai);
+                    if (IL) {
+                        ld4c(Pc + kb, ar, ai);
+                    } else {
+                        ld4(Pr + kb, ar);
+                        ld4(Pi + kb, ai);
+                    }
                 } else {
 #pragma unroll
                     for (int s = 0; s < 4; ++s) ar[s] = ai[s] = (R)0;
@@ -79,8 +88,14 @@ __global__ __launch_bounds__(512) void k_coarse_mfma(Geo g, int nc, const R* __r
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
                     const bool ok = kb + s < nc;
-                    ar[s] = (ok && mok) ? Pr[kb + s] : (R)0;
-                    ai[s] = (ok && mok) ? Pi[kb + s] : (R)0;
+                    if (IL) {
+                        const C2 a = (ok && mok) ? Pc[kb + s] : C2{0, 0};
+                        ar[s] = a.x;
+                        ai[s] = a.y;
+                    } else {
+                        ar[s] = (ok && mok) ? Pr[kb + s] : (R)0;
+                        ai[s] = (ok && mok) ? Pi[kb + s] : (R)0;
+                    }
                     C2 x = (ok && nok) ? v[kb + s] : C2{0, 0};
                     br[s] = x.x;
                     bi[s] = x.y;
@@ -217,11 +232,13 @@ __global__ void k_coarse_bf16(Geo g, int nc, const bf16_t* __restrict__ Dbf, con
 }
 
 int mg_coarse_apply(mglma_ctx* c, int prec, int gamma5, const void* in, void* out, int nrhs) {
-    return mg_stencil_apply(c, c->geo, c->nc, c->D64p, c->D32p, c->Dbf, prec, gamma5, in, out, nrhs);
+    if (prec == MGLMA_F32) MG_TRY(mg_need_d32(c));
+    return mg_stencil_apply(c, c->geo, c->nc, (const double*)c->D64, c->D32p, c->Dbf, prec, gamma5, in, out, nrhs);
 }
 
-// any level: the stencil of the grid g.L1 (block grid of a Geo) with planar
-// copies P64 / P32 / Pbf [V][9][re/im][nc][nc]
+// any level: the stencil of the grid g.L1 (block grid of a Geo): FP64 from
+// the interleaved operator P64 [V][9][nc][nc] complex, FP32 / BF16 from the
+// planar copies P32 / Pbf [V][9][re/im][nc][nc]
 int mg_stencil_apply(mglma_ctx* c, const Geo& g, int nc, const double* P64, const float* P32, const bf16_t* Pbf,
                      int prec, int gamma5, const void* in, void* out, int nrhs) {
     if (nrhs <= 0) return MGLMA_OK;
@@ -257,10 +274,10 @@ int mg_stencil_apply(mglma_ctx* c, const Geo& g, int nc, const double* P64, cons
     switch (prec) {
         case MGLMA_F64:
             if (vec)
-                hipLaunchKernelGGL((k_coarse_mfma<double, true>), grid, block, 0, c->stream, g, nc, P64,
+                hipLaunchKernelGGL((k_coarse_mfma<double, true, true>), grid, block, 0, c->stream, g, nc, P64,
                                    (const double2*)in, (double2*)out, nrhs, gamma5);
             else
-                hipLaunchKernelGGL((k_coarse_mfma<double, false>), grid, block, 0, c->stream, g, nc, P64,
+                hipLaunchKernelGGL((k_coarse_mfma<double, false, true>), grid, block, 0, c->stream, g, nc, P64,
                                    (const double2*)in, (double2*)out, nrhs, gamma5);
             break;
         case MGLMA_F32:

@@ -218,7 +218,6 @@ void mg_free_subspace(mglma_ctx* c) {
     mg_free(c, c->B16, nb * 4); c->B16 = nullptr;
     size_t nd = (size_t)g.V1 * 9 * c->nc * c->nc;
     mg_free(c, c->D64, nd * 16); c->D64 = nullptr;
-    mg_free(c, c->D64p, nd * 16); c->D64p = nullptr;
     mg_free(c, c->D32p, nd * 8); c->D32p = nullptr;
     mg_free(c, c->Dbf, nd * 4); c->Dbf = nullptr;
     mg_free(c, c->G1, (size_t)g.V1 * g.b[0] * 3 * c->Nv * c->Nv * 16); c->G1 = nullptr;

@@ -142,12 +142,10 @@ void mg_free_level2(mglma_ctx* c) {
     if (c->have_l2 || c->L2D64) {
         const size_t nd = (size_t)c->g2.V1 * 9 * c->nc * c->nc;
         mg_free(c, c->L2D64, nd * 16);
-        mg_free(c, c->L2D64p, nd * 16);
         mg_free(c, c->L2D32p, nd * 8);
         mg_free(c, c->L2Dbf, nd * 4);
     }
     c->L2D64 = nullptr;
-    c->L2D64p = nullptr;
     c->L2D32p = nullptr;
     c->L2Dbf = nullptr;
     c->have_l2 = false;
@@ -201,7 +199,6 @@ extern "C" int mglma_build_level2(mglma_ctx* c, const int b2[4]) {
     const int nc = c->nc;
     const size_t nd = (size_t)c->g2.V1 * 9 * nc * nc;
     MG_TRY(mg_malloc(c, (void**)&c->L2D64, nd * 16));
-    MG_TRY(mg_malloc(c, (void**)&c->L2D64p, nd * 16));
     MG_TRY(mg_malloc(c, (void**)&c->L2D32p, nd * 8));
     MG_TRY(mg_malloc(c, (void**)&c->L2Dbf, nd * 4));
     int r[4];
@@ -209,7 +206,7 @@ extern "C" int mglma_build_level2(mglma_ctx* c, const int b2[4]) {
     hipLaunchKernelGGL(k_l2_galerkin, dim3(c->g2.V1), dim3(256), 0, c->stream, c->geo, c->g2, r[0], r[1], r[2],
                        r[3], nc, c->D64, c->L2D64);
     HIP_TRY(hipGetLastError());
-    MG_TRY(mg_op_copies(c, (size_t)c->g2.V1 * 9, nc, c->L2D64, c->L2D64p, c->L2D32p, c->L2Dbf));
+    MG_TRY(mg_op_copies(c, (size_t)c->g2.V1 * 9, nc, c->L2D64, nullptr, c->L2D32p, c->L2Dbf));
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->have_l2 = true;
     return MGLMA_OK;
@@ -242,7 +239,7 @@ extern "C" int mglma_level2_apply(mglma_ctx* c, int prec, int gamma5, const void
     if (!c || !in || !out || in == out || nrhs < 0 || nrhs > 65535 * 16) return MGLMA_ERR_ARG;
     if (!c->have_l2) return MGLMA_ERR_NO_SUBSPACE;
     if (prec != MGLMA_F64 && prec != MGLMA_F32 && prec != MGLMA_BF16) return MGLMA_ERR_ARG;
-    return mg_stencil_apply(c, c->g2, c->nc, c->L2D64p, c->L2D32p, c->L2Dbf, prec, gamma5 ? 1 : 0, in, out, nrhs);
+    return mg_stencil_apply(c, c->g2, c->nc, (const double*)c->L2D64, c->L2D32p, c->L2Dbf, prec, gamma5 ? 1 : 0, in, out, nrhs);
 }
 
 extern "C" int mglma_level2_solve(mglma_ctx* c, const mglma_solve_params* p, const double* b, double* x, int nrhs,

@@ -256,9 +256,11 @@ struct mglma_ctx {
 
     // subspace: basis [V1][2][Nv][6][Vb], coarse operator [V1][9][nc][nc]
     int Nv = 0, nc = 0;
-    double2* B64 = nullptr; float2* B32 = nullptr;
+    double2* B64 = nullptr;
+    float2* B32 = nullptr;       // FP32 copy, formed on first use (mg_need_b32)
     __half2* B16 = nullptr;      // FP16 copy for the transfers of the BF16-coarse preconditioner
-    double2* D64 = nullptr; double* D64p = nullptr; float* D32p = nullptr;   // planar [blk][re/im][i][j] copies
+    double2* D64 = nullptr;      // D_1 [V1][9][nc][nc] complex (the FP64 matrix-core apply reads it directly)
+    float* D32p = nullptr;       // planar [blk][re/im][i][j] FP32 copy, formed on first use (mg_need_d32)
     bf16_t* Dbf = nullptr;       // [V1][9][2][nc][nc] planar re/im bfloat16
     double2* G1 = nullptr;       // coarse gammas [V1][b0][3][Nv][Nv] (alpha=0 rows, alpha=1 cols)
     bool have_subspace = false;
@@ -280,7 +282,7 @@ struct mglma_ctx {
     bool have_l2 = false;
     int b2[4] = {0, 0, 0, 0};
     Geo g2;
-    double2* L2D64 = nullptr; double* L2D64p = nullptr; float* L2D32p = nullptr; bf16_t* L2Dbf = nullptr;
+    double2* L2D64 = nullptr; float* L2D32p = nullptr; bf16_t* L2Dbf = nullptr;
 
     // top level
     int Nlm = 0, r = 0;
@@ -363,7 +365,11 @@ static inline size_t prec_cbytes(int prec) {
 }
 void mg_free_subspace(mglma_ctx* c);
 void mg_free_level2(mglma_ctx* c);
+// planar copies of an interleaved operator (any output may be NULL)
 int mg_op_copies(mglma_ctx* c, size_t nblk, int nc, const double2* D, double* D64p, float* D32p, bf16_t* Dbf);
+// the FP32 basis / FP32 planar D_1, formed from the FP64 ones when first needed
+int mg_need_b32(mglma_ctx* c);
+int mg_need_d32(mglma_ctx* c);
 // solve D_level x = b (level 1 or 2; coarse fields F64) to p->tol
 int mg_coarse_solve(mglma_ctx* c, const mglma_solve_params* p, const double* b, double* x, int nrhs,
                     mglma_solve_stats* stats, int level = 1);

@@ -241,7 +241,7 @@ static inline size_t level_n(mglma_ctx* c, int level) {
 }
 static int level_apply(mglma_ctx* c, int level, int prec, const void* in, void* out, int nrhs) {
     if (level == 2)
-        return mg_stencil_apply(c, c->g2, c->nc, c->L2D64p, c->L2D32p, c->L2Dbf, prec, 0, in, out, nrhs);
+        return mg_stencil_apply(c, c->g2, c->nc, (const double*)c->L2D64, c->L2D32p, c->L2Dbf, prec, 0, in, out, nrhs);
     return mg_coarse_apply(c, prec, 0, in, out, nrhs);
 }
 

@@ -155,11 +155,9 @@ __global__ __launch_bounds__(256) void k_apply_rinv(double2* __restrict__ B, int
                 if (d0 + q < d1) {
                     const size_t o = (size_t)(d0 + q) * K + k;
                     W[o] = make_double2(acc[q].re, acc[q].im);
-                    if (B32) {
-                        const size_t og = (size_t)ya * Nv * K + o;
-                        B32[og] = make_float2((float)acc[q].re, (float)acc[q].im);
-                        B16[og] = __floats2half2_rn((float)acc[q].re, (float)acc[q].im);
-                    }
+                    const size_t og = (size_t)ya * Nv * K + o;
+                    if (B32) B32[og] = make_float2((float)acc[q].re, (float)acc[q].im);
+                    if (B16) B16[og] = __floats2half2_rn((float)acc[q].re, (float)acc[q].im);
                 }
         }
     }
@@ -414,6 +412,7 @@ int mg_restrict(mglma_ctx* c, int prec, const void* fine, void* coarse, int nrhs
         prec = MGLMA_F32;
     }
     if (prec != MGLMA_F64 && prec != MGLMA_F32) return MGLMA_ERR_ARG;
+    if (prec == MGLMA_F32) MG_TRY(mg_need_b32(c));
     const size_t cb = prec == MGLMA_F64 ? 16 : 8;
     if (g.Vb % 4 == 0 && c->Nv <= 16 * RMT && (uintptr_t)fine % 16 == 0) {
         dim3 grid(g.V1, 2, (nrhs + 15) / 16);
@@ -463,6 +462,7 @@ int mg_prolong(mglma_ctx* c, int prec, const void* coarse, void* fine, int nrhs)
                                (const double2*)coarse, (double2*)fine, nrhs, nbw, rc);
             break;
         case MGLMA_F32:
+            MG_TRY(mg_need_b32(c));
             hipLaunchKernelGGL((k_prolong<float2, float>), grid, dim3(256), shb, c->stream, g, c->Nv, c->B32,
                                (const float2*)coarse, (float2*)fine, nrhs, nbw, rc);
             break;
@@ -499,17 +499,23 @@ __global__ void k_op_copies(size_t nblk, int nc, const double2* __restrict__ D, 
         double2 v = D[e];
         size_t blk = e / ((size_t)nc * nc), ij = e % ((size_t)nc * nc);
         const size_t er = (blk * 2 + 0) * nc * nc + ij, ei = er + (size_t)nc * nc;
-        D64p[er] = v.x;
-        D64p[ei] = v.y;
+        if (D64p) {
+            D64p[er] = v.x;
+            D64p[ei] = v.y;
+        }
         float fr = (float)v.x, fi = (float)v.y;
-        D32p[er] = fr;
-        D32p[ei] = fi;
-        // round to nearest even
-        uint32_t ur = __float_as_uint(fr), ui = __float_as_uint(fi);
-        ur += 0x7fff + ((ur >> 16) & 1);
-        ui += 0x7fff + ((ui >> 16) & 1);
-        Dbf[er] = (bf16_t)(ur >> 16);
-        Dbf[ei] = (bf16_t)(ui >> 16);
+        if (D32p) {
+            D32p[er] = fr;
+            D32p[ei] = fi;
+        }
+        if (Dbf) {
+            // round to nearest even
+            uint32_t ur = __float_as_uint(fr), ui = __float_as_uint(fi);
+            ur += 0x7fff + ((ur >> 16) & 1);
+            ui += 0x7fff + ((ui >> 16) & 1);
+            Dbf[er] = (bf16_t)(ur >> 16);
+            Dbf[ei] = (bf16_t)(ui >> 16);
+        }
     }
 }
 
@@ -672,12 +678,12 @@ extern "C" int mglma_build_subspace(mglma_ctx* c, int Nv, const double* tv) {
     const int nc = c->nc;
     size_t nb = (size_t)g.V * 12 * Nv;
     size_t nd = (size_t)g.V1 * 9 * nc * nc;
+    // resident: the FP64 basis (R, T of the FP64 path, the Galerkin build, the
+    // coarse gammas), its FP16 copy (the preconditioner's transfers), D_1 and
+    // its BF16 copy; the FP32 basis and FP32 D_1 are formed when first used
     MG_TRY(mg_malloc(c, (void**)&c->B64, nb * 16));
-    MG_TRY(mg_malloc(c, (void**)&c->B32, nb * 8));
     MG_TRY(mg_malloc(c, (void**)&c->B16, nb * 4));
     MG_TRY(mg_malloc(c, (void**)&c->D64, nd * 16));
-    MG_TRY(mg_malloc(c, (void**)&c->D64p, nd * 16));
-    MG_TRY(mg_malloc(c, (void**)&c->D32p, nd * 8));
     MG_TRY(mg_malloc(c, (void**)&c->Dbf, nd * 4));
     MG_TRY(mg_malloc(c, (void**)&c->G1, (size_t)g.V1 * g.b[0] * 3 * Nv * Nv * 16));
 
@@ -698,11 +704,17 @@ extern "C" int mglma_build_subspace(mglma_ctx* c, int Nv, const double* tv) {
     HIP_TRY(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     if (hbad) { mg_free_subspace(c); return MGLMA_ERR_RANK; }
-    MG_TRY(cholqr_pass(c, Gb, Rb, bad, true));   // also writes the FP32 and FP16 copies
+    MG_TRY(cholqr_pass(c, Gb, Rb, bad, true));   // also writes the FP16 copy
 
-    // 3. Galerkin operator, block by block (the column-major FP64 copy is the scratch of the pieces)
-    MG_TRY(mg_galerkin(c, (double2*)c->D64p));
-    MG_TRY(mg_op_copies(c, (size_t)g.V1 * 9, nc, c->D64, c->D64p, c->D32p, c->Dbf));
+    // 3. Galerkin operator, block by block; the forward pieces go to a
+    //    temporary of the operator's size, released after the build
+    double2* gtmp;
+    MG_TRY(mg_malloc(c, (void**)&gtmp, nd * 16));
+    int grc = mg_galerkin(c, gtmp);
+    if (grc == MGLMA_OK) grc = mg_op_copies(c, (size_t)g.V1 * 9, nc, c->D64, nullptr, nullptr, c->Dbf);
+    if (grc == MGLMA_OK && hipStreamSynchronize(c->stream) != hipSuccess) grc = MGLMA_ERR_HIP;
+    mg_free(c, gtmp, nd * 16);
+    if (grc != MGLMA_OK) { mg_free_subspace(c); return grc; }
 
     // 4. coarse gamma matrices
     if ((g.Vb / g.b[0]) % 4 == 0 && Nv <= 32)
@@ -723,6 +735,20 @@ int mg_op_copies(mglma_ctx* c, size_t nblk, int nc, const double2* D, double* D6
     hipLaunchKernelGGL(k_op_copies, dim3(2048), dim3(256), 0, c->stream, nblk, nc, D, D64p, D32p, Dbf);
     HIP_TRY(hipGetLastError());
     return MGLMA_OK;
+}
+
+int mg_need_b32(mglma_ctx* c) {
+    if (c->B32) return MGLMA_OK;
+    const size_t nb = (size_t)c->geo.V * 12 * c->Nv;
+    MG_TRY(mg_malloc(c, (void**)&c->B32, nb * 8));
+    return mg_convert(c, MGLMA_F64, c->B64, MGLMA_F32, c->B32, nb, 1, nullptr, 0);
+}
+
+int mg_need_d32(mglma_ctx* c) {
+    if (c->D32p) return MGLMA_OK;
+    const size_t nd = (size_t)c->geo.V1 * 9 * c->nc * c->nc;
+    MG_TRY(mg_malloc(c, (void**)&c->D32p, nd * 8));
+    return mg_op_copies(c, (size_t)c->geo.V1 * 9, c->nc, c->D64, nullptr, c->D32p, nullptr);
 }
 
 // ---------------------------------------------------------------------------
