@@ -465,7 +465,10 @@ def config4(wl, gb_per_rhs=23.0):
     L, Nv, Nlm, nsrc = wl["L"], wl["Nv"], wl["Nlm"], wl["nsrc"]
     out = {"diagnostic": "48^3x96 configuration (N_v = %d, N_lm = %d, %d sources x 4 spins)" % (Nv, Nlm, nsrc)}
     t0 = time.time()
-    U = synth_mod.gauge_field(L, wl["eps"], wl["seed"])
+    def prog(done, tot):
+        if done == tot or (done >> 20) % 8 == 0:
+            log("c4: gauge field %d / %d links (%.0f s)" % (done, tot, time.time() - t0))
+    U = synth_mod.gauge_field(L, wl["eps"], wl["seed"], progress=prog)
     out["gauge_host_s"] = round(time.time() - t0, 1)
     ctx = mglma.Context(L, wl["block"], wl["kappa"], wl["csw"])
     Ud = torch.from_numpy(U.view(np.float64)).cuda()
@@ -491,6 +494,8 @@ def config4(wl, gb_per_rhs=23.0):
             tv[k0:k0 + 4] = y / nrm[:, None, None, None]
     del y
     torch.cuda.synchronize()
+    ctx.release_workspace()          # the GCR workspace of the batches of four
+    torch.cuda.empty_cache()
     out["testvec_s"] = round(time.time() - t1, 1)
     t1 = time.time()
     ctx.build_subspace(tv)
@@ -516,6 +521,7 @@ def config4(wl, gb_per_rhs=23.0):
     t1 = time.time()
     G_exact = ctx.contract_top()
     out["contract_top_ms"] = round(1e3 * (time.time() - t1), 2)
+    ctx.release_workspace()
     torch.cuda.empty_cache()
     free, total = torch.cuda.mem_get_info()
     nb = int(max(1, min(3, (0.8 * free / 1e9) // (4 * gb_per_rhs))))     # sources per batch

@@ -153,6 +153,13 @@ long mglma_query(const mglma_ctx* ctx, int what);
  * not counting freed blocks the context keeps for reuse (at most 16 GiB;
  * rebuilding the subspace reuses them instead of calling hipMalloc).      */
 size_t mglma_resident_bytes(const mglma_ctx* ctx);
+/* Release the device workspaces that the calls keep between calls (solver
+ * and contraction scratch, sized by the largest batch seen) and the freed
+ * blocks kept for reuse, so that the memory is available to the caller or
+ * to the next large allocation (e.g. a subspace build after a setup phase
+ * with large batches).  Later calls allocate their workspace again.
+ * Synchronising.  Errors: ARG, HIP.                                        */
+int mglma_release_workspace(mglma_ctx* ctx);
 /* Bytes of one fine / coarse field of `prec` (times nrhs).                  */
 size_t mglma_fine_bytes(const mglma_ctx* ctx, int prec, int nrhs);
 size_t mglma_coarse_bytes(const mglma_ctx* ctx, int prec, int nrhs);

@@ -123,6 +123,27 @@ int mg_scratch(mglma_ctx* c, int slot, size_t bytes, void** out) {
     return MGLMA_OK;
 }
 
+// ABI: give the per-call workspaces and the reuse list back to the device
+extern "C" int mglma_release_workspace(mglma_ctx* c) {
+    if (!c) return MGLMA_ERR_ARG;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int k = 0; k < mglma_ctx::NSCR; ++k) {
+        Scratch& s = c->scr[k];
+        if (s.ptr) {
+            auto it = c->alloc_size.find(s.ptr);
+            if (it != c->alloc_size.end()) {
+                c->resident -= it->second;
+                c->alloc_size.erase(it);
+            }
+            (void)hipFree(s.ptr);
+        }
+        s.ptr = nullptr;
+        s.bytes = 0;
+    }
+    cache_release(c);
+    return MGLMA_OK;
+}
+
 int mg_host(mglma_ctx* c, size_t n, double** out) {
     if (c->hbuf_n < n) {
         if (c->hbuf) (void)hipHostFree(c->hbuf);

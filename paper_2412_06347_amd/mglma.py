@@ -34,7 +34,7 @@ SYMBOLS = [
     "mglma_level2_apply", "mglma_level2_solve", "mglma_level2_pieces", "mglma_save", "mglma_load",
     "mglma_adaptive_setup", "mglma_sap_smooth", "mglma_sap_timing", "mglma_sap_elapsed",
     "mglma_contract_pair", "mglma_contract_levels", "mglma_contract_levels_noalloc",
-    "mglma_contract_levels_acc", "mglma_slots_create", "mglma_slots_destroy", "mglma_slots_load", "mglma_slots_step", "mglma_slots_take",
+    "mglma_contract_levels_acc", "mglma_release_workspace", "mglma_slots_create", "mglma_slots_destroy", "mglma_slots_load", "mglma_slots_step", "mglma_slots_take",
 ]
 
 
@@ -161,6 +161,10 @@ class Context:
 
     def resident_bytes(self):
         return int(lib().mglma_resident_bytes(self._ctx))
+
+    def release_workspace(self):
+        """Free the workspaces kept between calls and the reuse list."""
+        _check(lib().mglma_release_workspace(self._ctx))
 
     # ---- allocation helpers (device memory from torch) ------------------
     def fine(self, nrhs, prec=F64, device="cuda"):

@@ -64,8 +64,9 @@ def _exp_i_hermitian(H, eps, chunk=1 << 20):
     return out
 
 
-def gauge_field(L, eps: float, seed: int) -> np.ndarray:
-    """Random SU(3) links, canonical ``[V][4][3][3]`` complex128."""
+def gauge_field(L, eps: float, seed: int, progress=None) -> np.ndarray:
+    """Random SU(3) links, canonical ``[V][4][3][3]`` complex128.  progress,
+    if given, is called with (links done, links) after each chunk."""
     V = volume(L)
     g = generator(seed, 1)
     lam = _gell_mann() / 2
@@ -76,6 +77,8 @@ def gauge_field(L, eps: float, seed: int) -> np.ndarray:
         h = g.standard_normal((n, 8))
         H = np.tensordot(h, lam, axes=(1, 0))
         U[i0:i0 + n] = _exp_i_hermitian(H, eps)
+        if progress is not None:
+            progress(i0 + n, V * 4)
     return U.reshape(V, 4, 3, 3)
 
 
