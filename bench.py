@@ -458,7 +458,7 @@ def config4(wl, gb_per_rhs=23.0):
     spins = 192 right-hand sides solved as multi-RHS batches sized by the
     free HBM, and the translation-averaged low-mode contraction eq:G_LL:exact.
     Test vectors: Gaussian fields drawn on the device (seeded torch
-    generator), improved by two rounds of 20 plain FP32 GCR(8) steps in
+    generator), improved by three rounds of 40 plain FP32 GCR(8) steps in
     batches of four.  Prints one JSON line with the times and sizes."""
     import torch
     from paper_2412_06347_amd import mglma, synth as synth_mod
@@ -484,10 +484,10 @@ def config4(wl, gb_per_rhs=23.0):
     gen.manual_seed(wl["seed"] + 1000)
     tv = ctx.fine(Nv)
     tv.normal_(generator=gen)
-    p = mglma.default_params(use_mg=0, inner=mglma.F32, max_outer=1, max_inner=20, gcr_m=8, tol=1e-30,
+    p = mglma.default_params(use_mg=0, inner=mglma.F32, max_outer=1, max_inner=40, gcr_m=8, tol=1e-30,
                              inner_tol=1e-30)
     y = ctx.fine(4)
-    for _ in range(2):
+    for _ in range(3):
         for k0 in range(0, Nv, 4):
             ctx.solve(tv[k0:k0 + 4], y, p, raise_on_error=False)
             nrm = torch.linalg.vector_norm(y.reshape(4, -1), dim=1)
