@@ -74,74 +74,114 @@ __global__ void k_split_modes(int Nlm, int V1, int nc, const double2* __restrict
     }
 }
 
-// Gamma2 partial: A[x0][k][a][b] = sum_{y in row(x0)} W0_y^+ (Gb_y(t) W1_y)  (W0/W1: alpha=0/1 rows).
-// grid (L0, 3, TSPLIT), block 256: workgroup z takes the z-th of TSPLIT
-// consecutive ranges of the coarse sites of the time row and writes its own
-// partial sum (added in z order by k_sum_parts).  Columns b in tiles of TB:
-// per coarse site the W1 rows of the tile are staged in LDS (coalesced),
-// T = Gb W1 (Nv x TB) is formed in LDS, then the W0 rows in chunks of 16 and
-// each thread adds one (a, b) entry of W0^+ T per chunk.  Needs Nv <= 64 and
-// r <= 128 (at most 8 chunks).
-#define TB 16
-#define TSPLIT 48
-__global__ __launch_bounds__(256) void k_top_gamma(Geo g, int Nv, int r, const double2* __restrict__ W,
-                                                   const double2* __restrict__ G1, double2* __restrict__ A) {
-    const int x0 = blockIdx.x, k = blockIdx.y, z = blockIdx.z;
-    const int b0 = g.b[0], y0 = x0 / b0, t = x0 % b0;
+// Gamma2 partial on the FP64 matrix cores (v_mfma_f64_16x16x4):
+//   A[z][x0][k][a][b] = sum_{y in range z of row(x0)} sum_c conj(W0_y[a][c]) T_y[c][b],
+//   T_y = Gb_y(t, k) W1_y   (c, d < Nv; W0 / W1 the alpha = 0 / 1 rows of W at y),
+// t = x0 mod b0.  grid (L0 * 3, ceil(r / 16) column tiles, TSPLIT site
+// ranges), block 256 = 4 wavefronts.  Per coarse site: wavefronts ct <
+// NCT = ceil(Nv / 16) form the 16-row tile ct of T's 16 columns of this
+// workgroup and leave it in LDS; then every wavefront adds W0^+ T to its
+// row tiles a = 16 (w + 4 j).  In an MFMA lane (lr, lq) supplies A[lr][k]
+// and B[k][lr] with k = k0 + 4 lq + s over four successive MFMAs s, so a
+// lane's four operator entries are consecutive in memory; register q of
+// the result is row lq + 4 q of the tile (FP64 layout).
+#define TSPLIT 16
+template <int NCT>
+__global__ __launch_bounds__(256) void k_top_gamma_mfma(Geo g, int Nv, int r, const double2* __restrict__ W,
+                                                        const double2* __restrict__ G1, double2* __restrict__ A) {
+    typedef Mfma<double>::v4 V4;
+    __shared__ double2 Ts[NCT * 16 * 16];
+    const int x0 = blockIdx.x / 3, k = blockIdx.x - 3 * x0;
+    const int bt = blockIdx.y * 16, z = blockIdx.z;
+    const int b0 = g.b[0], y0 = x0 / b0, t = x0 - y0 * b0;
     const int nc = 2 * Nv, rowsz = g.V1 / g.L1[0];
     const int ys0 = (int)((long)rowsz * z / TSPLIT), ys1 = (int)((long)rowsz * (z + 1) / TSPLIT);
     const size_t V1 = g.V1;
-    A += (size_t)z * g.L[0] * 3 * r * r;
-    __shared__ double2 W1s[TB * 64], Ts[64 * TB], W0s[16 * 64];
-    const int tid = threadIdx.x;
-    const int la = tid / TB, lb = tid % TB;       // this thread's entry (a0 + la, bt + lb) of a chunk
-    const int nchunk = (r + 15) / 16;
-    for (int bt = 0; bt < r; bt += TB) {
-        const int nb = r - bt < TB ? r - bt : TB;
-        cx<double> acc[8];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lq = lane >> 4;
+    const int nat = (r + 15) >> 4;
+    const int bcol = bt + lr;
+    const bool bok = bcol < r;
+    V4 cr[2], ci[2];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) acc[q] = cmk(0.0, 0.0);
-        for (int ys = ys0; ys < ys1; ++ys) {
-            const int y = y0 * rowsz + ys;
+    for (int j = 0; j < 2; ++j) {
+        cr[j] = V4{0, 0, 0, 0};
+        ci[j] = V4{0, 0, 0, 0};
+    }
+    for (int ys = ys0; ys < ys1; ++ys) {
+        const int y = y0 * rowsz + ys;
+        // T tile w = Gb rows 16 w .. 16 w + 15 times W1 (this workgroup's 16 columns)
+        if (w < NCT) {
             const double2* Gb = G1 + (((size_t)y * b0 + t) * 3 + k) * Nv * Nv;
-            __syncthreads();
-            for (int e = tid; e < nb * Nv; e += blockDim.x) {
-                const int bb = e / Nv, d = e - bb * Nv;
-                W1s[bb * 64 + d] = W[((size_t)(bt + bb) * V1 + y) * nc + Nv + d];
-            }
-            __syncthreads();
-            for (int e = tid; e < Nv * nb; e += blockDim.x) {
-                const int cc = e / nb, bb = e - cc * nb;
-                cx<double> s = cmk(0.0, 0.0);
-                for (int d = 0; d < Nv; ++d)
-                    cmac(s, ldc<double2, double>(Gb + cc * Nv + d), ldc<double2, double>(W1s + bb * 64 + d));
-                Ts[cc * TB + bb] = make_double2(s.re, s.im);
+            const double2* W1 = W + ((size_t)(bok ? bcol : 0) * V1 + y) * nc + Nv;
+            const int c = 16 * w + lr;
+            V4 tr = V4{0, 0, 0, 0}, ti = V4{0, 0, 0, 0};
+            for (int k0 = 0; k0 < Nv; k0 += 16) {
+                const int kb = k0 + 4 * lq;
+                double ar[4], ai[4], br[4], bi[4];
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int d = kb + s;
+                    const double2 gv = (c < Nv && d < Nv) ? Gb[(size_t)c * Nv + d] : make_double2(0.0, 0.0);
+                    const double2 wv = (bok && d < Nv) ? W1[d] : make_double2(0.0, 0.0);
+                    ar[s] = gv.x;
+                    ai[s] = gv.y;
+                    br[s] = wv.x;
+                    bi[s] = wv.y;
+                }
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    tr = Mfma<double>::mac(ar[s], br[s], tr);
+                    tr = Mfma<double>::mac(-ai[s], bi[s], tr);
+                    ti = Mfma<double>::mac(ar[s], bi[s], ti);
+                    ti = Mfma<double>::mac(ai[s], br[s], ti);
+                }
             }
 #pragma unroll
-            for (int ch = 0; ch < 8; ++ch) {
-                if (ch >= nchunk) continue;   // uniform over the workgroup
-                const int a0 = ch * 16, na = r - a0 < 16 ? r - a0 : 16;
-                __syncthreads();
-                for (int e = tid; e < na * Nv; e += blockDim.x) {
-                    const int aa = e / Nv, cc = e - aa * Nv;
-                    W0s[aa * 64 + cc] = W[((size_t)(a0 + aa) * V1 + y) * nc + cc];
+            for (int q = 0; q < 4; ++q)
+                Ts[(16 * w + Mfma<double>::row(lq, q)) * 16 + lr] = make_double2(tr[q], ti[q]);
+        }
+        __syncthreads();
+        // A tiles of this wavefront += W0^+ T
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int ta = w + 4 * j;
+            if (ta >= nat) continue;                       // uniform over the wavefront
+            const int a = 16 * ta + lr;
+            const double2* W0 = W + ((size_t)(a < r ? a : 0) * V1 + y) * nc;
+            for (int k0 = 0; k0 < Nv; k0 += 16) {
+                const int kb = k0 + 4 * lq;
+                double ar[4], ai[4], br[4], bi[4];
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int cc = kb + s;
+                    const double2 wv = (a < r && cc < Nv) ? W0[cc] : make_double2(0.0, 0.0);
+                    const double2 tv = cc < 16 * NCT ? Ts[cc * 16 + lr] : make_double2(0.0, 0.0);
+                    ar[s] = wv.x;
+                    ai[s] = wv.y;
+                    br[s] = tv.x;
+                    bi[s] = tv.y;
                 }
-                __syncthreads();
-                if (la < na && lb < nb) {
-                    cx<double> s = acc[ch];
-                    for (int cc = 0; cc < Nv; ++cc) {
-                        const double2 tv = Ts[cc * TB + lb];
-                        cjmac(s, ldc<double2, double>(W0s + la * 64 + cc), cmk(tv.x, tv.y));
-                    }
-                    acc[ch] = s;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    // conj(a) b
+                    cr[j] = Mfma<double>::mac(ar[s], br[s], cr[j]);
+                    cr[j] = Mfma<double>::mac(ai[s], bi[s], cr[j]);
+                    ci[j] = Mfma<double>::mac(ar[s], bi[s], ci[j]);
+                    ci[j] = Mfma<double>::mac(-ai[s], br[s], ci[j]);
                 }
             }
         }
+        __syncthreads();                                   // T of the next site overwrites Ts
+    }
+    double2* Az = A + (((size_t)z * g.L[0] + x0) * 3 + k) * r * r;
 #pragma unroll
-        for (int ch = 0; ch < 8; ++ch) {
-            const int a = ch * 16 + la;
-            if (ch < nchunk && a < r && lb < nb)
-                A[(((size_t)x0 * 3 + k) * r + a) * r + bt + lb] = make_double2(acc[ch].re, acc[ch].im);
+    for (int j = 0; j < 2; ++j) {
+        const int ta = w + 4 * j;
+        if (ta >= nat || !bok) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int a = 16 * ta + Mfma<double>::row(lq, q);
+            if (a < r) Az[(size_t)a * r + bcol] = make_double2(cr[j][q], ci[j][q]);
         }
     }
 }
@@ -231,7 +271,16 @@ extern "C" int mglma_set_top_modes(mglma_ctx* c, int Nlm, const double* modes) {
     const size_t na = (size_t)g.L[0] * 3 * r * r;
     MG_TRY(mg_scratch(c, 0, na * 16, (void**)&Ad));
     MG_TRY(mg_scratch(c, 6, (size_t)TSPLIT * na * 16, (void**)&Ap));
-    hipLaunchKernelGGL(k_top_gamma, dim3(g.L[0], 3, TSPLIT), dim3(256), 0, c->stream, g, c->Nv, r, c->W, c->G1, Ap);
+    {
+        const dim3 grid(g.L[0] * 3, (r + 15) / 16, TSPLIT);
+        const int nct = (c->Nv + 15) / 16;
+        switch (nct) {
+            case 1: hipLaunchKernelGGL(k_top_gamma_mfma<1>, grid, dim3(256), 0, c->stream, g, c->Nv, r, c->W, c->G1, Ap); break;
+            case 2: hipLaunchKernelGGL(k_top_gamma_mfma<2>, grid, dim3(256), 0, c->stream, g, c->Nv, r, c->W, c->G1, Ap); break;
+            case 3: hipLaunchKernelGGL(k_top_gamma_mfma<3>, grid, dim3(256), 0, c->stream, g, c->Nv, r, c->W, c->G1, Ap); break;
+            default: hipLaunchKernelGGL(k_top_gamma_mfma<4>, grid, dim3(256), 0, c->stream, g, c->Nv, r, c->W, c->G1, Ap); break;
+        }
+    }
     hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((na + 255) / 256 < 4096 ? (na + 255) / 256 : 4096)), dim3(256), 0,
                        c->stream, Ap, TSPLIT, na, Ad);
     HIP_TRY(hipGetLastError());
