@@ -258,3 +258,30 @@ def solve_eo_deflated(S, Y, bh):
     x0 = Y @ (Ei @ (Y.conj().T @ bh))
     z = np.linalg.lstsq(PL @ S, PL @ bh, rcond=None)[0]
     return x0 + PR @ z
+
+
+# ---------------------------------------------------------------------------
+# coarsening without chiral split (appendix on the spectra of coarse and fine
+# operators: the coarse spin degree of freedom trivial)
+# ---------------------------------------------------------------------------
+def nonchiral_basis(bl, testvecs_lat):
+    """Per block y the Nv fields theta_{B_y} v_c over all four spins,
+    Gram-Schmidt in order c: [V1][Nv][b0..b3][4][3]."""
+    Nv = testvecs_lat.shape[0]
+    vb = np.moveaxis(bl.to_blocks(testvecs_lat), 0, 1)         # [V1][Nv][b..][4][3]
+    q = gram_schmidt(vb.reshape(bl.V1, Nv, -1))
+    return q.reshape(bl.V1, Nv, *bl.b, 4, 3)
+
+
+def nonchiral_dense(Qd, bl, testvecs_lat):
+    """Q_nc = T_nc^+ Q T_nc (dense, (V1 Nv) x (V1 Nv)) for the dense Hermitian
+    fine operator Qd (canonical order) and the block basis without chiral
+    split; coarse index y * Nv + c.  Tiny lattices only."""
+    Nv = testvecs_lat.shape[0]
+    phi = nonchiral_basis(bl, testvecs_lat)
+    cols = np.zeros((bl.V1 * Nv, bl.V1, *bl.b, 4, 3), dtype=np.complex128)
+    for y in range(bl.V1):
+        for c in range(Nv):
+            cols[y * Nv + c, y] = phi[y, c]
+    T = bl.from_blocks(cols).reshape(bl.V1 * Nv, -1).T             # [12 V][V1 Nv]
+    return T.conj().T @ Qd @ T
