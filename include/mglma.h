@@ -291,7 +291,7 @@ int mglma_set_top_modes(mglma_ctx* ctx, int Nlm, const double* modes_dev);
  * subspace iteration on Q_1^2 over a block of nblk = nev + nguard coarse
  * vectors, FP64 throughout, with a Rayleigh-Ritz step on Q_1 per iteration.
  *   p->nev      wanted pairs (>= 1); p->nguard extra block vectors (>= 0),
- *               nblk <= 64 and nblk <= V1 nc
+ *               nblk <= 128 and nblk <= V1 nc
  *   p->degree   Chebyshev degree in Q_1^2 per iteration (0: 40)
  *   p->max_iter filter iterations (0: 100)
  *   p->tol      converged when |Q_1 v - lambda v| <= tol for every wanted
@@ -315,16 +315,45 @@ typedef struct {
     double max_res;         /* largest |Q_1 v - lambda v| of the wanted pairs  */
     double spectrum_bound;  /* the bound b >= lambda_max(Q_1^2) used          */
     double seconds;
+    double lambda_max_abs;  /* |lambda|_max of the operator estimated by the
+                               largest Lanczos Ritz value of its square     */
 } mglma_eig_stats;
 int mglma_coarse_eigs(mglma_ctx* ctx, const mglma_eig_params* p, const double* init_dev, double* evals,
                       double* evecs_dev, mglma_eig_stats* stats);
 /* The same for the fine operator Q = gamma5 M (the paper's low modes of Q,
  * from which its block basis is built): init_dev and evecs_dev are fine
  * fields in the device layout (F64, [nblk] and [nev] of them), the limits
- * nblk <= 64 and nblk <= 12 V.  Allocates five blocks of nblk fine fields.
+ * nblk <= 128 and nblk <= 12 V.  Allocates five blocks of nblk fine fields.
  * Errors: NO_GAUGE, ARG, NONFINITE, NOT_CONVERGED.                         */
 int mglma_fine_eigs(mglma_ctx* ctx, const mglma_eig_params* p, const double* init_dev, double* evals,
                     double* evecs_dev, mglma_eig_stats* stats);
+/* Spectral diagnostics of the Hermitian operators of every level (the
+ * appendices on the spectra of coarse and fine operators and on the
+ * condition numbers of coarse-grid operators): the same eigensolver on
+ *   MGLMA_OP_FINE       Q = gamma5 M (fine fields, device layout),
+ *   MGLMA_OP_COARSE     Q_1 = (gamma5)_1 D_1 (chirally split basis),
+ *   MGLMA_OP_LEVEL2     Q_2 = (gamma5)_2 D_2 of mglma_build_level2 (level-2
+ *                       fields [V2][nc]),
+ *   MGLMA_OP_NONCHIRAL  Q_nc = T_nc^+ Q T_nc of mglma_build_nonchiral
+ *                       (fields [V1][Nv]),
+ * with nblk <= 128.  The condition number of a level is
+ * stats->lambda_max_abs / |evals[0]|.  Errors as mglma_coarse_eigs, and
+ * NO_SUBSPACE when the level's operator is not built.                    */
+enum { MGLMA_OP_FINE = 0, MGLMA_OP_COARSE = 1, MGLMA_OP_LEVEL2 = 2, MGLMA_OP_NONCHIRAL = 3 };
+int mglma_level_eigs(mglma_ctx* ctx, int op, const mglma_eig_params* p, const double* init_dev, double* evals,
+                     double* evecs_dev, mglma_eig_stats* stats);
+/* The coarse operator without chiral split, for comparison with the
+ * chirally split one: per block the Nv vectors theta_B v_c (all four spins,
+ * testvecs_dev = the Nv test vectors of the subspace, F64 device layout)
+ * orthonormalised in order c (positive real diagonal) form T_nc, and
+ * Q_nc = T_nc^+ Q T_nc, built from D_1 as S^+ (gamma5)_1 D_1 S with
+ * S_y = Phi_y^+ (theta_B v_c) orthonormalised.  Kept until the subspace
+ * changes.  mglma_export_nonchiral_op copies it as [V1][9][Nv][Nv]
+ * complex128 (direction convention of D_1).  Needs Nv <= 32.
+ * Synchronising.  Errors: ARG, NO_SUBSPACE, RANK, OOM.                    */
+int mglma_build_nonchiral(mglma_ctx* ctx, const double* testvecs_dev);
+int mglma_export_nonchiral_op(mglma_ctx* ctx, double* out_dev);
+
 /* Local-coherence deficits (eq:cdeficit): eps[r] = |(1 - P) psi_r| / |psi_r|
  * for nrhs fine fields psi (device layout, F64), P = T R the projector on
  * the block subspace; 0 for a zero field.  eps is a host array [nrhs].

@@ -14,19 +14,6 @@
 //   FP32 vectors are rounded to bfloat16 on load and accumulation is FP32.
 #include "mglma_internal.h"
 
-__device__ __forceinline__ int coarse_nbr(const Geo& g, int y, int dir) {
-    if (dir == 0) return y;
-    int mu = (dir - 1) >> 1;
-    int sg = (dir & 1) ? 1 : -1;
-    // coordinate of y along mu in the block grid
-    int stride = g.sk[mu];
-    int cmu = (y / stride) % g.L1[mu];
-    int nmu = cmu + sg;
-    if (nmu < 0) nmu += g.L1[mu];
-    if (nmu >= g.L1[mu]) nmu -= g.L1[mu];
-    return y + (nmu - cmu) * stride;
-}
-
 // FP64 / FP32 on the matrix cores (v_mfma_*_16x16x4).
 // grid: (V1, ceil(nrhs/16)); block: 64 * ceil(nc/16) threads, wave w owns
 // output rows 16w..16w+15 and the 16 right-hand sides of blockIdx.y.

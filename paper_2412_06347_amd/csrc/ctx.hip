@@ -231,6 +231,8 @@ static void free_top(mglma_ctx* c) {
 void mg_free_subspace(mglma_ctx* c) {
     const Geo& g = c->geo;
     free_top(c);
+    mg_free(c, c->NC64, 0);
+    c->NC64 = nullptr;
     mg_eo_free(c);
     mg_free_level2(c);
     size_t nb = (size_t)g.V * 12 * c->Nv;

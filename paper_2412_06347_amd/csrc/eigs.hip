@@ -58,15 +58,20 @@ __global__ void k_ritz_resid(double2* __restrict__ out, const double2* __restric
     }
 }
 
-// Z_j = sum_i X_i M[i][j] for j < nb <= 64 (M complex, row-major nb x nb,
-// staged in LDS); each thread one entry index of all nb output vectors.
+// Z_j = sum_i X_i M[i][j] for j0 <= j < j0 + 64 and j < nb <= 128 (M
+// complex, row-major nb x nb; its columns j0..j0+63 staged in LDS); each
+// thread one entry index of those output vectors.
 __global__ __launch_bounds__(256) void k_block_combine(double2* __restrict__ Z, const double2* __restrict__ X,
-                                                       const double2* __restrict__ M, size_t n, int nb) {
-    extern __shared__ double2 sm[];
-    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) sm[e] = M[e];
+                                                       const double2* __restrict__ M, size_t n, int nb, int j0) {
+    extern __shared__ double2 sm[];   // [nb][64]
+    const int nj = nb - j0 < 64 ? nb - j0 : 64;
+    for (int e = threadIdx.x; e < nb * nj; e += blockDim.x) {
+        const int i = e / nj, j = e - i * nj;
+        sm[i * 64 + j] = M[(size_t)i * nb + j0 + j];
+    }
     __syncthreads();
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-        for (int j0 = 0; j0 < nb; j0 += 8) {
+        for (int jj = 0; jj < nj; jj += 8) {
             double2 acc[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) acc[q] = make_double2(0.0, 0.0);
@@ -74,8 +79,8 @@ __global__ __launch_bounds__(256) void k_block_combine(double2* __restrict__ Z, 
                 const double2 x = X[(size_t)i * n + e];
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
-                    if (j0 + q < nb) {
-                        const double2 m = sm[i * nb + j0 + q];
+                    if (jj + q < nj) {
+                        const double2 m = sm[i * 64 + jj + q];
                         acc[q].x = fma(x.x, m.x, fma(-x.y, m.y, acc[q].x));
                         acc[q].y = fma(x.x, m.y, fma(x.y, m.x, acc[q].y));
                     }
@@ -83,7 +88,7 @@ __global__ __launch_bounds__(256) void k_block_combine(double2* __restrict__ Z, 
             }
 #pragma unroll
             for (int q = 0; q < 8; ++q)
-                if (j0 + q < nb) Z[(size_t)(j0 + q) * n + e] = acc[q];
+                if (jj + q < nj) Z[(size_t)(j0 + jj + q) * n + e] = acc[q];
         }
     }
 }
@@ -91,8 +96,9 @@ __global__ __launch_bounds__(256) void k_block_combine(double2* __restrict__ Z, 
 int mg_block_combine(mglma_ctx* c, double2* Z, const double2* X, const double2* M_dev, size_t n, int nb) {
     size_t g = (n + 255) / 256;
     g = g > 4096 ? 4096 : (g < 1 ? 1 : g);
-    hipLaunchKernelGGL(k_block_combine, dim3((unsigned)g), dim3(256), (size_t)nb * nb * sizeof(double2), c->stream, Z,
-                       X, M_dev, n, nb);
+    for (int j0 = 0; j0 < nb; j0 += 64)
+        hipLaunchKernelGGL(k_block_combine, dim3((unsigned)g), dim3(256), (size_t)nb * 64 * sizeof(double2),
+                           c->stream, Z, X, M_dev, n, nb, j0);
     HIP_TRY(hipGetLastError());
     return MGLMA_OK;
 }
@@ -101,7 +107,7 @@ namespace {
 
 struct Eig {
     mglma_ctx* c;
-    int level;     // 0: fine Q = gamma5 M, 1: coarse Q_1
+    int level;     // MGLMA_OP_FINE, _COARSE, _LEVEL2 or _NONCHIRAL
     size_t n;      // complex entries per vector
     int nb;        // block size
     double2 *M = nullptr, *G = nullptr;   // device nb x nb matrices
@@ -112,20 +118,35 @@ struct Eig {
         size_t g = (tot + 255) / 256;
         return (int)(g > 4096 ? 4096 : (g < 1 ? 1 : g));
     }
-    // y = Q x for k vectors
+    // y = Q x for k vectors (the Hermitian operator of the level)
     int q1(const double2* x, double2* y, int k) {
         applies += k;
-        return level == 1 ? mg_coarse_apply(c, MGLMA_F64, 1, x, y, k) : mg_dslash(c, MGLMA_F64, 1, x, y, k);
+        switch (level) {
+            case MGLMA_OP_COARSE: return mg_coarse_apply(c, MGLMA_F64, 1, x, y, k);
+            case MGLMA_OP_LEVEL2:
+                return mg_stencil_apply(c, c->g2, c->nc, (const double*)c->L2D64, c->L2D32p, c->L2Dbf, MGLMA_F64, 1,
+                                        x, y, k);
+            case MGLMA_OP_NONCHIRAL:
+                return mg_stencil_apply(c, c->geo, c->Nv, (const double*)c->NC64, nullptr, nullptr, MGLMA_F64, 0, x,
+                                        y, k);
+            default: return mg_dslash(c, MGLMA_F64, 1, x, y, k);
+        }
     }
-    // host G[i][j] = <X_i, Y_j> for i < kx, j < ky
+    // host G[i][j] = <X_i, Y_j> for i < kx, j < ky (64 x 64 tiles)
     int gram(const double2* X, int kx, const double2* Y, int ky, std::vector<zc>& Gh) {
-        MG_TRY(mg_gram64(c, X, kx, Y, ky, n, (double*)G));
-        std::vector<double2> tmp((size_t)kx * ky);
-        HIP_TRY(hipMemcpyAsync(tmp.data(), G, tmp.size() * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
-        HIP_TRY(hipStreamSynchronize(c->stream));
         Gh.resize((size_t)kx * ky);
-        for (int j = 0; j < ky; ++j)
-            for (int i = 0; i < kx; ++i) Gh[(size_t)i * ky + j] = zc(tmp[(size_t)j * kx + i].x, tmp[(size_t)j * kx + i].y);
+        for (int i0 = 0; i0 < kx; i0 += 64)
+            for (int j0 = 0; j0 < ky; j0 += 64) {
+                const int ki = std::min(64, kx - i0), kj = std::min(64, ky - j0);
+                MG_TRY(mg_gram64(c, X + (size_t)i0 * n, ki, Y + (size_t)j0 * n, kj, n, (double*)G));
+                std::vector<double2> tmp((size_t)ki * kj);
+                HIP_TRY(hipMemcpyAsync(tmp.data(), G, tmp.size() * sizeof(double2), hipMemcpyDeviceToHost,
+                                       c->stream));
+                HIP_TRY(hipStreamSynchronize(c->stream));
+                for (int j = 0; j < kj; ++j)
+                    for (int i = 0; i < ki; ++i)
+                        Gh[(size_t)(i0 + i) * ky + j0 + j] = zc(tmp[(size_t)j * ki + i].x, tmp[(size_t)j * ki + i].y);
+            }
         return MGLMA_OK;
     }
     // Z = X Mh (Mh host, nb x nb row-major)
@@ -133,9 +154,7 @@ struct Eig {
         std::vector<double2> tmp((size_t)nb * nb);
         for (size_t e = 0; e < tmp.size(); ++e) tmp[e] = make_double2(Mh[e].real(), Mh[e].imag());
         HIP_TRY(hipMemcpyAsync(M, tmp.data(), tmp.size() * sizeof(double2), hipMemcpyHostToDevice, c->stream));
-        hipLaunchKernelGGL(k_block_combine, dim3(grid_for(n)), dim3(256), (size_t)nb * nb * sizeof(double2),
-                           c->stream, Z, X, M, n, nb);
-        HIP_TRY(hipGetLastError());
+        MG_TRY(mg_block_combine(c, Z, X, M, n, nb));
         HIP_TRY(hipStreamSynchronize(c->stream));   // tmp is a host stack buffer
         return MGLMA_OK;
     }
@@ -170,13 +189,30 @@ static int eigs_run(mglma_ctx* c, int level, const mglma_eig_params* p, const do
                     double* evecs, mglma_eig_stats* stats) {
     auto t0 = std::chrono::steady_clock::now();
     if (!c || !p || !init || !evals || !evecs) return MGLMA_ERR_ARG;
-    if (level == 1 && !c->have_subspace) return MGLMA_ERR_NO_SUBSPACE;
-    if (level == 0 && !c->have_gauge) return MGLMA_ERR_NO_GAUGE;
-    const size_t n = level == 1 ? (size_t)c->geo.V1 * c->nc : (size_t)12 * c->geo.V;
+    size_t n;
+    switch (level) {
+        case MGLMA_OP_FINE:
+            if (!c->have_gauge) return MGLMA_ERR_NO_GAUGE;
+            n = (size_t)12 * c->geo.V;
+            break;
+        case MGLMA_OP_COARSE:
+            if (!c->have_subspace) return MGLMA_ERR_NO_SUBSPACE;
+            n = (size_t)c->geo.V1 * c->nc;
+            break;
+        case MGLMA_OP_LEVEL2:
+            if (!c->have_l2) return MGLMA_ERR_NO_SUBSPACE;
+            n = (size_t)c->g2.V1 * c->nc;
+            break;
+        case MGLMA_OP_NONCHIRAL:
+            if (!c->NC64) return MGLMA_ERR_NO_SUBSPACE;
+            n = (size_t)c->geo.V1 * c->Nv;
+            break;
+        default: return MGLMA_ERR_ARG;
+    }
     const int nev = p->nev, nb = p->nev + p->nguard;
     const int deg = p->degree > 0 ? p->degree : 40;
     const int maxit = p->max_iter > 0 ? p->max_iter : 100;
-    if (nev < 1 || p->nguard < 0 || nb > 64 || (size_t)nb > n || !(p->tol > 0.0) || deg > 10000)
+    if (nev < 1 || p->nguard < 0 || nb > 128 || (size_t)nb > n || !(p->tol > 0.0) || deg > 10000)
         return MGLMA_ERR_ARG;
     Eig E;
     E.c = c; E.level = level; E.n = n; E.nb = nb;
@@ -212,7 +248,7 @@ static int eigs_run(mglma_ctx* c, int level, const mglma_eig_params* p, const do
     const int g1 = E.grid_for(n), gb = E.grid_for((size_t)nb * n);
 
     // ---- 1. spectral bound of A = Q_1^2: Lanczos on the first start vector
-    double bnd = 0.0;
+    double bnd = 0.0, lmax = 0.0;
     {
         const int m = (int)std::min<size_t>(24, n);
         double* h;
@@ -262,6 +298,7 @@ static int eigs_run(mglma_ctx* c, int level, const mglma_eig_params* p, const do
         double tmax = 0.0;
         for (double v2 : th) tmax = std::max(tmax, v2);
         bnd = 1.01 * (tmax + be[k - 1]);
+        lmax = std::sqrt(std::max(tmax, 0.0));      // largest Ritz value of A: |lambda|_max of Q estimated
     }
 
     // ---- 2. start block: orthonormalise init, first Rayleigh-Ritz for the cutoff
@@ -368,6 +405,7 @@ static int eigs_run(mglma_ctx* c, int level, const mglma_eig_params* p, const do
         stats->max_res = maxres;
         stats->spectrum_bound = bnd;
         stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        stats->lambda_max_abs = lmax;
     }
     cleanup();
     return nconv < nev ? MGLMA_ERR_NOT_CONVERGED : MGLMA_OK;
@@ -376,12 +414,111 @@ static int eigs_run(mglma_ctx* c, int level, const mglma_eig_params* p, const do
 
 extern "C" int mglma_coarse_eigs(mglma_ctx* c, const mglma_eig_params* p, const double* init, double* evals,
                                  double* evecs, mglma_eig_stats* stats) {
-    return eigs_run(c, 1, p, init, evals, evecs, stats);
+    return eigs_run(c, MGLMA_OP_COARSE, p, init, evals, evecs, stats);
 }
 
 extern "C" int mglma_fine_eigs(mglma_ctx* c, const mglma_eig_params* p, const double* init, double* evals,
                                double* evecs, mglma_eig_stats* stats) {
-    return eigs_run(c, 0, p, init, evals, evecs, stats);
+    return eigs_run(c, MGLMA_OP_FINE, p, init, evals, evecs, stats);
+}
+
+extern "C" int mglma_level_eigs(mglma_ctx* c, int op, const mglma_eig_params* p, const double* init, double* evals,
+                                double* evecs, mglma_eig_stats* stats) {
+    return eigs_run(c, op, p, init, evals, evecs, stats);
+}
+
+// ---------------------------------------------------------------------------
+// The coarse operator of the block basis without chiral split (appendix on
+// the spectra of coarse and fine operators: coarsening with a trivial coarse
+// spin).  Per block the Nv vectors theta_B v_c, orthonormalised in order c,
+// span a subspace of the chiral block basis: theta_B v_c = Phi_y X_y[:, c]
+// with X_y = Phi_y^+ theta_B v_c, the restriction of v_c.  Hence
+// T_nc = T S with S_y = the orthonormalised X_y, and
+//   Q_nc = T_nc^+ Q T_nc = S^+ (gamma5)_1 D_1 S,
+// a nine-point stencil of Nv x Nv blocks S_y^+ (gamma5)_1 D_1(y, dir) S_z.
+// ---------------------------------------------------------------------------
+// Xo[y][c][i] = X[c][y][i]  ([Nv][V1][nc] -> [V1][Nv][nc])
+__global__ void k_nc_transpose(int Nv, int V1, int nc, const double2* __restrict__ X, double2* __restrict__ Xo) {
+    const size_t tot = (size_t)Nv * V1 * nc;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e % nc);
+        const size_t t = e / nc;
+        const int c = (int)(t % Nv), y = (int)(t / Nv);
+        Xo[e] = X[((size_t)c * V1 + y) * nc + i];
+    }
+}
+
+// one workgroup per (y, dir): tmp = D_1(y, dir) S_z (nc x Nv, LDS), then
+// out[c][c'] = sum_i conj(S_y[i][c]) g5_i tmp[i][c']
+__global__ __launch_bounds__(256) void k_nc_op(Geo g, int Nv, const double2* __restrict__ D,
+                                               const double2* __restrict__ S, double2* __restrict__ out) {
+    extern __shared__ double2 tmp[];
+    const int y = blockIdx.x / 9, dir = blockIdx.x - 9 * y;
+    const int z = coarse_nbr(g, y, dir), nc = 2 * Nv;
+    const double2* Dd = D + ((size_t)y * 9 + dir) * nc * nc;
+    const double2* Sz = S + (size_t)z * Nv * nc;
+    const double2* Sy = S + (size_t)y * Nv * nc;
+    for (int e = threadIdx.x; e < nc * Nv; e += blockDim.x) {
+        const int i = e / Nv, cp = e - i * Nv;
+        cx<double> acc = cmk(0.0, 0.0);
+        for (int j = 0; j < nc; ++j) cmac(acc, ldc<double2, double>(Dd + (size_t)i * nc + j),
+                                         ldc<double2, double>(Sz + (size_t)cp * nc + j));
+        tmp[e] = make_double2(acc.re, acc.im);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < Nv * Nv; e += blockDim.x) {
+        const int cc = e / Nv, cp = e - cc * Nv;
+        cx<double> acc = cmk(0.0, 0.0);
+        for (int i = 0; i < nc; ++i) {
+            const double2 t = tmp[i * Nv + cp];
+            const double sg = i < Nv ? 1.0 : -1.0;
+            cjmac(acc, ldc<double2, double>(Sy + (size_t)cc * nc + i), cmk(sg * t.x, sg * t.y));
+        }
+        out[(((size_t)y * 9 + dir) * Nv + cc) * Nv + cp] = make_double2(acc.re, acc.im);
+    }
+}
+
+extern "C" int mglma_build_nonchiral(mglma_ctx* c, const double* tv) {
+    if (!c || !tv) return MGLMA_ERR_ARG;
+    if (!c->have_subspace) return MGLMA_ERR_NO_SUBSPACE;
+    const Geo& g = c->geo;
+    const int Nv = c->Nv, nc = c->nc;
+    if (Nv > 32) return MGLMA_ERR_ARG;
+    mg_free(c, c->NC64, 0);
+    c->NC64 = nullptr;
+    const size_t ncs = (size_t)g.V1 * nc;
+    double2 *X = nullptr, *Xo = nullptr;
+    int rc = mg_malloc(c, (void**)&X, (size_t)Nv * ncs * sizeof(double2));
+    if (rc == MGLMA_OK) rc = mg_malloc(c, (void**)&Xo, (size_t)Nv * ncs * sizeof(double2));
+    if (rc == MGLMA_OK) rc = mg_restrict(c, MGLMA_F64, tv, X, Nv);
+    if (rc == MGLMA_OK) {
+        hipLaunchKernelGGL(k_nc_transpose, dim3(2048), dim3(256), 0, c->stream, Nv, g.V1, nc, (const double2*)X, Xo);
+        if (hipGetLastError() != hipSuccess) rc = MGLMA_ERR_HIP;
+    }
+    if (rc == MGLMA_OK) rc = mg_cholqr_sets(c, Xo, g.V1, Nv, nc);
+    if (rc == MGLMA_OK) rc = mg_malloc(c, (void**)&c->NC64, (size_t)g.V1 * 9 * Nv * Nv * sizeof(double2));
+    if (rc == MGLMA_OK) {
+        hipLaunchKernelGGL(k_nc_op, dim3(g.V1 * 9), dim3(256), (size_t)nc * Nv * sizeof(double2), c->stream, g, Nv,
+                           (const double2*)c->D64, (const double2*)Xo, c->NC64);
+        if (hipGetLastError() != hipSuccess) rc = MGLMA_ERR_HIP;
+    }
+    if (hipStreamSynchronize(c->stream) != hipSuccess && rc == MGLMA_OK) rc = MGLMA_ERR_HIP;
+    if (X) mg_free(c, X, 0);
+    if (Xo) mg_free(c, Xo, 0);
+    if (rc != MGLMA_OK) {
+        mg_free(c, c->NC64, 0);
+        c->NC64 = nullptr;
+    }
+    return rc;
+}
+
+extern "C" int mglma_export_nonchiral_op(mglma_ctx* c, double* out) {
+    if (!c || !out) return MGLMA_ERR_ARG;
+    if (!c->NC64) return MGLMA_ERR_NO_SUBSPACE;
+    HIP_TRY(hipMemcpyAsync(out, c->NC64, (size_t)c->geo.V1 * 9 * c->Nv * c->Nv * sizeof(double2),
+                           hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return MGLMA_OK;
 }
 
 // ---------------------------------------------------------------------------

@@ -118,6 +118,21 @@ __device__ __forceinline__ int geo_bwd(const Geo& g, int i, int mu, const int lc
     return i + d + (g.L1[mu] - 1) * g.sk[mu] * g.Vb;
 }
 
+// stencil neighbour of coarse site y on the block grid g.L1: dir 0 = y itself,
+// 1 + 2 mu = +mu, 2 + 2 mu = -mu (periodic on the block grid)
+__device__ __forceinline__ int coarse_nbr(const Geo& g, int y, int dir) {
+    if (dir == 0) return y;
+    int mu = (dir - 1) >> 1;
+    int sg = (dir & 1) ? 1 : -1;
+    // coordinate of y along mu in the block grid
+    int stride = g.sk[mu];
+    int cmu = (y / stride) % g.L1[mu];
+    int nmu = cmu + sg;
+    if (nmu < 0) nmu += g.L1[mu];
+    if (nmu >= g.L1[mu]) nmu -= g.L1[mu];
+    return y + (nmu - cmu) * stride;
+}
+
 // ---------------------------------------------------------------------------
 // complex arithmetic
 // ---------------------------------------------------------------------------
@@ -277,6 +292,10 @@ struct mglma_ctx {
     float2* eo_SY = nullptr;       // [nc][Vh][nc] S y_a (the BF16 S of the solver)
     double2* eo_Einv = nullptr;    // [nc][nc] (Y^+ S Y)^{-1}
 
+    // diagnostics: the coarse operator of the basis without chiral split
+    // (T_nc^+ Q T_nc, [V1][9][Nv][Nv] complex, Hermitian stencil)
+    double2* NC64 = nullptr;
+
     // level 2 of the nested hierarchy: blocks of b2 fine sites (multiples of b),
     // D_2 = R_1 D_1 T_1 with the aggregating R_1 (same nc, grid g2.L1, V2 = g2.V1)
     bool have_l2 = false;
@@ -367,6 +386,8 @@ void mg_free_subspace(mglma_ctx* c);
 void mg_free_level2(mglma_ctx* c);
 // planar copies of an interleaved operator (any output may be NULL)
 int mg_op_copies(mglma_ctx* c, size_t nblk, int nc, const double2* D, double* D64p, float* D32p, bf16_t* Dbf);
+// two Cholesky-QR passes over nsets sets of Nv vectors of K complex ([nsets][Nv][K], FP64, in place)
+int mg_cholqr_sets(mglma_ctx* c, double2* B, int nsets, int Nv, int K);
 // the FP32 basis / FP32 planar D_1, formed from the FP64 ones when first needed
 int mg_need_b32(mglma_ctx* c);
 int mg_need_d32(mglma_ctx* c);

@@ -667,6 +667,31 @@ static int cholqr_pass(mglma_ctx* c, double2* Gb, double2* Rb, int* bad, bool co
     return MGLMA_OK;
 }
 
+// Cholesky QR, twice, of nsets sets of Nv vectors of K complex each (B
+// [nsets][Nv][K], in place, FP64): each set orthonormalised in order with a
+// positive real diagonal.  Errors: RANK.
+int mg_cholqr_sets(mglma_ctx* c, double2* B, int nsets, int Nv, int K) {
+    const size_t gsz = (size_t)nsets * Nv * Nv * sizeof(double2);
+    double2 *Gb, *Rb;
+    int* bad;
+    MG_TRY(mg_scratch(c, 0, gsz, (void**)&Gb));
+    MG_TRY(mg_scratch(c, 1, gsz, (void**)&Rb));
+    MG_TRY(mg_scratch(c, 7, 64, (void**)&bad));
+    HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int), c->stream));
+    for (int pass = 0; pass < 2; ++pass) {
+        const size_t sh = (size_t)Nv * (GCH + 1) * sizeof(double2);
+        hipLaunchKernelGGL(k_gram, dim3(nsets), dim3(256), sh, c->stream, B, Nv, K, Gb);
+        hipLaunchKernelGGL(k_chol_inv, dim3(nsets), dim3(64), 0, c->stream, Nv, Gb, Rb, 3e-7, bad);
+        hipLaunchKernelGGL(k_apply_rinv, dim3(nsets), dim3(256), (size_t)Nv * Nv * sizeof(double2), c->stream, B, Nv,
+                           K, (const double2*)Rb, (float2*)nullptr, (__half2*)nullptr);
+        HIP_TRY(hipGetLastError());
+    }
+    int hbad = 0;
+    HIP_TRY(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return hbad ? MGLMA_ERR_RANK : MGLMA_OK;
+}
+
 extern "C" int mglma_build_subspace(mglma_ctx* c, int Nv, const double* tv) {
     if (!c || !tv) return MGLMA_ERR_ARG;
     if (!c->have_gauge) return MGLMA_ERR_NO_GAUGE;

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libmglma.so")
 
 F64, F32, F16, BF16 = 0, 1, 2, 3
 SRC_POINT, SRC_STOCH = 0, 1
+OP_FINE, OP_COARSE, OP_LEVEL2, OP_NONCHIRAL = 0, 1, 2, 3
 SMOOTH_MR, SMOOTH_CAGCR, SMOOTH_SAP = 0, 1, 2
 
 SYMBOLS = [
@@ -34,7 +35,8 @@ SYMBOLS = [
     "mglma_level2_apply", "mglma_level2_solve", "mglma_level2_pieces", "mglma_save", "mglma_load",
     "mglma_adaptive_setup", "mglma_sap_smooth", "mglma_sap_timing", "mglma_sap_elapsed",
     "mglma_contract_pair", "mglma_contract_levels", "mglma_contract_levels_noalloc",
-    "mglma_contract_levels_acc", "mglma_release_workspace", "mglma_slots_create", "mglma_slots_destroy", "mglma_slots_load", "mglma_slots_step", "mglma_slots_take",
+    "mglma_contract_levels_acc", "mglma_release_workspace", "mglma_level_eigs", "mglma_build_nonchiral",
+    "mglma_export_nonchiral_op", "mglma_slots_create", "mglma_slots_destroy", "mglma_slots_load", "mglma_slots_step", "mglma_slots_take",
 ]
 
 
@@ -64,7 +66,7 @@ class EigParams(C.Structure):
 
 class EigStats(C.Structure):
     _fields_ = [("iters", C.c_int), ("applies", C.c_int), ("nconv", C.c_int), ("max_res", C.c_double),
-                ("spectrum_bound", C.c_double), ("seconds", C.c_double)]
+                ("spectrum_bound", C.c_double), ("seconds", C.c_double), ("lambda_max_abs", C.c_double)]
 
 
 class MglmaError(RuntimeError):
@@ -335,7 +337,21 @@ class Context:
             _check(rc)
         return rc, ev[:nev], vec[:nev], dict(iters=st.iters, applies=st.applies, nconv=st.nconv,
                                              max_res=st.max_res, spectrum_bound=st.spectrum_bound,
+                                             lambda_max_abs=st.lambda_max_abs,
                                              seconds=st.seconds)
+
+    def level_eigs(self, op, init, nev, tol=1e-12, degree=0, max_iter=0, raise_on_error=True):
+        """Low modes of the Hermitian operator of a level (OP_FINE, OP_COARSE,
+        OP_LEVEL2, OP_NONCHIRAL); init [nblk][...] in that level's layout."""
+        shape = tuple(init.shape[1:])
+        fn = lambda *a: lib().mglma_level_eigs(a[0], int(op), *a[1:])
+        return self._eigs(fn, shape, init, nev, tol, degree, max_iter, raise_on_error)
+
+    def build_nonchiral(self, testvecs):
+        _check(lib().mglma_build_nonchiral(self._ctx, _ptr(testvecs)))
+
+    def export_nonchiral_op(self, out):
+        _check(lib().mglma_export_nonchiral_op(self._ctx, _ptr(out)))
 
     def deficit(self, fine):
         """Local-coherence deficits |(1 - P) psi| / |psi| of nrhs fine fields."""

@@ -68,11 +68,11 @@ def test_eigs_arguments(case):
     with pytest.raises(mglma.MglmaError) as e:          # nev < 1
         _run(pair, 0, 2)
     assert e.value.code == -1
-    with pytest.raises(mglma.MglmaError) as e:          # block larger than 64
-        init = torch.zeros((65, pair.bl.V1, 2 * pair.Nv, 2), dtype=torch.float64, device="cuda")
+    with pytest.raises(mglma.MglmaError) as e:          # block larger than 128
+        init = torch.zeros((129, pair.bl.V1, 2 * pair.Nv, 2), dtype=torch.float64, device="cuda")
         pair.ctx.coarse_eigs(init, 8)
     assert e.value.code == -1
-    if n < 64:
+    if n < 128:
         with pytest.raises(mglma.MglmaError) as e:      # block larger than the coarse space
             _run(pair, n - 2, 4)
         assert e.value.code == -1
@@ -189,3 +189,18 @@ def test_basis_from_exact_low_modes():
         d = np.abs(lam1 - l).min()
         print("fine eigenvalue %.12f: nearest coarse %.2e" % (l, d))
         assert d < 1e-10
+
+
+def test_block_above_64():
+    """nblk = 96 (the 64-vector tiles of the Gram matrices and the chunked
+    block combination): eigenvalues against the oracle's dense spectrum."""
+    pair = Pair((4, 4, 4, 8), (2, 2, 2, 4), 20)
+    nev, ng = 48, 48
+    rc, lam, vec, st = _run(pair, nev, ng, seed=13)
+    A = coarse.coarse_dense(pair.D1, pair.nbr)
+    g5 = np.tile(subspace.coarse_gamma5(pair.Nv), pair.bl.V1)
+    Q = g5[:, None] * A
+    w = np.linalg.eigvalsh(0.5 * (Q + Q.conj().T))
+    ref = w[np.argsort(np.abs(w))[:nev]]
+    print("nblk 96: iters %d, max_res %.2e" % (st["iters"], st["max_res"]))
+    assert rc == 0 and np.abs(np.sort(lam) - np.sort(ref)).max() < 1e-10
