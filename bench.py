@@ -576,6 +576,93 @@ def config4(wl, gb_per_rhs=23.0):
     print(json.dumps(out), flush=True)
 
 
+def spectra_and_conditioning(wl, Nv=16, seed=5100):
+    """Appendices on the spectra of coarse and fine operators and on the
+    condition numbers of coarse-grid operators, on a synthetic ensemble: the
+    2 Nv lowest modes of Q (device eigensolver, residual <= 1e-12), the block
+    basis (4^4 blocks) from the Nv lowest, the lowest eigenvalues of the
+    chirally split Q_1 and of the coarse operator without chiral split; then
+    for the operators of the hierarchy (fine Q; Q_1 on 4^4 blocks; Q_2 on
+    8^4 blocks; the low-mode-averaging operator diag(lambda_1..lambda_Nv))
+    their dimension, condition number |lambda|_max / |lambda|_min and the
+    iteration count of unpreconditioned FP64 GCR(16) on a random right-hand
+    side to 1e-10."""
+    import torch
+    from paper_2412_06347_amd import mglma, synth as synth_mod
+    L = wl["L"]
+    U = torch.from_numpy(synth_mod.gauge_field(L, wl["eps"], wl["seed"]).view(np.float64)).cuda()
+    ctx = mglma.Context(L, wl["block"], wl["kappa"], wl["csw"])
+    ctx.load_gauge(U)
+    nev = 2 * Nv
+    nblk = nev + 16
+    init = ctx.fine(nblk)
+    for k0 in range(0, nblk, 8):
+        k1 = min(nblk, k0 + 8)
+        ctx.import_fields(torch.from_numpy(synth_mod.gaussian_fields(k1 - k0, L, seed + k0).view(np.float64)).cuda(),
+                          init[k0:k1])
+    t0 = time.perf_counter()
+    rc, lam_f, modes, st_f = ctx.level_eigs(mglma.OP_FINE, init, nev, tol=1e-12, degree=64, max_iter=300,
+                                            raise_on_error=False)
+    t_f = time.perf_counter() - t0
+    del init
+    tv = modes[:Nv].contiguous()
+    ctx.build_subspace(tv)
+    V1, nc = ctx.V1, ctx.nc
+
+    def coarse_low(op, n_per_site, nsites, k, sd):
+        init = torch.from_numpy(synth_mod.gaussian_coarse(k + 16, nsites, n_per_site, sd).view(np.float64)).cuda()
+        return ctx.level_eigs(op, init, k, tol=1e-12, max_iter=300, raise_on_error=False)
+
+    rc1, lam_1, _, st_1 = coarse_low(mglma.OP_COARSE, nc, V1, nev, seed + 1)
+    ctx.build_nonchiral(tv)
+    rcn, lam_n, _, st_n = coarse_low(mglma.OP_NONCHIRAL, Nv, V1, nev, seed + 2)
+    ctx.build_level2([2 * b for b in wl["block"]])
+    V2 = ctx.V2
+    rc2, lam_2, _, st_2 = coarse_low(mglma.OP_LEVEL2, nc, V2, 8, seed + 3)
+    # iteration counts of unpreconditioned FP64 GCR(16), random right-hand side, to 1e-10
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed + 4)
+    b = ctx.fine(1)
+    b.normal_(generator=g)
+    x = ctx.fine(1)
+    pf = mglma.default_params(tol=1e-10, max_outer=1, max_inner=20000, gcr_m=16, inner_tol=1e-10, use_mg=0,
+                              inner=mglma.F64, smoother=mglma.F64, coarse=mglma.F64)
+    rcf, sf = ctx.solve(b, x, pf, raise_on_error=False)
+    pc = mglma.default_params(tol=1e-10, max_outer=2000, coarse_iters=16, coarse=mglma.F64, coarse_eo=0)
+    bc = ctx.coarse(1)
+    bc.normal_(generator=g)
+    xc = ctx.coarse(1)
+    s1 = ctx.coarse_solve(bc, xc, pc)
+    b2 = ctx.level2_field(1)
+    b2.normal_(generator=g)
+    x2 = ctx.level2_field(1)
+    s2 = ctx.level2_solve(b2, x2, pc)
+    lma = np.abs(lam_f[:Nv])
+    ops = {
+        "LMA diag(lambda_1..lambda_%d) (one block)" % Nv: dict(dim=Nv, cond=float(lma.max() / lma.min()),
+                                                               gcr16_iterations=None),
+        "Q_2 (8^4 blocks, chiral)": dict(dim=V2 * nc, cond=st_2["lambda_max_abs"] / float(np.abs(lam_2).min()),
+                                         gcr16_iterations=s2[0]["coarse"], res=s2[0]["true_rel_res"]),
+        "Q_1 (4^4 blocks, chiral)": dict(dim=V1 * nc, cond=st_1["lambda_max_abs"] / float(np.abs(lam_1).min()),
+                                         gcr16_iterations=s1[0]["coarse"], res=s1[0]["true_rel_res"]),
+        "Q (fine)": dict(dim=12 * ctx.V, cond=st_f["lambda_max_abs"] / float(np.abs(lam_f).min()),
+                         gcr16_iterations=sf[0]["inner"], res=sf[0]["true_rel_res"]),
+    }
+    rnd = lambda a: [round(float(v), 8) for v in a]
+    print(json.dumps({
+        "diagnostic": "spectra and condition numbers of the operators of the hierarchy (synthetic fields)",
+        "workload": "%dx%d^3, eps=%g, kappa=%g, c_sw=%g; basis from the %d lowest modes of Q" %
+                    (L[0], L[1], wl["eps"], wl["kappa"], wl["csw"], Nv),
+        "fine_eigs": {"rc": rc, "seconds": round(t_f, 1), "iters": st_f["iters"], "max_res": st_f["max_res"]},
+        "lowest_abs_lambda": {"Q": rnd(np.abs(lam_f)), "Q_1 chiral": rnd(np.abs(lam_1)),
+                              "Q_nc (no chiral split)": rnd(np.abs(lam_n))},
+        "chiral_reproduces_lowest_%d" % Nv: float(np.abs(np.sort(np.abs(lam_1))[:Nv] -
+                                                         np.sort(np.abs(lam_f))[:Nv]).max()),
+        "nonchiral_below_Q_min": int(np.sum(np.abs(lam_n) < np.abs(lam_f).min() * (1 - 1e-9))),
+        "operators": ops,
+    }), flush=True)
+
+
 def setup_recipes(wl, reps=2):
     """Test-vector preparation recipes on the bench workload (the basis should
     span approximations of the low modes of Q, sec. "Local coherence and block
@@ -727,6 +814,9 @@ def main():
     ap.add_argument("--serve", action="store_true",
                     help="serving diagnostic instead of the bench: two resident ensembles, a closed burst for the "
                          "capacity, then a Poisson stream at 0.8 of it; solves/s and p50/p99 latency")
+    ap.add_argument("--cond", action="store_true",
+                    help="spectra and condition numbers of the hierarchy's operators instead of the bench "
+                         "(default workload 16c32)")
     ap.add_argument("--c4", action="store_true",
                     help="the 48^3x96 configuration (Nv = 32, Nlm = 64, 48 sources x 4 spins) instead of the bench")
     ap.add_argument("--setup", action="store_true",
@@ -759,6 +849,9 @@ def main():
         return
     if args.c4:
         config4(WORKLOADS["48c96"])
+        return
+    if args.cond:
+        spectra_and_conditioning(WORKLOADS["16c32" if args.workload == "24c48" else args.workload])
         return
     if args.serve:
         serving()

@@ -447,7 +447,8 @@ int  mglma_slots_take(mglma_slots* slots, int n, const int* ids, double* x_dev, 
 
 /* x = D_1^{-1} b on the coarse level (coarse fields, F64) to relative
  * residual p->tol; inner GCR uses the p->coarse operator inside FP64 defect
- * correction.  Synchronising.                                               */
+ * correction (with p->coarse = F64 the inner vectors are FP64 as well;
+ * FP32 inner vectors otherwise).  Synchronising.                          */
 int mglma_coarse_solve(mglma_ctx* ctx, const mglma_solve_params* p, const double* b_dev,
                        double* x_dev, int nrhs, mglma_solve_stats* stats);
 /* Coarse-level propagator pieces for fine sources eta (device layout, F64):

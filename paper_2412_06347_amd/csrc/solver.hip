@@ -254,6 +254,10 @@ static int coarse_kcycle(SolveCtx& S, int vp, int op, const void* b, void* x, in
 
 static int coarse_gcr_fixed(SolveCtx& S, int vp, int op, const void* b, void* x, int iters) {
     mglma_ctx* c = S.c;
+    // the operator's precision follows the vectors': FP64 vectors use the FP64
+    // operator, FP32 vectors never meet it (its apply reads FP64 vectors)
+    if (vp == MGLMA_F64) op = MGLMA_F64;
+    else if (op == MGLMA_F64) op = MGLMA_F32;
     if (S.level == 1 && S.p->kcycle > 0) {
         if (!c->have_l2) return MGLMA_ERR_NO_SUBSPACE;
         return coarse_kcycle(S, vp, op, b, x, iters);
@@ -740,7 +744,8 @@ int mg_coarse_solve(mglma_ctx* c, const mglma_solve_params* p, const double* b, 
     // coarse GCR without restarts for up to 32 steps per defect-correction cycle
     S.s.m = p->coarse_iters < 8 ? 8 : (p->coarse_iters > 32 ? 32 : p->coarse_iters);
     MG_TRY(mg_scratch(c, WS_SCAL, Scal::bytes(nrhs, S.s.m), (void**)&S.s.base));
-    const int vp = p->inner == MGLMA_F64 ? MGLMA_F64 : MGLMA_F32;
+    // an FP64 coarse operator asks for FP64 Krylov vectors
+    const int vp = (p->inner == MGLMA_F64 || p->coarse == MGLMA_F64) ? MGLMA_F64 : MGLMA_F32;
     double2 *r64, *t64;
     void *rin, *e;
     MG_TRY(mg_scratch(c, WS_CR64, setsz * 16, (void**)&r64));
