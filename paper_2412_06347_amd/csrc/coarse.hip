@@ -15,8 +15,9 @@
 #include "mglma_internal.h"
 
 // FP64 / FP32 on the matrix cores (v_mfma_*_16x16x4).
-// grid: (V1, ceil(nrhs/16)); block: 64 * ceil(nc/16) threads, wave w owns
-// output rows 16w..16w+15 and the 16 right-hand sides of blockIdx.y.
+// grid: the (coarse site, 16-rhs tile) items (site_tile); block: 64 *
+// ceil(nc/16) threads, wave w owns output rows 16w..16w+15 and the 16
+// right-hand sides of the item's tile.
 // Operator: planar copy P[y][dir][0 = re, 1 = im][i][j] in precision R.
 // In an MFMA lane (lr, lq) supplies A[row lr][k] and B[k][col lr] for one k
 // of four; over four successive MFMAs the lane walks k = k0 + 4 lq + s,
@@ -33,8 +34,9 @@ __global__ __launch_bounds__(512) void k_coarse_mfma(Geo g, int nc, const R* __r
                                                      typename VT<R>::c2* __restrict__ out, int nrhs, int gamma5) {
     typedef typename VT<R>::c2 C2;
     typedef typename Mfma<R>::v4 V4;
-    const int y = blockIdx.x;
-    const int n0 = blockIdx.y * 16;
+    int y, tile;
+    if (!site_tile(g.V1, (nrhs + 15) / 16, &y, &tile)) return;
+    const int n0 = tile * 16;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int m0 = w * 16;
     const int lr = lane & 15, lq = lane >> 4;
@@ -123,7 +125,7 @@ __device__ __forceinline__ short f2bf(float f) {
     return (short)(u >> 16);
 }
 
-// grid: (V1, ceil(nrhs/16)); block: 64 * ceil(nc/16) * DG threads.  Wave w
+// grid: the (coarse site, 16-rhs tile) items; block: 64 * ceil(nc/16) * DG threads.  Wave w
 // owns row tile w % ntr and the directions dir = w / ntr + DG * k of the nine
 // stencil entries; with DG > 1 the DG partial sums of a row tile are added in
 // LDS in a fixed order.  FULL: nc is a multiple of 16, so every fragment load
@@ -133,8 +135,9 @@ template <bool FULL, int DG>
 __global__ void k_coarse_bf16(Geo g, int nc, const bf16_t* __restrict__ Dbf, const float2* __restrict__ in,
                               float2* __restrict__ out, int nrhs, int gamma5) {
     __shared__ f4_t part[DG > 1 ? 2 * 4 * 64 * (DG - 1) : 1];   // DG > 1 only with <= 4 row tiles
-    const int y = blockIdx.x;
-    const int n0 = blockIdx.y * 16;
+    int y, tile;
+    if (!site_tile(g.V1, (nrhs + 15) / 16, &y, &tile)) return;
+    const int n0 = tile * 16;
     const int ntr = (nc + 15) / 16;
     const int wall = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int w = wall % ntr, dg = wall / ntr;
@@ -234,7 +237,7 @@ int mg_stencil_apply(mglma_ctx* c, const Geo& g, int nc, const double* P64, cons
         // in flight per coarse site
         constexpr int DG = COARSE_DG;
         const int ntr = (nc + 15) / 16;
-        dim3 grid(g.V1, (nrhs + 15) / 16);
+        dim3 grid(site_tile_grid(g.V1, (nrhs + 15) / 16));
         if (ntr <= 4) {
             dim3 block(64 * ntr * DG);
             if (nc % 16 == 0)
@@ -255,7 +258,7 @@ int mg_stencil_apply(mglma_ctx* c, const Geo& g, int nc, const double* P64, cons
         HIP_TRY(hipGetLastError());
         return MGLMA_OK;
     }
-    dim3 grid(g.V1, (nrhs + 15) / 16);
+    dim3 grid(site_tile_grid(g.V1, (nrhs + 15) / 16));
     dim3 block(64 * ((nc + 15) / 16));
     const bool vec = nc % 4 == 0;
     switch (prec) {

@@ -177,14 +177,16 @@ __global__ __launch_bounds__(256) void k_eo_hops(const double2* __restrict__ Din
 // Operator planar [V1][re/im][nc][nc].  VEC: nc % 4 == 0 (four-wide loads).
 template <bool VEC>
 __global__ __launch_bounds__(256) void k_diag_inv_mfma(int nc, int Vh, int V1, const int* __restrict__ site, int p0,
-                                                       const float* __restrict__ Dp, const float2* __restrict__ in,
-                                                       float2* __restrict__ out0, float2* __restrict__ out1,
-                                                       int nrhs) {
+                                                       int nsites, const float* __restrict__ Dp,
+                                                       const float2* __restrict__ in, float2* __restrict__ out0,
+                                                       float2* __restrict__ out1, int nrhs) {
     typedef Mfma<float>::v4 V4;
-    const int g = blockIdx.x + p0 * Vh;
+    int gs, tile;
+    if (!site_tile(nsites, (nrhs + 15) / 16, &gs, &tile)) return;
+    const int g = gs + p0 * Vh;
     const int p = g >= Vh ? 1 : 0, k = g - p * Vh;
     const int y = site[g];
-    const int n0 = blockIdx.y * 16;
+    const int n0 = tile * 16;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int m0 = w * 16, lr = lane & 15, lq = lane >> 4;
     const size_t nn = (size_t)nc * nc;
@@ -267,9 +269,10 @@ __global__ void k_coarse_hop_bf16(int nc, int Vh, const int* __restrict__ site, 
                                   const bf16_t* __restrict__ Hbf, const float2* __restrict__ in, const float2* xs,
                                   float2* out, int nrhs) {
     __shared__ f4_t part[DG > 1 ? 2 * 4 * 64 * (DG - 1) : 1];   // <= 4 row tiles
-    const int k = blockIdx.x;
+    int k, tile;
+    if (!site_tile(Vh, (nrhs + 15) / 16, &k, &tile)) return;
     const int y = site[k];
-    const int n0 = blockIdx.y * 16;
+    const int n0 = tile * 16;
     const int ntr = (nc + 15) / 16;
     const int wall = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int w = wall % ntr, dg = wall / ntr;
@@ -659,7 +662,7 @@ int mg_eo_hop(mglma_ctx* c, int po, const void* in, const void* xs, void* out, i
     const int* site = c->eo_site + (size_t)po * Vh;
     const int* nbr = c->eo_nbr + (size_t)po * Vh * 8;
     constexpr int DG = 4;
-    dim3 grid(Vh, (nrhs + 15) / 16), block(64 * ntr * DG);
+    dim3 grid(site_tile_grid(Vh, (nrhs + 15) / 16)), block(64 * ntr * DG);
     const bool full = nc % 16 == 0;
 #define HOP_LAUNCH(F, S)                                                                                     \
     hipLaunchKernelGGL((k_coarse_hop_bf16<F, DG, S>), grid, block, 0, c->stream, nc, Vh, site, nbr, c->eo_Hbf, \
@@ -682,13 +685,13 @@ int mg_eo_diag_inv(mglma_ctx* c, const void* in_full, void* out_e, void* out_o, 
     const int Vh = c->eo_Vh, nc = c->nc;
     const int p0 = out_e ? 0 : 1;
     const int nsites = (out_e && out_o) ? 2 * Vh : Vh;
-    dim3 grid(nsites, (nrhs + 15) / 16), block(64 * ((nc + 15) / 16));
+    dim3 grid(site_tile_grid(nsites, (nrhs + 15) / 16)), block(64 * ((nc + 15) / 16));
     if (nc % 4 == 0)
         hipLaunchKernelGGL(k_diag_inv_mfma<true>, grid, block, 0, c->stream, nc, Vh, (int)c->geo.V1, c->eo_site, p0,
-                           c->eo_Dinv32, (const float2*)in_full, (float2*)out_e, (float2*)out_o, nrhs);
+                           nsites, c->eo_Dinv32, (const float2*)in_full, (float2*)out_e, (float2*)out_o, nrhs);
     else
         hipLaunchKernelGGL(k_diag_inv_mfma<false>, grid, block, 0, c->stream, nc, Vh, (int)c->geo.V1, c->eo_site, p0,
-                           c->eo_Dinv32, (const float2*)in_full, (float2*)out_e, (float2*)out_o, nrhs);
+                           nsites, c->eo_Dinv32, (const float2*)in_full, (float2*)out_e, (float2*)out_o, nrhs);
     HIP_TRY(hipGetLastError());
     return MGLMA_OK;
 }

@@ -133,6 +133,21 @@ __device__ __forceinline__ int coarse_nbr(const Geo& g, int y, int dir) {
     return y + (nmu - cmu) * stride;
 }
 
+// Flat grid over (site, 16-right-hand-side tile) items, dealt to the eight
+// XCDs in contiguous ranges so that the tiles of one site run back to back
+// on one XCD (its operator blocks are read from HBM once and from that
+// XCD's L2 for the other tiles).  Launch with site_tile_grid blocks; false
+// for the padding workgroups (uniform over the workgroup).
+__device__ __forceinline__ bool site_tile(int nsite, int ntile, int* site, int* tile) {
+    const int bid = blockIdx.x, npad = gridDim.x;
+    const int item = (bid & 7) * (npad >> 3) + (bid >> 3);
+    if (item >= nsite * ntile) return false;
+    *site = item / ntile;
+    *tile = item - *site * ntile;
+    return true;
+}
+static inline unsigned site_tile_grid(long nsite, long ntile) { return (unsigned)((nsite * ntile + 7) / 8 * 8); }
+
 // ---------------------------------------------------------------------------
 // complex arithmetic
 // ---------------------------------------------------------------------------

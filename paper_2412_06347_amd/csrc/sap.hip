@@ -57,16 +57,28 @@ __device__ __forceinline__ void sap_hop(const cx<float> p[12], bool neg, const G
     __builtin_amdgcn_sched_barrier(0);
 }
 
-// hop of the full operator: neighbour read from the global field
+// hop of the full operator for the residual: the neighbour's spinor from the
+// LDS copy of the block's z when it lies inside the block (not across a
+// lattice wrap), else from the global field
 template <int MU, bool FWD, typename G>
-__device__ __forceinline__ void sap_hop_global(const Geo& g, int i, const int lc[4], const int yc[4],
-                                               const float2* __restrict__ f, const G* __restrict__ U,
-                                               cx<float> acc[12]) {
+__device__ __forceinline__ void sap_hop_res(const Geo& g, int i, int l, const int lc[4], const int yc[4],
+                                            const float2* __restrict__ f, const float2* __restrict__ zs,
+                                            const G* __restrict__ U, cx<float> acc[12]) {
     bool wrap;
     const int j = FWD ? geo_fwd(g, i, MU, lc, yc, &wrap) : geo_bwd(g, i, MU, lc, yc, &wrap);
+    const bool inb = FWD ? (lc[MU] + 1 < g.b[MU]) : (lc[MU] > 0);
     cx<float> p[12];
+    if (inb) {
+        const int jl = FWD ? l + g.sl[MU] : l - g.sl[MU];
 #pragma unroll
-    for (int sc = 0; sc < 12; ++sc) p[sc] = ldc<float2, float>(f + (size_t)sc * g.V + j);
+        for (int sc = 0; sc < 12; ++sc) {
+            const float2 v = zs[sc * SAP_MAXVB + jl];
+            p[sc] = cmk(v.x, v.y);
+        }
+    } else {
+#pragma unroll
+        for (int sc = 0; sc < 12; ++sc) p[sc] = ldc<float2, float>(f + (size_t)sc * g.V + j);
+    }
     sap_hop<MU, FWD, G>(p, wrap && g.bcneg[MU], U, g.V, FWD ? i : j, acc);
 }
 
@@ -139,25 +151,35 @@ __global__ __launch_bounds__(256, W) void k_sap_half(Geo g, const float2* __rest
     int lc[4] = {0, 0, 0, 0}, yc[4] = {0, 0, 0, 0};
     if (on) geo_coords(g, i, lc, yc);
 
-    // rho = r - M z on the block's sites
+    // rho = r - M z on the block's sites; the block's z staged in LDS (the
+    // s buffer, free until the block solve), so that the hops inside the
+    // block read LDS and only the hops across the block faces read z globally
+    if (on) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) sh[k * SAP_MAXVB + l] = pz[(size_t)k * V + i];
+    }
+    __syncthreads();
     cx<float> s[12];
     if (on) {
         cx<float> acc[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] = cmk(0.f, 0.f);
-        sap_hop_global<0, true, G>(g, i, lc, yc, pz, U, acc);
-        sap_hop_global<0, false, G>(g, i, lc, yc, pz, U, acc);
-        sap_hop_global<1, true, G>(g, i, lc, yc, pz, U, acc);
-        sap_hop_global<1, false, G>(g, i, lc, yc, pz, U, acc);
-        sap_hop_global<2, true, G>(g, i, lc, yc, pz, U, acc);
-        sap_hop_global<2, false, G>(g, i, lc, yc, pz, U, acc);
-        sap_hop_global<3, true, G>(g, i, lc, yc, pz, U, acc);
-        sap_hop_global<3, false, G>(g, i, lc, yc, pz, U, acc);
+        sap_hop_res<0, true, G>(g, i, l, lc, yc, pz, sh, U, acc);
+        sap_hop_res<0, false, G>(g, i, l, lc, yc, pz, sh, U, acc);
+        sap_hop_res<1, true, G>(g, i, l, lc, yc, pz, sh, U, acc);
+        sap_hop_res<1, false, G>(g, i, l, lc, yc, pz, sh, U, acc);
+        sap_hop_res<2, true, G>(g, i, l, lc, yc, pz, sh, U, acc);
+        sap_hop_res<2, false, G>(g, i, l, lc, yc, pz, sh, U, acc);
+        sap_hop_res<3, true, G>(g, i, l, lc, yc, pz, sh, U, acc);
+        sap_hop_res<3, false, G>(g, i, l, lc, yc, pz, sh, U, acc);
 #pragma unroll
         for (int ch = 0; ch < 2; ++ch) {
             cx<float> p[6], res[6];
 #pragma unroll
-            for (int k = 0; k < 6; ++k) p[k] = ldc<float2, float>(pz + (size_t)(6 * ch + k) * V + i);
+            for (int k = 0; k < 6; ++k) {
+                const float2 v = sh[(6 * ch + k) * SAP_MAXVB + l];
+                p[k] = cmk(v.x, v.y);
+            }
             clover_block<G, float>(C + (size_t)ch * 18 * V, V, i, p, res);
 #pragma unroll
             for (int k = 0; k < 6; ++k)
@@ -167,6 +189,7 @@ __global__ __launch_bounds__(256, W) void k_sap_half(Geo g, const float2* __rest
 #pragma unroll
         for (int k = 0; k < 12; ++k) s[k] = cmk(0.f, 0.f);
     }
+    __syncthreads();   // every read of the staged z before s takes its place
 #pragma unroll
     for (int k = 0; k < 12; ++k) sh[k * SAP_MAXVB + l] = make_float2(s[k].re, s[k].im);
 #pragma unroll
