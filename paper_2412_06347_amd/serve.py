@@ -103,24 +103,39 @@ class Engine:
             self.ctx = ctx
             ctx.load_gauge(self.U)
             Nv, Nlm = wl["Nv"], wl["Nlm"]
-            tv = synth.gaussian_fields(Nv, L, wl["seed"] + 1000)
+            # test vectors: Gaussian fields improved by three rounds of 40
+            # unpreconditioned FP32 GCR steps, in batches that fit the device
             x = ctx.fine(Nv)
-            ctx.import_fields(torch.from_numpy(tv.view(np.float64)).cuda(), x)
-            y = ctx.fine(Nv)
-            p = mglma.default_params(use_mg=0, inner=mglma.F32, max_outer=1, max_inner=40, gcr_m=16, tol=1e-30,
-                                     inner_tol=1e-30)
+            for k0 in range(0, Nv, 8):
+                k1 = min(Nv, k0 + 8)
+                tv = synth.gaussian_fields(k1 - k0, L, wl["seed"] + 1000 + k0)
+                ctx.import_fields(torch.from_numpy(tv.view(np.float64)).cuda(), x[k0:k1])
+                del tv
+            nb = int(wl.get("tv_batch", Nv))
+            y = ctx.fine(nb)
+            p = mglma.default_params(use_mg=0, inner=mglma.F32, max_outer=1, max_inner=40, gcr_m=16 if nb == Nv else 8,
+                                     tol=1e-30, inner_tol=1e-30)
             for _ in range(3):
-                ctx.solve(x, y, p, raise_on_error=False)
-                nrm = torch.linalg.vector_norm(y.reshape(Nv, -1), dim=1)
-                x = (y / nrm[:, None, None, None]).contiguous()
+                for k0 in range(0, Nv, nb):
+                    k1 = min(Nv, k0 + nb)
+                    ctx.solve(x[k0:k1], y[:k1 - k0], p, raise_on_error=False)
+                    nrm = torch.linalg.vector_norm(y[:k1 - k0].reshape(k1 - k0, -1), dim=1)
+                    x[k0:k1] = y[:k1 - k0] / nrm[:, None, None, None]
             del y
+            ctx.release_workspace()
             ctx.build_subspace(x)
             del x
             # top level: the Nlm lowest eigenvectors of Q_1 (device eigensolver)
-            init = torch.from_numpy(synth.gaussian_coarse(2 * Nlm, ctx.V1, ctx.nc, wl["seed"] + 4242).view(np.float64))
-            rc, lam, m, st = ctx.coarse_eigs(init.cuda(), Nlm, tol=1e-12)
+            init = torch.from_numpy(synth.gaussian_coarse(min(2 * Nlm, Nlm + 32), ctx.V1, ctx.nc,
+                                                          wl["seed"] + 4242).view(np.float64))
+            rc, lam, m, st = ctx.coarse_eigs(init.cuda(), Nlm, tol=1e-12, max_iter=int(wl.get("eig_iter", 100)),
+                                             raise_on_error=False)
             ctx.set_top_modes(m.contiguous())
+            del m, init
             self.G_top = ctx.contract_top()
+            # the setup's workspaces (batched GCR, eigensolver) are not needed
+            # by the requests: give them back before the ensemble is admitted
+            ctx.release_workspace()
         self.stream.synchronize()
         # SAP smoothing (FGCR(6), 2 cycles of 4 block steps) where the block
         # grid allows it (every extent even or one), CA-GCR(6) otherwise
