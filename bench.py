@@ -143,7 +143,7 @@ def measured_traffic(workload):
         return None
     rec = json.load(open(path))
     csrc = os.path.join(here, "paper_2412_06347_amd", "csrc")
-    src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("dslash.hip", "wilson.h"))
+    src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("dslash.hip", "wilson.h", "wilson_h.h"))
     if hashlib.sha256(src).hexdigest() != rec.get("dslash_source_sha256"):
         return None
     return rec.get("f16_12rhs_hbm_bytes_per_launch")
@@ -185,7 +185,7 @@ def measured_sap_traffic(workload):
         return None
     rec = json.load(open(path))
     csrc = os.path.join(here, "paper_2412_06347_amd", "csrc")
-    src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("sap.hip", "wilson.h"))
+    src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("sap.hip", "wilson.h", "wilson_h.h"))
     if hashlib.sha256(src).hexdigest() != rec.get("sap_source_sha256"):
         return None
     return rec.get("hbm_bytes_per_launch")

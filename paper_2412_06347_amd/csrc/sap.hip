@@ -9,15 +9,21 @@
 // whole extent) and adds d to z.
 //
 // One workgroup per (block, right-hand side), one thread per block site.
-// The block's minimal-residual vectors s and d live in LDS (12 complex FP32
-// per site each); links and clover come from the FP16 or FP32 copies
+// The block's z is staged in LDS for the residual (hops inside the block
+// read LDS) and then accumulates z + d there, written back once at the end;
+// the minimal-residual vector s lives in LDS for the block operator's
+// neighbour reads (FP32, or FP16 with FP16 links, where the block steps
+// compute on packed FP16 data with FP32 sums) and in FP32 registers for the
+// site's own arithmetic.  Links and clover come from the FP16 or FP32 copies
 // (L2-resident while the right-hand sides of a block run back to back),
 // vectors are FP32.  Blocks of one colour do not couple when every
 // block-grid extent is even or one, so one launch per colour updates them
 // all without ordering between workgroups.
 #include "mglma_internal.h"
 #include "wilson.h"
+#include "wilson_h.h"
 
+#include <type_traits>
 #include <vector>
 
 namespace {
@@ -110,6 +116,54 @@ __device__ __forceinline__ void sap_hop_block(const Geo& g, int blk, int l, cons
     sap_hop<MU, FWD, G>(p, neg, U, g.V, FWD ? blk * g.Vb + l : blk * g.Vb + jl, acc);
 }
 
+// the same hop of M_BB on packed FP16 data (FP16 links): the neighbour's
+// spinor from the FP16 copy of s in LDS, the link products as v_dot2_f32_f16
+// with FP32 sums
+template <int MU, bool FWD>
+__device__ __forceinline__ void sap_hop_block_h(const Geo& g, int blk, int l, const int lc[4],
+                                                const h2* __restrict__ sh, const h2* __restrict__ U,
+                                                cx<float> acc[12]) {
+    int jl;
+    bool neg = false;
+    if (FWD) {
+        if (lc[MU] + 1 < g.b[MU]) jl = l + g.sl[MU];
+        else if (g.L1[MU] == 1) { jl = l - (g.b[MU] - 1) * g.sl[MU]; neg = g.bcneg[MU] != 0; }
+        else return;
+    } else {
+        if (lc[MU] > 0) jl = l - g.sl[MU];
+        else if (g.L1[MU] == 1) { jl = l + (g.b[MU] - 1) * g.sl[MU]; neg = g.bcneg[MU] != 0; }
+        else return;
+    }
+    h2 p[12];
+#pragma unroll
+    for (int sc = 0; sc < 12; ++sc) p[sc] = sh[sc * SAP_MAXVB + jl];
+    const h2* ul = U + (size_t)(MU * 9) * g.V + (FWD ? blk * g.Vb + l : blk * g.Vb + jl);
+    h2 u[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) u[e] = ul[(size_t)e * g.V];
+    h2 hre[6], him[6];
+    proj_h<MU, FWD, FWD ? FN : FZ>(p, hre);
+    proj_h<MU, FWD, FWD ? FS : FSN>(p, him);
+    cx<float> o[6];
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            float re = 0.f, im = 0.f;
+#pragma unroll
+            for (int c2 = 0; c2 < 3; ++c2) {
+                const h2 uu = FWD ? u[a * 3 + c2] : u[c2 * 3 + a];
+                re = dot2(uu, hre[sp * 3 + c2], re);
+                im = dot2(uu, him[sp * 3 + c2], im);
+            }
+            o[sp * 3 + a] = cmk(re, im);
+        }
+    recon_h<MU, FWD>(acc, o, neg ? -1.f : 1.f);
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+__device__ __forceinline__ h2 to_h2(cx<float> v) { return h2{(_Float16)v.re, (_Float16)v.im}; }
+
 // sum of three values over the workgroup (every thread gets the totals)
 __device__ __forceinline__ void sap_reduce3(float& a, float& b, float& c, float* red) {
 #pragma unroll
@@ -151,12 +205,15 @@ __global__ __launch_bounds__(256, W) void k_sap_half(Geo g, const float2* __rest
     int lc[4] = {0, 0, 0, 0}, yc[4] = {0, 0, 0, 0};
     if (on) geo_coords(g, i, lc, yc);
 
-    // rho = r - M z on the block's sites; the block's z staged in LDS (the
-    // s buffer, free until the block solve), so that the hops inside the
-    // block read LDS and only the hops across the block faces read z globally
+    // rho = r - M z on the block's sites; the block's z staged in LDS (in the
+    // buffer that then accumulates z + d), so that the hops inside the block
+    // read LDS and only the hops across the block faces read z globally
     if (on) {
 #pragma unroll
-        for (int k = 0; k < 12; ++k) sh[k * SAP_MAXVB + l] = pz[(size_t)k * V + i];
+        for (int k = 0; k < 12; ++k) dsh[k * SAP_MAXVB + l] = pz[(size_t)k * V + i];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) dsh[k * SAP_MAXVB + l] = make_float2(0.f, 0.f);
     }
     __syncthreads();
     cx<float> s[12];
@@ -164,20 +221,20 @@ __global__ __launch_bounds__(256, W) void k_sap_half(Geo g, const float2* __rest
         cx<float> acc[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] = cmk(0.f, 0.f);
-        sap_hop_res<0, true, G>(g, i, l, lc, yc, pz, sh, U, acc);
-        sap_hop_res<0, false, G>(g, i, l, lc, yc, pz, sh, U, acc);
-        sap_hop_res<1, true, G>(g, i, l, lc, yc, pz, sh, U, acc);
-        sap_hop_res<1, false, G>(g, i, l, lc, yc, pz, sh, U, acc);
-        sap_hop_res<2, true, G>(g, i, l, lc, yc, pz, sh, U, acc);
-        sap_hop_res<2, false, G>(g, i, l, lc, yc, pz, sh, U, acc);
-        sap_hop_res<3, true, G>(g, i, l, lc, yc, pz, sh, U, acc);
-        sap_hop_res<3, false, G>(g, i, l, lc, yc, pz, sh, U, acc);
+        sap_hop_res<0, true, G>(g, i, l, lc, yc, pz, dsh, U, acc);
+        sap_hop_res<0, false, G>(g, i, l, lc, yc, pz, dsh, U, acc);
+        sap_hop_res<1, true, G>(g, i, l, lc, yc, pz, dsh, U, acc);
+        sap_hop_res<1, false, G>(g, i, l, lc, yc, pz, dsh, U, acc);
+        sap_hop_res<2, true, G>(g, i, l, lc, yc, pz, dsh, U, acc);
+        sap_hop_res<2, false, G>(g, i, l, lc, yc, pz, dsh, U, acc);
+        sap_hop_res<3, true, G>(g, i, l, lc, yc, pz, dsh, U, acc);
+        sap_hop_res<3, false, G>(g, i, l, lc, yc, pz, dsh, U, acc);
 #pragma unroll
         for (int ch = 0; ch < 2; ++ch) {
             cx<float> p[6], res[6];
 #pragma unroll
             for (int k = 0; k < 6; ++k) {
-                const float2 v = sh[(6 * ch + k) * SAP_MAXVB + l];
+                const float2 v = dsh[(6 * ch + k) * SAP_MAXVB + l];
                 p[k] = cmk(v.x, v.y);
             }
             clover_block<G, float>(C + (size_t)ch * 18 * V, V, i, p, res);
@@ -189,11 +246,36 @@ __global__ __launch_bounds__(256, W) void k_sap_half(Geo g, const float2* __rest
 #pragma unroll
         for (int k = 0; k < 12; ++k) s[k] = cmk(0.f, 0.f);
     }
-    __syncthreads();   // every read of the staged z before s takes its place
+    // FP16 links: the block steps compute on packed FP16 data, the block's s
+    // kept in LDS as FP16 (the first half of the staging buffer) for the
+    // neighbours' hops and in FP32 registers for the site's own arithmetic.
+    // The FP16 copy holds s / sigma, sigma the root mean square entry of s
+    // over the block (tracked through the steps by |s'|^2 = |s|^2 -
+    // |<t,s>|^2 / |t|^2), so that the block's values sit in FP16's normal
+    // range whatever the scale of the right-hand side (solutions of point
+    // sources fall off by orders of magnitude across the lattice); t = sigma
+    // M_BB (s / sigma).
+    constexpr bool PK = std::is_same<G, __half2>::value;
+    h2* sh16 = reinterpret_cast<h2*>(sh);
+    float ss = 0.f, sig = 1.f, isig = 1.f;
+    const float nent = 12.f * (float)g.Vb;
+    if (PK) {
+        float d1 = 0.f, d2 = 0.f;
 #pragma unroll
-    for (int k = 0; k < 12; ++k) sh[k * SAP_MAXVB + l] = make_float2(s[k].re, s[k].im);
+        for (int k = 0; k < 12; ++k) ss += s[k].re * s[k].re + s[k].im * s[k].im;
+        sap_reduce3(ss, d1, d2, red);
+        if (ss > 0.f && isfinite(ss)) {
+            sig = sqrtf(ss / nent);
+            isig = 1.f / sig;
+        }
+    }
+    // (the residual read only the staged z and global memory: s can take its
+    // place at once; the first block step's barrier orders these writes)
 #pragma unroll
-    for (int k = 0; k < 12; ++k) dsh[k * SAP_MAXVB + l] = make_float2(0.f, 0.f);
+    for (int k = 0; k < 12; ++k) {
+        if (PK) sh16[k * SAP_MAXVB + l] = to_h2(isig * s[k]);
+        else sh[k * SAP_MAXVB + l] = make_float2(s[k].re, s[k].im);
+    }
 
     // minimal-residual steps on M_BB d = rho_B: t = M_BB s, omega = <t,s>/<t,t>
     for (int it = 0; it < nmr; ++it) {
@@ -208,7 +290,32 @@ __global__ __launch_bounds__(256, W) void k_sap_half(Geo g, const float2* __rest
         cx<float> t[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) t[k] = cmk(0.f, 0.f);
-        if (on) {
+        if (on && PK) {
+            const h2* U16 = reinterpret_cast<const h2*>(Ui);
+            const h2* C16 = reinterpret_cast<const h2*>(Ci);
+            sap_hop_block_h<0, true>(g, blk, l, lc, sh16, U16, t);
+            sap_hop_block_h<0, false>(g, blk, l, lc, sh16, U16, t);
+            sap_hop_block_h<1, true>(g, blk, l, lc, sh16, U16, t);
+            sap_hop_block_h<1, false>(g, blk, l, lc, sh16, U16, t);
+            sap_hop_block_h<2, true>(g, blk, l, lc, sh16, U16, t);
+            sap_hop_block_h<2, false>(g, blk, l, lc, sh16, U16, t);
+            sap_hop_block_h<3, true>(g, blk, l, lc, sh16, U16, t);
+            sap_hop_block_h<3, false>(g, blk, l, lc, sh16, U16, t);
+#pragma unroll
+            for (int ch = 0; ch < 2; ++ch) {
+                h2 p[1][6];
+                cx<float> res[1][6];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    p[0][k] = to_h2(isig * s[6 * ch + k]);
+                    res[0][k] = -kappa * t[6 * ch + k];
+                }
+                const h2* cb = C16 + (size_t)ch * 18 * V + i;
+                clover_dot2<1>([&](int k) { return cb[(size_t)k * V]; }, p, res);
+#pragma unroll
+                for (int k = 0; k < 6; ++k) t[6 * ch + k] = sig * res[0][k];
+            }
+        } else if (on) {
             sap_hop_block<0, true, G>(g, blk, l, lc, sh, Ui, t);
             sap_hop_block<0, false, G>(g, blk, l, lc, sh, Ui, t);
             sap_hop_block<1, true, G>(g, blk, l, lc, sh, Ui, t);
@@ -234,24 +341,31 @@ __global__ __launch_bounds__(256, W) void k_sap_half(Geo g, const float2* __rest
         }
         sap_reduce3(are, aim, tt, red);   // also orders this step's LDS reads before the writes below
         const cx<float> om = tt > 0.f ? cmk(are / tt, aim / tt) : cmk(0.f, 0.f);
+        if (PK && tt > 0.f) {
+            // |s - om t|^2 = |s|^2 - |<t,s>|^2 / |t|^2 (kept above a tiny
+            // fraction of the previous value against cancellation)
+            const float sn = ss - (are * are + aim * aim) / tt;
+            ss = fmaxf(sn, 1e-12f * ss);
+            if (ss > 0.f && isfinite(ss)) {
+                sig = sqrtf(ss / nent);
+                isig = 1.f / sig;
+            }
+        }
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-            const float2 dv = dsh[k * SAP_MAXVB + l];
-            cx<float> dk = cmk(dv.x, dv.y);
-            cmac(dk, om, s[k]);
-            dsh[k * SAP_MAXVB + l] = make_float2(dk.re, dk.im);
+            const float2 zv = dsh[k * SAP_MAXVB + l];
+            cx<float> zk = cmk(zv.x, zv.y);
+            cmac(zk, om, s[k]);
+            dsh[k * SAP_MAXVB + l] = make_float2(zk.re, zk.im);
             s[k] = s[k] - om * t[k];
-            sh[k * SAP_MAXVB + l] = make_float2(s[k].re, s[k].im);
+            if (PK) sh16[k * SAP_MAXVB + l] = to_h2(isig * s[k]);
+            else sh[k * SAP_MAXVB + l] = make_float2(s[k].re, s[k].im);
         }
     }
     __syncthreads();   // every residual read of z (own block included) before the update
     if (on) {
 #pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            float2* a = pz + (size_t)k * V + i;
-            const float2 v = *a, dv = dsh[k * SAP_MAXVB + l];
-            *a = make_float2(v.x + dv.x, v.y + dv.y);
-        }
+        for (int k = 0; k < 12; ++k) pz[(size_t)k * V + i] = dsh[k * SAP_MAXVB + l];
     }
 }
 

@@ -47,6 +47,31 @@ def test_sap_cycles_parity(pair, prec, tol):
     assert e < tol
 
 
+@pytest.mark.parametrize("scale", [1e-7, 1e3])
+def test_sap_cycles_parity_scaled(pair, scale):
+    """FP16 links at right-hand sides far from unit scale (entries around
+    1e-7 lie below FP16's normal range): the FP16 block vectors are scaled
+    per block, so the relative error stays that of unit-scale inputs."""
+    from paper_2412_06347_amd import mglma
+    nrhs, ncycle, nmr = 2, 2, 4
+    r = scale * synth.gaussian_fields(nrhs, pair.L, 61)
+    z0 = 0.1 * scale * synth.gaussian_fields(nrhs, pair.L, 62)
+    rd, zd = pair.fine_dev(r, mglma.F32), pair.fine_dev(z0, mglma.F32)
+    pair.ctx.sap_smooth(rd, zd, ncycle=ncycle, nmr=nmr, prec=mglma.F16)
+    got = pair.fine_host(zd, mglma.F32)
+    bl = subspace.Blocking(pair.L, pair.b)
+    ref = []
+    for q in range(nrhs):
+        z = pair.lat(z0)[q]
+        for _ in range(ncycle):
+            z = sap.sap_cycle(pair.D, bl, pair.lat(r)[q], z, nmr)
+        ref.append(z)
+    ref = pair.canon(np.stack(ref))
+    e = relerr(got, ref)
+    print("SAP FP16, inputs scaled by %g: rel. error %.2e" % (scale, e))
+    assert e < 5e-3
+
+
 def test_sap_smoothed_solve(pair):
     from paper_2412_06347_amd import mglma
     b = synth.gaussian_fields(2, pair.L, 53)
