@@ -164,19 +164,39 @@ __device__ __forceinline__ void sap_hop_block_h(const Geo& g, int blk, int l, co
 
 __device__ __forceinline__ h2 to_h2(cx<float> v) { return h2{(_Float16)v.re, (_Float16)v.im}; }
 
-// sum of three values over the workgroup (every thread gets the totals)
-__device__ __forceinline__ void sap_reduce3(float& a, float& b, float& c, float* red) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        a += __shfl_xor(a, o, 64);
-        b += __shfl_xor(b, o, 64);
-        c += __shfl_xor(c, o, 64);
+// scale of the FP16 copy of a block vector: sigma = the root mean square
+// entry (|s|^2 / nent)^(1/2), formed as |s| / nent^(1/2) so that nothing
+// underflows, when |s|^2 is a normal FP32 number in [1e-36, 1e36]; else
+// sigma = 1 (a block with entries this small drops out of FP16 and is left
+// as it is; NaN and infinity also take this branch)
+__device__ __forceinline__ void sap_sigma(float ss, float rnent, float& sig, float& isig) {
+    if (ss >= 1e-36f && ss <= 1e36f) {
+        sig = sqrtf(ss) * rnent;
+        isig = 1.f / sig;
+    } else {
+        sig = 1.f;
+        isig = 1.f;
     }
+}
+
+// sum of N values over the workgroup (every thread gets the totals)
+template <int N>
+__device__ __forceinline__ void sap_reduce(float (&v)[N], float* red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int n = 0; n < N; ++n) v[n] += __shfl_xor(v[n], o, 64);
     const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    if ((threadIdx.x & 63) == 0) { red[3 * w] = a; red[3 * w + 1] = b; red[3 * w + 2] = c; }
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int n = 0; n < N; ++n) red[N * w + n] = v[n];
+    }
     __syncthreads();
-    a = b = c = 0.f;
-    for (int k = 0; k < nw; ++k) { a += red[3 * k]; b += red[3 * k + 1]; c += red[3 * k + 2]; }
+#pragma unroll
+    for (int n = 0; n < N; ++n) v[n] = 0.f;
+    for (int k = 0; k < nw; ++k)
+#pragma unroll
+        for (int n = 0; n < N; ++n) v[n] += red[N * k + n];
 }
 
 // W: waves per SIMD the register allocation is held to (LDS allows three
@@ -187,7 +207,7 @@ __global__ __launch_bounds__(256, W) void k_sap_half(Geo g, const float2* __rest
                                                   const int* __restrict__ blist, int nblk, int nrhs, int npad,
                                                   int nmr) {
     __shared__ float2 sh[12 * SAP_MAXVB];
-    __shared__ float red[3 * (SAP_MAXVB / 64)];
+    __shared__ float red[4 * (SAP_MAXVB / 64)];
     __shared__ float2 dsh[12 * SAP_MAXVB];
     // (block, rhs) items dealt to the XCDs in contiguous ranges, the right-hand
     // sides of one block back to back on one XCD (its links read once)
@@ -249,25 +269,25 @@ __global__ __launch_bounds__(256, W) void k_sap_half(Geo g, const float2* __rest
     // FP16 links: the block steps compute on packed FP16 data, the block's s
     // kept in LDS as FP16 (the first half of the staging buffer) for the
     // neighbours' hops and in FP32 registers for the site's own arithmetic.
-    // The FP16 copy holds s / sigma, sigma the root mean square entry of s
-    // over the block (tracked through the steps by |s'|^2 = |s|^2 -
-    // |<t,s>|^2 / |t|^2), so that the block's values sit in FP16's normal
-    // range whatever the scale of the right-hand side (solutions of point
-    // sources fall off by orders of magnitude across the lattice); t = sigma
-    // M_BB (s / sigma).
+    // The FP16 copy holds s / sigma, sigma the root mean square entry over
+    // the block of the previous step's s (of rho_B for the first step), so
+    // that the block's values sit in FP16's normal range whatever the scale
+    // of the right-hand side (solutions of point sources fall off by orders
+    // of magnitude across the lattice) and never overflow it (a
+    // minimal-residual step does not increase |s|); t = sigma M_BB (s /
+    // sigma).  |s|^2 is summed afresh in every step's reduction: tracking it
+    // by |s'|^2 = |s|^2 - |<t,s>|^2 / |t|^2 cancels when a step removes
+    // nearly all of a block's residual, and the scale then overflowed FP16.
     constexpr bool PK = std::is_same<G, __half2>::value;
     h2* sh16 = reinterpret_cast<h2*>(sh);
-    float ss = 0.f, sig = 1.f, isig = 1.f;
-    const float nent = 12.f * (float)g.Vb;
+    float sig = 1.f, isig = 1.f;
+    const float rnent = 1.f / sqrtf(12.f * (float)g.Vb);
     if (PK) {
-        float d1 = 0.f, d2 = 0.f;
+        float v[1] = {0.f};
 #pragma unroll
-        for (int k = 0; k < 12; ++k) ss += s[k].re * s[k].re + s[k].im * s[k].im;
-        sap_reduce3(ss, d1, d2, red);
-        if (ss > 0.f && isfinite(ss)) {
-            sig = sqrtf(ss / nent);
-            isig = 1.f / sig;
-        }
+        for (int k = 0; k < 12; ++k) v[0] += s[k].re * s[k].re + s[k].im * s[k].im;
+        sap_reduce<1>(v, red);
+        sap_sigma(v[0], rnent, sig, isig);
     }
     // (the residual read only the staged z and global memory: s can take its
     // place at once; the first block step's barrier orders these writes)
@@ -332,25 +352,28 @@ __global__ __launch_bounds__(256, W) void k_sap_half(Geo g, const float2* __rest
                 for (int k = 0; k < 6; ++k) t[6 * ch + k] = res[k] - kappa * t[6 * ch + k];
             }
         }
-        float are = 0.f, aim = 0.f, tt = 0.f;
+        // <t,s>, <t,t> and (FP16 links) |s|^2; the reduction also orders this
+        // step's LDS reads before the writes below
+        float v[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-            are += t[k].re * s[k].re + t[k].im * s[k].im;
-            aim += t[k].re * s[k].im - t[k].im * s[k].re;
-            tt += t[k].re * t[k].re + t[k].im * t[k].im;
+            v[0] += t[k].re * s[k].re + t[k].im * s[k].im;
+            v[1] += t[k].re * s[k].im - t[k].im * s[k].re;
+            v[2] += t[k].re * t[k].re + t[k].im * t[k].im;
+            if (PK) v[3] += s[k].re * s[k].re + s[k].im * s[k].im;
         }
-        sap_reduce3(are, aim, tt, red);   // also orders this step's LDS reads before the writes below
+        if (PK) {
+            sap_reduce<4>(v, red);
+        } else {
+            float w[3] = {v[0], v[1], v[2]};
+            sap_reduce<3>(w, red);
+            v[0] = w[0];
+            v[1] = w[1];
+            v[2] = w[2];
+        }
+        const float are = v[0], aim = v[1], tt = v[2];
         const cx<float> om = tt > 0.f ? cmk(are / tt, aim / tt) : cmk(0.f, 0.f);
-        if (PK && tt > 0.f) {
-            // |s - om t|^2 = |s|^2 - |<t,s>|^2 / |t|^2 (kept above a tiny
-            // fraction of the previous value against cancellation)
-            const float sn = ss - (are * are + aim * aim) / tt;
-            ss = fmaxf(sn, 1e-12f * ss);
-            if (ss > 0.f && isfinite(ss)) {
-                sig = sqrtf(ss / nent);
-                isig = 1.f / sig;
-            }
-        }
+        if (PK) sap_sigma(v[3], rnent, sig, isig);   // the scale of the next copy
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             const float2 zv = dsh[k * SAP_MAXVB + l];

@@ -118,22 +118,22 @@ struct Scal {
 // c_i -= gamma_j beta_ij for i < j.  One thread per right-hand side.
 __global__ void k_gcr_gamma(const double* __restrict__ beta, const double* __restrict__ alpha, int jn, int m,
                             double* __restrict__ gamma, int nrhs) {
+    // the running coefficients c live in gamma itself (c_j is final once the
+    // elimination reaches j), so the kernel needs no private arrays and no
+    // scratch memory
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrhs) return;
-    double cr[32], ci[32];
     for (int j = 0; j < jn; ++j) {
-        cr[j] = alpha[((size_t)j * nrhs + r) * 2];
-        ci[j] = alpha[((size_t)j * nrhs + r) * 2 + 1];
+        gamma[((size_t)j * nrhs + r) * 2] = alpha[((size_t)j * nrhs + r) * 2];
+        gamma[((size_t)j * nrhs + r) * 2 + 1] = alpha[((size_t)j * nrhs + r) * 2 + 1];
     }
     for (int j = jn - 1; j >= 0; --j) {
-        const double gr = cr[j], gi = ci[j];
-        gamma[((size_t)j * nrhs + r) * 2] = gr;
-        gamma[((size_t)j * nrhs + r) * 2 + 1] = gi;
+        const double gr = gamma[((size_t)j * nrhs + r) * 2], gi = gamma[((size_t)j * nrhs + r) * 2 + 1];
         const double* bj = beta + (size_t)j * m * nrhs * 2;
         for (int i = 0; i < j; ++i) {
             const double br = bj[((size_t)i * nrhs + r) * 2], bi = bj[((size_t)i * nrhs + r) * 2 + 1];
-            cr[i] -= gr * br - gi * bi;
-            ci[i] -= gr * bi + gi * br;
+            gamma[((size_t)i * nrhs + r) * 2] -= gr * br - gi * bi;
+            gamma[((size_t)i * nrhs + r) * 2 + 1] -= gr * bi + gi * br;
         }
     }
 }

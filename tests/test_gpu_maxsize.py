@@ -168,6 +168,9 @@ def test_maxsize_mg_solve(big):
     e_g = np.abs(G1h - G1o).max() / np.abs(G1o).max()
     print("48^3x96, Nv = 32: sampled basis and coarse gammas vs oracle, gammas %.2e" % e_g)
     assert e_g < 1e-12
+    # the probe's fields stay in torch's cache unless handed back; the
+    # library allocates its solver workspaces with hipMalloc
+    torch.cuda.empty_cache()
     bs = synth.gaussian_fields(2, LS, 302)
     b = ctx.fine(2)
     ctx.import_fields(to_dev(_tile(bs, LS)), b)
@@ -195,6 +198,10 @@ def test_maxsize_stochastic_levels(big):
     from paper_2412_06347_amd import mglma
     ctx, D = big
     assert ctx.nc == 2 * NV            # the subspace of the previous test
+    # this lattice fills most of the device: hand back torch's cached blocks
+    # and the previous solve's workspaces before the top level and the solves
+    torch.cuda.empty_cache()
+    ctx.release_workspace()
     t0 = time.time()
     modes = to_dev(synth.gaussian_coarse(NLM, ctx.V1, ctx.nc, 304))
     ctx.set_top_modes(modes)
@@ -208,6 +215,9 @@ def test_maxsize_stochastic_levels(big):
     eta = ctx.fine(4)
     ctx.noise_sources(xi, tn, eta)
     x = ctx.fine(4)
+    free, total = torch.cuda.mem_get_info()
+    print("48^3x96 before the solves: %.1f of %.1f GB free, library resident %.1f GB"
+          % (free / 1e9, total / 1e9, ctx.resident_bytes() / 1e9), flush=True)
     t0 = time.time()
     rc, st = ctx.solve(eta, x, bench.mixed_params(mglma, max_inner=400))
     torch.cuda.synchronize()

@@ -72,6 +72,73 @@ def test_sap_cycles_parity_scaled(pair, scale):
     assert e < 5e-3
 
 
+def test_sap_cycles_tiny_blocks(pair):
+    """FP16 links with blocks whose entries are far below the rest (a source
+    on one time slice, 1e-21 elsewhere: the block norms there underflow
+    FP32): those blocks drop out of the FP16 block steps instead of turning
+    the result non-finite, and the rest matches the oracle's cycles."""
+    from paper_2412_06347_amd import mglma
+    nrhs, ncycle, nmr = 2, 2, 4
+    r = synth.gaussian_fields(nrhs, pair.L, 71)
+    t = np.arange(int(np.prod(pair.L))) // int(np.prod(pair.L[1:]))
+    r = r * np.where(t == 0, 1.0, 1e-21)[None, :, None, None]
+    z0 = np.zeros_like(r)
+    rd, zd = pair.fine_dev(r, mglma.F32), pair.fine_dev(z0, mglma.F32)
+    pair.ctx.sap_smooth(rd, zd, ncycle=ncycle, nmr=nmr, prec=mglma.F16)
+    got = pair.fine_host(zd, mglma.F32)
+    assert np.isfinite(got).all()
+    bl = subspace.Blocking(pair.L, pair.b)
+    ref = []
+    for q in range(nrhs):
+        z = pair.lat(z0)[q]
+        for _ in range(ncycle):
+            z = sap.sap_cycle(pair.D, bl, pair.lat(r)[q], z, nmr)
+        ref.append(z)
+    ref = pair.canon(np.stack(ref))
+    e = relerr(got, ref)
+    print("SAP FP16, source on one time slice, 1e-21 elsewhere: rel. error %.2e" % e)
+    assert e < 5e-3
+
+
+def test_sap_block_eigenvector(pair):
+    """FP16 links where a block step removes nearly all of a block's residual:
+    r on one colour-0 block is an eigenvector of that block's M_BB, so the
+    first minimal-residual step leaves only rounding in s.  The FP16 copy's
+    scale comes from |s|^2 summed afresh (a running |s|^2 - |<t,s>|^2/|t|^2
+    cancels here and its scale overflowed FP16); the result stays finite
+    and matches the oracle's cycles."""
+    from paper_2412_06347_amd import mglma
+    if int(np.prod(pair.b)) > 16:
+        pytest.skip("dense block operator built for 2^4 blocks only")
+    bl = subspace.Blocking(pair.L, pair.b)
+    y0 = next(y for y in range(bl.V1) if sap.block_colour(bl, y) == 0)
+    mask = sap.block_mask(bl, y0)
+    idx = np.flatnonzero(np.broadcast_to(mask[..., None, None], tuple(pair.L) + (4, 3)))
+    n = idx.size
+    Mbb = np.zeros((n, n), dtype=complex)
+    for k in range(n):
+        e = np.zeros(tuple(pair.L) + (4, 3), dtype=complex)
+        e.flat[idx[k]] = 1.0
+        Mbb[:, k] = sap.block_apply(pair.D, mask, e).flat[idx]
+    lam, vec = np.linalg.eig(Mbb)
+    k = int(np.argsort(np.abs(lam))[n // 2])
+    f = np.zeros(tuple(pair.L) + (4, 3), dtype=complex)
+    f.flat[idx] = vec[:, k]
+    r = pair.canon(f[None])
+    z0 = np.zeros_like(r)
+    rd, zd = pair.fine_dev(r, mglma.F32), pair.fine_dev(z0, mglma.F32)
+    ncycle, nmr = 2, 4
+    pair.ctx.sap_smooth(rd, zd, ncycle=ncycle, nmr=nmr, prec=mglma.F16)
+    got = pair.fine_host(zd, mglma.F32)
+    assert np.isfinite(got).all()
+    z = pair.lat(z0)[0]
+    for _ in range(ncycle):
+        z = sap.sap_cycle(pair.D, bl, f, z, nmr)
+    e = relerr(got, pair.canon(z[None]))
+    print("SAP FP16, r an eigenvector of one block's M_BB: rel. error %.2e" % e)
+    assert e < 5e-3
+
+
 def test_sap_smoothed_solve(pair):
     from paper_2412_06347_amd import mglma
     b = synth.gaussian_fields(2, pair.L, 53)
