@@ -31,6 +31,8 @@ WORKLOADS = {
     # spin-diluted sources (192 right-hand sides); run by --c4
     "48c96": dict(L=(96, 48, 48, 48), block=(4, 4, 4, 4), eps=0.25, kappa=0.125, csw=1.0, Nv=32, Nlm=64, seed=4,
                   nsrc=48),
+    # 32^3 x 64, eps = 0.25, kappa = 0.125, the third volume of the wider serving mix
+    "32c64": dict(L=(64, 32, 32, 32), block=(4, 4, 4, 4), eps=0.25, kappa=0.125, csw=1.0, Nv=24, Nlm=16, seed=6),
     # 4^4, eps = 0.3, kappa = 0.120, 2^4 blocks
     "4c4": dict(L=(4, 4, 4, 4), block=(2, 2, 2, 2), eps=0.3, kappa=0.120, csw=1.0, Nv=8, Nlm=4, seed=1),
 }
@@ -724,17 +726,18 @@ def setup_recipes(wl, reps=2):
                       "recipes": out}), flush=True)
 
 
-def serving(reqs_n=60, seed=7, burst_n=24, max_src=8, emit=True):
-    """Serving mix (a reduced version of the serving workload: two resident
-    ensembles, 16^3 x 32 and 24^3 x 48): requests of 1-max_src stochastic
-    time-slice sources (x 4 spin-diluted right-hand sides) on a uniformly
-    drawn ensemble.  The isolated service rate from requests run one at a
-    time, then a Poisson stream at 0.8 of it; solves/s and p50/p99 latency
-    (arrival to the returned correlator levels)."""
+def serving(reqs_n=60, seed=7, burst_n=24, max_src=8, emit=True, mix=("16c32", "24c48")):
+    """Serving mix (a reduced version of the serving workload: resident
+    ensembles, by default 16^3 x 32 and 24^3 x 48): requests of 1-max_src
+    stochastic time-slice sources (x 4 spin-diluted right-hand sides) on a
+    uniformly drawn ensemble.  The isolated service rate from requests run
+    one at a time, then a Poisson stream at 0.8 of it; solves/s and p50/p99
+    latency (arrival to the returned correlator levels)."""
     import torch
     from paper_2412_06347_amd.serve import Server, poisson_arrivals
     free, _ = torch.cuda.mem_get_info()
-    ens = {"16c32": WORKLOADS["16c32"], "24c48": WORKLOADS["24c48"]}
+    ens = {name: WORKLOADS[name] for name in mix}
+    vols = " and ".join("%d^3x%d" % (ens[n]["L"][1], ens[n]["L"][0]) for n in mix)
     g = np.random.default_rng(seed)
 
     def draw(n):
@@ -747,14 +750,18 @@ def serving(reqs_n=60, seed=7, burst_n=24, max_src=8, emit=True):
             while time.perf_counter() - t0 < t:
                 time.sleep(0.0005)
             reqs.append(srv.submit(name, n_src, 1000 + k))
-        for r in reqs:
+        for k, r in enumerate(reqs):
             r.wait(600)
+            if emit:
+                log("serving: request %d/%d done (%s, %d sources, %.2f s)"
+                    % (k + 1, len(reqs), r.ensemble, r.n_src, r.t_done - r.t_arrival))
         return reqs
 
     srv = Server(hbm_budget=0.8 * free, max_batch_rhs=48)
     t0 = time.perf_counter()
     for name, wl in ens.items():
         srv.add_ensemble(name, wl)
+        log("serving: ensemble %s resident, %d slots (%.0f s)" % (name, srv.slots[name], time.perf_counter() - t0))
     setup = time.perf_counter() - t0
     srv.start()
     # isolated service rate: requests one at a time (each submitted when the
@@ -765,6 +772,8 @@ def serving(reqs_n=60, seed=7, burst_n=24, max_src=8, emit=True):
         r = srv.submit(name, n_src, 500 + k)
         r.wait(600)
         t_iso.append(r.t_done - r.t_arrival)
+        if emit:
+            log("serving: isolated request %d/%d (%s, %d sources, %.2f s)" % (k + 1, len(iso), name, n_src, t_iso[-1]))
     cap = dict(n=len(iso), solves=4 * sum(n for _, n in iso), seconds=float(np.sum(t_iso)),
                mean_service_s=float(np.mean(t_iso)))
     cap["solves_per_s"] = cap["solves"] / cap["seconds"]
@@ -780,17 +789,18 @@ def serving(reqs_n=60, seed=7, burst_n=24, max_src=8, emit=True):
     for eng in srv.engines.values():
         eng.pool.close()
         eng.ctx.close()
-    out = {"workload": "requests of 1-%d spin-diluted time-slice sources on resident 16^3x32 and 24^3x48 "
+    out = {"workload": "requests of 1-%d spin-diluted time-slice sources on resident %s "
                        "ensembles, mixed-precision MG to 1e-10, right-hand sides join and leave between outer "
-                       "cycles" % max_src,
+                       "cycles" % (max_src, vols),
            "isolated_solves_per_s": cap["solves_per_s"], "isolated_mean_service_s": cap["mean_service_s"],
            "poisson_requests": st["n"], "requests_per_s": rate,
            "offered_solves_per_s": rate * mean_rhs, "solves_per_s": st["solves_per_s"],
            "p50_s": st["p50_s"], "p99_s": st["p99_s"], "max_true_rel_res": res}
     if not emit:
         return out
-    print(json.dumps({"diagnostic": "serving mix: resident 16^3x32 and 24^3x48 ensembles, continuous batching "
-                                    "(right-hand sides join and leave between outer cycles)",
+    print(json.dumps({"diagnostic": "serving mix: resident %s ensembles, requests of 1-%d sources, continuous "
+                                    "batching (right-hand sides join and leave between outer cycles)"
+                                    % (vols, max_src),
                       "setup_s": round(setup, 1), "slots": srv.slots,
                       "isolated": cap,
                       "poisson": {"requests_per_s": rate, "offered_solves_per_s": rate * mean_rhs,
@@ -821,8 +831,11 @@ def main():
     ap.add_argument("--sap-only", action="store_true",
                     help="only run SAP smoother cycles of the workload (for hardware-counter runs)")
     ap.add_argument("--serve", action="store_true",
-                    help="serving diagnostic instead of the bench: two resident ensembles, a closed burst for the "
-                         "capacity, then a Poisson stream at 0.8 of it; solves/s and p50/p99 latency")
+                    help="serving diagnostic instead of the bench: two resident ensembles, the isolated service "
+                         "rate, then a Poisson stream at 0.8 of it; solves/s and p50/p99 latency")
+    ap.add_argument("--serve-wide", action="store_true",
+                    help="the same with three resident ensembles (16^3x32, 24^3x48, 32^3x64) and requests of "
+                         "1-48 sources")
     ap.add_argument("--cond", action="store_true",
                     help="spectra and condition numbers of the hierarchy's operators instead of the bench "
                          "(default workload 16c32)")
@@ -864,6 +877,9 @@ def main():
         return
     if args.serve:
         serving()
+        return
+    if args.serve_wide:
+        serving(reqs_n=40, burst_n=12, max_src=48, mix=("16c32", "24c48", "32c64"))
         return
     if args.sap_only:
         # the SAP smoother of the step (FP16 links, 12 RHS, the bench's block
