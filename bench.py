@@ -509,12 +509,31 @@ def config4(wl, gb_per_rhs=23.0):
     log("c4: subspace built (%.1f s), resident %.1f GB" % (time.time() - t1, ctx.resident_bytes() / 1e9))
     # top level: Nlm low modes of Q_1 from the device eigensolver
     t1 = time.time()
-    init = torch.from_numpy(synth_mod.gaussian_coarse(Nlm + 32, ctx.V1, ctx.nc, 4242).view(np.float64)).cuda()
-    rc, lam, modes, st = ctx.coarse_eigs(init, Nlm, tol=1e-12, max_iter=40, raise_on_error=False)
-    del init
+    # in pieces of 20 iterations, each continuing from the previous piece's
+    # whole block (a progress line per piece), at most 40 iterations: the
+    # synthetic field's low modes come in near-degenerate momentum shells and
+    # N_lm = 64 cuts through one of them, whose members the filter does not
+    # separate (a 128-vector block leaves the same 16 pairs unconverged after
+    # 120 iterations)
+    nblk = Nlm + 32
+    init = torch.from_numpy(synth_mod.gaussian_coarse(nblk, ctx.V1, ctx.nc, 4242).view(np.float64)).cuda()
+    its = 0
+    for piece in range(2):
+        rc, lam, blk, st = ctx.coarse_eigs(init, Nlm, tol=1e-12, max_iter=20, raise_on_error=False,
+                                           out_block=True)
+        its += st["iters"]
+        log("c4: eigensolver %d iterations, %d of %d pairs converged, largest residual %.2e (%.0f s)"
+            % (its, st["nconv"], Nlm, st["max_res"], time.time() - t1))
+        del init
+        init = blk
+        if rc == 0:
+            break
+    modes = blk[:Nlm].clone()
+    del init, blk
     torch.cuda.synchronize()
-    out["eigs"] = dict(rc=rc, seconds=round(time.time() - t1, 1), iters=st["iters"], nconv=st["nconv"],
-                       max_res=st["max_res"])
+    out["eigs"] = dict(rc=rc, seconds=round(time.time() - t1, 1), iters=its, nconv=st["nconv"],
+                       max_res=st["max_res"], block=nblk,
+                       ritz_values=[round(float(v), 6) for v in lam])
     t1 = time.time()
     ctx.set_top_modes(modes.contiguous())
     torch.cuda.synchronize()

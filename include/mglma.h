@@ -298,6 +298,10 @@ int mglma_set_top_modes(mglma_ctx* ctx, int Nlm, const double* modes_dev);
  *               pair (|v| = 1)
  *   init_dev    [nblk][V1][nc] complex128, the start block (its random
  *               numbers are the caller's; any block of full rank), read only
+ *   p->out_block 0: the outputs hold the nev wanted pairs; 1: they hold
+ *               all nblk Ritz pairs of the final block (evals [nblk],
+ *               evecs_dev [nblk][V1][nc]), a start block from which a later
+ *               call continues the iteration (long runs in bounded pieces)
  *   evals       host array [nev]: eigenvalues of Q_1 in order of |lambda|
  *   evecs_dev   [nev][V1][nc] complex128: orthonormal eigenvectors
  *   stats       may be NULL
@@ -307,6 +311,7 @@ int mglma_set_top_modes(mglma_ctx* ctx, int Nlm, const double* modes_dev);
 typedef struct {
     int nev, nguard, degree, max_iter;
     double tol;
+    int out_block;
 } mglma_eig_params;
 typedef struct {
     int iters;              /* filter iterations                              */

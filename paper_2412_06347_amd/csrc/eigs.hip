@@ -396,8 +396,9 @@ static int eigs_run(mglma_ctx* c, int level, const mglma_eig_params* p, const do
         EG_TRY(rayleigh_ritz(Y));
     }
     // ---- outputs
-    HIP_TRY(hipMemcpyAsync(evecs, X, (size_t)nev * n * sizeof(double2), hipMemcpyDeviceToDevice, c->stream));
-    for (int k = 0; k < nev; ++k) evals[k] = theta[k];
+    const int nout = p->out_block ? nb : nev;
+    HIP_TRY(hipMemcpyAsync(evecs, X, (size_t)nout * n * sizeof(double2), hipMemcpyDeviceToDevice, c->stream));
+    for (int k = 0; k < nout; ++k) evals[k] = theta[k];
     if (stats) {
         stats->iters = it;
         stats->applies = E.applies;

@@ -61,7 +61,7 @@ class SolveStats(C.Structure):
 
 class EigParams(C.Structure):
     _fields_ = [("nev", C.c_int), ("nguard", C.c_int), ("degree", C.c_int), ("max_iter", C.c_int),
-                ("tol", C.c_double)]
+                ("tol", C.c_double), ("out_block", C.c_int)]
 
 
 class EigStats(C.Structure):
@@ -313,11 +313,13 @@ class Context:
         _check(lib().mglma_coarse_pieces(self._ctx, C.byref(params or default_params()), _ptr(eta),
                                          _ptr(ge1), _ptr(top), eta.shape[0]))
 
-    def coarse_eigs(self, init, nev, tol=1e-12, degree=0, max_iter=0, raise_on_error=True):
+    def coarse_eigs(self, init, nev, tol=1e-12, degree=0, max_iter=0, raise_on_error=True, out_block=False):
         """Low modes of Q_1: init is the [nblk][V1][nc] complex128 start block
-        (nguard = nblk - nev).  Returns (rc, eigenvalues, eigenvectors, stats)."""
+        (nguard = nblk - nev).  Returns (rc, eigenvalues, eigenvectors, stats);
+        with out_block the whole final block (nblk pairs), from which a later
+        call continues."""
         return self._eigs(lib().mglma_coarse_eigs, (self.V1, self.nc, 2), init, nev, tol, degree, max_iter,
-                          raise_on_error)
+                          raise_on_error, out_block)
 
     def fine_eigs(self, init, nev, tol=1e-12, degree=0, max_iter=0, raise_on_error=True):
         """Low modes of Q = gamma5 M: init is [nblk][12][V][2] float64 (device
@@ -325,17 +327,19 @@ class Context:
         return self._eigs(lib().mglma_fine_eigs, (12, self.V, 2), init, nev, tol, degree, max_iter,
                           raise_on_error)
 
-    def _eigs(self, fn, shape, init, nev, tol, degree, max_iter, raise_on_error):
+    def _eigs(self, fn, shape, init, nev, tol, degree, max_iter, raise_on_error, out_block=False):
         import torch
         nb = init.shape[0]
-        par = EigParams(nev=nev, nguard=nb - nev, degree=degree, max_iter=max_iter, tol=tol)
-        ev = np.zeros(max(nev, 1), dtype=np.float64)
-        vec = torch.empty((max(nev, 1),) + shape, dtype=torch.float64, device=init.device)
+        par = EigParams(nev=nev, nguard=nb - nev, degree=degree, max_iter=max_iter, tol=tol,
+                        out_block=1 if out_block else 0)
+        nout = nb if out_block else nev
+        ev = np.zeros(max(nout, 1), dtype=np.float64)
+        vec = torch.empty((max(nout, 1),) + shape, dtype=torch.float64, device=init.device)
         st = EigStats()
         rc = fn(self._ctx, C.byref(par), _ptr(init), ev.ctypes.data_as(C.c_void_p), _ptr(vec), C.byref(st))
         if raise_on_error:
             _check(rc)
-        return rc, ev[:nev], vec[:nev], dict(iters=st.iters, applies=st.applies, nconv=st.nconv,
+        return rc, ev[:nout], vec[:nout], dict(iters=st.iters, applies=st.applies, nconv=st.nconv,
                                              max_res=st.max_res, spectrum_bound=st.spectrum_bound,
                                              lambda_max_abs=st.lambda_max_abs,
                                              seconds=st.seconds)

@@ -60,6 +60,32 @@ def test_low_modes_parity(case):
             assert abs(abs(np.vdot(Vo[k], V[k])) - 1.0) < 1e-9
 
 
+def test_eigs_continued_in_pieces(case):
+    """A run split into pieces of two iterations, each started from the
+    previous piece's whole final block (out_block), reaches the same modes
+    as the oracle's dense eigendecomposition."""
+    pair, nev, ng = case
+    nb = nev + ng
+    init = to_dev(synth.gaussian_coarse(nb, pair.bl.V1, 2 * pair.Nv, 11))
+    its = 0
+    for piece in range(60):
+        rc, lam, blk, st = pair.ctx.coarse_eigs(init, nev, max_iter=2, raise_on_error=False, out_block=True)
+        its += st["iters"]
+        assert blk.shape[0] == nb and lam.shape == (nb,)
+        if rc == 0:
+            break
+        init = blk
+    print("eigs in pieces of 2 iterations: %d pieces, %d iterations" % (piece + 1, its))
+    assert rc == 0
+    lam_o, _ = coarse.low_modes(pair.D1, pair.nbr, pair.Nv, nev)
+    assert np.abs(lam[:nev] - lam_o).max() < 1e-11
+    v = from_dev(blk[:nev])
+    g5 = subspace.coarse_gamma5(pair.Nv)[None, None, :]
+    Qv = g5 * coarse.coarse_apply(pair.D1, pair.nbr, v)
+    res = np.linalg.norm((Qv - lam[:nev, None, None] * v).reshape(nev, -1), axis=1)
+    assert res.max() <= 1e-12
+
+
 def test_eigs_arguments(case):
     pair, nev, ng = case
     from paper_2412_06347_amd import mglma
