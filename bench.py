@@ -769,6 +769,9 @@ def serving(reqs_n=60, seed=7, burst_n=24, max_src=8, emit=True, mix=("16c32", "
             while time.perf_counter() - t0 < t:
                 time.sleep(0.0005)
             reqs.append(srv.submit(name, n_src, 1000 + k))
+            if emit and (k + 1) % 10 == 0:
+                log("serving: %d/%d requests arrived, %d done (%.0f s)"
+                    % (k + 1, len(items), sum(r.done.is_set() for r in reqs), time.perf_counter() - t0))
         for k, r in enumerate(reqs):
             r.wait(600)
             if emit:
@@ -850,8 +853,9 @@ def main():
     ap.add_argument("--sap-only", action="store_true",
                     help="only run SAP smoother cycles of the workload (for hardware-counter runs)")
     ap.add_argument("--serve", action="store_true",
-                    help="serving diagnostic instead of the bench: two resident ensembles, the isolated service "
-                         "rate, then a Poisson stream at 0.8 of it; solves/s and p50/p99 latency")
+                    help="serving diagnostic instead of the bench: two resident ensembles, requests of 1-48 "
+                         "sources, the isolated service rate, then a Poisson stream of 500 requests at 0.8 of it; "
+                         "solves/s and p50/p99 latency")
     ap.add_argument("--serve-wide", action="store_true",
                     help="the same with three resident ensembles (16^3x32, 24^3x48, 32^3x64) and requests of "
                          "1-48 sources")
@@ -895,7 +899,7 @@ def main():
         spectra_and_conditioning(WORKLOADS["16c32" if args.workload == "24c48" else args.workload])
         return
     if args.serve:
-        serving()
+        serving(reqs_n=500, burst_n=24, max_src=48)
         return
     if args.serve_wide:
         serving(reqs_n=40, burst_n=12, max_src=48, mix=("16c32", "24c48", "32c64"))
