@@ -391,7 +391,10 @@ int mglma_adaptive_setup(mglma_ctx* ctx, const mglma_solve_params* p, double* te
  * whole extent, keeps its boundary phase).  r_dev, z_dev: [nrhs][12][V]
  * complex FP32 device layout (mglma_import_fields with F32); z is read as
  * the start and overwritten.  Links and clover: the FP16 (prec F16) or FP32
- * (prec F32) copies.  Needs every block-grid extent L_mu/b_mu even or one
+ * (prec F32) copies.  With F16 the block steps compute on packed FP16 data
+ * (the block's s rounded to FP16 after scaling by its root-mean-square
+ * entry, FP32 sums); the residual, the step coefficients and z stay FP32.
+ * Needs every block-grid extent L_mu/b_mu even or one
  * and at most 256 sites per block.  Asynchronous.  Errors: ARG, NO_GAUGE,
  * SHAPE (block grid or block size), OOM.                                   */
 int mglma_sap_smooth(mglma_ctx* ctx, int prec, int ncycle, int nmr, const float* r_dev, float* z_dev,
