@@ -142,8 +142,12 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds /* [4][NV
 template <int NV>
 __device__ __forceinline__ void write_partial(double (&v)[NV], double* lds, double* part, int nvals) {
     block_sum<NV>(v, lds);
-    if (threadIdx.x == 0)
-        for (int k = 0; k < nvals; ++k) part[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * NV + k] = v[k];
+    // (compile-time indices throughout, so v stays in registers)
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+            if (k < nvals) part[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * NV + k] = v[k];
+    }
 }
 
 // Second pass, one workgroup per rhs: add the nb partials (each thread a
@@ -165,29 +169,40 @@ __global__ __launch_bounds__(RB) void k_finish(const double* __restrict__ part, 
     for (int k = 0; k < NV; ++k) s[k] = 0.0;
     for (int b = threadIdx.x; b < nb; b += RB) {
         const double* pb = part + ((size_t)r * nb + b) * NV;
+        // every slot is summed (slots at or past nvals are never read out), so
+        // that s is indexed at compile time only and stays in registers
 #pragma unroll
-        for (int k = 0; k < NV; ++k)
-            if (k < nvals) s[k] += pb[k];
+        for (int k = 0; k < NV; ++k) s[k] += pb[k];
     }
-    block_sum<NV>(s, lds);
-    if (threadIdx.x == 0) {
-        if (mode == 2) {
-            const double d = s[NV > 2 ? 2 : 0];
+    // wavefront sums, then the four wavefront values of slot k added in a
+    // fixed order by thread k (the tail runs in parallel over the slots and
+    // needs no indexed register array)
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) s[k] = wave_sum(s[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) lds[w * NV + k] = s[k];
+    }
+    __syncthreads();
+    auto total = [&](int k) { return lds[k] + lds[NV + k] + lds[2 * NV + k] + lds[3 * NV + k]; };
+    if (mode == 2) {
+        if (threadIdx.x == 0) {
+            const double d = total(NV > 2 ? 2 : 0);
             const bool on = (mask == nullptr || mask[r]) && d > 0.0;
-            out[2 * r] = on ? s[0] / d : 0.0;
-            out[2 * r + 1] = on ? s[NV > 1 ? 1 : 0] / d : 0.0;
+            out[2 * r] = on ? total(0) / d : 0.0;
+            out[2 * r + 1] = on ? total(NV > 1 ? 1 : 0) / d : 0.0;
             if (aux) aux[r] = d;
-            return;
         }
-        for (int k = 0; k < nvals; ++k) {
-            if (mode == 0) {
-                out[(size_t)r * nvals + k] = s[k];
-            } else {
-                const size_t o = (size_t)(k >> 1) * ostride + r;
-                double v = s[k];
-                if (div) v = div[o] > 0.0 ? v / div[o] : 0.0;
-                out[o * 2 + (k & 1)] = v;
-            }
+        return;
+    }
+    for (int k = threadIdx.x; k < nvals; k += RB) {
+        const double v = total(k);
+        if (mode == 0) {
+            out[(size_t)r * nvals + k] = v;
+        } else {
+            const size_t o = (size_t)(k >> 1) * ostride + r;
+            out[o * 2 + (k & 1)] = div ? (div[o] > 0.0 ? v / div[o] : 0.0) : v;
         }
     }
 }
