@@ -61,3 +61,23 @@ def test_level_calls_reject_null_context_without_gpu():
     out = (ctypes.c_double * 64)()
     assert lib.mglma_contract_levels(None, 1, 1, t, None, 0, None, 0, out) == -1
     assert lib.mglma_contract_pair(None, 1, 1, t, 0, None, None, out) == -1
+
+
+def test_header_compiles_as_c_and_cpp(tmp_path):
+    """The public header is plain C (and valid C++): a translation unit that
+    includes it and fills the parameter structs compiles with -Wall."""
+    import shutil
+    src = tmp_path / "use_header.c"
+    src.write_text('#include "mglma.h"\n'
+                   "int main(void) {\n"
+                   "    mglma_eig_params ep = {4, 4, 0, 0, 1e-12, 1};\n"
+                   "    mglma_eig_stats es;\n"
+                   "    (void)ep; (void)es;\n"
+                   "    return 0;\n"
+                   "}\n")
+    for cc, std, lang in (("gcc", "-std=c99", "c"), ("g++", "-std=c++17", "c++")):
+        if shutil.which(cc) is None:
+            pytest.skip("%s not available" % cc)
+        r = subprocess.run([cc, std, "-Wall", "-Wextra", "-Werror", "-fsyntax-only", "-x", lang,
+                            "-I", os.path.dirname(HEADER), str(src)], capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
