@@ -1142,54 +1142,65 @@ int mg_ca_update(mglma_ctx* c, int pprec, const void* P, size_t pstride, int k, 
 
 // ---------------------------------------------------------------------------
 // Gram matrix of two FP64 vector blocks: out[j][i] = <X_i, Y_j> (complex, the
-// layout of mg_multidot's output for j = 0..ky-1), kx, ky <= 64.  Pass 1:
-// GS workgroups each take a range of entries, stage 16 entries of every
-// vector in LDS at a time and accumulate the kx * ky products (up to 16 per
-// thread); pass 2 adds the GS partials in order.
+// layout of mg_multidot's output for j = 0..ky-1), kx, ky <= 64, on the FP64
+// matrix cores.  Pass 1: GRAM_GS workgroups each take a contiguous range of
+// entries; wave w owns the output rows i in [16w, 16w+16) and all four
+// 16-column tiles of j, and per 16 entries makes 4 steps x 4 tiles x 4 real
+// products (Re += xr yr + xi yi, Im += xr yi - xi yr) with
+// v_mfma_f64_16x16x4.  Lane (r, q) = (l % 16, l / 16) supplies row r and the
+// entries k0 + 4q + s, s = 0..3 (four consecutive entries of one vector, so
+// a wavefront reads 256 contiguous bytes per vector).  Pass 2 adds the
+// GRAM_GS partials in order.
 // ---------------------------------------------------------------------------
-#define GRAM_GS 128
-#define GRAM_KT 16
+#define GRAM_GS 512
 __global__ __launch_bounds__(256) void k_gram64_part(const double2* __restrict__ X, int kx, const double2* __restrict__ Y,
                                                      int ky, size_t n, double2* __restrict__ part) {
-    __shared__ double2 xs[64 * GRAM_KT], ys[64 * GRAM_KT];
-    const int gs = blockIdx.x, t = threadIdx.x;
+    typedef Mfma<double>::v4 v4;
+    const int gs = blockIdx.x, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r = lane & 15, q = lane >> 4;
     const size_t k0 = n * gs / GRAM_GS, k1 = n * (gs + 1) / GRAM_GS;
     const int nout = kx * ky;
-    double ar[16], ai[16];
+    const int i = 16 * w + r;                 // this lane's row of X
+    const bool xon = i < kx;
+    v4 cre[4], cim[4];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) ar[q] = ai[q] = 0.0;
-    for (size_t kb = k0; kb < k1; kb += GRAM_KT) {
-        const int kn = (int)(k1 - kb < GRAM_KT ? k1 - kb : GRAM_KT);
-        __syncthreads();
-        for (int e = t; e < kx * GRAM_KT; e += blockDim.x) {
-            const int i = e / GRAM_KT, kk = e - i * GRAM_KT;
-            xs[e] = kk < kn ? X[(size_t)i * n + kb + kk] : make_double2(0.0, 0.0);
-        }
-        for (int e = t; e < ky * GRAM_KT; e += blockDim.x) {
-            const int j = e / GRAM_KT, kk = e - j * GRAM_KT;
-            ys[e] = kk < kn ? Y[(size_t)j * n + kb + kk] : make_double2(0.0, 0.0);
-        }
-        __syncthreads();
+    for (int J = 0; J < 4; ++J) cre[J] = cim[J] = v4{0.0, 0.0, 0.0, 0.0};
+    if (16 * w < kx) {                        // uniform over the wavefront
+        for (size_t kb = k0; kb < k1; kb += 16) {
+            const size_t kq = kb + 4 * q;
+            double xr[4], xi[4];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int o = t + 256 * q;
-            if (o < nout) {
-                const int i = o % kx, j = o / kx;
-                const double2* xp = xs + i * GRAM_KT;
-                const double2* yp = ys + j * GRAM_KT;
-                for (int kk = 0; kk < GRAM_KT; ++kk) {
-                    const double2 a = xp[kk], b = yp[kk];
-                    ar[q] = fma(a.x, b.x, fma(a.y, b.y, ar[q]));
-                    ai[q] = fma(a.x, b.y, fma(-a.y, b.x, ai[q]));
+            for (int s = 0; s < 4; ++s) {
+                const bool ok = xon && kq + s < k1;
+                const double2 v = ok ? X[(size_t)i * n + kq + s] : make_double2(0.0, 0.0);
+                xr[s] = v.x;
+                xi[s] = v.y;
+            }
+#pragma unroll
+            for (int J = 0; J < 4; ++J) {
+                if (16 * J >= ky) break;       // uniform
+                const int j = 16 * J + r;
+                const bool yon = j < ky;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const bool ok = yon && kq + s < k1;
+                    const double2 v = ok ? Y[(size_t)j * n + kq + s] : make_double2(0.0, 0.0);
+                    cre[J] = Mfma<double>::mac(xr[s], v.x, cre[J]);
+                    cre[J] = Mfma<double>::mac(xi[s], v.y, cre[J]);
+                    cim[J] = Mfma<double>::mac(xr[s], v.y, cim[J]);
+                    cim[J] = Mfma<double>::mac(-xi[s], v.x, cim[J]);
                 }
             }
         }
     }
+    // register t of lane (r, q) holds output row 16 w + q + 4 t, column 16 J + r
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int o = t + 256 * q;
-        if (o < nout) part[(size_t)gs * nout + o] = make_double2(ar[q], ai[q]);
-    }
+    for (int J = 0; J < 4; ++J)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int io = 16 * w + Mfma<double>::row(q, t), jo = 16 * J + r;
+            if (io < kx && jo < ky) part[(size_t)gs * nout + (size_t)jo * kx + io] = make_double2(cre[J][t], cim[J][t]);
+        }
 }
 
 __global__ void k_gram64_sum(const double2* __restrict__ part, int nout, double2* __restrict__ out) {
