@@ -1150,7 +1150,7 @@ int mg_ca_update(mglma_ctx* c, int pprec, const void* P, size_t pstride, int k, 
 // v_mfma_f64_16x16x4.  Lane (r, q) = (l % 16, l / 16) supplies row r and the
 // entries k0 + 4q + s, s = 0..3 (four consecutive entries of one vector, so
 // a wavefront reads 256 contiguous bytes per vector).  Pass 2 adds the
-// GRAM_GS partials in order.
+// GRAM_GS partials of an entry in a fixed order (one wavefront per entry).
 // ---------------------------------------------------------------------------
 #define GRAM_GS 512
 __global__ __launch_bounds__(256) void k_gram64_part(const double2* __restrict__ X, int kx, const double2* __restrict__ Y,
@@ -1203,16 +1203,21 @@ __global__ __launch_bounds__(256) void k_gram64_part(const double2* __restrict__
         }
 }
 
-__global__ void k_gram64_sum(const double2* __restrict__ part, int nout, double2* __restrict__ out) {
-    const int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= nout) return;
+// pass 2: one wavefront per output entry; lane l adds the partials l, l + 64,
+// ... in order, then the fixed shuffle tree
+__global__ __launch_bounds__(256) void k_gram64_sum(const double2* __restrict__ part, int nout,
+                                                    double2* __restrict__ out) {
+    const int o = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (o >= nout) return;   // uniform over the wavefront
     double sr = 0.0, si = 0.0;
-    for (int gs = 0; gs < GRAM_GS; ++gs) {
+    for (int gs = lane; gs < GRAM_GS; gs += 64) {
         const double2 v = part[(size_t)gs * nout + o];
         sr += v.x;
         si += v.y;
     }
-    out[o] = make_double2(sr, si);
+    sr = wave_sum(sr);
+    si = wave_sum(si);
+    if (lane == 0) out[o] = make_double2(sr, si);
 }
 
 int mg_gram64(mglma_ctx* c, const void* X, int kx, const void* Y, int ky, size_t n, double* out_dev) {
@@ -1220,7 +1225,7 @@ int mg_gram64(mglma_ctx* c, const void* X, int kx, const void* Y, int ky, size_t
     MG_TRY(ensure_red(c, (size_t)GRAM_GS * kx * ky * 2));
     hipLaunchKernelGGL(k_gram64_part, dim3(GRAM_GS), dim3(256), 0, c->stream, (const double2*)X, kx,
                        (const double2*)Y, ky, n, (double2*)c->red_part);
-    hipLaunchKernelGGL(k_gram64_sum, dim3((kx * ky + 255) / 256), dim3(256), 0, c->stream,
+    hipLaunchKernelGGL(k_gram64_sum, dim3((kx * ky + 3) / 4), dim3(256), 0, c->stream,
                        (const double2*)c->red_part, kx * ky, (double2*)out_dev);
     HIP_TRY(hipGetLastError());
     return MGLMA_OK;
