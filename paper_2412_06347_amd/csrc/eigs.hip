@@ -58,47 +58,74 @@ __global__ void k_ritz_resid(double2* __restrict__ out, const double2* __restric
     }
 }
 
-// Z_j = sum_i X_i M[i][j] for j0 <= j < j0 + 64 and j < nb <= 128 (M
-// complex, row-major nb x nb; its columns j0..j0+63 staged in LDS); each
-// thread one entry index of those output vectors.
+// Z_j = sum_i X_i M[i][j] for j < nb <= 128 (M complex, row-major nb x nb)
+// on the FP64 matrix cores: the output tile (16 j) x (16 entries e) is
+// D[j][e] = sum_i M[i][j] X_i[e], four real products per complex one
+// (Re += Mr Xr - Mi Xi, Im += Mr Xi + Mi Xr).  Each wavefront owns 16
+// entries and all NJT = ceil(nb / 16) tiles of j, so X is read once; lane
+// (r, q) = (l % 16, l / 16) supplies M[i][16 J + r] and X_i[e0 + r] for
+// i = i0 + 4 q + s, s = 0..3, and writes Z_{16 J + q + 4 t}[e0 + r] (256
+// contiguous bytes per output vector).
+template <int NJT>
 __global__ __launch_bounds__(256) void k_block_combine(double2* __restrict__ Z, const double2* __restrict__ X,
-                                                       const double2* __restrict__ M, size_t n, int nb, int j0) {
-    extern __shared__ double2 sm[];   // [nb][64]
-    const int nj = nb - j0 < 64 ? nb - j0 : 64;
-    for (int e = threadIdx.x; e < nb * nj; e += blockDim.x) {
-        const int i = e / nj, j = e - i * nj;
-        sm[i * 64 + j] = M[(size_t)i * nb + j0 + j];
-    }
-    __syncthreads();
-    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-        for (int jj = 0; jj < nj; jj += 8) {
-            double2 acc[8];
+                                                       const double2* __restrict__ M, size_t n, int nb) {
+    typedef Mfma<double>::v4 v4;
+    const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+    const size_t e0 = ((size_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+    if (e0 >= n) return;   // uniform over the wavefront
+    const size_t e = e0 + r;
+    const bool eon = e < n;
+    v4 cre[NJT], cim[NJT];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) acc[q] = make_double2(0.0, 0.0);
-            for (int i = 0; i < nb; ++i) {
-                const double2 x = X[(size_t)i * n + e];
+    for (int J = 0; J < NJT; ++J) cre[J] = cim[J] = v4{0.0, 0.0, 0.0, 0.0};
+    for (int i0 = 0; i0 < nb; i0 += 16) {
+        double xr[4], xi[4];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    if (jj + q < nj) {
-                        const double2 m = sm[i * 64 + jj + q];
-                        acc[q].x = fma(x.x, m.x, fma(-x.y, m.y, acc[q].x));
-                        acc[q].y = fma(x.x, m.y, fma(x.y, m.x, acc[q].y));
-                    }
-                }
+        for (int s = 0; s < 4; ++s) {
+            const int i = i0 + 4 * q + s;
+            const double2 v = (eon && i < nb) ? X[(size_t)i * n + e] : make_double2(0.0, 0.0);
+            xr[s] = v.x;
+            xi[s] = v.y;
+        }
+#pragma unroll
+        for (int J = 0; J < NJT; ++J) {
+            const int j = 16 * J + r;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int i = i0 + 4 * q + s;
+                const double2 m = (i < nb && j < nb) ? M[(size_t)i * nb + j] : make_double2(0.0, 0.0);
+                cre[J] = Mfma<double>::mac(m.x, xr[s], cre[J]);
+                cre[J] = Mfma<double>::mac(-m.y, xi[s], cre[J]);
+                cim[J] = Mfma<double>::mac(m.x, xi[s], cim[J]);
+                cim[J] = Mfma<double>::mac(m.y, xr[s], cim[J]);
             }
-#pragma unroll
-            for (int q = 0; q < 8; ++q)
-                if (jj + q < nj) Z[(size_t)(j0 + jj + q) * n + e] = acc[q];
         }
     }
+    if (!eon) return;
+#pragma unroll
+    for (int J = 0; J < NJT; ++J)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int j = 16 * J + Mfma<double>::row(q, t);
+            if (j < nb) Z[(size_t)j * n + e] = make_double2(cre[J][t], cim[J][t]);
+        }
 }
 
 int mg_block_combine(mglma_ctx* c, double2* Z, const double2* X, const double2* M_dev, size_t n, int nb) {
-    size_t g = (n + 255) / 256;
-    g = g > 4096 ? 4096 : (g < 1 ? 1 : g);
-    for (int j0 = 0; j0 < nb; j0 += 64)
-        hipLaunchKernelGGL(k_block_combine, dim3((unsigned)g), dim3(256), (size_t)nb * 64 * sizeof(double2),
-                           c->stream, Z, X, M_dev, n, nb, j0);
+    if (nb < 1 || nb > 128) return MGLMA_ERR_ARG;
+    const size_t nwg = (n + 63) / 64;
+    if (nwg > 0x7fffffffu) return MGLMA_ERR_SHAPE;
+    const dim3 grid((unsigned)nwg), blk(256);
+    switch ((nb + 15) / 16) {
+        case 1: hipLaunchKernelGGL(k_block_combine<1>, grid, blk, 0, c->stream, Z, X, M_dev, n, nb); break;
+        case 2: hipLaunchKernelGGL(k_block_combine<2>, grid, blk, 0, c->stream, Z, X, M_dev, n, nb); break;
+        case 3: hipLaunchKernelGGL(k_block_combine<3>, grid, blk, 0, c->stream, Z, X, M_dev, n, nb); break;
+        case 4: hipLaunchKernelGGL(k_block_combine<4>, grid, blk, 0, c->stream, Z, X, M_dev, n, nb); break;
+        case 5: hipLaunchKernelGGL(k_block_combine<5>, grid, blk, 0, c->stream, Z, X, M_dev, n, nb); break;
+        case 6: hipLaunchKernelGGL(k_block_combine<6>, grid, blk, 0, c->stream, Z, X, M_dev, n, nb); break;
+        case 7: hipLaunchKernelGGL(k_block_combine<7>, grid, blk, 0, c->stream, Z, X, M_dev, n, nb); break;
+        default: hipLaunchKernelGGL(k_block_combine<8>, grid, blk, 0, c->stream, Z, X, M_dev, n, nb); break;
+    }
     HIP_TRY(hipGetLastError());
     return MGLMA_OK;
 }
