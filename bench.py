@@ -745,7 +745,7 @@ def setup_recipes(wl, reps=2):
                       "recipes": out}), flush=True)
 
 
-def serving(reqs_n=60, seed=7, burst_n=24, max_src=8, emit=True, mix=("16c32", "24c48")):
+def serving(reqs_n=60, seed=7, iso_n=24, max_src=8, emit=True, mix=("16c32", "24c48")):
     """Serving mix (a reduced version of the serving workload: resident
     ensembles, by default 16^3 x 32 and 24^3 x 48): requests of 1-max_src
     stochastic time-slice sources (x 4 spin-diluted right-hand sides) on a
@@ -788,7 +788,7 @@ def serving(reqs_n=60, seed=7, burst_n=24, max_src=8, emit=True, mix=("16c32", "
     srv.start()
     # isolated service rate: requests one at a time (each submitted when the
     # previous one has returned); the Poisson stream then runs at 0.8 of it
-    iso = draw(burst_n)
+    iso = draw(iso_n)
     t_iso = []
     for k, (name, n_src) in enumerate(iso):
         r = srv.submit(name, n_src, 500 + k)
@@ -899,10 +899,10 @@ def main():
         spectra_and_conditioning(WORKLOADS["16c32" if args.workload == "24c48" else args.workload])
         return
     if args.serve:
-        serving(reqs_n=500, burst_n=24, max_src=48)
+        serving(reqs_n=500, iso_n=24, max_src=48)
         return
     if args.serve_wide:
-        serving(reqs_n=40, burst_n=12, max_src=48, mix=("16c32", "24c48", "32c64"))
+        serving(reqs_n=40, iso_n=12, max_src=48, mix=("16c32", "24c48", "32c64"))
         return
     if args.sap_only:
         # the SAP smoother of the step (FP16 links, 12 RHS, the bench's block
@@ -1010,8 +1010,8 @@ def main():
     traffic16 = measured_traffic(args.workload)
     traffic_sap = measured_sap_traffic(args.workload)
     # bounded serving leg (continuous batching): the step's context is freed
-    # first; two resident ensembles, a short burst for the capacity and a
-    # Poisson stream of 40 requests at 0.8 of it
+    # first; two resident ensembles, 12 requests one at a time for the
+    # isolated service rate and a Poisson stream of 40 requests at 0.8 of it
     eig_info = P.eig
     serve = None
     if not args.no_serve:
@@ -1019,7 +1019,7 @@ def main():
         del P
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
-        serve = serving(reqs_n=40, burst_n=12, max_src=8, emit=False)
+        serve = serving(reqs_n=40, iso_n=12, max_src=8, emit=False)
     cpu = None
     if not args.no_cpu:
         n_plain, res_plain = n_plain_it
